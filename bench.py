@@ -1,0 +1,219 @@
+#!/usr/bin/env python3
+"""Benchmark of the bipartite iterative-scaling hot path on one MI355X.
+
+Workload: the HMM-like chain (32 nodes, n = 1024 points per node on a 1D grid,
+squared-Euclidean cost, eps = 1e-3, every 4th node observed with a 3-component
+Gaussian mixture), solved from cold start until the stopping sum of the
+Bipartite Iterative Scaling algorithm is <= 1e-6, followed by the FP64
+evaluation pass (dual, primal, transport, both-side stopping sum).  One step
+= one such solve + evaluation; inputs are resident in device memory before
+the timed region.
+
+Metric: edge-iterations/s (an edge-iteration is one edge's message in one
+half-sweep; a half-sweep carries |E| = 31 of them), with the device time to
+reach 1e-6 reported beside it.
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import statistics
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "edge-iterations/s and time-to-1e-6 marginal error; plain vs batched+warm-start"
+# VALU issue capacity of MI355X: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz.
+VALU_SLOTS_PER_S = 256 * 64 * 2.4e9
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_msg_chain_traffic.txt")
+KERNEL_SRC = os.path.join(ROOT, "paper_2406_10849_amd", "csrc", "gmot_kernels.hip")
+
+
+def log(msg: str) -> None:
+    print(msg, file=sys.stderr, flush=True)
+
+
+def host_info() -> dict:
+    model = ""
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    return {"nproc": os.cpu_count(), "affinity": len(os.sched_getaffinity(0)), "cpu": model}
+
+
+def kernel_sha() -> str:
+    return hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest()[:16]
+
+
+def measured_traffic():
+    """HBM bytes per message-kernel launch from the committed rocprofv3 PMC
+    summary, valid only for the kernel source it was taken on."""
+    if not os.path.exists(TRAFFIC_FILE):
+        return None
+    vals = {}
+    for line in open(TRAFFIC_FILE):
+        if ":" in line:
+            k, v = line.split(":", 1)
+            vals[k.strip()] = v.strip()
+    if vals.get("kernel_sha256_16") != kernel_sha():
+        return None
+    try:
+        return float(vals["fetch_bytes_per_launch"]) + float(vals["write_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
+def cpu_baseline(prob, seconds: float) -> dict:
+    """The FP64 oracle as it stands, on the host, for a bounded number of
+    half-sweeps of the same workload."""
+    from oracle import TreeOracle
+    o = TreeOracle(prob)
+    o.tstep()  # first half-sweep also fills the oracle's cost cache
+    steps = 0
+    t0 = time.perf_counter()
+    while True:
+        o.tstep()
+        steps += 1
+        el = time.perf_counter() - t0
+        if el >= seconds:
+            break
+    rate = prob.n_edges * steps / el
+    return {"value": rate, "unit": "edge-iterations/s", "cores": 1, "kind": "oracle",
+            "sample": f"{steps} half-sweeps (after one warm-up half-sweep) of the same 32-node chain, "
+                      f"FP64 numpy, single thread, {el:.1f} s"}
+
+
+def main() -> int:
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--tol", type=float, default=1e-6)
+    ap.add_argument("--check-every", type=int, default=16)
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--calib-copy", action="store_true",
+                    help="also run one 1 GiB device copy (PMC calibration for HBM byte counters)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported (the solver runs on a "
+              f"single device; see the sharding notes in DESIGN.md)", file=sys.stderr)
+        return 2
+
+    from workloads import make_config
+    from paper_2406_10849_amd import Context, Problem, last_tiles
+
+    log(f"host: {host_info()}")
+    prob = make_config(2)
+    n_edges = prob.n_edges
+    pairs_per_half_sweep = prob.pairs_per_tstep()
+    ctx = Context(0)
+    g = Problem(ctx, prob)
+    log("workload built; tuning tiles")
+    tuned = g.autotune()
+    log(f"autotune: {tuned}; tiles: {last_tiles()}")
+    for _ in range(max(args.warmup, 0)):
+        g.solve(tol=args.tol, max_steps=200000, check_every=args.check_every)
+        g.evaluate()
+        g.solve(tol=args.tol, max_steps=200000, check_every=args.check_every, timing=True)
+    g.stats(reset=True)
+
+    try:
+        import torch
+        sync = torch.cuda.synchronize if torch.cuda.is_available() else (lambda: None)
+    except Exception:
+        sync = lambda: None  # noqa: E731
+
+    def timed_region(timing: bool):
+        sync()
+        runs = []
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            r = g.solve(tol=args.tol, max_steps=200000, check_every=args.check_every, timing=timing)
+            ev = g.evaluate()
+            runs.append((r, ev))
+        sync()
+        return runs, time.perf_counter() - t0
+
+    # region 1: the product configuration (graph replay) -> value
+    runs, elapsed = timed_region(False)
+    # region 2: the same steps with HIP events around every stage -> kernel durations
+    g.stats(reset=True)
+    runs_t, elapsed_t = timed_region(True)
+    st = g.stats()
+    for i, (r, ev) in enumerate(runs + runs_t):
+        if r["status"] != "converged" or ev["err_sum"] > args.tol:
+            log(f"step {i}: not converged: {r} {ev}")
+            return 1
+    half_sweeps = [r["t"] for r, _ in runs]      # half-sweeps computed, including the one that passed the test
+    edge_iters = n_edges * sum(half_sweeps)
+    value = edge_iters / elapsed
+    ttt = statistics.median(r["seconds"] for r, _ in runs)
+    last_r, last_ev = runs[-1]
+    log(f"solve: {last_r}")
+    log(f"eval: {last_ev}")
+    log(f"stats: {st}")
+
+    D = prob.dim
+    peak = VALU_SLOTS_PER_S / (D + 2) / 1e9
+    avg_ms = st["msg_ms"] / max(st["msg_launches"], 1)
+    pairs_per_launch = st["msg_pairs"] / max(st["msg_launches"], 1)
+    achieved = pairs_per_launch / (avg_ms / 1e3) / 1e9 if avg_ms > 0 else 0.0
+    traffic = measured_traffic()
+    out = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "edge-iterations/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": 1e3 * elapsed / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64+f32exp",
+        "data": "synthetic",
+        "config": {"workload": "chain-hmm-32node-n1024", "nodes": prob.n_nodes, "edges": n_edges,
+                   "n": int(prob.sizes[0]), "dim": D, "eps": prob.eps, "tol": args.tol,
+                   "cost": "squared-euclidean, on the fly", "observed": "every 4th node, 3-comp GM",
+                   "schedule": "bipartite (layer-parallel)", "check_every": args.check_every},
+        "time_to_1e-6_s": ttt,
+        "half_sweeps_to_1e-6": int(statistics.median(half_sweeps)),
+        "value_event_timed_region": n_edges * sum(r["t"] for r, _ in runs_t) / elapsed_t,
+        "tiles": dict(tuned, **last_tiles()),
+        "pairs_per_s": pairs_per_half_sweep * sum(half_sweeps) / elapsed,
+        "final": {"err_sum_fp64": last_ev["err_sum"], "err_max_fp64": last_ev["err_max"],
+                  "dual": last_ev["dual"], "primal": last_ev["primal"], "transport": last_ev["transport"]},
+        "roofline": {"bound": "alu", "achieved": achieved, "peak": peak, "unit": "Gpair/s",
+                     "frac": achieved / peak, "traffic": traffic,
+                     "kernel": "k_msg", "avg_launch_ms": avg_ms, "pairs_per_launch": pairs_per_launch,
+                     "launches_timed": st["msg_launches"],
+                     "node_kernel_avg_ms": st["node_ms"] / max(st["node_launches"], 1)},
+    }
+    if not args.no_cpu_baseline:
+        log("timing the FP64 oracle on the host")
+        out["cpu_baseline"] = cpu_baseline(prob, args.cpu_seconds)
+    if args.calib_copy:
+        import torch
+        x = torch.empty(1 << 28, dtype=torch.float32, device="cuda")
+        y = torch.empty_like(x)
+        y.copy_(x)
+        torch.cuda.synchronize()
+        out["calib_copy_bytes"] = 2 * x.numel() * 4
+    print(json.dumps(out), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

@@ -1,0 +1,222 @@
+/*
+ * gmot.h -- C ABI of libgmot, a gfx950 (MI355X) solver for tree-structured
+ * coupled bi-marginal optimal transport with local entropic regularisation.
+ *
+ * Method: Fan, Haasler, Zhang, Karlsson, Chen, "A parallel framework for
+ * graphical optimal transport" (arXiv 2406.10849), Section 3.  The library
+ * runs the Bipartite Iterative Scaling algorithm (Algorithm tree_local_reg) in
+ * the log domain: per-edge Gibbs-kernel products K u are computed as
+ * log-sum-exp reductions with the cost formed on the fly, every edge that
+ * touches one colour class of the tree's 2-colouring is processed
+ * concurrently, and the two classes alternate.
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * - Return value: GMOT_OK (0) on success, a negative GMOT_E* code on error.
+ *   gmot_strerror() names a code; gmot_last_error() gives a message for the
+ *   most recent failure on the calling thread.  Failed calls leave their
+ *   outputs unspecified and their handles usable.
+ * - Non-convergence is not an error: it is reported in gmot_result.status.
+ * - Ownership: the caller owns every input array and may free it as soon as
+ *   the call that reads it returns (problem creation deep-copies its inputs
+ *   into device memory).  The library owns every handle; *_destroy frees it.
+ *   Output arrays are caller-allocated host memory unless a name ends in _dev.
+ * - Potentials are log-scalings Lam = log u (the paper's lambda = eps * Lam,
+ *   Section 3.2).  Directed-edge order: edge e = (a, b) contributes
+ *   Lam_(a,b) (n_a values, over supp(a)) then Lam_(b,a) (n_b values).
+ * - Iterations are half-sweeps: one half-sweep updates one colour class (the
+ *   paper's counter t).  Every edge carries exactly one message per
+ *   half-sweep.
+ * - A handle may be used from one thread at a time.
+ */
+#ifndef GMOT_H
+#define GMOT_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- error codes ---------------------------------------------------------- */
+#define GMOT_OK         0
+#define GMOT_EINVAL    -1   /* not a tree (edge count, cycle, disconnected, self-loop,
+                               duplicate edge), n_j < 1, eps <= 0, tol < 0, bad option  */
+#define GMOT_EMARGINAL -2   /* a given marginal has a negative entry or |sum - 1| > 1e-9
+                               (the library never renormalises silently)               */
+#define GMOT_ENOMEM    -3   /* device or host allocation failed                         */
+#define GMOT_EDEVICE   -4   /* a HIP call failed, or no gfx950 device is present        */
+#define GMOT_ENOTSUP   -5   /* unsupported input (dim outside 1..3, unknown cost kind)   */
+#define GMOT_ESTATE    -6   /* handle in the wrong state (e.g. batch of mixed contexts) */
+
+/* ---- solve status (gmot_result.status) ------------------------------------ */
+#define GMOT_CONVERGED      0   /* stopping sum <= tol                               */
+#define GMOT_NOT_CONVERGED  1   /* max_steps half-sweeps done, sum still > tol       */
+#define GMOT_NONFINITE      2   /* a NaN/Inf appeared; the last finite state is kept */
+
+/* ---- cost kinds ------------------------------------------------------------ */
+#define GMOT_COST_SQEUCLID  0   /* C(x, y) = |x - y|^2 from the supports, on the fly */
+#define GMOT_COST_EXPLICIT  1   /* per-edge cost matrices given as float32           */
+
+/* ---- arithmetic of the message kernel -------------------------------------- */
+#define GMOT_PREC_FP32CORE  0   /* FP64 state and exponent arguments, FP32 exp2, FP64
+                                   accumulation of FP32 pair sums                     */
+#define GMOT_PREC_FP64      1   /* everything in FP64                                  */
+
+typedef struct gmot_ctx gmot_ctx;         /* device, stream, tile-tuning cache        */
+typedef struct gmot_problem gmot_problem; /* one tree instance resident in HBM        */
+typedef struct gmot_batch gmot_batch;     /* many instances solved in shared launches */
+
+/*
+ * One instance of the coupled problem (eq. ot_graph_pairwise_mass):
+ *   min sum_e <C_e, B_e> + eps * H(B_e | gamma_a (x) gamma_b)
+ * with B_e 1 = mu_a, B_e^T 1 = mu_b, mu_j given on constrained nodes (Gamma)
+ * and free (unit mass) elsewhere; gamma_j = mu_j on Gamma, 1 elsewhere
+ * (eq. jointdist).  A constrained node of degree r > 1 acts as r constrained
+ * leaves with the same marginal (it splits the tree, Section 3.1).
+ */
+typedef struct {
+  int32_t        n_nodes;     /* N >= 1                                                */
+  int32_t        n_edges;     /* must be N - 1                                         */
+  const int32_t* edges;       /* [2 * n_edges]: (a, b) pairs; B_e is n_a x n_b          */
+  const int32_t* sizes;       /* [N]: support size n_j >= 1                             */
+  int32_t        dim;         /* D in 1..3 (GMOT_COST_SQEUCLID)                          */
+  const double*  support;     /* [sum_j n_j * D], node-major, point-major; may be NULL
+                                 for GMOT_COST_EXPLICIT                                  */
+  const uint8_t* is_fixed;    /* [N]: 1 if j in Gamma                                   */
+  const double*  marginal;    /* given marginals of constrained nodes, concatenated in
+                                 node order ([sum_{j in Gamma} n_j]); entries >= 0 and
+                                 each block sums to 1 within 1e-9                        */
+  int32_t        cost_kind;   /* GMOT_COST_*                                             */
+  const float*   cost;        /* GMOT_COST_EXPLICIT: per-edge n_a x n_b row-major
+                                 matrices concatenated in edge order                    */
+  double         eps;         /* regularisation, > 0                                    */
+} gmot_tree_desc;
+
+typedef struct {
+  double  tol;          /* stop at the first half-sweep t >= 2 whose stopping sum
+                           (Algorithm tree_local_reg) is <= tol; >= 0                  */
+  int64_t max_steps;    /* at most this many half-sweep updates (> 0)                  */
+  int32_t check_every;  /* half-sweeps per launched graph (even, >= 2; 0 = default)   */
+  int32_t precision;    /* GMOT_PREC_*                                                  */
+  int32_t restart;      /* 1: start from u = 1 (cold); 0: continue from the held state
+                           (after gmot_set_potentials, or a previous solve)            */
+  int32_t timing;       /* 1: launch the half-sweeps directly on the stream (not as a
+                           captured graph) with HIP events around every message and
+                           node stage, and accumulate the stage durations (read with
+                           gmot_*_stats); 0: graph replay, no events                  */
+  int32_t skip_verify;  /* GMOT_PREC_FP32CORE only.  0 (default): the FP32-core loop
+                           runs until its own stopping sum is <= 0.8 * tol, then FP64
+                           half-sweeps (at most 256) continue until the FP64 stopping
+                           sum is <= tol, so convergence is judged in FP64.  1: stop
+                           on the FP32-core sum <= tol.                              */
+  int32_t reserved;
+} gmot_opts;
+
+/* Kernel timing accumulated by solves with opts.timing = 1 (since the last
+ * reset).  Only half-sweeps that did work for at least one instance count. */
+typedef struct {
+  double  msg_ms;          /* summed duration of message-kernel launches (ms)           */
+  int64_t msg_launches;    /* half-sweeps timed (one message stage per half-sweep)     */
+  double  node_ms;         /* summed duration of node-kernel launches (ms)              */
+  int64_t node_launches;
+  double  msg_pairs;       /* (x, y) pairs those message stages processed               */
+  int64_t graph_launches;  /* graph replays issued (timed or not)                        */
+} gmot_stats;
+
+typedef struct {
+  int32_t status;        /* GMOT_CONVERGED / GMOT_NOT_CONVERGED / GMOT_NONFINITE         */
+  int32_t reserved;
+  int64_t steps;         /* half-sweep updates applied by this call                      */
+  int64_t t;             /* the paper's counter after the call (state = before step t)  */
+  double  err_sum;       /* stopping sum of the returned state (as measured in-loop)     */
+  double  err_max;       /* largest single per-edge term of that sum                     */
+  double  seconds;       /* device time from the first half-sweep to the stop decision   */
+} gmot_result;
+
+/* Objective values of the current state, computed in FP64 on the device
+ * (definitions: dual = -eps * f(u, rho) of eq. tree_dual_mass_consv; primal =
+ * sum_e <C_e,B_e> + eps H(B_e|M_e) with the -1 term of eq. entropy_term;
+ * transport = sum_e <C_e, B_e>; the stopping sum over both colour classes). */
+typedef struct {
+  double dual, primal, transport, gap;   /* gap = primal - dual                        */
+  double err_sum, err_max;               /* stopping sum over every node, largest term */
+  double mass_min, mass_max;             /* extremes of ||B_e||_1 over edges            */
+  double rho_spread;                     /* max over free nodes of the spread in x of
+                                            sum_k Lam_(j,k)(x) (0 at exact iterates)   */
+  double scale;                          /* sum |eps <Lam, mu>| + sum |eps rho| + eps|E|,
+                                            the scale for relative dual comparisons    */
+} gmot_eval;
+
+/* ---- context ---------------------------------------------------------------- */
+/* Bind device `device`; `hip_stream` (a hipStream_t, may be NULL) is the stream
+ * every launch is ordered on; NULL makes the library create its own. */
+int  gmot_ctx_create(gmot_ctx** out, int device, void* hip_stream);
+void gmot_ctx_destroy(gmot_ctx* ctx);
+
+/* ---- problems ----------------------------------------------------------------- */
+/* Validate `desc` (GMOT_EINVAL / GMOT_EMARGINAL / GMOT_ENOTSUP) and copy it to the
+ * device.  The tree is 2-coloured by BFS from node 0; `first_color` (0 or 1, or -1
+ * for the class of node 0) selects which class the first half-sweep updates.
+ * The potentials start at Lam = 0 (u = 1). */
+int  gmot_problem_create(gmot_ctx* ctx, const gmot_tree_desc* desc, int32_t first_color,
+                         gmot_problem** out);
+void gmot_problem_destroy(gmot_problem* p);
+
+/* Run Algorithm tree_local_reg until the stopping sum of the current state is
+ * <= opts->tol (check-then-update: the returned state is the one that passed)
+ * or opts->max_steps updates were applied. */
+int  gmot_solve(gmot_problem* p, const gmot_opts* opts, gmot_result* out);
+
+/* FP64 objective values and the both-side stopping sum of the held state. */
+int  gmot_evaluate(gmot_problem* p, gmot_eval* out);
+
+/* Number of doubles in the potential vector (sum_e n_a + n_b). */
+int64_t gmot_potentials_size(const gmot_problem* p);
+/* Copy the held potentials out / in (directed-edge order above).  Setting them
+ * makes the next gmot_solve with restart = 0 continue from them (warm start,
+ * or resume from a checkpoint); the counter t restarts at 1. */
+int  gmot_get_potentials(gmot_problem* p, double* out);
+int  gmot_set_potentials(gmot_problem* p, const double* in);
+/* Device-pointer variants, ordered on the context stream, no implicit sync. */
+int  gmot_get_potentials_dev(gmot_problem* p, double* out_dev);
+int  gmot_set_potentials_dev(gmot_problem* p, const double* in_dev);
+
+/* Plan B_e (eq. bi-marginal_B_sol) of edge `edge`, n_a x n_b row-major, FP64. */
+int  gmot_get_coupling(gmot_problem* p, int32_t edge, double* out);
+/* q_bar_j: arithmetic mean over neighbours k of B_(j,k) 1 (n_j values). */
+int  gmot_get_node_marginal(gmot_problem* p, int32_t node, double* out);
+
+/* ---- batches ------------------------------------------------------------------ */
+/* Group `count` problems of one context so that every half-sweep of all of them
+ * runs in the same launches; instances converge independently (a converged
+ * instance stops updating and keeps its passing state). */
+int  gmot_batch_create(gmot_ctx* ctx, gmot_problem* const* probs, int32_t count, gmot_batch** out);
+void gmot_batch_destroy(gmot_batch* b);
+/* outs: [count] results, one per instance. */
+int  gmot_batch_solve(gmot_batch* b, const gmot_opts* opts, gmot_result* outs);
+
+/* ---- tile autotuning ------------------------------------------------------------ */
+/* Time candidate message-kernel tilings (rows per lane 1 or 2, and the number of
+ * blocks a half-sweep is split into through column splits) with evaluation
+ * half-sweeps that leave the held state untouched, and keep the fastest plan.
+ * The choice is cached in the context under the instances' shapes, so later
+ * problems or batches of the same shapes start with it.  Outputs may be NULL. */
+int  gmot_problem_autotune(gmot_problem* p, int32_t* rows_per_lane, int32_t* target_blocks, double* best_ms);
+int  gmot_batch_autotune(gmot_batch* b, int32_t* rows_per_lane, int32_t* target_blocks, double* best_ms);
+
+/* ---- diagnostics ----------------------------------------------------------- */
+/* Copy out (and, if reset != 0, clear) the kernel timing of a problem's own
+ * solves or of a batch's solves. */
+int  gmot_problem_stats(gmot_problem* p, gmot_stats* out, int32_t reset);
+int  gmot_batch_stats(gmot_batch* b, gmot_stats* out, int32_t reset);
+const char* gmot_strerror(int code);
+const char* gmot_last_error(void);
+/* Message-kernel tile shape of the most recent plan: rows per block, column
+ * splits chosen for the largest message, and blocks per half-sweep per class. */
+int  gmot_last_tiles(int32_t* rows_per_block, int32_t* max_splits, int32_t* blocks_c0, int32_t* blocks_c1);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* GMOT_H */

@@ -1,0 +1,252 @@
+"""Python binding of libgmot (gfx950 solver for tree-structured coupled OT).
+
+Every step of the solver runs in the HIP library; this module only converts
+arguments.  Problems are described by any object with the fields of
+``workloads.TreeProblem`` (n_nodes, edges, sizes, dim, support, is_fixed,
+marginal, eps, cost_kind, cost).  PyTorch is optional: pass a torch CUDA
+stream (or its integer handle) to order the library's work on it, and torch
+tensors to the ``*_dev`` methods for device-to-device transfers.
+"""
+from __future__ import annotations
+
+import ctypes as C
+from typing import List, Optional, Sequence
+
+import numpy as np
+
+from . import _lib
+from ._lib import (GMOT_OK, GMOT_EINVAL, GMOT_EMARGINAL, GMOT_ENOMEM, GMOT_EDEVICE, GMOT_ENOTSUP, GMOT_ESTATE,
+                   GMOT_CONVERGED, GMOT_NOT_CONVERGED, GMOT_NONFINITE, GMOT_COST_SQEUCLID, GMOT_COST_EXPLICIT,
+                   GMOT_PREC_FP32CORE, GMOT_PREC_FP64)
+
+STATUS_NAMES = {GMOT_CONVERGED: "converged", GMOT_NOT_CONVERGED: "not_converged", GMOT_NONFINITE: "nonfinite"}
+PRECISIONS = {"fp32core": GMOT_PREC_FP32CORE, "fp64": GMOT_PREC_FP64}
+
+
+class GmotError(RuntimeError):
+    def __init__(self, code: int, where: str):
+        lib = _lib.load()
+        msg = lib.gmot_last_error().decode(errors="replace")
+        super().__init__(f"{where}: {lib.gmot_strerror(code).decode()} ({code}): {msg}")
+        self.code = code
+
+
+def _check(code: int, where: str) -> None:
+    if code != GMOT_OK:
+        raise GmotError(code, where)
+
+
+def _stream_handle(stream) -> Optional[int]:
+    if stream is None:
+        return None
+    if isinstance(stream, int):
+        return stream
+    return int(getattr(stream, "cuda_stream"))
+
+
+class Context:
+    """A device and the stream all library work is ordered on."""
+
+    def __init__(self, device: int = 0, stream=None):
+        self._lib = _lib.load()
+        h = C.c_void_p()
+        _check(self._lib.gmot_ctx_create(C.byref(h), int(device), _stream_handle(stream)), "gmot_ctx_create")
+        self._h = h
+        self.device = int(device)
+
+    def close(self):
+        if getattr(self, "_h", None) and self._h.value:
+            self._lib.gmot_ctx_destroy(self._h)
+            self._h = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def _as(arr, dtype):
+    return np.ascontiguousarray(np.asarray(arr, dtype=dtype))
+
+
+class Problem:
+    """One tree instance resident in device memory."""
+
+    def __init__(self, ctx: Context, prob, first_color: int = -1):
+        self._lib = ctx._lib
+        self.ctx = ctx
+        self.n_nodes = int(prob.n_nodes)
+        self.edges = _as(prob.edges, np.int32).reshape(-1, 2)
+        self.sizes = _as(prob.sizes, np.int32)
+        keep = []
+        d = _lib.TreeDesc()
+        d.n_nodes = self.n_nodes
+        d.n_edges = int(self.edges.shape[0])
+        e = self.edges.reshape(-1)
+        keep.append(e)
+        d.edges = e.ctypes.data_as(_lib.I32P)
+        keep.append(self.sizes)
+        d.sizes = self.sizes.ctypes.data_as(_lib.I32P)
+        d.dim = int(prob.dim)
+        sup = _as(prob.support, np.float64).reshape(-1)
+        keep.append(sup)
+        d.support = sup.ctypes.data_as(_lib.DP)
+        fx = _as(prob.is_fixed, np.uint8)
+        keep.append(fx)
+        d.is_fixed = fx.ctypes.data_as(C.POINTER(C.c_uint8))
+        mg = _as(prob.marginal, np.float64).reshape(-1)
+        keep.append(mg)
+        d.marginal = mg.ctypes.data_as(_lib.DP)
+        d.cost_kind = int(getattr(prob, "cost_kind", GMOT_COST_SQEUCLID))
+        if d.cost_kind == GMOT_COST_EXPLICIT:
+            cst = np.ascontiguousarray(np.concatenate([np.asarray(c, dtype=np.float32).reshape(-1) for c in prob.cost]))
+            keep.append(cst)
+            d.cost = cst.ctypes.data_as(C.POINTER(C.c_float))
+        d.eps = float(prob.eps)
+        h = C.c_void_p()
+        _check(self._lib.gmot_problem_create(ctx._h, C.byref(d), int(first_color), C.byref(h)), "gmot_problem_create")
+        self._h = h
+        self.n_pot = int(self._lib.gmot_potentials_size(h))
+
+    def close(self):
+        if getattr(self, "_h", None) and self._h.value:
+            self._lib.gmot_problem_destroy(self._h)
+            self._h = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @staticmethod
+    def _opts(tol, max_steps, check_every, precision, restart, timing=False, verify=True) -> _lib.Opts:
+        o = _lib.Opts()
+        o.tol = float(tol)
+        o.max_steps = int(max_steps)
+        o.check_every = int(check_every)
+        o.precision = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
+        o.restart = 1 if restart else 0
+        o.timing = 1 if timing else 0
+        o.skip_verify = 0 if verify else 1
+        return o
+
+    @staticmethod
+    def _stats(fn, h, reset) -> dict:
+        st = _lib.Stats()
+        _check(fn(h, C.byref(st), 1 if reset else 0), "gmot_*_stats")
+        return {name: (float(getattr(st, name)) if "ms" in name or "pairs" in name else int(getattr(st, name)))
+                for name, _ in _lib.Stats._fields_}
+
+    def stats(self, reset: bool = False) -> dict:
+        """Kernel timing accumulated by solves run with timing=True."""
+        return self._stats(self._lib.gmot_problem_stats, self._h, reset)
+
+    @staticmethod
+    def _autotune(fn, h) -> dict:
+        r, t, ms = C.c_int32(), C.c_int32(), C.c_double()
+        _check(fn(h, C.byref(r), C.byref(t), C.byref(ms)), "gmot_*_autotune")
+        return {"rows_per_lane": r.value, "target_blocks": t.value, "ms_per_eval_sweep": ms.value}
+
+    def autotune(self) -> dict:
+        """Pick the fastest message-kernel tiling for this problem (state untouched)."""
+        return self._autotune(self._lib.gmot_problem_autotune, self._h)
+
+    @staticmethod
+    def _res(r: _lib.Result) -> dict:
+        return {"status": STATUS_NAMES.get(r.status, str(r.status)), "steps": int(r.steps), "t": int(r.t),
+                "err_sum": float(r.err_sum), "err_max": float(r.err_max), "seconds": float(r.seconds)}
+
+    def solve(self, tol: float = 1e-6, max_steps: int = 100000, check_every: int = 0, precision="fp32core",
+              restart: bool = True, timing: bool = False, verify: bool = True) -> dict:
+        o = self._opts(tol, max_steps, check_every, precision, restart, timing, verify)
+        r = _lib.Result()
+        _check(self._lib.gmot_solve(self._h, C.byref(o), C.byref(r)), "gmot_solve")
+        return self._res(r)
+
+    def evaluate(self) -> dict:
+        ev = _lib.Eval()
+        _check(self._lib.gmot_evaluate(self._h, C.byref(ev)), "gmot_evaluate")
+        return {name: float(getattr(ev, name)) for name, _ in _lib.Eval._fields_}
+
+    def potentials(self) -> np.ndarray:
+        out = np.empty(self.n_pot, dtype=np.float64)
+        _check(self._lib.gmot_get_potentials(self._h, out.ctypes.data_as(_lib.DP)), "gmot_get_potentials")
+        return out
+
+    def set_potentials(self, lam) -> None:
+        a = _as(lam, np.float64).reshape(-1)
+        if a.shape[0] != self.n_pot:
+            raise ValueError(f"expected {self.n_pot} potentials, got {a.shape[0]}")
+        _check(self._lib.gmot_set_potentials(self._h, a.ctypes.data_as(_lib.DP)), "gmot_set_potentials")
+
+    def potentials_dev(self, out_tensor) -> None:
+        """Copy the potentials into a float64 device tensor (stream-ordered)."""
+        if out_tensor.numel() != self.n_pot or str(out_tensor.dtype) != "torch.float64":
+            raise ValueError("need a float64 device tensor of potentials_size elements")
+        _check(self._lib.gmot_get_potentials_dev(self._h, C.c_void_p(out_tensor.data_ptr())), "gmot_get_potentials_dev")
+
+    def set_potentials_dev(self, in_tensor) -> None:
+        if in_tensor.numel() != self.n_pot or str(in_tensor.dtype) != "torch.float64":
+            raise ValueError("need a float64 device tensor of potentials_size elements")
+        _check(self._lib.gmot_set_potentials_dev(self._h, C.c_void_p(in_tensor.data_ptr())), "gmot_set_potentials_dev")
+
+    def coupling(self, edge: int) -> np.ndarray:
+        a, b = self.edges[edge]
+        out = np.empty((int(self.sizes[a]), int(self.sizes[b])), dtype=np.float64)
+        _check(self._lib.gmot_get_coupling(self._h, int(edge), out.ctypes.data_as(_lib.DP)), "gmot_get_coupling")
+        return out
+
+    def node_marginal(self, node: int) -> np.ndarray:
+        out = np.empty(int(self.sizes[node]), dtype=np.float64)
+        _check(self._lib.gmot_get_node_marginal(self._h, int(node), out.ctypes.data_as(_lib.DP)),
+               "gmot_get_node_marginal")
+        return out
+
+
+class Batch:
+    """Many problems advanced by the same launches."""
+
+    def __init__(self, ctx: Context, problems: Sequence[Problem]):
+        self._lib = ctx._lib
+        self.ctx = ctx
+        self.problems = list(problems)
+        arr = (C.c_void_p * len(self.problems))(*[p._h.value for p in self.problems])
+        h = C.c_void_p()
+        _check(self._lib.gmot_batch_create(ctx._h, arr, len(self.problems), C.byref(h)), "gmot_batch_create")
+        self._h = h
+
+    def close(self):
+        if getattr(self, "_h", None) and self._h.value:
+            self._lib.gmot_batch_destroy(self._h)
+            self._h = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def solve(self, tol: float = 1e-6, max_steps: int = 100000, check_every: int = 0, precision="fp32core",
+              restart: bool = True, timing: bool = False, verify: bool = True) -> List[dict]:
+        o = Problem._opts(tol, max_steps, check_every, precision, restart, timing, verify)
+        rs = (_lib.Result * len(self.problems))()
+        _check(self._lib.gmot_batch_solve(self._h, C.byref(o), rs), "gmot_batch_solve")
+        return [Problem._res(r) for r in rs]
+
+    def stats(self, reset: bool = False) -> dict:
+        return Problem._stats(self._lib.gmot_batch_stats, self._h, reset)
+
+    def autotune(self) -> dict:
+        return Problem._autotune(self._lib.gmot_batch_autotune, self._h)
+
+
+def last_tiles() -> dict:
+    lib = _lib.load()
+    v = [C.c_int32() for _ in range(4)]
+    lib.gmot_last_tiles(*[C.byref(x) for x in v])
+    return {"rows_per_block": v[0].value, "max_splits": v[1].value, "blocks_c0": v[2].value, "blocks_c1": v[3].value}
+
+
+__all__ = ["Context", "Problem", "Batch", "GmotError", "last_tiles", "STATUS_NAMES"]

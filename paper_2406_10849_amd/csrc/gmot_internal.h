@@ -1,0 +1,140 @@
+// Device-side tables shared by the HIP kernels and the host runtime of libgmot.
+//
+// Notation (Section 3 of the paper): every edge e = (a, b) carries two
+// log-scalings, Lam_(a,b) over supp(a) and Lam_(b,a) over supp(b) ("directed
+// edges").  At half-sweep t the class S being updated receives one message
+// per incident edge,
+//     m_{k->j}(x) = log sum_y K_(j,k)(x, y) u_(k,j)(y) gamma_k(y)
+//                 = LSE_y [ Lam_(k,j)(y) + log gamma_k(y) - C(x, y) / eps ],
+// which is log of the product K (u * gamma) in Theorem tree_dual_var.  The
+// message kernel evaluates it in base 2 as
+//     w(x, y) = a(y) + sum_d c_d(x) y_d,   a(y) = log2e (Lam + log gamma - |y|^2/eps),
+//     c_d(x) = 2 log2e x_d / eps,          m(x) = ln2 * log2 sum_y 2^w - |x|^2 / eps
+// for the squared-Euclidean cost, and w = log2e (Lam + log gamma - C / eps)
+// for explicit cost matrices.
+//
+// Potentials are double-buffered by update count: the k-th update of a node
+// writes slot k % 2.  Before half-sweep t the class updated at t holds its
+// value in slot ((t - 1) / 2) % 2 and the other class in slot (t / 2) % 2, so a
+// half-sweep that ends in "converged" has written only the slot nobody reads
+// and the state that passed the test stays intact (check-then-update).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <cstdint>
+
+namespace gmot {
+
+constexpr int kBlock = 256;          // threads per block, every kernel
+constexpr int kChunk = 256;          // columns staged in LDS per chunk (one per thread)
+constexpr double kLog2e = 1.44269504088896340736;
+constexpr double kLn2 = 0.693147180559945309417;
+
+enum Done : int { kRunning = 0, kConverged = 1, kMaxSteps = 2, kNonFinite = 3 };
+
+// One message m_{k->j}: rows index supp(j) ("dst"), columns index supp(k) ("src").
+struct MsgDesc {
+  const double* supp_dst;    // [n_dst * dim]
+  const double* supp_src;    // [n_src * dim]
+  const double* lam_src[2];  // Lam_(k,j) slots, [n_src]
+  const double* lg_src;      // log gamma_k, [n_src]
+  double* lam_dst[2];        // Lam_(j,k) slots, [n_dst]
+  double2* partial;          // [ns * n_dst]: (row max, sum of 2^(w - max)) per column split
+  double* mfull;             // merged message m_{k->j}, [n_dst], natural log
+  const float* cost;         // explicit cost stored src-major: cost[y * n_dst + x] = C_(j,k)(x, y)
+  int32_t n_dst, n_src, ns, inst;
+  int32_t dim, cost_kind, pad0, pad1;
+  double eps;
+};
+
+// One block of the message kernel: rows [row0, row0 + rows per block) of a
+// message, columns [col0, col0 + ncols), writing column split `split`.
+struct K1Item {
+  int32_t msg, row0, col0, ncols, split, pad0, pad1, pad2;
+};
+
+// One node of the class being updated; its deg incoming messages are
+// msgs[msg0 .. msg0 + deg) in ascending neighbour order.
+struct NodeItem {
+  int32_t inst, node, n, deg;
+  int32_t fixed, msg0, err_idx, pad;
+  const double* lg;          // log gamma_j, [n]
+  const double* mu;          // mu_j for constrained nodes, else NULL
+  double* abar;              // scratch [n]: mean_k m_{k->j}
+  double* qbar;              // scratch [n]: arithmetic mean_k q_(j,k)
+};
+
+// Per-instance loop state, written only by the last node block of a half-sweep.
+struct InstState {
+  long long t;               // next half-sweep; the held state is "before step t"
+  long long updates;         // updates applied since the solve started
+  long long max_updates;
+  double tol;
+  double err_sum, err_max;   // stopping sum of the last checked state
+  long long checked_t;       // the half-sweep whose state the sum above measures
+  long long min_check_t;     // the stop test applies from this half-sweep on
+  int done;                  // Done
+  int counter;               // node blocks finished in the current half-sweep
+  int node0[2], nnodes[2];   // node-error index ranges per class
+  unsigned long long clk_start, clk_stop;
+};
+
+struct Tables {
+  const MsgDesc* msgs;
+  const K1Item* items;       // items of one class and one dimension (kernel argument slice)
+  const NodeItem* nodes;     // node items of one class
+  InstState* inst;
+  double2* node_err;         // (sum, max) per node item
+  double4* node_eval;        // evaluation pass: (err sum, err max, <Lam,mu> or rho, spread)
+  int* ndone;                // number of instances that reached a final state
+  int colour;                // class whose items / nodes these are
+};
+
+// Pair pass of the evaluation (transport, entropy, mass of each plan).
+struct EdgeDesc {
+  const double* supp_a;  const double* supp_b;
+  const double* lam_a;   const double* lam_b;     // committed slots of Lam_(a,b), Lam_(b,a)
+  const double* lg_a;    const double* lg_b;
+  const float* cost;                              // explicit, row-major n_a x n_b, or NULL
+  int32_t n_a, n_b, dim, cost_kind;
+  double eps;
+};
+struct PairItem { int32_t edge, row0, col0, ncols; };
+
+// ---- launch wrappers (defined in gmot_kernels.hip) ----
+hipError_t launch_msg(const Tables& tb, int n_items, int dim, int rows_per_lane, bool fp64, int eval_src_slot,
+                      hipStream_t s);
+hipError_t launch_node(const Tables& tb, int n_nodes, int colour, int eval_dst_slot, hipStream_t s);
+hipError_t launch_stamp(InstState* inst, int count, hipStream_t s);
+hipError_t launch_pairs(const EdgeDesc* edges, const PairItem* items, int n_items, double4* out, hipStream_t s);
+hipError_t launch_coupling(const EdgeDesc* edge, double* out, size_t total, hipStream_t s);
+
+// ---- warm-start data movement (defined in gmot_mlp.hip) ----
+// One star instance: center node 0 (free), edges (0, l) for leaves l = 1..L in
+// that order, all supports of size n.  Potentials of edge l-1 sit at
+// base + 2n(l-1): Lam_(0,l) (n values) then Lam_(l,0) (n values).
+struct StarDesc {
+  const double* lg_leaf;     // log mu of leaves 1..L, concatenated [L * n]
+  double* lam0;              // slot-0 base (written by the warm start)
+  const double* lam_cur;     // base of the slot holding the committed leaf potentials
+};
+hipError_t launch_star_features(const StarDesc* stars, int count, int L, int n, float shift, float scale, float* x,
+                                hipStream_t s);
+hipError_t launch_star_targets(const StarDesc* stars, int count, int L, int n, float out_scale, float* t,
+                               hipStream_t s);
+hipError_t launch_star_apply(const StarDesc* stars, int count, int L, int n, const float* y, float out_scale,
+                             int* rejected, hipStream_t s);
+
+}  // namespace gmot
+
+#ifdef __cplusplus
+#include <map>
+// Host-side context shared by the runtime and the MLP host code.
+struct gmot_ctx {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  bool own_stream = false;
+  double clk_hz = 1.0e8;
+  std::map<uint64_t, std::pair<int, int>> tuned;  // shape key -> (rows per lane, target blocks)
+};
+#endif

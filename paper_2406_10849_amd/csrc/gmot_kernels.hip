@@ -1,0 +1,533 @@
+// gfx950 kernels of the bipartite iterative-scaling hot path.
+//
+//   k_msg   -- message log-sum-exp m_{k->j} over one (row tile, column split) of
+//              one message (the K u products of Theorem tree_dual_var, eq. q).
+//   k_node  -- per-node merge of the column splits, stopping-sum terms of the
+//              state before the update (Algorithm tree_local_reg, Lemma
+//              f_upper_bound_tree for the arithmetic mean), the update of
+//              eq. bipartite_tree_updates1/2 in its closed form (Proposition
+//              equi), and, in the last block of an instance, the stop decision.
+//   k_pairs -- FP64 transport / entropy / mass sums of every plan
+//              (eq. bi-marginal_B_sol, eq. ot_graph_pairwise_mass).
+//   k_coupling -- one plan written out in FP64.
+//
+// Arithmetic contract of the FP32-core message kernel: FP64 potentials, FP64
+// exponent arguments (w - row max), FP32 v_exp_f32 on the reduced argument,
+// pairs of FP32 terms added in FP32 and accumulated in FP64, FP64 log.
+#include "gmot_internal.h"
+
+#include <cmath>
+
+namespace gmot {
+
+namespace {
+
+__device__ inline double wave_sum(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+__device__ inline double wave_max(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
+  return v;
+}
+// Block-wide reductions over the 4 waves of a 256-thread block; every thread
+// gets the result.  `sh` needs 4 doubles; the leading barrier protects reuse.
+__device__ inline double block_sum(double v, double* sh) {
+  v = wave_sum(v);
+  __syncthreads();
+  if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = v;
+  __syncthreads();
+  return (sh[0] + sh[1]) + (sh[2] + sh[3]);
+}
+__device__ inline double block_max(double v, double* sh) {
+  v = wave_max(v);
+  __syncthreads();
+  if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = v;
+  __syncthreads();
+  return fmax(fmax(sh[0], sh[1]), fmax(sh[2], sh[3]));
+}
+
+__device__ inline float exp2_hw(float x) { return __builtin_amdgcn_exp2f(x); }
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// Message log-sum-exp.  Block = 4 waves; lane l of wave w owns rows
+// row0 + (w*R + r)*64 + l, r < R.  Columns are streamed through LDS in chunks;
+// within a chunk the row max is found first (pass 1) and the scaled sum taken
+// second (pass 2); across chunks the running sum is rescaled when the max
+// grows.  Output: (max, sum 2^(w - max)) per row for this column split.
+// ---------------------------------------------------------------------------
+template <int DIM, int R, bool F64, bool EXPL>
+__global__ __launch_bounds__(kBlock) void k_msg(Tables tb, int eval_src_slot) {
+  const int colour = tb.colour;
+  constexpr int CH = EXPL ? 32 : kChunk;            // columns per LDS chunk
+  constexpr int STR = EXPL ? 1 : (DIM == 1 ? 2 : 4); // doubles per staged column
+  constexpr int TM = 256 * R;                        // rows per block
+  __shared__ double s_col[CH * STR];
+  __shared__ float s_cost[EXPL ? CH * TM : 1];
+
+  const K1Item it = tb.items[blockIdx.x];
+  const MsgDesc* __restrict__ md = tb.msgs + it.msg;
+  int src_slot = eval_src_slot;
+  if (eval_src_slot < 0) {
+    const InstState* st = tb.inst + md->inst;
+    const long long t = st->t;
+    // finished instances, and instances whose next half-sweep updates the other class, sit out
+    if (st->done || ((t & 1) == 1) != (colour == 0)) return;
+    src_slot = (int)((t >> 1) & 1);
+  }
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int n_dst = md->n_dst;
+  const double eps = md->eps;
+  const double cxs = 2.0 * kLog2e / eps;
+  const double ces = -kLog2e / eps;
+  const double* __restrict__ lam = md->lam_src[src_slot];
+  const double* __restrict__ lg = md->lg_src;
+  const double* __restrict__ ys = md->supp_src;
+
+  int row[R];
+  double cx[R][DIM];
+  double Mrun[R], Srun[R];
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    row[r] = it.row0 + (wave * R + r) * 64 + lane;
+    const bool v = row[r] < n_dst;
+#pragma unroll
+    for (int d = 0; d < DIM; ++d) cx[r][d] = (v && !EXPL) ? cxs * md->supp_dst[(size_t)row[r] * DIM + d] : 0.0;
+    Mrun[r] = -INFINITY;
+    Srun[r] = 0.0;
+  }
+
+  for (int c0 = 0; c0 < it.ncols; c0 += CH) {
+    const int cn = min(CH, it.ncols - c0);
+    const int cpad = (cn + 7) & ~7;
+    __syncthreads();  // previous chunk fully consumed
+    if (threadIdx.x < cpad) {
+      double a = -INFINITY;
+      double y[DIM > 0 ? DIM : 1];
+#pragma unroll
+      for (int d = 0; d < DIM; ++d) y[d] = 0.0;
+      if (threadIdx.x < cn) {
+        const int col = it.col0 + c0 + threadIdx.x;
+        double base = lam[col] + lg[col];
+        if (!EXPL) {
+          double y2 = 0.0;
+#pragma unroll
+          for (int d = 0; d < DIM; ++d) {
+            y[d] = ys[(size_t)col * DIM + d];
+            y2 = fma(y[d], y[d], y2);
+          }
+          base -= y2 / eps;
+        }
+        a = kLog2e * base;
+      }
+      s_col[threadIdx.x * STR] = a;
+      if (!EXPL) {
+#pragma unroll
+        for (int d = 0; d < DIM; ++d) s_col[threadIdx.x * STR + 1 + d] = y[d];
+      }
+    }
+    if (EXPL) {
+      // cost tile, stored src-major: cost[y * n_dst + x]; coalesced over x
+      for (int c = 0; c < cpad; ++c) {
+        const int col = it.col0 + c0 + c;
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+          const int lr = r * 256 + threadIdx.x;
+          const int x = it.row0 + lr;
+          float v = 0.0f;
+          if (c < cn && x < n_dst) v = md->cost[(size_t)col * n_dst + x];
+          s_cost[c * TM + lr] = v;
+        }
+      }
+    }
+    __syncthreads();
+
+    // pass 1: chunk max per row
+    double Mc[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) Mc[r] = -INFINITY;
+#pragma unroll 8
+    for (int c = 0; c < cpad; ++c) {
+      const double a = s_col[c * STR];
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        double w = a;
+        if (EXPL) {
+          w = fma(ces, (double)s_cost[c * TM + (wave * R + r) * 64 + lane], w);
+        } else {
+#pragma unroll
+          for (int d = 0; d < DIM; ++d) w = fma(cx[r][d], s_col[c * STR + 1 + d], w);
+        }
+        Mc[r] = fmax(Mc[r], w);
+      }
+    }
+    double shift[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      if (Mc[r] > Mrun[r]) {
+        Srun[r] *= exp2(Mrun[r] - Mc[r]);  // 0 when Mrun = -inf and Srun = 0
+        Mrun[r] = Mc[r];
+      }
+      shift[r] = (Mrun[r] == -INFINITY) ? 0.0 : Mrun[r];
+    }
+
+    // pass 2: sum of 2^(w - max)
+#pragma unroll 4
+    for (int c = 0; c < cpad; c += 2) {
+      const double a0 = s_col[c * STR];
+      const double a1 = s_col[(c + 1) * STR];
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        double w0 = a0, w1 = a1;
+        if (EXPL) {
+          w0 = fma(ces, (double)s_cost[c * TM + (wave * R + r) * 64 + lane], w0);
+          w1 = fma(ces, (double)s_cost[(c + 1) * TM + (wave * R + r) * 64 + lane], w1);
+        } else {
+#pragma unroll
+          for (int d = 0; d < DIM; ++d) {
+            w0 = fma(cx[r][d], s_col[c * STR + 1 + d], w0);
+            w1 = fma(cx[r][d], s_col[(c + 1) * STR + 1 + d], w1);
+          }
+        }
+        if (F64) {
+          Srun[r] += exp2(w0 - shift[r]) + exp2(w1 - shift[r]);
+        } else {
+          const float p = exp2_hw((float)(w0 - shift[r])) + exp2_hw((float)(w1 - shift[r]));
+          Srun[r] += (double)p;
+        }
+      }
+    }
+  }
+
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    if (row[r] < n_dst) md->partial[(size_t)it.split * n_dst + row[r]] = make_double2(Mrun[r], Srun[r]);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Node update.  One block per node j of the class being updated.
+//   A: merge the column splits into m_{k->j}(x) (natural log), keep the
+//      mean message abar(x) and the arithmetic mean qbar(x) of
+//      q_(j,k)(x) = exp(Lam_(j,k)(x) + log gamma_j(x) + m_{k->j}(x)).
+//   B: stopping-sum terms of the held state: ||q_(j,k) - mu_j||_1 (fixed) or
+//      ||q_(j,k) - qbar_j||_1 (free), one per incident edge.
+//   C: update (skipped in evaluation mode):
+//        fixed  Lam_(j,k) = -m_{k->j}
+//        free   Lam_(j,k) = abar - LSE_x abar - m_{k->j}
+//   D: the last block of the instance sums the node terms and decides.
+// Evaluation mode (eval_dst_slot >= 0) reads the given slot, writes no
+// potentials and adds <Lam, mu> (fixed) or rho_j and its spread (free).
+// ---------------------------------------------------------------------------
+template <bool EVAL>
+__global__ __launch_bounds__(kBlock) void k_node(Tables tb, int colour, int eval_dst_slot) {
+  __shared__ double sh[4];
+  __shared__ int s_last;
+  const NodeItem nd = tb.nodes[blockIdx.x];
+  InstState* st = tb.inst + nd.inst;
+  long long t = 0;
+  int cur = eval_dst_slot, nxt = 0;
+  if (!EVAL) {
+    if (st->done) return;
+    t = st->t;
+    if (((t & 1) == 1) != (colour == 0)) return;  // this instance updates the other class next
+    cur = (int)(((t - 1) >> 1) & 1);
+    nxt = cur ^ 1;
+  }
+  const int n = nd.n, deg = nd.deg;
+  const MsgDesc* __restrict__ mds = tb.msgs + nd.msg0;
+  const double eps = mds[0].eps;
+  const int dim = mds[0].dim;
+  const bool sq = mds[0].cost_kind == 0;
+  const double* __restrict__ xs = mds[0].supp_dst;
+
+  // A
+  for (int x = threadIdx.x; x < n; x += kBlock) {
+    double x2 = 0.0;
+    if (sq)
+      for (int d = 0; d < dim; ++d) x2 = fma(xs[(size_t)x * dim + d], xs[(size_t)x * dim + d], x2);
+    const double lgx = nd.lg[x];
+    double asum = 0.0, qsum = 0.0;
+    for (int k = 0; k < deg; ++k) {
+      const MsgDesc& md = mds[k];
+      double Mx = -INFINITY;
+      for (int s = 0; s < md.ns; ++s) Mx = fmax(Mx, md.partial[(size_t)s * n + x].x);
+      double S = 0.0;
+      if (Mx > -INFINITY)
+        for (int s = 0; s < md.ns; ++s) {
+          const double2 p = md.partial[(size_t)s * n + x];
+          if (p.y > 0.0) S += p.y * exp2(p.x - Mx);
+        }
+      const double m = (S > 0.0) ? kLn2 * (Mx + log2(S)) - x2 / eps : -INFINITY;
+      md.mfull[x] = m;
+      asum += m;
+      qsum += exp(md.lam_dst[cur][x] + lgx + m);
+    }
+    nd.abar[x] = asum / deg;
+    nd.qbar[x] = qsum / deg;
+  }
+  __syncthreads();
+
+  // B
+  double e_sum = 0.0, e_max = 0.0;
+  for (int k = 0; k < deg; ++k) {
+    const MsgDesc& md = mds[k];
+    double part = 0.0;
+    for (int x = threadIdx.x; x < n; x += kBlock) {
+      const double q = exp(md.lam_dst[cur][x] + nd.lg[x] + md.mfull[x]);
+      const double ref = nd.fixed ? nd.mu[x] : nd.qbar[x];
+      part += fabs(q - ref);
+    }
+    const double tot = block_sum(part, sh);
+    e_sum += tot;
+    e_max = fmax(e_max, tot);
+  }
+
+  if (EVAL) {
+    double v0 = 0.0, lo = INFINITY, hi = -INFINITY;
+    if (nd.fixed) {
+      for (int k = 0; k < deg; ++k) {
+        const double* L = mds[k].lam_dst[cur];
+        for (int x = threadIdx.x; x < n; x += kBlock) {
+          const double l = L[x];
+          if (nd.mu[x] > 0.0 && isfinite(l)) v0 += l * nd.mu[x];
+        }
+      }
+      v0 = block_sum(v0, sh);
+      lo = hi = 0.0;
+    } else {
+      for (int x = threadIdx.x; x < n; x += kBlock) {
+        double tot = 0.0;
+        for (int k = 0; k < deg; ++k) tot += mds[k].lam_dst[cur][x];
+        v0 += tot;
+        lo = fmin(lo, tot);
+        hi = fmax(hi, tot);
+      }
+      v0 = block_sum(v0, sh) / n;
+      lo = -block_max(-lo, sh);
+      hi = block_max(hi, sh);
+    }
+    if (threadIdx.x == 0) tb.node_eval[nd.err_idx] = make_double4(e_sum, e_max, v0, hi - lo);
+    return;
+  }
+
+  // C
+  if (nd.fixed) {
+    for (int k = 0; k < deg; ++k) {
+      const MsgDesc& md = mds[k];
+      double* out = md.lam_dst[nxt];
+      for (int x = threadIdx.x; x < n; x += kBlock) out[x] = -md.mfull[x];
+    }
+  } else {
+    double mx = -INFINITY;
+    for (int x = threadIdx.x; x < n; x += kBlock) mx = fmax(mx, nd.abar[x]);
+    mx = block_max(mx, sh);
+    double s = 0.0;
+    for (int x = threadIdx.x; x < n; x += kBlock) s += exp(nd.abar[x] - mx);
+    s = block_sum(s, sh);
+    const double lse = mx + log(s);
+    for (int k = 0; k < deg; ++k) {
+      const MsgDesc& md = mds[k];
+      double* out = md.lam_dst[nxt];
+      for (int x = threadIdx.x; x < n; x += kBlock) out[x] = (nd.abar[x] - lse) - md.mfull[x];
+    }
+  }
+
+  // D
+  if (threadIdx.x == 0) {
+    tb.node_err[nd.err_idx] = make_double2(e_sum, e_max);
+    __threadfence();
+    const int old = atomicAdd(&st->counter, 1);
+    s_last = (old == st->nnodes[colour] - 1);
+  }
+  __syncthreads();
+  if (s_last && threadIdx.x == 0) {
+    __threadfence();
+    double E = 0.0, Em = 0.0;
+    const int i0 = st->node0[colour], cnt = st->nnodes[colour];
+    for (int i = 0; i < cnt; ++i) {
+      const double2 v = tb.node_err[i0 + i];
+      E += v.x;
+      Em = fmax(Em, v.y);
+    }
+    st->counter = 0;
+    bool stop = false;
+    if (!isfinite(E)) {
+      st->done = kNonFinite;
+      if (t >= 2) st->t = t - 1;   // roll back to the last state whose sum was finite
+      stop = true;
+    } else {
+      st->err_sum = E;
+      st->err_max = Em;
+      st->checked_t = t;
+      if (t >= st->min_check_t && E <= st->tol) {
+        st->done = kConverged;     // step t's writes went to the unread slot
+        stop = true;
+      } else {
+        st->t = t + 1;
+        st->updates += 1;
+        if (st->updates >= st->max_updates) {
+          st->done = kMaxSteps;
+          stop = true;
+        }
+      }
+    }
+    if (stop) {
+      st->clk_stop = wall_clock64();
+      __threadfence();
+      atomicAdd(tb.ndone, 1);
+    }
+  }
+}
+
+__global__ void k_stamp(InstState* inst, int count) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < count) inst[i].clk_start = wall_clock64();
+}
+
+// ---------------------------------------------------------------------------
+// FP64 pair pass: for each plan, sum_xy C B, sum_xy B (log B - log M - 1)
+// and sum_xy B over a (256 rows x ncols) tile.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(kBlock) void k_pairs(const EdgeDesc* edges, const PairItem* items, double4* out) {
+  __shared__ double sh[4];
+  __shared__ double s_b[kChunk];
+  __shared__ double s_y[kChunk * 3];
+  const PairItem it = items[blockIdx.x];
+  const EdgeDesc ed = edges[it.edge];
+  const int x = it.row0 + threadIdx.x;
+  const bool vx = x < ed.n_a;
+  const bool sq = ed.cost_kind == 0;
+  double ax = -INFINITY, lax = 0.0, xp[3] = {0.0, 0.0, 0.0};
+  if (vx) {
+    lax = ed.lam_a[x];
+    ax = lax + ed.lg_a[x];
+    if (sq)
+      for (int d = 0; d < ed.dim; ++d) xp[d] = ed.supp_a[(size_t)x * ed.dim + d];
+  }
+  double sT = 0.0, sH = 0.0, sM = 0.0;
+  for (int c0 = 0; c0 < it.ncols; c0 += kChunk) {
+    const int cn = min(kChunk, it.ncols - c0);
+    __syncthreads();
+    if (threadIdx.x < cn) {
+      const int y = it.col0 + c0 + threadIdx.x;
+      s_b[threadIdx.x] = ed.lam_b[y];
+      if (sq)
+        for (int d = 0; d < ed.dim; ++d) s_y[threadIdx.x * 3 + d] = ed.supp_b[(size_t)y * ed.dim + d];
+    }
+    __syncthreads();
+    if (vx) {
+      for (int c = 0; c < cn; ++c) {
+        const int y = it.col0 + c0 + c;
+        double C;
+        if (sq) {
+          C = 0.0;
+          for (int d = 0; d < ed.dim; ++d) {
+            const double df = xp[d] - s_y[c * 3 + d];
+            C = fma(df, df, C);
+          }
+        } else {
+          C = (double)ed.cost[(size_t)x * ed.n_b + y];
+        }
+        const double lgb = ed.lg_b[y];
+        const double lb = s_b[c];
+        const double logB = ax + lb + lgb - C / ed.eps;
+        const double B = exp(logB);
+        if (B > 0.0) {
+          sT += C * B;
+          sH += B * (lax + lb - C / ed.eps - 1.0);
+          sM += B;
+        }
+      }
+    }
+  }
+  sT = block_sum(sT, sh);
+  sH = block_sum(sH, sh);
+  sM = block_sum(sM, sh);
+  if (threadIdx.x == 0) out[blockIdx.x] = make_double4(sT, sH, sM, (double)it.edge);
+}
+
+__global__ __launch_bounds__(kBlock) void k_coupling(const EdgeDesc* edp, double* out) {
+  const EdgeDesc ed = *edp;
+  const size_t total = (size_t)ed.n_a * ed.n_b;
+  for (size_t i = (size_t)blockIdx.x * kBlock + threadIdx.x; i < total; i += (size_t)gridDim.x * kBlock) {
+    const int x = (int)(i / ed.n_b), y = (int)(i % ed.n_b);
+    double C;
+    if (ed.cost_kind == 0) {
+      C = 0.0;
+      for (int d = 0; d < ed.dim; ++d) {
+        const double df = ed.supp_a[(size_t)x * ed.dim + d] - ed.supp_b[(size_t)y * ed.dim + d];
+        C = fma(df, df, C);
+      }
+    } else {
+      C = (double)ed.cost[i];
+    }
+    out[i] = exp(ed.lam_a[x] + ed.lg_a[x] + ed.lam_b[y] + ed.lg_b[y] - C / ed.eps);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// launch wrappers
+// ---------------------------------------------------------------------------
+template <int DIM, int R, bool F64, bool EXPL>
+static hipError_t launch_msg_t(const Tables& tb, int n_items, int eval_src_slot, hipStream_t s) {
+  hipLaunchKernelGGL((k_msg<DIM, R, F64, EXPL>), dim3(n_items), dim3(kBlock), 0, s, tb, eval_src_slot);
+  return hipGetLastError();
+}
+
+template <int R, bool F64>
+static hipError_t launch_msg_r(const Tables& tb, int n_items, int dim, int eval_src_slot, hipStream_t s) {
+  switch (dim) {
+    case 0: return launch_msg_t<1, R, F64, true>(tb, n_items, eval_src_slot, s);  // explicit cost
+    case 1: return launch_msg_t<1, R, F64, false>(tb, n_items, eval_src_slot, s);
+    case 2: return launch_msg_t<2, R, F64, false>(tb, n_items, eval_src_slot, s);
+    case 3: return launch_msg_t<3, R, F64, false>(tb, n_items, eval_src_slot, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+hipError_t launch_msg(const Tables& tb, int n_items, int dim, int rows_per_lane, bool fp64, int eval_src_slot,
+                      hipStream_t s) {
+  if (n_items <= 0) return hipSuccess;
+  if (rows_per_lane == 2) {
+    return fp64 ? launch_msg_r<2, true>(tb, n_items, dim, eval_src_slot, s)
+                : launch_msg_r<2, false>(tb, n_items, dim, eval_src_slot, s);
+  }
+  return fp64 ? launch_msg_r<1, true>(tb, n_items, dim, eval_src_slot, s)
+              : launch_msg_r<1, false>(tb, n_items, dim, eval_src_slot, s);
+}
+
+hipError_t launch_node(const Tables& tb, int n_nodes, int colour, int eval_dst_slot, hipStream_t s) {
+  if (n_nodes <= 0) return hipSuccess;
+  if (eval_dst_slot >= 0)
+    hipLaunchKernelGGL((k_node<true>), dim3(n_nodes), dim3(kBlock), 0, s, tb, colour, eval_dst_slot);
+  else
+    hipLaunchKernelGGL((k_node<false>), dim3(n_nodes), dim3(kBlock), 0, s, tb, colour, -1);
+  return hipGetLastError();
+}
+
+hipError_t launch_stamp(InstState* inst, int count, hipStream_t s) {
+  if (count <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_stamp, dim3((count + kBlock - 1) / kBlock), dim3(kBlock), 0, s, inst, count);
+  return hipGetLastError();
+}
+
+hipError_t launch_pairs(const EdgeDesc* edges, const PairItem* items, int n_items, double4* out, hipStream_t s) {
+  if (n_items <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_pairs, dim3(n_items), dim3(kBlock), 0, s, edges, items, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_coupling(const EdgeDesc* edge, double* out, size_t total, hipStream_t s) {
+  size_t blocks = (total + kBlock - 1) / kBlock;
+  if (blocks > 4096) blocks = 4096;
+  if (blocks < 1) blocks = 1;
+  hipLaunchKernelGGL(k_coupling, dim3((unsigned)blocks), dim3(kBlock), 0, s, edge, out);
+  return hipGetLastError();
+}
+
+}  // namespace gmot

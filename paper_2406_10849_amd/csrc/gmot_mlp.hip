@@ -1,0 +1,583 @@
+// Learned warm start: a small fully connected network trained on the GPU by
+// these kernels (BF16 MFMA GEMMs with FP32 accumulation, FP32 master weights
+// and Adam), plus the data movement between star instances and the network.
+// The network is not part of the paper's method; it only initialises the
+// potentials of the bipartite iteration, which stays the judge of convergence.
+#include "gmot.h"
+#include "gmot_internal.h"
+
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstring>
+#include <memory>
+#include <string>
+#include <vector>
+
+namespace gmot {
+
+namespace {
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float floatx4 __attribute__((ext_vector_type(4)));
+
+// float -> bfloat16 bits, round to nearest even (finite inputs)
+__device__ inline uint16_t to_bf16(float f) {
+  uint32_t u = __float_as_uint(f);
+  u += 0x7FFFu + ((u >> 16) & 1u);
+  return (uint16_t)(u >> 16);
+}
+
+__device__ inline double block_sum_d(double v, double* sh) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  __syncthreads();
+  if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = v;
+  __syncthreads();
+  return (sh[0] + sh[1]) + (sh[2] + sh[3]);
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------------------
+// GEMM  C[m][n] = sum_k A(m,k) B(k,n), BF16 inputs, FP32 accumulation on
+// v_mfma_f32_16x16x32_bf16.  A(m,k) = TA ? A[k*lda+m] : A[m*lda+k];
+// B(k,n) = TB ? B[n*ldb+k] : B[k*ldb+n].  M, N, K, lda, ldb multiples of 8.
+// Block: 4 waves, 64x64 macro tile, each wave 32x32 = 2x2 MFMA tiles; K in
+// steps of 32 staged through LDS with k contiguous per row / column.
+// ---------------------------------------------------------------------------
+enum Epi : int { kStore = 0, kBiasRelu = 1, kBias = 2, kMaskRelu = 3 };
+
+struct GemmArgs {
+  const uint16_t* A;
+  const uint16_t* B;
+  int M, N, K, lda, ldb, ldc;
+  float* C;             // FP32 output (row-major, ldc)
+  uint16_t* Cq;         // optional BF16 copy of the output (same layout)
+  const float* bias;    // [N] for kBias / kBiasRelu
+  const float* mask;    // [M x ldc] for kMaskRelu: multiply by (mask > 0)
+};
+
+template <bool TA, bool TB, int EPI>
+__global__ __launch_bounds__(256) void k_gemm(GemmArgs g) {
+  constexpr int LDK = 40;  // 32 k values + 8 padding, rows stay 16-byte aligned
+  __shared__ __attribute__((aligned(16))) uint16_t As[64 * LDK];
+  __shared__ __attribute__((aligned(16))) uint16_t Bs[64 * LDK];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int m0 = blockIdx.y * 64, n0 = blockIdx.x * 64;
+  const int wm = (wave >> 1) * 32, wn = (wave & 1) * 32;
+  floatx4 acc[2][2];
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j) acc[i][j] = floatx4{0.f, 0.f, 0.f, 0.f};
+
+  for (int k0 = 0; k0 < g.K; k0 += 32) {
+    if (!TA) {
+      const int r = tid >> 2, kc = (tid & 3) * 8;
+      const int m = m0 + r, k = k0 + kc;
+      uint4 v = make_uint4(0, 0, 0, 0);
+      if (m < g.M && k < g.K) v = *reinterpret_cast<const uint4*>(g.A + (size_t)m * g.lda + k);
+      *reinterpret_cast<uint4*>(&As[r * LDK + kc]) = v;
+    } else {
+      const int k = tid >> 3, mc = (tid & 7) * 8;
+      const int kk = k0 + k, m = m0 + mc;
+      uint4 v = make_uint4(0, 0, 0, 0);
+      if (kk < g.K && m < g.M) v = *reinterpret_cast<const uint4*>(g.A + (size_t)kk * g.lda + m);
+      const uint16_t* e = reinterpret_cast<const uint16_t*>(&v);
+#pragma unroll
+      for (int i = 0; i < 8; ++i) As[(mc + i) * LDK + k] = e[i];
+    }
+    if (TB) {
+      const int r = tid >> 2, kc = (tid & 3) * 8;
+      const int n = n0 + r, k = k0 + kc;
+      uint4 v = make_uint4(0, 0, 0, 0);
+      if (n < g.N && k < g.K) v = *reinterpret_cast<const uint4*>(g.B + (size_t)n * g.ldb + k);
+      *reinterpret_cast<uint4*>(&Bs[r * LDK + kc]) = v;
+    } else {
+      const int k = tid >> 3, nc = (tid & 7) * 8;
+      const int kk = k0 + k, n = n0 + nc;
+      uint4 v = make_uint4(0, 0, 0, 0);
+      if (kk < g.K && n < g.N) v = *reinterpret_cast<const uint4*>(g.B + (size_t)kk * g.ldb + n);
+      const uint16_t* e = reinterpret_cast<const uint16_t*>(&v);
+#pragma unroll
+      for (int i = 0; i < 8; ++i) Bs[(nc + i) * LDK + k] = e[i];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int sm = 0; sm < 2; ++sm)
+#pragma unroll
+      for (int sn = 0; sn < 2; ++sn) {
+        const bf16x8 a = *reinterpret_cast<const bf16x8*>(&As[(wm + sm * 16 + (lane & 15)) * LDK + (lane >> 4) * 8]);
+        const bf16x8 b = *reinterpret_cast<const bf16x8*>(&Bs[(wn + sn * 16 + (lane & 15)) * LDK + (lane >> 4) * 8]);
+        acc[sm][sn] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, acc[sm][sn], 0, 0, 0);
+      }
+    __syncthreads();
+  }
+
+#pragma unroll
+  for (int sm = 0; sm < 2; ++sm)
+#pragma unroll
+    for (int sn = 0; sn < 2; ++sn)
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const int m = m0 + wm + sm * 16 + (lane >> 4) * 4 + i;
+        const int n = n0 + wn + sn * 16 + (lane & 15);
+        if (m >= g.M || n >= g.N) continue;
+        float v = acc[sm][sn][i];
+        const size_t o = (size_t)m * g.ldc + n;
+        if (EPI == kBias || EPI == kBiasRelu) v += g.bias[n];
+        if (EPI == kBiasRelu) v = fmaxf(v, 0.f);
+        if (EPI == kMaskRelu) v = g.mask[o] > 0.f ? v : 0.f;
+        g.C[o] = v;
+        if (g.Cq) g.Cq[o] = to_bf16(v);
+      }
+}
+
+__global__ void k_quantize(const float* x, uint16_t* q, size_t n) {
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
+    q[i] = to_bf16(x[i]);
+}
+
+// r = y - t; dY = 2 r / (B n_out) (FP32 and BF16); per-block partial sums of r^2.
+__global__ __launch_bounds__(256) void k_mse(const float* y, const float* t, size_t n, float scale, float* dy,
+                                             uint16_t* dyq, double* part) {
+  __shared__ double sh[4];
+  double s = 0.0;
+  for (size_t i = (size_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (size_t)gridDim.x * 256) {
+    const float r = y[i] - t[i];
+    s += (double)r * (double)r;
+    const float d = scale * r;
+    dy[i] = d;
+    dyq[i] = to_bf16(d);
+  }
+  s = block_sum_d(s, sh);
+  if (threadIdx.x == 0) part[blockIdx.x] = s;
+}
+
+__global__ __launch_bounds__(256) void k_sum_parts(const double* part, int n, double* out) {
+  __shared__ double sh[4];
+  double s = 0.0;
+  for (int i = threadIdx.x; i < n; i += 256) s += part[i];
+  s = block_sum_d(s, sh);
+  if (threadIdx.x == 0) *out = s;
+}
+
+// db[n] = sum over the batch of dz[b][n]
+__global__ void k_bias_grad(const float* dz, int B, int N, float* db) {
+  const int n = blockIdx.x * blockDim.x + threadIdx.x;
+  if (n >= N) return;
+  float s = 0.f;
+  for (int b = 0; b < B; ++b) s += dz[(size_t)b * N + n];
+  db[n] = s;
+}
+
+__global__ void k_adam(float* p, const float* g, float* m, float* v, size_t n, float lr, float b1, float b2,
+                       float eps, float c1, float c2) {
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) {
+    const float gi = g[i];
+    const float mi = b1 * m[i] + (1.f - b1) * gi;
+    const float vi = b2 * v[i] + (1.f - b2) * gi * gi;
+    m[i] = mi;
+    v[i] = vi;
+    p[i] -= lr * (mi / c1) / (sqrtf(vi / c2) + eps);
+  }
+}
+
+// ---- star warm-start data movement ------------------------------------------
+__global__ __launch_bounds__(256) void k_star_features(const StarDesc* st, int L, int n, float shift, float scale,
+                                                       float* x) {
+  const int i = blockIdx.x / L, l = blockIdx.x % L;
+  const double* lg = st[i].lg_leaf + (size_t)l * n;
+  float* xo = x + ((size_t)i * L + l) * n;
+  for (int p = threadIdx.x; p < n; p += 256) xo[p] = (float)((fmax(lg[p], -40.0) - (double)shift) * (double)scale);
+}
+
+__global__ __launch_bounds__(256) void k_star_targets(const StarDesc* st, int L, int n, float out_scale, float* t) {
+  __shared__ double sh[4];
+  const int i = blockIdx.x / L, l = blockIdx.x % L;
+  const double* src = st[i].lam_cur + (size_t)2 * n * l + n;
+  double s = 0.0;
+  for (int p = threadIdx.x; p < n; p += 256) s += src[p];
+  const double mean = block_sum_d(s, sh) / n;
+  float* to = t + ((size_t)i * L + l) * n;
+  for (int p = threadIdx.x; p < n; p += 256) to[p] = (float)((src[p] - mean) / (double)out_scale);
+}
+
+__global__ __launch_bounds__(256) void k_star_apply(const StarDesc* st, int L, int n, const float* y, float out_scale,
+                                                    int* rejected) {
+  __shared__ double sh[4];
+  const int i = blockIdx.x;
+  const float* yi = y + (size_t)i * L * n;
+  double bad = 0.0;
+  for (int p = threadIdx.x; p < L * n; p += 256) bad += isfinite(yi[p]) ? 0.0 : 1.0;
+  bad = block_sum_d(bad, sh);
+  double* base = st[i].lam0;
+  for (int l = 0; l < L; ++l) {
+    double s = 0.0;
+    if (bad == 0.0)
+      for (int p = threadIdx.x; p < n; p += 256) s += yi[(size_t)l * n + p];
+    const double mean = block_sum_d(s, sh) / n;
+    double* center = base + (size_t)2 * n * l;
+    double* leaf = center + n;
+    for (int p = threadIdx.x; p < n; p += 256) {
+      center[p] = 0.0;
+      leaf[p] = bad == 0.0 ? (double)out_scale * ((double)yi[(size_t)l * n + p] - mean) : 0.0;
+    }
+  }
+  if (threadIdx.x == 0 && bad != 0.0) atomicAdd(rejected, 1);
+}
+
+hipError_t launch_star_features(const StarDesc* stars, int count, int L, int n, float shift, float scale, float* x,
+                                hipStream_t s) {
+  if (count <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_star_features, dim3(count * L), dim3(256), 0, s, stars, L, n, shift, scale, x);
+  return hipGetLastError();
+}
+hipError_t launch_star_targets(const StarDesc* stars, int count, int L, int n, float out_scale, float* t,
+                               hipStream_t s) {
+  if (count <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_star_targets, dim3(count * L), dim3(256), 0, s, stars, L, n, out_scale, t);
+  return hipGetLastError();
+}
+hipError_t launch_star_apply(const StarDesc* stars, int count, int L, int n, const float* y, float out_scale,
+                             int* rejected, hipStream_t s) {
+  if (count <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_star_apply, dim3(count), dim3(256), 0, s, stars, L, n, y, out_scale, rejected);
+  return hipGetLastError();
+}
+
+}  // namespace gmot
+
+using namespace gmot;
+
+// ---------------------------------------------------------------------------
+// MLP host object
+// ---------------------------------------------------------------------------
+namespace {
+thread_local std::string g_mlp_error;
+int mfail(int code, const std::string& m) {
+  g_mlp_error = m;
+  return code;
+}
+#define MCHK(x)                                                                               \
+  do {                                                                                        \
+    hipError_t e_ = (x);                                                                      \
+    if (e_ != hipSuccess) return mfail(GMOT_EDEVICE, std::string(#x) + ": " + hipGetErrorString(e_)); \
+  } while (0)
+
+uint64_t splitmix(uint64_t& s) {
+  uint64_t z = (s += 0x9E3779B97F4A7C15ull);
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  return z ^ (z >> 31);
+}
+}  // namespace
+
+struct gmot_mlp {
+  gmot_ctx* ctx = nullptr;
+  int L = 0;
+  std::vector<int> w;
+  std::vector<int64_t> offW, offB;
+  int64_t nparams = 0;
+  void* arena = nullptr;
+  float *params = nullptr, *grad = nullptr, *m1 = nullptr, *m2 = nullptr;
+  std::vector<uint16_t*> Wq;  // BF16 copies of the weights
+  int64_t adam_t = 0;
+  // activations for up to `cap` rows
+  int cap = 0;
+  void* act_arena = nullptr;
+  std::vector<float*> H;      // H[0] unused; H[l] = layer l output (FP32), H[L] = y
+  std::vector<uint16_t*> Hq;  // Hq[l] = BF16 GEMM input of layer l + 1 (Hq[0] = x)
+  std::vector<float*> dZ;     // dZ[l] = gradient wrt pre-activation of layer l
+  std::vector<uint16_t*> dZq;
+  double* part = nullptr;
+  double* loss_dev = nullptr;
+  float *ws_x = nullptr, *ws_y = nullptr;  // warm-start workspaces (cap rows)
+
+  ~gmot_mlp() {
+    if (arena) (void)hipFree(arena);
+    if (act_arena) (void)hipFree(act_arena);
+  }
+
+  int ensure_cap(int B) {
+    if (B <= cap) return GMOT_OK;
+    if (act_arena) {
+      (void)hipStreamSynchronize(ctx->stream);
+      (void)hipFree(act_arena);
+      act_arena = nullptr;
+    }
+    int newcap = std::max(B, 64);
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+      size_t o = (off + 255) / 256 * 256;
+      off = o + std::max<size_t>(bytes, 1);
+      return o;
+    };
+    std::vector<size_t> oH(L + 1), oHq(L + 1), oZ(L + 1), oZq(L + 1);
+    for (int l = 0; l <= L; ++l) {
+      oH[l] = take(sizeof(float) * (size_t)newcap * w[l]);
+      oHq[l] = take(sizeof(uint16_t) * (size_t)newcap * w[l]);
+      oZ[l] = take(sizeof(float) * (size_t)newcap * w[l]);
+      oZq[l] = take(sizeof(uint16_t) * (size_t)newcap * w[l]);
+    }
+    const size_t oPart = take(sizeof(double) * 1024);
+    const size_t oLoss = take(sizeof(double));
+    const size_t oX = take(sizeof(float) * (size_t)newcap * w[0]);
+    const size_t oY = take(sizeof(float) * (size_t)newcap * w[L]);
+    if (hipMalloc(&act_arena, off) != hipSuccess) return mfail(GMOT_ENOMEM, "activation buffers");
+    char* b = (char*)act_arena;
+    H.assign(L + 1, nullptr);
+    Hq.assign(L + 1, nullptr);
+    dZ.assign(L + 1, nullptr);
+    dZq.assign(L + 1, nullptr);
+    for (int l = 0; l <= L; ++l) {
+      H[l] = (float*)(b + oH[l]);
+      Hq[l] = (uint16_t*)(b + oHq[l]);
+      dZ[l] = (float*)(b + oZ[l]);
+      dZq[l] = (uint16_t*)(b + oZq[l]);
+    }
+    part = (double*)(b + oPart);
+    loss_dev = (double*)(b + oLoss);
+    ws_x = (float*)(b + oX);
+    ws_y = (float*)(b + oY);
+    cap = newcap;
+    return GMOT_OK;
+  }
+
+  int refresh_wq() {
+    for (int l = 1; l <= L; ++l) {
+      const size_t n = (size_t)w[l] * w[l - 1];
+      hipLaunchKernelGGL(k_quantize, dim3((unsigned)std::min<size_t>(4096, (n + 255) / 256)), dim3(256), 0,
+                         ctx->stream, params + offW[l], Wq[l], n);
+      MCHK(hipGetLastError());
+    }
+    return GMOT_OK;
+  }
+};
+
+template <bool TA, bool TB, int EPI>
+static hipError_t gemm(const GemmArgs& g, hipStream_t s) {
+  dim3 grid((g.N + 63) / 64, (g.M + 63) / 64);
+  hipLaunchKernelGGL((k_gemm<TA, TB, EPI>), grid, dim3(256), 0, s, g);
+  return hipGetLastError();
+}
+
+static int mlp_forward(gmot_mlp* m, const float* x, int B) {
+  hipStream_t s = m->ctx->stream;
+  const size_t nx = (size_t)B * m->w[0];
+  hipLaunchKernelGGL(k_quantize, dim3((unsigned)std::min<size_t>(4096, (nx + 255) / 256)), dim3(256), 0, s, x,
+                     m->Hq[0], nx);
+  MCHK(hipGetLastError());
+  for (int l = 1; l <= m->L; ++l) {
+    GemmArgs g{};
+    g.A = m->Hq[l - 1];
+    g.B = m->Wq[l];
+    g.M = B;
+    g.N = m->w[l];
+    g.K = m->w[l - 1];
+    g.lda = m->w[l - 1];
+    g.ldb = m->w[l - 1];
+    g.ldc = m->w[l];
+    g.C = m->H[l];
+    g.Cq = l < m->L ? m->Hq[l] : nullptr;
+    g.bias = m->params + m->offB[l];
+    MCHK(l < m->L ? gemm<false, true, kBiasRelu>(g, s) : gemm<false, true, kBias>(g, s));
+  }
+  return GMOT_OK;
+}
+
+static int check_batch(gmot_mlp* m, int B) {
+  if (B < 8 || (B % 8) != 0) return mfail(GMOT_ENOTSUP, "batch must be a positive multiple of 8");
+  return m->ensure_cap(B);
+}
+
+extern "C" {
+
+int gmot_mlp_create(gmot_ctx* ctx, int32_t n_layers, const int32_t* widths, uint64_t seed, gmot_mlp** out) {
+  if (!ctx || !widths || !out || n_layers < 1) return mfail(GMOT_EINVAL, "bad network description");
+  for (int l = 0; l <= n_layers; ++l)
+    if (widths[l] < 8 || widths[l] % 8) return mfail(GMOT_ENOTSUP, "layer widths must be multiples of 8");
+  MCHK(hipSetDevice(ctx->device));
+  std::unique_ptr<gmot_mlp> m(new gmot_mlp());
+  m->ctx = ctx;
+  m->L = n_layers;
+  m->w.assign(widths, widths + n_layers + 1);
+  m->offW.assign(n_layers + 1, 0);
+  m->offB.assign(n_layers + 1, 0);
+  int64_t o = 0;
+  for (int l = 1; l <= n_layers; ++l) {
+    m->offW[l] = o;
+    o += (int64_t)m->w[l] * m->w[l - 1];
+    m->offB[l] = o;
+    o += m->w[l];
+  }
+  m->nparams = o;
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    size_t r = (off + 255) / 256 * 256;
+    off = r + std::max<size_t>(bytes, 1);
+    return r;
+  };
+  const size_t oP = take(sizeof(float) * o), oG = take(sizeof(float) * o), oM = take(sizeof(float) * o),
+               oV = take(sizeof(float) * o);
+  std::vector<size_t> oW(n_layers + 1, 0);
+  for (int l = 1; l <= n_layers; ++l) oW[l] = take(sizeof(uint16_t) * (size_t)m->w[l] * m->w[l - 1]);
+  if (hipMalloc(&m->arena, off) != hipSuccess) return mfail(GMOT_ENOMEM, "parameter buffers");
+  char* b = (char*)m->arena;
+  m->params = (float*)(b + oP);
+  m->grad = (float*)(b + oG);
+  m->m1 = (float*)(b + oM);
+  m->m2 = (float*)(b + oV);
+  m->Wq.assign(n_layers + 1, nullptr);
+  for (int l = 1; l <= n_layers; ++l) m->Wq[l] = (uint16_t*)(b + oW[l]);
+  // He-uniform weights from a splitmix64 stream, zero biases
+  std::vector<float> h(o, 0.f);
+  uint64_t st = seed;
+  for (int l = 1; l <= n_layers; ++l) {
+    const double lim = std::sqrt(6.0 / m->w[l - 1]);
+    for (int64_t i = 0; i < (int64_t)m->w[l] * m->w[l - 1]; ++i) {
+      const double u = (double)(splitmix(st) >> 11) * (1.0 / 9007199254740992.0);
+      h[m->offW[l] + i] = (float)((2.0 * u - 1.0) * lim);
+    }
+  }
+  int rc = gmot_mlp_set_params(m.get(), h.data());
+  if (rc) return rc;
+  *out = m.release();
+  return GMOT_OK;
+}
+
+void gmot_mlp_destroy(gmot_mlp* m) {
+  if (!m) return;
+  (void)hipStreamSynchronize(m->ctx->stream);
+  delete m;
+}
+
+int64_t gmot_mlp_num_params(const gmot_mlp* m) { return m ? m->nparams : -1; }
+
+int gmot_mlp_get_params(gmot_mlp* m, float* out) {
+  if (!m || !out) return mfail(GMOT_EINVAL, "null network or output");
+  MCHK(hipStreamSynchronize(m->ctx->stream));
+  MCHK(hipMemcpy(out, m->params, sizeof(float) * m->nparams, hipMemcpyDeviceToHost));
+  return GMOT_OK;
+}
+
+int gmot_mlp_set_params(gmot_mlp* m, const float* in) {
+  if (!m || !in) return mfail(GMOT_EINVAL, "null network or input");
+  MCHK(hipStreamSynchronize(m->ctx->stream));
+  MCHK(hipMemcpy(m->params, in, sizeof(float) * m->nparams, hipMemcpyHostToDevice));
+  MCHK(hipMemset(m->m1, 0, sizeof(float) * m->nparams));
+  MCHK(hipMemset(m->m2, 0, sizeof(float) * m->nparams));
+  m->adam_t = 0;
+  return m->refresh_wq();
+}
+
+int gmot_mlp_forward_dev(gmot_mlp* m, const float* x_dev, int32_t batch, float* y_dev) {
+  if (!m || !x_dev || !y_dev) return mfail(GMOT_EINVAL, "null argument");
+  int rc = check_batch(m, batch);
+  if (rc) return rc;
+  rc = mlp_forward(m, x_dev, batch);
+  if (rc) return rc;
+  MCHK(hipMemcpyAsync(y_dev, m->H[m->L], sizeof(float) * (size_t)batch * m->w[m->L], hipMemcpyDeviceToDevice,
+                      m->ctx->stream));
+  return GMOT_OK;
+}
+
+int gmot_mlp_loss_grad_dev(gmot_mlp* m, const float* x_dev, const float* t_dev, int32_t batch, double* loss,
+                           float* grad_dev) {
+  if (!m || !x_dev || !t_dev) return mfail(GMOT_EINVAL, "null argument");
+  int rc = check_batch(m, batch);
+  if (rc) return rc;
+  rc = mlp_forward(m, x_dev, batch);
+  if (rc) return rc;
+  hipStream_t s = m->ctx->stream;
+  const int L = m->L;
+  const size_t ny = (size_t)batch * m->w[L];
+  const int nblk = (int)std::min<size_t>(1024, (ny + 255) / 256);
+  hipLaunchKernelGGL(k_mse, dim3(nblk), dim3(256), 0, s, m->H[L], t_dev, ny, (float)(2.0 / (double)ny), m->dZ[L],
+                     m->dZq[L], m->part);
+  MCHK(hipGetLastError());
+  hipLaunchKernelGGL(k_sum_parts, dim3(1), dim3(256), 0, s, m->part, nblk, m->loss_dev);
+  MCHK(hipGetLastError());
+  for (int l = L; l >= 1; --l) {
+    // dW_l = dZ_l^T H_{l-1}: A(m=o, k=b) = dZq[b][o] (transposed), B(k=b, n=i) = Hq[b][i]
+    GemmArgs gw{};
+    gw.A = m->dZq[l];
+    gw.B = m->Hq[l - 1];
+    gw.M = m->w[l];
+    gw.N = m->w[l - 1];
+    gw.K = batch;
+    gw.lda = m->w[l];
+    gw.ldb = m->w[l - 1];
+    gw.ldc = m->w[l - 1];
+    gw.C = m->grad + m->offW[l];
+    MCHK((gemm<true, false, kStore>(gw, s)));
+    hipLaunchKernelGGL(k_bias_grad, dim3((m->w[l] + 255) / 256), dim3(256), 0, s, m->dZ[l], batch, m->w[l],
+                       m->grad + m->offB[l]);
+    MCHK(hipGetLastError());
+    if (l > 1) {
+      // dZ_{l-1} = (dZq_l W_l) * (H_{l-1} > 0): A = dZq [b][o], B(k=o, n=i) = Wq[o][i]
+      GemmArgs gx{};
+      gx.A = m->dZq[l];
+      gx.B = m->Wq[l];
+      gx.M = batch;
+      gx.N = m->w[l - 1];
+      gx.K = m->w[l];
+      gx.lda = m->w[l];
+      gx.ldb = m->w[l - 1];
+      gx.ldc = m->w[l - 1];
+      gx.C = m->dZ[l - 1];
+      gx.Cq = m->dZq[l - 1];
+      gx.mask = m->H[l - 1];
+      MCHK((gemm<false, false, kMaskRelu>(gx, s)));
+    }
+  }
+  if (grad_dev)
+    MCHK(hipMemcpyAsync(grad_dev, m->grad, sizeof(float) * m->nparams, hipMemcpyDeviceToDevice, s));
+  if (loss) {
+    double sum = 0.0;
+    MCHK(hipMemcpyAsync(&sum, m->loss_dev, sizeof(double), hipMemcpyDeviceToHost, s));
+    MCHK(hipStreamSynchronize(s));
+    *loss = sum / (double)ny;
+  }
+  return GMOT_OK;
+}
+
+int gmot_mlp_adam_step(gmot_mlp* m, float lr, float beta1, float beta2, float adam_eps) {
+  if (!m) return mfail(GMOT_EINVAL, "null network");
+  if (!(lr > 0.f) || !(beta1 >= 0.f && beta1 < 1.f) || !(beta2 >= 0.f && beta2 < 1.f) || !(adam_eps > 0.f))
+    return mfail(GMOT_EINVAL, "bad Adam hyper-parameters");
+  m->adam_t += 1;
+  const float c1 = 1.f - std::pow(beta1, (float)m->adam_t);
+  const float c2 = 1.f - std::pow(beta2, (float)m->adam_t);
+  hipLaunchKernelGGL(k_adam, dim3((unsigned)std::min<int64_t>(4096, (m->nparams + 255) / 256)), dim3(256), 0,
+                     m->ctx->stream, m->params, m->grad, m->m1, m->m2, (size_t)m->nparams, lr, beta1, beta2,
+                     adam_eps, c1, c2);
+  MCHK(hipGetLastError());
+  return m->refresh_wq();
+}
+
+int gmot_mlp_train_step_dev(gmot_mlp* m, const float* x_dev, const float* t_dev, int32_t batch, float lr,
+                            double* loss) {
+  int rc = gmot_mlp_loss_grad_dev(m, x_dev, t_dev, batch, loss, nullptr);
+  if (rc) return rc;
+  return gmot_mlp_adam_step(m, lr, 0.9f, 0.999f, 1e-8f);
+}
+
+const char* gmot_mlp_last_error(void) { return g_mlp_error.c_str(); }
+
+}  // extern "C"
+
+// Internal accessors for the runtime's warm-start entry point.
+int gmot_mlp_widths(const gmot_mlp* m, int* n_in, int* n_out) {
+  *n_in = m->w[0];
+  *n_out = m->w[m->L];
+  return GMOT_OK;
+}
+int gmot_mlp_workspace(gmot_mlp* m, int B, float** x, float** y) {
+  int rc = m->ensure_cap(B);
+  if (rc) return rc;
+  *x = m->ws_x;
+  *y = m->ws_y;
+  return GMOT_OK;
+}

@@ -1,0 +1,1293 @@
+// Host runtime of libgmot: validation, device arenas, work lists, the
+// graph-captured half-sweep loop and the FP64 evaluation pass.
+//
+// Schedule (Algorithm tree_local_reg): the tree is 2-coloured by BFS from node
+// 0; class 0 ("S1", the class of node 0 unless the caller picks the other one)
+// is updated on odd half-sweeps, class 1 on even ones.  A half-sweep is two
+// launches: the message kernel over every (row tile, column split) of every
+// message into the class, then the node kernel over the class's nodes.  `k`
+// half-sweeps are captured in one hipGraph; the host replays it two deep and
+// polls a pinned 4-byte counter of finished instances between replays.  Once an
+// instance has stopped, its kernels return at entry, so overshooting replays
+// cost only empty launches.
+#include "gmot.h"
+#include "gmot_internal.h"
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <deque>
+#include <map>
+#include <memory>
+#include <string>
+#include <vector>
+
+using namespace gmot;
+
+namespace {
+
+thread_local std::string g_last_error;
+struct TileStats { int rows = 0, max_splits = 0, blocks[2] = {0, 0}; };
+thread_local TileStats g_tiles;
+
+int fail(int code, const std::string& msg) {
+  g_last_error = msg;
+  return code;
+}
+
+#define HIPCHK(x)                                                                     \
+  do {                                                                                \
+    hipError_t e_ = (x);                                                              \
+    if (e_ != hipSuccess) return fail(GMOT_EDEVICE, std::string(#x) + ": " + hipGetErrorString(e_)); \
+  } while (0)
+
+int64_t ceil_div(int64_t a, int64_t b) { return (a + b - 1) / b; }
+
+size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
+
+}  // namespace
+
+struct Plan;
+
+
+struct gmot_problem {
+  gmot_ctx* ctx = nullptr;
+  int N = 0, E = 0, dim = 1, cost_kind = 0, first_color = 0;
+  double eps = 1.0;
+  std::vector<int> sizes, edges;
+  std::vector<uint8_t> fixed;
+  std::vector<std::vector<int>> nbrs;      // ascending
+  std::vector<std::vector<int>> nbr_de;    // directed edge id of (j, nbrs[j][i])
+  std::vector<int> colour;                 // 0 = first class
+  std::vector<int64_t> node_off;           // [N+1] point offsets
+  std::vector<int64_t> de_off;             // [2E+1]; de 2e = (a,b), 2e+1 = (b,a)
+  std::vector<int64_t> cost_off;           // [E+1] offsets of C_e; C_e^T follows all C_e
+  int64_t total_pts = 0, total_de = 0, total_cost = 0;
+  void* arena = nullptr;
+  double* d_support = nullptr;
+  double* d_lg = nullptr;
+  double* d_mu = nullptr;
+  double* d_lam[2] = {nullptr, nullptr};
+  double* d_mfull = nullptr;
+  double* d_abar = nullptr;
+  double* d_qbar = nullptr;
+  float* d_cost = nullptr;
+  int64_t t = 1;
+  Plan* plan = nullptr;
+
+  int de_of(int j, int k) const {
+    for (size_t i = 0; i < nbrs[j].size(); ++i)
+      if (nbrs[j][i] == k) return nbr_de[j][i];
+    return -1;
+  }
+  // slot holding the committed value of class c's potentials
+  int slot_of_class(int c) const { return c == 0 ? (int)((t / 2) & 1) : (int)(((t - 1) / 2) & 1); }
+};
+
+// A captured run of k half-sweeps.  The timed variant is not captured: it
+// launches the k half-sweeps directly, recording one of two alternating chains
+// of 2k + 1 events (before the message stage of step i, between message and
+// node stage, after the node stage), so one chain can be read back while the
+// next replay runs.
+struct GraphEntry {
+  bool fp64 = false, timed = false;
+  int start = 0, k = 0;
+  hipGraphExec_t exec[2] = {nullptr, nullptr};
+  std::vector<hipEvent_t> ev[2];
+};
+
+struct Plan {
+  gmot_ctx* ctx = nullptr;
+  std::vector<gmot_problem*> probs;
+  int R = 1;
+  int target_blocks = 1536;
+  std::vector<MsgDesc> msgs;
+  std::vector<K1Item> items[2][4];  // [class][0 = explicit, 1..3 = dim]
+  std::vector<NodeItem> nodes[2];
+  std::vector<InstState> inst;
+  int total_nodes = 0;
+  void* arena = nullptr;
+  MsgDesc* d_msgs = nullptr;
+  K1Item* d_items[2][4] = {};
+  NodeItem* d_nodes[2] = {};
+  InstState* d_inst = nullptr;
+  double2* d_node_err = nullptr;
+  double4* d_node_eval = nullptr;
+  int* d_ndone = nullptr;
+  double2* d_partial = nullptr;
+  int* h_ndone = nullptr;  // pinned, two mailboxes
+  std::vector<GraphEntry> graphs;
+  TileStats stats;
+  std::vector<double> inst_pairs[2];  // (x, y) pairs of each instance's messages into class c
+  gmot_stats acc{};
+
+  ~Plan() {
+    for (auto& g : graphs)
+      for (int i = 0; i < 2; ++i) {
+        if (g.exec[i]) (void)hipGraphExecDestroy(g.exec[i]);
+        for (hipEvent_t e : g.ev[i]) (void)hipEventDestroy(e);
+      }
+    if (arena) (void)hipFree(arena);
+    if (h_ndone) (void)hipHostFree(h_ndone);
+  }
+
+  Tables tables(int c, int dk) const {
+    Tables tb{};
+    tb.msgs = d_msgs;
+    tb.items = dk >= 0 ? d_items[c][dk] : nullptr;
+    tb.nodes = d_nodes[c];
+    tb.inst = d_inst;
+    tb.node_err = d_node_err;
+    tb.node_eval = d_node_eval;
+    tb.ndone = d_ndone;
+    tb.colour = c;
+    return tb;
+  }
+
+  // One half-sweep for class c; with `ev`, events ev[0] before the message
+  // stage, ev[1] between the stages and ev[2] after the node stage.
+  hipError_t launch_tstep(int c, bool fp64, hipStream_t s, const hipEvent_t* ev = nullptr) const {
+    hipError_t e;
+    if (ev && (e = hipEventRecord(ev[0], s)) != hipSuccess) return e;
+    for (int dk = 0; dk < 4; ++dk) {
+      if (items[c][dk].empty()) continue;
+      e = launch_msg(tables(c, dk), (int)items[c][dk].size(), dk, R, fp64, -1, s);
+      if (e != hipSuccess) return e;
+    }
+    if (ev && (e = hipEventRecord(ev[1], s)) != hipSuccess) return e;
+    e = launch_node(tables(c, -1), (int)nodes[c].size(), c, -1, s);
+    if (e != hipSuccess) return e;
+    if (ev && (e = hipEventRecord(ev[2], s)) != hipSuccess) return e;
+    return hipSuccess;
+  }
+};
+
+// ---------------------------------------------------------------------------
+// plan construction
+// ---------------------------------------------------------------------------
+static int build_plan(gmot_ctx* ctx, const std::vector<gmot_problem*>& probs, int R, int target_blocks,
+                      Plan** out) {
+  std::unique_ptr<Plan> pl(new Plan());
+  pl->ctx = ctx;
+  pl->probs = probs;
+  pl->R = R;
+  pl->target_blocks = target_blocks;
+  const int TM = 256 * R;
+
+  // messages and node items (class-major within each instance)
+  std::vector<int> msg_class;
+  int err_counter = 0;
+  for (size_t i = 0; i < probs.size(); ++i) {
+    gmot_problem* p = probs[i];
+    InstState st{};
+    for (int c = 0; c < 2; ++c) {
+      st.node0[c] = err_counter;
+      int cnt = 0;
+      for (int j = 0; j < p->N; ++j) {
+        if (p->colour[j] != c || p->nbrs[j].empty()) continue;
+        NodeItem nd{};
+        nd.inst = (int)i;
+        nd.node = j;
+        nd.n = p->sizes[j];
+        nd.deg = (int)p->nbrs[j].size();
+        nd.fixed = p->fixed[j];
+        nd.msg0 = (int)pl->msgs.size();
+        nd.err_idx = err_counter++;
+        nd.lg = p->d_lg + p->node_off[j];
+        nd.mu = p->fixed[j] ? p->d_mu + p->node_off[j] : nullptr;
+        nd.abar = p->d_abar + p->node_off[j];
+        nd.qbar = p->d_qbar + p->node_off[j];
+        pl->nodes[c].push_back(nd);
+        ++cnt;
+        for (size_t q = 0; q < p->nbrs[j].size(); ++q) {
+          const int k = p->nbrs[j][q];
+          const int de_dst = p->nbr_de[j][q];  // (j,k)
+          const int de_src = de_dst ^ 1;       // (k,j)
+          MsgDesc md{};
+          md.supp_dst = p->d_support + p->node_off[j] * p->dim;
+          md.supp_src = p->d_support + p->node_off[k] * p->dim;
+          for (int s = 0; s < 2; ++s) {
+            md.lam_src[s] = p->d_lam[s] + p->de_off[de_src];
+            md.lam_dst[s] = p->d_lam[s] + p->de_off[de_dst];
+          }
+          md.lg_src = p->d_lg + p->node_off[k];
+          md.mfull = p->d_mfull + p->de_off[de_dst];
+          if (p->cost_kind == GMOT_COST_EXPLICIT) {
+            const int e = de_dst >> 1;
+            // stored src-major: dst = b uses C_e (rows a = src), dst = a uses C_e^T
+            const bool dst_is_b = (de_dst & 1) == 1;
+            md.cost = dst_is_b ? p->d_cost + p->cost_off[e] : p->d_cost + p->total_cost + p->cost_off[e];
+          }
+          md.n_dst = p->sizes[j];
+          md.n_src = p->sizes[k];
+          md.inst = (int)i;
+          md.dim = p->dim;
+          md.cost_kind = p->cost_kind;
+          md.eps = p->eps;
+          pl->msgs.push_back(md);
+          msg_class.push_back(c);
+        }
+      }
+      st.nnodes[c] = cnt;
+    }
+    pl->inst.push_back(st);
+  }
+  pl->total_nodes = err_counter;
+  for (int c = 0; c < 2; ++c) pl->inst_pairs[c].assign(probs.size(), 0.0);
+  for (size_t m = 0; m < pl->msgs.size(); ++m)
+    pl->inst_pairs[msg_class[m]][pl->msgs[m].inst] += (double)pl->msgs[m].n_dst * pl->msgs[m].n_src;
+
+  // column splits: enough blocks per class to fill the device
+  int64_t row_tiles[2] = {0, 0};
+  for (size_t m = 0; m < pl->msgs.size(); ++m) row_tiles[msg_class[m]] += ceil_div(pl->msgs[m].n_dst, TM);
+  int64_t want_ns[2];
+  for (int c = 0; c < 2; ++c)
+    want_ns[c] = row_tiles[c] > 0 ? std::max<int64_t>(1, (target_blocks + row_tiles[c] / 2) / row_tiles[c]) : 1;
+  int64_t partial_total = 0;
+  std::vector<int64_t> partial_off(pl->msgs.size());
+  pl->stats = TileStats();
+  pl->stats.rows = TM;
+  for (size_t m = 0; m < pl->msgs.size(); ++m) {
+    MsgDesc& md = pl->msgs[m];
+    const int c = msg_class[m];
+    int64_t ns = std::min<int64_t>(want_ns[c], std::max<int64_t>(1, ceil_div(md.n_src, 64)));
+    const int64_t cw = ceil_div(md.n_src, ns);
+    ns = ceil_div(md.n_src, cw);
+    md.ns = (int)ns;
+    partial_off[m] = partial_total;
+    partial_total += ns * md.n_dst;
+    pl->stats.max_splits = std::max(pl->stats.max_splits, (int)ns);
+    const int dk = md.cost_kind == GMOT_COST_EXPLICIT ? 0 : md.dim;
+    for (int64_t rt = 0; rt < ceil_div(md.n_dst, TM); ++rt)
+      for (int64_t s = 0; s < ns; ++s) {
+        K1Item it{};
+        it.msg = (int)m;
+        it.row0 = (int)(rt * TM);
+        it.col0 = (int)(s * cw);
+        it.ncols = (int)std::min<int64_t>(cw, md.n_src - s * cw);
+        it.split = (int)s;
+        pl->items[c][dk].push_back(it);
+      }
+  }
+  for (int c = 0; c < 2; ++c) {
+    pl->stats.blocks[c] = 0;
+    for (int dk = 0; dk < 4; ++dk) pl->stats.blocks[c] += (int)pl->items[c][dk].size();
+  }
+
+  // one device allocation for every table
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    size_t o = align_up(off, 256);
+    off = o + std::max<size_t>(bytes, 1);
+    return o;
+  };
+  const size_t o_msgs = take(sizeof(MsgDesc) * pl->msgs.size());
+  size_t o_items[2][4];
+  for (int c = 0; c < 2; ++c)
+    for (int dk = 0; dk < 4; ++dk) o_items[c][dk] = take(sizeof(K1Item) * pl->items[c][dk].size());
+  size_t o_nodes[2];
+  for (int c = 0; c < 2; ++c) o_nodes[c] = take(sizeof(NodeItem) * pl->nodes[c].size());
+  const size_t o_inst = take(sizeof(InstState) * pl->inst.size());
+  const size_t o_err = take(sizeof(double2) * std::max(1, pl->total_nodes));
+  const size_t o_eval = take(sizeof(double4) * std::max(1, pl->total_nodes));
+  const size_t o_ndone = take(sizeof(int) * 4);
+  const size_t o_part = take(sizeof(double2) * std::max<int64_t>(1, partial_total));
+  const size_t total = off;
+  if (hipMalloc(&pl->arena, total) != hipSuccess) return fail(GMOT_ENOMEM, "plan arena allocation failed");
+  char* base = (char*)pl->arena;
+  pl->d_msgs = (MsgDesc*)(base + o_msgs);
+  for (int c = 0; c < 2; ++c)
+    for (int dk = 0; dk < 4; ++dk) pl->d_items[c][dk] = (K1Item*)(base + o_items[c][dk]);
+  for (int c = 0; c < 2; ++c) pl->d_nodes[c] = (NodeItem*)(base + o_nodes[c]);
+  pl->d_inst = (InstState*)(base + o_inst);
+  pl->d_node_err = (double2*)(base + o_err);
+  pl->d_node_eval = (double4*)(base + o_eval);
+  pl->d_ndone = (int*)(base + o_ndone);
+  pl->d_partial = (double2*)(base + o_part);
+  for (size_t m = 0; m < pl->msgs.size(); ++m) pl->msgs[m].partial = pl->d_partial + partial_off[m];
+
+  hipStream_t s = ctx->stream;
+  HIPCHK(hipMemcpyAsync(pl->d_msgs, pl->msgs.data(), sizeof(MsgDesc) * pl->msgs.size(), hipMemcpyHostToDevice, s));
+  for (int c = 0; c < 2; ++c) {
+    for (int dk = 0; dk < 4; ++dk)
+      if (!pl->items[c][dk].empty())
+        HIPCHK(hipMemcpyAsync(pl->d_items[c][dk], pl->items[c][dk].data(), sizeof(K1Item) * pl->items[c][dk].size(),
+                              hipMemcpyHostToDevice, s));
+    if (!pl->nodes[c].empty())
+      HIPCHK(hipMemcpyAsync(pl->d_nodes[c], pl->nodes[c].data(), sizeof(NodeItem) * pl->nodes[c].size(),
+                            hipMemcpyHostToDevice, s));
+  }
+  HIPCHK(hipHostMalloc((void**)&pl->h_ndone, sizeof(int) * 2, hipHostMallocDefault));
+  HIPCHK(hipStreamSynchronize(s));
+  g_tiles = pl->stats;
+  *out = pl.release();
+  return GMOT_OK;
+}
+
+static uint64_t shape_key(const std::vector<gmot_problem*>& probs) {
+  uint64_t h = 1469598103934665603ull;  // FNV-1a
+  auto mix = [&](uint64_t v) {
+    h ^= v;
+    h *= 1099511628211ull;
+  };
+  mix(probs.size());
+  for (const gmot_problem* p : probs) {
+    mix((uint64_t)p->N);
+    mix((uint64_t)p->dim);
+    mix((uint64_t)p->cost_kind);
+    mix((uint64_t)p->first_color);
+    for (int s : p->sizes) mix((uint64_t)s);
+    for (int e : p->edges) mix((uint64_t)e);
+  }
+  return h;
+}
+
+constexpr int kDefaultRows = 1;
+constexpr int kDefaultTarget = 1024;
+
+// Tile choice: a tuned choice cached in the context for these shapes, else
+// the default; GMOT_TILES="R,target" overrides both.
+static int choose_tiles(gmot_ctx* ctx, const std::vector<gmot_problem*>& probs, int* R, int* target) {
+  *R = kDefaultRows;
+  *target = kDefaultTarget;
+  auto it = ctx->tuned.find(shape_key(probs));
+  if (it != ctx->tuned.end()) {
+    *R = it->second.first;
+    *target = it->second.second;
+  }
+  if (const char* v = std::getenv("GMOT_TILES")) {
+    int r = 0, t = 0;
+    if (std::sscanf(v, "%d,%d", &r, &t) == 2 && (r == 1 || r == 2) && t > 0) {
+      *R = r;
+      *target = t;
+    }
+  }
+  return 0;
+}
+
+static int capture_one(Plan* pl, bool fp64, int start, int k, const std::vector<hipEvent_t>* ev,
+                       hipGraphExec_t* out) {
+  hipStream_t s = pl->ctx->stream;
+  HIPCHK(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+  hipError_t le = hipSuccess;
+  for (int i = 0; i < k && le == hipSuccess; ++i)
+    le = pl->launch_tstep((start + i) & 1, fp64, s, ev ? ev->data() + 2 * i : nullptr);
+  hipGraph_t graph = nullptr;
+  hipError_t ce = hipStreamEndCapture(s, &graph);
+  if (le != hipSuccess) {
+    if (graph) (void)hipGraphDestroy(graph);
+    return fail(GMOT_EDEVICE, std::string("kernel launch during capture: ") + hipGetErrorString(le));
+  }
+  if (ce != hipSuccess) return fail(GMOT_EDEVICE, std::string("hipStreamEndCapture: ") + hipGetErrorString(ce));
+  hipGraphExec_t exec = nullptr;
+  hipError_t ie = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(graph);
+  if (ie != hipSuccess) return fail(GMOT_EDEVICE, std::string("hipGraphInstantiate: ") + hipGetErrorString(ie));
+  *out = exec;
+  return GMOT_OK;
+}
+
+static int get_graph(Plan* pl, bool fp64, int start, int k, bool timed, GraphEntry** out) {
+  for (auto& g : pl->graphs)
+    if (g.fp64 == fp64 && g.start == start && g.k == k && g.timed == timed) {
+      *out = &g;
+      return GMOT_OK;
+    }
+  GraphEntry g;
+  g.fp64 = fp64;
+  g.start = start;
+  g.k = k;
+  g.timed = timed;
+  if (timed) {
+    // HIP events recorded by graph nodes cannot be timed, so the timed variant
+    // launches directly on the stream with two alternating event chains.
+    for (int c = 0; c < 2; ++c) {
+      g.ev[c].resize(2 * k + 1);
+      for (auto& e : g.ev[c]) HIPCHK(hipEventCreate(&e));
+    }
+  } else {
+    int rc = capture_one(pl, fp64, start, k, nullptr, &g.exec[0]);
+    if (rc) return rc;
+  }
+  pl->graphs.push_back(std::move(g));
+  *out = &pl->graphs.back();
+  return GMOT_OK;
+}
+
+// Run every instance of the plan from its problem's held state.
+// Instances with active[i] == 0 do not run and keep their result untouched.
+// The stop test applies from half-sweep max(2, t_start + min_updates) on: the
+// paper's loop never stops before the second half-sweep, and the FP64 verify
+// phase must first make one class exact in FP64.
+static int run_plan(Plan* pl, const gmot_opts* o, gmot_result* outs, const std::vector<char>* active = nullptr,
+                    int64_t min_updates = 0) {
+  hipStream_t s = pl->ctx->stream;
+  const size_t n = pl->probs.size();
+  int parity = -1;
+  int already = 0;
+  for (size_t i = 0; i < n; ++i) {
+    gmot_problem* p = pl->probs[i];
+    InstState& st = pl->inst[i];
+    if (active && !(*active)[i]) {
+      st.t = p->t;
+      st.done = kMaxSteps;
+      st.updates = 0;
+      ++already;
+      continue;
+    }
+    st.t = p->t;
+    st.min_check_t = std::max<int64_t>(2, p->t + min_updates);
+    st.updates = 0;
+    st.max_updates = o->max_steps;
+    st.tol = o->tol;
+    st.err_sum = INFINITY;
+    st.err_max = INFINITY;
+    st.checked_t = 0;
+    st.counter = 0;
+    st.clk_start = st.clk_stop = 0;
+    st.done = kRunning;
+    if (p->E == 0) {  // single node: nothing to scale
+      st.done = kConverged;
+      st.err_sum = st.err_max = 0.0;
+      ++already;
+      continue;
+    }
+    const int par = (int)(p->t & 1);
+    // instances at the other parity sit out one launch and then run in step
+    if (parity < 0) parity = par;
+  }
+  HIPCHK(hipMemcpyAsync(pl->d_inst, pl->inst.data(), sizeof(InstState) * n, hipMemcpyHostToDevice, s));
+  HIPCHK(hipMemcpyAsync(pl->d_ndone, &already, sizeof(int), hipMemcpyHostToDevice, s));
+  HIPCHK(hipStreamSynchronize(s));
+  if (already < (int)n) {
+    int k = o->check_every > 0 ? o->check_every : 16;
+    if (k & 1) ++k;
+    if (k > o->max_steps + 1) k = (int)std::max<int64_t>(2, (o->max_steps + 1) & ~int64_t(1));
+    const int start = parity == 1 ? 0 : 1;  // odd t updates class 0
+    const bool fp64 = o->precision == GMOT_PREC_FP64;
+    const bool timed = o->timing != 0;
+    const bool no_graph = std::getenv("GMOT_NO_GRAPH") != nullptr && !timed;
+    GraphEntry* g = nullptr;
+    if (!no_graph) {
+      int rc = get_graph(pl, fp64, start, k, timed, &g);
+      if (rc) return rc;
+    }
+    HIPCHK(launch_stamp(pl->d_inst, (int)n, s));
+    std::vector<int64_t> t_start(n);
+    for (size_t i = 0; i < n; ++i) t_start[i] = pl->inst[i].t;
+    // every replay advances each running instance by k half-sweeps (one fewer
+    // for an instance that starts at the other parity), so this bound is exact
+    const int64_t max_launches = ceil_div(o->max_steps + 1, k) + 1;
+    hipEvent_t ev[2];
+    HIPCHK(hipEventCreateWithFlags(&ev[0], hipEventDisableTiming));
+    HIPCHK(hipEventCreateWithFlags(&ev[1], hipEventDisableTiming));
+    // per-step durations of timed replays: (step since the start of this call, message ms, node ms)
+    struct StepTime { int64_t step; float msg_ms, node_ms; };
+    std::vector<StepTime> times;
+    auto launch_one = [&](int slot) -> hipError_t {
+      hipError_t e;
+      if (timed) {
+        e = hipSuccess;
+        for (int i = 0; i < k && e == hipSuccess; ++i)
+          e = pl->launch_tstep((start + i) & 1, fp64, s, g->ev[slot].data() + 2 * i);
+      } else if (no_graph) {
+        e = hipSuccess;
+        for (int i = 0; i < k && e == hipSuccess; ++i) e = pl->launch_tstep((start + i) & 1, fp64, s);
+      } else {
+        e = hipGraphLaunch(g->exec[0], s);
+      }
+      if (e != hipSuccess) return e;
+      e = hipMemcpyAsync(pl->h_ndone + slot, pl->d_ndone, sizeof(int), hipMemcpyDeviceToHost, s);
+      if (e != hipSuccess) return e;
+      return hipEventRecord(ev[slot], s);
+    };
+    auto read_times = [&](int64_t replay) -> hipError_t {
+      const std::vector<hipEvent_t>& E = g->ev[replay & 1];
+      for (int i = 0; i < k; ++i) {
+        float a = 0.f, b = 0.f;
+        hipError_t e = hipEventElapsedTime(&a, E[2 * i], E[2 * i + 1]);
+        if (e == hipSuccess) e = hipEventElapsedTime(&b, E[2 * i + 1], E[2 * i + 2]);
+        if (e != hipSuccess) return e;
+        times.push_back({replay * k + i, a, b});
+      }
+      return hipSuccess;
+    };
+    int64_t launched = 0, waited = 0;
+    hipError_t le = hipSuccess;
+    while (launched < std::min<int64_t>(2, max_launches) && le == hipSuccess) le = launch_one((int)(launched++ & 1));
+    while (le == hipSuccess && waited < launched) {
+      const int slot = (int)(waited & 1);
+      le = hipEventSynchronize(ev[slot]);
+      if (le != hipSuccess) break;
+      if (timed) le = read_times(waited);
+      if (le != hipSuccess) break;
+      ++waited;
+      if (pl->h_ndone[slot] >= (int)n) break;
+      if (launched < max_launches) le = launch_one((int)(launched++ & 1));
+    }
+    hipError_t se = hipStreamSynchronize(s);
+    (void)hipEventDestroy(ev[0]);
+    (void)hipEventDestroy(ev[1]);
+    if (le != hipSuccess) return fail(GMOT_EDEVICE, std::string("half-sweep loop: ") + hipGetErrorString(le));
+    if (se != hipSuccess) return fail(GMOT_EDEVICE, std::string("half-sweep loop: ") + hipGetErrorString(se));
+    pl->acc.graph_launches += launched;
+    HIPCHK(hipMemcpy(pl->inst.data(), pl->d_inst, sizeof(InstState) * n, hipMemcpyDeviceToHost));
+    if (timed) {
+      // last half-sweep (counted from the start of this call) that did work, per instance
+      std::vector<int64_t> last(n, -1);
+      int64_t last_any = -1;
+      for (size_t i = 0; i < n; ++i) {
+        const InstState& st = pl->inst[i];
+        if (pl->probs[i]->E == 0) continue;
+        const int64_t abs_last = st.done == kConverged ? st.checked_t : st.done == kNonFinite ? st.t + 1 : st.t - 1;
+        last[i] = abs_last - t_start[i];
+        last_any = std::max(last_any, last[i]);
+      }
+      for (const StepTime& tt : times) {
+        if (tt.step > last_any) continue;
+        const int c = (int)((start + tt.step) & 1);
+        pl->acc.msg_ms += tt.msg_ms;
+        pl->acc.node_ms += tt.node_ms;
+        pl->acc.msg_launches += 1;
+        pl->acc.node_launches += 1;
+        for (size_t i = 0; i < n; ++i)
+          if (tt.step <= last[i]) pl->acc.msg_pairs += pl->inst_pairs[c][i];
+      }
+    }
+  }
+  int rc = GMOT_OK;
+  for (size_t i = 0; i < n; ++i) {
+    if (active && !(*active)[i]) continue;
+    gmot_problem* p = pl->probs[i];
+    const InstState& st = pl->inst[i];
+    gmot_result& r = outs[i];
+    std::memset(&r, 0, sizeof(r));
+    if (st.done == kRunning) rc = fail(GMOT_ESTATE, "an instance was still running when the launch budget ended");
+    p->t = st.t;
+    r.status = st.done == kConverged ? GMOT_CONVERGED : st.done == kNonFinite ? GMOT_NONFINITE : GMOT_NOT_CONVERGED;
+    r.steps = st.updates;
+    r.t = st.t;
+    r.err_sum = st.err_sum;
+    r.err_max = st.err_max;
+    r.seconds = (st.clk_stop > st.clk_start) ? (double)(st.clk_stop - st.clk_start) / pl->ctx->clk_hz : 0.0;
+  }
+  return rc;
+}
+
+// FP32-core solves judge convergence in FP64: the FP32-core loop stops at
+// kVerifyMargin * tol, then FP64 half-sweeps run until the FP64 stopping sum
+// is <= tol (the FP32 exponentials leave a noise floor of a few 1e-9 per edge
+// on the sum, which the margin absorbs).
+constexpr double kVerifyMargin = 0.8;
+constexpr int64_t kVerifySteps = 256;
+
+static int solve_plan(Plan* pl, const gmot_opts* o, gmot_result* outs) {
+  const size_t n = pl->probs.size();
+  if (o->precision != GMOT_PREC_FP32CORE || o->skip_verify) return run_plan(pl, o, outs);
+  gmot_opts o1 = *o;
+  o1.tol = o->tol * kVerifyMargin;
+  int rc = run_plan(pl, &o1, outs);
+  if (rc) return rc;
+  std::vector<char> active(n, 0);
+  bool any = false;
+  int64_t budget = kVerifySteps;
+  for (size_t i = 0; i < n; ++i) {
+    active[i] = outs[i].status == GMOT_CONVERGED && pl->probs[i]->E > 0;
+    any = any || active[i];
+    if (active[i]) budget = std::min<int64_t>(budget, std::max<int64_t>(1, o->max_steps - outs[i].steps));
+  }
+  if (!any) return GMOT_OK;
+  gmot_opts o2 = *o;
+  o2.precision = GMOT_PREC_FP64;
+  o2.restart = 0;
+  o2.timing = 0;
+  o2.check_every = 2;
+  o2.max_steps = budget;
+  std::vector<gmot_result> r2(n);
+  rc = run_plan(pl, &o2, r2.data(), &active, 1);
+  if (rc) return rc;
+  for (size_t i = 0; i < n; ++i) {
+    if (!active[i]) continue;
+    outs[i].status = r2[i].status;
+    outs[i].steps += r2[i].steps;
+    outs[i].t = r2[i].t;
+    outs[i].err_sum = r2[i].err_sum;
+    outs[i].err_max = r2[i].err_max;
+    outs[i].seconds += r2[i].seconds;
+  }
+  return GMOT_OK;
+}
+
+// ---------------------------------------------------------------------------
+// problem creation
+// ---------------------------------------------------------------------------
+static int validate_and_copy(const gmot_tree_desc* d, gmot_problem* p, int first_color) {
+  if (!d) return fail(GMOT_EINVAL, "null descriptor");
+  if (d->n_nodes < 1) return fail(GMOT_EINVAL, "a tree needs at least one node");
+  if (d->n_edges != d->n_nodes - 1) return fail(GMOT_EINVAL, "a tree on N nodes has N-1 edges");
+  if (!d->sizes || !d->is_fixed || (d->n_edges > 0 && !d->edges))
+    return fail(GMOT_EINVAL, "missing sizes, is_fixed or edges");
+  if (!(d->eps > 0.0) || !std::isfinite(d->eps)) return fail(GMOT_EINVAL, "eps must be positive and finite");
+  if (d->cost_kind != GMOT_COST_SQEUCLID && d->cost_kind != GMOT_COST_EXPLICIT)
+    return fail(GMOT_ENOTSUP, "unknown cost kind");
+  if (d->cost_kind == GMOT_COST_SQEUCLID && (d->dim < 1 || d->dim > 3))
+    return fail(GMOT_ENOTSUP, "support dimension must be 1, 2 or 3");
+  if (d->cost_kind == GMOT_COST_SQEUCLID && !d->support) return fail(GMOT_EINVAL, "missing support points");
+  if (d->cost_kind == GMOT_COST_EXPLICIT && d->n_edges > 0 && !d->cost) return fail(GMOT_EINVAL, "missing cost");
+  if (first_color < -1 || first_color > 1) return fail(GMOT_EINVAL, "first_color must be -1, 0 or 1");
+  const int N = d->n_nodes, E = d->n_edges;
+  p->N = N;
+  p->E = E;
+  p->dim = d->cost_kind == GMOT_COST_SQEUCLID ? d->dim : 1;
+  p->cost_kind = d->cost_kind;
+  p->eps = d->eps;
+  p->sizes.assign(d->sizes, d->sizes + N);
+  p->fixed.assign(d->is_fixed, d->is_fixed + N);
+  for (int j = 0; j < N; ++j) {
+    if (p->sizes[j] < 1) return fail(GMOT_EINVAL, "every node needs at least one support point");
+    if (p->sizes[j] > (1 << 24)) return fail(GMOT_ENOTSUP, "support larger than 2^24 points");
+    p->fixed[j] = p->fixed[j] ? 1 : 0;
+  }
+  p->edges.assign(d->edges, d->edges + 2 * E);
+  p->nbrs.assign(N, {});
+  p->nbr_de.assign(N, {});
+  std::vector<std::pair<int, int>> keys;
+  for (int e = 0; e < E; ++e) {
+    const int a = p->edges[2 * e], b = p->edges[2 * e + 1];
+    if (a < 0 || a >= N || b < 0 || b >= N) return fail(GMOT_EINVAL, "edge endpoint out of range");
+    if (a == b) return fail(GMOT_EINVAL, "self-loop");
+    keys.push_back({std::min(a, b), std::max(a, b)});
+  }
+  std::sort(keys.begin(), keys.end());
+  if (std::adjacent_find(keys.begin(), keys.end()) != keys.end()) return fail(GMOT_EINVAL, "duplicate edge");
+  // neighbours in ascending order with their directed-edge ids
+  std::vector<std::vector<std::pair<int, int>>> adj(N);
+  for (int e = 0; e < E; ++e) {
+    const int a = p->edges[2 * e], b = p->edges[2 * e + 1];
+    adj[a].push_back({b, 2 * e});
+    adj[b].push_back({a, 2 * e + 1});
+  }
+  for (int j = 0; j < N; ++j) {
+    std::sort(adj[j].begin(), adj[j].end());
+    for (auto& pr : adj[j]) {
+      p->nbrs[j].push_back(pr.first);
+      p->nbr_de[j].push_back(pr.second);
+    }
+  }
+  // BFS 2-colouring from node 0; also proves connectivity (with N-1 edges: a tree)
+  p->colour.assign(N, -1);
+  p->colour[0] = 0;
+  std::deque<int> dq{0};
+  int seen = 1;
+  while (!dq.empty()) {
+    const int v = dq.front();
+    dq.pop_front();
+    for (int w : p->nbrs[v])
+      if (p->colour[w] < 0) {
+        p->colour[w] = 1 - p->colour[v];
+        ++seen;
+        dq.push_back(w);
+      }
+  }
+  if (seen != N) return fail(GMOT_EINVAL, "graph is not connected (not a tree)");
+  p->first_color = first_color < 0 ? 0 : first_color;
+  if (p->first_color == 1)
+    for (int j = 0; j < N; ++j) p->colour[j] = 1 - p->colour[j];
+  // offsets
+  p->node_off.assign(N + 1, 0);
+  for (int j = 0; j < N; ++j) p->node_off[j + 1] = p->node_off[j] + p->sizes[j];
+  p->total_pts = p->node_off[N];
+  p->de_off.assign(2 * E + 1, 0);
+  for (int e = 0; e < E; ++e) {
+    const int a = p->edges[2 * e], b = p->edges[2 * e + 1];
+    p->de_off[2 * e + 1] = p->de_off[2 * e] + p->sizes[a];
+    p->de_off[2 * e + 2] = p->de_off[2 * e + 1] + p->sizes[b];
+  }
+  p->total_de = p->de_off[2 * E];
+  p->cost_off.assign(E + 1, 0);
+  for (int e = 0; e < E; ++e) {
+    const int a = p->edges[2 * e], b = p->edges[2 * e + 1];
+    p->cost_off[e + 1] = p->cost_off[e] + (int64_t)p->sizes[a] * p->sizes[b];
+  }
+  p->total_cost = p->cost_kind == GMOT_COST_EXPLICIT ? p->cost_off[E] : 0;
+  // marginals
+  int64_t nfixed = 0;
+  for (int j = 0; j < N; ++j)
+    if (p->fixed[j]) nfixed += p->sizes[j];
+  if (nfixed > 0 && !d->marginal) return fail(GMOT_EINVAL, "missing marginals");
+  {
+    int64_t o = 0;
+    for (int j = 0; j < N; ++j) {
+      if (!p->fixed[j]) continue;
+      double sum = 0.0;
+      for (int x = 0; x < p->sizes[j]; ++x) {
+        const double v = d->marginal[o + x];
+        if (!(v >= 0.0) || !std::isfinite(v))
+          return fail(GMOT_EMARGINAL, "marginal of node " + std::to_string(j) + " has a negative or non-finite entry");
+        sum += v;
+      }
+      if (std::fabs(sum - 1.0) > 1e-9)
+        return fail(GMOT_EMARGINAL, "marginal of node " + std::to_string(j) + " does not sum to 1");
+      o += p->sizes[j];
+    }
+  }
+  if (d->cost_kind == GMOT_COST_EXPLICIT) {
+    for (int64_t i = 0; i < p->cost_off[E]; ++i)
+      if (!std::isfinite(d->cost[i])) return fail(GMOT_EINVAL, "non-finite cost entry");
+  }
+  return GMOT_OK;
+}
+
+static int upload(const gmot_tree_desc* d, gmot_problem* p) {
+  hipStream_t s = p->ctx->stream;
+  const int64_t P = p->total_pts, D = p->total_de;
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    size_t o = align_up(off, 256);
+    off = o + std::max<size_t>(bytes, 1);
+    return o;
+  };
+  const size_t o_sup = take(sizeof(double) * P * p->dim);
+  const size_t o_lg = take(sizeof(double) * P);
+  const size_t o_mu = take(sizeof(double) * P);
+  const size_t o_lam0 = take(sizeof(double) * D);
+  const size_t o_lam1 = take(sizeof(double) * D);
+  const size_t o_mf = take(sizeof(double) * D);
+  const size_t o_ab = take(sizeof(double) * P);
+  const size_t o_qb = take(sizeof(double) * P);
+  const size_t o_cost = take(sizeof(float) * 2 * p->total_cost);
+  if (hipMalloc(&p->arena, off) != hipSuccess) return fail(GMOT_ENOMEM, "problem arena allocation failed");
+  char* base = (char*)p->arena;
+  p->d_support = (double*)(base + o_sup);
+  p->d_lg = (double*)(base + o_lg);
+  p->d_mu = (double*)(base + o_mu);
+  p->d_lam[0] = (double*)(base + o_lam0);
+  p->d_lam[1] = (double*)(base + o_lam1);
+  p->d_mfull = (double*)(base + o_mf);
+  p->d_abar = (double*)(base + o_ab);
+  p->d_qbar = (double*)(base + o_qb);
+  p->d_cost = p->total_cost ? (float*)(base + o_cost) : nullptr;
+
+  std::vector<double> lg(P, 0.0), mu(P, 0.0), sup((size_t)P * p->dim, 0.0);
+  int64_t o = 0;
+  for (int j = 0; j < p->N; ++j) {
+    if (!p->fixed[j]) continue;
+    for (int x = 0; x < p->sizes[j]; ++x) {
+      const double v = d->marginal[o + x];
+      mu[p->node_off[j] + x] = v;
+      lg[p->node_off[j] + x] = v > 0.0 ? std::log(v) : -INFINITY;
+    }
+    o += p->sizes[j];
+  }
+  if (d->cost_kind == GMOT_COST_SQEUCLID) std::memcpy(sup.data(), d->support, sizeof(double) * P * p->dim);
+  HIPCHK(hipMemcpy(p->d_support, sup.data(), sizeof(double) * P * p->dim, hipMemcpyHostToDevice));
+  HIPCHK(hipMemcpy(p->d_lg, lg.data(), sizeof(double) * P, hipMemcpyHostToDevice));
+  HIPCHK(hipMemcpy(p->d_mu, mu.data(), sizeof(double) * P, hipMemcpyHostToDevice));
+  HIPCHK(hipMemsetAsync(p->d_lam[0], 0, sizeof(double) * D, s));
+  HIPCHK(hipMemsetAsync(p->d_lam[1], 0, sizeof(double) * D, s));
+  HIPCHK(hipMemsetAsync(p->d_mfull, 0, sizeof(double) * D, s));
+  if (p->total_cost) {
+    HIPCHK(hipMemcpy(p->d_cost, d->cost, sizeof(float) * p->total_cost, hipMemcpyHostToDevice));
+    std::vector<float> tr;
+    for (int e = 0; e < p->E; ++e) {
+      const int a = p->edges[2 * e], b = p->edges[2 * e + 1];
+      const int na = p->sizes[a], nb = p->sizes[b];
+      tr.assign((size_t)na * nb, 0.0f);
+      const float* src = d->cost + p->cost_off[e];
+      for (int x = 0; x < na; ++x)
+        for (int y = 0; y < nb; ++y) tr[(size_t)y * na + x] = src[(size_t)x * nb + y];
+      HIPCHK(hipMemcpy(p->d_cost + p->total_cost + p->cost_off[e], tr.data(), sizeof(float) * tr.size(),
+                       hipMemcpyHostToDevice));
+    }
+  }
+  HIPCHK(hipStreamSynchronize(s));
+  return GMOT_OK;
+}
+
+static int ensure_plan(gmot_problem* p) {
+  if (p->plan) return GMOT_OK;
+  int R, target;
+  choose_tiles(p->ctx, {p}, &R, &target);
+  return build_plan(p->ctx, {p}, R, target, &p->plan);
+}
+
+// Device time of one evaluation half-sweep per class with the FP32-core
+// message kernel (the state is read, never written).
+static int time_plan(Plan* pl, double* ms) {
+  hipStream_t s = pl->ctx->stream;
+  hipEvent_t a, b;
+  HIPCHK(hipEventCreate(&a));
+  HIPCHK(hipEventCreate(&b));
+  auto pass = [&]() -> hipError_t {
+    for (int c = 0; c < 2; ++c) {
+      for (int dk = 0; dk < 4; ++dk)
+        if (!pl->items[c][dk].empty()) {
+          hipError_t e = launch_msg(pl->tables(c, dk), (int)pl->items[c][dk].size(), dk, pl->R, false, 0, s);
+          if (e != hipSuccess) return e;
+        }
+      hipError_t e = launch_node(pl->tables(c, -1), (int)pl->nodes[c].size(), c, 0, s);
+      if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+  };
+  hipError_t e = pass();
+  const int reps = 3;
+  if (e == hipSuccess) e = hipEventRecord(a, s);
+  for (int r = 0; r < reps && e == hipSuccess; ++r) e = pass();
+  if (e == hipSuccess) e = hipEventRecord(b, s);
+  if (e == hipSuccess) e = hipEventSynchronize(b);
+  float f = 0.f;
+  if (e == hipSuccess) e = hipEventElapsedTime(&f, a, b);
+  (void)hipEventDestroy(a);
+  (void)hipEventDestroy(b);
+  if (e != hipSuccess) return fail(GMOT_EDEVICE, std::string("autotune timing: ") + hipGetErrorString(e));
+  *ms = f / reps;
+  return GMOT_OK;
+}
+
+static int autotune(gmot_ctx* ctx, const std::vector<gmot_problem*>& probs, Plan** plan_io, int32_t* R_out,
+                    int32_t* T_out, double* ms_out) {
+  static const int kCand[][2] = {{1, 256}, {1, 512}, {1, 1024}, {1, 2048}, {1, 4096},
+                                 {2, 256}, {2, 512}, {2, 1024}, {2, 2048}};
+  Plan* best = nullptr;
+  double best_ms = INFINITY;
+  int bR = kDefaultRows, bT = kDefaultTarget;
+  for (const auto& cand : kCand) {
+    Plan* pl = nullptr;
+    int rc = build_plan(ctx, probs, cand[0], cand[1], &pl);
+    if (rc) {
+      delete best;
+      return rc;
+    }
+    double ms = 0;
+    rc = time_plan(pl, &ms);
+    if (rc) {
+      delete pl;
+      delete best;
+      return rc;
+    }
+    if (ms < best_ms) {
+      delete best;
+      best = pl;
+      best_ms = ms;
+      bR = cand[0];
+      bT = cand[1];
+    } else {
+      delete pl;
+    }
+  }
+  ctx->tuned[shape_key(probs)] = {bR, bT};
+  delete *plan_io;
+  *plan_io = best;
+  g_tiles = best->stats;
+  if (R_out) *R_out = bR;
+  if (T_out) *T_out = bT;
+  if (ms_out) *ms_out = best_ms;
+  return GMOT_OK;
+}
+
+static int validate_opts(const gmot_opts* o) {
+  if (!o) return fail(GMOT_EINVAL, "null options");
+  if (!(o->tol >= 0.0)) return fail(GMOT_EINVAL, "tol must be >= 0");
+  if (o->max_steps < 1) return fail(GMOT_EINVAL, "max_steps must be positive");
+  if (o->check_every < 0) return fail(GMOT_EINVAL, "check_every must be >= 0");
+  if (o->precision != GMOT_PREC_FP32CORE && o->precision != GMOT_PREC_FP64)
+    return fail(GMOT_EINVAL, "unknown precision");
+  return GMOT_OK;
+}
+
+static int restart_problem(gmot_problem* p) {
+  if (p->total_de > 0) HIPCHK(hipMemsetAsync(p->d_lam[0], 0, sizeof(double) * p->total_de, p->ctx->stream));
+  p->t = 1;
+  return GMOT_OK;
+}
+
+// ---------------------------------------------------------------------------
+// evaluation pass (FP64)
+// ---------------------------------------------------------------------------
+static int eval_messages(gmot_problem* p, int only_class) {
+  Plan* pl = p->plan;
+  hipStream_t s = p->ctx->stream;
+  for (int c = 0; c < 2; ++c) {
+    if (only_class >= 0 && c != only_class) continue;
+    const int src_slot = p->slot_of_class(1 - c);
+    for (int dk = 0; dk < 4; ++dk)
+      if (!pl->items[c][dk].empty())
+        HIPCHK(launch_msg(pl->tables(c, dk), (int)pl->items[c][dk].size(), dk, pl->R, true, src_slot, s));
+    HIPCHK(launch_node(pl->tables(c, -1), (int)pl->nodes[c].size(), c, p->slot_of_class(c), s));
+  }
+  return GMOT_OK;
+}
+
+static EdgeDesc edge_desc(const gmot_problem* p, int e) {
+  const int a = p->edges[2 * e], b = p->edges[2 * e + 1];
+  EdgeDesc ed{};
+  ed.supp_a = p->d_support + p->node_off[a] * p->dim;
+  ed.supp_b = p->d_support + p->node_off[b] * p->dim;
+  ed.lam_a = p->d_lam[p->slot_of_class(p->colour[a])] + p->de_off[2 * e];
+  ed.lam_b = p->d_lam[p->slot_of_class(p->colour[b])] + p->de_off[2 * e + 1];
+  ed.lg_a = p->d_lg + p->node_off[a];
+  ed.lg_b = p->d_lg + p->node_off[b];
+  ed.cost = p->cost_kind == GMOT_COST_EXPLICIT ? p->d_cost + p->cost_off[e] : nullptr;
+  ed.n_a = p->sizes[a];
+  ed.n_b = p->sizes[b];
+  ed.dim = p->dim;
+  ed.cost_kind = p->cost_kind;
+  ed.eps = p->eps;
+  return ed;
+}
+
+// ---------------------------------------------------------------------------
+// C ABI
+// ---------------------------------------------------------------------------
+extern "C" {
+
+int gmot_ctx_create(gmot_ctx** out, int device, void* hip_stream) {
+  if (!out) return fail(GMOT_EINVAL, "null output");
+  int count = 0;
+  if (hipGetDeviceCount(&count) != hipSuccess || count < 1) return fail(GMOT_EDEVICE, "no HIP device");
+  if (device < 0 || device >= count) return fail(GMOT_EINVAL, "device index out of range");
+  hipDeviceProp_t prop;
+  HIPCHK(hipGetDeviceProperties(&prop, device));
+  if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0)
+    return fail(GMOT_EDEVICE, std::string("libgmot is built for gfx950, found ") + prop.gcnArchName);
+  HIPCHK(hipSetDevice(device));
+  std::unique_ptr<gmot_ctx> c(new gmot_ctx());
+  c->device = device;
+  if (hip_stream) {
+    c->stream = (hipStream_t)hip_stream;
+  } else {
+    HIPCHK(hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking));
+    c->own_stream = true;
+  }
+  int khz = 0;
+  if (hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, device) == hipSuccess && khz > 0)
+    c->clk_hz = 1000.0 * khz;
+  *out = c.release();
+  return GMOT_OK;
+}
+
+void gmot_ctx_destroy(gmot_ctx* ctx) {
+  if (!ctx) return;
+  if (ctx->own_stream) (void)hipStreamDestroy(ctx->stream);
+  delete ctx;
+}
+
+int gmot_problem_create(gmot_ctx* ctx, const gmot_tree_desc* desc, int32_t first_color, gmot_problem** out) {
+  if (!ctx || !out) return fail(GMOT_EINVAL, "null context or output");
+  std::unique_ptr<gmot_problem> p(new gmot_problem());
+  p->ctx = ctx;
+  int rc = validate_and_copy(desc, p.get(), first_color);
+  if (rc) return rc;
+  HIPCHK(hipSetDevice(ctx->device));
+  rc = upload(desc, p.get());
+  if (rc) {
+    if (p->arena) (void)hipFree(p->arena);
+    return rc;
+  }
+  *out = p.release();
+  return GMOT_OK;
+}
+
+void gmot_problem_destroy(gmot_problem* p) {
+  if (!p) return;
+  (void)hipStreamSynchronize(p->ctx->stream);
+  delete p->plan;
+  if (p->arena) (void)hipFree(p->arena);
+  delete p;
+}
+
+int gmot_solve(gmot_problem* p, const gmot_opts* o, gmot_result* out) {
+  if (!p || !out) return fail(GMOT_EINVAL, "null problem or result");
+  int rc = validate_opts(o);
+  if (rc) return rc;
+  HIPCHK(hipSetDevice(p->ctx->device));
+  if (o->restart) {
+    rc = restart_problem(p);
+    if (rc) return rc;
+  }
+  rc = ensure_plan(p);
+  if (rc) return rc;
+  return solve_plan(p->plan, o, out);
+}
+
+int gmot_evaluate(gmot_problem* p, gmot_eval* out) {
+  if (!p || !out) return fail(GMOT_EINVAL, "null problem or output");
+  std::memset(out, 0, sizeof(*out));
+  if (p->E == 0) return GMOT_OK;
+  HIPCHK(hipSetDevice(p->ctx->device));
+  int rc = ensure_plan(p);
+  if (rc) return rc;
+  Plan* pl = p->plan;
+  hipStream_t s = p->ctx->stream;
+  rc = eval_messages(p, -1);
+  if (rc) return rc;
+  // pair pass
+  std::vector<EdgeDesc> eds;
+  std::vector<PairItem> items;
+  for (int e = 0; e < p->E; ++e) {
+    eds.push_back(edge_desc(p, e));
+    const int na = eds.back().n_a, nb = eds.back().n_b;
+    const int cw = 2048;
+    for (int r0 = 0; r0 < na; r0 += kBlock)
+      for (int c0 = 0; c0 < nb; c0 += cw) items.push_back({e, r0, c0, std::min(cw, nb - c0)});
+  }
+  void* buf = nullptr;
+  const size_t b_ed = align_up(sizeof(EdgeDesc) * eds.size(), 256);
+  const size_t b_it = align_up(sizeof(PairItem) * items.size(), 256);
+  const size_t b_out = sizeof(double4) * items.size();
+  if (hipMalloc(&buf, b_ed + b_it + b_out) != hipSuccess) return fail(GMOT_ENOMEM, "evaluation buffers");
+  char* base = (char*)buf;
+  std::vector<double4> parts(items.size());
+  std::vector<double4> ne(pl->total_nodes);
+  hipError_t e1 = hipMemcpyAsync(base, eds.data(), sizeof(EdgeDesc) * eds.size(), hipMemcpyHostToDevice, s);
+  if (e1 == hipSuccess)
+    e1 = hipMemcpyAsync(base + b_ed, items.data(), sizeof(PairItem) * items.size(), hipMemcpyHostToDevice, s);
+  if (e1 == hipSuccess)
+    e1 = launch_pairs((EdgeDesc*)base, (PairItem*)(base + b_ed), (int)items.size(), (double4*)(base + b_ed + b_it), s);
+  if (e1 == hipSuccess)
+    e1 = hipMemcpyAsync(parts.data(), base + b_ed + b_it, b_out, hipMemcpyDeviceToHost, s);
+  if (e1 == hipSuccess)
+    e1 = hipMemcpyAsync(ne.data(), pl->d_node_eval, sizeof(double4) * pl->total_nodes, hipMemcpyDeviceToHost, s);
+  if (e1 == hipSuccess) e1 = hipStreamSynchronize(s);
+  (void)hipFree(buf);
+  if (e1 != hipSuccess) return fail(GMOT_EDEVICE, std::string("evaluation: ") + hipGetErrorString(e1));
+  std::vector<double> T(p->E, 0.0), H(p->E, 0.0), M(p->E, 0.0);
+  for (size_t i = 0; i < items.size(); ++i) {
+    const int e = items[i].edge;
+    T[e] += parts[i].x;
+    H[e] += parts[i].y;
+    M[e] += parts[i].z;
+  }
+  double Tsum = 0, Hsum = 0, Msum = 0, mmin = INFINITY, mmax = -INFINITY;
+  for (int e = 0; e < p->E; ++e) {
+    Tsum += T[e];
+    Hsum += H[e];
+    Msum += M[e];
+    mmin = std::min(mmin, M[e]);
+    mmax = std::max(mmax, M[e]);
+  }
+  double err = 0, errm = 0, lin = 0, rho = 0, spread = 0, scale = p->eps * p->E;
+  for (int c = 0; c < 2; ++c)
+    for (const NodeItem& nd : pl->nodes[c]) {
+      const double4 v = ne[nd.err_idx];
+      err += v.x;
+      errm = std::max(errm, v.y);
+      if (nd.fixed) {
+        lin += v.z;
+        scale += p->eps * std::fabs(v.z);
+      } else {
+        rho += v.z;
+        scale += p->eps * std::fabs(v.z);
+        spread = std::max(spread, v.w);
+      }
+    }
+  out->dual = p->eps * (lin + rho - Msum);
+  out->transport = Tsum;
+  out->primal = Tsum + p->eps * Hsum;
+  out->gap = out->primal - out->dual;
+  out->err_sum = err;
+  out->err_max = errm;
+  out->mass_min = mmin;
+  out->mass_max = mmax;
+  out->rho_spread = spread;
+  out->scale = scale;
+  return GMOT_OK;
+}
+
+int64_t gmot_potentials_size(const gmot_problem* p) { return p ? p->total_de : -1; }
+
+int gmot_get_potentials(gmot_problem* p, double* out) {
+  if (!p || (!out && p->total_de > 0)) return fail(GMOT_EINVAL, "null problem or output");
+  if (p->total_de == 0) return GMOT_OK;
+  HIPCHK(hipSetDevice(p->ctx->device));
+  std::vector<double> s0(p->total_de), s1(p->total_de);
+  HIPCHK(hipStreamSynchronize(p->ctx->stream));
+  HIPCHK(hipMemcpy(s0.data(), p->d_lam[0], sizeof(double) * p->total_de, hipMemcpyDeviceToHost));
+  HIPCHK(hipMemcpy(s1.data(), p->d_lam[1], sizeof(double) * p->total_de, hipMemcpyDeviceToHost));
+  for (int de = 0; de < 2 * p->E; ++de) {
+    const int e = de >> 1;
+    const int j = (de & 1) ? p->edges[2 * e + 1] : p->edges[2 * e];
+    const std::vector<double>& src = p->slot_of_class(p->colour[j]) ? s1 : s0;
+    std::copy(src.begin() + p->de_off[de], src.begin() + p->de_off[de + 1], out + p->de_off[de]);
+  }
+  return GMOT_OK;
+}
+
+int gmot_get_potentials_dev(gmot_problem* p, double* out_dev) {
+  if (!p || (!out_dev && p->total_de > 0)) return fail(GMOT_EINVAL, "null problem or output");
+  HIPCHK(hipSetDevice(p->ctx->device));
+  for (int de = 0; de < 2 * p->E; ++de) {
+    const int e = de >> 1;
+    const int j = (de & 1) ? p->edges[2 * e + 1] : p->edges[2 * e];
+    const double* src = p->d_lam[p->slot_of_class(p->colour[j])] + p->de_off[de];
+    HIPCHK(hipMemcpyAsync(out_dev + p->de_off[de], src, sizeof(double) * (p->de_off[de + 1] - p->de_off[de]),
+                          hipMemcpyDeviceToDevice, p->ctx->stream));
+  }
+  return GMOT_OK;
+}
+
+int gmot_set_potentials(gmot_problem* p, const double* in) {
+  if (!p || (!in && p->total_de > 0)) return fail(GMOT_EINVAL, "null problem or input");
+  for (int64_t i = 0; i < p->total_de; ++i)
+    if (!std::isfinite(in[i])) return fail(GMOT_EINVAL, "non-finite potential");
+  HIPCHK(hipSetDevice(p->ctx->device));
+  HIPCHK(hipStreamSynchronize(p->ctx->stream));
+  if (p->total_de) HIPCHK(hipMemcpy(p->d_lam[0], in, sizeof(double) * p->total_de, hipMemcpyHostToDevice));
+  p->t = 1;
+  return GMOT_OK;
+}
+
+int gmot_set_potentials_dev(gmot_problem* p, const double* in_dev) {
+  if (!p || (!in_dev && p->total_de > 0)) return fail(GMOT_EINVAL, "null problem or input");
+  HIPCHK(hipSetDevice(p->ctx->device));
+  if (p->total_de)
+    HIPCHK(hipMemcpyAsync(p->d_lam[0], in_dev, sizeof(double) * p->total_de, hipMemcpyDeviceToDevice,
+                          p->ctx->stream));
+  p->t = 1;
+  return GMOT_OK;
+}
+
+int gmot_get_coupling(gmot_problem* p, int32_t edge, double* out) {
+  if (!p || !out) return fail(GMOT_EINVAL, "null problem or output");
+  if (edge < 0 || edge >= p->E) return fail(GMOT_EINVAL, "edge index out of range");
+  HIPCHK(hipSetDevice(p->ctx->device));
+  const EdgeDesc ed = edge_desc(p, edge);
+  const size_t total = (size_t)ed.n_a * ed.n_b;
+  void* buf = nullptr;
+  if (hipMalloc(&buf, 256 + sizeof(double) * total) != hipSuccess) return fail(GMOT_ENOMEM, "coupling buffer");
+  hipStream_t s = p->ctx->stream;
+  hipError_t e = hipMemcpyAsync(buf, &ed, sizeof(ed), hipMemcpyHostToDevice, s);
+  if (e == hipSuccess) e = launch_coupling((EdgeDesc*)buf, (double*)((char*)buf + 256), total, s);
+  if (e == hipSuccess) e = hipMemcpyAsync(out, (char*)buf + 256, sizeof(double) * total, hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  (void)hipFree(buf);
+  if (e != hipSuccess) return fail(GMOT_EDEVICE, std::string("coupling: ") + hipGetErrorString(e));
+  return GMOT_OK;
+}
+
+int gmot_get_node_marginal(gmot_problem* p, int32_t node, double* out) {
+  if (!p || !out) return fail(GMOT_EINVAL, "null problem or output");
+  if (node < 0 || node >= p->N) return fail(GMOT_EINVAL, "node index out of range");
+  if (p->E == 0) {
+    if (!p->fixed[node]) return fail(GMOT_EINVAL, "a lone free node has no marginal");
+    HIPCHK(hipMemcpy(out, p->d_mu, sizeof(double) * p->sizes[0], hipMemcpyDeviceToHost));
+    return GMOT_OK;
+  }
+  HIPCHK(hipSetDevice(p->ctx->device));
+  int rc = ensure_plan(p);
+  if (rc) return rc;
+  rc = eval_messages(p, p->colour[node]);
+  if (rc) return rc;
+  HIPCHK(hipStreamSynchronize(p->ctx->stream));
+  HIPCHK(hipMemcpy(out, p->d_qbar + p->node_off[node], sizeof(double) * p->sizes[node], hipMemcpyDeviceToHost));
+  return GMOT_OK;
+}
+
+struct gmot_batch {
+  gmot_ctx* ctx = nullptr;
+  std::vector<gmot_problem*> probs;
+  Plan* plan = nullptr;
+};
+
+int gmot_batch_create(gmot_ctx* ctx, gmot_problem* const* probs, int32_t count, gmot_batch** out) {
+  if (!ctx || !probs || !out || count < 1) return fail(GMOT_EINVAL, "bad batch arguments");
+  std::unique_ptr<gmot_batch> b(new gmot_batch());
+  b->ctx = ctx;
+  for (int i = 0; i < count; ++i) {
+    if (!probs[i]) return fail(GMOT_EINVAL, "null problem in batch");
+    if (probs[i]->ctx != ctx) return fail(GMOT_ESTATE, "batch mixes contexts");
+    b->probs.push_back(probs[i]);
+  }
+  HIPCHK(hipSetDevice(ctx->device));
+  int R, target;
+  choose_tiles(ctx, b->probs, &R, &target);
+  int rc = build_plan(ctx, b->probs, R, target, &b->plan);
+  if (rc) return rc;
+  *out = b.release();
+  return GMOT_OK;
+}
+
+void gmot_batch_destroy(gmot_batch* b) {
+  if (!b) return;
+  (void)hipStreamSynchronize(b->ctx->stream);
+  delete b->plan;
+  delete b;
+}
+
+int gmot_batch_solve(gmot_batch* b, const gmot_opts* o, gmot_result* outs) {
+  if (!b || !outs) return fail(GMOT_EINVAL, "null batch or results");
+  int rc = validate_opts(o);
+  if (rc) return rc;
+  HIPCHK(hipSetDevice(b->ctx->device));
+  if (o->restart)
+    for (gmot_problem* p : b->probs) {
+      rc = restart_problem(p);
+      if (rc) return rc;
+    }
+  return solve_plan(b->plan, o, outs);
+}
+
+int gmot_problem_autotune(gmot_problem* p, int32_t* rows_per_lane, int32_t* target_blocks, double* best_ms) {
+  if (!p) return fail(GMOT_EINVAL, "null problem");
+  if (p->E == 0) return GMOT_OK;
+  HIPCHK(hipSetDevice(p->ctx->device));
+  return autotune(p->ctx, {p}, &p->plan, rows_per_lane, target_blocks, best_ms);
+}
+
+int gmot_batch_autotune(gmot_batch* b, int32_t* rows_per_lane, int32_t* target_blocks, double* best_ms) {
+  if (!b) return fail(GMOT_EINVAL, "null batch");
+  HIPCHK(hipSetDevice(b->ctx->device));
+  return autotune(b->ctx, b->probs, &b->plan, rows_per_lane, target_blocks, best_ms);
+}
+
+static int copy_stats(Plan* pl, gmot_stats* out, int32_t reset) {
+  if (!out) return fail(GMOT_EINVAL, "null output");
+  if (!pl) {
+    std::memset(out, 0, sizeof(*out));
+    return GMOT_OK;
+  }
+  *out = pl->acc;
+  if (reset) pl->acc = gmot_stats{};
+  return GMOT_OK;
+}
+
+int gmot_problem_stats(gmot_problem* p, gmot_stats* out, int32_t reset) {
+  if (!p) return fail(GMOT_EINVAL, "null problem");
+  return copy_stats(p->plan, out, reset);
+}
+
+int gmot_batch_stats(gmot_batch* b, gmot_stats* out, int32_t reset) {
+  if (!b) return fail(GMOT_EINVAL, "null batch");
+  return copy_stats(b->plan, out, reset);
+}
+
+const char* gmot_strerror(int code) {
+  switch (code) {
+    case GMOT_OK: return "ok";
+    case GMOT_EINVAL: return "invalid argument";
+    case GMOT_EMARGINAL: return "invalid marginal";
+    case GMOT_ENOMEM: return "out of memory";
+    case GMOT_EDEVICE: return "device error";
+    case GMOT_ENOTSUP: return "not supported";
+    case GMOT_ESTATE: return "invalid state";
+    default: return "unknown error";
+  }
+}
+
+const char* gmot_last_error(void) { return g_last_error.c_str(); }
+
+int gmot_last_tiles(int32_t* rows_per_block, int32_t* max_splits, int32_t* blocks_c0, int32_t* blocks_c1) {
+  if (rows_per_block) *rows_per_block = g_tiles.rows;
+  if (max_splits) *max_splits = g_tiles.max_splits;
+  if (blocks_c0) *blocks_c0 = g_tiles.blocks[0];
+  if (blocks_c1) *blocks_c1 = g_tiles.blocks[1];
+  return GMOT_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,282 @@
+"""HIP path against the FP64 oracle, through the C ABI (needs an MI355X).
+
+Tolerances
+----------
+* FP64 path (precision="fp64"): potentials and objectives within 1e-9 relative
+  of the oracle after the same number of half-sweeps (only summation order
+  differs).
+* FP32-core path: dual objective within 1e-6 relative to the scale
+  s = sum |eps <Lam, mu>| + sum |eps rho| + eps |E|, plans within 1e-6
+  absolute, after the same half-sweeps; converged runs must show a stopping
+  sum <= tol re-measured by the oracle in FP64 from the returned potentials,
+  and a dual within 1e-6 (relative to s) of the oracle's converged dual.
+"""
+import copy
+
+import numpy as np
+import pytest
+
+from oracle import TreeOracle
+from workloads import (make_config, make_chain, make_star, make_tree, make_random_tree, make_batched_stars,
+                       COST_EXPLICIT)
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    from paper_2406_10849_amd import Context
+    return Context(0)
+
+
+def gpu_problem(ctx, p, first_color=-1):
+    from paper_2406_10849_amd import Problem
+    return Problem(ctx, p, first_color=first_color)
+
+
+def oracle_lam(o, flat):
+    return o.set_potentials(flat)
+
+
+def test_config1_star_fp64_1000_half_sweeps(ctx):
+    p = make_config(1)
+    g = gpu_problem(ctx, p)
+    r = g.solve(tol=0.0, max_steps=1000, precision="fp64")
+    assert r["steps"] == 1000 and r["t"] == 1001
+    o = TreeOracle(p)
+    o.run_fixed(1000)
+    lo, lg = o.potentials(), g.potentials()
+    assert np.max(np.abs(lo - lg)) <= 1e-9 * max(1.0, np.max(np.abs(lo)))
+    eo, eg = o.evaluate(), g.evaluate()
+    assert abs(eg["dual"] - eo["dual"]) <= 1e-10 * eo["scale"]
+    assert abs(eg["primal"] - eo["primal"]) <= 1e-10 * eo["scale"]
+    assert abs(eg["transport"] - eo["transport"]) <= 1e-10
+    assert abs(eg["err_sum"] - eo["err_sum"]) <= 1e-12 + 1e-6 * eo["err_sum"]
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32core"])
+def test_small_chain_fixed_steps(ctx, precision):
+    p = make_chain(n_nodes=12, n=200, eps=1e-3)
+    g = gpu_problem(ctx, p)
+    steps = 40
+    r = g.solve(tol=0.0, max_steps=steps, precision=precision)
+    assert r["steps"] == steps
+    o = TreeOracle(p)
+    hist = o.run_fixed(steps)
+    eo = o.evaluate()
+    eg = g.evaluate()
+    tol = 1e-9 if precision == "fp64" else 1e-6
+    assert abs(eg["dual"] - eo["dual"]) <= tol * eo["scale"]
+    for e in [0, 5, 10]:
+        assert np.max(np.abs(g.coupling(e) - o.coupling(e))) <= tol
+    # in-loop stopping sum of the last checked state vs the oracle's
+    assert abs(r["err_sum"] - hist[-1][0]) <= 0.1 * hist[-1][0] + 1e-8
+
+
+def converged_check(g, p, tol, dstar, scale):
+    o = TreeOracle(p)
+    lam = o.set_potentials(g.potentials())
+    e_sum, e_max = o.full_error(lam)
+    assert e_sum <= tol + 1e-10, e_sum
+    ev = o.evaluate(lam)
+    assert abs(ev["dual"] - dstar) <= 1e-6 * scale
+    return e_sum
+
+
+def test_small_chain_converged(ctx):
+    p = make_chain(n_nodes=12, n=200, eps=1e-3)
+    ref = TreeOracle(p)
+    ref.solve(tol=1e-11, max_steps=20000)
+    er = ref.evaluate()
+    g = gpu_problem(ctx, p)
+    r = g.solve(tol=1e-6, max_steps=20000)
+    assert r["status"] == "converged"
+    converged_check(g, p, 1e-6, er["dual"], er["scale"])
+
+
+def test_random_tree_2d_ragged(ctx):
+    p = make_random_tree(n_nodes=20, n_lo=30, n_hi=700, eps=5e-3, dim=2, cfg_id=3, instance=7)
+    o = TreeOracle(p)
+    o.run_fixed(12)
+    g = gpu_problem(ctx, p)
+    g.solve(tol=0.0, max_steps=12)
+    eo, eg = o.evaluate(), g.evaluate()
+    assert abs(eg["dual"] - eo["dual"]) <= 1e-6 * eo["scale"]
+    for e in range(0, p.n_edges, 4):
+        assert np.max(np.abs(g.coupling(e) - o.coupling(e))) <= 1e-6
+
+
+def test_random_tree_converged(ctx):
+    p = make_random_tree(n_nodes=16, n_lo=20, n_hi=300, eps=5e-3, dim=2, cfg_id=3, instance=8)
+    ref = TreeOracle(p)
+    ref.solve(tol=1e-11, max_steps=50000)
+    er = ref.evaluate()
+    g = gpu_problem(ctx, p)
+    r = g.solve(tol=1e-6, max_steps=50000)
+    assert r["status"] == "converged"
+    converged_check(g, p, 1e-6, er["dual"], er["scale"])
+
+
+def test_batched_stars_mixed_dims(ctx):
+    from paper_2406_10849_amd import Batch
+    probs = make_batched_stars(count=6, l_lo=2, l_hi=5, n_lo=20, n_hi=300)
+    gps = [gpu_problem(ctx, p) for p in probs]
+    b = Batch(ctx, gps)
+    rs = b.solve(tol=1e-6, max_steps=20000)
+    for p, g, r in zip(probs, gps, rs):
+        assert r["status"] == "converged"
+        ref = TreeOracle(p)
+        ref.solve(tol=1e-11, max_steps=20000)
+        er = ref.evaluate()
+        converged_check(g, p, 1e-6, er["dual"], er["scale"])
+        # same schedule as solving the instance alone (tiles may differ, so the
+        # FP32 rounding and hence the stopping step may move by a half-sweep)
+        solo = gpu_problem(ctx, p)
+        rs1 = solo.solve(tol=1e-6, max_steps=20000)
+        assert abs(rs1["t"] - r["t"]) <= 2
+
+
+def test_batch_with_mixed_parities(ctx):
+    from paper_2406_10849_amd import Batch
+    probs = make_batched_stars(count=3, l_lo=2, l_hi=4, n_lo=40, n_hi=200, first_instance=50)
+    gps = [gpu_problem(ctx, p) for p in probs]
+    refs = [TreeOracle(p) for p in probs]
+    for i, (g, o) in enumerate(zip(gps, refs)):   # instance i starts at half-sweep i + 1
+        if i:
+            g.solve(tol=0.0, max_steps=i, precision="fp64")
+            o.run_fixed(i)
+    b = Batch(ctx, gps)
+    rs = b.solve(tol=0.0, max_steps=7, precision="fp64", restart=False)
+    for g, o, r in zip(gps, refs, rs):
+        o.run_fixed(7)
+        assert r["steps"] == 7
+        assert np.max(np.abs(g.potentials() - o.potentials())) <= 1e-9 * max(1.0, np.max(np.abs(o.potentials())))
+
+
+def test_timing_stats_count_working_half_sweeps(ctx):
+    p = make_chain(n_nodes=10, n=150, eps=1e-2)
+    g = gpu_problem(ctx, p)
+    g.stats(reset=True)
+    r = g.solve(tol=1e-6, max_steps=5000, timing=True, verify=False)
+    st = g.stats(reset=True)
+    assert r["status"] == "converged"
+    assert st["msg_launches"] == r["t"]          # half-sweeps 1..t computed messages
+    assert st["node_launches"] == r["t"]
+    assert abs(st["msg_pairs"] - r["t"] * p.pairs_per_tstep()) < 0.5
+    assert st["msg_ms"] > 0 and st["node_ms"] > 0
+
+
+def test_evaluate_matches_oracle_on_given_potentials(ctx):
+    p = make_tree([(0, 1), (1, 2), (1, 3), (3, 4), (3, 5)], [50, 300, 70, 260, 90, 33], [1, 0, 1, 0, 1, 1],
+                  eps=0.05, instance=21, dim=2)
+    o = TreeOracle(p)
+    o.run_fixed(7)
+    g = gpu_problem(ctx, p)
+    g.set_potentials(o.potentials())
+    eg, eo = g.evaluate(), o.evaluate()
+    for key in ["dual", "primal", "transport"]:
+        assert abs(eg[key] - eo[key]) <= 1e-10 * max(1.0, eo["scale"]), key
+    assert abs(eg["err_sum"] - eo["err_sum"]) <= 1e-10 + 1e-8 * eo["err_sum"]
+    assert abs(eg["mass_min"] - min(eo["masses"])) <= 1e-12
+    for j in range(p.n_nodes):
+        assert np.max(np.abs(g.node_marginal(j) - o.node_marginal(j))) <= 1e-12
+    for e in range(p.n_edges):
+        assert np.max(np.abs(g.coupling(e) - o.coupling(e))) <= 1e-12
+
+
+def test_edge_cases(ctx):
+    # two-node problems: fixed-fixed (Sinkhorn), fixed-free, one-point supports
+    for sizes, fixed in [([37, 300], [1, 1]), ([260, 5], [1, 0]), ([1, 40], [1, 0]), ([1, 1], [1, 1])]:
+        p = make_tree([(0, 1)], sizes, fixed, eps=0.1, instance=31)
+        g = gpu_problem(ctx, p)
+        r = g.solve(tol=1e-9, max_steps=5000, precision="fp64")
+        assert r["status"] == "converged"
+        o = TreeOracle(p)
+        ro = o.solve(tol=1e-9, max_steps=5000)
+        assert r["t"] == ro["t"]
+        assert np.max(np.abs(g.coupling(0) - o.coupling(0))) <= 1e-12
+        r = g.solve(tol=1e-9, max_steps=5000)
+        assert r["status"] == "converged"
+        assert np.max(np.abs(g.coupling(0) - o.coupling(0))) <= 1e-8
+    # a single node: nothing to do
+    p = make_tree(np.zeros((0, 2), dtype=np.int32), [5], [1], eps=0.1)
+    g = gpu_problem(ctx, p)
+    r = g.solve(tol=1e-6, max_steps=10)
+    assert r["status"] == "converged" and r["steps"] == 0
+
+
+def test_first_colour_and_restart(ctx):
+    p = make_star(n=90, leaves=4, eps=0.02)
+    g = gpu_problem(ctx, p, first_color=1)
+    o = TreeOracle(p, first_color=1)
+    g.solve(tol=0.0, max_steps=9)
+    o.run_fixed(9)
+    assert np.max(np.abs(g.coupling(2) - o.coupling(2))) <= 1e-6
+    # continue without restart == one longer run
+    g.solve(tol=0.0, max_steps=6, restart=False)
+    o.run_fixed(6)
+    assert np.max(np.abs(g.coupling(2) - o.coupling(2))) <= 1e-6
+    # warm start from given potentials
+    g2 = gpu_problem(ctx, p, first_color=1)
+    g2.set_potentials(g.potentials())
+    r2 = g2.solve(tol=1e-7, max_steps=5000, restart=False, precision="fp64")
+    o2 = TreeOracle(p, first_color=1)
+    o2.Lam = o2.set_potentials(g.potentials())
+    ro2 = o2.solve(tol=1e-7, max_steps=5000)
+    assert r2["t"] == ro2["t"]
+    assert np.max(np.abs(g2.potentials() - o2.potentials())) <= 1e-9 * max(1.0, np.max(np.abs(o2.potentials())))
+
+
+def test_explicit_cost(ctx):
+    p = make_tree([(0, 1), (1, 2), (1, 3)], [40, 300, 77, 260], [1, 0, 1, 1], eps=0.05, instance=41)
+    q = copy.deepcopy(p)
+    q.cost_kind = COST_EXPLICIT
+    rng = np.random.default_rng(5)
+    q.cost = []
+    for a, b in p.edges:
+        X, Y = p.node_support(int(a)), p.node_support(int(b))
+        C = np.sum((X[:, None, :] - Y[None, :, :]) ** 2, axis=2) + rng.uniform(0, 0.2, size=(X.shape[0], Y.shape[0]))
+        q.cost.append(C.astype(np.float32))
+    o = TreeOracle(q)
+    o.run_fixed(10)
+    g = gpu_problem(ctx, q)
+    g.solve(tol=0.0, max_steps=10)
+    eo, eg = o.evaluate(), g.evaluate()
+    assert abs(eg["dual"] - eo["dual"]) <= 1e-6 * eo["scale"]
+    for e in range(p.n_edges):
+        assert np.max(np.abs(g.coupling(e) - o.coupling(e))) <= 1e-6
+
+
+def test_invalid_inputs_rejected(ctx):
+    from paper_2406_10849_amd import GmotError, GMOT_EINVAL, GMOT_EMARGINAL
+    p = make_tree([(0, 1), (1, 2)], [4, 5, 6], [1, 0, 1], eps=0.1)
+    bad = copy.deepcopy(p)
+    bad.edges = np.array([[0, 1], [0, 1]], dtype=np.int32)
+    with pytest.raises(GmotError) as ei:
+        gpu_problem(ctx, bad)
+    assert ei.value.code == GMOT_EINVAL
+    bad = copy.deepcopy(p)
+    bad.marginal = bad.marginal * 1.001
+    with pytest.raises(GmotError) as ei:
+        gpu_problem(ctx, bad)
+    assert ei.value.code == GMOT_EMARGINAL
+    g = gpu_problem(ctx, p)
+    with pytest.raises(GmotError):
+        g.solve(tol=-1.0)
+    with pytest.raises(GmotError):
+        g.solve(max_steps=0)
+
+
+def test_full_size_chain_converges(ctx):
+    """The benchmark workload (32-node chain, n = 1024, eps = 1e-3) with the
+    benchmark's launch configuration; the oracle re-measures the stopping sum of
+    the returned state in FP64."""
+    p = make_config(2)
+    g = gpu_problem(ctx, p)
+    r = g.solve(tol=1e-6, max_steps=200000)
+    assert r["status"] == "converged"
+    o = TreeOracle(p)
+    lam = o.set_potentials(g.potentials())
+    e_sum, e_max = o.full_error(lam)
+    assert e_sum <= 1e-6 + 1e-10, e_sum
+    assert abs(e_sum - g.evaluate()["err_sum"]) <= 1e-9
