@@ -94,6 +94,77 @@ def cpu_baseline(prob, seconds: float) -> dict:
                       f"FP64 numpy, single thread, {el:.1f} s"}
 
 
+def bench_batched(ctx, tol: float, count: int) -> dict:
+    """Uneven barycenter stars (4-16 leaves, n in [128, 2048], 1D/2D grids,
+    eps = 1e-2): all instances advanced by the same launches of one captured
+    graph, against each instance solved on its own (its own plan, graph and
+    launches), both to the same stopping sum."""
+    from workloads import make_batched_stars
+    from paper_2406_10849_amd import Batch, Problem
+    probs = make_batched_stars(count=count)
+    gps = [Problem(ctx, p) for p in probs]
+    b = Batch(ctx, gps)
+    tuned = b.autotune()
+    b.solve(tol=tol, max_steps=200000)              # warm-up (graph capture)
+    t0 = time.perf_counter()
+    rb = b.solve(tol=tol, max_steps=200000)
+    t_batch = time.perf_counter() - t0
+    assert all(r["status"] == "converged" for r in rb), "batched solve did not converge"
+    for g in gps:                                   # per-instance plans and graphs built outside the timing
+        g.solve(tol=tol, max_steps=200000)
+    t0 = time.perf_counter()
+    rs = [g.solve(tol=tol, max_steps=200000) for g in gps]
+    t_single = time.perf_counter() - t0
+    assert all(r["status"] == "converged" for r in rs), "per-instance solve did not converge"
+    pairs = sum(p.pairs_per_tstep() * r["t"] for p, r in zip(probs, rb))
+    edges = sum(p.n_edges * r["t"] for p, r in zip(probs, rb))
+    out = {"instances": count, "edges": sum(p.n_edges for p in probs),
+           "pairs_per_half_sweep": sum(p.pairs_per_tstep() for p in probs),
+           "batched_s": t_batch, "per_instance_s": t_single, "speedup": t_single / t_batch,
+           "batched_edge_iterations_per_s": edges / t_batch, "batched_pairs_per_s": pairs / t_batch,
+           "max_half_sweeps": max(r["t"] for r in rb), "tiles": tuned}
+    b.close()
+    for g in gps:
+        g.close()
+    return out
+
+
+def bench_warm(ctx, tol: float, n_train: int, n_test: int, epochs: int) -> dict:
+    """Learned warm start on 8-leaf stars (n = 1024, 1D grid, eps = 1e-2): train
+    on solver-generated pairs, then on held-out instances compare (a) each
+    instance solved cold on its own (plain), (b) all cold in one batch and (c)
+    all warm-started in one batch (features, network and potentials included in
+    the time), every solve judged by the iteration's own stopping rule."""
+    from workloads import make_warmstart_star
+    from paper_2406_10849_amd import Problem, warmstart
+    import torch
+    t0 = time.perf_counter()
+    train = [make_warmstart_star(instance=i) for i in range(n_train)]
+    data = warmstart.generate(ctx, train, batch=512, tol=tol)
+    t_gen = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    net, losses = warmstart.fit(ctx, data, [8192, 512, 512, 512, 8192], epochs=epochs, batch=256, lr=1e-3)
+    torch.cuda.synchronize()
+    t_fit = time.perf_counter() - t0
+    test = [make_warmstart_star(instance=10 ** 6 + i) for i in range(n_test)]
+    res = warmstart.compare(ctx, net, data.scaling, test, batch=n_test, tol=tol)
+    # plain: every test instance on its own, cold
+    gps = [Problem(ctx, p) for p in test]
+    for g in gps[:4]:
+        g.solve(tol=tol)
+    t0 = time.perf_counter()
+    rs = [g.solve(tol=tol) for g in gps]
+    t_plain = time.perf_counter() - t0
+    for g in gps:
+        g.close()
+    del data
+    torch.cuda.empty_cache()
+    return dict(res, train_instances=n_train, epochs=epochs, loss_first=losses[0], loss_last=losses[-1],
+                generate_s=t_gen, fit_s=t_fit, plain_per_instance_s=t_plain,
+                plain_half_sweeps_mean=float(sum(r["t"] for r in rs) / len(rs)),
+                speedup_batched_warm_vs_plain=t_plain / res["warm_wall_s"])
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -105,6 +176,11 @@ def main() -> int:
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--calib-copy", action="store_true",
                     help="also run one 1 GiB device copy (PMC calibration for HBM byte counters)")
+    ap.add_argument("--no-extras", action="store_true", help="skip the batched and warm-start comparisons")
+    ap.add_argument("--batched-count", type=int, default=512)
+    ap.add_argument("--warm-train", type=int, default=4096)
+    ap.add_argument("--warm-test", type=int, default=512)
+    ap.add_argument("--warm-epochs", type=int, default=30)
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported (the solver runs on a "
@@ -199,8 +275,15 @@ def main() -> int:
                      "frac": achieved / peak, "traffic": traffic,
                      "kernel": "k_msg", "avg_launch_ms": avg_ms, "pairs_per_launch": pairs_per_launch,
                      "launches_timed": st["msg_launches"],
-                     "node_kernel_avg_ms": st["node_ms"] / max(st["node_launches"], 1)},
+                     "half_sweep_avg_ms": st["sweep_ms"] / max(st["msg_launches"], 1)},
     }
+    if not args.no_extras:
+        log("batched stars: one graph for all instances vs per-instance launches")
+        out["batched"] = bench_batched(ctx, args.tol, args.batched_count)
+        log(f"batched: {out['batched']}")
+        log("learned warm start")
+        out["warm_start"] = bench_warm(ctx, args.tol, args.warm_train, args.warm_test, args.warm_epochs)
+        log(f"warm start: {out['warm_start']}")
     if not args.no_cpu_baseline:
         log("timing the FP64 oracle on the host")
         out["cpu_baseline"] = cpu_baseline(prob, args.cpu_seconds)

@@ -110,17 +110,22 @@ typedef struct {
                            half-sweeps (at most 256) continue until the FP64 stopping
                            sum is <= tol, so convergence is judged in FP64.  1: stop
                            on the FP32-core sum <= tol.                              */
-  int32_t reserved;
+  int32_t schedule;     /* GMOT_SCHED_LAYER (default): every message of the class being
+                           updated in one launch; GMOT_SCHED_PER_EDGE: the same
+                           half-sweep with one launch per message (same iterates)    */
 } gmot_opts;
+
+#define GMOT_SCHED_LAYER     0
+#define GMOT_SCHED_PER_EDGE  1
 
 /* Kernel timing accumulated by solves with opts.timing = 1 (since the last
  * reset).  Only half-sweeps that did work for at least one instance count. */
 typedef struct {
-  double  msg_ms;          /* summed duration of message-kernel launches (ms)           */
-  int64_t msg_launches;    /* half-sweeps timed (one message stage per half-sweep)     */
-  double  node_ms;         /* summed duration of node-kernel launches (ms)              */
-  int64_t node_launches;
-  double  msg_pairs;       /* (x, y) pairs those message stages processed               */
+  double  msg_ms;          /* summed duration of the message-kernel stages (ms)         */
+  double  sweep_ms;        /* summed duration of whole half-sweeps: message, tile and
+                              finalise kernels (ms)                                    */
+  int64_t msg_launches;    /* half-sweeps timed                                         */
+  double  msg_pairs;       /* (x, y) pairs those half-sweeps processed                  */
   int64_t graph_launches;  /* graph replays issued (timed or not)                        */
 } gmot_stats;
 
@@ -195,6 +200,58 @@ int  gmot_batch_create(gmot_ctx* ctx, gmot_problem* const* probs, int32_t count,
 void gmot_batch_destroy(gmot_batch* b);
 /* outs: [count] results, one per instance. */
 int  gmot_batch_solve(gmot_batch* b, const gmot_opts* opts, gmot_result* outs);
+
+/* ---- learned warm start ------------------------------------------------------------
+ * Not part of the paper's method: a small network predicts starting potentials
+ * for star instances; the bipartite iteration then runs as usual and remains
+ * the judge of convergence (a cold start is the fallback).  For the callers
+ * that want fewer half-sweeps on families of similar barycenter problems. */
+typedef struct gmot_mlp gmot_mlp;
+
+/* Fully connected network widths[0] -> ... -> widths[n_layers], ReLU between
+ * layers, linear output.  GEMM inputs are rounded to BF16 (nearest even) and
+ * accumulated in FP32 on the matrix cores; parameters, activations, Adam
+ * moments and the loss are FP32.  Every width must be a multiple of 8
+ * (GMOT_ENOTSUP otherwise).  Weights are He-uniform from `seed`, biases 0. */
+int  gmot_mlp_create(gmot_ctx* ctx, int32_t n_layers, const int32_t* widths, uint64_t seed, gmot_mlp** out);
+void gmot_mlp_destroy(gmot_mlp* m);
+int64_t gmot_mlp_num_params(const gmot_mlp* m);
+/* FP32 parameters, layer by layer: W_l (widths[l] x widths[l-1], row-major), b_l.
+ * Setting them also clears the Adam state. */
+int  gmot_mlp_get_params(gmot_mlp* m, float* out);
+int  gmot_mlp_set_params(gmot_mlp* m, const float* in);
+/* Device buffers, row-major FP32: x [batch x widths[0]], y [batch x widths[n]];
+ * batch must be a positive multiple of 8.  Stream-ordered on the context. */
+int  gmot_mlp_forward_dev(gmot_mlp* m, const float* x_dev, int32_t batch, float* y_dev);
+/* Mean-squared-error loss sum (y - t)^2 / (batch * widths[n]) (host, after a
+ * sync; may be NULL) and its FP32 parameter gradient (device, parameter layout;
+ * may be NULL) for targets t_dev [batch x widths[n]]. */
+int  gmot_mlp_loss_grad_dev(gmot_mlp* m, const float* x_dev, const float* t_dev, int32_t batch, double* loss,
+                            float* grad_dev);
+/* Bias-corrected Adam step with the gradient of the last loss_grad call. */
+int  gmot_mlp_adam_step(gmot_mlp* m, float lr, float beta1, float beta2, float adam_eps);
+/* loss_grad followed by Adam(lr, 0.9, 0.999, 1e-8). */
+int  gmot_mlp_train_step_dev(gmot_mlp* m, const float* x_dev, const float* t_dev, int32_t batch, float lr,
+                             double* loss);
+const char* gmot_mlp_last_error(void);
+
+/* Star instances for the warm start: node 0 is a free center, edges are
+ * (0,1), (0,2), ..., (0,L) in that order, leaves 1..L are constrained, every
+ * support has the same size n, and all instances of one call share L and n.
+ *   features: x[i][l*n + p] = (max(log mu_l(p), -40) - shift) * scale
+ *   targets:  t[i][l*n + p] = (Lam_(l,0)(p) - mean_p Lam_(l,0)) / out_scale, from
+ *             the held (committed) potentials
+ *   apply:    Lam_(l,0) = out_scale * (y_l - mean_p y_l), Lam_(0,l) = 0 become the
+ *             held potentials (t restarts at 1, the center is updated first);
+ *             an instance whose prediction has a non-finite entry gets the cold
+ *             start instead and is counted in *rejected. */
+int  gmot_star_features_dev(gmot_problem* const* probs, int32_t count, float shift, float scale, float* x_dev);
+int  gmot_star_targets_dev(gmot_problem* const* probs, int32_t count, float out_scale, float* t_dev);
+int  gmot_star_apply_dev(gmot_problem* const* probs, int32_t count, const float* y_dev, float out_scale,
+                         int32_t* rejected);
+/* features -> forward -> apply in one call, with library-owned workspaces. */
+int  gmot_mlp_warm_start(gmot_mlp* m, gmot_problem* const* probs, int32_t count, float shift, float scale,
+                         float out_scale, int32_t* rejected);
 
 /* ---- tile autotuning ------------------------------------------------------------ */
 /* Time candidate message-kernel tilings (rows per lane 1 or 2, and the number of

@@ -21,6 +21,7 @@ from ._lib import (GMOT_OK, GMOT_EINVAL, GMOT_EMARGINAL, GMOT_ENOMEM, GMOT_EDEVI
 
 STATUS_NAMES = {GMOT_CONVERGED: "converged", GMOT_NOT_CONVERGED: "not_converged", GMOT_NONFINITE: "nonfinite"}
 PRECISIONS = {"fp32core": GMOT_PREC_FP32CORE, "fp64": GMOT_PREC_FP64}
+SCHEDULES = {"layer": 0, "per_edge": 1}
 
 
 class GmotError(RuntimeError):
@@ -121,7 +122,8 @@ class Problem:
             pass
 
     @staticmethod
-    def _opts(tol, max_steps, check_every, precision, restart, timing=False, verify=True) -> _lib.Opts:
+    def _opts(tol, max_steps, check_every, precision, restart, timing=False, verify=True,
+              schedule="layer") -> _lib.Opts:
         o = _lib.Opts()
         o.tol = float(tol)
         o.max_steps = int(max_steps)
@@ -130,6 +132,7 @@ class Problem:
         o.restart = 1 if restart else 0
         o.timing = 1 if timing else 0
         o.skip_verify = 0 if verify else 1
+        o.schedule = SCHEDULES[schedule] if isinstance(schedule, str) else int(schedule)
         return o
 
     @staticmethod
@@ -159,8 +162,8 @@ class Problem:
                 "err_sum": float(r.err_sum), "err_max": float(r.err_max), "seconds": float(r.seconds)}
 
     def solve(self, tol: float = 1e-6, max_steps: int = 100000, check_every: int = 0, precision="fp32core",
-              restart: bool = True, timing: bool = False, verify: bool = True) -> dict:
-        o = self._opts(tol, max_steps, check_every, precision, restart, timing, verify)
+              restart: bool = True, timing: bool = False, verify: bool = True, schedule="layer") -> dict:
+        o = self._opts(tol, max_steps, check_every, precision, restart, timing, verify, schedule)
         r = _lib.Result()
         _check(self._lib.gmot_solve(self._h, C.byref(o), C.byref(r)), "gmot_solve")
         return self._res(r)
@@ -229,8 +232,8 @@ class Batch:
             pass
 
     def solve(self, tol: float = 1e-6, max_steps: int = 100000, check_every: int = 0, precision="fp32core",
-              restart: bool = True, timing: bool = False, verify: bool = True) -> List[dict]:
-        o = Problem._opts(tol, max_steps, check_every, precision, restart, timing, verify)
+              restart: bool = True, timing: bool = False, verify: bool = True, schedule="layer") -> List[dict]:
+        o = Problem._opts(tol, max_steps, check_every, precision, restart, timing, verify, schedule)
         rs = (_lib.Result * len(self.problems))()
         _check(self._lib.gmot_batch_solve(self._h, C.byref(o), rs), "gmot_batch_solve")
         return [Problem._res(r) for r in rs]
@@ -242,6 +245,96 @@ class Batch:
         return Problem._autotune(self._lib.gmot_batch_autotune, self._h)
 
 
+def _handles(problems) -> "C.Array":
+    return (C.c_void_p * len(problems))(*[p._h.value for p in problems])
+
+
+def _dptr(t) -> C.c_void_p:
+    """Device pointer of a contiguous float32 torch tensor."""
+    if str(t.dtype) != "torch.float32" or not t.is_contiguous() or t.device.type != "cuda":
+        raise ValueError("need a contiguous float32 device tensor")
+    return C.c_void_p(t.data_ptr())
+
+
+class MLP:
+    """Warm-start network trained and run by the library's HIP kernels."""
+
+    def __init__(self, ctx: Context, widths: Sequence[int], seed: int = 0):
+        self._lib = ctx._lib
+        self.ctx = ctx
+        self.widths = [int(w) for w in widths]
+        arr = (C.c_int32 * len(self.widths))(*self.widths)
+        h = C.c_void_p()
+        _check(self._lib.gmot_mlp_create(ctx._h, len(self.widths) - 1, arr, int(seed), C.byref(h)), "gmot_mlp_create")
+        self._h = h
+        self.n_params = int(self._lib.gmot_mlp_num_params(h))
+
+    def close(self):
+        if getattr(self, "_h", None) and self._h.value:
+            self._lib.gmot_mlp_destroy(self._h)
+            self._h = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def get_params(self) -> np.ndarray:
+        out = np.empty(self.n_params, dtype=np.float32)
+        _check(self._lib.gmot_mlp_get_params(self._h, out.ctypes.data_as(C.POINTER(C.c_float))), "gmot_mlp_get_params")
+        return out
+
+    def set_params(self, p) -> None:
+        a = _as(p, np.float32).reshape(-1)
+        if a.shape[0] != self.n_params:
+            raise ValueError("wrong parameter count")
+        _check(self._lib.gmot_mlp_set_params(self._h, a.ctypes.data_as(C.POINTER(C.c_float))), "gmot_mlp_set_params")
+
+    def forward(self, x, y) -> None:
+        _check(self._lib.gmot_mlp_forward_dev(self._h, _dptr(x), int(x.shape[0]), _dptr(y)), "gmot_mlp_forward_dev")
+
+    def loss_grad(self, x, t, grad=None) -> float:
+        loss = C.c_double()
+        g = _dptr(grad) if grad is not None else None
+        _check(self._lib.gmot_mlp_loss_grad_dev(self._h, _dptr(x), _dptr(t), int(x.shape[0]), C.byref(loss), g),
+               "gmot_mlp_loss_grad_dev")
+        return loss.value
+
+    def adam_step(self, lr: float, beta1: float = 0.9, beta2: float = 0.999, eps: float = 1e-8) -> None:
+        _check(self._lib.gmot_mlp_adam_step(self._h, lr, beta1, beta2, eps), "gmot_mlp_adam_step")
+
+    def train_step(self, x, t, lr: float) -> float:
+        loss = C.c_double()
+        _check(self._lib.gmot_mlp_train_step_dev(self._h, _dptr(x), _dptr(t), int(x.shape[0]), lr, C.byref(loss)),
+               "gmot_mlp_train_step_dev")
+        return loss.value
+
+    def warm_start(self, problems: Sequence[Problem], shift: float, scale: float, out_scale: float) -> int:
+        rej = C.c_int32()
+        _check(self._lib.gmot_mlp_warm_start(self._h, _handles(problems), len(problems), shift, scale, out_scale,
+                                             C.byref(rej)), "gmot_mlp_warm_start")
+        return rej.value
+
+
+def star_features(problems: Sequence[Problem], x, shift: float, scale: float) -> None:
+    lib = _lib.load()
+    _check(lib.gmot_star_features_dev(_handles(problems), len(problems), shift, scale, _dptr(x)), "gmot_star_features_dev")
+
+
+def star_targets(problems: Sequence[Problem], t, out_scale: float) -> None:
+    lib = _lib.load()
+    _check(lib.gmot_star_targets_dev(_handles(problems), len(problems), out_scale, _dptr(t)), "gmot_star_targets_dev")
+
+
+def star_apply(problems: Sequence[Problem], y, out_scale: float) -> int:
+    lib = _lib.load()
+    rej = C.c_int32()
+    _check(lib.gmot_star_apply_dev(_handles(problems), len(problems), _dptr(y), out_scale, C.byref(rej)),
+           "gmot_star_apply_dev")
+    return rej.value
+
+
 def last_tiles() -> dict:
     lib = _lib.load()
     v = [C.c_int32() for _ in range(4)]
@@ -249,4 +342,5 @@ def last_tiles() -> dict:
     return {"rows_per_block": v[0].value, "max_splits": v[1].value, "blocks_c0": v[2].value, "blocks_c1": v[3].value}
 
 
-__all__ = ["Context", "Problem", "Batch", "GmotError", "last_tiles", "STATUS_NAMES"]
+__all__ = ["Context", "Problem", "Batch", "MLP", "GmotError", "last_tiles", "star_features", "star_targets",
+           "star_apply", "STATUS_NAMES"]

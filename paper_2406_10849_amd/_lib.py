@@ -51,16 +51,15 @@ class Opts(C.Structure):
         ("restart", C.c_int32),
         ("timing", C.c_int32),
         ("skip_verify", C.c_int32),
-        ("reserved", C.c_int32),
+        ("schedule", C.c_int32),
     ]
 
 
 class Stats(C.Structure):
     _fields_ = [
         ("msg_ms", C.c_double),
+        ("sweep_ms", C.c_double),
         ("msg_launches", C.c_int64),
-        ("node_ms", C.c_double),
-        ("node_launches", C.c_int64),
         ("msg_pairs", C.c_double),
         ("graph_launches", C.c_int64),
     ]
@@ -111,6 +110,20 @@ SIGNATURES = {
     "gmot_strerror": (C.c_char_p, [C.c_int]),
     "gmot_last_error": (C.c_char_p, []),
     "gmot_last_tiles": (C.c_int, [I32P, I32P, I32P, I32P]),
+    "gmot_mlp_create": (C.c_int, [VP, C.c_int32, I32P, C.c_uint64, C.POINTER(VP)]),
+    "gmot_mlp_destroy": (None, [VP]),
+    "gmot_mlp_num_params": (C.c_int64, [VP]),
+    "gmot_mlp_get_params": (C.c_int, [VP, C.POINTER(C.c_float)]),
+    "gmot_mlp_set_params": (C.c_int, [VP, C.POINTER(C.c_float)]),
+    "gmot_mlp_forward_dev": (C.c_int, [VP, VP, C.c_int32, VP]),
+    "gmot_mlp_loss_grad_dev": (C.c_int, [VP, VP, VP, C.c_int32, DP, VP]),
+    "gmot_mlp_adam_step": (C.c_int, [VP, C.c_float, C.c_float, C.c_float, C.c_float]),
+    "gmot_mlp_train_step_dev": (C.c_int, [VP, VP, VP, C.c_int32, C.c_float, DP]),
+    "gmot_mlp_last_error": (C.c_char_p, []),
+    "gmot_star_features_dev": (C.c_int, [C.POINTER(VP), C.c_int32, C.c_float, C.c_float, VP]),
+    "gmot_star_targets_dev": (C.c_int, [C.POINTER(VP), C.c_int32, C.c_float, VP]),
+    "gmot_star_apply_dev": (C.c_int, [C.POINTER(VP), C.c_int32, VP, C.c_float, I32P]),
+    "gmot_mlp_warm_start": (C.c_int, [VP, C.POINTER(VP), C.c_int32, C.c_float, C.c_float, C.c_float, I32P]),
     "gmot_problem_autotune": (C.c_int, [VP, I32P, I32P, DP]),
     "gmot_batch_autotune": (C.c_int, [VP, I32P, I32P, DP]),
     "gmot_problem_stats": (C.c_int, [VP, C.POINTER(Stats), C.c_int32]),
@@ -127,6 +140,14 @@ def load() -> C.CDLL:
         return _LIB
     if not os.path.exists(LIB_PATH):
         raise ImportError(f"libgmot.so is not built ({LIB_PATH}); run `python -m paper_2406_10849_amd.build`")
+    # PyTorch wheels carry their own HIP runtime with the same soname.  Loading
+    # torch first makes libgmot bind to that runtime, so the process holds one
+    # HIP runtime and torch streams and device pointers can be passed in; the
+    # other order would load a second runtime next to torch's.
+    try:
+        import torch  # noqa: F401
+    except ImportError:
+        pass
     lib = C.CDLL(LIB_PATH)
     for name, (res, args) in SIGNATURES.items():
         fn = getattr(lib, name)

@@ -18,6 +18,20 @@
 // value in slot ((t - 1) / 2) % 2 and the other class in slot (t / 2) % 2, so a
 // half-sweep that ends in "converged" has written only the slot nobody reads
 // and the state that passed the test stays intact (check-then-update).
+//
+// A free node's potentials are held as Lam_(j,k)(x) = L_(j,k)(x) - c_j: the
+// update writes L = abar - m_{k->j} row tile by row tile, and the node-wide
+// normaliser c_j = LSE_x abar is written once all tiles are done (constrained
+// nodes have c_j = 0).  c_j is double-buffered like the potentials.
+//
+// One half-sweep is three stream-ordered launches: the message kernel (one
+// block per (row tile, column split) of a message, per support dimension), the
+// tile kernel (one block per 256-row tile of a node of the class: merge of the
+// column splits, stopping-sum terms of the state before the update, update of
+// L, and a tile record), and the finalise kernel (one block per instance: c_j
+// from the tile records, the stopping sum and the stop decision).  Kernel
+// boundaries make each stage's writes visible to the next, so no block waits
+// on, or fences for, another block.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -36,9 +50,10 @@ enum Done : int { kRunning = 0, kConverged = 1, kMaxSteps = 2, kNonFinite = 3 };
 struct MsgDesc {
   const double* supp_dst;    // [n_dst * dim]
   const double* supp_src;    // [n_src * dim]
-  const double* lam_src[2];  // Lam_(k,j) slots, [n_src]
+  const double* lam_src[2];  // stored L_(k,j) slots, [n_src]
+  const double* c_src;       // c_k slots [2] (NULL: constrained source, c = 0)
   const double* lg_src;      // log gamma_k, [n_src]
-  double* lam_dst[2];        // Lam_(j,k) slots, [n_dst]
+  double* lam_dst[2];        // stored L_(j,k) slots, [n_dst]
   double2* partial;          // [ns * n_dst]: (row max, sum of 2^(w - max)) per column split
   double* mfull;             // merged message m_{k->j}, [n_dst], natural log
   const float* cost;         // explicit cost stored src-major: cost[y * n_dst + x] = C_(j,k)(x, y)
@@ -53,15 +68,26 @@ struct K1Item {
   int32_t msg, row0, col0, ncols, split, pad0, pad1, pad2;
 };
 
+constexpr int kTileRows = 256;  // rows per block of the tile kernel
+
 // One node of the class being updated; its deg incoming messages are
-// msgs[msg0 .. msg0 + deg) in ascending neighbour order.
+// msgs[msg0 .. msg0 + deg) in ascending neighbour order.  Its rows form
+// `tiles` tiles of kTileRows; tile records (deg stopping-sum terms, then the
+// tile's LSE max and scaled sum of abar) start at tpart + tile * (deg + 2).
 struct NodeItem {
   int32_t inst, node, n, deg;
-  int32_t fixed, msg0, err_idx, pad;
+  int32_t fixed, msg0, err_idx, tiles;
   const double* lg;          // log gamma_j, [n]
   const double* mu;          // mu_j for constrained nodes, else NULL
   double* abar;              // scratch [n]: mean_k m_{k->j}
   double* qbar;              // scratch [n]: arithmetic mean_k q_(j,k)
+  double* c;                 // c_j slots [2] (NULL for constrained nodes)
+  double* tpart;             // tile records
+};
+
+// One block of the tile kernel: rows [row0, row0 + kTileRows) of node item `node`.
+struct TileItem {
+  int32_t node, row0;
 };
 
 // Per-instance loop state, written only by the last node block of a half-sweep.
@@ -83,8 +109,8 @@ struct Tables {
   const MsgDesc* msgs;
   const K1Item* items;       // items of one class and one dimension (kernel argument slice)
   const NodeItem* nodes;     // node items of one class
+  const TileItem* tiles;     // tile items of one class
   InstState* inst;
-  double2* node_err;         // (sum, max) per node item
   double4* node_eval;        // evaluation pass: (err sum, err max, <Lam,mu> or rho, spread)
   int* ndone;                // number of instances that reached a final state
   int colour;                // class whose items / nodes these are
@@ -93,7 +119,8 @@ struct Tables {
 // Pair pass of the evaluation (transport, entropy, mass of each plan).
 struct EdgeDesc {
   const double* supp_a;  const double* supp_b;
-  const double* lam_a;   const double* lam_b;     // committed slots of Lam_(a,b), Lam_(b,a)
+  const double* lam_a;   const double* lam_b;     // committed slots of L_(a,b), L_(b,a)
+  const double* c_a;     const double* c_b;       // committed c of a and b (NULL: 0)
   const double* lg_a;    const double* lg_b;
   const float* cost;                              // explicit, row-major n_a x n_b, or NULL
   int32_t n_a, n_b, dim, cost_kind;
@@ -104,7 +131,12 @@ struct PairItem { int32_t edge, row0, col0, ncols; };
 // ---- launch wrappers (defined in gmot_kernels.hip) ----
 hipError_t launch_msg(const Tables& tb, int n_items, int dim, int rows_per_lane, bool fp64, int eval_src_slot,
                       hipStream_t s);
-hipError_t launch_node(const Tables& tb, int n_nodes, int colour, int eval_dst_slot, hipStream_t s);
+hipError_t launch_tile(const Tables& tb, int n_tiles, hipStream_t s);
+hipError_t launch_finalize(const Tables& tb, int n_inst, hipStream_t s);
+hipError_t launch_node_eval(const Tables& tb, int n_nodes, int slot, hipStream_t s);
+// dst[i] = src[i] - (c ? *c : 0) over segments (potential read-back on the device)
+struct SegCopy { const double* src; double* dst; const double* c; int64_t len; };
+hipError_t launch_seg_copy(const SegCopy* segs, int n_segs, hipStream_t s);
 hipError_t launch_stamp(InstState* inst, int count, hipStream_t s);
 hipError_t launch_pairs(const EdgeDesc* edges, const PairItem* items, int n_items, double4* out, hipStream_t s);
 hipError_t launch_coupling(const EdgeDesc* edge, double* out, size_t total, hipStream_t s);
@@ -136,5 +168,11 @@ struct gmot_ctx {
   bool own_stream = false;
   double clk_hz = 1.0e8;
   std::map<uint64_t, std::pair<int, int>> tuned;  // shape key -> (rows per lane, target blocks)
+  void* scratch = nullptr;                         // small tables of the warm-start calls
+  size_t scratch_size = 0;
 };
+// Accessors of the network object for the runtime's warm-start entry point.
+struct gmot_mlp;
+int gmot_mlp_widths(const gmot_mlp* m, int* n_in, int* n_out);
+int gmot_mlp_workspace(gmot_mlp* m, int B, float** x, float** y);
 #endif

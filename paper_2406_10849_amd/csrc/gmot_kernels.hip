@@ -1,19 +1,24 @@
 // gfx950 kernels of the bipartite iterative-scaling hot path.
 //
-//   k_msg   -- message log-sum-exp m_{k->j} over one (row tile, column split) of
-//              one message (the K u products of Theorem tree_dual_var, eq. q).
-//   k_node  -- per-node merge of the column splits, stopping-sum terms of the
-//              state before the update (Algorithm tree_local_reg, Lemma
-//              f_upper_bound_tree for the arithmetic mean), the update of
-//              eq. bipartite_tree_updates1/2 in its closed form (Proposition
-//              equi), and, in the last block of an instance, the stop decision.
-//   k_pairs -- FP64 transport / entropy / mass sums of every plan
-//              (eq. bi-marginal_B_sol, eq. ot_graph_pairwise_mass).
-//   k_coupling -- one plan written out in FP64.
+//   k_msg<..., ITER>  -- message log-sum-exp m_{k->j} over a (row tile, column
+//              split) of one message (the K u products of Theorem
+//              tree_dual_var, eq. q).
+//   k_tile     -- per 256-row tile of a node of the class: merge of the column
+//              splits, stopping-sum terms of the state before the update
+//              (Algorithm tree_local_reg; Lemma f_upper_bound_tree for the
+//              arithmetic mean) and the update of eq. bipartite_tree_updates1/2
+//              in its closed form (Proposition equi).
+//   k_finalize -- per instance: node normalisers, stopping sum, stop decision.
+//   k_msg<..., EVAL>  -- the same message LSE with given slots, no update.
+//   k_node_eval       -- evaluation: merge, stopping-sum terms, <Lam, mu> / rho.
+//   k_pairs           -- FP64 transport / entropy / mass sums of every plan
+//                        (eq. bi-marginal_B_sol, eq. ot_graph_pairwise_mass).
+//   k_coupling        -- one plan written out in FP64.
 //
 // Arithmetic contract of the FP32-core message kernel: FP64 potentials, FP64
 // exponent arguments (w - row max), FP32 v_exp_f32 on the reduced argument,
-// pairs of FP32 terms added in FP32 and accumulated in FP64, FP64 log.
+// pairs of FP32 terms added in FP32 and accumulated in FP64, FP64 merge, log,
+// stopping-sum terms and node normalisers.
 #include "gmot_internal.h"
 
 #include <cmath>
@@ -51,6 +56,56 @@ __device__ inline double block_max(double v, double* sh) {
 
 __device__ inline float exp2_hw(float x) { return __builtin_amdgcn_exp2f(x); }
 
+// m_{k->j}(x) in natural log from the column-split partials of row x.
+__device__ inline double merge_row(const MsgDesc& md, int n, int x, double x2) {
+  double Mx = -INFINITY;
+  for (int s = 0; s < md.ns; ++s) Mx = fmax(Mx, md.partial[(size_t)s * n + x].x);
+  if (!(Mx > -INFINITY)) return -INFINITY;
+  double S = 0.0;
+  for (int s = 0; s < md.ns; ++s) {
+    const double2 p = md.partial[(size_t)s * n + x];
+    if (p.y > 0.0) S += (p.x == Mx) ? p.y : p.y * exp2(p.x - Mx);
+  }
+  return (S > 0.0) ? kLn2 * (Mx + log2(S)) - x2 / md.eps : -INFINITY;
+}
+
+__device__ inline double sq_norm(const double* xs, int dim, int x) {
+  double x2 = 0.0;
+  for (int d = 0; d < dim; ++d) x2 = fma(xs[(size_t)x * dim + d], xs[(size_t)x * dim + d], x2);
+  return x2;
+}
+
+// Stop decision of an instance after its half-sweep t, from the stopping sum
+// E of the state before the update and its largest per-edge term Em (one
+// thread of the instance's finalise block).
+__device__ void decide(const Tables& tb, InstState* st, long long t, double E, double Em) {
+  bool stop = false;
+  if (!isfinite(E)) {
+    st->done = kNonFinite;
+    if (t >= 2) st->t = t - 1;  // roll back to the last state whose sum was finite
+    stop = true;
+  } else {
+    st->err_sum = E;
+    st->err_max = Em;
+    st->checked_t = t;
+    if (t >= st->min_check_t && E <= st->tol) {
+      st->done = kConverged;  // this half-sweep wrote only the unread slots
+      stop = true;
+    } else {
+      st->t = t + 1;
+      st->updates += 1;
+      if (st->updates >= st->max_updates) {
+        st->done = kMaxSteps;
+        stop = true;
+      }
+    }
+  }
+  if (stop) {
+    st->clk_stop = wall_clock64();
+    atomicAdd(tb.ndone, 1);
+  }
+}
+
 }  // namespace
 
 // ---------------------------------------------------------------------------
@@ -59,10 +114,11 @@ __device__ inline float exp2_hw(float x) { return __builtin_amdgcn_exp2f(x); }
 // within a chunk the row max is found first (pass 1) and the scaled sum taken
 // second (pass 2); across chunks the running sum is rescaled when the max
 // grows.  Output: (max, sum 2^(w - max)) per row for this column split.
+// ITER: slots come from the instance counter; finished instances (or those
+// whose next half-sweep updates the other class) return at entry.
 // ---------------------------------------------------------------------------
-template <int DIM, int R, bool F64, bool EXPL>
+template <int DIM, int R, bool F64, bool EXPL, bool ITER>
 __global__ __launch_bounds__(kBlock) void k_msg(Tables tb, int eval_src_slot) {
-  const int colour = tb.colour;
   constexpr int CH = EXPL ? 32 : kChunk;            // columns per LDS chunk
   constexpr int STR = EXPL ? 1 : (DIM == 1 ? 2 : 4); // doubles per staged column
   constexpr int TM = 256 * R;                        // rows per block
@@ -72,11 +128,10 @@ __global__ __launch_bounds__(kBlock) void k_msg(Tables tb, int eval_src_slot) {
   const K1Item it = tb.items[blockIdx.x];
   const MsgDesc* __restrict__ md = tb.msgs + it.msg;
   int src_slot = eval_src_slot;
-  if (eval_src_slot < 0) {
+  if (ITER) {
     const InstState* st = tb.inst + md->inst;
     const long long t = st->t;
-    // finished instances, and instances whose next half-sweep updates the other class, sit out
-    if (st->done || ((t & 1) == 1) != (colour == 0)) return;
+    if (st->done || ((t & 1) == 1) != (tb.colour == 0)) return;
     src_slot = (int)((t >> 1) & 1);
   }
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -85,6 +140,7 @@ __global__ __launch_bounds__(kBlock) void k_msg(Tables tb, int eval_src_slot) {
   const double cxs = 2.0 * kLog2e / eps;
   const double ces = -kLog2e / eps;
   const double* __restrict__ lam = md->lam_src[src_slot];
+  const double csrc = md->c_src ? md->c_src[src_slot] : 0.0;
   const double* __restrict__ lg = md->lg_src;
   const double* __restrict__ ys = md->supp_src;
 
@@ -112,7 +168,7 @@ __global__ __launch_bounds__(kBlock) void k_msg(Tables tb, int eval_src_slot) {
       for (int d = 0; d < DIM; ++d) y[d] = 0.0;
       if (threadIdx.x < cn) {
         const int col = it.col0 + c0 + threadIdx.x;
-        double base = lam[col] + lg[col];
+        double base = (lam[col] - csrc) + lg[col];
         if (!EXPL) {
           double y2 = 0.0;
 #pragma unroll
@@ -210,75 +266,149 @@ __global__ __launch_bounds__(kBlock) void k_msg(Tables tb, int eval_src_slot) {
 }
 
 // ---------------------------------------------------------------------------
-// Node update.  One block per node j of the class being updated.
-//   A: merge the column splits into m_{k->j}(x) (natural log), keep the
-//      mean message abar(x) and the arithmetic mean qbar(x) of
-//      q_(j,k)(x) = exp(Lam_(j,k)(x) + log gamma_j(x) + m_{k->j}(x)).
-//   B: stopping-sum terms of the held state: ||q_(j,k) - mu_j||_1 (fixed) or
-//      ||q_(j,k) - qbar_j||_1 (free), one per incident edge.
-//   C: update (skipped in evaluation mode):
-//        fixed  Lam_(j,k) = -m_{k->j}
-//        free   Lam_(j,k) = abar - LSE_x abar - m_{k->j}
-//   D: the last block of the instance sums the node terms and decides.
-// Evaluation mode (eval_dst_slot >= 0) reads the given slot, writes no
-// potentials and adds <Lam, mu> (fixed) or rho_j and its spread (free).
+// Tile kernel: one thread per row x of a 256-row tile of node j.
+//   merge  m_{k->j}(x) from the column splits (FP64)
+//   terms  fixed:  mu(x) |expm1(Lam_(j,k)(x) + m_{k->j}(x))| = |q_(j,k)(x) - mu(x)|
+//          free:   |q_(j,k)(x) - qbar(x)|, q = exp(Lam + m), qbar the mean over k
+//   update fixed:  L_(j,k) = -m_{k->j}        (c_j = 0)
+//          free:   L_(j,k) = abar - m_{k->j}  (abar = mean_k m; c_j = LSE_x abar
+//                  is formed by the finalise kernel from the tile records)
+// Record: per incident edge the tile's sum of terms, then the tile's LSE of abar.
 // ---------------------------------------------------------------------------
-template <bool EVAL>
-__global__ __launch_bounds__(kBlock) void k_node(Tables tb, int colour, int eval_dst_slot) {
+__global__ __launch_bounds__(kBlock) void k_tile(Tables tb) {
   __shared__ double sh[4];
-  __shared__ int s_last;
-  const NodeItem nd = tb.nodes[blockIdx.x];
-  InstState* st = tb.inst + nd.inst;
-  long long t = 0;
-  int cur = eval_dst_slot, nxt = 0;
-  if (!EVAL) {
-    if (st->done) return;
-    t = st->t;
-    if (((t & 1) == 1) != (colour == 0)) return;  // this instance updates the other class next
-    cur = (int)(((t - 1) >> 1) & 1);
-    nxt = cur ^ 1;
-  }
-  const int n = nd.n, deg = nd.deg;
+  const TileItem ti = tb.tiles[blockIdx.x];
+  const NodeItem& nd = tb.nodes[ti.node];
+  const InstState* st = tb.inst + nd.inst;
+  const long long t = st->t;
+  if (st->done || ((t & 1) == 1) != (tb.colour == 0)) return;
+  const int cur = (int)(((t - 1) >> 1) & 1), nxt = cur ^ 1;
   const MsgDesc* __restrict__ mds = tb.msgs + nd.msg0;
-  const double eps = mds[0].eps;
+  const int n = nd.n, deg = nd.deg;
   const int dim = mds[0].dim;
   const bool sq = mds[0].cost_kind == 0;
   const double* __restrict__ xs = mds[0].supp_dst;
+  const double c_old = nd.c ? nd.c[cur] : 0.0;
+  double* rec = nd.tpart + (size_t)(ti.row0 / kTileRows) * (deg + 2);
+  const int x = ti.row0 + threadIdx.x;
+  const bool vx = x < n;
 
-  // A
-  for (int x = threadIdx.x; x < n; x += kBlock) {
-    double x2 = 0.0;
-    if (sq)
-      for (int d = 0; d < dim; ++d) x2 = fma(xs[(size_t)x * dim + d], xs[(size_t)x * dim + d], x2);
-    const double lgx = nd.lg[x];
+  double a = -INFINITY, qb = 0.0;
+  if (vx) {
+    const double x2 = sq ? sq_norm(xs, dim, x) : 0.0;
     double asum = 0.0, qsum = 0.0;
     for (int k = 0; k < deg; ++k) {
       const MsgDesc& md = mds[k];
-      double Mx = -INFINITY;
-      for (int s = 0; s < md.ns; ++s) Mx = fmax(Mx, md.partial[(size_t)s * n + x].x);
-      double S = 0.0;
-      if (Mx > -INFINITY)
-        for (int s = 0; s < md.ns; ++s) {
-          const double2 p = md.partial[(size_t)s * n + x];
-          if (p.y > 0.0) S += p.y * exp2(p.x - Mx);
-        }
-      const double m = (S > 0.0) ? kLn2 * (Mx + log2(S)) - x2 / eps : -INFINITY;
+      const double m = merge_row(md, n, x, x2);
       md.mfull[x] = m;
       asum += m;
-      qsum += exp(md.lam_dst[cur][x] + lgx + m);
+      if (!nd.fixed) qsum += exp(md.lam_dst[cur][x] - c_old + m);
     }
-    nd.abar[x] = asum / deg;
+    a = asum / deg;
+    qb = qsum / deg;
+  }
+  for (int k = 0; k < deg; ++k) {
+    const MsgDesc& md = mds[k];
+    double part = 0.0;
+    if (vx) {
+      const double m = md.mfull[x];
+      const double l = md.lam_dst[cur][x];
+      if (nd.fixed) {
+        const double mu = nd.mu[x];
+        if (mu > 0.0) part = mu * fabs(expm1(l + m));
+        md.lam_dst[nxt][x] = -m;
+      } else {
+        part = fabs(exp(l - c_old + m) - qb);
+        md.lam_dst[nxt][x] = a - m;
+      }
+    }
+    const double tot = block_sum(part, sh);
+    if (threadIdx.x == 0) rec[k] = tot;
+  }
+  if (!nd.fixed) {
+    const double M = block_max(a, sh);
+    const double s = (vx && a > -INFINITY) ? exp(a - M) : 0.0;
+    const double S = block_sum(s, sh);
+    if (threadIdx.x == 0) {
+      rec[deg] = M;
+      rec[deg + 1] = S;
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Finalise kernel: one block per instance.  Thread i handles the instance's
+// class nodes i, i + 256, ...: per-edge terms summed over tiles (the node's
+// stopping-sum terms), and for free nodes c_j = LSE over the tile records;
+// then the block sums the terms and thread 0 takes the stop decision.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(kBlock) void k_finalize(Tables tb) {
+  __shared__ double sh[4];
+  InstState* st = tb.inst + blockIdx.x;
+  const long long t = st->t;
+  if (st->done || ((t & 1) == 1) != (tb.colour == 0)) return;
+  const int nxt = (int)((((t - 1) >> 1) & 1) ^ 1);
+  const int i0 = st->node0[tb.colour], cnt = st->nnodes[tb.colour];
+  double esum = 0.0, emax = 0.0;
+  for (int i = threadIdx.x; i < cnt; i += kBlock) {
+    const NodeItem& nd = tb.nodes[i0 + i];
+    const int deg = nd.deg;
+    for (int k = 0; k < deg; ++k) {
+      double e = 0.0;
+      for (int tt = 0; tt < nd.tiles; ++tt) e += nd.tpart[(size_t)tt * (deg + 2) + k];
+      esum += e;
+      emax = fmax(emax, e);
+    }
+    if (!nd.fixed) {
+      double M = -INFINITY;
+      for (int tt = 0; tt < nd.tiles; ++tt) M = fmax(M, nd.tpart[(size_t)tt * (deg + 2) + deg]);
+      double S = 0.0;
+      for (int tt = 0; tt < nd.tiles; ++tt) {
+        const double mt = nd.tpart[(size_t)tt * (deg + 2) + deg];
+        if (mt > -INFINITY) S += nd.tpart[(size_t)tt * (deg + 2) + deg + 1] * exp(mt - M);
+      }
+      nd.c[nxt] = M + log(S);
+    }
+  }
+  const double E = block_sum(esum, sh);
+  const double Em = block_max(emax, sh);
+  if (threadIdx.x == 0) decide(tb, st, t, E, Em);
+}
+
+// ---------------------------------------------------------------------------
+// Evaluation node pass (one block per node, given slot): merge the splits,
+// stopping-sum terms of the state, qbar (the node marginal q_bar_j), and
+// <Lam, mu> (constrained) or rho_j and its spread in x (free).
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(kBlock) void k_node_eval(Tables tb, int slot) {
+  __shared__ double sh[4];
+  const NodeItem nd = tb.nodes[blockIdx.x];
+  const int n = nd.n, deg = nd.deg;
+  const MsgDesc* __restrict__ mds = tb.msgs + nd.msg0;
+  const int dim = mds[0].dim;
+  const bool sq = mds[0].cost_kind == 0;
+  const double* __restrict__ xs = mds[0].supp_dst;
+  const double cj = nd.c ? nd.c[slot] : 0.0;
+
+  for (int x = threadIdx.x; x < n; x += kBlock) {
+    const double x2 = sq ? sq_norm(xs, dim, x) : 0.0;
+    const double lgx = nd.lg[x];
+    double qsum = 0.0;
+    for (int k = 0; k < deg; ++k) {
+      const MsgDesc& md = mds[k];
+      const double m = merge_row(md, n, x, x2);
+      md.mfull[x] = m;
+      qsum += exp(md.lam_dst[slot][x] - cj + lgx + m);
+    }
     nd.qbar[x] = qsum / deg;
   }
   __syncthreads();
-
-  // B
   double e_sum = 0.0, e_max = 0.0;
   for (int k = 0; k < deg; ++k) {
     const MsgDesc& md = mds[k];
     double part = 0.0;
     for (int x = threadIdx.x; x < n; x += kBlock) {
-      const double q = exp(md.lam_dst[cur][x] + nd.lg[x] + md.mfull[x]);
+      const double q = exp(md.lam_dst[slot][x] - cj + nd.lg[x] + md.mfull[x]);
       const double ref = nd.fixed ? nd.mu[x] : nd.qbar[x];
       part += fabs(q - ref);
     }
@@ -286,102 +416,30 @@ __global__ __launch_bounds__(kBlock) void k_node(Tables tb, int colour, int eval
     e_sum += tot;
     e_max = fmax(e_max, tot);
   }
-
-  if (EVAL) {
-    double v0 = 0.0, lo = INFINITY, hi = -INFINITY;
-    if (nd.fixed) {
-      for (int k = 0; k < deg; ++k) {
-        const double* L = mds[k].lam_dst[cur];
-        for (int x = threadIdx.x; x < n; x += kBlock) {
-          const double l = L[x];
-          if (nd.mu[x] > 0.0 && isfinite(l)) v0 += l * nd.mu[x];
-        }
-      }
-      v0 = block_sum(v0, sh);
-      lo = hi = 0.0;
-    } else {
-      for (int x = threadIdx.x; x < n; x += kBlock) {
-        double tot = 0.0;
-        for (int k = 0; k < deg; ++k) tot += mds[k].lam_dst[cur][x];
-        v0 += tot;
-        lo = fmin(lo, tot);
-        hi = fmax(hi, tot);
-      }
-      v0 = block_sum(v0, sh) / n;
-      lo = -block_max(-lo, sh);
-      hi = block_max(hi, sh);
-    }
-    if (threadIdx.x == 0) tb.node_eval[nd.err_idx] = make_double4(e_sum, e_max, v0, hi - lo);
-    return;
-  }
-
-  // C
+  double v0 = 0.0, lo = INFINITY, hi = -INFINITY;
   if (nd.fixed) {
     for (int k = 0; k < deg; ++k) {
-      const MsgDesc& md = mds[k];
-      double* out = md.lam_dst[nxt];
-      for (int x = threadIdx.x; x < n; x += kBlock) out[x] = -md.mfull[x];
-    }
-  } else {
-    double mx = -INFINITY;
-    for (int x = threadIdx.x; x < n; x += kBlock) mx = fmax(mx, nd.abar[x]);
-    mx = block_max(mx, sh);
-    double s = 0.0;
-    for (int x = threadIdx.x; x < n; x += kBlock) s += exp(nd.abar[x] - mx);
-    s = block_sum(s, sh);
-    const double lse = mx + log(s);
-    for (int k = 0; k < deg; ++k) {
-      const MsgDesc& md = mds[k];
-      double* out = md.lam_dst[nxt];
-      for (int x = threadIdx.x; x < n; x += kBlock) out[x] = (nd.abar[x] - lse) - md.mfull[x];
-    }
-  }
-
-  // D
-  if (threadIdx.x == 0) {
-    tb.node_err[nd.err_idx] = make_double2(e_sum, e_max);
-    __threadfence();
-    const int old = atomicAdd(&st->counter, 1);
-    s_last = (old == st->nnodes[colour] - 1);
-  }
-  __syncthreads();
-  if (s_last && threadIdx.x == 0) {
-    __threadfence();
-    double E = 0.0, Em = 0.0;
-    const int i0 = st->node0[colour], cnt = st->nnodes[colour];
-    for (int i = 0; i < cnt; ++i) {
-      const double2 v = tb.node_err[i0 + i];
-      E += v.x;
-      Em = fmax(Em, v.y);
-    }
-    st->counter = 0;
-    bool stop = false;
-    if (!isfinite(E)) {
-      st->done = kNonFinite;
-      if (t >= 2) st->t = t - 1;   // roll back to the last state whose sum was finite
-      stop = true;
-    } else {
-      st->err_sum = E;
-      st->err_max = Em;
-      st->checked_t = t;
-      if (t >= st->min_check_t && E <= st->tol) {
-        st->done = kConverged;     // step t's writes went to the unread slot
-        stop = true;
-      } else {
-        st->t = t + 1;
-        st->updates += 1;
-        if (st->updates >= st->max_updates) {
-          st->done = kMaxSteps;
-          stop = true;
-        }
+      const double* Ls = mds[k].lam_dst[slot];
+      for (int x = threadIdx.x; x < n; x += kBlock) {
+        const double l = Ls[x];
+        if (nd.mu[x] > 0.0 && isfinite(l)) v0 += l * nd.mu[x];
       }
     }
-    if (stop) {
-      st->clk_stop = wall_clock64();
-      __threadfence();
-      atomicAdd(tb.ndone, 1);
+    v0 = block_sum(v0, sh);
+    lo = hi = 0.0;
+  } else {
+    for (int x = threadIdx.x; x < n; x += kBlock) {
+      double tot = 0.0;
+      for (int k = 0; k < deg; ++k) tot += mds[k].lam_dst[slot][x] - cj;
+      v0 += tot;
+      lo = fmin(lo, tot);
+      hi = fmax(hi, tot);
     }
+    v0 = block_sum(v0, sh) / n;
+    lo = -block_max(-lo, sh);
+    hi = block_max(hi, sh);
   }
+  if (threadIdx.x == 0) tb.node_eval[nd.err_idx] = make_double4(e_sum, e_max, v0, hi - lo);
 }
 
 __global__ void k_stamp(InstState* inst, int count) {
@@ -402,9 +460,11 @@ __global__ __launch_bounds__(kBlock) void k_pairs(const EdgeDesc* edges, const P
   const int x = it.row0 + threadIdx.x;
   const bool vx = x < ed.n_a;
   const bool sq = ed.cost_kind == 0;
+  const double ca = ed.c_a ? *ed.c_a : 0.0;
+  const double cb = ed.c_b ? *ed.c_b : 0.0;
   double ax = -INFINITY, lax = 0.0, xp[3] = {0.0, 0.0, 0.0};
   if (vx) {
-    lax = ed.lam_a[x];
+    lax = ed.lam_a[x] - ca;
     ax = lax + ed.lg_a[x];
     if (sq)
       for (int d = 0; d < ed.dim; ++d) xp[d] = ed.supp_a[(size_t)x * ed.dim + d];
@@ -415,7 +475,7 @@ __global__ __launch_bounds__(kBlock) void k_pairs(const EdgeDesc* edges, const P
     __syncthreads();
     if (threadIdx.x < cn) {
       const int y = it.col0 + c0 + threadIdx.x;
-      s_b[threadIdx.x] = ed.lam_b[y];
+      s_b[threadIdx.x] = ed.lam_b[y] - cb;
       if (sq)
         for (int d = 0; d < ed.dim; ++d) s_y[threadIdx.x * 3 + d] = ed.supp_b[(size_t)y * ed.dim + d];
     }
@@ -453,6 +513,8 @@ __global__ __launch_bounds__(kBlock) void k_pairs(const EdgeDesc* edges, const P
 
 __global__ __launch_bounds__(kBlock) void k_coupling(const EdgeDesc* edp, double* out) {
   const EdgeDesc ed = *edp;
+  const double ca = ed.c_a ? *ed.c_a : 0.0;
+  const double cb = ed.c_b ? *ed.c_b : 0.0;
   const size_t total = (size_t)ed.n_a * ed.n_b;
   for (size_t i = (size_t)blockIdx.x * kBlock + threadIdx.x; i < total; i += (size_t)gridDim.x * kBlock) {
     const int x = (int)(i / ed.n_b), y = (int)(i % ed.n_b);
@@ -466,7 +528,7 @@ __global__ __launch_bounds__(kBlock) void k_coupling(const EdgeDesc* edp, double
     } else {
       C = (double)ed.cost[i];
     }
-    out[i] = exp(ed.lam_a[x] + ed.lg_a[x] + ed.lam_b[y] + ed.lg_b[y] - C / ed.eps);
+    out[i] = exp((ed.lam_a[x] - ca) + ed.lg_a[x] + (ed.lam_b[y] - cb) + ed.lg_b[y] - C / ed.eps);
   }
 }
 
@@ -475,7 +537,10 @@ __global__ __launch_bounds__(kBlock) void k_coupling(const EdgeDesc* edp, double
 // ---------------------------------------------------------------------------
 template <int DIM, int R, bool F64, bool EXPL>
 static hipError_t launch_msg_t(const Tables& tb, int n_items, int eval_src_slot, hipStream_t s) {
-  hipLaunchKernelGGL((k_msg<DIM, R, F64, EXPL>), dim3(n_items), dim3(kBlock), 0, s, tb, eval_src_slot);
+  if (eval_src_slot >= 0)
+    hipLaunchKernelGGL((k_msg<DIM, R, F64, EXPL, false>), dim3(n_items), dim3(kBlock), 0, s, tb, eval_src_slot);
+  else
+    hipLaunchKernelGGL((k_msg<DIM, R, F64, EXPL, true>), dim3(n_items), dim3(kBlock), 0, s, tb, -1);
   return hipGetLastError();
 }
 
@@ -501,12 +566,33 @@ hipError_t launch_msg(const Tables& tb, int n_items, int dim, int rows_per_lane,
               : launch_msg_r<1, false>(tb, n_items, dim, eval_src_slot, s);
 }
 
-hipError_t launch_node(const Tables& tb, int n_nodes, int colour, int eval_dst_slot, hipStream_t s) {
+hipError_t launch_tile(const Tables& tb, int n_tiles, hipStream_t s) {
+  if (n_tiles <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_tile, dim3(n_tiles), dim3(kBlock), 0, s, tb);
+  return hipGetLastError();
+}
+
+hipError_t launch_finalize(const Tables& tb, int n_inst, hipStream_t s) {
+  if (n_inst <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_finalize, dim3(n_inst), dim3(kBlock), 0, s, tb);
+  return hipGetLastError();
+}
+
+hipError_t launch_node_eval(const Tables& tb, int n_nodes, int slot, hipStream_t s) {
   if (n_nodes <= 0) return hipSuccess;
-  if (eval_dst_slot >= 0)
-    hipLaunchKernelGGL((k_node<true>), dim3(n_nodes), dim3(kBlock), 0, s, tb, colour, eval_dst_slot);
-  else
-    hipLaunchKernelGGL((k_node<false>), dim3(n_nodes), dim3(kBlock), 0, s, tb, colour, -1);
+  hipLaunchKernelGGL(k_node_eval, dim3(n_nodes), dim3(kBlock), 0, s, tb, slot);
+  return hipGetLastError();
+}
+
+__global__ __launch_bounds__(kBlock) void k_seg_copy(const SegCopy* segs) {
+  const SegCopy sg = segs[blockIdx.x];
+  const double c = sg.c ? *sg.c : 0.0;
+  for (int64_t i = threadIdx.x; i < sg.len; i += kBlock) sg.dst[i] = sg.src[i] - c;
+}
+
+hipError_t launch_seg_copy(const SegCopy* segs, int n_segs, hipStream_t s) {
+  if (n_segs <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_seg_copy, dim3(n_segs), dim3(kBlock), 0, s, segs);
   return hipGetLastError();
 }
 

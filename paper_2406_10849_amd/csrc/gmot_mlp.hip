@@ -382,7 +382,7 @@ static int mlp_forward(gmot_mlp* m, const float* x, int B) {
     g.C = m->H[l];
     g.Cq = l < m->L ? m->Hq[l] : nullptr;
     g.bias = m->params + m->offB[l];
-    MCHK(l < m->L ? gemm<false, true, kBiasRelu>(g, s) : gemm<false, true, kBias>(g, s));
+    MCHK((l < m->L ? gemm<false, true, kBiasRelu>(g, s) : gemm<false, true, kBias>(g, s)));
   }
   return GMOT_OK;
 }
@@ -466,8 +466,8 @@ int gmot_mlp_set_params(gmot_mlp* m, const float* in) {
   if (!m || !in) return mfail(GMOT_EINVAL, "null network or input");
   MCHK(hipStreamSynchronize(m->ctx->stream));
   MCHK(hipMemcpy(m->params, in, sizeof(float) * m->nparams, hipMemcpyHostToDevice));
-  MCHK(hipMemset(m->m1, 0, sizeof(float) * m->nparams));
-  MCHK(hipMemset(m->m2, 0, sizeof(float) * m->nparams));
+  MCHK(hipMemsetAsync(m->m1, 0, sizeof(float) * m->nparams, m->ctx->stream));
+  MCHK(hipMemsetAsync(m->m2, 0, sizeof(float) * m->nparams, m->ctx->stream));
   m->adam_t = 0;
   return m->refresh_wq();
 }

@@ -76,9 +76,12 @@ struct gmot_problem {
   double* d_mfull = nullptr;
   double* d_abar = nullptr;
   double* d_qbar = nullptr;
+  double* d_c = nullptr;  // [2N]: node normaliser c_j, slot s at 2j + s (0 for constrained nodes)
   float* d_cost = nullptr;
   int64_t t = 1;
   Plan* plan = nullptr;
+
+  const double* c_ptr(int j) const { return fixed[j] ? nullptr : d_c + 2 * j; }
 
   int de_of(int j, int k) const {
     for (size_t i = 0; i < nbrs[j].size(); ++i)
@@ -91,11 +94,10 @@ struct gmot_problem {
 
 // A captured run of k half-sweeps.  The timed variant is not captured: it
 // launches the k half-sweeps directly, recording one of two alternating chains
-// of 2k + 1 events (before the message stage of step i, between message and
-// node stage, after the node stage), so one chain can be read back while the
-// next replay runs.
+// of 3k events (before step i, after its message stage, after its finalise
+// kernel), so one chain can be read back while the next replay runs.
 struct GraphEntry {
-  bool fp64 = false, timed = false;
+  bool fp64 = false, timed = false, per_edge = false;
   int start = 0, k = 0;
   hipGraphExec_t exec[2] = {nullptr, nullptr};
   std::vector<hipEvent_t> ev[2];
@@ -108,6 +110,7 @@ struct Plan {
   int target_blocks = 1536;
   std::vector<MsgDesc> msgs;
   std::vector<K1Item> items[2][4];  // [class][0 = explicit, 1..3 = dim]
+  std::vector<std::pair<int, int>> msg_items[2][4];  // per message: (first item, item count)
   std::vector<NodeItem> nodes[2];
   std::vector<InstState> inst;
   int total_nodes = 0;
@@ -116,10 +119,12 @@ struct Plan {
   K1Item* d_items[2][4] = {};
   NodeItem* d_nodes[2] = {};
   InstState* d_inst = nullptr;
-  double2* d_node_err = nullptr;
   double4* d_node_eval = nullptr;
   int* d_ndone = nullptr;
   double2* d_partial = nullptr;
+  double* d_tpart = nullptr;
+  std::vector<TileItem> tiles[2];
+  TileItem* d_tiles[2] = {};
   int* h_ndone = nullptr;  // pinned, two mailboxes
   std::vector<GraphEntry> graphs;
   TileStats stats;
@@ -142,25 +147,39 @@ struct Plan {
     tb.items = dk >= 0 ? d_items[c][dk] : nullptr;
     tb.nodes = d_nodes[c];
     tb.inst = d_inst;
-    tb.node_err = d_node_err;
     tb.node_eval = d_node_eval;
     tb.ndone = d_ndone;
+    tb.tiles = d_tiles[c];
     tb.colour = c;
     return tb;
   }
 
-  // One half-sweep for class c; with `ev`, events ev[0] before the message
-  // stage, ev[1] between the stages and ev[2] after the node stage.
-  hipError_t launch_tstep(int c, bool fp64, hipStream_t s, const hipEvent_t* ev = nullptr) const {
+  // One half-sweep for class c: the message kernel (one launch per support
+  // dimension, or with per_edge one launch per message), then the tile and
+  // finalise kernels; with `ev`, events ev[0] before, ev[1] after the message
+  // stage and ev[2] after the finalise kernel.
+  hipError_t launch_tstep(int c, bool fp64, hipStream_t s, const hipEvent_t* ev = nullptr,
+                          bool per_edge = false) const {
     hipError_t e;
     if (ev && (e = hipEventRecord(ev[0], s)) != hipSuccess) return e;
     for (int dk = 0; dk < 4; ++dk) {
       if (items[c][dk].empty()) continue;
-      e = launch_msg(tables(c, dk), (int)items[c][dk].size(), dk, R, fp64, -1, s);
-      if (e != hipSuccess) return e;
+      if (!per_edge) {
+        e = launch_msg(tables(c, dk), (int)items[c][dk].size(), dk, R, fp64, -1, s);
+        if (e != hipSuccess) return e;
+        continue;
+      }
+      for (const auto& r : msg_items[c][dk]) {
+        Tables tb = tables(c, dk);
+        tb.items += r.first;
+        e = launch_msg(tb, r.second, dk, R, fp64, -1, s);
+        if (e != hipSuccess) return e;
+      }
     }
     if (ev && (e = hipEventRecord(ev[1], s)) != hipSuccess) return e;
-    e = launch_node(tables(c, -1), (int)nodes[c].size(), c, -1, s);
+    e = launch_tile(tables(c, -1), (int)tiles[c].size(), s);
+    if (e != hipSuccess) return e;
+    e = launch_finalize(tables(c, -1), (int)inst.size(), s);
     if (e != hipSuccess) return e;
     if (ev && (e = hipEventRecord(ev[2], s)) != hipSuccess) return e;
     return hipSuccess;
@@ -186,7 +205,7 @@ static int build_plan(gmot_ctx* ctx, const std::vector<gmot_problem*>& probs, in
     gmot_problem* p = probs[i];
     InstState st{};
     for (int c = 0; c < 2; ++c) {
-      st.node0[c] = err_counter;
+      st.node0[c] = (int)pl->nodes[c].size();
       int cnt = 0;
       for (int j = 0; j < p->N; ++j) {
         if (p->colour[j] != c || p->nbrs[j].empty()) continue;
@@ -202,6 +221,10 @@ static int build_plan(gmot_ctx* ctx, const std::vector<gmot_problem*>& probs, in
         nd.mu = p->fixed[j] ? p->d_mu + p->node_off[j] : nullptr;
         nd.abar = p->d_abar + p->node_off[j];
         nd.qbar = p->d_qbar + p->node_off[j];
+        nd.c = p->fixed[j] ? nullptr : p->d_c + 2 * j;
+        nd.tiles = (int)ceil_div(p->sizes[j], kTileRows);
+        for (int r = 0; r < nd.tiles; ++r)
+          pl->tiles[c].push_back({(int)pl->nodes[c].size(), r * kTileRows});
         pl->nodes[c].push_back(nd);
         ++cnt;
         for (size_t q = 0; q < p->nbrs[j].size(); ++q) {
@@ -216,6 +239,7 @@ static int build_plan(gmot_ctx* ctx, const std::vector<gmot_problem*>& probs, in
             md.lam_dst[s] = p->d_lam[s] + p->de_off[de_dst];
           }
           md.lg_src = p->d_lg + p->node_off[k];
+          md.c_src = p->c_ptr(k);
           md.mfull = p->d_mfull + p->de_off[de_dst];
           if (p->cost_kind == GMOT_COST_EXPLICIT) {
             const int e = de_dst >> 1;
@@ -263,6 +287,7 @@ static int build_plan(gmot_ctx* ctx, const std::vector<gmot_problem*>& probs, in
     partial_total += ns * md.n_dst;
     pl->stats.max_splits = std::max(pl->stats.max_splits, (int)ns);
     const int dk = md.cost_kind == GMOT_COST_EXPLICIT ? 0 : md.dim;
+    pl->msg_items[c][dk].push_back({(int)pl->items[c][dk].size(), (int)(ceil_div(md.n_dst, TM) * ns)});
     for (int64_t rt = 0; rt < ceil_div(md.n_dst, TM); ++rt)
       for (int64_t s = 0; s < ns; ++s) {
         K1Item it{};
@@ -274,6 +299,14 @@ static int build_plan(gmot_ctx* ctx, const std::vector<gmot_problem*>& probs, in
         pl->items[c][dk].push_back(it);
       }
   }
+  // tile records of every node
+  int64_t tpart_total = 0;
+  std::vector<int64_t> tpart_off[2];
+  for (int c = 0; c < 2; ++c)
+    for (const NodeItem& nd : pl->nodes[c]) {
+      tpart_off[c].push_back(tpart_total);
+      tpart_total += (int64_t)nd.tiles * (nd.deg + 2);
+    }
   for (int c = 0; c < 2; ++c) {
     pl->stats.blocks[c] = 0;
     for (int dk = 0; dk < 4; ++dk) pl->stats.blocks[c] += (int)pl->items[c][dk].size();
@@ -293,10 +326,12 @@ static int build_plan(gmot_ctx* ctx, const std::vector<gmot_problem*>& probs, in
   size_t o_nodes[2];
   for (int c = 0; c < 2; ++c) o_nodes[c] = take(sizeof(NodeItem) * pl->nodes[c].size());
   const size_t o_inst = take(sizeof(InstState) * pl->inst.size());
-  const size_t o_err = take(sizeof(double2) * std::max(1, pl->total_nodes));
   const size_t o_eval = take(sizeof(double4) * std::max(1, pl->total_nodes));
   const size_t o_ndone = take(sizeof(int) * 4);
   const size_t o_part = take(sizeof(double2) * std::max<int64_t>(1, partial_total));
+  size_t o_tiles[2];
+  for (int c = 0; c < 2; ++c) o_tiles[c] = take(sizeof(TileItem) * pl->tiles[c].size());
+  const size_t o_tpart = take(sizeof(double) * std::max<int64_t>(1, tpart_total));
   const size_t total = off;
   if (hipMalloc(&pl->arena, total) != hipSuccess) return fail(GMOT_ENOMEM, "plan arena allocation failed");
   char* base = (char*)pl->arena;
@@ -305,10 +340,13 @@ static int build_plan(gmot_ctx* ctx, const std::vector<gmot_problem*>& probs, in
     for (int dk = 0; dk < 4; ++dk) pl->d_items[c][dk] = (K1Item*)(base + o_items[c][dk]);
   for (int c = 0; c < 2; ++c) pl->d_nodes[c] = (NodeItem*)(base + o_nodes[c]);
   pl->d_inst = (InstState*)(base + o_inst);
-  pl->d_node_err = (double2*)(base + o_err);
   pl->d_node_eval = (double4*)(base + o_eval);
   pl->d_ndone = (int*)(base + o_ndone);
   pl->d_partial = (double2*)(base + o_part);
+  for (int c = 0; c < 2; ++c) pl->d_tiles[c] = (TileItem*)(base + o_tiles[c]);
+  pl->d_tpart = (double*)(base + o_tpart);
+  for (int c = 0; c < 2; ++c)
+    for (size_t i = 0; i < pl->nodes[c].size(); ++i) pl->nodes[c][i].tpart = pl->d_tpart + tpart_off[c][i];
   for (size_t m = 0; m < pl->msgs.size(); ++m) pl->msgs[m].partial = pl->d_partial + partial_off[m];
 
   hipStream_t s = ctx->stream;
@@ -320,6 +358,9 @@ static int build_plan(gmot_ctx* ctx, const std::vector<gmot_problem*>& probs, in
                               hipMemcpyHostToDevice, s));
     if (!pl->nodes[c].empty())
       HIPCHK(hipMemcpyAsync(pl->d_nodes[c], pl->nodes[c].data(), sizeof(NodeItem) * pl->nodes[c].size(),
+                            hipMemcpyHostToDevice, s));
+    if (!pl->tiles[c].empty())
+      HIPCHK(hipMemcpyAsync(pl->d_tiles[c], pl->tiles[c].data(), sizeof(TileItem) * pl->tiles[c].size(),
                             hipMemcpyHostToDevice, s));
   }
   HIPCHK(hipHostMalloc((void**)&pl->h_ndone, sizeof(int) * 2, hipHostMallocDefault));
@@ -370,13 +411,13 @@ static int choose_tiles(gmot_ctx* ctx, const std::vector<gmot_problem*>& probs, 
   return 0;
 }
 
-static int capture_one(Plan* pl, bool fp64, int start, int k, const std::vector<hipEvent_t>* ev,
+static int capture_one(Plan* pl, bool fp64, bool per_edge, int start, int k, const std::vector<hipEvent_t>* ev,
                        hipGraphExec_t* out) {
   hipStream_t s = pl->ctx->stream;
   HIPCHK(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
   hipError_t le = hipSuccess;
   for (int i = 0; i < k && le == hipSuccess; ++i)
-    le = pl->launch_tstep((start + i) & 1, fp64, s, ev ? ev->data() + 2 * i : nullptr);
+    le = pl->launch_tstep((start + i) & 1, fp64, s, ev ? ev->data() + 3 * i : nullptr, per_edge);
   hipGraph_t graph = nullptr;
   hipError_t ce = hipStreamEndCapture(s, &graph);
   if (le != hipSuccess) {
@@ -392,9 +433,9 @@ static int capture_one(Plan* pl, bool fp64, int start, int k, const std::vector<
   return GMOT_OK;
 }
 
-static int get_graph(Plan* pl, bool fp64, int start, int k, bool timed, GraphEntry** out) {
+static int get_graph(Plan* pl, bool fp64, bool per_edge, int start, int k, bool timed, GraphEntry** out) {
   for (auto& g : pl->graphs)
-    if (g.fp64 == fp64 && g.start == start && g.k == k && g.timed == timed) {
+    if (g.fp64 == fp64 && g.per_edge == per_edge && g.start == start && g.k == k && g.timed == timed) {
       *out = &g;
       return GMOT_OK;
     }
@@ -403,15 +444,16 @@ static int get_graph(Plan* pl, bool fp64, int start, int k, bool timed, GraphEnt
   g.start = start;
   g.k = k;
   g.timed = timed;
+  g.per_edge = per_edge;
   if (timed) {
     // HIP events recorded by graph nodes cannot be timed, so the timed variant
     // launches directly on the stream with two alternating event chains.
     for (int c = 0; c < 2; ++c) {
-      g.ev[c].resize(2 * k + 1);
+      g.ev[c].resize(3 * k);
       for (auto& e : g.ev[c]) HIPCHK(hipEventCreate(&e));
     }
   } else {
-    int rc = capture_one(pl, fp64, start, k, nullptr, &g.exec[0]);
+    int rc = capture_one(pl, fp64, per_edge, start, k, nullptr, &g.exec[0]);
     if (rc) return rc;
   }
   pl->graphs.push_back(std::move(g));
@@ -471,10 +513,11 @@ static int run_plan(Plan* pl, const gmot_opts* o, gmot_result* outs, const std::
     const int start = parity == 1 ? 0 : 1;  // odd t updates class 0
     const bool fp64 = o->precision == GMOT_PREC_FP64;
     const bool timed = o->timing != 0;
+    const bool per_edge = o->schedule == GMOT_SCHED_PER_EDGE;
     const bool no_graph = std::getenv("GMOT_NO_GRAPH") != nullptr && !timed;
     GraphEntry* g = nullptr;
     if (!no_graph) {
-      int rc = get_graph(pl, fp64, start, k, timed, &g);
+      int rc = get_graph(pl, fp64, per_edge, start, k, timed, &g);
       if (rc) return rc;
     }
     HIPCHK(launch_stamp(pl->d_inst, (int)n, s));
@@ -487,17 +530,17 @@ static int run_plan(Plan* pl, const gmot_opts* o, gmot_result* outs, const std::
     HIPCHK(hipEventCreateWithFlags(&ev[0], hipEventDisableTiming));
     HIPCHK(hipEventCreateWithFlags(&ev[1], hipEventDisableTiming));
     // per-step durations of timed replays: (step since the start of this call, message ms, node ms)
-    struct StepTime { int64_t step; float msg_ms, node_ms; };
+    struct StepTime { int64_t step; float msg_ms, sweep_ms; };
     std::vector<StepTime> times;
     auto launch_one = [&](int slot) -> hipError_t {
       hipError_t e;
       if (timed) {
         e = hipSuccess;
         for (int i = 0; i < k && e == hipSuccess; ++i)
-          e = pl->launch_tstep((start + i) & 1, fp64, s, g->ev[slot].data() + 2 * i);
+          e = pl->launch_tstep((start + i) & 1, fp64, s, g->ev[slot].data() + 3 * i, per_edge);
       } else if (no_graph) {
         e = hipSuccess;
-        for (int i = 0; i < k && e == hipSuccess; ++i) e = pl->launch_tstep((start + i) & 1, fp64, s);
+        for (int i = 0; i < k && e == hipSuccess; ++i) e = pl->launch_tstep((start + i) & 1, fp64, s, nullptr, per_edge);
       } else {
         e = hipGraphLaunch(g->exec[0], s);
       }
@@ -510,8 +553,8 @@ static int run_plan(Plan* pl, const gmot_opts* o, gmot_result* outs, const std::
       const std::vector<hipEvent_t>& E = g->ev[replay & 1];
       for (int i = 0; i < k; ++i) {
         float a = 0.f, b = 0.f;
-        hipError_t e = hipEventElapsedTime(&a, E[2 * i], E[2 * i + 1]);
-        if (e == hipSuccess) e = hipEventElapsedTime(&b, E[2 * i + 1], E[2 * i + 2]);
+        hipError_t e = hipEventElapsedTime(&a, E[3 * i], E[3 * i + 1]);  // message kernel
+        if (e == hipSuccess) e = hipEventElapsedTime(&b, E[3 * i], E[3 * i + 2]);  // whole half-sweep
         if (e != hipSuccess) return e;
         times.push_back({replay * k + i, a, b});
       }
@@ -552,9 +595,8 @@ static int run_plan(Plan* pl, const gmot_opts* o, gmot_result* outs, const std::
         if (tt.step > last_any) continue;
         const int c = (int)((start + tt.step) & 1);
         pl->acc.msg_ms += tt.msg_ms;
-        pl->acc.node_ms += tt.node_ms;
+        pl->acc.sweep_ms += tt.sweep_ms;
         pl->acc.msg_launches += 1;
-        pl->acc.node_launches += 1;
         for (size_t i = 0; i < n; ++i)
           if (tt.step <= last[i]) pl->acc.msg_pairs += pl->inst_pairs[c][i];
       }
@@ -760,6 +802,7 @@ static int upload(const gmot_tree_desc* d, gmot_problem* p) {
   const size_t o_mf = take(sizeof(double) * D);
   const size_t o_ab = take(sizeof(double) * P);
   const size_t o_qb = take(sizeof(double) * P);
+  const size_t o_c = take(sizeof(double) * 2 * p->N);
   const size_t o_cost = take(sizeof(float) * 2 * p->total_cost);
   if (hipMalloc(&p->arena, off) != hipSuccess) return fail(GMOT_ENOMEM, "problem arena allocation failed");
   char* base = (char*)p->arena;
@@ -771,6 +814,7 @@ static int upload(const gmot_tree_desc* d, gmot_problem* p) {
   p->d_mfull = (double*)(base + o_mf);
   p->d_abar = (double*)(base + o_ab);
   p->d_qbar = (double*)(base + o_qb);
+  p->d_c = (double*)(base + o_c);
   p->d_cost = p->total_cost ? (float*)(base + o_cost) : nullptr;
 
   std::vector<double> lg(P, 0.0), mu(P, 0.0), sup((size_t)P * p->dim, 0.0);
@@ -791,6 +835,7 @@ static int upload(const gmot_tree_desc* d, gmot_problem* p) {
   HIPCHK(hipMemsetAsync(p->d_lam[0], 0, sizeof(double) * D, s));
   HIPCHK(hipMemsetAsync(p->d_lam[1], 0, sizeof(double) * D, s));
   HIPCHK(hipMemsetAsync(p->d_mfull, 0, sizeof(double) * D, s));
+  HIPCHK(hipMemsetAsync(p->d_c, 0, sizeof(double) * 2 * p->N, s));
   if (p->total_cost) {
     HIPCHK(hipMemcpy(p->d_cost, d->cost, sizeof(float) * p->total_cost, hipMemcpyHostToDevice));
     std::vector<float> tr;
@@ -816,37 +861,59 @@ static int ensure_plan(gmot_problem* p) {
   return build_plan(p->ctx, {p}, R, target, &p->plan);
 }
 
-// Device time of one evaluation half-sweep per class with the FP32-core
-// message kernel (the state is read, never written).
+// Mean device time of a fused FP32-core half-sweep under this plan: a few real
+// half-sweeps from the held state, which is snapshotted before and restored
+// after (potential slots, node normalisers and counters).
 static int time_plan(Plan* pl, double* ms) {
   hipStream_t s = pl->ctx->stream;
-  hipEvent_t a, b;
-  HIPCHK(hipEventCreate(&a));
-  HIPCHK(hipEventCreate(&b));
-  auto pass = [&]() -> hipError_t {
-    for (int c = 0; c < 2; ++c) {
-      for (int dk = 0; dk < 4; ++dk)
-        if (!pl->items[c][dk].empty()) {
-          hipError_t e = launch_msg(pl->tables(c, dk), (int)pl->items[c][dk].size(), dk, pl->R, false, 0, s);
-          if (e != hipSuccess) return e;
-        }
-      hipError_t e = launch_node(pl->tables(c, -1), (int)pl->nodes[c].size(), c, 0, s);
-      if (e != hipSuccess) return e;
+  const size_t n = pl->probs.size();
+  std::vector<size_t> off(n + 1, 0);
+  for (size_t i = 0; i < n; ++i) {
+    const gmot_problem* p = pl->probs[i];
+    off[i + 1] = off[i] + 2 * (size_t)p->total_de + 2 * (size_t)p->N;
+  }
+  double* snap = nullptr;
+  if (hipMalloc(&snap, sizeof(double) * std::max<size_t>(1, off[n])) != hipSuccess)
+    return fail(GMOT_ENOMEM, "autotune snapshot");
+  std::vector<int64_t> t_saved(n);
+  hipError_t e = hipSuccess;
+  auto copy_state = [&](bool save) {
+    for (size_t i = 0; i < n && e == hipSuccess; ++i) {
+      gmot_problem* p = pl->probs[i];
+      double* b = snap + off[i];
+      const size_t D = p->total_de;
+      const hipMemcpyKind k = hipMemcpyDeviceToDevice;
+      if (e == hipSuccess) e = hipMemcpyAsync(save ? b : p->d_lam[0], save ? p->d_lam[0] : b, sizeof(double) * D, k, s);
+      if (e == hipSuccess)
+        e = hipMemcpyAsync(save ? b + D : p->d_lam[1], save ? p->d_lam[1] : b + D, sizeof(double) * D, k, s);
+      if (e == hipSuccess)
+        e = hipMemcpyAsync(save ? b + 2 * D : p->d_c, save ? p->d_c : b + 2 * D, sizeof(double) * 2 * p->N, k, s);
+      if (save) t_saved[i] = p->t;
+      else p->t = t_saved[i];
     }
-    return hipSuccess;
   };
-  hipError_t e = pass();
-  const int reps = 3;
-  if (e == hipSuccess) e = hipEventRecord(a, s);
-  for (int r = 0; r < reps && e == hipSuccess; ++r) e = pass();
-  if (e == hipSuccess) e = hipEventRecord(b, s);
-  if (e == hipSuccess) e = hipEventSynchronize(b);
-  float f = 0.f;
-  if (e == hipSuccess) e = hipEventElapsedTime(&f, a, b);
-  (void)hipEventDestroy(a);
-  (void)hipEventDestroy(b);
+  copy_state(true);
+  const gmot_stats acc = pl->acc;
+  pl->acc = gmot_stats{};
+  int rc = GMOT_OK;
+  if (e == hipSuccess) {
+    gmot_opts o{};
+    o.tol = 0.0;
+    o.max_steps = 6;
+    o.check_every = 2;
+    o.precision = GMOT_PREC_FP32CORE;
+    o.timing = 1;
+    o.skip_verify = 1;
+    std::vector<gmot_result> r(n);
+    rc = run_plan(pl, &o, r.data());
+  }
+  *ms = pl->acc.msg_launches ? pl->acc.msg_ms / (double)pl->acc.msg_launches : INFINITY;
+  pl->acc = acc;
+  copy_state(false);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  (void)hipFree(snap);
+  if (rc) return rc;
   if (e != hipSuccess) return fail(GMOT_EDEVICE, std::string("autotune timing: ") + hipGetErrorString(e));
-  *ms = f / reps;
   return GMOT_OK;
 }
 
@@ -898,11 +965,14 @@ static int validate_opts(const gmot_opts* o) {
   if (o->check_every < 0) return fail(GMOT_EINVAL, "check_every must be >= 0");
   if (o->precision != GMOT_PREC_FP32CORE && o->precision != GMOT_PREC_FP64)
     return fail(GMOT_EINVAL, "unknown precision");
+  if (o->schedule != GMOT_SCHED_LAYER && o->schedule != GMOT_SCHED_PER_EDGE)
+    return fail(GMOT_EINVAL, "unknown schedule");
   return GMOT_OK;
 }
 
 static int restart_problem(gmot_problem* p) {
   if (p->total_de > 0) HIPCHK(hipMemsetAsync(p->d_lam[0], 0, sizeof(double) * p->total_de, p->ctx->stream));
+  HIPCHK(hipMemsetAsync(p->d_c, 0, sizeof(double) * 2 * p->N, p->ctx->stream));
   p->t = 1;
   return GMOT_OK;
 }
@@ -919,7 +989,7 @@ static int eval_messages(gmot_problem* p, int only_class) {
     for (int dk = 0; dk < 4; ++dk)
       if (!pl->items[c][dk].empty())
         HIPCHK(launch_msg(pl->tables(c, dk), (int)pl->items[c][dk].size(), dk, pl->R, true, src_slot, s));
-    HIPCHK(launch_node(pl->tables(c, -1), (int)pl->nodes[c].size(), c, p->slot_of_class(c), s));
+    HIPCHK(launch_node_eval(pl->tables(c, -1), (int)pl->nodes[c].size(), p->slot_of_class(c), s));
   }
   return GMOT_OK;
 }
@@ -929,8 +999,11 @@ static EdgeDesc edge_desc(const gmot_problem* p, int e) {
   EdgeDesc ed{};
   ed.supp_a = p->d_support + p->node_off[a] * p->dim;
   ed.supp_b = p->d_support + p->node_off[b] * p->dim;
-  ed.lam_a = p->d_lam[p->slot_of_class(p->colour[a])] + p->de_off[2 * e];
-  ed.lam_b = p->d_lam[p->slot_of_class(p->colour[b])] + p->de_off[2 * e + 1];
+  const int sa = p->slot_of_class(p->colour[a]), sb = p->slot_of_class(p->colour[b]);
+  ed.lam_a = p->d_lam[sa] + p->de_off[2 * e];
+  ed.lam_b = p->d_lam[sb] + p->de_off[2 * e + 1];
+  ed.c_a = p->fixed[a] ? nullptr : p->d_c + 2 * a + sa;
+  ed.c_b = p->fixed[b] ? nullptr : p->d_c + 2 * b + sb;
   ed.lg_a = p->d_lg + p->node_off[a];
   ed.lg_b = p->d_lg + p->node_off[b];
   ed.cost = p->cost_kind == GMOT_COST_EXPLICIT ? p->d_cost + p->cost_off[e] : nullptr;
@@ -974,6 +1047,8 @@ int gmot_ctx_create(gmot_ctx** out, int device, void* hip_stream) {
 
 void gmot_ctx_destroy(gmot_ctx* ctx) {
   if (!ctx) return;
+  (void)hipStreamSynchronize(ctx->stream);
+  if (ctx->scratch) (void)hipFree(ctx->scratch);
   if (ctx->own_stream) (void)hipStreamDestroy(ctx->stream);
   delete ctx;
 }
@@ -1106,29 +1181,43 @@ int gmot_get_potentials(gmot_problem* p, double* out) {
   if (!p || (!out && p->total_de > 0)) return fail(GMOT_EINVAL, "null problem or output");
   if (p->total_de == 0) return GMOT_OK;
   HIPCHK(hipSetDevice(p->ctx->device));
-  std::vector<double> s0(p->total_de), s1(p->total_de);
+  // Lam_(j,k) = L_(j,k) - c_j with both read from node j's committed slot
+  std::vector<double> s0(p->total_de), s1(p->total_de), cv(2 * p->N);
   HIPCHK(hipStreamSynchronize(p->ctx->stream));
   HIPCHK(hipMemcpy(s0.data(), p->d_lam[0], sizeof(double) * p->total_de, hipMemcpyDeviceToHost));
   HIPCHK(hipMemcpy(s1.data(), p->d_lam[1], sizeof(double) * p->total_de, hipMemcpyDeviceToHost));
+  HIPCHK(hipMemcpy(cv.data(), p->d_c, sizeof(double) * 2 * p->N, hipMemcpyDeviceToHost));
   for (int de = 0; de < 2 * p->E; ++de) {
     const int e = de >> 1;
     const int j = (de & 1) ? p->edges[2 * e + 1] : p->edges[2 * e];
-    const std::vector<double>& src = p->slot_of_class(p->colour[j]) ? s1 : s0;
-    std::copy(src.begin() + p->de_off[de], src.begin() + p->de_off[de + 1], out + p->de_off[de]);
+    const int slot = p->slot_of_class(p->colour[j]);
+    const std::vector<double>& src = slot ? s1 : s0;
+    const double c = p->fixed[j] ? 0.0 : cv[2 * j + slot];
+    for (int64_t i = p->de_off[de]; i < p->de_off[de + 1]; ++i) out[i] = src[i] - c;
   }
   return GMOT_OK;
 }
 
 int gmot_get_potentials_dev(gmot_problem* p, double* out_dev) {
   if (!p || (!out_dev && p->total_de > 0)) return fail(GMOT_EINVAL, "null problem or output");
+  if (p->total_de == 0) return GMOT_OK;
   HIPCHK(hipSetDevice(p->ctx->device));
+  std::vector<SegCopy> segs(2 * p->E);
   for (int de = 0; de < 2 * p->E; ++de) {
     const int e = de >> 1;
     const int j = (de & 1) ? p->edges[2 * e + 1] : p->edges[2 * e];
-    const double* src = p->d_lam[p->slot_of_class(p->colour[j])] + p->de_off[de];
-    HIPCHK(hipMemcpyAsync(out_dev + p->de_off[de], src, sizeof(double) * (p->de_off[de + 1] - p->de_off[de]),
-                          hipMemcpyDeviceToDevice, p->ctx->stream));
+    const int slot = p->slot_of_class(p->colour[j]);
+    segs[de] = {p->d_lam[slot] + p->de_off[de], out_dev + p->de_off[de],
+                p->fixed[j] ? nullptr : p->d_c + 2 * j + slot, p->de_off[de + 1] - p->de_off[de]};
   }
+  void* buf = nullptr;
+  if (hipMalloc(&buf, sizeof(SegCopy) * segs.size()) != hipSuccess) return fail(GMOT_ENOMEM, "copy table");
+  hipError_t e = hipMemcpyAsync(buf, segs.data(), sizeof(SegCopy) * segs.size(), hipMemcpyHostToDevice,
+                                p->ctx->stream);
+  if (e == hipSuccess) e = launch_seg_copy((const SegCopy*)buf, (int)segs.size(), p->ctx->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(p->ctx->stream);
+  (void)hipFree(buf);
+  if (e != hipSuccess) return fail(GMOT_EDEVICE, std::string("potential read-back: ") + hipGetErrorString(e));
   return GMOT_OK;
 }
 
@@ -1139,6 +1228,8 @@ int gmot_set_potentials(gmot_problem* p, const double* in) {
   HIPCHK(hipSetDevice(p->ctx->device));
   HIPCHK(hipStreamSynchronize(p->ctx->stream));
   if (p->total_de) HIPCHK(hipMemcpy(p->d_lam[0], in, sizeof(double) * p->total_de, hipMemcpyHostToDevice));
+  HIPCHK(hipMemset(p->d_c, 0, sizeof(double) * 2 * p->N));
+  HIPCHK(hipDeviceSynchronize());
   p->t = 1;
   return GMOT_OK;
 }
@@ -1149,6 +1240,7 @@ int gmot_set_potentials_dev(gmot_problem* p, const double* in_dev) {
   if (p->total_de)
     HIPCHK(hipMemcpyAsync(p->d_lam[0], in_dev, sizeof(double) * p->total_de, hipMemcpyDeviceToDevice,
                           p->ctx->stream));
+  HIPCHK(hipMemsetAsync(p->d_c, 0, sizeof(double) * 2 * p->N, p->ctx->stream));
   p->t = 1;
   return GMOT_OK;
 }
@@ -1244,6 +1336,112 @@ int gmot_batch_autotune(gmot_batch* b, int32_t* rows_per_lane, int32_t* target_b
   if (!b) return fail(GMOT_EINVAL, "null batch");
   HIPCHK(hipSetDevice(b->ctx->device));
   return autotune(b->ctx, b->probs, &b->plan, rows_per_lane, target_blocks, best_ms);
+}
+
+// ---- star warm-start data movement ------------------------------------------
+static int star_descs(gmot_problem* const* probs, int32_t count, int* L_out, int* n_out, StarDesc** d_out,
+                      int** d_rejected) {
+  if (!probs || count < 1) return fail(GMOT_EINVAL, "no problems");
+  gmot_ctx* ctx = probs[0]->ctx;
+  int L = -1, n = -1;
+  std::vector<StarDesc> h(count);
+  for (int i = 0; i < count; ++i) {
+    const gmot_problem* p = probs[i];
+    if (!p || p->ctx != ctx) return fail(GMOT_ESTATE, "problems must share one context");
+    bool ok = p->E >= 1 && p->N == p->E + 1 && !p->fixed[0] && p->first_color == 0 &&
+              p->cost_kind == GMOT_COST_SQEUCLID;
+    for (int e = 0; ok && e < p->E; ++e) ok = p->edges[2 * e] == 0 && p->edges[2 * e + 1] == e + 1;
+    for (int j = 1; ok && j < p->N; ++j) ok = p->fixed[j] && p->sizes[j] == p->sizes[0];
+    if (!ok) return fail(GMOT_EINVAL, "warm start needs star instances (free center 0, edges (0,l), equal sizes)");
+    if (L < 0) {
+      L = p->E;
+      n = p->sizes[0];
+    }
+    if (p->E != L || p->sizes[0] != n) return fail(GMOT_EINVAL, "star instances of one call must share L and n");
+    h[i].lg_leaf = p->d_lg + p->node_off[1];
+    h[i].lam0 = p->d_lam[0] + p->de_off[0];
+    h[i].lam_cur = p->d_lam[p->slot_of_class(p->colour[1])] + p->de_off[0];
+  }
+  const size_t need = align_up(sizeof(StarDesc) * count, 256) + 256;
+  if (ctx->scratch_size < need) {
+    HIPCHK(hipStreamSynchronize(ctx->stream));
+    if (ctx->scratch) (void)hipFree(ctx->scratch);
+    ctx->scratch = nullptr;
+    ctx->scratch_size = 0;
+    if (hipMalloc(&ctx->scratch, need) != hipSuccess) return fail(GMOT_ENOMEM, "warm-start tables");
+    ctx->scratch_size = need;
+  }
+  StarDesc* d = (StarDesc*)ctx->scratch;
+  // earlier launches may still read the scratch tables: wait, then copy synchronously
+  HIPCHK(hipStreamSynchronize(ctx->stream));
+  HIPCHK(hipMemcpy(d, h.data(), sizeof(StarDesc) * count, hipMemcpyHostToDevice));
+  *L_out = L;
+  *n_out = n;
+  *d_out = d;
+  if (d_rejected) *d_rejected = (int*)((char*)ctx->scratch + align_up(sizeof(StarDesc) * count, 256));
+  return GMOT_OK;
+}
+
+int gmot_star_features_dev(gmot_problem* const* probs, int32_t count, float shift, float scale, float* x_dev) {
+  if (!x_dev) return fail(GMOT_EINVAL, "null output");
+  int L, n;
+  StarDesc* d;
+  int rc = star_descs(probs, count, &L, &n, &d, nullptr);
+  if (rc) return rc;
+  HIPCHK(launch_star_features(d, count, L, n, shift, scale, x_dev, probs[0]->ctx->stream));
+  return GMOT_OK;
+}
+
+int gmot_star_targets_dev(gmot_problem* const* probs, int32_t count, float out_scale, float* t_dev) {
+  if (!t_dev || !(out_scale > 0.f)) return fail(GMOT_EINVAL, "null output or non-positive scale");
+  int L, n;
+  StarDesc* d;
+  int rc = star_descs(probs, count, &L, &n, &d, nullptr);
+  if (rc) return rc;
+  HIPCHK(launch_star_targets(d, count, L, n, out_scale, t_dev, probs[0]->ctx->stream));
+  return GMOT_OK;
+}
+
+int gmot_star_apply_dev(gmot_problem* const* probs, int32_t count, const float* y_dev, float out_scale,
+                        int32_t* rejected) {
+  if (!y_dev) return fail(GMOT_EINVAL, "null prediction");
+  int L, n;
+  StarDesc* d;
+  int* d_rej = nullptr;
+  int rc = star_descs(probs, count, &L, &n, &d, &d_rej);
+  if (rc) return rc;
+  hipStream_t s = probs[0]->ctx->stream;
+  HIPCHK(hipMemsetAsync(d_rej, 0, sizeof(int), s));
+  for (int i = 0; i < count; ++i) HIPCHK(hipMemsetAsync(probs[i]->d_c, 0, sizeof(double) * 2 * probs[i]->N, s));
+  HIPCHK(launch_star_apply(d, count, L, n, y_dev, out_scale, d_rej, s));
+  int rej = 0;
+  HIPCHK(hipMemcpyAsync(&rej, d_rej, sizeof(int), hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  for (int i = 0; i < count; ++i) probs[i]->t = 1;
+  if (rejected) *rejected = rej;
+  return GMOT_OK;
+}
+
+int gmot_mlp_warm_start(gmot_mlp* m, gmot_problem* const* probs, int32_t count, float shift, float scale,
+                        float out_scale, int32_t* rejected) {
+  if (!m || !probs || count < 1) return fail(GMOT_EINVAL, "null network or problems");
+  int n_in = 0, n_out = 0;
+  gmot_mlp_widths(m, &n_in, &n_out);
+  const int B = (count + 7) / 8 * 8;
+  float *x = nullptr, *y = nullptr;
+  int rc = gmot_mlp_workspace(m, B, &x, &y);
+  if (rc) return fail(rc, gmot_mlp_last_error());
+  int L, n;
+  StarDesc* d;
+  rc = star_descs(probs, count, &L, &n, &d, nullptr);
+  if (rc) return rc;
+  if (L * n != n_in || L * n != n_out) return fail(GMOT_EINVAL, "network widths do not match L * n");
+  hipStream_t s = probs[0]->ctx->stream;
+  if (B > count) HIPCHK(hipMemsetAsync(x + (size_t)count * n_in, 0, sizeof(float) * (size_t)(B - count) * n_in, s));
+  HIPCHK(launch_star_features(d, count, L, n, shift, scale, x, s));
+  rc = gmot_mlp_forward_dev(m, x, B, y);
+  if (rc) return fail(rc, gmot_mlp_last_error());
+  return gmot_star_apply_dev(probs, count, y, out_scale, rejected);
 }
 
 static int copy_stats(Plan* pl, gmot_stats* out, int32_t reset) {

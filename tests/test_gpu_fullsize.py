@@ -1,0 +1,57 @@
+"""Full-size workloads on the GPU, checked by the FP64 oracle on the returned
+state (needs an MI355X).
+
+At these sizes the oracle cannot run the iteration itself, so each check
+re-measures what holds at any size: the stopping sum of the GPU's returned
+potentials over every node (computed by the oracle in FP64 from those
+potentials), the GPU's own FP64 evaluation against the oracle's evaluation
+of the same potentials, unit mass of every plan (Lemma tree_mass) and the
+duality-gap bound |P - D| <= C_inf E."""
+import numpy as np
+import pytest
+
+from oracle import TreeOracle
+from workloads import make_config, make_batched_stars
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    from paper_2406_10849_amd import Context
+    return Context(0)
+
+
+def check_state(g, p, tol):
+    o = TreeOracle(p)
+    lam = o.set_potentials(g.potentials())
+    e_sum, _ = o.full_error(lam)
+    assert e_sum <= tol + 1e-10, e_sum
+    eg = g.evaluate()
+    assert abs(eg["err_sum"] - e_sum) <= 1e-9
+    assert abs(eg["mass_min"] - 1.0) <= 1e-9 and abs(eg["mass_max"] - 1.0) <= 1e-9
+    assert abs(eg["gap"]) <= o.c_inf() * eg["err_sum"] + 1e-12
+    return e_sum, eg
+
+
+def test_random_tree_256_nodes_2d_converges(ctx):
+    """256-node Pruefer tree, n in [256, 4096] on 2D grids, eps = 5e-3."""
+    from paper_2406_10849_amd import Problem
+    p = make_config(3)
+    g = Problem(ctx, p)
+    r = g.solve(tol=1e-6, max_steps=200000)
+    assert r["status"] == "converged"
+    check_state(g, p, 1e-6)
+
+
+def test_batched_512_stars_sampled(ctx):
+    """512 uneven stars in one batch; 8 sampled instances re-measured."""
+    from paper_2406_10849_amd import Batch, Problem
+    probs = make_batched_stars(count=512)
+    gps = [Problem(ctx, p) for p in probs]
+    b = Batch(ctx, gps)
+    rs = b.solve(tol=1e-6, max_steps=200000)
+    assert all(r["status"] == "converged" for r in rs)
+    rng = np.random.default_rng(0)
+    for i in rng.choice(len(probs), size=8, replace=False):
+        check_state(gps[i], probs[i], 1e-6)
