@@ -121,7 +121,9 @@ typedef struct {
 /* Kernel timing accumulated by solves with opts.timing = 1 (since the last
  * reset).  Only half-sweeps that did work for at least one instance count. */
 typedef struct {
-  double  msg_ms;          /* summed duration of the message-kernel stages (ms)         */
+  double  msg_ms;          /* summed duration of the message-kernel stages (ms), each the
+                              mean of 4 back-to-back repeats of the stage (it only reads
+                              the state), so event overhead is not counted              */
   double  sweep_ms;        /* summed duration of whole half-sweeps: message, tile and
                               finalise kernels (ms)                                    */
   int64_t msg_launches;    /* half-sweeps timed                                         */
@@ -192,6 +194,34 @@ int  gmot_get_coupling(gmot_problem* p, int32_t edge, double* out);
 /* q_bar_j: arithmetic mean over neighbours k of B_(j,k) 1 (n_j values). */
 int  gmot_get_node_marginal(gmot_problem* p, int32_t node, double* out);
 
+/* ---- rounding (Algorithm round) -------------------------------------------------- */
+/* After a half-sweep the class S that was not updated last (the one the next
+ * half-sweep would update) misses its marginals.  gmot_round rounds every plan
+ * B_(j,k), j its end in S, with the rounding of Altschuler, Weed and Rigollet
+ * (NeurIPS 2017, Algorithm 2) onto the plans with row marginal r_j (mu_j for a
+ * constrained node, the arithmetic mean q_bar_j of the node's plan marginals
+ * for a free node) and column marginal B_(j,k)^T 1, so that every node's
+ * marginals agree on all its edges and equal mu_j where constrained.  The
+ * state is not changed; all arithmetic is FP64 on the device.  Lemma round
+ * bounds |transport - unrounded transport| by 2 c_inf err_side.
+ * Requires a state produced by at least one half-sweep (t >= 2; otherwise
+ * GMOT_ESTATE): unit plan mass (Lemma tree_mass) is what makes the rounded
+ * marginals exact. */
+typedef struct {
+  double  transport;   /* sum_e <C_e, G_e> over the rounded plans G_e                    */
+  double  err_side;    /* sum over j in S, k in N(j) of |r_j - B_(j,k) 1|_1              */
+  double  c_inf;       /* max |C| over all pairs of all edges                            */
+  int32_t side;        /* S: 0 = the class updated on odd half-sweeps, 1 = the other      */
+  int32_t reserved;
+} gmot_round_result;
+
+/* edge_transport: optional host array of n_edges, <C_e, G_e> per edge.
+ * Keeps device buffers (4 doubles per potential entry) until the state changes. */
+int  gmot_round(gmot_problem* p, gmot_round_result* out, double* edge_transport);
+/* G_e of the last gmot_round of the held state, n_a x n_b row-major, FP64 (host
+ * array).  GMOT_ESTATE if the state changed since (or no rounding was done). */
+int  gmot_get_rounded_coupling(gmot_problem* p, int32_t edge, double* out);
+
 /* ---- batches ------------------------------------------------------------------ */
 /* Group `count` problems of one context so that every half-sweep of all of them
  * runs in the same launches; instances converge independently (a converged
@@ -255,8 +285,10 @@ int  gmot_mlp_warm_start(gmot_mlp* m, gmot_problem* const* probs, int32_t count,
 
 /* ---- tile autotuning ------------------------------------------------------------ */
 /* Time candidate message-kernel tilings (rows per lane 1 or 2, and the number of
- * blocks a half-sweep is split into through column splits) with evaluation
- * half-sweeps that leave the held state untouched, and keep the fastest plan.
+ * blocks a half-sweep is split into through column splits) by the device time
+ * of a few real FP32-core half-sweeps (message, tile and finalise kernels) run
+ * from a snapshot of the held state, which is restored afterwards, and keep
+ * the fastest plan; best_ms is that half-sweep time.
  * The choice is cached in the context under the instances' shapes, so later
  * problems or batches of the same shapes start with it.  Outputs may be NULL. */
 int  gmot_problem_autotune(gmot_problem* p, int32_t* rows_per_lane, int32_t* target_blocks, double* best_ms);

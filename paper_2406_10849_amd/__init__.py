@@ -207,6 +207,21 @@ class Problem:
                "gmot_get_node_marginal")
         return out
 
+    def round(self) -> dict:
+        """gmot_round: rounded transport, per-edge transport, err_side, c_inf, side."""
+        r = _lib.RoundResult()
+        per_edge = np.zeros(max(len(self.edges), 1), dtype=np.float64)
+        _check(self._lib.gmot_round(self._h, C.byref(r), per_edge.ctypes.data_as(_lib.DP)), "gmot_round")
+        return {"transport": r.transport, "edge_transport": per_edge[:len(self.edges)].copy(),
+                "err_side": r.err_side, "c_inf": r.c_inf, "side": r.side}
+
+    def rounded_coupling(self, edge: int) -> np.ndarray:
+        a, b = self.edges[edge]
+        out = np.empty((int(self.sizes[a]), int(self.sizes[b])), dtype=np.float64)
+        _check(self._lib.gmot_get_rounded_coupling(self._h, int(edge), out.ctypes.data_as(_lib.DP)),
+               "gmot_get_rounded_coupling")
+        return out
+
 
 class Batch:
     """Many problems advanced by the same launches."""

@@ -85,6 +85,13 @@ class Eval(C.Structure):
     ]
 
 
+class RoundResult(C.Structure):
+    _fields_ = [
+        ("transport", C.c_double), ("err_side", C.c_double), ("c_inf", C.c_double),
+        ("side", C.c_int32), ("reserved", C.c_int32),
+    ]
+
+
 VP = C.c_void_p
 I32P = C.POINTER(C.c_int32)
 DP = C.POINTER(C.c_double)
@@ -104,6 +111,8 @@ SIGNATURES = {
     "gmot_set_potentials_dev": (C.c_int, [VP, VP]),
     "gmot_get_coupling": (C.c_int, [VP, C.c_int32, DP]),
     "gmot_get_node_marginal": (C.c_int, [VP, C.c_int32, DP]),
+    "gmot_round": (C.c_int, [VP, C.POINTER(RoundResult), DP]),
+    "gmot_get_rounded_coupling": (C.c_int, [VP, C.c_int32, DP]),
     "gmot_batch_create": (C.c_int, [VP, C.POINTER(VP), C.c_int32, C.POINTER(VP)]),
     "gmot_batch_destroy": (None, [VP]),
     "gmot_batch_solve": (C.c_int, [VP, C.POINTER(Opts), C.POINTER(Result)]),

@@ -15,7 +15,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libgmot.so")
 
-SOURCES = ["gmot_kernels.hip", "gmot_mlp.hip", "gmot_runtime.cpp"]
+SOURCES = ["gmot_kernels.hip", "gmot_round.hip", "gmot_mlp.hip", "gmot_runtime.cpp"]
 
 # Packed FP32 instructions are switched off for every HIP object; the
 # host pass reports that it does not know the feature, which is harmless.

@@ -65,7 +65,7 @@ struct MsgDesc {
 // One block of the message kernel: rows [row0, row0 + rows per block) of a
 // message, columns [col0, col0 + ncols), writing column split `split`.
 struct K1Item {
-  int32_t msg, row0, col0, ncols, split, pad0, pad1, pad2;
+  int32_t msg, row0, col0, ncols, split, inst, pad0, pad1;
 };
 
 constexpr int kTileRows = 256;  // rows per block of the tile kernel
@@ -85,9 +85,11 @@ struct NodeItem {
   double* tpart;             // tile records
 };
 
-// One block of the tile kernel: rows [row0, row0 + kTileRows) of node item `node`.
+// One block of the tile kernel: rows [row0, row0 + kTileRows) of node item
+// `node` of instance `inst` (carried here so the instance state and the node
+// item load in parallel).
 struct TileItem {
-  int32_t node, row0;
+  int32_t node, row0, inst, pad;
 };
 
 // Per-instance loop state, written only by the last node block of a half-sweep.
@@ -128,6 +130,29 @@ struct EdgeDesc {
 };
 struct PairItem { int32_t edge, row0, col0, ncols; };
 
+// Rounding (Algorithm round): one directed edge (j, k) seen with rows on j.
+struct RoundDesc {
+  const double* supp_r;  const double* supp_c;    // supports of j (rows) and k (columns)
+  const double* lam_r;   const double* lam_c;     // committed L_(j,k), L_(k,j)
+  const double* c_r;     const double* c_c;       // committed c_j, c_k (NULL: 0)
+  const double* lg_r;    const double* lg_c;
+  const float* cost;                              // explicit: cost[y * n_r + x] = C(x, y); else NULL
+  double* rs;            // [n_r] row sums B1 (pass 0)
+  double* tg;            // [n_r] row target r (rows in S)
+  double* sc;            // [n_r] row scaling: X (rows in S) or Y (rows on the other side)
+  double* er;            // [n_r] residual: e_r (rows in S) or e_c
+  const double* sc_col;  // [n_c] column scaling of the pass (NULL: 1)
+  const double* er_col;  // [n_c] e_c of the columns (pass 2)
+  int32_t n_r, n_c, dim, cost_kind;
+  double eps;
+};
+struct RoundItem { int32_t desc, row0; };
+// A node of S; its directed edges are descs d0 .. d0 + deg.
+struct RoundNode {
+  int32_t n, deg, d0, pad;
+  const double* mu;      // mu_j for constrained nodes, else NULL
+};
+
 // ---- launch wrappers (defined in gmot_kernels.hip) ----
 hipError_t launch_msg(const Tables& tb, int n_items, int dim, int rows_per_lane, bool fp64, int eval_src_slot,
                       hipStream_t s);
@@ -140,6 +165,13 @@ hipError_t launch_seg_copy(const SegCopy* segs, int n_segs, hipStream_t s);
 hipError_t launch_stamp(InstState* inst, int count, hipStream_t s);
 hipError_t launch_pairs(const EdgeDesc* edges, const PairItem* items, int n_items, double4* out, hipStream_t s);
 hipError_t launch_coupling(const EdgeDesc* edge, double* out, size_t total, hipStream_t s);
+
+// ---- rounding (defined in gmot_round.hip) ----
+hipError_t launch_round_rows(int pass, const RoundDesc* ds, const RoundItem* items, int n_items, double4* part,
+                             hipStream_t s);
+hipError_t launch_round_node(const RoundNode* nodes, int n_nodes, const RoundDesc* ds, double* err, hipStream_t s);
+hipError_t launch_round_plan(const RoundDesc* d, const RoundDesc* o, double inv_s, int s_is_a, double* out,
+                             size_t total, hipStream_t s);
 
 // ---- warm-start data movement (defined in gmot_mlp.hip) ----
 // One star instance: center node 0 (free), edges (0, l) for leaves l = 1..L in

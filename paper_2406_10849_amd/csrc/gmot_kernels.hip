@@ -27,6 +27,9 @@ namespace gmot {
 
 namespace {
 
+constexpr int kRegDeg = 8;     // incident edges whose messages the tile kernel keeps in registers
+constexpr int kRecChunk = 64;  // tile records reduced per block barrier
+
 __device__ inline double wave_sum(double v) {
 #pragma unroll
   for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
@@ -129,7 +132,7 @@ __global__ __launch_bounds__(kBlock) void k_msg(Tables tb, int eval_src_slot) {
   const MsgDesc* __restrict__ md = tb.msgs + it.msg;
   int src_slot = eval_src_slot;
   if (ITER) {
-    const InstState* st = tb.inst + md->inst;
+    const InstState* st = tb.inst + it.inst;
     const long long t = st->t;
     if (st->done || ((t & 1) == 1) != (tb.colour == 0)) return;
     src_slot = (int)((t >> 1) & 1);
@@ -276,63 +279,114 @@ __global__ __launch_bounds__(kBlock) void k_msg(Tables tb, int eval_src_slot) {
 // Record: per incident edge the tile's sum of terms, then the tile's LSE of abar.
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(kBlock) void k_tile(Tables tb) {
-  __shared__ double sh[4];
+  __shared__ double sh_rec[4][kRecChunk + 2];
   const TileItem ti = tb.tiles[blockIdx.x];
-  const NodeItem& nd = tb.nodes[ti.node];
-  const InstState* st = tb.inst + nd.inst;
+  const InstState* st = tb.inst + ti.inst;
+  const NodeItem nd = tb.nodes[ti.node];
   const long long t = st->t;
-  if (st->done || ((t & 1) == 1) != (tb.colour == 0)) return;
+  const int done = st->done;
+  if (done || ((t & 1) == 1) != (tb.colour == 0)) return;
   const int cur = (int)(((t - 1) >> 1) & 1), nxt = cur ^ 1;
   const MsgDesc* __restrict__ mds = tb.msgs + nd.msg0;
   const int n = nd.n, deg = nd.deg;
+  const bool fixed = nd.fixed != 0;
   const int dim = mds[0].dim;
   const bool sq = mds[0].cost_kind == 0;
   const double* __restrict__ xs = mds[0].supp_dst;
   const double c_old = nd.c ? nd.c[cur] : 0.0;
-  double* rec = nd.tpart + (size_t)(ti.row0 / kTileRows) * (deg + 2);
+  double* __restrict__ rec = nd.tpart + (size_t)(ti.row0 / kTileRows) * (deg + 2);
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int x = ti.row0 + threadIdx.x;
   const bool vx = x < n;
+  const double mux = (vx && fixed) ? nd.mu[x] : 0.0;
+  const double x2 = (vx && sq) ? sq_norm(xs, dim, x) : 0.0;
 
-  double a = -INFINITY, qb = 0.0;
-  if (vx) {
-    const double x2 = sq ? sq_norm(xs, dim, x) : 0.0;
-    double asum = 0.0, qsum = 0.0;
-    for (int k = 0; k < deg; ++k) {
+  // merged messages and held potentials: registers for the first kRegDeg
+  // edges, the mfull scratch row beyond (star centres of high degree)
+  double mreg[kRegDeg], lreg[kRegDeg];
+  double asum = 0.0, qsum = 0.0;
+#pragma unroll
+  for (int k = 0; k < kRegDeg; ++k) {
+    mreg[k] = 0.0;
+    lreg[k] = 0.0;
+    if (k < deg && vx) {
       const MsgDesc& md = mds[k];
       const double m = merge_row(md, n, x, x2);
-      md.mfull[x] = m;
+      const double l = md.lam_dst[cur][x];
+      mreg[k] = m;
+      lreg[k] = l;
       asum += m;
-      if (!nd.fixed) qsum += exp(md.lam_dst[cur][x] - c_old + m);
+      if (!fixed) qsum += exp(l - c_old + m);
     }
-    a = asum / deg;
-    qb = qsum / deg;
   }
-  for (int k = 0; k < deg; ++k) {
+  for (int k = kRegDeg; k < deg; ++k) {
+    if (!vx) continue;
     const MsgDesc& md = mds[k];
+    const double m = merge_row(md, n, x, x2);
+    md.mfull[x] = m;
+    asum += m;
+    if (!fixed) qsum += exp(md.lam_dst[cur][x] - c_old + m);
+  }
+  const double a = vx ? asum / deg : -INFINITY;
+  const double qb = qsum / deg;
+
+  // stopping-sum term of edge k at row x, and the update of L_(j,k)(x)
+  auto term = [&](int k, double m, double l) -> double {
     double part = 0.0;
     if (vx) {
-      const double m = md.mfull[x];
-      const double l = md.lam_dst[cur][x];
-      if (nd.fixed) {
-        const double mu = nd.mu[x];
-        if (mu > 0.0) part = mu * fabs(expm1(l + m));
-        md.lam_dst[nxt][x] = -m;
+      double* __restrict__ Ln = mds[k].lam_dst[nxt];
+      if (fixed) {
+        if (mux > 0.0) part = mux * fabs(expm1(l + m));
+        Ln[x] = -m;
       } else {
         part = fabs(exp(l - c_old + m) - qb);
-        md.lam_dst[nxt][x] = a - m;
+        Ln[x] = a - m;
       }
     }
-    const double tot = block_sum(part, sh);
-    if (threadIdx.x == 0) rec[k] = tot;
-  }
-  if (!nd.fixed) {
-    const double M = block_max(a, sh);
-    const double s = (vx && a > -INFINITY) ? exp(a - M) : 0.0;
-    const double S = block_sum(s, sh);
-    if (threadIdx.x == 0) {
+    return wave_sum(part);
+  };
+
+  // records in chunks of kRecChunk edges, one barrier per chunk
+  for (int k0 = 0; k0 < deg; k0 += kRecChunk) {
+    const int kn = min(kRecChunk, deg - k0);
+    if (k0 == 0) {
+#pragma unroll
+      for (int k = 0; k < kRegDeg; ++k) {
+        if (k < kn) {
+          const double p = term(k, mreg[k], lreg[k]);
+          if (lane == 0) sh_rec[wave][k] = p;
+        }
+      }
+    }
+    for (int k = max(k0, kRegDeg); k < k0 + kn; ++k) {
+      const double m = vx ? mds[k].mfull[x] : 0.0;
+      const double l = vx ? mds[k].lam_dst[cur][x] : 0.0;
+      const double p = term(k, m, l);
+      if (lane == 0) sh_rec[wave][k - k0] = p;
+    }
+    const bool last = k0 + kn == deg;
+    if (last && !fixed) {
+      // per-wave LSE of abar over the wave's rows
+      const double Mw = wave_max(a);
+      const double Sw = wave_sum((a > -INFINITY) ? exp(a - Mw) : 0.0);
+      if (lane == 0) {
+        sh_rec[wave][kn] = Mw;
+        sh_rec[wave][kn + 1] = Sw;
+      }
+    }
+    __syncthreads();
+    const int i = threadIdx.x;
+    if (i < kn) rec[k0 + i] = (sh_rec[0][i] + sh_rec[1][i]) + (sh_rec[2][i] + sh_rec[3][i]);
+    if (last && !fixed && i == kn) {
+      double M = -INFINITY;
+      for (int w = 0; w < 4; ++w) M = fmax(M, sh_rec[w][kn]);
+      double S = 0.0;
+      for (int w = 0; w < 4; ++w)
+        if (sh_rec[w][kn] > -INFINITY) S += sh_rec[w][kn + 1] * exp(sh_rec[w][kn] - M);
       rec[deg] = M;
       rec[deg + 1] = S;
     }
+    if (!last) __syncthreads();
   }
 }
 
@@ -343,7 +397,7 @@ __global__ __launch_bounds__(kBlock) void k_tile(Tables tb) {
 // then the block sums the terms and thread 0 takes the stop decision.
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(kBlock) void k_finalize(Tables tb) {
-  __shared__ double sh[4];
+  __shared__ double sh[4][2];
   InstState* st = tb.inst + blockIdx.x;
   const long long t = st->t;
   if (st->done || ((t & 1) == 1) != (tb.colour == 0)) return;
@@ -351,28 +405,38 @@ __global__ __launch_bounds__(kBlock) void k_finalize(Tables tb) {
   const int i0 = st->node0[tb.colour], cnt = st->nnodes[tb.colour];
   double esum = 0.0, emax = 0.0;
   for (int i = threadIdx.x; i < cnt; i += kBlock) {
-    const NodeItem& nd = tb.nodes[i0 + i];
-    const int deg = nd.deg;
+    const NodeItem nd = tb.nodes[i0 + i];
+    const int deg = nd.deg, stride = deg + 2, tiles = nd.tiles;
+    const double* __restrict__ tp = nd.tpart;
     for (int k = 0; k < deg; ++k) {
       double e = 0.0;
-      for (int tt = 0; tt < nd.tiles; ++tt) e += nd.tpart[(size_t)tt * (deg + 2) + k];
+      for (int tt = 0; tt < tiles; ++tt) e += tp[(size_t)tt * stride + k];
       esum += e;
       emax = fmax(emax, e);
     }
     if (!nd.fixed) {
       double M = -INFINITY;
-      for (int tt = 0; tt < nd.tiles; ++tt) M = fmax(M, nd.tpart[(size_t)tt * (deg + 2) + deg]);
+      for (int tt = 0; tt < tiles; ++tt) M = fmax(M, tp[(size_t)tt * stride + deg]);
       double S = 0.0;
-      for (int tt = 0; tt < nd.tiles; ++tt) {
-        const double mt = nd.tpart[(size_t)tt * (deg + 2) + deg];
-        if (mt > -INFINITY) S += nd.tpart[(size_t)tt * (deg + 2) + deg + 1] * exp(mt - M);
+      for (int tt = 0; tt < tiles; ++tt) {
+        const double mt = tp[(size_t)tt * stride + deg];
+        if (mt > -INFINITY) S += tp[(size_t)tt * stride + deg + 1] * exp(mt - M);
       }
       nd.c[nxt] = M + log(S);
     }
   }
-  const double E = block_sum(esum, sh);
-  const double Em = block_max(emax, sh);
-  if (threadIdx.x == 0) decide(tb, st, t, E, Em);
+  esum = wave_sum(esum);
+  emax = wave_max(emax);
+  if ((threadIdx.x & 63) == 0) {
+    sh[threadIdx.x >> 6][0] = esum;
+    sh[threadIdx.x >> 6][1] = emax;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const double E = (sh[0][0] + sh[1][0]) + (sh[2][0] + sh[3][0]);
+    const double Em = fmax(fmax(sh[0][1], sh[1][1]), fmax(sh[2][1], sh[3][1]));
+    decide(tb, st, t, E, Em);
+  }
 }
 
 // ---------------------------------------------------------------------------

@@ -53,6 +53,7 @@ size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 }  // namespace
 
 struct Plan;
+struct RoundState;
 
 
 struct gmot_problem {
@@ -79,7 +80,9 @@ struct gmot_problem {
   double* d_c = nullptr;  // [2N]: node normaliser c_j, slot s at 2j + s (0 for constrained nodes)
   float* d_cost = nullptr;
   int64_t t = 1;
+  uint64_t version = 0;   // bumped whenever the held state changes
   Plan* plan = nullptr;
+  RoundState* round = nullptr;
 
   const double* c_ptr(int j) const { return fixed[j] ? nullptr : d_c + 2 * j; }
 
@@ -92,10 +95,15 @@ struct gmot_problem {
   int slot_of_class(int c) const { return c == 0 ? (int)((t / 2) & 1) : (int)(((t - 1) / 2) & 1); }
 };
 
+// Timing mode: events per half-sweep, and back-to-back repeats of the message
+// stage between the first two (so their mean excludes the event overhead).
+constexpr int kStepEvents = 4;
+constexpr int kMsgBurst = 4;
+
 // A captured run of k half-sweeps.  The timed variant is not captured: it
 // launches the k half-sweeps directly, recording one of two alternating chains
-// of 3k events (before step i, after its message stage, after its finalise
-// kernel), so one chain can be read back while the next replay runs.
+// of kStepEvents * k events (see Plan::launch_tstep), so one chain can be read
+// back while the next replay runs.
 struct GraphEntry {
   bool fp64 = false, timed = false, per_edge = false;
   int start = 0, k = 0;
@@ -158,10 +166,8 @@ struct Plan {
   // dimension, or with per_edge one launch per message), then the tile and
   // finalise kernels; with `ev`, events ev[0] before, ev[1] after the message
   // stage and ev[2] after the finalise kernel.
-  hipError_t launch_tstep(int c, bool fp64, hipStream_t s, const hipEvent_t* ev = nullptr,
-                          bool per_edge = false) const {
+  hipError_t launch_msg_stage(int c, bool fp64, hipStream_t s, bool per_edge) const {
     hipError_t e;
-    if (ev && (e = hipEventRecord(ev[0], s)) != hipSuccess) return e;
     for (int dk = 0; dk < 4; ++dk) {
       if (items[c][dk].empty()) continue;
       if (!per_edge) {
@@ -176,12 +182,30 @@ struct Plan {
         if (e != hipSuccess) return e;
       }
     }
-    if (ev && (e = hipEventRecord(ev[1], s)) != hipSuccess) return e;
+    return hipSuccess;
+  }
+
+  // One half-sweep of class c.  With events (timing mode, direct launches):
+  // ev[0], the message stage kMsgBurst times, ev[1], the message stage,
+  // ev[2], tile and finalise kernels, ev[3].  The message stage only reads
+  // the state and rewrites its partials, so the repeats are idempotent; their
+  // mean is the message stage's duration without the event overhead.
+  hipError_t launch_tstep(int c, bool fp64, hipStream_t s, const hipEvent_t* ev = nullptr,
+                          bool per_edge = false) const {
+    hipError_t e;
+    if (ev) {
+      if ((e = hipEventRecord(ev[0], s)) != hipSuccess) return e;
+      for (int r = 0; r < kMsgBurst; ++r)
+        if ((e = launch_msg_stage(c, fp64, s, per_edge)) != hipSuccess) return e;
+      if ((e = hipEventRecord(ev[1], s)) != hipSuccess) return e;
+    }
+    if ((e = launch_msg_stage(c, fp64, s, per_edge)) != hipSuccess) return e;
+    if (ev && (e = hipEventRecord(ev[2], s)) != hipSuccess) return e;
     e = launch_tile(tables(c, -1), (int)tiles[c].size(), s);
     if (e != hipSuccess) return e;
     e = launch_finalize(tables(c, -1), (int)inst.size(), s);
     if (e != hipSuccess) return e;
-    if (ev && (e = hipEventRecord(ev[2], s)) != hipSuccess) return e;
+    if (ev && (e = hipEventRecord(ev[3], s)) != hipSuccess) return e;
     return hipSuccess;
   }
 };
@@ -224,7 +248,7 @@ static int build_plan(gmot_ctx* ctx, const std::vector<gmot_problem*>& probs, in
         nd.c = p->fixed[j] ? nullptr : p->d_c + 2 * j;
         nd.tiles = (int)ceil_div(p->sizes[j], kTileRows);
         for (int r = 0; r < nd.tiles; ++r)
-          pl->tiles[c].push_back({(int)pl->nodes[c].size(), r * kTileRows});
+          pl->tiles[c].push_back({(int)pl->nodes[c].size(), r * kTileRows, (int)i, 0});
         pl->nodes[c].push_back(nd);
         ++cnt;
         for (size_t q = 0; q < p->nbrs[j].size(); ++q) {
@@ -296,6 +320,7 @@ static int build_plan(gmot_ctx* ctx, const std::vector<gmot_problem*>& probs, in
         it.col0 = (int)(s * cw);
         it.ncols = (int)std::min<int64_t>(cw, md.n_src - s * cw);
         it.split = (int)s;
+        it.inst = md.inst;
         pl->items[c][dk].push_back(it);
       }
   }
@@ -417,7 +442,7 @@ static int capture_one(Plan* pl, bool fp64, bool per_edge, int start, int k, con
   HIPCHK(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
   hipError_t le = hipSuccess;
   for (int i = 0; i < k && le == hipSuccess; ++i)
-    le = pl->launch_tstep((start + i) & 1, fp64, s, ev ? ev->data() + 3 * i : nullptr, per_edge);
+    le = pl->launch_tstep((start + i) & 1, fp64, s, ev ? ev->data() + kStepEvents * i : nullptr, per_edge);
   hipGraph_t graph = nullptr;
   hipError_t ce = hipStreamEndCapture(s, &graph);
   if (le != hipSuccess) {
@@ -449,7 +474,7 @@ static int get_graph(Plan* pl, bool fp64, bool per_edge, int start, int k, bool 
     // HIP events recorded by graph nodes cannot be timed, so the timed variant
     // launches directly on the stream with two alternating event chains.
     for (int c = 0; c < 2; ++c) {
-      g.ev[c].resize(3 * k);
+      g.ev[c].resize(kStepEvents * k);
       for (auto& e : g.ev[c]) HIPCHK(hipEventCreate(&e));
     }
   } else {
@@ -537,7 +562,7 @@ static int run_plan(Plan* pl, const gmot_opts* o, gmot_result* outs, const std::
       if (timed) {
         e = hipSuccess;
         for (int i = 0; i < k && e == hipSuccess; ++i)
-          e = pl->launch_tstep((start + i) & 1, fp64, s, g->ev[slot].data() + 3 * i, per_edge);
+          e = pl->launch_tstep((start + i) & 1, fp64, s, g->ev[slot].data() + kStepEvents * i, per_edge);
       } else if (no_graph) {
         e = hipSuccess;
         for (int i = 0; i < k && e == hipSuccess; ++i) e = pl->launch_tstep((start + i) & 1, fp64, s, nullptr, per_edge);
@@ -553,10 +578,11 @@ static int run_plan(Plan* pl, const gmot_opts* o, gmot_result* outs, const std::
       const std::vector<hipEvent_t>& E = g->ev[replay & 1];
       for (int i = 0; i < k; ++i) {
         float a = 0.f, b = 0.f;
-        hipError_t e = hipEventElapsedTime(&a, E[3 * i], E[3 * i + 1]);  // message kernel
-        if (e == hipSuccess) e = hipEventElapsedTime(&b, E[3 * i], E[3 * i + 2]);  // whole half-sweep
+        const hipEvent_t* q = E.data() + kStepEvents * i;
+        hipError_t e = hipEventElapsedTime(&a, q[0], q[1]);                  // kMsgBurst message stages
+        if (e == hipSuccess) e = hipEventElapsedTime(&b, q[1], q[3]);      // one half-sweep
         if (e != hipSuccess) return e;
-        times.push_back({replay * k + i, a, b});
+        times.push_back({replay * k + i, a / kMsgBurst, b});
       }
       return hipSuccess;
     };
@@ -611,6 +637,7 @@ static int run_plan(Plan* pl, const gmot_opts* o, gmot_result* outs, const std::
     std::memset(&r, 0, sizeof(r));
     if (st.done == kRunning) rc = fail(GMOT_ESTATE, "an instance was still running when the launch budget ended");
     p->t = st.t;
+    ++p->version;
     r.status = st.done == kConverged ? GMOT_CONVERGED : st.done == kNonFinite ? GMOT_NONFINITE : GMOT_NOT_CONVERGED;
     r.steps = st.updates;
     r.t = st.t;
@@ -861,7 +888,8 @@ static int ensure_plan(gmot_problem* p) {
   return build_plan(p->ctx, {p}, R, target, &p->plan);
 }
 
-// Mean device time of a fused FP32-core half-sweep under this plan: a few real
+// Mean device time of an FP32-core half-sweep (message stage, tile and
+// finalise kernels) under this plan: a few real
 // half-sweeps from the held state, which is snapshotted before and restored
 // after (potential slots, node normalisers and counters).
 static int time_plan(Plan* pl, double* ms) {
@@ -907,7 +935,7 @@ static int time_plan(Plan* pl, double* ms) {
     std::vector<gmot_result> r(n);
     rc = run_plan(pl, &o, r.data());
   }
-  *ms = pl->acc.msg_launches ? pl->acc.msg_ms / (double)pl->acc.msg_launches : INFINITY;
+  *ms = pl->acc.msg_launches ? pl->acc.sweep_ms / (double)pl->acc.msg_launches : INFINITY;
   pl->acc = acc;
   copy_state(false);
   if (e == hipSuccess) e = hipStreamSynchronize(s);
@@ -974,6 +1002,7 @@ static int restart_problem(gmot_problem* p) {
   if (p->total_de > 0) HIPCHK(hipMemsetAsync(p->d_lam[0], 0, sizeof(double) * p->total_de, p->ctx->stream));
   HIPCHK(hipMemsetAsync(p->d_c, 0, sizeof(double) * 2 * p->N, p->ctx->stream));
   p->t = 1;
+  ++p->version;
   return GMOT_OK;
 }
 
@@ -1018,6 +1047,174 @@ static EdgeDesc edge_desc(const gmot_problem* p, int e) {
 // ---------------------------------------------------------------------------
 // C ABI
 // ---------------------------------------------------------------------------
+
+// ---------------------------------------------------------------------------
+// rounding (Algorithm round)
+// ---------------------------------------------------------------------------
+// Device buffers of the last rounding of a problem: per directed edge the row
+// sums, targets, scalings and residuals (four arrays laid out like the
+// potentials), and the descriptors.  Valid while the problem's state version
+// is unchanged; the rounded plans are formed from them on request.
+struct RoundState {
+  void* buf = nullptr;
+  RoundDesc* d_desc = nullptr;          // [2E] with column weights (passes 1, 2; plan read-back)
+  std::vector<int> edge_desc;           // edge -> desc index of its end in S (opposite at + E)
+  std::vector<uint8_t> s_is_a;          // edge -> the end in S is the edge's first node
+  std::vector<double> inv_s;            // edge -> 1 / |e_r|_1 (0 when e_r = 0)
+  uint64_t version = ~0ull;
+  ~RoundState() {
+    if (buf) (void)hipFree(buf);
+  }
+};
+
+static RoundDesc round_desc(const gmot_problem* p, int de, double* arrays) {
+  const int e = de >> 1;
+  const bool fwd = (de & 1) == 0;
+  const int j = fwd ? p->edges[2 * e] : p->edges[2 * e + 1];
+  const int k = fwd ? p->edges[2 * e + 1] : p->edges[2 * e];
+  const int sj = p->slot_of_class(p->colour[j]), sk = p->slot_of_class(p->colour[k]);
+  RoundDesc d{};
+  d.supp_r = p->d_support + p->node_off[j] * p->dim;
+  d.supp_c = p->d_support + p->node_off[k] * p->dim;
+  d.lam_r = p->d_lam[sj] + p->de_off[de];
+  d.lam_c = p->d_lam[sk] + p->de_off[de ^ 1];
+  d.c_r = p->fixed[j] ? nullptr : p->d_c + 2 * j + sj;
+  d.c_c = p->fixed[k] ? nullptr : p->d_c + 2 * k + sk;
+  d.lg_r = p->d_lg + p->node_off[j];
+  d.lg_c = p->d_lg + p->node_off[k];
+  if (p->cost_kind == GMOT_COST_EXPLICIT)  // cost[y * n_j + x]: C_e^T when j = a, C_e when j = b
+    d.cost = fwd ? p->d_cost + p->total_cost + p->cost_off[e] : p->d_cost + p->cost_off[e];
+  const int64_t o = p->de_off[de], D = p->total_de;
+  d.rs = arrays + o;
+  d.tg = arrays + D + o;
+  d.sc = arrays + 2 * D + o;
+  d.er = arrays + 3 * D + o;
+  d.n_r = p->sizes[j];
+  d.n_c = p->sizes[k];
+  d.dim = p->dim;
+  d.cost_kind = p->cost_kind;
+  d.eps = p->eps;
+  return d;
+}
+
+static int round_problem(gmot_problem* p, gmot_round_result* out, double* edge_transport) {
+  const int E = p->E;
+  const int side = (p->t & 1) ? 0 : 1;  // the class the next half-sweep would update
+  // descriptors: ends in S grouped by node (ascending neighbours), opposites at + E
+  std::vector<int> sde;
+  std::vector<RoundNode> nodes;
+  std::vector<int> edge_desc(E, -1);
+  std::vector<uint8_t> s_is_a(E, 0);
+  for (int j = 0; j < p->N; ++j) {
+    if (p->colour[j] != side || p->nbrs[j].empty()) continue;
+    RoundNode nd{};
+    nd.n = p->sizes[j];
+    nd.deg = (int)p->nbrs[j].size();
+    nd.d0 = (int)sde.size();
+    nd.mu = p->fixed[j] ? p->d_mu + p->node_off[j] : nullptr;
+    nodes.push_back(nd);
+    for (int de : p->nbr_de[j]) {
+      edge_desc[de >> 1] = (int)sde.size();
+      s_is_a[de >> 1] = (de & 1) == 0;
+      sde.push_back(de);
+    }
+  }
+  if ((int)sde.size() != E) return fail(GMOT_ESTATE, "rounding: the tree is not bipartite as colored");
+  std::vector<RoundItem> it0, it1, it2;
+  for (int i = 0; i < 2 * E; ++i) {
+    const int de = i < E ? sde[i] : sde[i - E] ^ 1;
+    const int j = (de & 1) ? p->edges[2 * (de >> 1) + 1] : p->edges[2 * (de >> 1)];
+    for (int r0 = 0; r0 < p->sizes[j]; r0 += kBlock) {
+      it0.push_back({i, r0});
+      (i < E ? it2 : it1).push_back({i, r0});
+    }
+  }
+  const size_t D = (size_t)p->total_de;
+  const size_t o_desc0 = align_up(sizeof(double) * 4 * D, 256);
+  const size_t o_desc = o_desc0 + align_up(sizeof(RoundDesc) * 2 * E, 256);
+  const size_t o_it = o_desc + align_up(sizeof(RoundDesc) * 2 * E, 256);
+  const size_t n_it = it0.size() + it1.size() + it2.size();
+  const size_t o_nodes = o_it + align_up(sizeof(RoundItem) * n_it, 256);
+  const size_t o_part = o_nodes + align_up(sizeof(RoundNode) * nodes.size(), 256);
+  const size_t o_err = o_part + align_up(sizeof(double4) * it2.size(), 256);
+  const size_t total = o_err + sizeof(double) * nodes.size();
+  delete p->round;
+  p->round = nullptr;
+  std::unique_ptr<RoundState> rs(new RoundState());
+  if (hipMalloc(&rs->buf, total) != hipSuccess) return fail(GMOT_ENOMEM, "rounding buffers");
+  char* base = (char*)rs->buf;
+  double* arrays = (double*)base;
+  std::vector<RoundDesc> d0(2 * E), d12(2 * E);
+  for (int i = 0; i < 2 * E; ++i) {
+    const int de = i < E ? sde[i] : sde[i - E] ^ 1;
+    d0[i] = round_desc(p, de, arrays);
+  }
+  for (int i = 0; i < E; ++i) {
+    d12[i] = d0[i];              // rows in S, pass 2: columns weighted by Y, residual e_c
+    d12[i].sc_col = d0[i + E].sc;
+    d12[i].er_col = d0[i + E].er;
+    d12[i + E] = d0[i + E];      // rows on the other side, pass 1: columns weighted by X
+    d12[i + E].sc_col = d0[i].sc;
+  }
+  std::vector<RoundItem> items;
+  items.reserve(n_it);
+  items.insert(items.end(), it0.begin(), it0.end());
+  items.insert(items.end(), it1.begin(), it1.end());
+  items.insert(items.end(), it2.begin(), it2.end());
+  RoundDesc* dd0 = (RoundDesc*)(base + o_desc0);
+  RoundDesc* dd = (RoundDesc*)(base + o_desc);
+  RoundItem* di = (RoundItem*)(base + o_it);
+  RoundNode* dn = (RoundNode*)(base + o_nodes);
+  double4* dpart = (double4*)(base + o_part);
+  double* derr = (double*)(base + o_err);
+  hipStream_t s = p->ctx->stream;
+  std::vector<double4> parts(it2.size());
+  std::vector<double> errs(nodes.size());
+  hipError_t e = hipMemcpyAsync(dd0, d0.data(), sizeof(RoundDesc) * 2 * E, hipMemcpyHostToDevice, s);
+  if (e == hipSuccess) e = hipMemcpyAsync(dd, d12.data(), sizeof(RoundDesc) * 2 * E, hipMemcpyHostToDevice, s);
+  if (e == hipSuccess) e = hipMemcpyAsync(di, items.data(), sizeof(RoundItem) * n_it, hipMemcpyHostToDevice, s);
+  if (e == hipSuccess) e = hipMemcpyAsync(dn, nodes.data(), sizeof(RoundNode) * nodes.size(), hipMemcpyHostToDevice, s);
+  if (e == hipSuccess) e = launch_round_rows(0, dd0, di, (int)it0.size(), nullptr, s);
+  if (e == hipSuccess) e = launch_round_node(dn, (int)nodes.size(), dd0, derr, s);
+  if (e == hipSuccess) e = launch_round_rows(1, dd, di + it0.size(), (int)it1.size(), nullptr, s);
+  if (e == hipSuccess) e = launch_round_rows(2, dd, di + it0.size() + it1.size(), (int)it2.size(), dpart, s);
+  if (e == hipSuccess) e = hipMemcpyAsync(parts.data(), dpart, sizeof(double4) * parts.size(), hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipMemcpyAsync(errs.data(), derr, sizeof(double) * errs.size(), hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e != hipSuccess) return fail(GMOT_EDEVICE, std::string("rounding: ") + hipGetErrorString(e));
+  // per edge: transport of F, bilinear term, |e_r|_1, in the order of the items
+  std::vector<double> T(E, 0.0), Bl(E, 0.0), Se(E, 0.0);
+  double cinf = 0.0;
+  for (size_t i = 0; i < it2.size(); ++i) {
+    const int edge = sde[it2[i].desc] >> 1;
+    T[edge] += parts[i].x;
+    Bl[edge] += parts[i].y;
+    Se[edge] += parts[i].z;
+    cinf = std::max(cinf, parts[i].w);
+  }
+  rs->inv_s.assign(E, 0.0);
+  double tot = 0.0;
+  for (int edge = 0; edge < E; ++edge) {
+    if (Se[edge] > 0.0) rs->inv_s[edge] = 1.0 / Se[edge];
+    const double te = T[edge] + Bl[edge] * rs->inv_s[edge];
+    if (edge_transport) edge_transport[edge] = te;
+    tot += te;
+  }
+  double err = 0.0;
+  for (double v : errs) err += v;
+  out->transport = tot;
+  out->err_side = err;
+  out->c_inf = cinf;
+  out->side = side;
+  out->reserved = 0;
+  rs->d_desc = dd;
+  rs->edge_desc = std::move(edge_desc);
+  rs->s_is_a = std::move(s_is_a);
+  rs->version = p->version;
+  p->round = rs.release();
+  return GMOT_OK;
+}
+
 extern "C" {
 
 int gmot_ctx_create(gmot_ctx** out, int device, void* hip_stream) {
@@ -1073,6 +1270,7 @@ void gmot_problem_destroy(gmot_problem* p) {
   if (!p) return;
   (void)hipStreamSynchronize(p->ctx->stream);
   delete p->plan;
+  delete p->round;
   if (p->arena) (void)hipFree(p->arena);
   delete p;
 }
@@ -1175,6 +1373,38 @@ int gmot_evaluate(gmot_problem* p, gmot_eval* out) {
   return GMOT_OK;
 }
 
+int gmot_round(gmot_problem* p, gmot_round_result* out, double* edge_transport) {
+  if (!p || !out) return fail(GMOT_EINVAL, "null problem or output");
+  std::memset(out, 0, sizeof(*out));
+  out->side = (p->t & 1) ? 0 : 1;
+  if (p->E == 0) return GMOT_OK;
+  if (p->t < 2) return fail(GMOT_ESTATE, "rounding needs a state produced by at least one half-sweep");
+  HIPCHK(hipSetDevice(p->ctx->device));
+  return round_problem(p, out, edge_transport);
+}
+
+int gmot_get_rounded_coupling(gmot_problem* p, int32_t edge, double* out) {
+  if (!p || !out) return fail(GMOT_EINVAL, "null problem or output");
+  if (edge < 0 || edge >= p->E) return fail(GMOT_EINVAL, "edge index out of range");
+  if (!p->round || p->round->version != p->version)
+    return fail(GMOT_ESTATE, "no rounding of the held state: call gmot_round first");
+  HIPCHK(hipSetDevice(p->ctx->device));
+  const RoundState* rs = p->round;
+  const int i = rs->edge_desc[edge];
+  const size_t total = (size_t)p->sizes[p->edges[2 * edge]] * p->sizes[p->edges[2 * edge + 1]];
+  double* buf = nullptr;
+  if (hipMalloc(&buf, sizeof(double) * std::max<size_t>(1, total)) != hipSuccess)
+    return fail(GMOT_ENOMEM, "rounded plan buffer");
+  hipStream_t s = p->ctx->stream;
+  hipError_t e = launch_round_plan(rs->d_desc + i, rs->d_desc + i + p->E, rs->inv_s[edge], rs->s_is_a[edge], buf,
+                                   total, s);
+  if (e == hipSuccess) e = hipMemcpyAsync(out, buf, sizeof(double) * total, hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  (void)hipFree(buf);
+  if (e != hipSuccess) return fail(GMOT_EDEVICE, std::string("rounded plan: ") + hipGetErrorString(e));
+  return GMOT_OK;
+}
+
 int64_t gmot_potentials_size(const gmot_problem* p) { return p ? p->total_de : -1; }
 
 int gmot_get_potentials(gmot_problem* p, double* out) {
@@ -1231,6 +1461,7 @@ int gmot_set_potentials(gmot_problem* p, const double* in) {
   HIPCHK(hipMemset(p->d_c, 0, sizeof(double) * 2 * p->N));
   HIPCHK(hipDeviceSynchronize());
   p->t = 1;
+  ++p->version;
   return GMOT_OK;
 }
 
@@ -1242,6 +1473,7 @@ int gmot_set_potentials_dev(gmot_problem* p, const double* in_dev) {
                           p->ctx->stream));
   HIPCHK(hipMemsetAsync(p->d_c, 0, sizeof(double) * 2 * p->N, p->ctx->stream));
   p->t = 1;
+  ++p->version;
   return GMOT_OK;
 }
 
@@ -1417,7 +1649,10 @@ int gmot_star_apply_dev(gmot_problem* const* probs, int32_t count, const float* 
   int rej = 0;
   HIPCHK(hipMemcpyAsync(&rej, d_rej, sizeof(int), hipMemcpyDeviceToHost, s));
   HIPCHK(hipStreamSynchronize(s));
-  for (int i = 0; i < count; ++i) probs[i]->t = 1;
+  for (int i = 0; i < count; ++i) {
+    probs[i]->t = 1;
+    ++probs[i]->version;
+  }
   if (rejected) *rejected = rej;
   return GMOT_OK;
 }
