@@ -25,6 +25,8 @@ import statistics
 import sys
 import time
 
+import numpy as np
+
 ROOT = os.path.dirname(os.path.abspath(__file__))
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
@@ -32,6 +34,8 @@ if ROOT not in sys.path:
 METRIC = "edge-iterations/s and time-to-1e-6 marginal error; plain vs batched+warm-start"
 # VALU issue capacity of MI355X: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz.
 VALU_SLOTS_PER_S = 256 * 64 * 2.4e9
+# MI355X HBM3E peak, GB/s
+HBM_PEAK_GBS = 8000.0
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_msg_chain_traffic.txt")
 KERNEL_SRC = os.path.join(ROOT, "paper_2406_10849_amd", "csrc", "gmot_kernels.hip")
 
@@ -129,6 +133,60 @@ def bench_batched(ctx, tol: float, count: int) -> dict:
     return out
 
 
+def bench_tree(ctx, tol: float, half_sweeps: int) -> dict:
+    """The 256-node random tree (n in [256, 4096], 2D grids, eps = 5e-3):
+    (a) solved to the stopping sum with every message of a class in one
+    launch (layer-parallel) and with one launch per message (plain), and
+    (b) with explicit FP32 cost matrices (the squared distances, stored), whose
+    message kernel streams 4 bytes per pair from HBM: its roofline is HBM
+    bandwidth (the cost set, 4.8 GB per orientation, is far larger than the
+    256 MB last-level cache)."""
+    from workloads import make_config, COST_EXPLICIT
+    from paper_2406_10849_amd import Problem
+    p = make_config(3)
+    out = {"workload": "random-tree-256node-2d", "edges": p.n_edges,
+           "pairs_per_half_sweep": p.pairs_per_tstep()}
+    g = Problem(ctx, p)
+    g.autotune()
+    for sched in ("layer", "per_edge"):
+        g.solve(tol=tol, max_steps=200000, schedule=sched)     # graph capture outside the timing
+        t0 = time.perf_counter()
+        r = g.solve(tol=tol, max_steps=200000, schedule=sched)
+        dt = time.perf_counter() - t0
+        assert r["status"] == "converged", f"tree ({sched}) did not converge"
+        out[sched] = {"s": dt, "half_sweeps": r["t"], "edge_iterations_per_s": p.n_edges * r["t"] / dt}
+    out["layer_vs_plain_speedup"] = out["per_edge"]["s"] / out["layer"]["s"]
+    g.close()
+
+    cost = []
+    for a, b in p.edges:
+        X, Y = p.node_support(int(a)), p.node_support(int(b))
+        C = np.zeros((X.shape[0], Y.shape[0]))
+        for d in range(p.dim):
+            C += (X[:, d][:, None] - Y[:, d][None, :]) ** 2
+        cost.append(C.astype(np.float32))
+    p.cost_kind = COST_EXPLICIT
+    p.cost = cost
+    g = Problem(ctx, p)
+    del cost
+    tuned = g.autotune()
+    g.solve(tol=0.0, max_steps=4, timing=True)
+    g.stats(reset=True)
+    g.solve(tol=0.0, max_steps=half_sweeps, timing=True)
+    st = g.stats()
+    avg_ms = st["msg_ms"] / max(st["msg_launches"], 1)
+    pairs = st["msg_pairs"] / max(st["msg_launches"], 1)
+    gbs = 4.0 * pairs / (avg_ms / 1e3) / 1e9
+    out["explicit_cost"] = {
+        "tiles": tuned, "half_sweeps_timed": st["msg_launches"], "pairs_per_launch": pairs,
+        "avg_launch_ms": avg_ms, "half_sweep_avg_ms": st["sweep_ms"] / max(st["msg_launches"], 1),
+        "roofline": {"bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": gbs / HBM_PEAK_GBS, "traffic": None, "kernel": "k_msg<explicit>",
+                     "bytes_per_pair": 4}}
+    g.close()
+    return out
+
+
 def bench_warm(ctx, tol: float, n_train: int, n_test: int, epochs: int) -> dict:
     """Learned warm start on 8-leaf stars (n = 1024, 1D grid, eps = 1e-2): train
     on solver-generated pairs, then on held-out instances compare (a) each
@@ -178,8 +236,9 @@ def main() -> int:
                     help="also run one 1 GiB device copy (PMC calibration for HBM byte counters)")
     ap.add_argument("--no-extras", action="store_true", help="skip the batched and warm-start comparisons")
     ap.add_argument("--batched-count", type=int, default=512)
-    ap.add_argument("--warm-train", type=int, default=4096)
-    ap.add_argument("--warm-test", type=int, default=512)
+    ap.add_argument("--tree-half-sweeps", type=int, default=40)
+    ap.add_argument("--warm-train", type=int, default=20000)
+    ap.add_argument("--warm-test", type=int, default=1024)
     ap.add_argument("--warm-epochs", type=int, default=30)
     args = ap.parse_args()
     if args.gpus != 1:
@@ -277,10 +336,29 @@ def main() -> int:
                      "launches_timed": st["msg_launches"],
                      "half_sweep_avg_ms": st["sweep_ms"] / max(st["msg_launches"], 1)},
     }
+    # rounding of the converged state onto the constraint set (Algorithm round):
+    # four FP64 row passes over recomputed plan entries (row sums of both
+    # orientations, column scaling, final pass), outside the timed region
+    rt = []
+    for _ in range(5):
+        sync()
+        t0 = time.perf_counter()
+        rr = g.round()
+        sync()
+        rt.append(time.perf_counter() - t0)
+    round_ms = 1e3 * statistics.median(rt)
+    out["rounding"] = {"wall_ms": round_ms, "pair_evaluations": 4 * pairs_per_half_sweep,
+                       "pairs_per_s": 4 * pairs_per_half_sweep / (round_ms / 1e3),
+                       "transport_rounded": rr["transport"], "transport_unrounded": last_ev["transport"],
+                       "err_side": rr["err_side"], "lemma_round_bound": 2 * rr["c_inf"] * rr["err_side"]}
+    log(f"rounding: {out['rounding']}")
     if not args.no_extras:
         log("batched stars: one graph for all instances vs per-instance launches")
         out["batched"] = bench_batched(ctx, args.tol, args.batched_count)
         log(f"batched: {out['batched']}")
+        log("random tree: layer-parallel vs plain schedule, explicit-cost streaming")
+        out["tree"] = bench_tree(ctx, args.tol, args.tree_half_sweeps)
+        log(f"tree: {out['tree']}")
         log("learned warm start")
         out["warm_start"] = bench_warm(ctx, args.tol, args.warm_train, args.warm_test, args.warm_epochs)
         log(f"warm start: {out['warm_start']}")

@@ -106,14 +106,25 @@ typedef struct {
                            node stage, and accumulate the stage durations (read with
                            gmot_*_stats); 0: graph replay, no events                  */
   int32_t skip_verify;  /* GMOT_PREC_FP32CORE only.  0 (default): the FP32-core loop
-                           runs until its own stopping sum is <= 0.8 * tol, then FP64
-                           half-sweeps (at most 256) continue until the FP64 stopping
-                           sum is <= tol, so convergence is judged in FP64.  1: stop
-                           on the FP32-core sum <= tol.                              */
+                           runs until its own stopping sum is <= 0.8 * tol, or until
+                           that sum has not reached a new minimum for 128 half-sweeps
+                           (FP32 noise floor above tol), then FP64 half-sweeps continue
+                           within the remaining max_steps until the FP64 stopping sum
+                           is <= tol, so convergence is judged in FP64.  1: stop on
+                           the FP32-core sum <= tol.                                 */
   int32_t schedule;     /* GMOT_SCHED_LAYER (default): every message of the class being
                            updated in one launch; GMOT_SCHED_PER_EDGE: the same
                            half-sweep with one launch per message (same iterates)    */
+  int32_t msg_passes;   /* FP32-core message sums.  GMOT_PASSES_AUTO (0, default): two
+                           passes (row max, then sum) for the first two half-sweeps of
+                           the call, then one pass shifted by each row's max from the
+                           previous computation of the same message, with in-kernel
+                           re-shifting when a row leaves the FP32 range; the sums are
+                           exact either way.  GMOT_PASSES_TWO (2): always two passes. */
 } gmot_opts;
+
+#define GMOT_PASSES_AUTO  0
+#define GMOT_PASSES_TWO   2
 
 #define GMOT_SCHED_LAYER     0
 #define GMOT_SCHED_PER_EDGE  1

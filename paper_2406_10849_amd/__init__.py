@@ -22,6 +22,7 @@ from ._lib import (GMOT_OK, GMOT_EINVAL, GMOT_EMARGINAL, GMOT_ENOMEM, GMOT_EDEVI
 STATUS_NAMES = {GMOT_CONVERGED: "converged", GMOT_NOT_CONVERGED: "not_converged", GMOT_NONFINITE: "nonfinite"}
 PRECISIONS = {"fp32core": GMOT_PREC_FP32CORE, "fp64": GMOT_PREC_FP64}
 SCHEDULES = {"layer": 0, "per_edge": 1}
+PASSES = {"auto": 0, "two": 2}
 
 
 class GmotError(RuntimeError):
@@ -123,7 +124,7 @@ class Problem:
 
     @staticmethod
     def _opts(tol, max_steps, check_every, precision, restart, timing=False, verify=True,
-              schedule="layer") -> _lib.Opts:
+              schedule="layer", passes="auto") -> _lib.Opts:
         o = _lib.Opts()
         o.tol = float(tol)
         o.max_steps = int(max_steps)
@@ -133,6 +134,7 @@ class Problem:
         o.timing = 1 if timing else 0
         o.skip_verify = 0 if verify else 1
         o.schedule = SCHEDULES[schedule] if isinstance(schedule, str) else int(schedule)
+        o.msg_passes = PASSES[passes] if isinstance(passes, str) else int(passes)
         return o
 
     @staticmethod
@@ -162,8 +164,9 @@ class Problem:
                 "err_sum": float(r.err_sum), "err_max": float(r.err_max), "seconds": float(r.seconds)}
 
     def solve(self, tol: float = 1e-6, max_steps: int = 100000, check_every: int = 0, precision="fp32core",
-              restart: bool = True, timing: bool = False, verify: bool = True, schedule="layer") -> dict:
-        o = self._opts(tol, max_steps, check_every, precision, restart, timing, verify, schedule)
+              restart: bool = True, timing: bool = False, verify: bool = True, schedule="layer",
+              passes="auto") -> dict:
+        o = self._opts(tol, max_steps, check_every, precision, restart, timing, verify, schedule, passes)
         r = _lib.Result()
         _check(self._lib.gmot_solve(self._h, C.byref(o), C.byref(r)), "gmot_solve")
         return self._res(r)
@@ -247,8 +250,9 @@ class Batch:
             pass
 
     def solve(self, tol: float = 1e-6, max_steps: int = 100000, check_every: int = 0, precision="fp32core",
-              restart: bool = True, timing: bool = False, verify: bool = True, schedule="layer") -> List[dict]:
-        o = Problem._opts(tol, max_steps, check_every, precision, restart, timing, verify, schedule)
+              restart: bool = True, timing: bool = False, verify: bool = True, schedule="layer",
+              passes="auto") -> List[dict]:
+        o = Problem._opts(tol, max_steps, check_every, precision, restart, timing, verify, schedule, passes)
         rs = (_lib.Result * len(self.problems))()
         _check(self._lib.gmot_batch_solve(self._h, C.byref(o), rs), "gmot_batch_solve")
         return [Problem._res(r) for r in rs]

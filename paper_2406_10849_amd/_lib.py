@@ -52,6 +52,7 @@ class Opts(C.Structure):
         ("timing", C.c_int32),
         ("skip_verify", C.c_int32),
         ("schedule", C.c_int32),
+        ("msg_passes", C.c_int32),
     ]
 
 

@@ -44,7 +44,7 @@ constexpr int kChunk = 256;          // columns staged in LDS per chunk (one per
 constexpr double kLog2e = 1.44269504088896340736;
 constexpr double kLn2 = 0.693147180559945309417;
 
-enum Done : int { kRunning = 0, kConverged = 1, kMaxSteps = 2, kNonFinite = 3 };
+enum Done : int { kRunning = 0, kConverged = 1, kMaxSteps = 2, kNonFinite = 3, kStalled = 4 };
 
 // One message m_{k->j}: rows index supp(j) ("dst"), columns index supp(k) ("src").
 struct MsgDesc {
@@ -54,7 +54,8 @@ struct MsgDesc {
   const double* c_src;       // c_k slots [2] (NULL: constrained source, c = 0)
   const double* lg_src;      // log gamma_k, [n_src]
   double* lam_dst[2];        // stored L_(j,k) slots, [n_dst]
-  double2* partial;          // [ns * n_dst]: (row max, sum of 2^(w - max)) per column split
+  double2* partial;          // [n_dst * ns]: per row its ns column splits, each (split max M, sum of
+                             // 2^(w - M)); M of the previous computation is the next one-pass shift
   double* mfull;             // merged message m_{k->j}, [n_dst], natural log
   const float* cost;         // explicit cost stored src-major: cost[y * n_dst + x] = C_(j,k)(x, y)
   int32_t n_dst, n_src, ns, inst;
@@ -69,11 +70,12 @@ struct K1Item {
 };
 
 constexpr int kTileRows = 256;  // rows per block of the tile kernel
+constexpr int kRecExtra = 2;    // tile record entries after the per-edge terms
 
 // One node of the class being updated; its deg incoming messages are
 // msgs[msg0 .. msg0 + deg) in ascending neighbour order.  Its rows form
 // `tiles` tiles of kTileRows; tile records (deg stopping-sum terms, then the
-// tile's LSE max and scaled sum of abar) start at tpart + tile * (deg + 2).
+// tile's LSE max and scaled sum of abar) start at tpart + tile * (deg + kRecExtra).
 struct NodeItem {
   int32_t inst, node, n, deg;
   int32_t fixed, msg0, err_idx, tiles;
@@ -105,6 +107,10 @@ struct InstState {
   int counter;               // node blocks finished in the current half-sweep
   int node0[2], nnodes[2];   // node-error index ranges per class
   unsigned long long clk_start, clk_stop;
+  long long onepass_from;    // the FP32-core message kernel runs one pass from this half-sweep on
+  double best_err;           // smallest stopping sum seen in this call
+  long long best_t;          // the half-sweep that measured it
+  long long stall_window;    // stop as stalled after this many half-sweeps without a new minimum (0: never)
 };
 
 struct Tables {

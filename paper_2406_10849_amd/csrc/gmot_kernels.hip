@@ -29,6 +29,8 @@ namespace {
 
 constexpr int kRegDeg = 8;     // incident edges whose messages the tile kernel keeps in registers
 constexpr int kRecChunk = 64;  // tile records reduced per block barrier
+constexpr int kGroup = 4;      // edges whose loads the tile kernel issues together
+constexpr int kNsReg = 8;      // column splits per edge held in registers by the tile kernel
 
 __device__ inline double wave_sum(double v) {
 #pragma unroll
@@ -59,17 +61,25 @@ __device__ inline double block_max(double v, double* sh) {
 
 __device__ inline float exp2_hw(float x) { return __builtin_amdgcn_exp2f(x); }
 
-// m_{k->j}(x) in natural log from the column-split partials of row x.
-__device__ inline double merge_row(const MsgDesc& md, int n, int x, double x2) {
+// log2 sum_y 2^w(x, y) of row x from its column-split partials (M_s, S_s),
+// M_s the split's max and S_s its sum of 2^(w - M_s); also returns the row max
+// M (the next one-pass shift) and the sum S relative to it.
+struct Merged { double lse2, M, S; };
+__device__ inline Merged merge_splits(const double2* __restrict__ p, int ns) {
   double Mx = -INFINITY;
-  for (int s = 0; s < md.ns; ++s) Mx = fmax(Mx, md.partial[(size_t)s * n + x].x);
-  if (!(Mx > -INFINITY)) return -INFINITY;
+  for (int s = 0; s < ns; ++s) Mx = fmax(Mx, p[s].x);
+  if (!(Mx > -INFINITY)) return {-INFINITY, -INFINITY, 0.0};
   double S = 0.0;
-  for (int s = 0; s < md.ns; ++s) {
-    const double2 p = md.partial[(size_t)s * n + x];
-    if (p.y > 0.0) S += (p.x == Mx) ? p.y : p.y * exp2(p.x - Mx);
+  for (int s = 0; s < ns; ++s) {
+    const double2 q = p[s];
+    if (q.y > 0.0) S += (q.x == Mx) ? q.y : q.y * exp2(q.x - Mx);
   }
-  return (S > 0.0) ? kLn2 * (Mx + log2(S)) - x2 / md.eps : -INFINITY;
+  return {(S > 0.0) ? Mx + log2(S) : -INFINITY, Mx, S};
+}
+// m_{k->j}(x) in natural log from the column-split partials of row x.
+__device__ inline double merge_row(const MsgDesc& md, int x, double x2) {
+  const Merged g = merge_splits(md.partial + (size_t)x * md.ns, md.ns);
+  return (g.lse2 > -INFINITY) ? kLn2 * g.lse2 - x2 / md.eps : -INFINITY;
 }
 
 __device__ inline double sq_norm(const double* xs, int dim, int x) {
@@ -91,8 +101,15 @@ __device__ void decide(const Tables& tb, InstState* st, long long t, double E, d
     st->err_sum = E;
     st->err_max = Em;
     st->checked_t = t;
+    if (E < st->best_err) {
+      st->best_err = E;
+      st->best_t = t;
+    }
     if (t >= st->min_check_t && E <= st->tol) {
       st->done = kConverged;  // this half-sweep wrote only the unread slots
+      stop = true;
+    } else if (st->stall_window > 0 && t - st->best_t >= st->stall_window) {
+      st->done = kStalled;    // no new minimum for a while: the state before t is kept
       stop = true;
     } else {
       st->t = t + 1;
@@ -113,13 +130,28 @@ __device__ void decide(const Tables& tb, InstState* st, long long t, double E, d
 
 // ---------------------------------------------------------------------------
 // Message log-sum-exp.  Block = 4 waves; lane l of wave w owns rows
-// row0 + (w*R + r)*64 + l, r < R.  Columns are streamed through LDS in chunks;
-// within a chunk the row max is found first (pass 1) and the scaled sum taken
-// second (pass 2); across chunks the running sum is rescaled when the max
-// grows.  Output: (max, sum 2^(w - max)) per row for this column split.
+// row0 + (w*R + r)*64 + l, r < R.  Columns are streamed through LDS in chunks.
+// Output per row and column split: (M, sum 2^(w - M)) with M the split's max.
+//
+// Two passes (first computations, FP64 path, evaluation): per chunk, pass 1
+// finds the row max and pass 2 sums 2^(w - max); the running sum is rescaled
+// when the max grows.
+// One pass (FP32-core iteration from the third half-sweep of a call on): the
+// shift s is the max of the same row and column split at the previous
+// computation of the message (still in the partial buffer), and one pass sums
+// 2^(w - s) while tracking the max.  Any finite s gives the
+// exact sum while the terms stay in FP32 range; a chunk whose max exceeds s by
+// more than kShiftHi moves s up to that max and is summed again, and if a
+// row's max ends more than kShiftLo below s (its top terms would lose FP32
+// precision) the block repeats its columns in two passes.  Both decisions are
+// block-uniform.  Near convergence s differs from the max by the drift of the
+// iteration, so the dominant terms' arguments are nearly exact, as in two passes.
 // ITER: slots come from the instance counter; finished instances (or those
 // whose next half-sweep updates the other class) return at entry.
 // ---------------------------------------------------------------------------
+constexpr double kShiftHi = 96.0;
+constexpr double kShiftLo = -96.0;
+
 template <int DIM, int R, bool F64, bool EXPL, bool ITER>
 __global__ __launch_bounds__(kBlock) void k_msg(Tables tb, int eval_src_slot) {
   constexpr int CH = EXPL ? 32 : kChunk;            // columns per LDS chunk
@@ -131,11 +163,13 @@ __global__ __launch_bounds__(kBlock) void k_msg(Tables tb, int eval_src_slot) {
   const K1Item it = tb.items[blockIdx.x];
   const MsgDesc* __restrict__ md = tb.msgs + it.msg;
   int src_slot = eval_src_slot;
+  bool one = false;
   if (ITER) {
     const InstState* st = tb.inst + it.inst;
     const long long t = st->t;
     if (st->done || ((t & 1) == 1) != (tb.colour == 0)) return;
     src_slot = (int)((t >> 1) & 1);
+    one = !F64 && t >= st->onepass_from;
   }
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int n_dst = md->n_dst;
@@ -149,122 +183,195 @@ __global__ __launch_bounds__(kBlock) void k_msg(Tables tb, int eval_src_slot) {
 
   int row[R];
   double cx[R][DIM];
-  double Mrun[R], Srun[R];
+  double s0[R];  // one-pass shift from the previous computation
 #pragma unroll
   for (int r = 0; r < R; ++r) {
     row[r] = it.row0 + (wave * R + r) * 64 + lane;
     const bool v = row[r] < n_dst;
 #pragma unroll
     for (int d = 0; d < DIM; ++d) cx[r][d] = (v && !EXPL) ? cxs * md->supp_dst[(size_t)row[r] * DIM + d] : 0.0;
-    Mrun[r] = -INFINITY;
-    Srun[r] = 0.0;
+    s0[r] = 0.0;
+    if (one && v) {
+      const double m = md->partial[(size_t)row[r] * md->ns + it.split].x;
+      s0[r] = isfinite(m) ? m : 0.0;
+    }
   }
 
-  for (int c0 = 0; c0 < it.ncols; c0 += CH) {
-    const int cn = min(CH, it.ncols - c0);
-    const int cpad = (cn + 7) & ~7;
-    __syncthreads();  // previous chunk fully consumed
-    if (threadIdx.x < cpad) {
-      double a = -INFINITY;
-      double y[DIM > 0 ? DIM : 1];
-#pragma unroll
-      for (int d = 0; d < DIM; ++d) y[d] = 0.0;
-      if (threadIdx.x < cn) {
-        const int col = it.col0 + c0 + threadIdx.x;
-        double base = (lam[col] - csrc) + lg[col];
-        if (!EXPL) {
-          double y2 = 0.0;
-#pragma unroll
-          for (int d = 0; d < DIM; ++d) {
-            y[d] = ys[(size_t)col * DIM + d];
-            y2 = fma(y[d], y[d], y2);
-          }
-          base -= y2 / eps;
-        }
-        a = kLog2e * base;
-      }
-      s_col[threadIdx.x * STR] = a;
-      if (!EXPL) {
-#pragma unroll
-        for (int d = 0; d < DIM; ++d) s_col[threadIdx.x * STR + 1 + d] = y[d];
-      }
-    }
+  // w(x, y) of local row slot (wave*R + r) and staged column c
+  auto wval = [&](int r, int c, double a) -> double {
+    double w = a;
     if (EXPL) {
-      // cost tile, stored src-major: cost[y * n_dst + x]; coalesced over x
-      for (int c = 0; c < cpad; ++c) {
-        const int col = it.col0 + c0 + c;
+      w = fma(ces, (double)s_cost[c * TM + (wave * R + r) * 64 + lane], w);
+    } else {
 #pragma unroll
-        for (int r = 0; r < R; ++r) {
-          const int lr = r * 256 + threadIdx.x;
-          const int x = it.row0 + lr;
-          float v = 0.0f;
-          if (c < cn && x < n_dst) v = md->cost[(size_t)col * n_dst + x];
-          s_cost[c * TM + lr] = v;
-        }
-      }
+      for (int d = 0; d < DIM; ++d) w = fma(cx[r][d], s_col[c * STR + 1 + d], w);
     }
-    __syncthreads();
-
-    // pass 1: chunk max per row
-    double Mc[R];
+    return w;
+  };
+  // sum of 2^(w - sh) over the staged chunk (pairs of FP32 terms, FP64 accumulation)
+  auto chunk_sum = [&](int cpad, const double* sh, double* out) {
 #pragma unroll
-    for (int r = 0; r < R; ++r) Mc[r] = -INFINITY;
-#pragma unroll 8
-    for (int c = 0; c < cpad; ++c) {
-      const double a = s_col[c * STR];
-#pragma unroll
-      for (int r = 0; r < R; ++r) {
-        double w = a;
-        if (EXPL) {
-          w = fma(ces, (double)s_cost[c * TM + (wave * R + r) * 64 + lane], w);
-        } else {
-#pragma unroll
-          for (int d = 0; d < DIM; ++d) w = fma(cx[r][d], s_col[c * STR + 1 + d], w);
-        }
-        Mc[r] = fmax(Mc[r], w);
-      }
-    }
-    double shift[R];
-#pragma unroll
-    for (int r = 0; r < R; ++r) {
-      if (Mc[r] > Mrun[r]) {
-        Srun[r] *= exp2(Mrun[r] - Mc[r]);  // 0 when Mrun = -inf and Srun = 0
-        Mrun[r] = Mc[r];
-      }
-      shift[r] = (Mrun[r] == -INFINITY) ? 0.0 : Mrun[r];
-    }
-
-    // pass 2: sum of 2^(w - max)
+    for (int r = 0; r < R; ++r) out[r] = 0.0;
 #pragma unroll 4
     for (int c = 0; c < cpad; c += 2) {
       const double a0 = s_col[c * STR];
       const double a1 = s_col[(c + 1) * STR];
 #pragma unroll
       for (int r = 0; r < R; ++r) {
-        double w0 = a0, w1 = a1;
-        if (EXPL) {
-          w0 = fma(ces, (double)s_cost[c * TM + (wave * R + r) * 64 + lane], w0);
-          w1 = fma(ces, (double)s_cost[(c + 1) * TM + (wave * R + r) * 64 + lane], w1);
-        } else {
-#pragma unroll
-          for (int d = 0; d < DIM; ++d) {
-            w0 = fma(cx[r][d], s_col[c * STR + 1 + d], w0);
-            w1 = fma(cx[r][d], s_col[(c + 1) * STR + 1 + d], w1);
-          }
-        }
+        const double w0 = wval(r, c, a0), w1 = wval(r, c + 1, a1);
         if (F64) {
-          Srun[r] += exp2(w0 - shift[r]) + exp2(w1 - shift[r]);
+          out[r] += exp2(w0 - sh[r]) + exp2(w1 - sh[r]);
         } else {
-          const float p = exp2_hw((float)(w0 - shift[r])) + exp2_hw((float)(w1 - shift[r]));
-          Srun[r] += (double)p;
+          const float p = exp2_hw((float)(w0 - sh[r])) + exp2_hw((float)(w1 - sh[r]));
+          out[r] += (double)p;
         }
       }
     }
+  };
+
+  double Mrun[R], Srun[R], shift[R];
+  for (int attempt = 0; attempt < 2; ++attempt) {
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      Mrun[r] = -INFINITY;
+      Srun[r] = 0.0;
+      shift[r] = s0[r];
+    }
+    for (int c0 = 0; c0 < it.ncols; c0 += CH) {
+      const int cn = min(CH, it.ncols - c0);
+      const int cpad = (cn + 7) & ~7;
+      __syncthreads();  // previous chunk fully consumed
+      if (threadIdx.x < cpad) {
+        double a = -INFINITY;
+        double y[DIM > 0 ? DIM : 1];
+#pragma unroll
+        for (int d = 0; d < DIM; ++d) y[d] = 0.0;
+        if (threadIdx.x < cn) {
+          const int col = it.col0 + c0 + threadIdx.x;
+          double base = (lam[col] - csrc) + lg[col];
+          if (!EXPL) {
+            double y2 = 0.0;
+#pragma unroll
+            for (int d = 0; d < DIM; ++d) {
+              y[d] = ys[(size_t)col * DIM + d];
+              y2 = fma(y[d], y[d], y2);
+            }
+            base -= y2 / eps;
+          }
+          a = kLog2e * base;
+        }
+        s_col[threadIdx.x * STR] = a;
+        if (!EXPL) {
+#pragma unroll
+          for (int d = 0; d < DIM; ++d) s_col[threadIdx.x * STR + 1 + d] = y[d];
+        }
+      }
+      if (EXPL) {
+        // cost tile, stored src-major: cost[y * n_dst + x]; coalesced over x
+        for (int c = 0; c < cpad; ++c) {
+          const int col = it.col0 + c0 + c;
+#pragma unroll
+          for (int r = 0; r < R; ++r) {
+            const int lr = r * 256 + threadIdx.x;
+            const int x = it.row0 + lr;
+            float v = 0.0f;
+            if (c < cn && x < n_dst) v = md->cost[(size_t)col * n_dst + x];
+            s_cost[c * TM + lr] = v;
+          }
+        }
+      }
+      __syncthreads();
+
+      if (one) {
+        // one pass: sum relative to the shift, chunk max alongside
+        double Mc[R], Sc[R];
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+          Mc[r] = -INFINITY;
+          Sc[r] = 0.0;
+        }
+#pragma unroll 4
+        for (int c = 0; c < cpad; c += 2) {
+          const double a0 = s_col[c * STR];
+          const double a1 = s_col[(c + 1) * STR];
+#pragma unroll
+          for (int r = 0; r < R; ++r) {
+            const double w0 = wval(r, c, a0), w1 = wval(r, c + 1, a1);
+            Mc[r] = fmax(Mc[r], fmax(w0, w1));
+            const float p = exp2_hw((float)(w0 - shift[r])) + exp2_hw((float)(w1 - shift[r]));
+            Sc[r] += (double)p;
+          }
+        }
+        int hi = 0;
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+          Mrun[r] = fmax(Mrun[r], Mc[r]);
+          if (row[r] < n_dst && Mc[r] - shift[r] > kShiftHi) hi = 1;
+        }
+        if (__syncthreads_or(hi)) {
+          // move the shift of far-exceeded rows up to the chunk max and sum again
+#pragma unroll
+          for (int r = 0; r < R; ++r) {
+            if (Mc[r] - shift[r] > kShiftHi) {
+              Srun[r] *= exp2(shift[r] - Mc[r]);
+              shift[r] = Mc[r];
+            }
+          }
+          chunk_sum(cpad, shift, Sc);
+        }
+#pragma unroll
+        for (int r = 0; r < R; ++r) Srun[r] += Sc[r];
+      } else {
+        // pass 1: chunk max per row
+        double Mc[R];
+#pragma unroll
+        for (int r = 0; r < R; ++r) Mc[r] = -INFINITY;
+#pragma unroll 8
+        for (int c = 0; c < cpad; ++c) {
+          const double a = s_col[c * STR];
+#pragma unroll
+          for (int r = 0; r < R; ++r) Mc[r] = fmax(Mc[r], wval(r, c, a));
+        }
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+          if (Mc[r] > Mrun[r]) {
+            Srun[r] *= exp2(Mrun[r] - Mc[r]);  // 0 when Mrun = -inf and Srun = 0
+            Mrun[r] = Mc[r];
+          }
+          shift[r] = (Mrun[r] == -INFINITY) ? 0.0 : Mrun[r];
+        }
+        // pass 2: sum of 2^(w - max)
+        double Sc[R];
+        chunk_sum(cpad, shift, Sc);
+#pragma unroll
+        for (int r = 0; r < R; ++r) Srun[r] += Sc[r];
+      }
+    }
+    if (!one) break;
+    // one pass: express the sum relative to the split max; rows whose max fell
+    // far below the shift send the block back through its columns in two passes
+    int lo = 0;
+#pragma unroll
+    for (int r = 0; r < R; ++r)
+      if (row[r] < n_dst && Mrun[r] > -INFINITY && Mrun[r] - shift[r] < kShiftLo) lo = 1;
+    if (__syncthreads_or(lo)) {
+      one = false;
+      continue;
+    }
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      if (Mrun[r] > -INFINITY) {
+        Srun[r] *= exp2(shift[r] - Mrun[r]);
+      } else {
+        Srun[r] = 0.0;
+      }
+    }
+    break;
   }
 
 #pragma unroll
   for (int r = 0; r < R; ++r) {
-    if (row[r] < n_dst) md->partial[(size_t)it.split * n_dst + row[r]] = make_double2(Mrun[r], Srun[r]);
+    if (row[r] < n_dst) md->partial[(size_t)row[r] * md->ns + it.split] = make_double2(Mrun[r], Srun[r]);
   }
 }
 
@@ -276,25 +383,29 @@ __global__ __launch_bounds__(kBlock) void k_msg(Tables tb, int eval_src_slot) {
 //   update fixed:  L_(j,k) = -m_{k->j}        (c_j = 0)
 //          free:   L_(j,k) = abar - m_{k->j}  (abar = mean_k m; c_j = LSE_x abar
 //                  is formed by the finalise kernel from the tile records)
-// Record: per incident edge the tile's sum of terms, then the tile's LSE of abar.
+// Record: per incident edge the tile's sum of terms, then the tile's LSE of
+// abar (max, scaled sum).
+// The loads of a group of kGroup edges (descriptors, split partials, held
+// potentials) are issued together, so a tile waits for memory once per group
+// rather than several times per edge.
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(kBlock) void k_tile(Tables tb) {
-  __shared__ double sh_rec[4][kRecChunk + 2];
+  __shared__ double sh_rec[4][kRecChunk + kRecExtra];
   const TileItem ti = tb.tiles[blockIdx.x];
   const InstState* st = tb.inst + ti.inst;
   const NodeItem nd = tb.nodes[ti.node];
   const long long t = st->t;
-  const int done = st->done;
-  if (done || ((t & 1) == 1) != (tb.colour == 0)) return;
+  if (st->done || ((t & 1) == 1) != (tb.colour == 0)) return;
   const int cur = (int)(((t - 1) >> 1) & 1), nxt = cur ^ 1;
   const MsgDesc* __restrict__ mds = tb.msgs + nd.msg0;
   const int n = nd.n, deg = nd.deg;
   const bool fixed = nd.fixed != 0;
   const int dim = mds[0].dim;
   const bool sq = mds[0].cost_kind == 0;
+  const double ieps = 1.0 / mds[0].eps;
   const double* __restrict__ xs = mds[0].supp_dst;
   const double c_old = nd.c ? nd.c[cur] : 0.0;
-  double* __restrict__ rec = nd.tpart + (size_t)(ti.row0 / kTileRows) * (deg + 2);
+  double* __restrict__ rec = nd.tpart + (size_t)(ti.row0 / kTileRows) * (deg + kRecExtra);
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int x = ti.row0 + threadIdx.x;
   const bool vx = x < n;
@@ -305,27 +416,66 @@ __global__ __launch_bounds__(kBlock) void k_tile(Tables tb) {
   // edges, the mfull scratch row beyond (star centres of high degree)
   double mreg[kRegDeg], lreg[kRegDeg];
   double asum = 0.0, qsum = 0.0;
+  auto finish = [&](const MsgDesc& md, const Merged& g, double l) -> double {
+    const double m = (g.lse2 > -INFINITY) ? kLn2 * g.lse2 - x2 * ieps : -INFINITY;
+    asum += m;
+    if (!fixed) qsum += exp(l - c_old + m);
+    return m;
+  };
 #pragma unroll
-  for (int k = 0; k < kRegDeg; ++k) {
-    mreg[k] = 0.0;
-    lreg[k] = 0.0;
-    if (k < deg && vx) {
-      const MsgDesc& md = mds[k];
-      const double m = merge_row(md, n, x, x2);
-      const double l = md.lam_dst[cur][x];
-      mreg[k] = m;
-      lreg[k] = l;
-      asum += m;
-      if (!fixed) qsum += exp(l - c_old + m);
+  for (int g0 = 0; g0 < kRegDeg; g0 += kGroup) {
+    const double2* P[kGroup];
+    const double* Lc[kGroup];
+    int NS[kGroup];
+#pragma unroll
+    for (int u = 0; u < kGroup; ++u) {
+      const bool on = g0 + u < deg;
+      P[u] = on ? mds[g0 + u].partial : nullptr;
+      Lc[u] = on ? mds[g0 + u].lam_dst[cur] : nullptr;
+      NS[u] = on ? mds[g0 + u].ns : 0;
+    }
+    double2 pv[kGroup][kNsReg];
+    double lv[kGroup];
+#pragma unroll
+    for (int u = 0; u < kGroup; ++u) {
+      const bool on = vx && g0 + u < deg;
+      lv[u] = on ? Lc[u][x] : 0.0;
+#pragma unroll
+      for (int s2 = 0; s2 < kNsReg; ++s2)
+        pv[u][s2] = (on && s2 < NS[u]) ? P[u][(size_t)x * NS[u] + s2] : make_double2(-INFINITY, 0.0);
+    }
+#pragma unroll
+    for (int u = 0; u < kGroup; ++u) {
+      const int k = g0 + u;
+      mreg[k] = 0.0;
+      lreg[k] = lv[u];
+      if (k < deg && vx) {
+        Merged g;
+        if (NS[u] <= kNsReg) {
+          double Mx = -INFINITY;
+#pragma unroll
+          for (int s2 = 0; s2 < kNsReg; ++s2) Mx = fmax(Mx, pv[u][s2].x);
+          double S = 0.0;
+          if (Mx > -INFINITY) {
+#pragma unroll
+            for (int s2 = 0; s2 < kNsReg; ++s2) {
+              const double2 q = pv[u][s2];
+              if (q.y > 0.0) S += (q.x == Mx) ? q.y : q.y * exp2(q.x - Mx);
+            }
+          }
+          g = {(S > 0.0) ? Mx + log2(S) : -INFINITY, Mx, S};
+        } else {
+          g = merge_splits(P[u] + (size_t)x * NS[u], NS[u]);
+        }
+        mreg[k] = finish(mds[k], g, lv[u]);
+      }
     }
   }
   for (int k = kRegDeg; k < deg; ++k) {
     if (!vx) continue;
     const MsgDesc& md = mds[k];
-    const double m = merge_row(md, n, x, x2);
-    md.mfull[x] = m;
-    asum += m;
-    if (!fixed) qsum += exp(md.lam_dst[cur][x] - c_old + m);
+    const Merged g = merge_splits(md.partial + (size_t)x * md.ns, md.ns);
+    md.mfull[x] = finish(md, g, md.lam_dst[cur][x]);
   }
   const double a = vx ? asum / deg : -INFINITY;
   const double qb = qsum / deg;
@@ -406,7 +556,7 @@ __global__ __launch_bounds__(kBlock) void k_finalize(Tables tb) {
   double esum = 0.0, emax = 0.0;
   for (int i = threadIdx.x; i < cnt; i += kBlock) {
     const NodeItem nd = tb.nodes[i0 + i];
-    const int deg = nd.deg, stride = deg + 2, tiles = nd.tiles;
+    const int deg = nd.deg, stride = deg + kRecExtra, tiles = nd.tiles;
     const double* __restrict__ tp = nd.tpart;
     for (int k = 0; k < deg; ++k) {
       double e = 0.0;
@@ -460,7 +610,7 @@ __global__ __launch_bounds__(kBlock) void k_node_eval(Tables tb, int slot) {
     double qsum = 0.0;
     for (int k = 0; k < deg; ++k) {
       const MsgDesc& md = mds[k];
-      const double m = merge_row(md, n, x, x2);
+      const double m = merge_row(md, x, x2);
       md.mfull[x] = m;
       qsum += exp(md.lam_dst[slot][x] - cj + lgx + m);
     }

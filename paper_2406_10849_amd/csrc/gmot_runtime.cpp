@@ -330,7 +330,7 @@ static int build_plan(gmot_ctx* ctx, const std::vector<gmot_problem*>& probs, in
   for (int c = 0; c < 2; ++c)
     for (const NodeItem& nd : pl->nodes[c]) {
       tpart_off[c].push_back(tpart_total);
-      tpart_total += (int64_t)nd.tiles * (nd.deg + 2);
+      tpart_total += (int64_t)nd.tiles * (nd.deg + kRecExtra);
     }
   for (int c = 0; c < 2; ++c) {
     pl->stats.blocks[c] = 0;
@@ -492,7 +492,7 @@ static int get_graph(Plan* pl, bool fp64, bool per_edge, int start, int k, bool 
 // paper's loop never stops before the second half-sweep, and the FP64 verify
 // phase must first make one class exact in FP64.
 static int run_plan(Plan* pl, const gmot_opts* o, gmot_result* outs, const std::vector<char>* active = nullptr,
-                    int64_t min_updates = 0) {
+                    int64_t min_updates = 0, int64_t stall_window = 0, std::vector<char>* stalled = nullptr) {
   hipStream_t s = pl->ctx->stream;
   const size_t n = pl->probs.size();
   int parity = -1;
@@ -517,6 +517,11 @@ static int run_plan(Plan* pl, const gmot_opts* o, gmot_result* outs, const std::
     st.checked_t = 0;
     st.counter = 0;
     st.clk_start = st.clk_stop = 0;
+    // the first computation of every message in this call takes two passes
+    st.onepass_from = o->msg_passes == GMOT_PASSES_TWO ? INT64_MAX : p->t + 2;
+    st.best_err = INFINITY;
+    st.best_t = p->t;
+    st.stall_window = stall_window;
     st.done = kRunning;
     if (p->E == 0) {  // single node: nothing to scale
       st.done = kConverged;
@@ -613,7 +618,8 @@ static int run_plan(Plan* pl, const gmot_opts* o, gmot_result* outs, const std::
       for (size_t i = 0; i < n; ++i) {
         const InstState& st = pl->inst[i];
         if (pl->probs[i]->E == 0) continue;
-        const int64_t abs_last = st.done == kConverged ? st.checked_t : st.done == kNonFinite ? st.t + 1 : st.t - 1;
+        const int64_t abs_last = (st.done == kConverged || st.done == kStalled) ? st.checked_t
+                                 : st.done == kNonFinite ? st.t + 1 : st.t - 1;
         last[i] = abs_last - t_start[i];
         last_any = std::max(last_any, last[i]);
       }
@@ -639,6 +645,7 @@ static int run_plan(Plan* pl, const gmot_opts* o, gmot_result* outs, const std::
     p->t = st.t;
     ++p->version;
     r.status = st.done == kConverged ? GMOT_CONVERGED : st.done == kNonFinite ? GMOT_NONFINITE : GMOT_NOT_CONVERGED;
+    if (stalled) (*stalled)[i] = st.done == kStalled;
     r.steps = st.updates;
     r.t = st.t;
     r.err_sum = st.err_sum;
@@ -649,24 +656,30 @@ static int run_plan(Plan* pl, const gmot_opts* o, gmot_result* outs, const std::
 }
 
 // FP32-core solves judge convergence in FP64: the FP32-core loop stops at
-// kVerifyMargin * tol, then FP64 half-sweeps run until the FP64 stopping sum
-// is <= tol (the FP32 exponentials leave a noise floor of a few 1e-9 per edge
-// on the sum, which the margin absorbs).
+// kVerifyMargin * tol, or when its stopping sum has not reached a new minimum
+// for kStallWindow half-sweeps (the FP32 exponentials leave a noise floor that
+// can lie above a small tol), and FP64 half-sweeps then run from that state
+// until the FP64 stopping sum is <= tol, within the remaining step budget.
+// On large trees the FP32-core sum can read below the FP64 sum of the same
+// state (the iteration settles at the fixed point of the rounded map), which
+// the FP64 phase corrects.
 constexpr double kVerifyMargin = 0.8;
-constexpr int64_t kVerifySteps = 256;
+constexpr int64_t kStallWindow = 128;
 
 static int solve_plan(Plan* pl, const gmot_opts* o, gmot_result* outs) {
   const size_t n = pl->probs.size();
   if (o->precision != GMOT_PREC_FP32CORE || o->skip_verify) return run_plan(pl, o, outs);
   gmot_opts o1 = *o;
   o1.tol = o->tol * kVerifyMargin;
-  int rc = run_plan(pl, &o1, outs);
+  std::vector<char> stalled(n, 0);
+  // tol = 0 asks for exactly max_steps half-sweeps (or an exact fixed point): no stall test
+  int rc = run_plan(pl, &o1, outs, nullptr, 0, o->tol > 0.0 ? kStallWindow : 0, &stalled);
   if (rc) return rc;
   std::vector<char> active(n, 0);
   bool any = false;
-  int64_t budget = kVerifySteps;
+  int64_t budget = o->max_steps;
   for (size_t i = 0; i < n; ++i) {
-    active[i] = outs[i].status == GMOT_CONVERGED && pl->probs[i]->E > 0;
+    active[i] = (outs[i].status == GMOT_CONVERGED || stalled[i]) && pl->probs[i]->E > 0;
     any = any || active[i];
     if (active[i]) budget = std::min<int64_t>(budget, std::max<int64_t>(1, o->max_steps - outs[i].steps));
   }
@@ -995,6 +1008,8 @@ static int validate_opts(const gmot_opts* o) {
     return fail(GMOT_EINVAL, "unknown precision");
   if (o->schedule != GMOT_SCHED_LAYER && o->schedule != GMOT_SCHED_PER_EDGE)
     return fail(GMOT_EINVAL, "unknown schedule");
+  if (o->msg_passes != GMOT_PASSES_AUTO && o->msg_passes != GMOT_PASSES_TWO)
+    return fail(GMOT_EINVAL, "unknown msg_passes");
   return GMOT_OK;
 }
 

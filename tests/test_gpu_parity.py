@@ -293,3 +293,24 @@ def test_per_edge_schedule_gives_identical_iterates(ctx):
     rb = b.solve(tol=0.0, max_steps=15, schedule="per_edge")
     assert ra["steps"] == rb["steps"] == 15
     assert np.array_equal(a.potentials(), b.potentials())
+
+
+def test_one_pass_matches_two_pass(ctx):
+    """The one-pass message sums (shifted by the previous row max) and the
+    two-pass sums give the same FP32-core iterates within the FP32-core
+    tolerance, and both match the oracle after the same half-sweeps."""
+    cases = [make_chain(n_nodes=12, n=200, eps=1e-3),
+             make_random_tree(n_nodes=20, n_lo=100, n_hi=600, instance=5)]
+    for p in cases:
+        g1, g2 = gpu_problem(ctx, p), gpu_problem(ctx, p)
+        steps = 60
+        r1 = g1.solve(tol=0.0, max_steps=steps, passes="auto")
+        r2 = g2.solve(tol=0.0, max_steps=steps, passes="two")
+        assert r1["steps"] == r2["steps"] == steps
+        o = TreeOracle(p)
+        o.run_fixed(steps)
+        eo = o.evaluate()
+        for g in (g1, g2):
+            assert abs(g.evaluate()["dual"] - eo["dual"]) <= 1e-6 * eo["scale"]
+        for e in range(0, p.n_edges, 3):
+            assert np.max(np.abs(g1.coupling(e) - g2.coupling(e))) <= 1e-6
