@@ -36,7 +36,7 @@ METRIC = "edge-iterations/s and time-to-1e-6 marginal error; plain vs batched+wa
 VALU_SLOTS_PER_S = 256 * 64 * 2.4e9
 # MI355X HBM3E peak, GB/s
 HBM_PEAK_GBS = 8000.0
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_msg_chain_traffic.txt")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_node_chain32_traffic.txt")
 KERNEL_SRC = os.path.join(ROOT, "paper_2406_10849_amd", "csrc", "gmot_kernels.hip")
 
 
@@ -61,7 +61,7 @@ def kernel_sha() -> str:
 
 
 def measured_traffic():
-    """HBM bytes per message-kernel launch from the committed rocprofv3 PMC
+    """HBM bytes per node-kernel launch from the committed rocprofv3 PMC
     summary, valid only for the kernel source it was taken on."""
     if not os.path.exists(TRAFFIC_FILE):
         return None
@@ -148,14 +148,14 @@ def bench_tree(ctx, tol: float, half_sweeps: int) -> dict:
            "pairs_per_half_sweep": p.pairs_per_tstep()}
     g = Problem(ctx, p)
     g.autotune()
-    for sched in ("layer", "per_edge"):
+    for sched in ("layer", "per_node"):
         g.solve(tol=tol, max_steps=200000, schedule=sched)     # graph capture outside the timing
         t0 = time.perf_counter()
         r = g.solve(tol=tol, max_steps=200000, schedule=sched)
         dt = time.perf_counter() - t0
         assert r["status"] == "converged", f"tree ({sched}) did not converge"
         out[sched] = {"s": dt, "half_sweeps": r["t"], "edge_iterations_per_s": p.n_edges * r["t"] / dt}
-    out["layer_vs_plain_speedup"] = out["per_edge"]["s"] / out["layer"]["s"]
+    out["layer_vs_plain_speedup"] = out["per_node"]["s"] / out["layer"]["s"]
     g.close()
 
     cost = []
@@ -181,7 +181,7 @@ def bench_tree(ctx, tol: float, half_sweeps: int) -> dict:
         "tiles": tuned, "half_sweeps_timed": st["msg_launches"], "pairs_per_launch": pairs,
         "avg_launch_ms": avg_ms, "half_sweep_avg_ms": st["sweep_ms"] / max(st["msg_launches"], 1),
         "roofline": {"bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": gbs / HBM_PEAK_GBS, "traffic": None, "kernel": "k_msg<explicit>",
+                     "frac": gbs / HBM_PEAK_GBS, "traffic": None, "kernel": "k_node<explicit cost>",
                      "bytes_per_pair": 4}}
     g.close()
     return out
@@ -332,7 +332,7 @@ def main() -> int:
                   "dual": last_ev["dual"], "primal": last_ev["primal"], "transport": last_ev["transport"]},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": peak, "unit": "Gpair/s",
                      "frac": achieved / peak, "traffic": traffic,
-                     "kernel": "k_msg", "avg_launch_ms": avg_ms, "pairs_per_launch": pairs_per_launch,
+                     "kernel": "k_node", "avg_launch_ms": avg_ms, "pairs_per_launch": pairs_per_launch,
                      "launches_timed": st["msg_launches"],
                      "half_sweep_avg_ms": st["sweep_ms"] / max(st["msg_launches"], 1)},
     }

@@ -113,8 +113,9 @@ typedef struct {
                            is <= tol, so convergence is judged in FP64.  1: stop on
                            the FP32-core sum <= tol.                                 */
   int32_t schedule;     /* GMOT_SCHED_LAYER (default): every message of the class being
-                           updated in one launch; GMOT_SCHED_PER_EDGE: the same
-                           half-sweep with one launch per message (same iterates)    */
+                           updated in one launch; GMOT_SCHED_PER_NODE: the same
+                           half-sweep with one launch per node, issued node after
+                           node (same iterates)                                      */
   int32_t msg_passes;   /* FP32-core message sums.  GMOT_PASSES_AUTO (0, default): two
                            passes (row max, then sum) for the first two half-sweeps of
                            the call, then one pass shifted by each row's max from the
@@ -127,16 +128,17 @@ typedef struct {
 #define GMOT_PASSES_TWO   2
 
 #define GMOT_SCHED_LAYER     0
-#define GMOT_SCHED_PER_EDGE  1
+#define GMOT_SCHED_PER_NODE  1
 
 /* Kernel timing accumulated by solves with opts.timing = 1 (since the last
  * reset).  Only half-sweeps that did work for at least one instance count. */
 typedef struct {
-  double  msg_ms;          /* summed duration of the message-kernel stages (ms), each the
-                              mean of 4 back-to-back repeats of the stage (it only reads
-                              the state), so event overhead is not counted              */
-  double  sweep_ms;        /* summed duration of whole half-sweeps: message, tile and
-                              finalise kernels (ms)                                    */
+  double  msg_ms;          /* summed duration of the node-kernel stages (messages, terms
+                              and update; ms), each the mean of 4 back-to-back repeats of
+                              the stage (each repeat rewrites the same slots from the
+                              same state), so event overhead is not counted             */
+  double  sweep_ms;        /* summed duration of whole half-sweeps: node stage and
+                              finalise kernel (ms)                                     */
   int64_t msg_launches;    /* half-sweeps timed                                         */
   double  msg_pairs;       /* (x, y) pairs those half-sweeps processed                  */
   int64_t graph_launches;  /* graph replays issued (timed or not)                        */
@@ -295,15 +297,15 @@ int  gmot_mlp_warm_start(gmot_mlp* m, gmot_problem* const* probs, int32_t count,
                          float out_scale, int32_t* rejected);
 
 /* ---- tile autotuning ------------------------------------------------------------ */
-/* Time candidate message-kernel tilings (rows per lane 1 or 2, and the number of
- * blocks a half-sweep is split into through column splits) by the device time
- * of a few real FP32-core half-sweeps (message, tile and finalise kernels) run
- * from a snapshot of the held state, which is restored afterwards, and keep
- * the fastest plan; best_ms is that half-sweep time.
+/* Time the candidate node-kernel block shapes (2, 4 or 8 waves per 64-row
+ * tile; the waves split each edge's source columns) by the device time of a
+ * few real FP32-core half-sweeps (node stage and finalise kernel) run from a
+ * snapshot of the held state, which is restored afterwards, and keep the
+ * fastest plan; best_ms is that half-sweep time.
  * The choice is cached in the context under the instances' shapes, so later
  * problems or batches of the same shapes start with it.  Outputs may be NULL. */
-int  gmot_problem_autotune(gmot_problem* p, int32_t* rows_per_lane, int32_t* target_blocks, double* best_ms);
-int  gmot_batch_autotune(gmot_batch* b, int32_t* rows_per_lane, int32_t* target_blocks, double* best_ms);
+int  gmot_problem_autotune(gmot_problem* p, int32_t* waves_per_block, double* best_ms);
+int  gmot_batch_autotune(gmot_batch* b, int32_t* waves_per_block, double* best_ms);
 
 /* ---- diagnostics ----------------------------------------------------------- */
 /* Copy out (and, if reset != 0, clear) the kernel timing of a problem's own
@@ -312,9 +314,9 @@ int  gmot_problem_stats(gmot_problem* p, gmot_stats* out, int32_t reset);
 int  gmot_batch_stats(gmot_batch* b, gmot_stats* out, int32_t reset);
 const char* gmot_strerror(int code);
 const char* gmot_last_error(void);
-/* Message-kernel tile shape of the most recent plan: rows per block, column
- * splits chosen for the largest message, and blocks per half-sweep per class. */
-int  gmot_last_tiles(int32_t* rows_per_block, int32_t* max_splits, int32_t* blocks_c0, int32_t* blocks_c1);
+/* Node-kernel shape of the most recent plan: rows per block (64), waves per
+ * block, and blocks per half-sweep for each class. */
+int  gmot_last_tiles(int32_t* rows_per_block, int32_t* waves_per_block, int32_t* blocks_c0, int32_t* blocks_c1);
 
 #ifdef __cplusplus
 }

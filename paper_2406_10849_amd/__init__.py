@@ -21,7 +21,7 @@ from ._lib import (GMOT_OK, GMOT_EINVAL, GMOT_EMARGINAL, GMOT_ENOMEM, GMOT_EDEVI
 
 STATUS_NAMES = {GMOT_CONVERGED: "converged", GMOT_NOT_CONVERGED: "not_converged", GMOT_NONFINITE: "nonfinite"}
 PRECISIONS = {"fp32core": GMOT_PREC_FP32CORE, "fp64": GMOT_PREC_FP64}
-SCHEDULES = {"layer": 0, "per_edge": 1}
+SCHEDULES = {"layer": 0, "per_node": 1}
 PASSES = {"auto": 0, "two": 2}
 
 
@@ -150,12 +150,12 @@ class Problem:
 
     @staticmethod
     def _autotune(fn, h) -> dict:
-        r, t, ms = C.c_int32(), C.c_int32(), C.c_double()
-        _check(fn(h, C.byref(r), C.byref(t), C.byref(ms)), "gmot_*_autotune")
-        return {"rows_per_lane": r.value, "target_blocks": t.value, "ms_per_eval_sweep": ms.value}
+        w, ms = C.c_int32(), C.c_double()
+        _check(fn(h, C.byref(w), C.byref(ms)), "gmot_*_autotune")
+        return {"waves_per_block": w.value, "ms_per_half_sweep": ms.value}
 
     def autotune(self) -> dict:
-        """Pick the fastest message-kernel tiling for this problem (state untouched)."""
+        """Pick the fastest node-kernel block shape for this problem (state untouched)."""
         return self._autotune(self._lib.gmot_problem_autotune, self._h)
 
     @staticmethod
@@ -358,7 +358,8 @@ def last_tiles() -> dict:
     lib = _lib.load()
     v = [C.c_int32() for _ in range(4)]
     lib.gmot_last_tiles(*[C.byref(x) for x in v])
-    return {"rows_per_block": v[0].value, "max_splits": v[1].value, "blocks_c0": v[2].value, "blocks_c1": v[3].value}
+    return {"rows_per_block": v[0].value, "waves_per_block": v[1].value, "blocks_c0": v[2].value,
+            "blocks_c1": v[3].value}
 
 
 __all__ = ["Context", "Problem", "Batch", "MLP", "GmotError", "last_tiles", "star_features", "star_targets",

@@ -24,14 +24,14 @@
 // normaliser c_j = LSE_x abar is written once all tiles are done (constrained
 // nodes have c_j = 0).  c_j is double-buffered like the potentials.
 //
-// One half-sweep is three stream-ordered launches: the message kernel (one
-// block per (row tile, column split) of a message, per support dimension), the
-// tile kernel (one block per 256-row tile of a node of the class: merge of the
-// column splits, stopping-sum terms of the state before the update, update of
-// L, and a tile record), and the finalise kernel (one block per instance: c_j
-// from the tile records, the stopping sum and the stop decision).  Kernel
-// boundaries make each stage's writes visible to the next, so no block waits
-// on, or fences for, another block.
+// One half-sweep is two stream-ordered launches: the node kernel (one block
+// per 64-row tile of every node of the class, per support dimension: the
+// messages of all incident edges for those rows, the stopping-sum terms of the
+// state before the update, the update of L, and a tile record) and the
+// finalise kernel (one block per instance: c_j from the tile records, the
+// stopping sum and the stop decision).  The kernel boundary makes the tiles'
+// writes visible to the finalise kernel, so no block waits on, or fences for,
+// another block.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -54,8 +54,10 @@ struct MsgDesc {
   const double* c_src;       // c_k slots [2] (NULL: constrained source, c = 0)
   const double* lg_src;      // log gamma_k, [n_src]
   double* lam_dst[2];        // stored L_(j,k) slots, [n_dst]
-  double2* partial;          // [n_dst * ns]: per row its ns column splits, each (split max M, sum of
-                             // 2^(w - M)); M of the previous computation is the next one-pass shift
+  double2* partial;          // [n_dst * ns]: evaluation pass, per row its ns column splits, each
+                             // (split max M, sum of 2^(w - M))
+  double* wmax;              // [kMaxWaves * n_dst]: node kernel, wave-major, per row the max of
+                             // each wave's column range at the last computation (next shift)
   double* mfull;             // merged message m_{k->j}, [n_dst], natural log
   const float* cost;         // explicit cost stored src-major: cost[y * n_dst + x] = C_(j,k)(x, y)
   int32_t n_dst, n_src, ns, inst;
@@ -69,12 +71,13 @@ struct K1Item {
   int32_t msg, row0, col0, ncols, split, inst, pad0, pad1;
 };
 
-constexpr int kTileRows = 256;  // rows per block of the tile kernel
+constexpr int kNodeRows = 64;   // rows per block of the node kernel (one per lane)
+constexpr int kMaxWaves = 8;    // waves per node-kernel block: 2, 4 or 8
 constexpr int kRecExtra = 2;    // tile record entries after the per-edge terms
 
 // One node of the class being updated; its deg incoming messages are
 // msgs[msg0 .. msg0 + deg) in ascending neighbour order.  Its rows form
-// `tiles` tiles of kTileRows; tile records (deg stopping-sum terms, then the
+// `tiles` tiles of kNodeRows; tile records (deg stopping-sum terms, then the
 // tile's LSE max and scaled sum of abar) start at tpart + tile * (deg + kRecExtra).
 struct NodeItem {
   int32_t inst, node, n, deg;
@@ -87,7 +90,7 @@ struct NodeItem {
   double* tpart;             // tile records
 };
 
-// One block of the tile kernel: rows [row0, row0 + kTileRows) of node item
+// One block of the node kernel: rows [row0, row0 + kNodeRows) of node item
 // `node` of instance `inst` (carried here so the instance state and the node
 // item load in parallel).
 struct TileItem {
@@ -160,9 +163,10 @@ struct RoundNode {
 };
 
 // ---- launch wrappers (defined in gmot_kernels.hip) ----
-hipError_t launch_msg(const Tables& tb, int n_items, int dim, int rows_per_lane, bool fp64, int eval_src_slot,
-                      hipStream_t s);
-hipError_t launch_tile(const Tables& tb, int n_tiles, hipStream_t s);
+// FP64 evaluation messages from potential slot src_slot of the source class
+hipError_t launch_msg(const Tables& tb, int n_items, int dim, int rows_per_lane, int src_slot, hipStream_t s);
+// node kernel over n_tiles tiles of one class and support-dimension group (dim 0: explicit cost)
+hipError_t launch_node(const Tables& tb, int n_tiles, int dim, int waves, bool fp64, hipStream_t s);
 hipError_t launch_finalize(const Tables& tb, int n_inst, hipStream_t s);
 hipError_t launch_node_eval(const Tables& tb, int n_nodes, int slot, hipStream_t s);
 // dst[i] = src[i] - (c ? *c : 0) over segments (potential read-back on the device)
@@ -205,7 +209,7 @@ struct gmot_ctx {
   hipStream_t stream = nullptr;
   bool own_stream = false;
   double clk_hz = 1.0e8;
-  std::map<uint64_t, std::pair<int, int>> tuned;  // shape key -> (rows per lane, target blocks)
+  std::map<uint64_t, int> tuned;  // shape key -> waves per node-kernel block
   void* scratch = nullptr;                         // small tables of the warm-start calls
   size_t scratch_size = 0;
 };

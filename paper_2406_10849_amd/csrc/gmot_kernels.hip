@@ -1,21 +1,20 @@
 // gfx950 kernels of the bipartite iterative-scaling hot path.
 //
-//   k_msg<..., ITER>  -- message log-sum-exp m_{k->j} over a (row tile, column
-//              split) of one message (the K u products of Theorem
-//              tree_dual_var, eq. q).
-//   k_tile     -- per 256-row tile of a node of the class: merge of the column
-//              splits, stopping-sum terms of the state before the update
-//              (Algorithm tree_local_reg; Lemma f_upper_bound_tree for the
-//              arithmetic mean) and the update of eq. bipartite_tree_updates1/2
-//              in its closed form (Proposition equi).
+//   k_node     -- one half-sweep's work for a 64-row tile of a node of the
+//                 class being updated: the message log-sum-exps of every
+//                 incident edge (the K u products of Theorem tree_dual_var,
+//                 eq. q), the stopping-sum terms of the state before the update
+//                 (Algorithm tree_local_reg; Lemma f_upper_bound_tree for the
+//                 arithmetic mean) and the update of eq. bipartite_tree_updates1/2
+//                 in its closed form (Prop. equi).
 //   k_finalize -- per instance: node normalisers, stopping sum, stop decision.
-//   k_msg<..., EVAL>  -- the same message LSE with given slots, no update.
+//   k_msg             -- FP64 message LSE with given slots (evaluation).
 //   k_node_eval       -- evaluation: merge, stopping-sum terms, <Lam, mu> / rho.
 //   k_pairs           -- FP64 transport / entropy / mass sums of every plan
 //                        (eq. bi-marginal_B_sol, eq. ot_graph_pairwise_mass).
 //   k_coupling        -- one plan written out in FP64.
 //
-// Arithmetic contract of the FP32-core message kernel: FP64 potentials, FP64
+// Arithmetic contract of the FP32-core node kernel: FP64 potentials, FP64
 // exponent arguments (w - row max), FP32 v_exp_f32 on the reduced argument,
 // pairs of FP32 terms added in FP32 and accumulated in FP64, FP64 merge, log,
 // stopping-sum terms and node normalisers.
@@ -27,10 +26,6 @@ namespace gmot {
 
 namespace {
 
-constexpr int kRegDeg = 8;     // incident edges whose messages the tile kernel keeps in registers
-constexpr int kRecChunk = 64;  // tile records reduced per block barrier
-constexpr int kGroup = 4;      // edges whose loads the tile kernel issues together
-constexpr int kNsReg = 8;      // column splits per edge held in registers by the tile kernel
 
 __device__ inline double wave_sum(double v) {
 #pragma unroll
@@ -129,31 +124,15 @@ __device__ void decide(const Tables& tb, InstState* st, long long t, double E, d
 }  // namespace
 
 // ---------------------------------------------------------------------------
-// Message log-sum-exp.  Block = 4 waves; lane l of wave w owns rows
-// row0 + (w*R + r)*64 + l, r < R.  Columns are streamed through LDS in chunks.
-// Output per row and column split: (M, sum 2^(w - M)) with M the split's max.
-//
-// Two passes (first computations, FP64 path, evaluation): per chunk, pass 1
-// finds the row max and pass 2 sums 2^(w - max); the running sum is rescaled
-// when the max grows.
-// One pass (FP32-core iteration from the third half-sweep of a call on): the
-// shift s is the max of the same row and column split at the previous
-// computation of the message (still in the partial buffer), and one pass sums
-// 2^(w - s) while tracking the max.  Any finite s gives the
-// exact sum while the terms stay in FP32 range; a chunk whose max exceeds s by
-// more than kShiftHi moves s up to that max and is summed again, and if a
-// row's max ends more than kShiftLo below s (its top terms would lose FP32
-// precision) the block repeats its columns in two passes.  Both decisions are
-// block-uniform.  Near convergence s differs from the max by the drift of the
-// iteration, so the dominant terms' arguments are nearly exact, as in two passes.
-// ITER: slots come from the instance counter; finished instances (or those
-// whose next half-sweep updates the other class) return at entry.
+// Evaluation message kernel (FP64, two passes).  Block = 4 waves; lane l of
+// wave w owns rows row0 + (w*R + r)*64 + l, r < R; columns stream through LDS
+// in chunks.  Per chunk, pass 1 finds the row max and pass 2 sums 2^(w - max);
+// the running sum is rescaled when the max grows.  Output per row and column
+// split: (M, sum 2^(w - M)), M the split's max, merged by the evaluation node
+// pass.  The potentials are read from the given slot of the source class.
 // ---------------------------------------------------------------------------
-constexpr double kShiftHi = 96.0;
-constexpr double kShiftLo = -96.0;
-
-template <int DIM, int R, bool F64, bool EXPL, bool ITER>
-__global__ __launch_bounds__(kBlock) void k_msg(Tables tb, int eval_src_slot) {
+template <int DIM, int R, bool EXPL>
+__global__ __launch_bounds__(kBlock) void k_msg(Tables tb, int src_slot) {
   constexpr int CH = EXPL ? 32 : kChunk;            // columns per LDS chunk
   constexpr int STR = EXPL ? 1 : (DIM == 1 ? 2 : 4); // doubles per staged column
   constexpr int TM = 256 * R;                        // rows per block
@@ -162,15 +141,6 @@ __global__ __launch_bounds__(kBlock) void k_msg(Tables tb, int eval_src_slot) {
 
   const K1Item it = tb.items[blockIdx.x];
   const MsgDesc* __restrict__ md = tb.msgs + it.msg;
-  int src_slot = eval_src_slot;
-  bool one = false;
-  if (ITER) {
-    const InstState* st = tb.inst + it.inst;
-    const long long t = st->t;
-    if (st->done || ((t & 1) == 1) != (tb.colour == 0)) return;
-    src_slot = (int)((t >> 1) & 1);
-    one = !F64 && t >= st->onepass_from;
-  }
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int n_dst = md->n_dst;
   const double eps = md->eps;
@@ -183,21 +153,16 @@ __global__ __launch_bounds__(kBlock) void k_msg(Tables tb, int eval_src_slot) {
 
   int row[R];
   double cx[R][DIM];
-  double s0[R];  // one-pass shift from the previous computation
+  double Mrun[R], Srun[R];
 #pragma unroll
   for (int r = 0; r < R; ++r) {
     row[r] = it.row0 + (wave * R + r) * 64 + lane;
     const bool v = row[r] < n_dst;
 #pragma unroll
     for (int d = 0; d < DIM; ++d) cx[r][d] = (v && !EXPL) ? cxs * md->supp_dst[(size_t)row[r] * DIM + d] : 0.0;
-    s0[r] = 0.0;
-    if (one && v) {
-      const double m = md->partial[(size_t)row[r] * md->ns + it.split].x;
-      s0[r] = isfinite(m) ? m : 0.0;
-    }
+    Mrun[r] = -INFINITY;
+    Srun[r] = 0.0;
   }
-
-  // w(x, y) of local row slot (wave*R + r) and staged column c
   auto wval = [&](int r, int c, double a) -> double {
     double w = a;
     if (EXPL) {
@@ -208,167 +173,58 @@ __global__ __launch_bounds__(kBlock) void k_msg(Tables tb, int eval_src_slot) {
     }
     return w;
   };
-  // sum of 2^(w - sh) over the staged chunk (pairs of FP32 terms, FP64 accumulation)
-  auto chunk_sum = [&](int cpad, const double* sh, double* out) {
-#pragma unroll
-    for (int r = 0; r < R; ++r) out[r] = 0.0;
-#pragma unroll 4
-    for (int c = 0; c < cpad; c += 2) {
-      const double a0 = s_col[c * STR];
-      const double a1 = s_col[(c + 1) * STR];
-#pragma unroll
-      for (int r = 0; r < R; ++r) {
-        const double w0 = wval(r, c, a0), w1 = wval(r, c + 1, a1);
-        if (F64) {
-          out[r] += exp2(w0 - sh[r]) + exp2(w1 - sh[r]);
-        } else {
-          const float p = exp2_hw((float)(w0 - sh[r])) + exp2_hw((float)(w1 - sh[r]));
-          out[r] += (double)p;
-        }
-      }
-    }
-  };
 
-  double Mrun[R], Srun[R], shift[R];
-  for (int attempt = 0; attempt < 2; ++attempt) {
+  for (int c0 = 0; c0 < it.ncols; c0 += CH) {
+    const int cn = min(CH, it.ncols - c0);
+    __syncthreads();  // previous chunk fully consumed
+    if (threadIdx.x < cn) {
+      const int col = it.col0 + c0 + threadIdx.x;
+      double base = (lam[col] - csrc) + lg[col];
+      if (!EXPL) {
+        double y2 = 0.0;
 #pragma unroll
-    for (int r = 0; r < R; ++r) {
-      Mrun[r] = -INFINITY;
-      Srun[r] = 0.0;
-      shift[r] = s0[r];
+        for (int d = 0; d < DIM; ++d) {
+          const double y = ys[(size_t)col * DIM + d];
+          s_col[threadIdx.x * STR + 1 + d] = y;
+          y2 = fma(y, y, y2);
+        }
+        base -= y2 / eps;
+      }
+      s_col[threadIdx.x * STR] = kLog2e * base;
     }
-    for (int c0 = 0; c0 < it.ncols; c0 += CH) {
-      const int cn = min(CH, it.ncols - c0);
-      const int cpad = (cn + 7) & ~7;
-      __syncthreads();  // previous chunk fully consumed
-      if (threadIdx.x < cpad) {
-        double a = -INFINITY;
-        double y[DIM > 0 ? DIM : 1];
-#pragma unroll
-        for (int d = 0; d < DIM; ++d) y[d] = 0.0;
-        if (threadIdx.x < cn) {
-          const int col = it.col0 + c0 + threadIdx.x;
-          double base = (lam[col] - csrc) + lg[col];
-          if (!EXPL) {
-            double y2 = 0.0;
-#pragma unroll
-            for (int d = 0; d < DIM; ++d) {
-              y[d] = ys[(size_t)col * DIM + d];
-              y2 = fma(y[d], y[d], y2);
-            }
-            base -= y2 / eps;
-          }
-          a = kLog2e * base;
-        }
-        s_col[threadIdx.x * STR] = a;
-        if (!EXPL) {
-#pragma unroll
-          for (int d = 0; d < DIM; ++d) s_col[threadIdx.x * STR + 1 + d] = y[d];
-        }
-      }
-      if (EXPL) {
-        // cost tile, stored src-major: cost[y * n_dst + x]; coalesced over x
-        for (int c = 0; c < cpad; ++c) {
-          const int col = it.col0 + c0 + c;
-#pragma unroll
-          for (int r = 0; r < R; ++r) {
-            const int lr = r * 256 + threadIdx.x;
-            const int x = it.row0 + lr;
-            float v = 0.0f;
-            if (c < cn && x < n_dst) v = md->cost[(size_t)col * n_dst + x];
-            s_cost[c * TM + lr] = v;
-          }
-        }
-      }
-      __syncthreads();
-
-      if (one) {
-        // one pass: sum relative to the shift, chunk max alongside
-        double Mc[R], Sc[R];
+    if (EXPL) {
+      // cost tile, stored src-major: cost[y * n_dst + x]; coalesced over x
+      for (int c = 0; c < cn; ++c) {
+        const int col = it.col0 + c0 + c;
 #pragma unroll
         for (int r = 0; r < R; ++r) {
-          Mc[r] = -INFINITY;
-          Sc[r] = 0.0;
+          const int lr = r * 256 + threadIdx.x;
+          const int x = it.row0 + lr;
+          s_cost[c * TM + lr] = x < n_dst ? md->cost[(size_t)col * n_dst + x] : 0.0f;
         }
-#pragma unroll 4
-        for (int c = 0; c < cpad; c += 2) {
-          const double a0 = s_col[c * STR];
-          const double a1 = s_col[(c + 1) * STR];
-#pragma unroll
-          for (int r = 0; r < R; ++r) {
-            const double w0 = wval(r, c, a0), w1 = wval(r, c + 1, a1);
-            Mc[r] = fmax(Mc[r], fmax(w0, w1));
-            const float p = exp2_hw((float)(w0 - shift[r])) + exp2_hw((float)(w1 - shift[r]));
-            Sc[r] += (double)p;
-          }
-        }
-        int hi = 0;
-#pragma unroll
-        for (int r = 0; r < R; ++r) {
-          Mrun[r] = fmax(Mrun[r], Mc[r]);
-          if (row[r] < n_dst && Mc[r] - shift[r] > kShiftHi) hi = 1;
-        }
-        if (__syncthreads_or(hi)) {
-          // move the shift of far-exceeded rows up to the chunk max and sum again
-#pragma unroll
-          for (int r = 0; r < R; ++r) {
-            if (Mc[r] - shift[r] > kShiftHi) {
-              Srun[r] *= exp2(shift[r] - Mc[r]);
-              shift[r] = Mc[r];
-            }
-          }
-          chunk_sum(cpad, shift, Sc);
-        }
-#pragma unroll
-        for (int r = 0; r < R; ++r) Srun[r] += Sc[r];
-      } else {
-        // pass 1: chunk max per row
-        double Mc[R];
-#pragma unroll
-        for (int r = 0; r < R; ++r) Mc[r] = -INFINITY;
-#pragma unroll 8
-        for (int c = 0; c < cpad; ++c) {
-          const double a = s_col[c * STR];
-#pragma unroll
-          for (int r = 0; r < R; ++r) Mc[r] = fmax(Mc[r], wval(r, c, a));
-        }
-#pragma unroll
-        for (int r = 0; r < R; ++r) {
-          if (Mc[r] > Mrun[r]) {
-            Srun[r] *= exp2(Mrun[r] - Mc[r]);  // 0 when Mrun = -inf and Srun = 0
-            Mrun[r] = Mc[r];
-          }
-          shift[r] = (Mrun[r] == -INFINITY) ? 0.0 : Mrun[r];
-        }
-        // pass 2: sum of 2^(w - max)
-        double Sc[R];
-        chunk_sum(cpad, shift, Sc);
-#pragma unroll
-        for (int r = 0; r < R; ++r) Srun[r] += Sc[r];
       }
     }
-    if (!one) break;
-    // one pass: express the sum relative to the split max; rows whose max fell
-    // far below the shift send the block back through its columns in two passes
-    int lo = 0;
+    __syncthreads();
+    double Mc[R];
 #pragma unroll
-    for (int r = 0; r < R; ++r)
-      if (row[r] < n_dst && Mrun[r] > -INFINITY && Mrun[r] - shift[r] < kShiftLo) lo = 1;
-    if (__syncthreads_or(lo)) {
-      one = false;
-      continue;
+    for (int r = 0; r < R; ++r) Mc[r] = -INFINITY;
+    for (int c = 0; c < cn; ++c) {
+      const double a = s_col[c * STR];
+#pragma unroll
+      for (int r = 0; r < R; ++r) Mc[r] = fmax(Mc[r], wval(r, c, a));
     }
 #pragma unroll
     for (int r = 0; r < R; ++r) {
-      if (Mrun[r] > -INFINITY) {
-        Srun[r] *= exp2(shift[r] - Mrun[r]);
-      } else {
-        Srun[r] = 0.0;
+      if (Mc[r] > Mrun[r]) {
+        Srun[r] *= exp2(Mrun[r] - Mc[r]);  // 0 when Mrun = -inf and Srun = 0
+        Mrun[r] = Mc[r];
       }
+      const double sh = (Mrun[r] == -INFINITY) ? 0.0 : Mrun[r];
+      double S = 0.0;
+      for (int c = 0; c < cn; ++c) S += exp2(wval(r, c, s_col[c * STR]) - sh);
+      Srun[r] += S;
     }
-    break;
   }
-
 #pragma unroll
   for (int r = 0; r < R; ++r) {
     if (row[r] < n_dst) md->partial[(size_t)row[r] * md->ns + it.split] = make_double2(Mrun[r], Srun[r]);
@@ -376,114 +232,273 @@ __global__ __launch_bounds__(kBlock) void k_msg(Tables tb, int eval_src_slot) {
 }
 
 // ---------------------------------------------------------------------------
-// Tile kernel: one thread per row x of a 256-row tile of node j.
-//   merge  m_{k->j}(x) from the column splits (FP64)
-//   terms  fixed:  mu(x) |expm1(Lam_(j,k)(x) + m_{k->j}(x))| = |q_(j,k)(x) - mu(x)|
-//          free:   |q_(j,k)(x) - qbar(x)|, q = exp(Lam + m), qbar the mean over k
-//   update fixed:  L_(j,k) = -m_{k->j}        (c_j = 0)
-//          free:   L_(j,k) = abar - m_{k->j}  (abar = mean_k m; c_j = LSE_x abar
-//                  is formed by the finalise kernel from the tile records)
-// Record: per incident edge the tile's sum of terms, then the tile's LSE of
-// abar (max, scaled sum).
-// The loads of a group of kGroup edges (descriptors, split partials, held
-// potentials) are issued together, so a tile waits for memory once per group
-// rather than several times per edge.
+// Node kernel: one half-sweep's work for one 64-row tile of a node j of the
+// class being updated (Algorithm tree_local_reg; one lane per row x).
+//
+//   messages  for every incident edge (j, k), m_{k->j}(x) = LSE over supp(k):
+//             the W waves of the block split supp(k) into W column ranges; each
+//             wave streams its range through its own LDS staging buffer and
+//             returns (max, sum 2^(w - max)) per row; the partials are merged
+//             in FP64 through LDS by one wave per edge (edges rotate over the
+//             waves, so merging overlaps the next edge's sums).
+//   terms     of the state before the update (Lemma f_upper_bound_tree):
+//             fixed: mu(x) |expm1(Lam_(j,k)(x) + m_{k->j}(x))| = |q_(j,k)(x) - mu(x)|,
+//             free:  |q_(j,k)(x) - qbar(x)|, q = exp(Lam + m), qbar the mean over k
+//   update    (eq. bipartite_tree_updates1/2 in the closed form of Prop. equi)
+//             fixed: L_(j,k) = -m_{k->j}; free: L_(j,k) = abar - m_{k->j},
+//             abar = mean_k m_{k->j}, with the normaliser c_j = LSE_x abar formed
+//             by the finalise kernel from the tile records.
+//   record    per edge the tile's sum of terms, then (max, scaled sum) of abar.
+//
+// Sums (FP32 core): pairs of v_exp_f32 terms of the FP64-reduced argument,
+// added in FP32 and accumulated in FP64.  From the third half-sweep of a call
+// on, one pass shifted by the previous max of the same row and column range
+// (kept in wmax) with the new max tracked alongside; a chunk whose max exceeds
+// the shift by more than kShiftHi moves the shift and is summed again, and a
+// row whose max ends more than kShiftLo below its shift sends the wave back
+// through its range in two passes.  Both decisions are wave-uniform.  The
+// first two half-sweeps of a call take two passes (chunk max, then sum); the
+// FP64 variant (F64) always does, with FP64 exponentials.
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(kBlock) void k_tile(Tables tb) {
-  __shared__ double sh_rec[4][kRecChunk + kRecExtra];
+constexpr int kFinWaves = 16;    // waves per finalise block (one node each)
+constexpr double kShiftHi = 96.0;
+constexpr double kShiftLo = -96.0;
+constexpr int kNodeDegLDS = 16;  // merged messages of the first 16 edges stay in LDS
+
+// Orders a wave's LDS writes before its later LDS reads (wave-private buffers).
+__device__ inline void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+template <int DIM, int W, bool F64, bool EXPL>
+__global__ __launch_bounds__(64 * W) void k_node(Tables tb) {
+  constexpr int CH = EXPL ? 32 : 64;                 // columns per wave chunk
+  constexpr int STR = EXPL ? 1 : (DIM == 1 ? 2 : 4); // doubles per staged column
+  __shared__ double s_col[W][CH * STR];
+  __shared__ double2 s_part[2][W][64];
+  __shared__ double s_m[kNodeDegLDS][64];
+
   const TileItem ti = tb.tiles[blockIdx.x];
   const InstState* st = tb.inst + ti.inst;
   const NodeItem nd = tb.nodes[ti.node];
   const long long t = st->t;
   if (st->done || ((t & 1) == 1) != (tb.colour == 0)) return;
   const int cur = (int)(((t - 1) >> 1) & 1), nxt = cur ^ 1;
+  const int src_slot = (int)((t >> 1) & 1);
+  const bool one = !F64 && t >= st->onepass_from;
   const MsgDesc* __restrict__ mds = tb.msgs + nd.msg0;
   const int n = nd.n, deg = nd.deg;
-  const bool fixed = nd.fixed != 0;
-  const int dim = mds[0].dim;
-  const bool sq = mds[0].cost_kind == 0;
-  const double ieps = 1.0 / mds[0].eps;
-  const double* __restrict__ xs = mds[0].supp_dst;
-  const double c_old = nd.c ? nd.c[cur] : 0.0;
-  double* __restrict__ rec = nd.tpart + (size_t)(ti.row0 / kTileRows) * (deg + kRecExtra);
-  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-  const int x = ti.row0 + threadIdx.x;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int x = ti.row0 + lane;
   const bool vx = x < n;
-  const double mux = (vx && fixed) ? nd.mu[x] : 0.0;
-  const double x2 = (vx && sq) ? sq_norm(xs, dim, x) : 0.0;
+  const double eps = mds[0].eps;
+  const double cxs = 2.0 * kLog2e / eps;
+  const double ces = -kLog2e / eps;
+  double cx[DIM > 0 ? DIM : 1];
+  double x2 = 0.0;
+#pragma unroll
+  for (int d = 0; d < DIM; ++d) {
+    const double v = (vx && !EXPL) ? mds[0].supp_dst[(size_t)x * DIM + d] : 0.0;
+    cx[d] = cxs * v;
+    x2 = fma(v, v, x2);
+  }
+  double* __restrict__ stage = s_col[wv];
 
-  // merged messages and held potentials: registers for the first kRegDeg
-  // edges, the mfull scratch row beyond (star centres of high degree)
-  double mreg[kRegDeg], lreg[kRegDeg];
-  double asum = 0.0, qsum = 0.0;
-  auto finish = [&](const MsgDesc& md, const Merged& g, double l) -> double {
-    const double m = (g.lse2 > -INFINITY) ? kLn2 * g.lse2 - x2 * ieps : -INFINITY;
-    asum += m;
-    if (!fixed) qsum += exp(l - c_old + m);
-    return m;
-  };
+  for (int k = 0; k < deg; ++k) {
+    const MsgDesc& md = mds[k];
+    const int n_src = md.n_src;
+    const int per = (n_src + W - 1) / W;
+    const int c_lo = min(wv * per, n_src), c_hi = min(c_lo + per, n_src);
+    const double* __restrict__ lam = md.lam_src[src_slot];
+    const double csrc = md.c_src ? md.c_src[src_slot] : 0.0;
+    const double* __restrict__ lg = md.lg_src;
+    const double* __restrict__ ys = md.supp_src;
+    const float* __restrict__ cost = md.cost;
+    double* __restrict__ wmax = md.wmax;
+
+    // A chunk's column data is fetched into registers (lane = column), then
+    // staged in the wave's LDS buffer; padded columns get a = -inf and y = 0,
+    // so they add exactly nothing.  The one-pass loop fetches the next chunk
+    // before summing the current one, so its loads overlap the arithmetic.
+    double f_base = -INFINITY;
+    double f_y[DIM > 0 ? DIM : 1];
+    auto fetch_chunk = [&](int c0, int cn) {
+      const int col = c0 + lane;
+      f_base = -INFINITY;
 #pragma unroll
-  for (int g0 = 0; g0 < kRegDeg; g0 += kGroup) {
-    const double2* P[kGroup];
-    const double* Lc[kGroup];
-    int NS[kGroup];
+      for (int d = 0; d < DIM; ++d) f_y[d] = 0.0;
+      if (lane < cn) {
+        f_base = (lam[col] - csrc) + lg[col];
+        if (!EXPL) {
 #pragma unroll
-    for (int u = 0; u < kGroup; ++u) {
-      const bool on = g0 + u < deg;
-      P[u] = on ? mds[g0 + u].partial : nullptr;
-      Lc[u] = on ? mds[g0 + u].lam_dst[cur] : nullptr;
-      NS[u] = on ? mds[g0 + u].ns : 0;
-    }
-    double2 pv[kGroup][kNsReg];
-    double lv[kGroup];
-#pragma unroll
-    for (int u = 0; u < kGroup; ++u) {
-      const bool on = vx && g0 + u < deg;
-      lv[u] = on ? Lc[u][x] : 0.0;
-#pragma unroll
-      for (int s2 = 0; s2 < kNsReg; ++s2)
-        pv[u][s2] = (on && s2 < NS[u]) ? P[u][(size_t)x * NS[u] + s2] : make_double2(-INFINITY, 0.0);
-    }
-#pragma unroll
-    for (int u = 0; u < kGroup; ++u) {
-      const int k = g0 + u;
-      mreg[k] = 0.0;
-      lreg[k] = lv[u];
-      if (k < deg && vx) {
-        Merged g;
-        if (NS[u] <= kNsReg) {
-          double Mx = -INFINITY;
-#pragma unroll
-          for (int s2 = 0; s2 < kNsReg; ++s2) Mx = fmax(Mx, pv[u][s2].x);
-          double S = 0.0;
-          if (Mx > -INFINITY) {
-#pragma unroll
-            for (int s2 = 0; s2 < kNsReg; ++s2) {
-              const double2 q = pv[u][s2];
-              if (q.y > 0.0) S += (q.x == Mx) ? q.y : q.y * exp2(q.x - Mx);
-            }
-          }
-          g = {(S > 0.0) ? Mx + log2(S) : -INFINITY, Mx, S};
-        } else {
-          g = merge_splits(P[u] + (size_t)x * NS[u], NS[u]);
+          for (int d = 0; d < DIM; ++d) f_y[d] = ys[(size_t)col * DIM + d];
         }
-        mreg[k] = finish(mds[k], g, lv[u]);
+      }
+    };
+    auto stage_fetched = [&]() {
+      double a = f_base;
+      if (!EXPL) {
+        double y2 = 0.0;
+#pragma unroll
+        for (int d = 0; d < DIM; ++d) y2 = fma(f_y[d], f_y[d], y2);
+        a -= y2 / eps;
+      }
+      a *= kLog2e;
+      if (lane < CH) {
+        stage[lane * STR] = a;
+        if (!EXPL) {
+#pragma unroll
+          for (int d = 0; d < DIM; ++d) stage[lane * STR + 1 + d] = f_y[d];
+        }
+      }
+      wave_sync();
+    };
+    auto stage_chunk = [&](int c0, int cn) {
+      fetch_chunk(c0, cn);
+      stage_fetched();
+    };
+    float cv[EXPL ? CH : 1];
+    auto load_cost = [&](int c0, int cn) {
+      if (EXPL) {
+#pragma unroll
+        for (int c = 0; c < CH; ++c) cv[c] = (vx && c < cn) ? cost[(size_t)(c0 + c) * n + x] : 0.0f;
+      }
+    };
+    auto wcol = [&](int c) -> double {
+      double w = stage[c * STR];
+      if (EXPL) {
+        w = fma(ces, (double)cv[c], w);
+      } else {
+#pragma unroll
+        for (int d = 0; d < DIM; ++d) w = fma(cx[d], stage[c * STR + 1 + d], w);
+      }
+      return w;
+    };
+    // sum of 2^(w - sh) over the staged chunk (padded columns give 0)
+    auto chunk_sum = [&](double sh) -> double {
+      double S = 0.0;
+#pragma unroll 8
+      for (int c = 0; c < CH; c += 2) {
+        const double w0 = wcol(c), w1 = wcol(c + 1);
+        if (F64) {
+          S += exp2(w0 - sh) + exp2(w1 - sh);
+        } else {
+          const float p = exp2_hw((float)(w0 - sh)) + exp2_hw((float)(w1 - sh));
+          S += (double)p;
+        }
+      }
+      return S;
+    };
+    auto chunk_max = [&]() -> double {
+      double M = -INFINITY;
+#pragma unroll 8
+      for (int c = 0; c < CH; ++c) M = fmax(M, wcol(c));
+      return M;
+    };
+
+    double M = -INFINITY, S = 0.0;
+    bool two = !one;
+    if (one) {
+      const double pm = vx ? wmax[(size_t)wv * n + x] : 0.0;
+      double sh = isfinite(pm) ? pm : 0.0;
+      if (c_lo < c_hi) fetch_chunk(c_lo, min(CH, c_hi - c_lo));
+      for (int c0 = c_lo; c0 < c_hi; c0 += CH) {
+        const int cn = min(CH, c_hi - c0);
+        load_cost(c0, cn);
+        stage_fetched();
+        if (c0 + CH < c_hi) fetch_chunk(c0 + CH, min(CH, c_hi - c0 - CH));
+        // one pass: sum relative to the shift, chunk max alongside
+        double Mc = -INFINITY, Sc = 0.0;
+#pragma unroll 8
+        for (int c = 0; c < CH; c += 2) {
+          const double w0 = wcol(c), w1 = wcol(c + 1);
+          Mc = fmax(Mc, fmax(w0, w1));
+          const float p = exp2_hw((float)(w0 - sh)) + exp2_hw((float)(w1 - sh));
+          Sc += (double)p;
+        }
+        if (__any(vx && Mc - sh > kShiftHi)) {
+          if (Mc - sh > kShiftHi) {
+            S *= exp2(sh - Mc);
+            sh = Mc;
+          }
+          Sc = chunk_sum(sh);
+        }
+        M = fmax(M, Mc);
+        S += Sc;
+        wave_sync();
+      }
+      if (__any(vx && M > -INFINITY && M - sh < kShiftLo)) {
+        two = true;  // the row's terms fell out of FP32 range: two passes
+      } else {
+        S = (M > -INFINITY) ? S * exp2(sh - M) : 0.0;
+      }
+    }
+    if (two) {
+      M = -INFINITY;
+      S = 0.0;
+      for (int c0 = c_lo; c0 < c_hi; c0 += CH) {
+        const int cn = min(CH, c_hi - c0);
+        load_cost(c0, cn);
+        stage_chunk(c0, cn);
+        const double Mc = chunk_max();
+        if (Mc > M) {
+          S *= exp2(M - Mc);  // 0 when M = -inf and S = 0
+          M = Mc;
+        }
+        S += chunk_sum(M == -INFINITY ? 0.0 : M);
+        wave_sync();
+      }
+    }
+    if (vx) wmax[(size_t)wv * n + x] = M;
+    s_part[k & 1][wv][lane] = make_double2(M, S);
+    __syncthreads();
+    if (wv == k % W) {
+      // merge the W column ranges of edge k for the tile's rows
+      double Mx = -INFINITY;
+#pragma unroll
+      for (int u = 0; u < W; ++u) Mx = fmax(Mx, s_part[k & 1][u][lane].x);
+      double St = 0.0;
+      if (Mx > -INFINITY) {
+#pragma unroll
+        for (int u = 0; u < W; ++u) {
+          const double2 q = s_part[k & 1][u][lane];
+          if (q.y > 0.0) St += (q.x == Mx) ? q.y : q.y * exp2(q.x - Mx);
+        }
+      }
+      const double m = (Mx > -INFINITY && St > 0.0) ? kLn2 * (Mx + log2(St)) - x2 / eps : -INFINITY;
+      if (k < kNodeDegLDS) {
+        s_m[k][lane] = m;
+      } else if (vx) {
+        md.mfull[x] = m;
       }
     }
   }
-  for (int k = kRegDeg; k < deg; ++k) {
-    if (!vx) continue;
-    const MsgDesc& md = mds[k];
-    const Merged g = merge_splits(md.partial + (size_t)x * md.ns, md.ns);
-    md.mfull[x] = finish(md, g, md.lam_dst[cur][x]);
+  __syncthreads();
+  if (wv != 0) return;
+
+  // wave 0: stopping-sum terms of the state before the update, the update,
+  // and the tile record
+  const bool fixed = nd.fixed != 0;
+  const double c_old = nd.c ? nd.c[cur] : 0.0;
+  const double mux = (vx && fixed) ? nd.mu[x] : 0.0;
+  double* __restrict__ rec = nd.tpart + (size_t)(ti.row0 / kNodeRows) * (deg + kRecExtra);
+  auto mval = [&](int k) -> double { return k < kNodeDegLDS ? s_m[k][lane] : (vx ? mds[k].mfull[x] : 0.0); };
+  double asum = 0.0, qsum = 0.0;
+  for (int k = 0; k < deg; ++k) {
+    if (!vx) break;
+    const double m = mval(k);
+    asum += m;
+    if (!fixed) qsum += exp(mds[k].lam_dst[cur][x] - c_old + m);
   }
   const double a = vx ? asum / deg : -INFINITY;
   const double qb = qsum / deg;
-
-  // stopping-sum term of edge k at row x, and the update of L_(j,k)(x)
-  auto term = [&](int k, double m, double l) -> double {
+  for (int k = 0; k < deg; ++k) {
     double part = 0.0;
     if (vx) {
+      const double m = mval(k);
+      const double l = mds[k].lam_dst[cur][x];
       double* __restrict__ Ln = mds[k].lam_dst[nxt];
       if (fixed) {
         if (mux > 0.0) part = mux * fabs(expm1(l + m));
@@ -493,98 +508,79 @@ __global__ __launch_bounds__(kBlock) void k_tile(Tables tb) {
         Ln[x] = a - m;
       }
     }
-    return wave_sum(part);
-  };
-
-  // records in chunks of kRecChunk edges, one barrier per chunk
-  for (int k0 = 0; k0 < deg; k0 += kRecChunk) {
-    const int kn = min(kRecChunk, deg - k0);
-    if (k0 == 0) {
-#pragma unroll
-      for (int k = 0; k < kRegDeg; ++k) {
-        if (k < kn) {
-          const double p = term(k, mreg[k], lreg[k]);
-          if (lane == 0) sh_rec[wave][k] = p;
-        }
-      }
+    part = wave_sum(part);
+    if (lane == 0) rec[k] = part;
+  }
+  if (!fixed) {
+    const double Mw = wave_max(a);
+    const double Sw = wave_sum((a > -INFINITY) ? exp(a - Mw) : 0.0);
+    if (lane == 0) {
+      rec[deg] = Mw;
+      rec[deg + 1] = Sw;
     }
-    for (int k = max(k0, kRegDeg); k < k0 + kn; ++k) {
-      const double m = vx ? mds[k].mfull[x] : 0.0;
-      const double l = vx ? mds[k].lam_dst[cur][x] : 0.0;
-      const double p = term(k, m, l);
-      if (lane == 0) sh_rec[wave][k - k0] = p;
-    }
-    const bool last = k0 + kn == deg;
-    if (last && !fixed) {
-      // per-wave LSE of abar over the wave's rows
-      const double Mw = wave_max(a);
-      const double Sw = wave_sum((a > -INFINITY) ? exp(a - Mw) : 0.0);
-      if (lane == 0) {
-        sh_rec[wave][kn] = Mw;
-        sh_rec[wave][kn + 1] = Sw;
-      }
-    }
-    __syncthreads();
-    const int i = threadIdx.x;
-    if (i < kn) rec[k0 + i] = (sh_rec[0][i] + sh_rec[1][i]) + (sh_rec[2][i] + sh_rec[3][i]);
-    if (last && !fixed && i == kn) {
-      double M = -INFINITY;
-      for (int w = 0; w < 4; ++w) M = fmax(M, sh_rec[w][kn]);
-      double S = 0.0;
-      for (int w = 0; w < 4; ++w)
-        if (sh_rec[w][kn] > -INFINITY) S += sh_rec[w][kn + 1] * exp(sh_rec[w][kn] - M);
-      rec[deg] = M;
-      rec[deg + 1] = S;
-    }
-    if (!last) __syncthreads();
   }
 }
 
 // ---------------------------------------------------------------------------
-// Finalise kernel: one block per instance.  Thread i handles the instance's
-// class nodes i, i + 256, ...: per-edge terms summed over tiles (the node's
-// stopping-sum terms), and for free nodes c_j = LSE over the tile records;
-// then the block sums the terms and thread 0 takes the stop decision.
+// Finalise kernel: one block of kFinWaves waves per instance, one wave per
+// node of the class (nodes w, w + kFinWaves, ...): per-edge terms summed over
+// the node's tile records (lanes over tiles), and for free nodes
+// c_j = LSE over the tile records of abar; then the block sums the terms in a
+// fixed order and thread 0 takes the stop decision.
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(kBlock) void k_finalize(Tables tb) {
-  __shared__ double sh[4][2];
+__global__ __launch_bounds__(64 * kFinWaves) void k_finalize(Tables tb) {
+  __shared__ double sh[kFinWaves][2];
   InstState* st = tb.inst + blockIdx.x;
   const long long t = st->t;
   if (st->done || ((t & 1) == 1) != (tb.colour == 0)) return;
   const int nxt = (int)((((t - 1) >> 1) & 1) ^ 1);
   const int i0 = st->node0[tb.colour], cnt = st->nnodes[tb.colour];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   double esum = 0.0, emax = 0.0;
-  for (int i = threadIdx.x; i < cnt; i += kBlock) {
+  for (int i = wv; i < cnt; i += kFinWaves) {
     const NodeItem nd = tb.nodes[i0 + i];
     const int deg = nd.deg, stride = deg + kRecExtra, tiles = nd.tiles;
     const double* __restrict__ tp = nd.tpart;
     for (int k = 0; k < deg; ++k) {
       double e = 0.0;
-      for (int tt = 0; tt < tiles; ++tt) e += tp[(size_t)tt * stride + k];
+      for (int tt = lane; tt < tiles; tt += 64) e += tp[(size_t)tt * stride + k];
+      e = wave_sum(e);
       esum += e;
       emax = fmax(emax, e);
     }
     if (!nd.fixed) {
-      double M = -INFINITY;
-      for (int tt = 0; tt < tiles; ++tt) M = fmax(M, tp[(size_t)tt * stride + deg]);
-      double S = 0.0;
-      for (int tt = 0; tt < tiles; ++tt) {
+      double M = -INFINITY, Mt[2] = {-INFINITY, -INFINITY}, St[2] = {0.0, 0.0};
+      // the first 128 tiles stay in registers; larger nodes reread their records
+      for (int tt = lane, u = 0; tt < tiles; tt += 64, ++u) {
         const double mt = tp[(size_t)tt * stride + deg];
-        if (mt > -INFINITY) S += tp[(size_t)tt * stride + deg + 1] * exp(mt - M);
+        if (u < 2) {
+          Mt[u] = mt;
+          St[u] = tp[(size_t)tt * stride + deg + 1];
+        }
+        M = fmax(M, mt);
       }
-      nd.c[nxt] = M + log(S);
+      M = wave_max(M);
+      double S = 0.0;
+      for (int tt = lane, u = 0; tt < tiles; tt += 64, ++u) {
+        const double mt = u < 2 ? Mt[u] : tp[(size_t)tt * stride + deg];
+        const double sv = u < 2 ? St[u] : tp[(size_t)tt * stride + deg + 1];
+        if (mt > -INFINITY) S += sv * exp(mt - M);
+      }
+      S = wave_sum(S);
+      if (lane == 0) nd.c[nxt] = M + log(S);
     }
   }
-  esum = wave_sum(esum);
-  emax = wave_max(emax);
-  if ((threadIdx.x & 63) == 0) {
-    sh[threadIdx.x >> 6][0] = esum;
-    sh[threadIdx.x >> 6][1] = emax;
+  if (lane == 0) {
+    sh[wv][0] = esum;
+    sh[wv][1] = emax;
   }
   __syncthreads();
   if (threadIdx.x == 0) {
-    const double E = (sh[0][0] + sh[1][0]) + (sh[2][0] + sh[3][0]);
-    const double Em = fmax(fmax(sh[0][1], sh[1][1]), fmax(sh[2][1], sh[3][1]));
+    double E = 0.0, Em = 0.0;
+    for (int w = 0; w < kFinWaves; ++w) {
+      E += sh[w][0];
+      Em = fmax(Em, sh[w][1]);
+    }
     decide(tb, st, t, E, Em);
   }
 }
@@ -749,46 +745,60 @@ __global__ __launch_bounds__(kBlock) void k_coupling(const EdgeDesc* edp, double
 // ---------------------------------------------------------------------------
 // launch wrappers
 // ---------------------------------------------------------------------------
-template <int DIM, int R, bool F64, bool EXPL>
-static hipError_t launch_msg_t(const Tables& tb, int n_items, int eval_src_slot, hipStream_t s) {
-  if (eval_src_slot >= 0)
-    hipLaunchKernelGGL((k_msg<DIM, R, F64, EXPL, false>), dim3(n_items), dim3(kBlock), 0, s, tb, eval_src_slot);
-  else
-    hipLaunchKernelGGL((k_msg<DIM, R, F64, EXPL, true>), dim3(n_items), dim3(kBlock), 0, s, tb, -1);
+template <int DIM, int R, bool EXPL>
+static hipError_t launch_msg_t(const Tables& tb, int n_items, int src_slot, hipStream_t s) {
+  hipLaunchKernelGGL((k_msg<DIM, R, EXPL>), dim3(n_items), dim3(kBlock), 0, s, tb, src_slot);
   return hipGetLastError();
 }
 
-template <int R, bool F64>
-static hipError_t launch_msg_r(const Tables& tb, int n_items, int dim, int eval_src_slot, hipStream_t s) {
+template <int R>
+static hipError_t launch_msg_r(const Tables& tb, int n_items, int dim, int src_slot, hipStream_t s) {
   switch (dim) {
-    case 0: return launch_msg_t<1, R, F64, true>(tb, n_items, eval_src_slot, s);  // explicit cost
-    case 1: return launch_msg_t<1, R, F64, false>(tb, n_items, eval_src_slot, s);
-    case 2: return launch_msg_t<2, R, F64, false>(tb, n_items, eval_src_slot, s);
-    case 3: return launch_msg_t<3, R, F64, false>(tb, n_items, eval_src_slot, s);
+    case 0: return launch_msg_t<1, R, true>(tb, n_items, src_slot, s);  // explicit cost
+    case 1: return launch_msg_t<1, R, false>(tb, n_items, src_slot, s);
+    case 2: return launch_msg_t<2, R, false>(tb, n_items, src_slot, s);
+    case 3: return launch_msg_t<3, R, false>(tb, n_items, src_slot, s);
     default: return hipErrorInvalidValue;
   }
 }
 
-hipError_t launch_msg(const Tables& tb, int n_items, int dim, int rows_per_lane, bool fp64, int eval_src_slot,
-                      hipStream_t s) {
+hipError_t launch_msg(const Tables& tb, int n_items, int dim, int rows_per_lane, int src_slot, hipStream_t s) {
   if (n_items <= 0) return hipSuccess;
-  if (rows_per_lane == 2) {
-    return fp64 ? launch_msg_r<2, true>(tb, n_items, dim, eval_src_slot, s)
-                : launch_msg_r<2, false>(tb, n_items, dim, eval_src_slot, s);
-  }
-  return fp64 ? launch_msg_r<1, true>(tb, n_items, dim, eval_src_slot, s)
-              : launch_msg_r<1, false>(tb, n_items, dim, eval_src_slot, s);
+  if (src_slot < 0 || src_slot > 1) return hipErrorInvalidValue;
+  return rows_per_lane == 2 ? launch_msg_r<2>(tb, n_items, dim, src_slot, s)
+                            : launch_msg_r<1>(tb, n_items, dim, src_slot, s);
 }
 
-hipError_t launch_tile(const Tables& tb, int n_tiles, hipStream_t s) {
-  if (n_tiles <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_tile, dim3(n_tiles), dim3(kBlock), 0, s, tb);
+template <int DIM, int W, bool F64, bool EXPL>
+static hipError_t launch_node_t(const Tables& tb, int n_tiles, hipStream_t s) {
+  hipLaunchKernelGGL((k_node<DIM, W, F64, EXPL>), dim3(n_tiles), dim3(64 * W), 0, s, tb);
   return hipGetLastError();
+}
+
+template <int W, bool F64>
+static hipError_t launch_node_w(const Tables& tb, int n_tiles, int dim, hipStream_t s) {
+  switch (dim) {
+    case 0: return launch_node_t<1, W, F64, true>(tb, n_tiles, s);  // explicit cost
+    case 1: return launch_node_t<1, W, F64, false>(tb, n_tiles, s);
+    case 2: return launch_node_t<2, W, F64, false>(tb, n_tiles, s);
+    case 3: return launch_node_t<3, W, F64, false>(tb, n_tiles, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+hipError_t launch_node(const Tables& tb, int n_tiles, int dim, int waves, bool fp64, hipStream_t s) {
+  if (n_tiles <= 0) return hipSuccess;
+  switch (waves) {
+    case 2: return fp64 ? launch_node_w<2, true>(tb, n_tiles, dim, s) : launch_node_w<2, false>(tb, n_tiles, dim, s);
+    case 4: return fp64 ? launch_node_w<4, true>(tb, n_tiles, dim, s) : launch_node_w<4, false>(tb, n_tiles, dim, s);
+    case 8: return fp64 ? launch_node_w<8, true>(tb, n_tiles, dim, s) : launch_node_w<8, false>(tb, n_tiles, dim, s);
+    default: return hipErrorInvalidValue;
+  }
 }
 
 hipError_t launch_finalize(const Tables& tb, int n_inst, hipStream_t s) {
   if (n_inst <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_finalize, dim3(n_inst), dim3(kBlock), 0, s, tb);
+  hipLaunchKernelGGL(k_finalize, dim3(n_inst), dim3(64 * kFinWaves), 0, s, tb);
   return hipGetLastError();
 }
 

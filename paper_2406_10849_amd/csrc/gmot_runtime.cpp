@@ -105,7 +105,7 @@ constexpr int kMsgBurst = 4;
 // of kStepEvents * k events (see Plan::launch_tstep), so one chain can be read
 // back while the next replay runs.
 struct GraphEntry {
-  bool fp64 = false, timed = false, per_edge = false;
+  bool fp64 = false, timed = false, per_node = false;
   int start = 0, k = 0;
   hipGraphExec_t exec[2] = {nullptr, nullptr};
   std::vector<hipEvent_t> ev[2];
@@ -114,8 +114,9 @@ struct GraphEntry {
 struct Plan {
   gmot_ctx* ctx = nullptr;
   std::vector<gmot_problem*> probs;
-  int R = 1;
-  int target_blocks = 1536;
+  int W = 4;                 // waves per node-kernel block
+  int R = 1;                 // evaluation message kernel: rows per lane
+  int target_blocks = 1024;  // evaluation message kernel: blocks per class (via column splits)
   std::vector<MsgDesc> msgs;
   std::vector<K1Item> items[2][4];  // [class][0 = explicit, 1..3 = dim]
   std::vector<std::pair<int, int>> msg_items[2][4];  // per message: (first item, item count)
@@ -130,9 +131,11 @@ struct Plan {
   double4* d_node_eval = nullptr;
   int* d_ndone = nullptr;
   double2* d_partial = nullptr;
+  double* d_wmax = nullptr;
   double* d_tpart = nullptr;
-  std::vector<TileItem> tiles[2];
-  TileItem* d_tiles[2] = {};
+  std::vector<TileItem> tiles[2][4];                 // [class][0 = explicit, 1..3 = dim]
+  std::vector<std::pair<int, int>> node_tiles[2][4];  // per node: (first tile, tile count)
+  TileItem* d_tiles[2][4] = {};
   int* h_ndone = nullptr;  // pinned, two mailboxes
   std::vector<GraphEntry> graphs;
   TileStats stats;
@@ -157,52 +160,49 @@ struct Plan {
     tb.inst = d_inst;
     tb.node_eval = d_node_eval;
     tb.ndone = d_ndone;
-    tb.tiles = d_tiles[c];
+    tb.tiles = dk >= 0 ? d_tiles[c][dk] : nullptr;
     tb.colour = c;
     return tb;
   }
 
-  // One half-sweep for class c: the message kernel (one launch per support
-  // dimension, or with per_edge one launch per message), then the tile and
-  // finalise kernels; with `ev`, events ev[0] before, ev[1] after the message
-  // stage and ev[2] after the finalise kernel.
-  hipError_t launch_msg_stage(int c, bool fp64, hipStream_t s, bool per_edge) const {
+  // The node stage of class c: one launch per support-dimension group, or
+  // with per_node one launch per node (the same tiles, issued node by node).
+  hipError_t launch_node_stage(int c, bool fp64, hipStream_t s, bool per_node) const {
     hipError_t e;
     for (int dk = 0; dk < 4; ++dk) {
-      if (items[c][dk].empty()) continue;
-      if (!per_edge) {
-        e = launch_msg(tables(c, dk), (int)items[c][dk].size(), dk, R, fp64, -1, s);
+      if (tiles[c][dk].empty()) continue;
+      if (!per_node) {
+        e = launch_node(tables(c, dk), (int)tiles[c][dk].size(), dk, W, fp64, s);
         if (e != hipSuccess) return e;
         continue;
       }
-      for (const auto& r : msg_items[c][dk]) {
+      for (const auto& r : node_tiles[c][dk]) {
         Tables tb = tables(c, dk);
-        tb.items += r.first;
-        e = launch_msg(tb, r.second, dk, R, fp64, -1, s);
+        tb.tiles += r.first;
+        e = launch_node(tb, r.second, dk, W, fp64, s);
         if (e != hipSuccess) return e;
       }
     }
     return hipSuccess;
   }
 
-  // One half-sweep of class c.  With events (timing mode, direct launches):
-  // ev[0], the message stage kMsgBurst times, ev[1], the message stage,
-  // ev[2], tile and finalise kernels, ev[3].  The message stage only reads
-  // the state and rewrites its partials, so the repeats are idempotent; their
-  // mean is the message stage's duration without the event overhead.
+  // One half-sweep of class c: the node stage, then the finalise kernel.  With
+  // events (timing mode, direct launches): ev[0], the node stage kMsgBurst
+  // times, ev[1], the node stage, ev[2], the finalise kernel, ev[3].  A repeat
+  // of the node stage reads the same state and rewrites the same slots (only
+  // its shifts differ), so the burst's mean is the node stage's duration
+  // without the event overhead.
   hipError_t launch_tstep(int c, bool fp64, hipStream_t s, const hipEvent_t* ev = nullptr,
-                          bool per_edge = false) const {
+                          bool per_node = false) const {
     hipError_t e;
     if (ev) {
       if ((e = hipEventRecord(ev[0], s)) != hipSuccess) return e;
       for (int r = 0; r < kMsgBurst; ++r)
-        if ((e = launch_msg_stage(c, fp64, s, per_edge)) != hipSuccess) return e;
+        if ((e = launch_node_stage(c, fp64, s, per_node)) != hipSuccess) return e;
       if ((e = hipEventRecord(ev[1], s)) != hipSuccess) return e;
     }
-    if ((e = launch_msg_stage(c, fp64, s, per_edge)) != hipSuccess) return e;
+    if ((e = launch_node_stage(c, fp64, s, per_node)) != hipSuccess) return e;
     if (ev && (e = hipEventRecord(ev[2], s)) != hipSuccess) return e;
-    e = launch_tile(tables(c, -1), (int)tiles[c].size(), s);
-    if (e != hipSuccess) return e;
     e = launch_finalize(tables(c, -1), (int)inst.size(), s);
     if (e != hipSuccess) return e;
     if (ev && (e = hipEventRecord(ev[3], s)) != hipSuccess) return e;
@@ -213,14 +213,16 @@ struct Plan {
 // ---------------------------------------------------------------------------
 // plan construction
 // ---------------------------------------------------------------------------
-static int build_plan(gmot_ctx* ctx, const std::vector<gmot_problem*>& probs, int R, int target_blocks,
-                      Plan** out) {
+static int build_plan(gmot_ctx* ctx, const std::vector<gmot_problem*>& probs, int W, Plan** out) {
   std::unique_ptr<Plan> pl(new Plan());
   pl->ctx = ctx;
   pl->probs = probs;
-  pl->R = R;
-  pl->target_blocks = target_blocks;
+  pl->W = W;
+  const int R = pl->R, target_blocks = pl->target_blocks;
   const int TM = 256 * R;
+  // node tiles per (class, dimension group), with each node's work (pairs) for ordering
+  struct NodeTiles { int node_item, n_tiles, inst; double work; };
+  std::vector<NodeTiles> ntl[2][4];
 
   // messages and node items (class-major within each instance)
   std::vector<int> msg_class;
@@ -246,9 +248,13 @@ static int build_plan(gmot_ctx* ctx, const std::vector<gmot_problem*>& probs, in
         nd.abar = p->d_abar + p->node_off[j];
         nd.qbar = p->d_qbar + p->node_off[j];
         nd.c = p->fixed[j] ? nullptr : p->d_c + 2 * j;
-        nd.tiles = (int)ceil_div(p->sizes[j], kTileRows);
-        for (int r = 0; r < nd.tiles; ++r)
-          pl->tiles[c].push_back({(int)pl->nodes[c].size(), r * kTileRows, (int)i, 0});
+        nd.tiles = (int)ceil_div(p->sizes[j], kNodeRows);
+        {
+          double src_cols = 0.0;
+          for (int k : p->nbrs[j]) src_cols += p->sizes[k];
+          const int dk = p->cost_kind == GMOT_COST_EXPLICIT ? 0 : p->dim;
+          ntl[c][dk].push_back({(int)pl->nodes[c].size(), nd.tiles, (int)i, src_cols});
+        }
         pl->nodes[c].push_back(nd);
         ++cnt;
         for (size_t q = 0; q < p->nbrs[j].size(); ++q) {
@@ -299,7 +305,6 @@ static int build_plan(gmot_ctx* ctx, const std::vector<gmot_problem*>& probs, in
   int64_t partial_total = 0;
   std::vector<int64_t> partial_off(pl->msgs.size());
   pl->stats = TileStats();
-  pl->stats.rows = TM;
   for (size_t m = 0; m < pl->msgs.size(); ++m) {
     MsgDesc& md = pl->msgs[m];
     const int c = msg_class[m];
@@ -309,7 +314,6 @@ static int build_plan(gmot_ctx* ctx, const std::vector<gmot_problem*>& probs, in
     md.ns = (int)ns;
     partial_off[m] = partial_total;
     partial_total += ns * md.n_dst;
-    pl->stats.max_splits = std::max(pl->stats.max_splits, (int)ns);
     const int dk = md.cost_kind == GMOT_COST_EXPLICIT ? 0 : md.dim;
     pl->msg_items[c][dk].push_back({(int)pl->items[c][dk].size(), (int)(ceil_div(md.n_dst, TM) * ns)});
     for (int64_t rt = 0; rt < ceil_div(md.n_dst, TM); ++rt)
@@ -324,6 +328,23 @@ static int build_plan(gmot_ctx* ctx, const std::vector<gmot_problem*>& probs, in
         pl->items[c][dk].push_back(it);
       }
   }
+  // node-kernel tiles: the heaviest nodes (most source columns per row) first,
+  // so their long blocks start early; each node's tiles stay consecutive
+  for (int c = 0; c < 2; ++c)
+    for (int dk = 0; dk < 4; ++dk) {
+      std::stable_sort(ntl[c][dk].begin(), ntl[c][dk].end(),
+                       [](const NodeTiles& u, const NodeTiles& v) { return u.work > v.work; });
+      for (const NodeTiles& q : ntl[c][dk]) {
+        pl->node_tiles[c][dk].push_back({(int)pl->tiles[c][dk].size(), q.n_tiles});
+        for (int r = 0; r < q.n_tiles; ++r) pl->tiles[c][dk].push_back({q.node_item, r * kNodeRows, q.inst, 0});
+      }
+    }
+  int64_t wmax_total = 0;
+  std::vector<int64_t> wmax_off(pl->msgs.size());
+  for (size_t m = 0; m < pl->msgs.size(); ++m) {
+    wmax_off[m] = wmax_total;
+    wmax_total += (int64_t)pl->msgs[m].n_dst * kMaxWaves;
+  }
   // tile records of every node
   int64_t tpart_total = 0;
   std::vector<int64_t> tpart_off[2];
@@ -332,9 +353,11 @@ static int build_plan(gmot_ctx* ctx, const std::vector<gmot_problem*>& probs, in
       tpart_off[c].push_back(tpart_total);
       tpart_total += (int64_t)nd.tiles * (nd.deg + kRecExtra);
     }
+  pl->stats.rows = kNodeRows;
+  pl->stats.max_splits = W;
   for (int c = 0; c < 2; ++c) {
     pl->stats.blocks[c] = 0;
-    for (int dk = 0; dk < 4; ++dk) pl->stats.blocks[c] += (int)pl->items[c][dk].size();
+    for (int dk = 0; dk < 4; ++dk) pl->stats.blocks[c] += (int)pl->tiles[c][dk].size();
   }
 
   // one device allocation for every table
@@ -354,8 +377,10 @@ static int build_plan(gmot_ctx* ctx, const std::vector<gmot_problem*>& probs, in
   const size_t o_eval = take(sizeof(double4) * std::max(1, pl->total_nodes));
   const size_t o_ndone = take(sizeof(int) * 4);
   const size_t o_part = take(sizeof(double2) * std::max<int64_t>(1, partial_total));
-  size_t o_tiles[2];
-  for (int c = 0; c < 2; ++c) o_tiles[c] = take(sizeof(TileItem) * pl->tiles[c].size());
+  const size_t o_wmax = take(sizeof(double) * std::max<int64_t>(1, wmax_total));
+  size_t o_tiles[2][4];
+  for (int c = 0; c < 2; ++c)
+    for (int dk = 0; dk < 4; ++dk) o_tiles[c][dk] = take(sizeof(TileItem) * pl->tiles[c][dk].size());
   const size_t o_tpart = take(sizeof(double) * std::max<int64_t>(1, tpart_total));
   const size_t total = off;
   if (hipMalloc(&pl->arena, total) != hipSuccess) return fail(GMOT_ENOMEM, "plan arena allocation failed");
@@ -368,11 +393,16 @@ static int build_plan(gmot_ctx* ctx, const std::vector<gmot_problem*>& probs, in
   pl->d_node_eval = (double4*)(base + o_eval);
   pl->d_ndone = (int*)(base + o_ndone);
   pl->d_partial = (double2*)(base + o_part);
-  for (int c = 0; c < 2; ++c) pl->d_tiles[c] = (TileItem*)(base + o_tiles[c]);
+  pl->d_wmax = (double*)(base + o_wmax);
+  for (int c = 0; c < 2; ++c)
+    for (int dk = 0; dk < 4; ++dk) pl->d_tiles[c][dk] = (TileItem*)(base + o_tiles[c][dk]);
   pl->d_tpart = (double*)(base + o_tpart);
   for (int c = 0; c < 2; ++c)
     for (size_t i = 0; i < pl->nodes[c].size(); ++i) pl->nodes[c][i].tpart = pl->d_tpart + tpart_off[c][i];
-  for (size_t m = 0; m < pl->msgs.size(); ++m) pl->msgs[m].partial = pl->d_partial + partial_off[m];
+  for (size_t m = 0; m < pl->msgs.size(); ++m) {
+    pl->msgs[m].partial = pl->d_partial + partial_off[m];
+    pl->msgs[m].wmax = pl->d_wmax + wmax_off[m];
+  }
 
   hipStream_t s = ctx->stream;
   HIPCHK(hipMemcpyAsync(pl->d_msgs, pl->msgs.data(), sizeof(MsgDesc) * pl->msgs.size(), hipMemcpyHostToDevice, s));
@@ -384,10 +414,13 @@ static int build_plan(gmot_ctx* ctx, const std::vector<gmot_problem*>& probs, in
     if (!pl->nodes[c].empty())
       HIPCHK(hipMemcpyAsync(pl->d_nodes[c], pl->nodes[c].data(), sizeof(NodeItem) * pl->nodes[c].size(),
                             hipMemcpyHostToDevice, s));
-    if (!pl->tiles[c].empty())
-      HIPCHK(hipMemcpyAsync(pl->d_tiles[c], pl->tiles[c].data(), sizeof(TileItem) * pl->tiles[c].size(),
-                            hipMemcpyHostToDevice, s));
+    for (int dk = 0; dk < 4; ++dk)
+      if (!pl->tiles[c][dk].empty())
+        HIPCHK(hipMemcpyAsync(pl->d_tiles[c][dk], pl->tiles[c][dk].data(),
+                              sizeof(TileItem) * pl->tiles[c][dk].size(), hipMemcpyHostToDevice, s));
   }
+  // one-pass shifts start at 0; the first two half-sweeps of every call take two passes anyway
+  HIPCHK(hipMemsetAsync(pl->d_wmax, 0, sizeof(double) * std::max<int64_t>(1, wmax_total), s));
   HIPCHK(hipHostMalloc((void**)&pl->h_ndone, sizeof(int) * 2, hipHostMallocDefault));
   HIPCHK(hipStreamSynchronize(s));
   g_tiles = pl->stats;
@@ -413,36 +446,28 @@ static uint64_t shape_key(const std::vector<gmot_problem*>& probs) {
   return h;
 }
 
-constexpr int kDefaultRows = 1;
-constexpr int kDefaultTarget = 1024;
+constexpr int kDefaultWaves = 4;
 
-// Tile choice: a tuned choice cached in the context for these shapes, else
-// the default; GMOT_TILES="R,target" overrides both.
-static int choose_tiles(gmot_ctx* ctx, const std::vector<gmot_problem*>& probs, int* R, int* target) {
-  *R = kDefaultRows;
-  *target = kDefaultTarget;
+// Waves per node-kernel block: a tuned choice cached in the context for these
+// shapes, else the default; GMOT_WAVES=2|4|8 overrides both.
+static int choose_waves(gmot_ctx* ctx, const std::vector<gmot_problem*>& probs) {
+  int W = kDefaultWaves;
   auto it = ctx->tuned.find(shape_key(probs));
-  if (it != ctx->tuned.end()) {
-    *R = it->second.first;
-    *target = it->second.second;
+  if (it != ctx->tuned.end()) W = it->second;
+  if (const char* v = std::getenv("GMOT_WAVES")) {
+    const int w = std::atoi(v);
+    if (w == 2 || w == 4 || w == 8) W = w;
   }
-  if (const char* v = std::getenv("GMOT_TILES")) {
-    int r = 0, t = 0;
-    if (std::sscanf(v, "%d,%d", &r, &t) == 2 && (r == 1 || r == 2) && t > 0) {
-      *R = r;
-      *target = t;
-    }
-  }
-  return 0;
+  return W;
 }
 
-static int capture_one(Plan* pl, bool fp64, bool per_edge, int start, int k, const std::vector<hipEvent_t>* ev,
+static int capture_one(Plan* pl, bool fp64, bool per_node, int start, int k, const std::vector<hipEvent_t>* ev,
                        hipGraphExec_t* out) {
   hipStream_t s = pl->ctx->stream;
   HIPCHK(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
   hipError_t le = hipSuccess;
   for (int i = 0; i < k && le == hipSuccess; ++i)
-    le = pl->launch_tstep((start + i) & 1, fp64, s, ev ? ev->data() + kStepEvents * i : nullptr, per_edge);
+    le = pl->launch_tstep((start + i) & 1, fp64, s, ev ? ev->data() + kStepEvents * i : nullptr, per_node);
   hipGraph_t graph = nullptr;
   hipError_t ce = hipStreamEndCapture(s, &graph);
   if (le != hipSuccess) {
@@ -458,9 +483,9 @@ static int capture_one(Plan* pl, bool fp64, bool per_edge, int start, int k, con
   return GMOT_OK;
 }
 
-static int get_graph(Plan* pl, bool fp64, bool per_edge, int start, int k, bool timed, GraphEntry** out) {
+static int get_graph(Plan* pl, bool fp64, bool per_node, int start, int k, bool timed, GraphEntry** out) {
   for (auto& g : pl->graphs)
-    if (g.fp64 == fp64 && g.per_edge == per_edge && g.start == start && g.k == k && g.timed == timed) {
+    if (g.fp64 == fp64 && g.per_node == per_node && g.start == start && g.k == k && g.timed == timed) {
       *out = &g;
       return GMOT_OK;
     }
@@ -469,7 +494,7 @@ static int get_graph(Plan* pl, bool fp64, bool per_edge, int start, int k, bool 
   g.start = start;
   g.k = k;
   g.timed = timed;
-  g.per_edge = per_edge;
+  g.per_node = per_node;
   if (timed) {
     // HIP events recorded by graph nodes cannot be timed, so the timed variant
     // launches directly on the stream with two alternating event chains.
@@ -478,7 +503,7 @@ static int get_graph(Plan* pl, bool fp64, bool per_edge, int start, int k, bool 
       for (auto& e : g.ev[c]) HIPCHK(hipEventCreate(&e));
     }
   } else {
-    int rc = capture_one(pl, fp64, per_edge, start, k, nullptr, &g.exec[0]);
+    int rc = capture_one(pl, fp64, per_node, start, k, nullptr, &g.exec[0]);
     if (rc) return rc;
   }
   pl->graphs.push_back(std::move(g));
@@ -543,11 +568,11 @@ static int run_plan(Plan* pl, const gmot_opts* o, gmot_result* outs, const std::
     const int start = parity == 1 ? 0 : 1;  // odd t updates class 0
     const bool fp64 = o->precision == GMOT_PREC_FP64;
     const bool timed = o->timing != 0;
-    const bool per_edge = o->schedule == GMOT_SCHED_PER_EDGE;
+    const bool per_node = o->schedule == GMOT_SCHED_PER_NODE;
     const bool no_graph = std::getenv("GMOT_NO_GRAPH") != nullptr && !timed;
     GraphEntry* g = nullptr;
     if (!no_graph) {
-      int rc = get_graph(pl, fp64, per_edge, start, k, timed, &g);
+      int rc = get_graph(pl, fp64, per_node, start, k, timed, &g);
       if (rc) return rc;
     }
     HIPCHK(launch_stamp(pl->d_inst, (int)n, s));
@@ -567,10 +592,10 @@ static int run_plan(Plan* pl, const gmot_opts* o, gmot_result* outs, const std::
       if (timed) {
         e = hipSuccess;
         for (int i = 0; i < k && e == hipSuccess; ++i)
-          e = pl->launch_tstep((start + i) & 1, fp64, s, g->ev[slot].data() + kStepEvents * i, per_edge);
+          e = pl->launch_tstep((start + i) & 1, fp64, s, g->ev[slot].data() + kStepEvents * i, per_node);
       } else if (no_graph) {
         e = hipSuccess;
-        for (int i = 0; i < k && e == hipSuccess; ++i) e = pl->launch_tstep((start + i) & 1, fp64, s, nullptr, per_edge);
+        for (int i = 0; i < k && e == hipSuccess; ++i) e = pl->launch_tstep((start + i) & 1, fp64, s, nullptr, per_node);
       } else {
         e = hipGraphLaunch(g->exec[0], s);
       }
@@ -896,13 +921,11 @@ static int upload(const gmot_tree_desc* d, gmot_problem* p) {
 
 static int ensure_plan(gmot_problem* p) {
   if (p->plan) return GMOT_OK;
-  int R, target;
-  choose_tiles(p->ctx, {p}, &R, &target);
-  return build_plan(p->ctx, {p}, R, target, &p->plan);
+  return build_plan(p->ctx, {p}, choose_waves(p->ctx, {p}), &p->plan);
 }
 
-// Mean device time of an FP32-core half-sweep (message stage, tile and
-// finalise kernels) under this plan: a few real
+// Mean device time of an FP32-core half-sweep (node stage and finalise
+// kernel) under this plan: a few real
 // half-sweeps from the held state, which is snapshotted before and restored
 // after (potential slots, node normalisers and counters).
 static int time_plan(Plan* pl, double* ms) {
@@ -958,16 +981,15 @@ static int time_plan(Plan* pl, double* ms) {
   return GMOT_OK;
 }
 
-static int autotune(gmot_ctx* ctx, const std::vector<gmot_problem*>& probs, Plan** plan_io, int32_t* R_out,
-                    int32_t* T_out, double* ms_out) {
-  static const int kCand[][2] = {{1, 256}, {1, 512}, {1, 1024}, {1, 2048}, {1, 4096},
-                                 {2, 256}, {2, 512}, {2, 1024}, {2, 2048}};
+static int autotune(gmot_ctx* ctx, const std::vector<gmot_problem*>& probs, Plan** plan_io, int32_t* W_out,
+                    double* ms_out) {
+  static const int kCand[] = {2, 4, 8};
   Plan* best = nullptr;
   double best_ms = INFINITY;
-  int bR = kDefaultRows, bT = kDefaultTarget;
-  for (const auto& cand : kCand) {
+  int bW = kDefaultWaves;
+  for (const int cand : kCand) {
     Plan* pl = nullptr;
-    int rc = build_plan(ctx, probs, cand[0], cand[1], &pl);
+    int rc = build_plan(ctx, probs, cand, &pl);
     if (rc) {
       delete best;
       return rc;
@@ -983,18 +1005,16 @@ static int autotune(gmot_ctx* ctx, const std::vector<gmot_problem*>& probs, Plan
       delete best;
       best = pl;
       best_ms = ms;
-      bR = cand[0];
-      bT = cand[1];
+      bW = cand;
     } else {
       delete pl;
     }
   }
-  ctx->tuned[shape_key(probs)] = {bR, bT};
+  ctx->tuned[shape_key(probs)] = bW;
   delete *plan_io;
   *plan_io = best;
   g_tiles = best->stats;
-  if (R_out) *R_out = bR;
-  if (T_out) *T_out = bT;
+  if (W_out) *W_out = bW;
   if (ms_out) *ms_out = best_ms;
   return GMOT_OK;
 }
@@ -1006,7 +1026,7 @@ static int validate_opts(const gmot_opts* o) {
   if (o->check_every < 0) return fail(GMOT_EINVAL, "check_every must be >= 0");
   if (o->precision != GMOT_PREC_FP32CORE && o->precision != GMOT_PREC_FP64)
     return fail(GMOT_EINVAL, "unknown precision");
-  if (o->schedule != GMOT_SCHED_LAYER && o->schedule != GMOT_SCHED_PER_EDGE)
+  if (o->schedule != GMOT_SCHED_LAYER && o->schedule != GMOT_SCHED_PER_NODE)
     return fail(GMOT_EINVAL, "unknown schedule");
   if (o->msg_passes != GMOT_PASSES_AUTO && o->msg_passes != GMOT_PASSES_TWO)
     return fail(GMOT_EINVAL, "unknown msg_passes");
@@ -1032,7 +1052,7 @@ static int eval_messages(gmot_problem* p, int only_class) {
     const int src_slot = p->slot_of_class(1 - c);
     for (int dk = 0; dk < 4; ++dk)
       if (!pl->items[c][dk].empty())
-        HIPCHK(launch_msg(pl->tables(c, dk), (int)pl->items[c][dk].size(), dk, pl->R, true, src_slot, s));
+        HIPCHK(launch_msg(pl->tables(c, dk), (int)pl->items[c][dk].size(), dk, pl->R, src_slot, s));
     HIPCHK(launch_node_eval(pl->tables(c, -1), (int)pl->nodes[c].size(), p->slot_of_class(c), s));
   }
   return GMOT_OK;
@@ -1544,9 +1564,7 @@ int gmot_batch_create(gmot_ctx* ctx, gmot_problem* const* probs, int32_t count, 
     b->probs.push_back(probs[i]);
   }
   HIPCHK(hipSetDevice(ctx->device));
-  int R, target;
-  choose_tiles(ctx, b->probs, &R, &target);
-  int rc = build_plan(ctx, b->probs, R, target, &b->plan);
+  int rc = build_plan(ctx, b->probs, choose_waves(ctx, b->probs), &b->plan);
   if (rc) return rc;
   *out = b.release();
   return GMOT_OK;
@@ -1572,17 +1590,17 @@ int gmot_batch_solve(gmot_batch* b, const gmot_opts* o, gmot_result* outs) {
   return solve_plan(b->plan, o, outs);
 }
 
-int gmot_problem_autotune(gmot_problem* p, int32_t* rows_per_lane, int32_t* target_blocks, double* best_ms) {
+int gmot_problem_autotune(gmot_problem* p, int32_t* waves_per_block, double* best_ms) {
   if (!p) return fail(GMOT_EINVAL, "null problem");
   if (p->E == 0) return GMOT_OK;
   HIPCHK(hipSetDevice(p->ctx->device));
-  return autotune(p->ctx, {p}, &p->plan, rows_per_lane, target_blocks, best_ms);
+  return autotune(p->ctx, {p}, &p->plan, waves_per_block, best_ms);
 }
 
-int gmot_batch_autotune(gmot_batch* b, int32_t* rows_per_lane, int32_t* target_blocks, double* best_ms) {
+int gmot_batch_autotune(gmot_batch* b, int32_t* waves_per_block, double* best_ms) {
   if (!b) return fail(GMOT_EINVAL, "null batch");
   HIPCHK(hipSetDevice(b->ctx->device));
-  return autotune(b->ctx, b->probs, &b->plan, rows_per_lane, target_blocks, best_ms);
+  return autotune(b->ctx, b->probs, &b->plan, waves_per_block, best_ms);
 }
 
 // ---- star warm-start data movement ------------------------------------------
@@ -1730,9 +1748,9 @@ const char* gmot_strerror(int code) {
 
 const char* gmot_last_error(void) { return g_last_error.c_str(); }
 
-int gmot_last_tiles(int32_t* rows_per_block, int32_t* max_splits, int32_t* blocks_c0, int32_t* blocks_c1) {
+int gmot_last_tiles(int32_t* rows_per_block, int32_t* waves_per_block, int32_t* blocks_c0, int32_t* blocks_c1) {
   if (rows_per_block) *rows_per_block = g_tiles.rows;
-  if (max_splits) *max_splits = g_tiles.max_splits;
+  if (waves_per_block) *waves_per_block = g_tiles.max_splits;
   if (blocks_c0) *blocks_c0 = g_tiles.blocks[0];
   if (blocks_c1) *blocks_c1 = g_tiles.blocks[1];
   return GMOT_OK;

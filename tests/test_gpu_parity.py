@@ -283,20 +283,22 @@ def test_full_size_chain_converges(ctx):
     assert abs(e_sum - g.evaluate()["err_sum"]) <= 1e-9
 
 
-def test_per_edge_schedule_gives_identical_iterates(ctx):
-    """The per-edge schedule launches every message of a half-sweep separately;
-    the arithmetic per row is unchanged, so the iterates are bit-identical."""
+def test_per_node_schedule_gives_identical_iterates(ctx):
+    """The per-node schedule launches the tiles of each node of a half-sweep
+    separately, node after node; the arithmetic per row is unchanged, so the
+    iterates are bit-identical."""
     p = make_random_tree(n_nodes=12, n_lo=30, n_hi=400, eps=5e-3, dim=2, cfg_id=3, instance=9)
     a = gpu_problem(ctx, p)
     b = gpu_problem(ctx, p)
     ra = a.solve(tol=0.0, max_steps=15)
-    rb = b.solve(tol=0.0, max_steps=15, schedule="per_edge")
+    rb = b.solve(tol=0.0, max_steps=15, schedule="per_node")
     assert ra["steps"] == rb["steps"] == 15
     assert np.array_equal(a.potentials(), b.potentials())
 
 
 def test_one_pass_matches_two_pass(ctx):
-    """The one-pass message sums (shifted by the previous row max) and the
+    """The one-pass message sums (shifted by the previous max of each row and
+    column range) and the
     two-pass sums give the same FP32-core iterates within the FP32-core
     tolerance, and both match the oracle after the same half-sweeps."""
     cases = [make_chain(n_nodes=12, n=200, eps=1e-3),
