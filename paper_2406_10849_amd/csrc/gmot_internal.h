@@ -71,13 +71,13 @@ struct K1Item {
   int32_t msg, row0, col0, ncols, split, inst, pad0, pad1;
 };
 
-constexpr int kNodeRows = 64;   // rows per block of the node kernel (one per lane)
+constexpr int kNodeRowsLane = 64;  // rows per node-kernel tile per row-per-lane (tile = 64 * R rows)
 constexpr int kMaxWaves = 8;    // waves per node-kernel block: 2, 4 or 8
 constexpr int kRecExtra = 2;    // tile record entries after the per-edge terms
 
 // One node of the class being updated; its deg incoming messages are
 // msgs[msg0 .. msg0 + deg) in ascending neighbour order.  Its rows form
-// `tiles` tiles of kNodeRows; tile records (deg stopping-sum terms, then the
+// `tiles` tiles of 64 R rows; tile records (deg stopping-sum terms, then the
 // tile's LSE max and scaled sum of abar) start at tpart + tile * (deg + kRecExtra).
 struct NodeItem {
   int32_t inst, node, n, deg;
@@ -90,7 +90,7 @@ struct NodeItem {
   double* tpart;             // tile records
 };
 
-// One block of the node kernel: rows [row0, row0 + kNodeRows) of node item
+// One block of the node kernel: rows [row0, row0 + 64 R) of node item
 // `node` of instance `inst` (carried here so the instance state and the node
 // item load in parallel).
 struct TileItem {
@@ -165,8 +165,10 @@ struct RoundNode {
 // ---- launch wrappers (defined in gmot_kernels.hip) ----
 // FP64 evaluation messages from potential slot src_slot of the source class
 hipError_t launch_msg(const Tables& tb, int n_items, int dim, int rows_per_lane, int src_slot, hipStream_t s);
-// node kernel over n_tiles tiles of one class and support-dimension group (dim 0: explicit cost)
-hipError_t launch_node(const Tables& tb, int n_tiles, int dim, int waves, bool fp64, hipStream_t s);
+// node kernel over n_tiles tiles of one class and support-dimension group (dim 0: explicit
+// cost); tiles of 64 * rows_per_lane rows
+hipError_t launch_node(const Tables& tb, int n_tiles, int dim, int waves, int rows_per_lane, bool fp64,
+                       hipStream_t s);
 hipError_t launch_finalize(const Tables& tb, int n_inst, hipStream_t s);
 hipError_t launch_node_eval(const Tables& tb, int n_nodes, int slot, hipStream_t s);
 // dst[i] = src[i] - (c ? *c : 0) over segments (potential read-back on the device)
@@ -209,7 +211,7 @@ struct gmot_ctx {
   hipStream_t stream = nullptr;
   bool own_stream = false;
   double clk_hz = 1.0e8;
-  std::map<uint64_t, int> tuned;  // shape key -> waves per node-kernel block
+  std::map<uint64_t, std::pair<int, int>> tuned;  // shape key -> (waves per block, rows per lane)
   void* scratch = nullptr;                         // small tables of the warm-start calls
   size_t scratch_size = 0;
 };

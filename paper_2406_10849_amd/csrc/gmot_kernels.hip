@@ -272,13 +272,14 @@ __device__ inline void wave_sync() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-template <int DIM, int W, bool F64, bool EXPL>
+template <int DIM, int W, int R, bool F64, bool EXPL>
 __global__ __launch_bounds__(64 * W) void k_node(Tables tb) {
   constexpr int CH = EXPL ? 32 : 64;                 // columns per wave chunk
   constexpr int STR = EXPL ? 1 : (DIM == 1 ? 2 : 4); // doubles per staged column
+  constexpr int TR = 64 * R;                         // rows per tile
   __shared__ double s_col[W][CH * STR];
-  __shared__ double2 s_part[2][W][64];
-  __shared__ double s_m[kNodeDegLDS][64];
+  __shared__ double2 s_part[2][W][TR];
+  __shared__ double s_m[kNodeDegLDS][TR];
 
   const TileItem ti = tb.tiles[blockIdx.x];
   const InstState* st = tb.inst + ti.inst;
@@ -291,18 +292,24 @@ __global__ __launch_bounds__(64 * W) void k_node(Tables tb) {
   const MsgDesc* __restrict__ mds = tb.msgs + nd.msg0;
   const int n = nd.n, deg = nd.deg;
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  const int x = ti.row0 + lane;
-  const bool vx = x < n;
+  int x[R];
+  bool vx[R];
   const double eps = mds[0].eps;
   const double cxs = 2.0 * kLog2e / eps;
   const double ces = -kLog2e / eps;
-  double cx[DIM > 0 ? DIM : 1];
-  double x2 = 0.0;
+  double cx[R][DIM > 0 ? DIM : 1];
+  double x2[R];
 #pragma unroll
-  for (int d = 0; d < DIM; ++d) {
-    const double v = (vx && !EXPL) ? mds[0].supp_dst[(size_t)x * DIM + d] : 0.0;
-    cx[d] = cxs * v;
-    x2 = fma(v, v, x2);
+  for (int r = 0; r < R; ++r) {
+    x[r] = ti.row0 + r * 64 + lane;
+    vx[r] = x[r] < n;
+    x2[r] = 0.0;
+#pragma unroll
+    for (int d = 0; d < DIM; ++d) {
+      const double v = (vx[r] && !EXPL) ? mds[0].supp_dst[(size_t)x[r] * DIM + d] : 0.0;
+      cx[r][d] = cxs * v;
+      x2[r] = fma(v, v, x2[r]);
+    }
   }
   double* __restrict__ stage = s_col[wv];
 
@@ -359,119 +366,178 @@ __global__ __launch_bounds__(64 * W) void k_node(Tables tb) {
       fetch_chunk(c0, cn);
       stage_fetched();
     };
-    float cv[EXPL ? CH : 1];
+    float cv[EXPL ? R : 1][EXPL ? CH : 1];
     auto load_cost = [&](int c0, int cn) {
       if (EXPL) {
 #pragma unroll
-        for (int c = 0; c < CH; ++c) cv[c] = (vx && c < cn) ? cost[(size_t)(c0 + c) * n + x] : 0.0f;
+        for (int r = 0; r < R; ++r)
+#pragma unroll
+          for (int c = 0; c < CH; ++c)
+            cv[r][c] = (vx[r] && c < cn) ? cost[(size_t)(c0 + c) * n + x[r]] : 0.0f;
       }
     };
-    auto wcol = [&](int c) -> double {
-      double w = stage[c * STR];
+    auto wcol = [&](int r, int c, double a) -> double {
+      double w = a;
       if (EXPL) {
-        w = fma(ces, (double)cv[c], w);
+        w = fma(ces, (double)cv[r][c], w);
       } else {
 #pragma unroll
-        for (int d = 0; d < DIM; ++d) w = fma(cx[d], stage[c * STR + 1 + d], w);
+        for (int d = 0; d < DIM; ++d) w = fma(cx[r][d], stage[c * STR + 1 + d], w);
       }
       return w;
     };
-    // sum of 2^(w - sh) over the staged chunk (padded columns give 0)
-    auto chunk_sum = [&](double sh) -> double {
-      double S = 0.0;
-#pragma unroll 8
+    // sums of 2^(w - sh[r]) over the staged chunk (padded columns give 0)
+    auto chunk_sum = [&](const double* sh, double* Sc) {
+#pragma unroll
+      for (int r = 0; r < R; ++r) Sc[r] = 0.0;
+#pragma unroll 4
       for (int c = 0; c < CH; c += 2) {
-        const double w0 = wcol(c), w1 = wcol(c + 1);
-        if (F64) {
-          S += exp2(w0 - sh) + exp2(w1 - sh);
-        } else {
-          const float p = exp2_hw((float)(w0 - sh)) + exp2_hw((float)(w1 - sh));
-          S += (double)p;
+        const double a0 = stage[c * STR], a1 = stage[(c + 1) * STR];
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+          const double w0 = wcol(r, c, a0), w1 = wcol(r, c + 1, a1);
+          if (F64) {
+            Sc[r] += exp2(w0 - sh[r]) + exp2(w1 - sh[r]);
+          } else {
+            const float p = exp2_hw((float)(w0 - sh[r])) + exp2_hw((float)(w1 - sh[r]));
+            Sc[r] += (double)p;
+          }
         }
       }
-      return S;
     };
-    auto chunk_max = [&]() -> double {
-      double M = -INFINITY;
-#pragma unroll 8
-      for (int c = 0; c < CH; ++c) M = fmax(M, wcol(c));
-      return M;
+    auto chunk_max = [&](double* Mc) {
+#pragma unroll
+      for (int r = 0; r < R; ++r) Mc[r] = -INFINITY;
+#pragma unroll 4
+      for (int c = 0; c < CH; ++c) {
+        const double a = stage[c * STR];
+#pragma unroll
+        for (int r = 0; r < R; ++r) Mc[r] = fmax(Mc[r], wcol(r, c, a));
+      }
     };
 
-    double M = -INFINITY, S = 0.0;
+    double M[R], S[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      M[r] = -INFINITY;
+      S[r] = 0.0;
+    }
     bool two = !one;
     if (one) {
-      const double pm = vx ? wmax[(size_t)wv * n + x] : 0.0;
-      double sh = isfinite(pm) ? pm : 0.0;
+      double sh[R];
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        const double pm = vx[r] ? wmax[(size_t)wv * n + x[r]] : 0.0;
+        sh[r] = isfinite(pm) ? pm : 0.0;
+      }
       if (c_lo < c_hi) fetch_chunk(c_lo, min(CH, c_hi - c_lo));
       for (int c0 = c_lo; c0 < c_hi; c0 += CH) {
         const int cn = min(CH, c_hi - c0);
         load_cost(c0, cn);
         stage_fetched();
         if (c0 + CH < c_hi) fetch_chunk(c0 + CH, min(CH, c_hi - c0 - CH));
-        // one pass: sum relative to the shift, chunk max alongside
-        double Mc = -INFINITY, Sc = 0.0;
-#pragma unroll 8
+        // one pass: sums relative to the shifts, chunk maxima alongside
+        double Mc[R], Sc[R];
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+          Mc[r] = -INFINITY;
+          Sc[r] = 0.0;
+        }
+#pragma unroll 4
         for (int c = 0; c < CH; c += 2) {
-          const double w0 = wcol(c), w1 = wcol(c + 1);
-          Mc = fmax(Mc, fmax(w0, w1));
-          const float p = exp2_hw((float)(w0 - sh)) + exp2_hw((float)(w1 - sh));
-          Sc += (double)p;
-        }
-        if (__any(vx && Mc - sh > kShiftHi)) {
-          if (Mc - sh > kShiftHi) {
-            S *= exp2(sh - Mc);
-            sh = Mc;
+          const double a0 = stage[c * STR], a1 = stage[(c + 1) * STR];
+#pragma unroll
+          for (int r = 0; r < R; ++r) {
+            const double w0 = wcol(r, c, a0), w1 = wcol(r, c + 1, a1);
+            Mc[r] = fmax(Mc[r], fmax(w0, w1));
+            const float p = exp2_hw((float)(w0 - sh[r])) + exp2_hw((float)(w1 - sh[r]));
+            Sc[r] += (double)p;
           }
-          Sc = chunk_sum(sh);
         }
-        M = fmax(M, Mc);
-        S += Sc;
+        int hi = 0;
+#pragma unroll
+        for (int r = 0; r < R; ++r) hi |= (vx[r] && Mc[r] - sh[r] > kShiftHi) ? 1 : 0;
+        if (__any(hi)) {
+#pragma unroll
+          for (int r = 0; r < R; ++r) {
+            if (Mc[r] - sh[r] > kShiftHi) {
+              S[r] *= exp2(sh[r] - Mc[r]);
+              sh[r] = Mc[r];
+            }
+          }
+          chunk_sum(sh, Sc);
+        }
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+          M[r] = fmax(M[r], Mc[r]);
+          S[r] += Sc[r];
+        }
         wave_sync();
       }
-      if (__any(vx && M > -INFINITY && M - sh < kShiftLo)) {
-        two = true;  // the row's terms fell out of FP32 range: two passes
+      int lo = 0;
+#pragma unroll
+      for (int r = 0; r < R; ++r) lo |= (vx[r] && M[r] > -INFINITY && M[r] - sh[r] < kShiftLo) ? 1 : 0;
+      if (__any(lo)) {
+        two = true;  // a row's terms fell out of FP32 range: two passes
       } else {
-        S = (M > -INFINITY) ? S * exp2(sh - M) : 0.0;
+#pragma unroll
+        for (int r = 0; r < R; ++r) S[r] = (M[r] > -INFINITY) ? S[r] * exp2(sh[r] - M[r]) : 0.0;
       }
     }
     if (two) {
-      M = -INFINITY;
-      S = 0.0;
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        M[r] = -INFINITY;
+        S[r] = 0.0;
+      }
       for (int c0 = c_lo; c0 < c_hi; c0 += CH) {
         const int cn = min(CH, c_hi - c0);
         load_cost(c0, cn);
         stage_chunk(c0, cn);
-        const double Mc = chunk_max();
-        if (Mc > M) {
-          S *= exp2(M - Mc);  // 0 when M = -inf and S = 0
-          M = Mc;
+        double Mc[R], Sc[R], sh[R];
+        chunk_max(Mc);
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+          if (Mc[r] > M[r]) {
+            S[r] *= exp2(M[r] - Mc[r]);  // 0 when M = -inf and S = 0
+            M[r] = Mc[r];
+          }
+          sh[r] = M[r] == -INFINITY ? 0.0 : M[r];
         }
-        S += chunk_sum(M == -INFINITY ? 0.0 : M);
+        chunk_sum(sh, Sc);
+#pragma unroll
+        for (int r = 0; r < R; ++r) S[r] += Sc[r];
         wave_sync();
       }
     }
-    if (vx) wmax[(size_t)wv * n + x] = M;
-    s_part[k & 1][wv][lane] = make_double2(M, S);
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      if (vx[r]) wmax[(size_t)wv * n + x[r]] = M[r];
+      s_part[k & 1][wv][r * 64 + lane] = make_double2(M[r], S[r]);
+    }
     __syncthreads();
     if (wv == k % W) {
       // merge the W column ranges of edge k for the tile's rows
-      double Mx = -INFINITY;
 #pragma unroll
-      for (int u = 0; u < W; ++u) Mx = fmax(Mx, s_part[k & 1][u][lane].x);
-      double St = 0.0;
-      if (Mx > -INFINITY) {
+      for (int r = 0; r < R; ++r) {
+        const int lr = r * 64 + lane;
+        double Mx = -INFINITY;
 #pragma unroll
-        for (int u = 0; u < W; ++u) {
-          const double2 q = s_part[k & 1][u][lane];
-          if (q.y > 0.0) St += (q.x == Mx) ? q.y : q.y * exp2(q.x - Mx);
+        for (int u = 0; u < W; ++u) Mx = fmax(Mx, s_part[k & 1][u][lr].x);
+        double St = 0.0;
+        if (Mx > -INFINITY) {
+#pragma unroll
+          for (int u = 0; u < W; ++u) {
+            const double2 q = s_part[k & 1][u][lr];
+            if (q.y > 0.0) St += (q.x == Mx) ? q.y : q.y * exp2(q.x - Mx);
+          }
         }
-      }
-      const double m = (Mx > -INFINITY && St > 0.0) ? kLn2 * (Mx + log2(St)) - x2 / eps : -INFINITY;
-      if (k < kNodeDegLDS) {
-        s_m[k][lane] = m;
-      } else if (vx) {
-        md.mfull[x] = m;
+        const double m = (Mx > -INFINITY && St > 0.0) ? kLn2 * (Mx + log2(St)) - x2[r] / eps : -INFINITY;
+        if (k < kNodeDegLDS) {
+          s_m[k][lr] = m;
+        } else if (vx[r]) {
+          md.mfull[x[r]] = m;
+        }
       }
     }
   }
@@ -482,38 +548,52 @@ __global__ __launch_bounds__(64 * W) void k_node(Tables tb) {
   // and the tile record
   const bool fixed = nd.fixed != 0;
   const double c_old = nd.c ? nd.c[cur] : 0.0;
-  const double mux = (vx && fixed) ? nd.mu[x] : 0.0;
-  double* __restrict__ rec = nd.tpart + (size_t)(ti.row0 / kNodeRows) * (deg + kRecExtra);
-  auto mval = [&](int k) -> double { return k < kNodeDegLDS ? s_m[k][lane] : (vx ? mds[k].mfull[x] : 0.0); };
-  double asum = 0.0, qsum = 0.0;
-  for (int k = 0; k < deg; ++k) {
-    if (!vx) break;
-    const double m = mval(k);
-    asum += m;
-    if (!fixed) qsum += exp(mds[k].lam_dst[cur][x] - c_old + m);
+  double* __restrict__ rec = nd.tpart + (size_t)(ti.row0 / TR) * (deg + kRecExtra);
+  double mux[R], a[R], qb[R];
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    mux[r] = (vx[r] && fixed) ? nd.mu[x[r]] : 0.0;
+    const int lr = r * 64 + lane;
+    double asum = 0.0, qsum = 0.0;
+    if (vx[r]) {
+      for (int k = 0; k < deg; ++k) {
+        const double m = k < kNodeDegLDS ? s_m[k][lr] : mds[k].mfull[x[r]];
+        asum += m;
+        if (!fixed) qsum += exp(mds[k].lam_dst[cur][x[r]] - c_old + m);
+      }
+    }
+    a[r] = vx[r] ? asum / deg : -INFINITY;
+    qb[r] = qsum / deg;
   }
-  const double a = vx ? asum / deg : -INFINITY;
-  const double qb = qsum / deg;
   for (int k = 0; k < deg; ++k) {
     double part = 0.0;
-    if (vx) {
-      const double m = mval(k);
-      const double l = mds[k].lam_dst[cur][x];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      if (!vx[r]) continue;
+      const int lr = r * 64 + lane;
+      const double m = k < kNodeDegLDS ? s_m[k][lr] : mds[k].mfull[x[r]];
+      const double l = mds[k].lam_dst[cur][x[r]];
       double* __restrict__ Ln = mds[k].lam_dst[nxt];
       if (fixed) {
-        if (mux > 0.0) part = mux * fabs(expm1(l + m));
-        Ln[x] = -m;
+        if (mux[r] > 0.0) part += mux[r] * fabs(expm1(l + m));
+        Ln[x[r]] = -m;
       } else {
-        part = fabs(exp(l - c_old + m) - qb);
-        Ln[x] = a - m;
+        part += fabs(exp(l - c_old + m) - qb[r]);
+        Ln[x[r]] = a[r] - m;
       }
     }
     part = wave_sum(part);
     if (lane == 0) rec[k] = part;
   }
   if (!fixed) {
-    const double Mw = wave_max(a);
-    const double Sw = wave_sum((a > -INFINITY) ? exp(a - Mw) : 0.0);
+    double am = -INFINITY;
+#pragma unroll
+    for (int r = 0; r < R; ++r) am = fmax(am, a[r]);
+    const double Mw = wave_max(am);
+    double sv = 0.0;
+#pragma unroll
+    for (int r = 0; r < R; ++r) sv += (a[r] > -INFINITY) ? exp(a[r] - Mw) : 0.0;
+    const double Sw = wave_sum(sv);
     if (lane == 0) {
       rec[deg] = Mw;
       rec[deg + 1] = Sw;
@@ -769,31 +849,41 @@ hipError_t launch_msg(const Tables& tb, int n_items, int dim, int rows_per_lane,
                             : launch_msg_r<1>(tb, n_items, dim, src_slot, s);
 }
 
-template <int DIM, int W, bool F64, bool EXPL>
+template <int DIM, int W, int R, bool F64, bool EXPL>
 static hipError_t launch_node_t(const Tables& tb, int n_tiles, hipStream_t s) {
-  hipLaunchKernelGGL((k_node<DIM, W, F64, EXPL>), dim3(n_tiles), dim3(64 * W), 0, s, tb);
+  hipLaunchKernelGGL((k_node<DIM, W, R, F64, EXPL>), dim3(n_tiles), dim3(64 * W), 0, s, tb);
   return hipGetLastError();
 }
 
-template <int W, bool F64>
+template <int W, int R, bool F64>
 static hipError_t launch_node_w(const Tables& tb, int n_tiles, int dim, hipStream_t s) {
   switch (dim) {
-    case 0: return launch_node_t<1, W, F64, true>(tb, n_tiles, s);  // explicit cost
-    case 1: return launch_node_t<1, W, F64, false>(tb, n_tiles, s);
-    case 2: return launch_node_t<2, W, F64, false>(tb, n_tiles, s);
-    case 3: return launch_node_t<3, W, F64, false>(tb, n_tiles, s);
+    case 0:  // explicit cost (one row per lane only)
+      if (R != 1) return hipErrorInvalidValue;
+      return launch_node_t<1, W, 1, F64, true>(tb, n_tiles, s);
+    case 1: return launch_node_t<1, W, R, F64, false>(tb, n_tiles, s);
+    case 2: return launch_node_t<2, W, R, F64, false>(tb, n_tiles, s);
+    case 3: return launch_node_t<3, W, R, F64, false>(tb, n_tiles, s);
     default: return hipErrorInvalidValue;
   }
 }
 
-hipError_t launch_node(const Tables& tb, int n_tiles, int dim, int waves, bool fp64, hipStream_t s) {
-  if (n_tiles <= 0) return hipSuccess;
+template <int R>
+static hipError_t launch_node_r(const Tables& tb, int n_tiles, int dim, int waves, bool fp64, hipStream_t s) {
   switch (waves) {
-    case 2: return fp64 ? launch_node_w<2, true>(tb, n_tiles, dim, s) : launch_node_w<2, false>(tb, n_tiles, dim, s);
-    case 4: return fp64 ? launch_node_w<4, true>(tb, n_tiles, dim, s) : launch_node_w<4, false>(tb, n_tiles, dim, s);
-    case 8: return fp64 ? launch_node_w<8, true>(tb, n_tiles, dim, s) : launch_node_w<8, false>(tb, n_tiles, dim, s);
+    case 2: return fp64 ? launch_node_w<2, R, true>(tb, n_tiles, dim, s) : launch_node_w<2, R, false>(tb, n_tiles, dim, s);
+    case 4: return fp64 ? launch_node_w<4, R, true>(tb, n_tiles, dim, s) : launch_node_w<4, R, false>(tb, n_tiles, dim, s);
+    case 8: return fp64 ? launch_node_w<8, R, true>(tb, n_tiles, dim, s) : launch_node_w<8, R, false>(tb, n_tiles, dim, s);
     default: return hipErrorInvalidValue;
   }
+}
+
+hipError_t launch_node(const Tables& tb, int n_tiles, int dim, int waves, int rows_per_lane, bool fp64,
+                       hipStream_t s) {
+  if (n_tiles <= 0) return hipSuccess;
+  if (rows_per_lane == 1) return launch_node_r<1>(tb, n_tiles, dim, waves, fp64, s);
+  if (rows_per_lane == 2 && dim > 0) return launch_node_r<2>(tb, n_tiles, dim, waves, fp64, s);
+  return hipErrorInvalidValue;  // explicit-cost tiles take one row per lane
 }
 
 hipError_t launch_finalize(const Tables& tb, int n_inst, hipStream_t s) {

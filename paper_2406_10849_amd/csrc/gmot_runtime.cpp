@@ -115,6 +115,7 @@ struct Plan {
   gmot_ctx* ctx = nullptr;
   std::vector<gmot_problem*> probs;
   int W = 4;                 // waves per node-kernel block
+  int NR = 1;                // node-kernel rows per lane (tiles of 64 * NR rows)
   int R = 1;                 // evaluation message kernel: rows per lane
   int target_blocks = 1024;  // evaluation message kernel: blocks per class (via column splits)
   std::vector<MsgDesc> msgs;
@@ -172,14 +173,14 @@ struct Plan {
     for (int dk = 0; dk < 4; ++dk) {
       if (tiles[c][dk].empty()) continue;
       if (!per_node) {
-        e = launch_node(tables(c, dk), (int)tiles[c][dk].size(), dk, W, fp64, s);
+        e = launch_node(tables(c, dk), (int)tiles[c][dk].size(), dk, W, NR, fp64, s);
         if (e != hipSuccess) return e;
         continue;
       }
       for (const auto& r : node_tiles[c][dk]) {
         Tables tb = tables(c, dk);
         tb.tiles += r.first;
-        e = launch_node(tb, r.second, dk, W, fp64, s);
+        e = launch_node(tb, r.second, dk, W, NR, fp64, s);
         if (e != hipSuccess) return e;
       }
     }
@@ -213,11 +214,17 @@ struct Plan {
 // ---------------------------------------------------------------------------
 // plan construction
 // ---------------------------------------------------------------------------
-static int build_plan(gmot_ctx* ctx, const std::vector<gmot_problem*>& probs, int W, Plan** out) {
+static int build_plan(gmot_ctx* ctx, const std::vector<gmot_problem*>& probs, int W, int NR, Plan** out) {
   std::unique_ptr<Plan> pl(new Plan());
   pl->ctx = ctx;
   pl->probs = probs;
+  // explicit-cost tiles keep one row per lane (each lane holds its rows' cost
+  // chunk in registers)
+  for (const gmot_problem* p : probs)
+    if (p->cost_kind == GMOT_COST_EXPLICIT) NR = 1;
   pl->W = W;
+  pl->NR = NR;
+  const int TRows = kNodeRowsLane * NR;
   const int R = pl->R, target_blocks = pl->target_blocks;
   const int TM = 256 * R;
   // node tiles per (class, dimension group), with each node's work (pairs) for ordering
@@ -248,7 +255,7 @@ static int build_plan(gmot_ctx* ctx, const std::vector<gmot_problem*>& probs, in
         nd.abar = p->d_abar + p->node_off[j];
         nd.qbar = p->d_qbar + p->node_off[j];
         nd.c = p->fixed[j] ? nullptr : p->d_c + 2 * j;
-        nd.tiles = (int)ceil_div(p->sizes[j], kNodeRows);
+        nd.tiles = (int)ceil_div(p->sizes[j], TRows);
         {
           double src_cols = 0.0;
           for (int k : p->nbrs[j]) src_cols += p->sizes[k];
@@ -336,7 +343,7 @@ static int build_plan(gmot_ctx* ctx, const std::vector<gmot_problem*>& probs, in
                        [](const NodeTiles& u, const NodeTiles& v) { return u.work > v.work; });
       for (const NodeTiles& q : ntl[c][dk]) {
         pl->node_tiles[c][dk].push_back({(int)pl->tiles[c][dk].size(), q.n_tiles});
-        for (int r = 0; r < q.n_tiles; ++r) pl->tiles[c][dk].push_back({q.node_item, r * kNodeRows, q.inst, 0});
+        for (int r = 0; r < q.n_tiles; ++r) pl->tiles[c][dk].push_back({q.node_item, r * TRows, q.inst, 0});
       }
     }
   int64_t wmax_total = 0;
@@ -353,7 +360,7 @@ static int build_plan(gmot_ctx* ctx, const std::vector<gmot_problem*>& probs, in
       tpart_off[c].push_back(tpart_total);
       tpart_total += (int64_t)nd.tiles * (nd.deg + kRecExtra);
     }
-  pl->stats.rows = kNodeRows;
+  pl->stats.rows = TRows;
   pl->stats.max_splits = W;
   for (int c = 0; c < 2; ++c) {
     pl->stats.blocks[c] = 0;
@@ -447,18 +454,20 @@ static uint64_t shape_key(const std::vector<gmot_problem*>& probs) {
 }
 
 constexpr int kDefaultWaves = 4;
+constexpr int kDefaultRowsLane = 2;
 
-// Waves per node-kernel block: a tuned choice cached in the context for these
-// shapes, else the default; GMOT_WAVES=2|4|8 overrides both.
-static int choose_waves(gmot_ctx* ctx, const std::vector<gmot_problem*>& probs) {
-  int W = kDefaultWaves;
+// Node-kernel block shape (waves per block, rows per lane): a tuned choice
+// cached in the context for these shapes, else the default; GMOT_NODE_SHAPE="W,R"
+// (W in 2, 4, 8; R in 1, 2) overrides both.
+static std::pair<int, int> choose_shape(gmot_ctx* ctx, const std::vector<gmot_problem*>& probs) {
+  std::pair<int, int> wr{kDefaultWaves, kDefaultRowsLane};
   auto it = ctx->tuned.find(shape_key(probs));
-  if (it != ctx->tuned.end()) W = it->second;
-  if (const char* v = std::getenv("GMOT_WAVES")) {
-    const int w = std::atoi(v);
-    if (w == 2 || w == 4 || w == 8) W = w;
+  if (it != ctx->tuned.end()) wr = it->second;
+  if (const char* v = std::getenv("GMOT_NODE_SHAPE")) {
+    int w = 0, r = 0;
+    if (std::sscanf(v, "%d,%d", &w, &r) == 2 && (w == 2 || w == 4 || w == 8) && (r == 1 || r == 2)) wr = {w, r};
   }
-  return W;
+  return wr;
 }
 
 static int capture_one(Plan* pl, bool fp64, bool per_node, int start, int k, const std::vector<hipEvent_t>* ev,
@@ -921,7 +930,8 @@ static int upload(const gmot_tree_desc* d, gmot_problem* p) {
 
 static int ensure_plan(gmot_problem* p) {
   if (p->plan) return GMOT_OK;
-  return build_plan(p->ctx, {p}, choose_waves(p->ctx, {p}), &p->plan);
+  const auto wr = choose_shape(p->ctx, {p});
+  return build_plan(p->ctx, {p}, wr.first, wr.second, &p->plan);
 }
 
 // Mean device time of an FP32-core half-sweep (node stage and finalise
@@ -982,14 +992,14 @@ static int time_plan(Plan* pl, double* ms) {
 }
 
 static int autotune(gmot_ctx* ctx, const std::vector<gmot_problem*>& probs, Plan** plan_io, int32_t* W_out,
-                    double* ms_out) {
-  static const int kCand[] = {2, 4, 8};
+                    int32_t* R_out, double* ms_out) {
+  static const int kCand[][2] = {{2, 1}, {4, 1}, {8, 1}, {2, 2}, {4, 2}, {8, 2}};
   Plan* best = nullptr;
   double best_ms = INFINITY;
-  int bW = kDefaultWaves;
-  for (const int cand : kCand) {
+  std::pair<int, int> bWR{kDefaultWaves, kDefaultRowsLane};
+  for (const auto& cand : kCand) {
     Plan* pl = nullptr;
-    int rc = build_plan(ctx, probs, cand, &pl);
+    int rc = build_plan(ctx, probs, cand[0], cand[1], &pl);
     if (rc) {
       delete best;
       return rc;
@@ -1005,16 +1015,17 @@ static int autotune(gmot_ctx* ctx, const std::vector<gmot_problem*>& probs, Plan
       delete best;
       best = pl;
       best_ms = ms;
-      bW = cand;
+      bWR = {cand[0], cand[1]};
     } else {
       delete pl;
     }
   }
-  ctx->tuned[shape_key(probs)] = bW;
+  ctx->tuned[shape_key(probs)] = bWR;
   delete *plan_io;
   *plan_io = best;
   g_tiles = best->stats;
-  if (W_out) *W_out = bW;
+  if (W_out) *W_out = bWR.first;
+  if (R_out) *R_out = bWR.second;
   if (ms_out) *ms_out = best_ms;
   return GMOT_OK;
 }
@@ -1564,7 +1575,8 @@ int gmot_batch_create(gmot_ctx* ctx, gmot_problem* const* probs, int32_t count, 
     b->probs.push_back(probs[i]);
   }
   HIPCHK(hipSetDevice(ctx->device));
-  int rc = build_plan(ctx, b->probs, choose_waves(ctx, b->probs), &b->plan);
+  const auto wr = choose_shape(ctx, b->probs);
+  int rc = build_plan(ctx, b->probs, wr.first, wr.second, &b->plan);
   if (rc) return rc;
   *out = b.release();
   return GMOT_OK;
@@ -1590,17 +1602,17 @@ int gmot_batch_solve(gmot_batch* b, const gmot_opts* o, gmot_result* outs) {
   return solve_plan(b->plan, o, outs);
 }
 
-int gmot_problem_autotune(gmot_problem* p, int32_t* waves_per_block, double* best_ms) {
+int gmot_problem_autotune(gmot_problem* p, int32_t* waves_per_block, int32_t* rows_per_lane, double* best_ms) {
   if (!p) return fail(GMOT_EINVAL, "null problem");
   if (p->E == 0) return GMOT_OK;
   HIPCHK(hipSetDevice(p->ctx->device));
-  return autotune(p->ctx, {p}, &p->plan, waves_per_block, best_ms);
+  return autotune(p->ctx, {p}, &p->plan, waves_per_block, rows_per_lane, best_ms);
 }
 
-int gmot_batch_autotune(gmot_batch* b, int32_t* waves_per_block, double* best_ms) {
+int gmot_batch_autotune(gmot_batch* b, int32_t* waves_per_block, int32_t* rows_per_lane, double* best_ms) {
   if (!b) return fail(GMOT_EINVAL, "null batch");
   HIPCHK(hipSetDevice(b->ctx->device));
-  return autotune(b->ctx, b->probs, &b->plan, waves_per_block, best_ms);
+  return autotune(b->ctx, b->probs, &b->plan, waves_per_block, rows_per_lane, best_ms);
 }
 
 // ---- star warm-start data movement ------------------------------------------

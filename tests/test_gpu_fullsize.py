@@ -55,3 +55,26 @@ def test_batched_512_stars_sampled(ctx):
     rng = np.random.default_rng(0)
     for i in rng.choice(len(probs), size=8, replace=False):
         check_state(gps[i], probs[i], 1e-6)
+
+
+def test_chain_dual_matches_converged_reference():
+    """32-node chain (n = 1024, eps = 1e-3), solved to a stopping sum of 1e-6
+    on the device, against the FP64 oracle's state at a stopping sum of 1e-10
+    (tests/golden/chain32_n1024_converged.json, written by make_chain_golden.py,
+    which calls only the oracle).  Both duals are within 2 C_inf E of the
+    optimum (Lemma f_upper_bound_tree), so they agree to 1e-6 of the scale;
+    primals are within C_inf E of their duals, so they agree to
+    3 C_inf (E_gpu + E_ref)."""
+    import json
+    import os
+    from paper_2406_10849_amd import Context, Problem
+    ref = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "chain32_n1024_converged.json")))
+    p = make_config(2)
+    g = Problem(Context(0), p)
+    r = g.solve(tol=1e-6, max_steps=200000)
+    assert r["status"] == "converged"
+    ev = g.evaluate()
+    assert ev["err_sum"] <= 1e-6
+    assert abs(ev["dual"] - ref["dual"]) <= 1e-6 * ref["scale"]
+    assert abs(ev["dual"] - ref["dual"]) <= 2 * ref["c_inf"] * (ev["err_sum"] + ref["err_sum"])
+    assert abs(ev["primal"] - ref["primal"]) <= 3 * ref["c_inf"] * (ev["err_sum"] + ref["err_sum"])
