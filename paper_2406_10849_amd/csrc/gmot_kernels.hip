@@ -277,9 +277,13 @@ __global__ __launch_bounds__(64 * W) void k_node(Tables tb) {
   constexpr int CH = EXPL ? 32 : 64;                 // columns per wave chunk
   constexpr int STR = EXPL ? 1 : (DIM == 1 ? 2 : 4); // doubles per staged column
   constexpr int TR = 64 * R;                         // rows per tile
+  constexpr int NT = 64 * W;                         // threads per block
+  constexpr int NP = kNodeDegLDS > W ? kNodeDegLDS : W;
   __shared__ double s_col[W][CH * STR];
-  __shared__ double2 s_part[2][W][TR];
+  __shared__ double2 s_part[NP][TR];  // (edge, range) partials; then per-(edge, row) terms
   __shared__ double s_m[kNodeDegLDS][TR];
+  __shared__ double s_q[kNodeDegLDS][TR];
+  __shared__ double s_x2[TR];
 
   const TileItem ti = tb.tiles[blockIdx.x];
   const InstState* st = tb.inst + ti.inst;
@@ -291,6 +295,8 @@ __global__ __launch_bounds__(64 * W) void k_node(Tables tb) {
   const bool one = !F64 && t >= st->onepass_from;
   const MsgDesc* __restrict__ mds = tb.msgs + nd.msg0;
   const int n = nd.n, deg = nd.deg;
+  const bool lds = deg <= kNodeDegLDS;
+  const bool fixed = nd.fixed != 0;
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   int x[R];
   bool vx[R];
@@ -310,14 +316,23 @@ __global__ __launch_bounds__(64 * W) void k_node(Tables tb) {
       cx[r][d] = cxs * v;
       x2[r] = fma(v, v, x2[r]);
     }
+    if (wv == 0) s_x2[r * 64 + lane] = x2[r];
   }
   double* __restrict__ stage = s_col[wv];
 
-  for (int k = 0; k < deg; ++k) {
+  // Edges run on different waves: with deg >= W each wave takes whole edges
+  // (k = wv, wv + W, ...); otherwise g = W / deg waves share an edge, each
+  // summing one of g column ranges.
+  const int g = deg >= W ? 1 : W / deg;
+  const int k_first = deg >= W ? wv : (wv < deg * g ? wv / g : deg);
+  const int k_step = deg >= W ? W : deg;
+  const int sub = deg >= W ? 0 : wv % g;
+
+  for (int k = k_first; k < deg; k += k_step) {
     const MsgDesc& md = mds[k];
     const int n_src = md.n_src;
-    const int per = (n_src + W - 1) / W;
-    const int c_lo = min(wv * per, n_src), c_hi = min(c_lo + per, n_src);
+    const int per = (n_src + g - 1) / g;
+    const int c_lo = min(sub * per, n_src), c_hi = min(c_lo + per, n_src);
     const double* __restrict__ lam = md.lam_src[src_slot];
     const double csrc = md.c_src ? md.c_src[src_slot] : 0.0;
     const double* __restrict__ lg = md.lg_src;
@@ -427,7 +442,7 @@ __global__ __launch_bounds__(64 * W) void k_node(Tables tb) {
       double sh[R];
 #pragma unroll
       for (int r = 0; r < R; ++r) {
-        const double pm = vx[r] ? wmax[(size_t)wv * n + x[r]] : 0.0;
+        const double pm = vx[r] ? wmax[(size_t)sub * n + x[r]] : 0.0;
         sh[r] = isfinite(pm) ? pm : 0.0;
       }
       if (c_lo < c_hi) fetch_chunk(c_lo, min(CH, c_hi - c_lo));
@@ -512,52 +527,114 @@ __global__ __launch_bounds__(64 * W) void k_node(Tables tb) {
     }
 #pragma unroll
     for (int r = 0; r < R; ++r) {
-      if (vx[r]) wmax[(size_t)wv * n + x[r]] = M[r];
-      s_part[k & 1][wv][r * 64 + lane] = make_double2(M[r], S[r]);
-    }
-    __syncthreads();
-    if (wv == k % W) {
-      // merge the W column ranges of edge k for the tile's rows
-#pragma unroll
-      for (int r = 0; r < R; ++r) {
-        const int lr = r * 64 + lane;
-        double Mx = -INFINITY;
-#pragma unroll
-        for (int u = 0; u < W; ++u) Mx = fmax(Mx, s_part[k & 1][u][lr].x);
-        double St = 0.0;
-        if (Mx > -INFINITY) {
-#pragma unroll
-          for (int u = 0; u < W; ++u) {
-            const double2 q = s_part[k & 1][u][lr];
-            if (q.y > 0.0) St += (q.x == Mx) ? q.y : q.y * exp2(q.x - Mx);
-          }
-        }
-        const double m = (Mx > -INFINITY && St > 0.0) ? kLn2 * (Mx + log2(St)) - x2[r] / eps : -INFINITY;
-        if (k < kNodeDegLDS) {
-          s_m[k][lr] = m;
-        } else if (vx[r]) {
-          md.mfull[x[r]] = m;
-        }
+      if (vx[r]) wmax[(size_t)sub * n + x[r]] = M[r];
+      if (lds) {
+        s_part[k * g + sub][r * 64 + lane] = make_double2(M[r], S[r]);
+      } else if (vx[r]) {
+        // one range per edge (g = 1): the message goes straight to mfull
+        md.mfull[x[r]] = (M[r] > -INFINITY && S[r] > 0.0) ? kLn2 * (M[r] + log2(S[r])) - x2[r] / eps : -INFINITY;
       }
     }
   }
   __syncthreads();
-  if (wv != 0) return;
-
-  // wave 0: stopping-sum terms of the state before the update, the update,
-  // and the tile record
-  const bool fixed = nd.fixed != 0;
-  const double c_old = nd.c ? nd.c[cur] : 0.0;
   double* __restrict__ rec = nd.tpart + (size_t)(ti.row0 / TR) * (deg + kRecExtra);
+  const double c_old = nd.c ? nd.c[cur] : 0.0;
+
+  if (lds) {
+    // merge the g ranges of every (edge, row) into m (natural log)
+    for (int it = threadIdx.x; it < deg * TR; it += NT) {
+      const int k = it / TR, lr = it - k * TR;
+      double Mx = -INFINITY;
+      for (int u = 0; u < g; ++u) Mx = fmax(Mx, s_part[k * g + u][lr].x);
+      double St = 0.0;
+      if (Mx > -INFINITY) {
+        for (int u = 0; u < g; ++u) {
+          const double2 q = s_part[k * g + u][lr];
+          if (q.y > 0.0) St += (q.x == Mx) ? q.y : q.y * exp2(q.x - Mx);
+        }
+      }
+      s_m[k][lr] = (Mx > -INFINITY && St > 0.0) ? kLn2 * (Mx + log2(St)) - s_x2[lr] / eps : -INFINITY;
+    }
+    __syncthreads();
+    // per (edge, row): q (free) or the term and update (constrained)
+    for (int it = threadIdx.x; it < deg * TR; it += NT) {
+      const int k = it / TR, lr = it - k * TR;
+      const int xr = ti.row0 + lr;
+      double term = 0.0;
+      if (xr < n) {
+        const double m = s_m[k][lr];
+        const double l = mds[k].lam_dst[cur][xr];
+        if (fixed) {
+          const double mu = nd.mu[xr];
+          if (mu > 0.0) term = mu * fabs(expm1(l + m));
+          mds[k].lam_dst[nxt][xr] = -m;
+        } else {
+          s_q[k][lr] = exp(l - c_old + m);
+        }
+      }
+      if (fixed) s_part[k][lr].x = term;
+    }
+    __syncthreads();
+    if (!fixed) {
+      // free node: abar and qbar per row, then the terms and the update
+      for (int it = threadIdx.x; it < deg * TR; it += NT) {
+        const int k = it / TR, lr = it - k * TR;
+        const int xr = ti.row0 + lr;
+        double term = 0.0;
+        if (xr < n) {
+          double as = 0.0, qs = 0.0;
+          for (int kk = 0; kk < deg; ++kk) {
+            as += s_m[kk][lr];
+            qs += s_q[kk][lr];
+          }
+          term = fabs(s_q[k][lr] - qs / deg);
+          mds[k].lam_dst[nxt][xr] = as / deg - s_m[k][lr];
+        }
+        s_part[k][lr].x = term;
+      }
+      __syncthreads();
+    }
+    // tile record: per-edge term sums (edge k on wave k mod W), then abar's LSE
+    for (int k = wv; k < deg; k += W) {
+      double part = 0.0;
+#pragma unroll
+      for (int r = 0; r < R; ++r) part += s_part[k][r * 64 + lane].x;
+      part = wave_sum(part);
+      if (lane == 0) rec[k] = part;
+    }
+    if (!fixed && wv == W - 1) {
+      double av[R], am = -INFINITY;
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        const int lr = r * 64 + lane;
+        double as = 0.0;
+        for (int kk = 0; kk < deg; ++kk) as += s_m[kk][lr];
+        av[r] = vx[r] ? as / deg : -INFINITY;
+        am = fmax(am, av[r]);
+      }
+      const double Mw = wave_max(am);
+      double sv = 0.0;
+#pragma unroll
+      for (int r = 0; r < R; ++r) sv += (av[r] > -INFINITY) ? exp(av[r] - Mw) : 0.0;
+      const double Sw = wave_sum(sv);
+      if (lane == 0) {
+        rec[deg] = Mw;
+        rec[deg + 1] = Sw;
+      }
+    }
+    return;
+  }
+
+  // more than kNodeDegLDS edges: wave 0 reads the messages from mfull
+  if (wv != 0) return;
   double mux[R], a[R], qb[R];
 #pragma unroll
   for (int r = 0; r < R; ++r) {
     mux[r] = (vx[r] && fixed) ? nd.mu[x[r]] : 0.0;
-    const int lr = r * 64 + lane;
     double asum = 0.0, qsum = 0.0;
     if (vx[r]) {
       for (int k = 0; k < deg; ++k) {
-        const double m = k < kNodeDegLDS ? s_m[k][lr] : mds[k].mfull[x[r]];
+        const double m = mds[k].mfull[x[r]];
         asum += m;
         if (!fixed) qsum += exp(mds[k].lam_dst[cur][x[r]] - c_old + m);
       }
@@ -570,8 +647,7 @@ __global__ __launch_bounds__(64 * W) void k_node(Tables tb) {
 #pragma unroll
     for (int r = 0; r < R; ++r) {
       if (!vx[r]) continue;
-      const int lr = r * 64 + lane;
-      const double m = k < kNodeDegLDS ? s_m[k][lr] : mds[k].mfull[x[r]];
+      const double m = mds[k].mfull[x[r]];
       const double l = mds[k].lam_dst[cur][x[r]];
       double* __restrict__ Ln = mds[k].lam_dst[nxt];
       if (fixed) {

@@ -17,6 +17,7 @@
 
 #include <algorithm>
 #include <chrono>
+#include <array>
 #include <cmath>
 #include <cstdio>
 #include <cstdlib>
@@ -994,10 +995,16 @@ static int time_plan(Plan* pl, double* ms) {
 static int autotune(gmot_ctx* ctx, const std::vector<gmot_problem*>& probs, Plan** plan_io, int32_t* W_out,
                     int32_t* R_out, double* ms_out) {
   static const int kCand[][2] = {{2, 1}, {4, 1}, {8, 1}, {2, 2}, {4, 2}, {8, 2}};
+  std::vector<std::array<int, 2>> cands;
+  for (const auto& c : kCand) cands.push_back({c[0], c[1]});
+  if (std::getenv("GMOT_NODE_SHAPE")) {  // a pinned shape is the only candidate
+    const auto wr = choose_shape(ctx, probs);
+    cands = {{wr.first, wr.second}};
+  }
   Plan* best = nullptr;
   double best_ms = INFINITY;
   std::pair<int, int> bWR{kDefaultWaves, kDefaultRowsLane};
-  for (const auto& cand : kCand) {
+  for (const auto& cand : cands) {
     Plan* pl = nullptr;
     int rc = build_plan(ctx, probs, cand[0], cand[1], &pl);
     if (rc) {
