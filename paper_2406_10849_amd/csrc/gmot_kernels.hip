@@ -319,6 +319,16 @@ __global__ __launch_bounds__(64 * W) void k_node(Tables tb) {
     if (wv == 0) s_x2[r * 64 + lane] = x2[r];
   }
   double* __restrict__ stage = s_col[wv];
+  // the held potential (and mu) of this thread's first (edge, row) item of the
+  // update phase, loaded now so that phase does not wait for memory
+  double l_item = 0.0, mu_item = 0.0;
+  if (deg <= kNodeDegLDS && (int)threadIdx.x < deg * TR) {
+    const int k = threadIdx.x / TR, xr = ti.row0 + (int)threadIdx.x - k * TR;
+    if (xr < n) {
+      l_item = mds[k].lam_dst[cur][xr];
+      if (nd.fixed) mu_item = nd.mu[xr];
+    }
+  }
 
   // Edges run on different waves: with deg >= W each wave takes whole edges
   // (k = wv, wv + W, ...); otherwise g = W / deg waves share an edge, each
@@ -344,20 +354,27 @@ __global__ __launch_bounds__(64 * W) void k_node(Tables tb) {
     // staged in the wave's LDS buffer; padded columns get a = -inf and y = 0,
     // so they add exactly nothing.  The one-pass loop fetches the next chunk
     // before summing the current one, so its loads overlap the arithmetic.
-    double f_base = -INFINITY;
-    double f_y[DIM > 0 ? DIM : 1];
-    auto fetch_chunk = [&](int c0, int cn) {
+    double f_base = -INFINITY, g_base = -INFINITY;
+    double f_y[DIM > 0 ? DIM : 1], g_y[DIM > 0 ? DIM : 1];
+    auto fetch_into = [&](int c0, int cn, double& base, double* y) {
       const int col = c0 + lane;
-      f_base = -INFINITY;
+      base = -INFINITY;
 #pragma unroll
-      for (int d = 0; d < DIM; ++d) f_y[d] = 0.0;
+      for (int d = 0; d < DIM; ++d) y[d] = 0.0;
       if (lane < cn) {
-        f_base = (lam[col] - csrc) + lg[col];
+        base = (lam[col] - csrc) + lg[col];
         if (!EXPL) {
 #pragma unroll
-          for (int d = 0; d < DIM; ++d) f_y[d] = ys[(size_t)col * DIM + d];
+          for (int d = 0; d < DIM; ++d) y[d] = ys[(size_t)col * DIM + d];
         }
       }
+    };
+    auto fetch_chunk = [&](int c0, int cn) { fetch_into(c0, cn, f_base, f_y); };
+    // the chunk after next goes to the second register set; move it up
+    auto advance = [&]() {
+      f_base = g_base;
+#pragma unroll
+      for (int d = 0; d < DIM; ++d) f_y[d] = g_y[d];
     };
     auto stage_fetched = [&]() {
       double a = f_base;
@@ -446,11 +463,13 @@ __global__ __launch_bounds__(64 * W) void k_node(Tables tb) {
         sh[r] = isfinite(pm) ? pm : 0.0;
       }
       if (c_lo < c_hi) fetch_chunk(c_lo, min(CH, c_hi - c_lo));
+      if (c_lo + CH < c_hi) fetch_into(c_lo + CH, min(CH, c_hi - c_lo - CH), g_base, g_y);
       for (int c0 = c_lo; c0 < c_hi; c0 += CH) {
         const int cn = min(CH, c_hi - c0);
         load_cost(c0, cn);
         stage_fetched();
-        if (c0 + CH < c_hi) fetch_chunk(c0 + CH, min(CH, c_hi - c0 - CH));
+        advance();
+        if (c0 + 2 * CH < c_hi) fetch_into(c0 + 2 * CH, min(CH, c_hi - c0 - 2 * CH), g_base, g_y);
         // one pass: sums relative to the shifts, chunk maxima alongside
         double Mc[R], Sc[R];
 #pragma unroll
@@ -563,9 +582,10 @@ __global__ __launch_bounds__(64 * W) void k_node(Tables tb) {
       double term = 0.0;
       if (xr < n) {
         const double m = s_m[k][lr];
-        const double l = mds[k].lam_dst[cur][xr];
+        const bool first = it == (int)threadIdx.x;
+        const double l = first ? l_item : mds[k].lam_dst[cur][xr];
         if (fixed) {
-          const double mu = nd.mu[xr];
+          const double mu = first ? mu_item : nd.mu[xr];
           if (mu > 0.0) term = mu * fabs(expm1(l + m));
           mds[k].lam_dst[nxt][xr] = -m;
         } else {

@@ -316,3 +316,42 @@ def test_one_pass_matches_two_pass(ctx):
             assert abs(g.evaluate()["dual"] - eo["dual"]) <= 1e-6 * eo["scale"]
         for e in range(0, p.n_edges, 3):
             assert np.max(np.abs(g1.coupling(e) - g2.coupling(e))) <= 1e-6
+
+
+@pytest.mark.parametrize("shape", ["2,1", "4,1", "8,1", "2,2", "4,2", "8,2"])
+def test_every_node_shape_matches_oracle(ctx, shape, monkeypatch):
+    """Each node-kernel block shape (waves per block, rows per lane), pinned
+    through GMOT_NODE_SHAPE, on a ragged 2D tree with a constrained interior
+    node and a star centre of degree 5: FP64 iterates to 1e-9 of the oracle
+    and FP32-core ones to 1e-6 (dual relative to the scale)."""
+    monkeypatch.setenv("GMOT_NODE_SHAPE", shape)
+    edges = [(0, 1), (0, 2), (0, 3), (0, 4), (0, 5), (5, 6), (6, 7)]
+    p = make_tree(edges, [300, 70, 129, 64, 1, 257, 190, 33], [0, 1, 1, 1, 1, 1, 0, 1], dim=2, eps=0.02,
+                  instance=60)
+    o = TreeOracle(p)
+    o.run_fixed(12)
+    eo = o.evaluate()
+    for precision, tol in (("fp64", 1e-9), ("fp32core", 1e-6)):
+        g = gpu_problem(ctx, p)
+        r = g.solve(tol=0.0, max_steps=12, precision=precision)
+        assert r["steps"] == 12
+        assert abs(g.evaluate()["dual"] - eo["dual"]) <= tol * eo["scale"]
+        for e in range(p.n_edges):
+            assert np.max(np.abs(g.coupling(e) - o.coupling(e))) <= tol
+
+
+def test_three_dimensional_supports(ctx):
+    """D = 3 supports (random points) on a small tree: FP64 iterates and a
+    converged FP32-core solve against the oracle."""
+    p = make_tree([(0, 1), (1, 2), (1, 3)], [90, 200, 65, 140], [1, 0, 1, 1], dim=3, eps=0.05, instance=61)
+    o = TreeOracle(p)
+    o.run_fixed(20)
+    g = gpu_problem(ctx, p)
+    g.solve(tol=0.0, max_steps=20, precision="fp64")
+    assert np.max(np.abs(g.potentials() - o.potentials())) <= 1e-9 * max(1.0, np.max(np.abs(o.potentials())))
+    r = g.solve(tol=1e-6, max_steps=100000)
+    assert r["status"] == "converged"
+    ref = TreeOracle(p)
+    ref.solve(tol=1e-10, max_steps=100000)
+    er = ref.evaluate()
+    converged_check(g, p, 1e-6, er["dual"], er["scale"])
