@@ -60,9 +60,10 @@ def kernel_sha() -> str:
     return hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest()[:16]
 
 
-def measured_traffic():
+def measured_traffic(shape):
     """HBM bytes per node-kernel launch from the committed rocprofv3 PMC
-    summary, valid only for the kernel source it was taken on."""
+    summary, valid only for the kernel source and node shape (waves per
+    block, rows per lane, lane groups) it was taken on."""
     if not os.path.exists(TRAFFIC_FILE):
         return None
     vals = {}
@@ -70,7 +71,7 @@ def measured_traffic():
         if ":" in line:
             k, v = line.split(":", 1)
             vals[k.strip()] = v.strip()
-    if vals.get("kernel_sha256_16") != kernel_sha():
+    if vals.get("kernel_sha256_16") != kernel_sha() or vals.get("shape") != "%d,%d,%d" % shape:
         return None
     try:
         return float(vals["fetch_bytes_per_launch"]) + float(vals["write_bytes_per_launch"])
@@ -305,7 +306,7 @@ def main() -> int:
     avg_ms = st["msg_ms"] / max(st["msg_launches"], 1)
     pairs_per_launch = st["msg_pairs"] / max(st["msg_launches"], 1)
     achieved = pairs_per_launch / (avg_ms / 1e3) / 1e9 if avg_ms > 0 else 0.0
-    traffic = measured_traffic()
+    traffic = measured_traffic((tuned["waves_per_block"], tuned["rows_per_lane"], tuned["lane_groups"]))
     out = {
         "metric": METRIC,
         "value": value,

@@ -297,16 +297,19 @@ int  gmot_mlp_warm_start(gmot_mlp* m, gmot_problem* const* probs, int32_t count,
                          float out_scale, int32_t* rejected);
 
 /* ---- tile autotuning ------------------------------------------------------------ */
-/* Time the candidate node-kernel block shapes (2, 4 or 8 waves per tile, the
- * waves splitting each edge's source columns; 1 or 2 rows per lane, i.e. tiles
- * of 64 or 128 rows) by the device time of a
+/* Time the candidate node-kernel block shapes (2, 4, 8 or 16 waves per tile, the
+ * waves splitting each edge's source columns; 1 or 2 rows per lane; 1 or 2 lane
+ * groups per wave, the groups of a wave splitting its columns again; tiles of
+ * 64 * rows_per_lane / lane_groups rows) by the device time of a
  * few real FP32-core half-sweeps (node stage and finalise kernel) run from a
  * snapshot of the held state, which is restored afterwards, and keep the
  * fastest plan; best_ms is that half-sweep time.
  * The choice is cached in the context under the instances' shapes, so later
  * problems or batches of the same shapes start with it.  Outputs may be NULL. */
-int  gmot_problem_autotune(gmot_problem* p, int32_t* waves_per_block, int32_t* rows_per_lane, double* best_ms);
-int  gmot_batch_autotune(gmot_batch* b, int32_t* waves_per_block, int32_t* rows_per_lane, double* best_ms);
+int  gmot_problem_autotune(gmot_problem* p, int32_t* waves_per_block, int32_t* rows_per_lane,
+                           int32_t* lane_groups, double* best_ms);
+int  gmot_batch_autotune(gmot_batch* b, int32_t* waves_per_block, int32_t* rows_per_lane,
+                         int32_t* lane_groups, double* best_ms);
 
 /* ---- diagnostics ----------------------------------------------------------- */
 /* Copy out (and, if reset != 0, clear) the kernel timing of a problem's own

@@ -150,9 +150,10 @@ class Problem:
 
     @staticmethod
     def _autotune(fn, h) -> dict:
-        w, r, ms = C.c_int32(), C.c_int32(), C.c_double()
-        _check(fn(h, C.byref(w), C.byref(r), C.byref(ms)), "gmot_*_autotune")
-        return {"waves_per_block": w.value, "rows_per_lane": r.value, "ms_per_half_sweep": ms.value}
+        w, r, g, ms = C.c_int32(), C.c_int32(), C.c_int32(), C.c_double()
+        _check(fn(h, C.byref(w), C.byref(r), C.byref(g), C.byref(ms)), "gmot_*_autotune")
+        return {"waves_per_block": w.value, "rows_per_lane": r.value, "lane_groups": g.value,
+                "ms_per_half_sweep": ms.value}
 
     def autotune(self) -> dict:
         """Pick the fastest node-kernel block shape for this problem (state untouched)."""

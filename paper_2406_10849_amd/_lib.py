@@ -134,8 +134,8 @@ SIGNATURES = {
     "gmot_star_targets_dev": (C.c_int, [C.POINTER(VP), C.c_int32, C.c_float, VP]),
     "gmot_star_apply_dev": (C.c_int, [C.POINTER(VP), C.c_int32, VP, C.c_float, I32P]),
     "gmot_mlp_warm_start": (C.c_int, [VP, C.POINTER(VP), C.c_int32, C.c_float, C.c_float, C.c_float, I32P]),
-    "gmot_problem_autotune": (C.c_int, [VP, I32P, I32P, DP]),
-    "gmot_batch_autotune": (C.c_int, [VP, I32P, I32P, DP]),
+    "gmot_problem_autotune": (C.c_int, [VP, I32P, I32P, I32P, DP]),
+    "gmot_batch_autotune": (C.c_int, [VP, I32P, I32P, I32P, DP]),
     "gmot_problem_stats": (C.c_int, [VP, C.POINTER(Stats), C.c_int32]),
     "gmot_batch_stats": (C.c_int, [VP, C.POINTER(Stats), C.c_int32]),
 }

@@ -56,7 +56,7 @@ struct MsgDesc {
   double* lam_dst[2];        // stored L_(j,k) slots, [n_dst]
   double2* partial;          // [n_dst * ns]: evaluation pass, per row its ns column splits, each
                              // (split max M, sum of 2^(w - M))
-  double* wmax;              // [kMaxWaves * n_dst]: node kernel, wave-major, per row the max of
+  double* wmax;              // [kMaxRanges * n_dst]: node kernel, wave-major, per row the max of
                              // each wave's column range at the last computation (next shift)
   double* mfull;             // merged message m_{k->j}, [n_dst], natural log
   const float* cost;         // explicit cost stored src-major: cost[y * n_dst + x] = C_(j,k)(x, y)
@@ -72,7 +72,8 @@ struct K1Item {
 };
 
 constexpr int kNodeRowsLane = 64;  // rows per node-kernel tile per row-per-lane (tile = 64 * R rows)
-constexpr int kMaxWaves = 8;    // waves per node-kernel block: 2, 4 or 8
+constexpr int kMaxWaves = 16;   // waves per node-kernel block: 2, 4, 8 or 16
+constexpr int kMaxRanges = 2 * kMaxWaves;  // column ranges per edge in one node-kernel block
 constexpr int kRecExtra = 2;    // tile record entries after the per-edge terms
 
 // One node of the class being updated; its deg incoming messages are
@@ -166,9 +167,10 @@ struct RoundNode {
 // FP64 evaluation messages from potential slot src_slot of the source class
 hipError_t launch_msg(const Tables& tb, int n_items, int dim, int rows_per_lane, int src_slot, hipStream_t s);
 // node kernel over n_tiles tiles of one class and support-dimension group (dim 0: explicit
-// cost); tiles of 64 * rows_per_lane rows
-hipError_t launch_node(const Tables& tb, int n_tiles, int dim, int waves, int rows_per_lane, bool fp64,
-                       hipStream_t s);
+// cost); tiles of 64 * rows_per_lane / lane_groups rows, each wave's lanes in lane_groups
+// groups that sum separate column ranges (1, or 2 with two rows per lane)
+hipError_t launch_node(const Tables& tb, int n_tiles, int dim, int waves, int rows_per_lane, int lane_groups,
+                       bool fp64, hipStream_t s);
 hipError_t launch_finalize(const Tables& tb, int n_inst, hipStream_t s);
 hipError_t launch_node_eval(const Tables& tb, int n_nodes, int slot, hipStream_t s);
 // dst[i] = src[i] - (c ? *c : 0) over segments (potential read-back on the device)
@@ -206,12 +208,18 @@ hipError_t launch_star_apply(const StarDesc* stars, int count, int L, int n, con
 #ifdef __cplusplus
 #include <map>
 // Host-side context shared by the runtime and the MLP host code.
+// Node-kernel block shape: W waves per block, R rows per lane, H lane groups per
+// wave (tiles of 64 * R / H rows).
+struct NodeShape {
+  int W, R, H;
+};
+
 struct gmot_ctx {
   int device = 0;
   hipStream_t stream = nullptr;
   bool own_stream = false;
   double clk_hz = 1.0e8;
-  std::map<uint64_t, std::pair<int, int>> tuned;  // shape key -> (waves per block, rows per lane)
+  std::map<uint64_t, NodeShape> tuned;  // instance shapes key -> tuned node-kernel shape
   void* scratch = nullptr;                         // small tables of the warm-start calls
   size_t scratch_size = 0;
 };

@@ -272,13 +272,17 @@ __device__ inline void wave_sync() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-template <int DIM, int W, int R, bool F64, bool EXPL>
+template <int DIM, int W, int R, int H, bool F64, bool EXPL>
 __global__ __launch_bounds__(64 * W) void k_node(Tables tb) {
+  static_assert(R % H == 0 && (H == 1 || !EXPL), "lane groups need as many rows per lane");
+  constexpr int LPR = 64 / H;                        // lanes per lane group
   constexpr int CH = EXPL ? 32 : 64;                 // columns per wave chunk
+  constexpr int CHH = CH / H;                        // columns per lane-group chunk
   constexpr int STR = EXPL ? 1 : (DIM == 1 ? 2 : 4); // doubles per staged column
-  constexpr int TR = 64 * R;                         // rows per tile
+  constexpr int TR = LPR * R;                        // rows per tile
   constexpr int NT = 64 * W;                         // threads per block
-  constexpr int NP = kNodeDegLDS > W ? kNodeDegLDS : W;
+  // (edge, range) partials: deg * H ranges when deg >= W (deg <= kNodeDegLDS), else W * H
+  constexpr int NP = (kNodeDegLDS > W ? kNodeDegLDS : W) * H;
   __shared__ double s_col[W][CH * STR];
   __shared__ double2 s_part[NP][TR];  // (edge, range) partials; then per-(edge, row) terms
   __shared__ double s_m[kNodeDegLDS][TR];
@@ -298,6 +302,9 @@ __global__ __launch_bounds__(64 * W) void k_node(Tables tb) {
   const bool lds = deg <= kNodeDegLDS;
   const bool fixed = nd.fixed != 0;
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  // H lane groups of LPR lanes: lane (group h, index i) holds rows i, i + LPR, ...
+  // of the tile and sums column range h of its wave's share of each edge
+  const int lrow = lane % LPR, half = lane / LPR;
   int x[R];
   bool vx[R];
   const double eps = mds[0].eps;
@@ -307,7 +314,7 @@ __global__ __launch_bounds__(64 * W) void k_node(Tables tb) {
   double x2[R];
 #pragma unroll
   for (int r = 0; r < R; ++r) {
-    x[r] = ti.row0 + r * 64 + lane;
+    x[r] = ti.row0 + r * LPR + lrow;
     vx[r] = x[r] < n;
     x2[r] = 0.0;
 #pragma unroll
@@ -316,7 +323,7 @@ __global__ __launch_bounds__(64 * W) void k_node(Tables tb) {
       cx[r][d] = cxs * v;
       x2[r] = fma(v, v, x2[r]);
     }
-    if (wv == 0) s_x2[r * 64 + lane] = x2[r];
+    if (wv == 0 && half == 0) s_x2[r * LPR + lrow] = x2[r];
   }
   double* __restrict__ stage = s_col[wv];
   // the held potential (and mu) of this thread's first (edge, row) item of the
@@ -331,9 +338,11 @@ __global__ __launch_bounds__(64 * W) void k_node(Tables tb) {
   }
 
   // Edges run on different waves: with deg >= W each wave takes whole edges
-  // (k = wv, wv + W, ...); otherwise g = W / deg waves share an edge, each
-  // summing one of g column ranges.
+  // (k = wv, wv + W, ...); otherwise g = W / deg waves share an edge.  Each
+  // wave's share is split over its H lane groups: gr = g * H column ranges per
+  // edge, range rid = sub * H + half.
   const int g = deg >= W ? 1 : W / deg;
+  const int gr = g * H;
   const int k_first = deg >= W ? wv : (wv < deg * g ? wv / g : deg);
   const int k_step = deg >= W ? W : deg;
   const int sub = deg >= W ? 0 : wv % g;
@@ -341,8 +350,12 @@ __global__ __launch_bounds__(64 * W) void k_node(Tables tb) {
   for (int k = k_first; k < deg; k += k_step) {
     const MsgDesc& md = mds[k];
     const int n_src = md.n_src;
-    const int per = (n_src + g - 1) / g;
-    const int c_lo = min(sub * per, n_src), c_hi = min(c_lo + per, n_src);
+    const int per = (n_src + gr - 1) / gr;
+    const int rid = sub * H + half;
+    const int c_lo = min(rid * per, n_src), c_hi = min(c_lo + per, n_src);
+    // chunk loop length, the same for every lane group (a short last range
+    // runs on with empty chunks)
+    const int span = H == 1 ? c_hi - c_lo : per;
     const double* __restrict__ lam = md.lam_src[src_slot];
     const double csrc = md.c_src ? md.c_src[src_slot] : 0.0;
     const double* __restrict__ lg = md.lg_src;
@@ -350,18 +363,19 @@ __global__ __launch_bounds__(64 * W) void k_node(Tables tb) {
     const float* __restrict__ cost = md.cost;
     double* __restrict__ wmax = md.wmax;
 
-    // A chunk's column data is fetched into registers (lane = column), then
-    // staged in the wave's LDS buffer; padded columns get a = -inf and y = 0,
-    // so they add exactly nothing.  The one-pass loop fetches the next chunk
-    // before summing the current one, so its loads overlap the arithmetic.
+    // A chunk's column data is fetched into registers (lane = column of its
+    // group's range), then staged in the wave's LDS buffer (group h at column
+    // h * CHH); padded columns get a = -inf and y = 0, so they add exactly
+    // nothing.  The one-pass loop fetches the next chunk before summing the
+    // current one, so its loads overlap the arithmetic.
     double f_base = -INFINITY, g_base = -INFINITY;
     double f_y[DIM > 0 ? DIM : 1], g_y[DIM > 0 ? DIM : 1];
     auto fetch_into = [&](int c0, int cn, double& base, double* y) {
-      const int col = c0 + lane;
+      const int col = c0 + lrow;
       base = -INFINITY;
 #pragma unroll
       for (int d = 0; d < DIM; ++d) y[d] = 0.0;
-      if (lane < cn) {
+      if (lrow < cn) {
         base = (lam[col] - csrc) + lg[col];
         if (!EXPL) {
 #pragma unroll
@@ -385,11 +399,12 @@ __global__ __launch_bounds__(64 * W) void k_node(Tables tb) {
         a -= y2 / eps;
       }
       a *= kLog2e;
-      if (lane < CH) {
-        stage[lane * STR] = a;
+      if (lrow < CHH) {
+        const int sc = (half * CHH + lrow) * STR;
+        stage[sc] = a;
         if (!EXPL) {
 #pragma unroll
-          for (int d = 0; d < DIM; ++d) stage[lane * STR + 1 + d] = f_y[d];
+          for (int d = 0; d < DIM; ++d) stage[sc + 1 + d] = f_y[d];
         }
       }
       wave_sync();
@@ -398,6 +413,7 @@ __global__ __launch_bounds__(64 * W) void k_node(Tables tb) {
       fetch_chunk(c0, cn);
       stage_fetched();
     };
+    const double* __restrict__ sth = stage + half * CHH * STR;  // this lane group's columns
     float cv[EXPL ? R : 1][EXPL ? CH : 1];
     auto load_cost = [&](int c0, int cn) {
       if (EXPL) {
@@ -414,7 +430,7 @@ __global__ __launch_bounds__(64 * W) void k_node(Tables tb) {
         w = fma(ces, (double)cv[r][c], w);
       } else {
 #pragma unroll
-        for (int d = 0; d < DIM; ++d) w = fma(cx[r][d], stage[c * STR + 1 + d], w);
+        for (int d = 0; d < DIM; ++d) w = fma(cx[r][d], sth[c * STR + 1 + d], w);
       }
       return w;
     };
@@ -423,8 +439,8 @@ __global__ __launch_bounds__(64 * W) void k_node(Tables tb) {
 #pragma unroll
       for (int r = 0; r < R; ++r) Sc[r] = 0.0;
 #pragma unroll 4
-      for (int c = 0; c < CH; c += 2) {
-        const double a0 = stage[c * STR], a1 = stage[(c + 1) * STR];
+      for (int c = 0; c < CHH; c += 2) {
+        const double a0 = sth[c * STR], a1 = sth[(c + 1) * STR];
 #pragma unroll
         for (int r = 0; r < R; ++r) {
           const double w0 = wcol(r, c, a0), w1 = wcol(r, c + 1, a1);
@@ -441,8 +457,8 @@ __global__ __launch_bounds__(64 * W) void k_node(Tables tb) {
 #pragma unroll
       for (int r = 0; r < R; ++r) Mc[r] = -INFINITY;
 #pragma unroll 4
-      for (int c = 0; c < CH; ++c) {
-        const double a = stage[c * STR];
+      for (int c = 0; c < CHH; ++c) {
+        const double a = sth[c * STR];
 #pragma unroll
         for (int r = 0; r < R; ++r) Mc[r] = fmax(Mc[r], wcol(r, c, a));
       }
@@ -459,17 +475,18 @@ __global__ __launch_bounds__(64 * W) void k_node(Tables tb) {
       double sh[R];
 #pragma unroll
       for (int r = 0; r < R; ++r) {
-        const double pm = vx[r] ? wmax[(size_t)sub * n + x[r]] : 0.0;
+        const double pm = vx[r] ? wmax[(size_t)rid * n + x[r]] : 0.0;
         sh[r] = isfinite(pm) ? pm : 0.0;
       }
-      if (c_lo < c_hi) fetch_chunk(c_lo, min(CH, c_hi - c_lo));
-      if (c_lo + CH < c_hi) fetch_into(c_lo + CH, min(CH, c_hi - c_lo - CH), g_base, g_y);
-      for (int c0 = c_lo; c0 < c_hi; c0 += CH) {
-        const int cn = min(CH, c_hi - c0);
+      if (span > 0) fetch_chunk(c_lo, min(CHH, c_hi - c_lo));
+      if (CHH < span) fetch_into(c_lo + CHH, min(CHH, c_hi - c_lo - CHH), g_base, g_y);
+      for (int j0 = 0; j0 < span; j0 += CHH) {
+        const int c0 = c_lo + j0;
+        const int cn = min(CHH, c_hi - c0);
         load_cost(c0, cn);
         stage_fetched();
         advance();
-        if (c0 + 2 * CH < c_hi) fetch_into(c0 + 2 * CH, min(CH, c_hi - c0 - 2 * CH), g_base, g_y);
+        if (j0 + 2 * CHH < span) fetch_into(c0 + 2 * CHH, min(CHH, c_hi - c0 - 2 * CHH), g_base, g_y);
         // one pass: sums relative to the shifts, chunk maxima alongside
         double Mc[R], Sc[R];
 #pragma unroll
@@ -478,8 +495,8 @@ __global__ __launch_bounds__(64 * W) void k_node(Tables tb) {
           Sc[r] = 0.0;
         }
 #pragma unroll 4
-        for (int c = 0; c < CH; c += 2) {
-          const double a0 = stage[c * STR], a1 = stage[(c + 1) * STR];
+        for (int c = 0; c < CHH; c += 2) {
+          const double a0 = sth[c * STR], a1 = sth[(c + 1) * STR];
 #pragma unroll
           for (int r = 0; r < R; ++r) {
             const double w0 = wcol(r, c, a0), w1 = wcol(r, c + 1, a1);
@@ -524,8 +541,9 @@ __global__ __launch_bounds__(64 * W) void k_node(Tables tb) {
         M[r] = -INFINITY;
         S[r] = 0.0;
       }
-      for (int c0 = c_lo; c0 < c_hi; c0 += CH) {
-        const int cn = min(CH, c_hi - c0);
+      for (int j0 = 0; j0 < span; j0 += CHH) {
+        const int c0 = c_lo + j0;
+        const int cn = min(CHH, c_hi - c0);
         load_cost(c0, cn);
         stage_chunk(c0, cn);
         double Mc[R], Sc[R], sh[R];
@@ -546,12 +564,26 @@ __global__ __launch_bounds__(64 * W) void k_node(Tables tb) {
     }
 #pragma unroll
     for (int r = 0; r < R; ++r) {
-      if (vx[r]) wmax[(size_t)sub * n + x[r]] = M[r];
+      if (vx[r]) wmax[(size_t)rid * n + x[r]] = M[r];
       if (lds) {
-        s_part[k * g + sub][r * 64 + lane] = make_double2(M[r], S[r]);
-      } else if (vx[r]) {
-        // one range per edge (g = 1): the message goes straight to mfull
-        md.mfull[x[r]] = (M[r] > -INFINITY && S[r] > 0.0) ? kLn2 * (M[r] + log2(S[r])) - x2[r] / eps : -INFINITY;
+        s_part[k * gr + rid][r * LPR + lrow] = make_double2(M[r], S[r]);
+      } else {
+        // one wave per edge (g = 1): its H ranges merged across the lane
+        // groups, the message goes straight to mfull
+        double Mm = M[r], Sm = S[r];
+        if (H == 2) {
+          const double Mo = __shfl_xor(Mm, LPR), So = __shfl_xor(Sm, LPR);
+          const double Mx = fmax(Mm, Mo);
+          double St = 0.0;
+          if (Mx > -INFINITY) {
+            if (Sm > 0.0) St += Sm * exp2(Mm - Mx);
+            if (So > 0.0) St += So * exp2(Mo - Mx);
+          }
+          Mm = Mx;
+          Sm = St;
+        }
+        if (vx[r] && half == 0)
+          md.mfull[x[r]] = (Mm > -INFINITY && Sm > 0.0) ? kLn2 * (Mm + log2(Sm)) - x2[r] / eps : -INFINITY;
       }
     }
   }
@@ -560,15 +592,15 @@ __global__ __launch_bounds__(64 * W) void k_node(Tables tb) {
   const double c_old = nd.c ? nd.c[cur] : 0.0;
 
   if (lds) {
-    // merge the g ranges of every (edge, row) into m (natural log)
+    // merge the gr ranges of every (edge, row) into m (natural log)
     for (int it = threadIdx.x; it < deg * TR; it += NT) {
       const int k = it / TR, lr = it - k * TR;
       double Mx = -INFINITY;
-      for (int u = 0; u < g; ++u) Mx = fmax(Mx, s_part[k * g + u][lr].x);
+      for (int u = 0; u < gr; ++u) Mx = fmax(Mx, s_part[k * gr + u][lr].x);
       double St = 0.0;
       if (Mx > -INFINITY) {
-        for (int u = 0; u < g; ++u) {
-          const double2 q = s_part[k * g + u][lr];
+        for (int u = 0; u < gr; ++u) {
+          const double2 q = s_part[k * gr + u][lr];
           if (q.y > 0.0) St += (q.x == Mx) ? q.y : q.y * exp2(q.x - Mx);
         }
       }
@@ -615,27 +647,28 @@ __global__ __launch_bounds__(64 * W) void k_node(Tables tb) {
       __syncthreads();
     }
     // tile record: per-edge term sums (edge k on wave k mod W), then abar's LSE
+    constexpr int TQ = TR / 64;  // tile rows per lane of one wave
     for (int k = wv; k < deg; k += W) {
       double part = 0.0;
 #pragma unroll
-      for (int r = 0; r < R; ++r) part += s_part[k][r * 64 + lane].x;
+      for (int q = 0; q < TQ; ++q) part += s_part[k][q * 64 + lane].x;
       part = wave_sum(part);
       if (lane == 0) rec[k] = part;
     }
     if (!fixed && wv == W - 1) {
-      double av[R], am = -INFINITY;
+      double av[TQ], am = -INFINITY;
 #pragma unroll
-      for (int r = 0; r < R; ++r) {
-        const int lr = r * 64 + lane;
+      for (int q = 0; q < TQ; ++q) {
+        const int lr = q * 64 + lane;
         double as = 0.0;
         for (int kk = 0; kk < deg; ++kk) as += s_m[kk][lr];
-        av[r] = vx[r] ? as / deg : -INFINITY;
-        am = fmax(am, av[r]);
+        av[q] = ti.row0 + lr < n ? as / deg : -INFINITY;
+        am = fmax(am, av[q]);
       }
       const double Mw = wave_max(am);
       double sv = 0.0;
 #pragma unroll
-      for (int r = 0; r < R; ++r) sv += (av[r] > -INFINITY) ? exp(av[r] - Mw) : 0.0;
+      for (int q = 0; q < TQ; ++q) sv += (av[q] > -INFINITY) ? exp(av[q] - Mw) : 0.0;
       const double Sw = wave_sum(sv);
       if (lane == 0) {
         rec[deg] = Mw;
@@ -645,8 +678,11 @@ __global__ __launch_bounds__(64 * W) void k_node(Tables tb) {
     return;
   }
 
-  // more than kNodeDegLDS edges: wave 0 reads the messages from mfull
+  // more than kNodeDegLDS edges: wave 0 reads the messages from mfull (lane
+  // group 0 holds every row of the tile)
   if (wv != 0) return;
+#pragma unroll
+  for (int r = 0; r < R; ++r) vx[r] = vx[r] && half == 0;
   double mux[R], a[R], qb[R];
 #pragma unroll
   for (int r = 0; r < R; ++r) {
@@ -945,41 +981,45 @@ hipError_t launch_msg(const Tables& tb, int n_items, int dim, int rows_per_lane,
                             : launch_msg_r<1>(tb, n_items, dim, src_slot, s);
 }
 
-template <int DIM, int W, int R, bool F64, bool EXPL>
+template <int DIM, int W, int R, int H, bool F64, bool EXPL>
 static hipError_t launch_node_t(const Tables& tb, int n_tiles, hipStream_t s) {
-  hipLaunchKernelGGL((k_node<DIM, W, R, F64, EXPL>), dim3(n_tiles), dim3(64 * W), 0, s, tb);
+  hipLaunchKernelGGL((k_node<DIM, W, R, H, F64, EXPL>), dim3(n_tiles), dim3(64 * W), 0, s, tb);
   return hipGetLastError();
 }
 
-template <int W, int R, bool F64>
+template <int W, int R, int H, bool F64>
 static hipError_t launch_node_w(const Tables& tb, int n_tiles, int dim, hipStream_t s) {
   switch (dim) {
-    case 0:  // explicit cost (one row per lane only)
-      if (R != 1) return hipErrorInvalidValue;
-      return launch_node_t<1, W, 1, F64, true>(tb, n_tiles, s);
-    case 1: return launch_node_t<1, W, R, F64, false>(tb, n_tiles, s);
-    case 2: return launch_node_t<2, W, R, F64, false>(tb, n_tiles, s);
-    case 3: return launch_node_t<3, W, R, F64, false>(tb, n_tiles, s);
+    case 0:  // explicit cost (one row per lane, one lane group only)
+      if (R != 1 || H != 1) return hipErrorInvalidValue;
+      return launch_node_t<1, W, 1, 1, F64, true>(tb, n_tiles, s);
+    case 1: return launch_node_t<1, W, R, H, F64, false>(tb, n_tiles, s);
+    case 2: return launch_node_t<2, W, R, H, F64, false>(tb, n_tiles, s);
+    case 3: return launch_node_t<3, W, R, H, F64, false>(tb, n_tiles, s);
     default: return hipErrorInvalidValue;
   }
 }
 
-template <int R>
+template <int R, int H>
 static hipError_t launch_node_r(const Tables& tb, int n_tiles, int dim, int waves, bool fp64, hipStream_t s) {
   switch (waves) {
-    case 2: return fp64 ? launch_node_w<2, R, true>(tb, n_tiles, dim, s) : launch_node_w<2, R, false>(tb, n_tiles, dim, s);
-    case 4: return fp64 ? launch_node_w<4, R, true>(tb, n_tiles, dim, s) : launch_node_w<4, R, false>(tb, n_tiles, dim, s);
-    case 8: return fp64 ? launch_node_w<8, R, true>(tb, n_tiles, dim, s) : launch_node_w<8, R, false>(tb, n_tiles, dim, s);
+    case 2: return fp64 ? launch_node_w<2, R, H, true>(tb, n_tiles, dim, s) : launch_node_w<2, R, H, false>(tb, n_tiles, dim, s);
+    case 4: return fp64 ? launch_node_w<4, R, H, true>(tb, n_tiles, dim, s) : launch_node_w<4, R, H, false>(tb, n_tiles, dim, s);
+    case 8: return fp64 ? launch_node_w<8, R, H, true>(tb, n_tiles, dim, s) : launch_node_w<8, R, H, false>(tb, n_tiles, dim, s);
+    case 16: return fp64 ? launch_node_w<16, R, H, true>(tb, n_tiles, dim, s) : launch_node_w<16, R, H, false>(tb, n_tiles, dim, s);
     default: return hipErrorInvalidValue;
   }
 }
 
-hipError_t launch_node(const Tables& tb, int n_tiles, int dim, int waves, int rows_per_lane, bool fp64,
-                       hipStream_t s) {
+hipError_t launch_node(const Tables& tb, int n_tiles, int dim, int waves, int rows_per_lane, int lane_groups,
+                       bool fp64, hipStream_t s) {
   if (n_tiles <= 0) return hipSuccess;
-  if (rows_per_lane == 1) return launch_node_r<1>(tb, n_tiles, dim, waves, fp64, s);
-  if (rows_per_lane == 2 && dim > 0) return launch_node_r<2>(tb, n_tiles, dim, waves, fp64, s);
-  return hipErrorInvalidValue;  // explicit-cost tiles take one row per lane
+  if (rows_per_lane == 1 && lane_groups == 1) return launch_node_r<1, 1>(tb, n_tiles, dim, waves, fp64, s);
+  // explicit-cost tiles take one row per lane and one lane group
+  if (dim == 0) return hipErrorInvalidValue;
+  if (rows_per_lane == 2 && lane_groups == 1) return launch_node_r<2, 1>(tb, n_tiles, dim, waves, fp64, s);
+  if (rows_per_lane == 2 && lane_groups == 2) return launch_node_r<2, 2>(tb, n_tiles, dim, waves, fp64, s);
+  return hipErrorInvalidValue;
 }
 
 hipError_t launch_finalize(const Tables& tb, int n_inst, hipStream_t s) {

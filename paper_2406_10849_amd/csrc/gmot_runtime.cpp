@@ -116,7 +116,8 @@ struct Plan {
   gmot_ctx* ctx = nullptr;
   std::vector<gmot_problem*> probs;
   int W = 4;                 // waves per node-kernel block
-  int NR = 1;                // node-kernel rows per lane (tiles of 64 * NR rows)
+  int NR = 1;                // node-kernel rows per lane
+  int NH = 1;                // node-kernel lane groups per wave (tiles of 64 * NR / NH rows)
   int R = 1;                 // evaluation message kernel: rows per lane
   int target_blocks = 1024;  // evaluation message kernel: blocks per class (via column splits)
   std::vector<MsgDesc> msgs;
@@ -174,14 +175,14 @@ struct Plan {
     for (int dk = 0; dk < 4; ++dk) {
       if (tiles[c][dk].empty()) continue;
       if (!per_node) {
-        e = launch_node(tables(c, dk), (int)tiles[c][dk].size(), dk, W, NR, fp64, s);
+        e = launch_node(tables(c, dk), (int)tiles[c][dk].size(), dk, W, NR, NH, fp64, s);
         if (e != hipSuccess) return e;
         continue;
       }
       for (const auto& r : node_tiles[c][dk]) {
         Tables tb = tables(c, dk);
         tb.tiles += r.first;
-        e = launch_node(tb, r.second, dk, W, NR, fp64, s);
+        e = launch_node(tb, r.second, dk, W, NR, NH, fp64, s);
         if (e != hipSuccess) return e;
       }
     }
@@ -215,17 +216,18 @@ struct Plan {
 // ---------------------------------------------------------------------------
 // plan construction
 // ---------------------------------------------------------------------------
-static int build_plan(gmot_ctx* ctx, const std::vector<gmot_problem*>& probs, int W, int NR, Plan** out) {
+static int build_plan(gmot_ctx* ctx, const std::vector<gmot_problem*>& probs, NodeShape shape, Plan** out) {
   std::unique_ptr<Plan> pl(new Plan());
   pl->ctx = ctx;
   pl->probs = probs;
-  // explicit-cost tiles keep one row per lane (each lane holds its rows' cost
-  // chunk in registers)
+  // explicit-cost tiles keep one row per lane and one lane group (each lane
+  // holds its rows' cost chunk in registers)
   for (const gmot_problem* p : probs)
-    if (p->cost_kind == GMOT_COST_EXPLICIT) NR = 1;
-  pl->W = W;
-  pl->NR = NR;
-  const int TRows = kNodeRowsLane * NR;
+    if (p->cost_kind == GMOT_COST_EXPLICIT) shape.R = shape.H = 1;
+  pl->W = shape.W;
+  pl->NR = shape.R;
+  pl->NH = shape.H;
+  const int TRows = kNodeRowsLane * shape.R / shape.H;
   const int R = pl->R, target_blocks = pl->target_blocks;
   const int TM = 256 * R;
   // node tiles per (class, dimension group), with each node's work (pairs) for ordering
@@ -351,7 +353,7 @@ static int build_plan(gmot_ctx* ctx, const std::vector<gmot_problem*>& probs, in
   std::vector<int64_t> wmax_off(pl->msgs.size());
   for (size_t m = 0; m < pl->msgs.size(); ++m) {
     wmax_off[m] = wmax_total;
-    wmax_total += (int64_t)pl->msgs[m].n_dst * kMaxWaves;
+    wmax_total += (int64_t)pl->msgs[m].n_dst * kMaxRanges;
   }
   // tile records of every node
   int64_t tpart_total = 0;
@@ -362,7 +364,7 @@ static int build_plan(gmot_ctx* ctx, const std::vector<gmot_problem*>& probs, in
       tpart_total += (int64_t)nd.tiles * (nd.deg + kRecExtra);
     }
   pl->stats.rows = TRows;
-  pl->stats.max_splits = W;
+  pl->stats.max_splits = shape.W;
   for (int c = 0; c < 2; ++c) {
     pl->stats.blocks[c] = 0;
     for (int dk = 0; dk < 4; ++dk) pl->stats.blocks[c] += (int)pl->tiles[c][dk].size();
@@ -454,21 +456,26 @@ static uint64_t shape_key(const std::vector<gmot_problem*>& probs) {
   return h;
 }
 
-constexpr int kDefaultWaves = 4;
-constexpr int kDefaultRowsLane = 2;
+constexpr NodeShape kDefaultShape{4, 2, 1};
 
-// Node-kernel block shape (waves per block, rows per lane): a tuned choice
-// cached in the context for these shapes, else the default; GMOT_NODE_SHAPE="W,R"
-// (W in 2, 4, 8; R in 1, 2) overrides both.
-static std::pair<int, int> choose_shape(gmot_ctx* ctx, const std::vector<gmot_problem*>& probs) {
-  std::pair<int, int> wr{kDefaultWaves, kDefaultRowsLane};
+static bool valid_shape(const NodeShape& s) {
+  return (s.W == 2 || s.W == 4 || s.W == 8 || s.W == 16) && (s.R == 1 || s.R == 2) && (s.H == 1 || s.H == 2) &&
+         s.R % s.H == 0;
+}
+
+// Node-kernel block shape: a tuned choice cached in the context for these
+// shapes, else the default; GMOT_NODE_SHAPE="W,R" or "W,R,H" (W in 2, 4, 8,
+// 16; R in 1, 2; H in 1, 2 with H <= R) overrides both.
+static NodeShape choose_shape(gmot_ctx* ctx, const std::vector<gmot_problem*>& probs) {
+  NodeShape sh = kDefaultShape;
   auto it = ctx->tuned.find(shape_key(probs));
-  if (it != ctx->tuned.end()) wr = it->second;
+  if (it != ctx->tuned.end()) sh = it->second;
   if (const char* v = std::getenv("GMOT_NODE_SHAPE")) {
-    int w = 0, r = 0;
-    if (std::sscanf(v, "%d,%d", &w, &r) == 2 && (w == 2 || w == 4 || w == 8) && (r == 1 || r == 2)) wr = {w, r};
+    NodeShape e{0, 0, 1};
+    const int got = std::sscanf(v, "%d,%d,%d", &e.W, &e.R, &e.H);
+    if (got >= 2 && valid_shape(e)) sh = e;
   }
-  return wr;
+  return sh;
 }
 
 static int capture_one(Plan* pl, bool fp64, bool per_node, int start, int k, const std::vector<hipEvent_t>* ev,
@@ -931,8 +938,7 @@ static int upload(const gmot_tree_desc* d, gmot_problem* p) {
 
 static int ensure_plan(gmot_problem* p) {
   if (p->plan) return GMOT_OK;
-  const auto wr = choose_shape(p->ctx, {p});
-  return build_plan(p->ctx, {p}, wr.first, wr.second, &p->plan);
+  return build_plan(p->ctx, {p}, choose_shape(p->ctx, {p}), &p->plan);
 }
 
 // Mean device time of an FP32-core half-sweep (node stage and finalise
@@ -993,20 +999,25 @@ static int time_plan(Plan* pl, double* ms) {
 }
 
 static int autotune(gmot_ctx* ctx, const std::vector<gmot_problem*>& probs, Plan** plan_io, int32_t* W_out,
-                    int32_t* R_out, double* ms_out) {
-  static const int kCand[][2] = {{2, 1}, {4, 1}, {8, 1}, {2, 2}, {4, 2}, {8, 2}};
-  std::vector<std::array<int, 2>> cands;
-  for (const auto& c : kCand) cands.push_back({c[0], c[1]});
+                    int32_t* R_out, int32_t* H_out, double* ms_out) {
+  static const NodeShape kCand[] = {{2, 1, 1},  {4, 1, 1}, {8, 1, 1}, {16, 1, 1}, {2, 2, 1}, {4, 2, 1},
+                                    {8, 2, 1},  {16, 2, 1}, {4, 2, 2}, {8, 2, 2}, {16, 2, 2}};
+  bool expl = false;
+  for (const gmot_problem* p : probs) expl = expl || p->cost_kind == GMOT_COST_EXPLICIT;
+  std::vector<NodeShape> cands;
+  for (const auto& c : kCand)
+    if (!expl || (c.R == 1 && c.H == 1)) cands.push_back(c);  // explicit cost: one row per lane
   if (std::getenv("GMOT_NODE_SHAPE")) {  // a pinned shape is the only candidate
-    const auto wr = choose_shape(ctx, probs);
-    cands = {{wr.first, wr.second}};
+    NodeShape pin = choose_shape(ctx, probs);
+    if (expl) pin.R = pin.H = 1;
+    cands = {pin};
   }
   Plan* best = nullptr;
   double best_ms = INFINITY;
-  std::pair<int, int> bWR{kDefaultWaves, kDefaultRowsLane};
+  NodeShape bWR = kDefaultShape;
   for (const auto& cand : cands) {
     Plan* pl = nullptr;
-    int rc = build_plan(ctx, probs, cand[0], cand[1], &pl);
+    int rc = build_plan(ctx, probs, cand, &pl);
     if (rc) {
       delete best;
       return rc;
@@ -1022,7 +1033,7 @@ static int autotune(gmot_ctx* ctx, const std::vector<gmot_problem*>& probs, Plan
       delete best;
       best = pl;
       best_ms = ms;
-      bWR = {cand[0], cand[1]};
+      bWR = cand;
     } else {
       delete pl;
     }
@@ -1031,8 +1042,9 @@ static int autotune(gmot_ctx* ctx, const std::vector<gmot_problem*>& probs, Plan
   delete *plan_io;
   *plan_io = best;
   g_tiles = best->stats;
-  if (W_out) *W_out = bWR.first;
-  if (R_out) *R_out = bWR.second;
+  if (W_out) *W_out = bWR.W;
+  if (R_out) *R_out = bWR.R;
+  if (H_out) *H_out = bWR.H;
   if (ms_out) *ms_out = best_ms;
   return GMOT_OK;
 }
@@ -1582,8 +1594,7 @@ int gmot_batch_create(gmot_ctx* ctx, gmot_problem* const* probs, int32_t count, 
     b->probs.push_back(probs[i]);
   }
   HIPCHK(hipSetDevice(ctx->device));
-  const auto wr = choose_shape(ctx, b->probs);
-  int rc = build_plan(ctx, b->probs, wr.first, wr.second, &b->plan);
+  int rc = build_plan(ctx, b->probs, choose_shape(ctx, b->probs), &b->plan);
   if (rc) return rc;
   *out = b.release();
   return GMOT_OK;
@@ -1609,17 +1620,19 @@ int gmot_batch_solve(gmot_batch* b, const gmot_opts* o, gmot_result* outs) {
   return solve_plan(b->plan, o, outs);
 }
 
-int gmot_problem_autotune(gmot_problem* p, int32_t* waves_per_block, int32_t* rows_per_lane, double* best_ms) {
+int gmot_problem_autotune(gmot_problem* p, int32_t* waves_per_block, int32_t* rows_per_lane, int32_t* lane_groups,
+                          double* best_ms) {
   if (!p) return fail(GMOT_EINVAL, "null problem");
   if (p->E == 0) return GMOT_OK;
   HIPCHK(hipSetDevice(p->ctx->device));
-  return autotune(p->ctx, {p}, &p->plan, waves_per_block, rows_per_lane, best_ms);
+  return autotune(p->ctx, {p}, &p->plan, waves_per_block, rows_per_lane, lane_groups, best_ms);
 }
 
-int gmot_batch_autotune(gmot_batch* b, int32_t* waves_per_block, int32_t* rows_per_lane, double* best_ms) {
+int gmot_batch_autotune(gmot_batch* b, int32_t* waves_per_block, int32_t* rows_per_lane, int32_t* lane_groups,
+                        double* best_ms) {
   if (!b) return fail(GMOT_EINVAL, "null batch");
   HIPCHK(hipSetDevice(b->ctx->device));
-  return autotune(b->ctx, b->probs, &b->plan, waves_per_block, rows_per_lane, best_ms);
+  return autotune(b->ctx, b->probs, &b->plan, waves_per_block, rows_per_lane, lane_groups, best_ms);
 }
 
 // ---- star warm-start data movement ------------------------------------------

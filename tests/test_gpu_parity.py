@@ -318,26 +318,38 @@ def test_one_pass_matches_two_pass(ctx):
             assert np.max(np.abs(g1.coupling(e) - g2.coupling(e))) <= 1e-6
 
 
-@pytest.mark.parametrize("shape", ["2,1", "4,1", "8,1", "2,2", "4,2", "8,2"])
-def test_every_node_shape_matches_oracle(ctx, shape, monkeypatch):
-    """Each node-kernel block shape (waves per block, rows per lane), pinned
-    through GMOT_NODE_SHAPE, on a ragged 2D tree with a constrained interior
-    node and a star centre of degree 5: FP64 iterates to 1e-9 of the oracle
-    and FP32-core ones to 1e-6 (dual relative to the scale)."""
-    monkeypatch.setenv("GMOT_NODE_SHAPE", shape)
+SHAPES = ["2,1", "4,1", "8,1", "16,1", "2,2", "4,2", "8,2", "16,2", "2,2,2", "4,2,2", "8,2,2", "16,2,2"]
+
+
+def _shape_cases():
+    # a ragged 2D tree with a constrained interior node and a star centre of
+    # degree 5, and a free star centre of degree 20 (more edges than the block
+    # keeps in LDS: its messages go through the full-message buffer)
     edges = [(0, 1), (0, 2), (0, 3), (0, 4), (0, 5), (5, 6), (6, 7)]
-    p = make_tree(edges, [300, 70, 129, 64, 1, 257, 190, 33], [0, 1, 1, 1, 1, 1, 0, 1], dim=2, eps=0.02,
+    t = make_tree(edges, [300, 70, 129, 64, 1, 257, 190, 33], [0, 1, 1, 1, 1, 1, 0, 1], dim=2, eps=0.02,
                   instance=60)
-    o = TreeOracle(p)
-    o.run_fixed(12)
-    eo = o.evaluate()
-    for precision, tol in (("fp64", 1e-9), ("fp32core", 1e-6)):
-        g = gpu_problem(ctx, p)
-        r = g.solve(tol=0.0, max_steps=12, precision=precision)
-        assert r["steps"] == 12
-        assert abs(g.evaluate()["dual"] - eo["dual"]) <= tol * eo["scale"]
-        for e in range(p.n_edges):
-            assert np.max(np.abs(g.coupling(e) - o.coupling(e))) <= tol
+    star = make_tree([(0, k) for k in range(1, 21)], [150] + [37 + 11 * k for k in range(20)],
+                     [0] + [1] * 20, dim=1, eps=0.05, instance=62)
+    return [t, star]
+
+
+@pytest.mark.parametrize("shape", SHAPES)
+def test_every_node_shape_matches_oracle(ctx, shape, monkeypatch):
+    """Each node-kernel block shape (waves per block, rows per lane, lane
+    groups per wave), pinned through GMOT_NODE_SHAPE: FP64 iterates to 1e-9
+    of the oracle and FP32-core ones to 1e-6 (dual relative to the scale)."""
+    monkeypatch.setenv("GMOT_NODE_SHAPE", shape)
+    for p in _shape_cases():
+        o = TreeOracle(p)
+        o.run_fixed(12)
+        eo = o.evaluate()
+        for precision, tol in (("fp64", 1e-9), ("fp32core", 1e-6)):
+            g = gpu_problem(ctx, p)
+            r = g.solve(tol=0.0, max_steps=12, precision=precision)
+            assert r["steps"] == 12
+            assert abs(g.evaluate()["dual"] - eo["dual"]) <= tol * eo["scale"]
+            for e in range(p.n_edges):
+                assert np.max(np.abs(g.coupling(e) - o.coupling(e))) <= tol
 
 
 def test_three_dimensional_supports(ctx):
