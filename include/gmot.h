@@ -121,10 +121,14 @@ typedef struct {
                            the call, then one pass shifted by each row's max from the
                            previous computation of the same message, with in-kernel
                            re-shifting when a row leaves the FP32 range; the sums are
-                           exact either way.  GMOT_PASSES_TWO (2): always two passes. */
+                           exact either way.  GMOT_PASSES_ONE (1): one pass from the
+                           first half-sweep, shifted by the maxima of the plan's last
+                           computation (0 before any).  GMOT_PASSES_TWO (2): always two
+                           passes. */
 } gmot_opts;
 
 #define GMOT_PASSES_AUTO  0
+#define GMOT_PASSES_ONE   1
 #define GMOT_PASSES_TWO   2
 
 #define GMOT_SCHED_LAYER     0

@@ -21,6 +21,7 @@
 #include "gmot_internal.h"
 
 #include <cmath>
+#include <type_traits>
 
 namespace gmot {
 
@@ -260,6 +261,12 @@ __global__ __launch_bounds__(kBlock) void k_msg(Tables tb, int src_slot) {
 // first two half-sweeps of a call take two passes (chunk max, then sum); the
 // FP64 variant (F64) always does, with FP64 exponentials.
 // ---------------------------------------------------------------------------
+// Global address space views of device arrays reached through descriptors:
+// loads through them are counted in order with the other vector loads, so a
+// prefetch does not force a wait at the end of its (divergent) block.
+typedef const __attribute__((address_space(1))) double GDbl;
+typedef __attribute__((address_space(1))) double GDblW;
+typedef const __attribute__((address_space(1))) float GFlt;
 constexpr int kFinWaves = 16;    // waves per finalise block (one node each)
 constexpr double kShiftHi = 96.0;
 constexpr double kShiftLo = -96.0;
@@ -281,6 +288,9 @@ __global__ __launch_bounds__(64 * W) void k_node(Tables tb) {
   constexpr int STR = EXPL ? 1 : (DIM == 1 ? 2 : 4); // doubles per staged column
   constexpr int TR = LPR * R;                        // rows per tile
   constexpr int NT = 64 * W;                         // threads per block
+  // one-dimensional on-the-fly costs fold an affine part of the one-pass
+  // shift into the staged columns (one FP64 FMA per pair)
+  constexpr bool FOLD = DIM == 1 && !EXPL && !F64;
   // (edge, range) partials: deg * H ranges when deg >= W (deg <= kNodeDegLDS), else W * H
   constexpr int NP = (kNodeDegLDS > W ? kNodeDegLDS : W) * H;
   __shared__ double s_col[W][CH * STR];
@@ -347,7 +357,12 @@ __global__ __launch_bounds__(64 * W) void k_node(Tables tb) {
   const int k_step = deg >= W ? W : deg;
   const int sub = deg >= W ? 0 : wv % g;
 
-  for (int k = k_first; k < deg; k += k_step) {
+  // One edge's sums.  LDS_T: the partials stay in LDS (deg <= kNodeDegLDS);
+  // otherwise the message goes to global memory at once.  The two cases are
+  // separate loops so the common one holds no global store (a store in flight
+  // makes every later wait for a load wait for all of them).
+  auto edge_sums = [&](const int k, auto lds_t) {
+    constexpr bool LDS_T = decltype(lds_t)::value;
     const MsgDesc& md = mds[k];
     const int n_src = md.n_src;
     const int per = (n_src + gr - 1) / gr;
@@ -356,55 +371,65 @@ __global__ __launch_bounds__(64 * W) void k_node(Tables tb) {
     // chunk loop length, the same for every lane group (a short last range
     // runs on with empty chunks)
     const int span = H == 1 ? c_hi - c_lo : per;
-    const double* __restrict__ lam = md.lam_src[src_slot];
-    const double csrc = md.c_src ? md.c_src[src_slot] : 0.0;
-    const double* __restrict__ lg = md.lg_src;
-    const double* __restrict__ ys = md.supp_src;
-    const float* __restrict__ cost = md.cost;
-    double* __restrict__ wmax = md.wmax;
+    const GDbl* __restrict__ lam = (const GDbl*)md.lam_src[src_slot];
+    const double csrc = md.c_src ? ((const GDbl*)md.c_src)[src_slot] : 0.0;
+    const GDbl* __restrict__ lg = (const GDbl*)md.lg_src;
+    const GDbl* __restrict__ ys = (const GDbl*)md.supp_src;
+    const GFlt* __restrict__ cost = (const GFlt*)md.cost;
+    GDblW* __restrict__ wmax = (GDblW*)md.wmax;
 
     // A chunk's column data is fetched into registers (lane = column of its
     // group's range), then staged in the wave's LDS buffer (group h at column
     // h * CHH); padded columns get a = -inf and y = 0, so they add exactly
     // nothing.  The one-pass loop fetches the next chunk before summing the
     // current one, so its loads overlap the arithmetic.
-    double f_base = -INFINITY, g_base = -INFINITY;
-    double f_y[DIM > 0 ? DIM : 1], g_y[DIM > 0 ? DIM : 1];
-    auto fetch_into = [&](int c0, int cn, double& base, double* y) {
-      const int col = c0 + lrow;
-      base = -INFINITY;
-#pragma unroll
-      for (int d = 0; d < DIM; ++d) y[d] = 0.0;
-      if (lrow < cn) {
-        base = (lam[col] - csrc) + lg[col];
-        if (!EXPL) {
-#pragma unroll
-          for (int d = 0; d < DIM; ++d) y[d] = ys[(size_t)col * DIM + d];
-        }
-      }
+    // staged columns are (a(y) - al, y - be): al = be = 0 except in the
+    // one-pass sums of FOLD kernels
+    double al = 0.0, be = 0.0;
+    // A fetch only issues the loads (lane lrow: column c0 + lrow, clamped into
+    // the support, with a flag for columns inside the chunk); all arithmetic
+    // on them happens at staging, so loads of later chunks stay in flight.
+    struct Raw {
+      double l, g, y[DIM > 0 ? DIM : 1];
+      bool v;
     };
-    auto fetch_chunk = [&](int c0, int cn) { fetch_into(c0, cn, f_base, f_y); };
-    // the chunk after next goes to the second register set; move it up
-    auto advance = [&]() {
-      f_base = g_base;
-#pragma unroll
-      for (int d = 0; d < DIM; ++d) f_y[d] = g_y[d];
-    };
-    auto stage_fetched = [&]() {
-      double a = f_base;
+    Raw f_raw, g_raw;
+    auto fetch_into = [&](int c0, int cn, Raw& o) {
+      const int col = min(c0 + lrow, n_src - 1);
+      o.v = lrow < cn;
+      o.l = lam[col];
+      o.g = lg[col];
       if (!EXPL) {
-        double y2 = 0.0;
 #pragma unroll
-        for (int d = 0; d < DIM; ++d) y2 = fma(f_y[d], f_y[d], y2);
-        a -= y2 / eps;
+        for (int d = 0; d < DIM; ++d) o.y[d] = ys[(size_t)col * DIM + d];
       }
-      a *= kLog2e;
+    };
+    auto fetch_chunk = [&](int c0, int cn) { fetch_into(c0, cn, f_raw); };
+    // the chunk after next goes to the second register set; move it up
+    auto advance = [&]() { f_raw = g_raw; };
+    auto stage_fetched = [&]() {
+      double a = -INFINITY, yv[DIM > 0 ? DIM : 1];
+#pragma unroll
+      for (int d = 0; d < DIM; ++d) yv[d] = 0.0;
+      if (f_raw.v) {
+        a = (f_raw.l - csrc) + f_raw.g;
+        if (!EXPL) {
+          double y2 = 0.0;
+#pragma unroll
+          for (int d = 0; d < DIM; ++d) {
+            yv[d] = f_raw.y[d];
+            y2 = fma(yv[d], yv[d], y2);
+          }
+          a -= y2 / eps;
+        }
+        a = a * kLog2e - al;
+      }
       if (lrow < CHH) {
         const int sc = (half * CHH + lrow) * STR;
         stage[sc] = a;
         if (!EXPL) {
 #pragma unroll
-          for (int d = 0; d < DIM; ++d) stage[sc + 1 + d] = f_y[d];
+          for (int d = 0; d < DIM; ++d) stage[sc + 1 + d] = yv[d] - (d == 0 ? be : 0.0);
         }
       }
       wave_sync();
@@ -453,14 +478,15 @@ __global__ __launch_bounds__(64 * W) void k_node(Tables tb) {
         }
       }
     };
-    auto chunk_max = [&](double* Mc) {
+    // maxima over the staged chunk of the staged exponent minus off[r]
+    auto chunk_max = [&](const double* off, double* Mc) {
 #pragma unroll
       for (int r = 0; r < R; ++r) Mc[r] = -INFINITY;
 #pragma unroll 4
       for (int c = 0; c < CHH; ++c) {
         const double a = sth[c * STR];
 #pragma unroll
-        for (int r = 0; r < R; ++r) Mc[r] = fmax(Mc[r], wcol(r, c, a));
+        for (int r = 0; r < R; ++r) Mc[r] = fmax(Mc[r], wcol(r, c, a) - off[r]);
       }
     };
 
@@ -472,51 +498,138 @@ __global__ __launch_bounds__(64 * W) void k_node(Tables tb) {
     }
     bool two = !one;
     if (one) {
-      double sh[R];
+      // Row x is shifted by s(x) = sb(x) + dl(x).  With FOLD, sb(x) = al + be cx(x)
+      // is the chord, over the lane group's rows of least and greatest cx, of the
+      // previous row maxima (convex in cx), folded into the staged columns; a
+      // wave whose every row's previous max lies within [-64, 32] of the chord
+      // sums with dl = 0 and one FMA per pair ("folded"), otherwise (and after a
+      // re-shift) dl(x) carries the rest of the previous max ("row mode").
+      // Without FOLD, sb = 0 and s(x) is the previous max as is.
+      double sb[R], dl[R];
+      bool pmok[R];
+      double pmv[R];
+      // Every load here is unconditional (indexes clamped into the arrays), so
+      // the compiler can wait for exactly the ones a step needs: the previous
+      // maxima first, then the first two chunks' columns (only their staging
+      // needs the shift).
 #pragma unroll
       for (int r = 0; r < R; ++r) {
-        const double pm = vx[r] ? wmax[(size_t)rid * n + x[r]] : 0.0;
-        sh[r] = isfinite(pm) ? pm : 0.0;
+        pmv[r] = wmax[(size_t)rid * n + min(x[r], n - 1)];
+        sb[r] = 0.0;
       }
-      if (span > 0) fetch_chunk(c_lo, min(CHH, c_hi - c_lo));
-      if (CHH < span) fetch_into(c_lo + CHH, min(CHH, c_hi - c_lo - CHH), g_base, g_y);
+      fetch_chunk(c_lo, min(CHH, c_hi - c_lo));
+      fetch_into(c_lo + CHH, min(CHH, c_hi - c_lo - CHH), g_raw);
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        if (!vx[r]) pmv[r] = 0.0;
+        pmok[r] = vx[r] && isfinite(pmv[r]);
+      }
+      bool rowmode = true;
+      if constexpr (FOLD) {
+        // chord through the lane group's first and last valid rows (the rows
+        // of least and greatest cx when the supports are sorted; otherwise the
+        // check below sends the wave to row mode), read with v_readlane
+        const int i_last = min(TR, n - ti.row0) - 1;  // >= 0: the tile has a valid row
+        const int r_last = i_last / LPR, l_last = i_last - r_last * LPR;
+        double cl = 0.0, pl = 0.0;
+#pragma unroll
+        for (int r = 0; r < R; ++r)
+          if (r == r_last) {
+            cl = cx[r][0];
+            pl = pmv[r];
+          }
+        auto rdl = [](double v, int l) -> double {
+          const long long b = __double_as_longlong(v);
+          const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffff), l);
+          const int hi = __builtin_amdgcn_readlane((int)(b >> 32), l);
+          return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+        };
+        double c0v = rdl(cx[0][0], 0), p0v = rdl(pmv[0], 0), c1v = rdl(cl, l_last), p1v = rdl(pl, l_last);
+        if (H == 2) {
+          const double c0h = rdl(cx[0][0], LPR), p0h = rdl(pmv[0], LPR);
+          const double c1h = rdl(cl, LPR + l_last), p1h = rdl(pl, LPR + l_last);
+          if (half) {
+            c0v = c0h; p0v = p0h; c1v = c1h; p1v = p1h;
+          }
+        }
+        if (isfinite(p0v) && isfinite(p1v)) {
+          if (c1v != c0v) {
+            be = (p1v - p0v) / (c1v - c0v);
+            al = p0v - be * c0v;
+          } else {
+            al = fmax(p0v, p1v);
+          }
+        }
+        if (!isfinite(al) || !isfinite(be)) al = be = 0.0;
+        int bad = 0;
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+          sb[r] = fma(be, cx[r][0], al);
+          if (pmok[r] && !(pmv[r] - sb[r] >= -64.0 && pmv[r] - sb[r] <= 32.0)) bad = 1;
+        }
+        rowmode = __any(bad);
+      }
+#pragma unroll
+      for (int r = 0; r < R; ++r) dl[r] = rowmode ? (pmok[r] ? pmv[r] : 0.0) - sb[r] : 0.0;
+
       for (int j0 = 0; j0 < span; j0 += CHH) {
         const int c0 = c_lo + j0;
         const int cn = min(CHH, c_hi - c0);
         load_cost(c0, cn);
         stage_fetched();
         advance();
-        if (j0 + 2 * CHH < span) fetch_into(c0 + 2 * CHH, min(CHH, c_hi - c0 - 2 * CHH), g_base, g_y);
-        // one pass: sums relative to the shifts, chunk maxima alongside
-        double Mc[R], Sc[R];
+        fetch_into(c0 + 2 * CHH, min(CHH, c_hi - c0 - 2 * CHH), g_raw);  // past the range: masked
+        // one pass: sums of 2^(d) with d the staged exponent minus dl, FP32
+        // maxima of d alongside
+        float Mf[R];
+        double Sc[R];
 #pragma unroll
         for (int r = 0; r < R; ++r) {
-          Mc[r] = -INFINITY;
+          Mf[r] = -INFINITY;
           Sc[r] = 0.0;
         }
+        auto pass = [&](auto row_t) {
+          constexpr bool ROW = decltype(row_t)::value;
 #pragma unroll 4
-        for (int c = 0; c < CHH; c += 2) {
-          const double a0 = sth[c * STR], a1 = sth[(c + 1) * STR];
+          for (int c = 0; c < CHH; c += 2) {
+            const double a0 = sth[c * STR], a1 = sth[(c + 1) * STR];
 #pragma unroll
-          for (int r = 0; r < R; ++r) {
-            const double w0 = wcol(r, c, a0), w1 = wcol(r, c + 1, a1);
-            Mc[r] = fmax(Mc[r], fmax(w0, w1));
-            const float p = exp2_hw((float)(w0 - sh[r])) + exp2_hw((float)(w1 - sh[r]));
-            Sc[r] += (double)p;
-          }
-        }
-        int hi = 0;
-#pragma unroll
-        for (int r = 0; r < R; ++r) hi |= (vx[r] && Mc[r] - sh[r] > kShiftHi) ? 1 : 0;
-        if (__any(hi)) {
-#pragma unroll
-          for (int r = 0; r < R; ++r) {
-            if (Mc[r] - sh[r] > kShiftHi) {
-              S[r] *= exp2(sh[r] - Mc[r]);
-              sh[r] = Mc[r];
+            for (int r = 0; r < R; ++r) {
+              double d0 = wcol(r, c, a0), d1 = wcol(r, c + 1, a1);
+              if (ROW) {
+                d0 -= dl[r];
+                d1 -= dl[r];
+              }
+              const float f0 = (float)d0, f1 = (float)d1;
+              Mf[r] = fmaxf(Mf[r], fmaxf(f0, f1));
+              const float p = exp2_hw(f0) + exp2_hw(f1);
+              Sc[r] += (double)p;
             }
           }
-          chunk_sum(sh, Sc);
+        };
+        if (rowmode) pass(std::true_type{});
+        else pass(std::false_type{});
+        double Mc[R];  // chunk maxima of the exponent, absolute
+#pragma unroll
+        for (int r = 0; r < R; ++r) Mc[r] = (sb[r] + dl[r]) + (double)Mf[r];
+        int hi = 0;
+#pragma unroll
+        for (int r = 0; r < R; ++r) hi |= (vx[r] && !(Mf[r] <= (float)kShiftHi)) ? 1 : 0;
+        if (__any(hi)) {
+          // exact FP64 maxima; rows far above their shift move it and the
+          // chunk is summed again in row mode
+          double Md[R];
+          chunk_max(dl, Md);
+#pragma unroll
+          for (int r = 0; r < R; ++r) {
+            Mc[r] = (sb[r] + dl[r]) + Md[r];
+            if (Md[r] > kShiftHi) {
+              S[r] *= exp2(-Md[r]);
+              dl[r] += Md[r];
+            }
+          }
+          rowmode = true;
+          chunk_sum(dl, Sc);
         }
 #pragma unroll
         for (int r = 0; r < R; ++r) {
@@ -527,15 +640,17 @@ __global__ __launch_bounds__(64 * W) void k_node(Tables tb) {
       }
       int lo = 0;
 #pragma unroll
-      for (int r = 0; r < R; ++r) lo |= (vx[r] && M[r] > -INFINITY && M[r] - sh[r] < kShiftLo) ? 1 : 0;
+      for (int r = 0; r < R; ++r) lo |= (vx[r] && M[r] > -INFINITY && M[r] - (sb[r] + dl[r]) < kShiftLo) ? 1 : 0;
       if (__any(lo)) {
         two = true;  // a row's terms fell out of FP32 range: two passes
       } else {
 #pragma unroll
-        for (int r = 0; r < R; ++r) S[r] = (M[r] > -INFINITY) ? S[r] * exp2(sh[r] - M[r]) : 0.0;
+        for (int r = 0; r < R; ++r) S[r] = (M[r] > -INFINITY) ? S[r] * exp2((sb[r] + dl[r]) - M[r]) : 0.0;
       }
     }
     if (two) {
+      al = be = 0.0;
+      const double zero[R] = {};
 #pragma unroll
       for (int r = 0; r < R; ++r) {
         M[r] = -INFINITY;
@@ -547,7 +662,7 @@ __global__ __launch_bounds__(64 * W) void k_node(Tables tb) {
         load_cost(c0, cn);
         stage_chunk(c0, cn);
         double Mc[R], Sc[R], sh[R];
-        chunk_max(Mc);
+        chunk_max(zero, Mc);
 #pragma unroll
         for (int r = 0; r < R; ++r) {
           if (Mc[r] > M[r]) {
@@ -564,10 +679,11 @@ __global__ __launch_bounds__(64 * W) void k_node(Tables tb) {
     }
 #pragma unroll
     for (int r = 0; r < R; ++r) {
-      if (vx[r]) wmax[(size_t)rid * n + x[r]] = M[r];
-      if (lds) {
+      if (LDS_T) {
+        // the range maxima go to wmax in the merge below
         s_part[k * gr + rid][r * LPR + lrow] = make_double2(M[r], S[r]);
       } else {
+        if (vx[r]) wmax[(size_t)rid * n + x[r]] = M[r];
         // one wave per edge (g = 1): its H ranges merged across the lane
         // groups, the message goes straight to mfull
         double Mm = M[r], Sm = S[r];
@@ -586,17 +702,29 @@ __global__ __launch_bounds__(64 * W) void k_node(Tables tb) {
           md.mfull[x[r]] = (Mm > -INFINITY && Sm > 0.0) ? kLn2 * (Mm + log2(Sm)) - x2[r] / eps : -INFINITY;
       }
     }
+  };
+  if (lds) {
+    for (int k = k_first; k < deg; k += k_step) edge_sums(k, std::true_type{});
+  } else {
+    for (int k = k_first; k < deg; k += k_step) edge_sums(k, std::false_type{});
   }
   __syncthreads();
   double* __restrict__ rec = nd.tpart + (size_t)(ti.row0 / TR) * (deg + kRecExtra);
   const double c_old = nd.c ? nd.c[cur] : 0.0;
 
   if (lds) {
-    // merge the gr ranges of every (edge, row) into m (natural log)
+    // merge the gr ranges of every (edge, row) into m (natural log); each
+    // range's max is the row's next one-pass shift
     for (int it = threadIdx.x; it < deg * TR; it += NT) {
       const int k = it / TR, lr = it - k * TR;
+      const int xr = ti.row0 + lr;
+      double* __restrict__ wm = mds[k].wmax;
       double Mx = -INFINITY;
-      for (int u = 0; u < gr; ++u) Mx = fmax(Mx, s_part[k * gr + u][lr].x);
+      for (int u = 0; u < gr; ++u) {
+        const double mu = s_part[k * gr + u][lr].x;
+        if (xr < n) wm[(size_t)u * n + xr] = mu;
+        Mx = fmax(Mx, mu);
+      }
       double St = 0.0;
       if (Mx > -INFINITY) {
         for (int u = 0; u < gr; ++u) {

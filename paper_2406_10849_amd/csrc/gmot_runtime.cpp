@@ -559,8 +559,10 @@ static int run_plan(Plan* pl, const gmot_opts* o, gmot_result* outs, const std::
     st.checked_t = 0;
     st.counter = 0;
     st.clk_start = st.clk_stop = 0;
-    // the first computation of every message in this call takes two passes
-    st.onepass_from = o->msg_passes == GMOT_PASSES_TWO ? INT64_MAX : p->t + 2;
+    // by default the first computation of every message in this call takes two passes
+    st.onepass_from = o->msg_passes == GMOT_PASSES_TWO ? INT64_MAX
+                      : o->msg_passes == GMOT_PASSES_ONE ? p->t
+                                                          : p->t + 2;
     st.best_err = INFINITY;
     st.best_t = p->t;
     st.stall_window = stall_window;
@@ -1058,7 +1060,7 @@ static int validate_opts(const gmot_opts* o) {
     return fail(GMOT_EINVAL, "unknown precision");
   if (o->schedule != GMOT_SCHED_LAYER && o->schedule != GMOT_SCHED_PER_NODE)
     return fail(GMOT_EINVAL, "unknown schedule");
-  if (o->msg_passes != GMOT_PASSES_AUTO && o->msg_passes != GMOT_PASSES_TWO)
+  if (o->msg_passes != GMOT_PASSES_AUTO && o->msg_passes != GMOT_PASSES_ONE && o->msg_passes != GMOT_PASSES_TWO)
     return fail(GMOT_EINVAL, "unknown msg_passes");
   return GMOT_OK;
 }

@@ -367,3 +367,63 @@ def test_three_dimensional_supports(ctx):
     ref.solve(tol=1e-10, max_steps=100000)
     er = ref.evaluate()
     converged_check(g, p, 1e-6, er["dual"], er["scale"])
+
+
+def _shuffled(p, seed):
+    """The same problem with every node's support points (and marginal) in a
+    seeded random order."""
+    q = copy.deepcopy(p)
+    rng = np.random.default_rng(seed)
+    off, moff = p.offsets(), p.marginal_offsets()
+    for j in range(p.n_nodes):
+        perm = rng.permutation(int(p.sizes[j]))
+        q.support[off[j]:off[j + 1]] = p.support[off[j]:off[j + 1]][perm]
+        if p.is_fixed[j]:
+            m0, m1 = moff[j], moff[j] + int(p.sizes[j])
+            q.marginal[m0:m1] = p.marginal[m0:m1][perm]
+    return q
+
+
+def test_scattered_one_dimensional_rows(ctx):
+    """1D supports in a random order per node: a tile's rows spread over the
+    whole support, so the one-pass sums keep a separate shift per row instead
+    of the per-tile affine one; FP32-core iterates against the oracle and
+    against two-pass sums after the same half-sweeps."""
+    p = _shuffled(make_chain(n_nodes=8, n=300, eps=1e-3), 5)
+    steps = 40
+    o = TreeOracle(p)
+    o.run_fixed(steps)
+    eo = o.evaluate()
+    g1, g2 = gpu_problem(ctx, p), gpu_problem(ctx, p)
+    assert g1.solve(tol=0.0, max_steps=steps, passes="auto")["steps"] == steps
+    assert g2.solve(tol=0.0, max_steps=steps, passes="two")["steps"] == steps
+    for g in (g1, g2):
+        assert abs(g.evaluate()["dual"] - eo["dual"]) <= 1e-6 * eo["scale"]
+        for e in range(p.n_edges):
+            assert np.max(np.abs(g.coupling(e) - o.coupling(e))) <= 1e-6
+
+
+@pytest.mark.parametrize("offset", [300.0, -300.0])
+def test_one_pass_far_from_stored_shifts(ctx, offset):
+    """One-pass sums from the first half-sweep (passes="one") on potentials
+    moved 300 nats away from those the stored shifts were computed for: every
+    row's max lies far above its shift (moved inside the kernel) or far below
+    it (the wave falls back to two passes).  Iterates against the oracle run
+    from the same potentials, sorted and shuffled 1D supports."""
+    for p in (make_chain(n_nodes=8, n=200, eps=1e-2), _shuffled(make_chain(n_nodes=8, n=200, eps=1e-2), 6)):
+        g = gpu_problem(ctx, p)
+        g.solve(tol=0.0, max_steps=6)
+        o = TreeOracle(p)
+        o.run_fixed(6)
+        lam = o.potentials() + offset
+        g.set_potentials(lam)
+        o2 = TreeOracle(p)
+        o2.Lam = o2.set_potentials(lam)
+        steps = 4
+        r = g.solve(tol=0.0, max_steps=steps, passes="one", restart=False, verify=False)
+        assert r["steps"] == steps
+        o2.run_fixed(steps)
+        eo = o2.evaluate()
+        assert abs(g.evaluate()["dual"] - eo["dual"]) <= 1e-6 * eo["scale"]
+        for e in range(p.n_edges):
+            assert np.max(np.abs(g.coupling(e) - o2.coupling(e))) <= 1e-6
