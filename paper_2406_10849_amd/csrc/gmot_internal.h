@@ -46,14 +46,18 @@ constexpr double kLn2 = 0.693147180559945309417;
 
 enum Done : int { kRunning = 0, kConverged = 1, kMaxSteps = 2, kNonFinite = 3, kStalled = 4 };
 
+// Potential slots per class: a class's held potentials after its u-th update
+// are in slot u mod kSlots, so the two states before any update stay intact.
+constexpr int kSlots = 3;
+
 // One message m_{k->j}: rows index supp(j) ("dst"), columns index supp(k) ("src").
 struct MsgDesc {
   const double* supp_dst;    // [n_dst * dim]
   const double* supp_src;    // [n_src * dim]
-  const double* lam_src[2];  // stored L_(k,j) slots, [n_src]
-  const double* c_src;       // c_k slots [2] (NULL: constrained source, c = 0)
+  const double* lam_src[kSlots];  // stored L_(k,j) slots, [n_src]
+  const double* c_src;       // c_k slots [kSlots] (NULL: constrained source, c = 0)
   const double* lg_src;      // log gamma_k, [n_src]
-  double* lam_dst[2];        // stored L_(j,k) slots, [n_dst]
+  double* lam_dst[kSlots];   // stored L_(j,k) slots, [n_dst]
   double2* partial;          // [n_dst * ns]: evaluation pass, per row its ns column splits, each
                              // (split max M, sum of 2^(w - M))
   double* wmax;              // [kMaxRanges * n_dst]: node kernel, wave-major, per row the max of

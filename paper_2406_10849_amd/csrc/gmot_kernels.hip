@@ -304,8 +304,9 @@ __global__ __launch_bounds__(64 * W) void k_node(Tables tb) {
   const NodeItem nd = tb.nodes[ti.node];
   const long long t = st->t;
   if (st->done || ((t & 1) == 1) != (tb.colour == 0)) return;
-  const int cur = (int)(((t - 1) >> 1) & 1), nxt = cur ^ 1;
-  const int src_slot = (int)((t >> 1) & 1);
+  // slots: this class's held state before t, its update, the other class's held state
+  const int cur = (int)(((t - 1) >> 1) % kSlots), nxt = (cur + 1) % kSlots;
+  const int src_slot = (int)((t >> 1) % kSlots);
   const bool one = !F64 && t >= st->onepass_from;
   const MsgDesc* __restrict__ mds = tb.msgs + nd.msg0;
   const int n = nd.n, deg = nd.deg;
@@ -873,7 +874,7 @@ __global__ __launch_bounds__(64 * kFinWaves) void k_finalize(Tables tb) {
   InstState* st = tb.inst + blockIdx.x;
   const long long t = st->t;
   if (st->done || ((t & 1) == 1) != (tb.colour == 0)) return;
-  const int nxt = (int)((((t - 1) >> 1) & 1) ^ 1);
+  const int nxt = (int)((((t - 1) >> 1) + 1) % kSlots);
   const int i0 = st->node0[tb.colour], cnt = st->nnodes[tb.colour];
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   double esum = 0.0, emax = 0.0;
@@ -1104,7 +1105,7 @@ static hipError_t launch_msg_r(const Tables& tb, int n_items, int dim, int src_s
 
 hipError_t launch_msg(const Tables& tb, int n_items, int dim, int rows_per_lane, int src_slot, hipStream_t s) {
   if (n_items <= 0) return hipSuccess;
-  if (src_slot < 0 || src_slot > 1) return hipErrorInvalidValue;
+  if (src_slot < 0 || src_slot >= kSlots) return hipErrorInvalidValue;
   return rows_per_lane == 2 ? launch_msg_r<2>(tb, n_items, dim, src_slot, s)
                             : launch_msg_r<1>(tb, n_items, dim, src_slot, s);
 }

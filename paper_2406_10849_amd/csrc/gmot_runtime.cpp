@@ -74,18 +74,18 @@ struct gmot_problem {
   double* d_support = nullptr;
   double* d_lg = nullptr;
   double* d_mu = nullptr;
-  double* d_lam[2] = {nullptr, nullptr};
+  double* d_lam[kSlots] = {};
   double* d_mfull = nullptr;
   double* d_abar = nullptr;
   double* d_qbar = nullptr;
-  double* d_c = nullptr;  // [2N]: node normaliser c_j, slot s at 2j + s (0 for constrained nodes)
+  double* d_c = nullptr;  // [kSlots N]: node normaliser c_j, slot s at kSlots j + s (0 for constrained nodes)
   float* d_cost = nullptr;
   int64_t t = 1;
   uint64_t version = 0;   // bumped whenever the held state changes
   Plan* plan = nullptr;
   RoundState* round = nullptr;
 
-  const double* c_ptr(int j) const { return fixed[j] ? nullptr : d_c + 2 * j; }
+  const double* c_ptr(int j) const { return fixed[j] ? nullptr : d_c + kSlots * j; }
 
   int de_of(int j, int k) const {
     for (size_t i = 0; i < nbrs[j].size(); ++i)
@@ -93,7 +93,7 @@ struct gmot_problem {
     return -1;
   }
   // slot holding the committed value of class c's potentials
-  int slot_of_class(int c) const { return c == 0 ? (int)((t / 2) & 1) : (int)(((t - 1) / 2) & 1); }
+  int slot_of_class(int c) const { return c == 0 ? (int)((t / 2) % kSlots) : (int)(((t - 1) / 2) % kSlots); }
 };
 
 // Timing mode: events per half-sweep, and back-to-back repeats of the message
@@ -257,7 +257,7 @@ static int build_plan(gmot_ctx* ctx, const std::vector<gmot_problem*>& probs, No
         nd.mu = p->fixed[j] ? p->d_mu + p->node_off[j] : nullptr;
         nd.abar = p->d_abar + p->node_off[j];
         nd.qbar = p->d_qbar + p->node_off[j];
-        nd.c = p->fixed[j] ? nullptr : p->d_c + 2 * j;
+        nd.c = p->fixed[j] ? nullptr : p->d_c + kSlots * j;
         nd.tiles = (int)ceil_div(p->sizes[j], TRows);
         {
           double src_cols = 0.0;
@@ -274,7 +274,7 @@ static int build_plan(gmot_ctx* ctx, const std::vector<gmot_problem*>& probs, No
           MsgDesc md{};
           md.supp_dst = p->d_support + p->node_off[j] * p->dim;
           md.supp_src = p->d_support + p->node_off[k] * p->dim;
-          for (int s = 0; s < 2; ++s) {
+          for (int s = 0; s < kSlots; ++s) {
             md.lam_src[s] = p->d_lam[s] + p->de_off[de_src];
             md.lam_dst[s] = p->d_lam[s] + p->de_off[de_dst];
           }
@@ -881,20 +881,19 @@ static int upload(const gmot_tree_desc* d, gmot_problem* p) {
   const size_t o_sup = take(sizeof(double) * P * p->dim);
   const size_t o_lg = take(sizeof(double) * P);
   const size_t o_mu = take(sizeof(double) * P);
-  const size_t o_lam0 = take(sizeof(double) * D);
-  const size_t o_lam1 = take(sizeof(double) * D);
+  size_t o_lam[kSlots];
+  for (int q = 0; q < kSlots; ++q) o_lam[q] = take(sizeof(double) * D);
   const size_t o_mf = take(sizeof(double) * D);
   const size_t o_ab = take(sizeof(double) * P);
   const size_t o_qb = take(sizeof(double) * P);
-  const size_t o_c = take(sizeof(double) * 2 * p->N);
+  const size_t o_c = take(sizeof(double) * kSlots * p->N);
   const size_t o_cost = take(sizeof(float) * 2 * p->total_cost);
   if (hipMalloc(&p->arena, off) != hipSuccess) return fail(GMOT_ENOMEM, "problem arena allocation failed");
   char* base = (char*)p->arena;
   p->d_support = (double*)(base + o_sup);
   p->d_lg = (double*)(base + o_lg);
   p->d_mu = (double*)(base + o_mu);
-  p->d_lam[0] = (double*)(base + o_lam0);
-  p->d_lam[1] = (double*)(base + o_lam1);
+  for (int q = 0; q < kSlots; ++q) p->d_lam[q] = (double*)(base + o_lam[q]);
   p->d_mfull = (double*)(base + o_mf);
   p->d_abar = (double*)(base + o_ab);
   p->d_qbar = (double*)(base + o_qb);
@@ -916,10 +915,9 @@ static int upload(const gmot_tree_desc* d, gmot_problem* p) {
   HIPCHK(hipMemcpy(p->d_support, sup.data(), sizeof(double) * P * p->dim, hipMemcpyHostToDevice));
   HIPCHK(hipMemcpy(p->d_lg, lg.data(), sizeof(double) * P, hipMemcpyHostToDevice));
   HIPCHK(hipMemcpy(p->d_mu, mu.data(), sizeof(double) * P, hipMemcpyHostToDevice));
-  HIPCHK(hipMemsetAsync(p->d_lam[0], 0, sizeof(double) * D, s));
-  HIPCHK(hipMemsetAsync(p->d_lam[1], 0, sizeof(double) * D, s));
+  for (int q = 0; q < kSlots; ++q) HIPCHK(hipMemsetAsync(p->d_lam[q], 0, sizeof(double) * D, s));
   HIPCHK(hipMemsetAsync(p->d_mfull, 0, sizeof(double) * D, s));
-  HIPCHK(hipMemsetAsync(p->d_c, 0, sizeof(double) * 2 * p->N, s));
+  HIPCHK(hipMemsetAsync(p->d_c, 0, sizeof(double) * kSlots * p->N, s));
   if (p->total_cost) {
     HIPCHK(hipMemcpy(p->d_cost, d->cost, sizeof(float) * p->total_cost, hipMemcpyHostToDevice));
     std::vector<float> tr;
@@ -953,7 +951,7 @@ static int time_plan(Plan* pl, double* ms) {
   std::vector<size_t> off(n + 1, 0);
   for (size_t i = 0; i < n; ++i) {
     const gmot_problem* p = pl->probs[i];
-    off[i + 1] = off[i] + 2 * (size_t)p->total_de + 2 * (size_t)p->N;
+    off[i + 1] = off[i] + kSlots * ((size_t)p->total_de + (size_t)p->N);
   }
   double* snap = nullptr;
   if (hipMalloc(&snap, sizeof(double) * std::max<size_t>(1, off[n])) != hipSuccess)
@@ -966,11 +964,11 @@ static int time_plan(Plan* pl, double* ms) {
       double* b = snap + off[i];
       const size_t D = p->total_de;
       const hipMemcpyKind k = hipMemcpyDeviceToDevice;
-      if (e == hipSuccess) e = hipMemcpyAsync(save ? b : p->d_lam[0], save ? p->d_lam[0] : b, sizeof(double) * D, k, s);
+      for (int q = 0; q < kSlots && e == hipSuccess; ++q)
+        e = hipMemcpyAsync(save ? b + q * D : p->d_lam[q], save ? p->d_lam[q] : b + q * D, sizeof(double) * D, k, s);
       if (e == hipSuccess)
-        e = hipMemcpyAsync(save ? b + D : p->d_lam[1], save ? p->d_lam[1] : b + D, sizeof(double) * D, k, s);
-      if (e == hipSuccess)
-        e = hipMemcpyAsync(save ? b + 2 * D : p->d_c, save ? p->d_c : b + 2 * D, sizeof(double) * 2 * p->N, k, s);
+        e = hipMemcpyAsync(save ? b + kSlots * D : p->d_c, save ? p->d_c : b + kSlots * D,
+                           sizeof(double) * kSlots * p->N, k, s);
       if (save) t_saved[i] = p->t;
       else p->t = t_saved[i];
     }
@@ -1067,7 +1065,7 @@ static int validate_opts(const gmot_opts* o) {
 
 static int restart_problem(gmot_problem* p) {
   if (p->total_de > 0) HIPCHK(hipMemsetAsync(p->d_lam[0], 0, sizeof(double) * p->total_de, p->ctx->stream));
-  HIPCHK(hipMemsetAsync(p->d_c, 0, sizeof(double) * 2 * p->N, p->ctx->stream));
+  HIPCHK(hipMemsetAsync(p->d_c, 0, sizeof(double) * kSlots * p->N, p->ctx->stream));
   p->t = 1;
   ++p->version;
   return GMOT_OK;
@@ -1098,8 +1096,8 @@ static EdgeDesc edge_desc(const gmot_problem* p, int e) {
   const int sa = p->slot_of_class(p->colour[a]), sb = p->slot_of_class(p->colour[b]);
   ed.lam_a = p->d_lam[sa] + p->de_off[2 * e];
   ed.lam_b = p->d_lam[sb] + p->de_off[2 * e + 1];
-  ed.c_a = p->fixed[a] ? nullptr : p->d_c + 2 * a + sa;
-  ed.c_b = p->fixed[b] ? nullptr : p->d_c + 2 * b + sb;
+  ed.c_a = p->fixed[a] ? nullptr : p->d_c + kSlots * a + sa;
+  ed.c_b = p->fixed[b] ? nullptr : p->d_c + kSlots * b + sb;
   ed.lg_a = p->d_lg + p->node_off[a];
   ed.lg_b = p->d_lg + p->node_off[b];
   ed.cost = p->cost_kind == GMOT_COST_EXPLICIT ? p->d_cost + p->cost_off[e] : nullptr;
@@ -1145,8 +1143,8 @@ static RoundDesc round_desc(const gmot_problem* p, int de, double* arrays) {
   d.supp_c = p->d_support + p->node_off[k] * p->dim;
   d.lam_r = p->d_lam[sj] + p->de_off[de];
   d.lam_c = p->d_lam[sk] + p->de_off[de ^ 1];
-  d.c_r = p->fixed[j] ? nullptr : p->d_c + 2 * j + sj;
-  d.c_c = p->fixed[k] ? nullptr : p->d_c + 2 * k + sk;
+  d.c_r = p->fixed[j] ? nullptr : p->d_c + kSlots * j + sj;
+  d.c_c = p->fixed[k] ? nullptr : p->d_c + kSlots * k + sk;
   d.lg_r = p->d_lg + p->node_off[j];
   d.lg_c = p->d_lg + p->node_off[k];
   if (p->cost_kind == GMOT_COST_EXPLICIT)  // cost[y * n_j + x]: C_e^T when j = a, C_e when j = b
@@ -1479,17 +1477,19 @@ int gmot_get_potentials(gmot_problem* p, double* out) {
   if (p->total_de == 0) return GMOT_OK;
   HIPCHK(hipSetDevice(p->ctx->device));
   // Lam_(j,k) = L_(j,k) - c_j with both read from node j's committed slot
-  std::vector<double> s0(p->total_de), s1(p->total_de), cv(2 * p->N);
+  std::vector<double> sv[kSlots], cv(kSlots * p->N);
   HIPCHK(hipStreamSynchronize(p->ctx->stream));
-  HIPCHK(hipMemcpy(s0.data(), p->d_lam[0], sizeof(double) * p->total_de, hipMemcpyDeviceToHost));
-  HIPCHK(hipMemcpy(s1.data(), p->d_lam[1], sizeof(double) * p->total_de, hipMemcpyDeviceToHost));
-  HIPCHK(hipMemcpy(cv.data(), p->d_c, sizeof(double) * 2 * p->N, hipMemcpyDeviceToHost));
+  for (int q = 0; q < kSlots; ++q) {
+    sv[q].resize(p->total_de);
+    HIPCHK(hipMemcpy(sv[q].data(), p->d_lam[q], sizeof(double) * p->total_de, hipMemcpyDeviceToHost));
+  }
+  HIPCHK(hipMemcpy(cv.data(), p->d_c, sizeof(double) * kSlots * p->N, hipMemcpyDeviceToHost));
   for (int de = 0; de < 2 * p->E; ++de) {
     const int e = de >> 1;
     const int j = (de & 1) ? p->edges[2 * e + 1] : p->edges[2 * e];
     const int slot = p->slot_of_class(p->colour[j]);
-    const std::vector<double>& src = slot ? s1 : s0;
-    const double c = p->fixed[j] ? 0.0 : cv[2 * j + slot];
+    const std::vector<double>& src = sv[slot];
+    const double c = p->fixed[j] ? 0.0 : cv[kSlots * j + slot];
     for (int64_t i = p->de_off[de]; i < p->de_off[de + 1]; ++i) out[i] = src[i] - c;
   }
   return GMOT_OK;
@@ -1505,7 +1505,7 @@ int gmot_get_potentials_dev(gmot_problem* p, double* out_dev) {
     const int j = (de & 1) ? p->edges[2 * e + 1] : p->edges[2 * e];
     const int slot = p->slot_of_class(p->colour[j]);
     segs[de] = {p->d_lam[slot] + p->de_off[de], out_dev + p->de_off[de],
-                p->fixed[j] ? nullptr : p->d_c + 2 * j + slot, p->de_off[de + 1] - p->de_off[de]};
+                p->fixed[j] ? nullptr : p->d_c + kSlots * j + slot, p->de_off[de + 1] - p->de_off[de]};
   }
   void* buf = nullptr;
   if (hipMalloc(&buf, sizeof(SegCopy) * segs.size()) != hipSuccess) return fail(GMOT_ENOMEM, "copy table");
@@ -1525,7 +1525,7 @@ int gmot_set_potentials(gmot_problem* p, const double* in) {
   HIPCHK(hipSetDevice(p->ctx->device));
   HIPCHK(hipStreamSynchronize(p->ctx->stream));
   if (p->total_de) HIPCHK(hipMemcpy(p->d_lam[0], in, sizeof(double) * p->total_de, hipMemcpyHostToDevice));
-  HIPCHK(hipMemset(p->d_c, 0, sizeof(double) * 2 * p->N));
+  HIPCHK(hipMemset(p->d_c, 0, sizeof(double) * kSlots * p->N));
   HIPCHK(hipDeviceSynchronize());
   p->t = 1;
   ++p->version;
@@ -1538,7 +1538,7 @@ int gmot_set_potentials_dev(gmot_problem* p, const double* in_dev) {
   if (p->total_de)
     HIPCHK(hipMemcpyAsync(p->d_lam[0], in_dev, sizeof(double) * p->total_de, hipMemcpyDeviceToDevice,
                           p->ctx->stream));
-  HIPCHK(hipMemsetAsync(p->d_c, 0, sizeof(double) * 2 * p->N, p->ctx->stream));
+  HIPCHK(hipMemsetAsync(p->d_c, 0, sizeof(double) * kSlots * p->N, p->ctx->stream));
   p->t = 1;
   ++p->version;
   return GMOT_OK;
@@ -1711,7 +1711,7 @@ int gmot_star_apply_dev(gmot_problem* const* probs, int32_t count, const float* 
   if (rc) return rc;
   hipStream_t s = probs[0]->ctx->stream;
   HIPCHK(hipMemsetAsync(d_rej, 0, sizeof(int), s));
-  for (int i = 0; i < count; ++i) HIPCHK(hipMemsetAsync(probs[i]->d_c, 0, sizeof(double) * 2 * probs[i]->N, s));
+  for (int i = 0; i < count; ++i) HIPCHK(hipMemsetAsync(probs[i]->d_c, 0, sizeof(double) * kSlots * probs[i]->N, s));
   HIPCHK(launch_star_apply(d, count, L, n, y_dev, out_scale, d_rej, s));
   int rej = 0;
   HIPCHK(hipMemcpyAsync(&rej, d_rej, sizeof(int), hipMemcpyDeviceToHost, s));
