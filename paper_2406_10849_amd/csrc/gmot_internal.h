@@ -64,8 +64,10 @@ struct MsgDesc {
                              // each wave's column range at the last computation (next shift)
   double* mfull;             // merged message m_{k->j}, [n_dst], natural log
   const float* cost;         // explicit cost stored src-major: cost[y * n_dst + x] = C_(j,k)(x, y)
+  const double* src_tpart;   // tile records of the source node k (its c_k comes from them)
   int32_t n_dst, n_src, ns, inst;
-  int32_t dim, cost_kind, pad0, pad1;
+  int32_t dim, cost_kind, src_tiles, src_deg;  // source node's tile count and degree
+  int32_t src_free, pad0, pad1, pad2;          // 1: free source node (c_k from the records), 0: c_k = 0
   double eps;
 };
 
@@ -91,7 +93,7 @@ struct NodeItem {
   const double* mu;          // mu_j for constrained nodes, else NULL
   double* abar;              // scratch [n]: mean_k m_{k->j}
   double* qbar;              // scratch [n]: arithmetic mean_k q_(j,k)
-  double* c;                 // c_j slots [2] (NULL for constrained nodes)
+  double* c;                 // c_j slots [kSlots] (NULL for constrained nodes)
   double* tpart;             // tile records
 };
 
@@ -119,6 +121,7 @@ struct InstState {
   double best_err;           // smallest stopping sum seen in this call
   long long best_t;          // the half-sweep that measured it
   long long stall_window;    // stop as stalled after this many half-sweeps without a new minimum (0: never)
+  long long t_first;         // first half-sweep of this run: tile records are this run's from t_first on
 };
 
 struct Tables {

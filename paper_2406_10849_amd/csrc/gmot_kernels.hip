@@ -38,6 +38,27 @@ __device__ inline double wave_max(double v) {
   for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
   return v;
 }
+
+// A free node's normaliser c_j = LSE over its tile records of the (max,
+// scaled sum) pairs of abar at record entry col: tiles lane, lane + 64, ...
+// per lane, then a wave max and a wave sum, so every caller gets the same
+// bits.  (m0, s0) are the pair of tile `lane`, loaded by the caller (any
+// value when lane >= tiles); every lane returns c_j.
+__device__ inline double tile_lse(const double* __restrict__ tp, int tiles, int stride, int col, double m0,
+                                  double s0) {
+  const int lane = threadIdx.x & 63;
+  if (lane >= tiles) m0 = -INFINITY;
+  double M = m0;
+  for (int tt = lane + 64; tt < tiles; tt += 64) M = fmax(M, tp[(size_t)tt * stride + col]);
+  M = wave_max(M);
+  double S = (m0 > -INFINITY) ? s0 * exp(m0 - M) : 0.0;
+  for (int tt = lane + 64; tt < tiles; tt += 64) {
+    const double mt = tp[(size_t)tt * stride + col];
+    if (mt > -INFINITY) S += tp[(size_t)tt * stride + col + 1] * exp(mt - M);
+  }
+  S = wave_sum(S);
+  return M + log(S);
+}
 // Block-wide reductions over the 4 waves of a 256-thread block; every thread
 // gets the result.  `sh` needs 4 doubles; the leading barrier protects reuse.
 __device__ inline double block_sum(double v, double* sh) {
@@ -298,6 +319,7 @@ __global__ __launch_bounds__(64 * W) void k_node(Tables tb) {
   __shared__ double s_m[kNodeDegLDS][TR];
   __shared__ double s_q[kNodeDegLDS][TR];
   __shared__ double s_x2[TR];
+  __shared__ double s_csrc[kNodeDegLDS];  // c_k of each edge's source node
 
   const TileItem ti = tb.tiles[blockIdx.x];
   const InstState* st = tb.inst + ti.inst;
@@ -308,6 +330,7 @@ __global__ __launch_bounds__(64 * W) void k_node(Tables tb) {
   const int cur = (int)(((t - 1) >> 1) % kSlots), nxt = (cur + 1) % kSlots;
   const int src_slot = (int)((t >> 1) % kSlots);
   const bool one = !F64 && t >= st->onepass_from;
+  const bool rec_ok = t - 1 >= st->t_first;
   const MsgDesc* __restrict__ mds = tb.msgs + nd.msg0;
   const int n = nd.n, deg = nd.deg;
   const bool lds = deg <= kNodeDegLDS;
@@ -372,8 +395,14 @@ __global__ __launch_bounds__(64 * W) void k_node(Tables tb) {
     // chunk loop length, the same for every lane group (a short last range
     // runs on with empty chunks)
     const int span = H == 1 ? c_hi - c_lo : per;
+    // The source's normaliser c_k only shifts the message (m = m' - c_k with m'
+    // summed over L + log gamma): it is formed from the source node's tile
+    // records after the column loop; those loads go out first.
+    const GDbl* __restrict__ srec = (const GDbl*)md.src_tpart;
+    const int s_stride = md.src_deg + kRecExtra, s_tile = min(lane, md.src_tiles - 1);
+    const double rec_m0 = srec[(size_t)s_tile * s_stride + md.src_deg];
+    const double rec_s0 = srec[(size_t)s_tile * s_stride + md.src_deg + 1];
     const GDbl* __restrict__ lam = (const GDbl*)md.lam_src[src_slot];
-    const double csrc = md.c_src ? ((const GDbl*)md.c_src)[src_slot] : 0.0;
     const GDbl* __restrict__ lg = (const GDbl*)md.lg_src;
     const GDbl* __restrict__ ys = (const GDbl*)md.supp_src;
     const GFlt* __restrict__ cost = (const GFlt*)md.cost;
@@ -413,7 +442,7 @@ __global__ __launch_bounds__(64 * W) void k_node(Tables tb) {
 #pragma unroll
       for (int d = 0; d < DIM; ++d) yv[d] = 0.0;
       if (f_raw.v) {
-        a = (f_raw.l - csrc) + f_raw.g;
+        a = f_raw.l + f_raw.g;
         if (!EXPL) {
           double y2 = 0.0;
 #pragma unroll
@@ -678,6 +707,13 @@ __global__ __launch_bounds__(64 * W) void k_node(Tables tb) {
         wave_sync();
       }
     }
+    // from the records when the source's last update (half-sweep t - 1) ran in
+    // this run, else its stored normaliser
+    double ck = 0.0;
+    if (sub == 0 && md.src_free)
+      ck = rec_ok ? tile_lse((const double*)md.src_tpart, md.src_tiles, s_stride, md.src_deg, rec_m0, rec_s0)
+                  : md.c_src[src_slot];
+    if (LDS_T && sub == 0 && lane == 0) s_csrc[k] = ck;
 #pragma unroll
     for (int r = 0; r < R; ++r) {
       if (LDS_T) {
@@ -700,7 +736,7 @@ __global__ __launch_bounds__(64 * W) void k_node(Tables tb) {
           Sm = St;
         }
         if (vx[r] && half == 0)
-          md.mfull[x[r]] = (Mm > -INFINITY && Sm > 0.0) ? kLn2 * (Mm + log2(Sm)) - x2[r] / eps : -INFINITY;
+          md.mfull[x[r]] = (Mm > -INFINITY && Sm > 0.0) ? kLn2 * (Mm + log2(Sm)) - x2[r] / eps - ck : -INFINITY;
       }
     }
   };
@@ -733,7 +769,7 @@ __global__ __launch_bounds__(64 * W) void k_node(Tables tb) {
           if (q.y > 0.0) St += (q.x == Mx) ? q.y : q.y * exp2(q.x - Mx);
         }
       }
-      s_m[k][lr] = (Mx > -INFINITY && St > 0.0) ? kLn2 * (Mx + log2(St)) - s_x2[lr] / eps : -INFINITY;
+      s_m[k][lr] = (Mx > -INFINITY && St > 0.0) ? kLn2 * (Mx + log2(St)) - s_x2[lr] / eps - s_csrc[k] : -INFINITY;
     }
     __syncthreads();
     // per (edge, row): q (free) or the term and update (constrained)
@@ -890,25 +926,9 @@ __global__ __launch_bounds__(64 * kFinWaves) void k_finalize(Tables tb) {
       emax = fmax(emax, e);
     }
     if (!nd.fixed) {
-      double M = -INFINITY, Mt[2] = {-INFINITY, -INFINITY}, St[2] = {0.0, 0.0};
-      // the first 128 tiles stay in registers; larger nodes reread their records
-      for (int tt = lane, u = 0; tt < tiles; tt += 64, ++u) {
-        const double mt = tp[(size_t)tt * stride + deg];
-        if (u < 2) {
-          Mt[u] = mt;
-          St[u] = tp[(size_t)tt * stride + deg + 1];
-        }
-        M = fmax(M, mt);
-      }
-      M = wave_max(M);
-      double S = 0.0;
-      for (int tt = lane, u = 0; tt < tiles; tt += 64, ++u) {
-        const double mt = u < 2 ? Mt[u] : tp[(size_t)tt * stride + deg];
-        const double sv = u < 2 ? St[u] : tp[(size_t)tt * stride + deg + 1];
-        if (mt > -INFINITY) S += sv * exp(mt - M);
-      }
-      S = wave_sum(S);
-      if (lane == 0) nd.c[nxt] = M + log(S);
+      const int t0 = min(lane, tiles - 1);
+      const double c = tile_lse(tp, tiles, stride, deg, tp[(size_t)t0 * stride + deg], tp[(size_t)t0 * stride + deg + 1]);
+      if (lane == 0) nd.c[nxt] = c;
     }
   }
   if (lane == 0) {

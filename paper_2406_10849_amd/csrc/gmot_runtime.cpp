@@ -236,6 +236,8 @@ static int build_plan(gmot_ctx* ctx, const std::vector<gmot_problem*>& probs, No
 
   // messages and node items (class-major within each instance)
   std::vector<int> msg_class;
+  std::map<size_t, std::pair<int, int>> msg_src;            // message -> (instance, source node)
+  std::map<std::pair<int, int>, std::pair<int, int>> item_of;  // (instance, node) -> (class, node item)
   int err_counter = 0;
   for (size_t i = 0; i < probs.size(); ++i) {
     gmot_problem* p = probs[i];
@@ -265,6 +267,7 @@ static int build_plan(gmot_ctx* ctx, const std::vector<gmot_problem*>& probs, No
           const int dk = p->cost_kind == GMOT_COST_EXPLICIT ? 0 : p->dim;
           ntl[c][dk].push_back({(int)pl->nodes[c].size(), nd.tiles, (int)i, src_cols});
         }
+        item_of[{(int)i, j}] = {c, (int)pl->nodes[c].size()};
         pl->nodes[c].push_back(nd);
         ++cnt;
         for (size_t q = 0; q < p->nbrs[j].size(); ++q) {
@@ -289,6 +292,8 @@ static int build_plan(gmot_ctx* ctx, const std::vector<gmot_problem*>& probs, No
           }
           md.n_dst = p->sizes[j];
           md.n_src = p->sizes[k];
+          md.src_free = p->fixed[k] ? 0 : 1;
+          msg_src[pl->msgs.size()] = {(int)i, k};
           md.inst = (int)i;
           md.dim = p->dim;
           md.cost_kind = p->cost_kind;
@@ -412,6 +417,12 @@ static int build_plan(gmot_ctx* ctx, const std::vector<gmot_problem*>& probs, No
   for (size_t m = 0; m < pl->msgs.size(); ++m) {
     pl->msgs[m].partial = pl->d_partial + partial_off[m];
     pl->msgs[m].wmax = pl->d_wmax + wmax_off[m];
+    // the source node's records (constrained sources too: read, then ignored)
+    const auto src = item_of.at(msg_src.at(m));
+    const NodeItem& sn = pl->nodes[src.first][src.second];
+    pl->msgs[m].src_tpart = sn.tpart;
+    pl->msgs[m].src_tiles = sn.tiles;
+    pl->msgs[m].src_deg = sn.deg;
   }
 
   hipStream_t s = ctx->stream;
@@ -550,6 +561,7 @@ static int run_plan(Plan* pl, const gmot_opts* o, gmot_result* outs, const std::
       continue;
     }
     st.t = p->t;
+    st.t_first = p->t;
     st.min_check_t = std::max<int64_t>(2, p->t + min_updates);
     st.updates = 0;
     st.max_updates = o->max_steps;
