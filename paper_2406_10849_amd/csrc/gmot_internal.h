@@ -122,6 +122,11 @@ struct InstState {
   long long best_t;          // the half-sweep that measured it
   long long stall_window;    // stop as stalled after this many half-sweeps without a new minimum (0: never)
   long long t_first;         // first half-sweep of this run: tile records are this run's from t_first on
+  // What the node blocks of a colour-c launch read (the fields above are
+  // written by the finalise step, which can run in the same launch): the
+  // half-sweep they compute, and whether the instance has stopped.
+  long long vt[2];
+  int vdone[2];
 };
 
 struct Tables {
@@ -133,6 +138,11 @@ struct Tables {
   double4* node_eval;        // evaluation pass: (err sum, err max, <Lam,mu> or rho, spread)
   int* ndone;                // number of instances that reached a final state
   int colour;                // class whose items / nodes these are
+  // finalise step carried by a node-kernel launch: its first n_fin blocks
+  // decide, per instance, the half-sweep of class fin_colour whose records the
+  // previous launch wrote (fin_nodes: that class's node items); 0: none
+  int n_fin, fin_colour;
+  const NodeItem* fin_nodes;
 };
 
 // Pair pass of the evaluation (transport, entropy, mass of each plan).

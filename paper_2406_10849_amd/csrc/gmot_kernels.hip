@@ -293,6 +293,72 @@ constexpr double kShiftHi = 96.0;
 constexpr double kShiftLo = -96.0;
 constexpr int kNodeDegLDS = 16;  // merged messages of the first 16 edges stay in LDS
 
+// The finalise step of one instance (one block of NW waves, one wave per node
+// of the class, nodes w, w + NW, ...): per-edge terms summed over the node's
+// tile records (lanes over tiles), every free node's normaliser c_j = LSE over
+// its tile records of abar, then the terms summed in a fixed order and the stop
+// decision by thread 0.  `colour` is the class whose records are complete; the
+// step does nothing unless the instance's next undecided half-sweep is of that
+// class.  It then publishes the view read by later node launches: run separately
+// after a node launch (fused = false) for the next two launches; carried by the
+// next node launch (fused = true), only for the launch after it, since that
+// launch's own node blocks are reading the other view.
+template <int NW>
+__device__ void fin_instance(const Tables& tb, const NodeItem* __restrict__ nodes, int colour, InstState* st,
+                             bool fused, double (*sh)[2]) {
+  const int other = 1 - colour;
+  if (st->done) {
+    if (threadIdx.x == 0) {
+      st->vdone[colour] = 1;
+      if (!fused) st->vdone[other] = 1;
+    }
+    return;
+  }
+  const long long t = st->t;
+  if (((t & 1) == 1) != (colour == 0)) return;
+  const int nxt = (int)((((t - 1) >> 1) + 1) % kSlots);
+  const int i0 = st->node0[colour], cnt = st->nnodes[colour];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  double esum = 0.0, emax = 0.0;
+  for (int i = wv; i < cnt; i += NW) {
+    const NodeItem nd = nodes[i0 + i];
+    const int deg = nd.deg, stride = deg + kRecExtra, tiles = nd.tiles;
+    const double* __restrict__ tp = nd.tpart;
+    for (int k = 0; k < deg; ++k) {
+      double e = 0.0;
+      for (int tt = lane; tt < tiles; tt += 64) e += tp[(size_t)tt * stride + k];
+      e = wave_sum(e);
+      esum += e;
+      emax = fmax(emax, e);
+    }
+    if (!nd.fixed) {
+      const int t0 = min(lane, tiles - 1);
+      const double c = tile_lse(tp, tiles, stride, deg, tp[(size_t)t0 * stride + deg], tp[(size_t)t0 * stride + deg + 1]);
+      if (lane == 0) nd.c[nxt] = c;
+    }
+  }
+  if (lane == 0) {
+    sh[wv][0] = esum;
+    sh[wv][1] = emax;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double E = 0.0, Em = 0.0;
+    for (int w = 0; w < NW; ++w) {
+      E += sh[w][0];
+      Em = fmax(Em, sh[w][1]);
+    }
+    decide(tb, st, t, E, Em);
+    const int stop = st->done != kRunning;
+    st->vt[colour] = t + 2;
+    st->vdone[colour] = stop;
+    if (!fused) {
+      st->vt[other] = t + 1;
+      st->vdone[other] = stop;
+    }
+  }
+}
+
 // Orders a wave's LDS writes before its later LDS reads (wave-private buffers).
 __device__ inline void wave_sync() {
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
@@ -321,11 +387,17 @@ __global__ __launch_bounds__(64 * W) void k_node(Tables tb) {
   __shared__ double s_x2[TR];
   __shared__ double s_csrc[kNodeDegLDS];  // c_k of each edge's source node
 
-  const TileItem ti = tb.tiles[blockIdx.x];
+  if ((int)blockIdx.x < tb.n_fin) {
+    // the finalise step of the previous launch's half-sweep, one block per instance
+    __shared__ double sh_fin[W][2];
+    fin_instance<W>(tb, tb.fin_nodes, tb.fin_colour, tb.inst + blockIdx.x, true, sh_fin);
+    return;
+  }
+  const TileItem ti = tb.tiles[blockIdx.x - tb.n_fin];
   const InstState* st = tb.inst + ti.inst;
   const NodeItem nd = tb.nodes[ti.node];
-  const long long t = st->t;
-  if (st->done || ((t & 1) == 1) != (tb.colour == 0)) return;
+  const long long t = st->vt[tb.colour];
+  if (st->vdone[tb.colour] || t < st->t_first || ((t & 1) == 1) != (tb.colour == 0)) return;
   // slots: this class's held state before t, its update, the other class's held state
   const int cur = (int)(((t - 1) >> 1) % kSlots), nxt = (cur + 1) % kSlots;
   const int src_slot = (int)((t >> 1) % kSlots);
@@ -907,43 +979,7 @@ __global__ __launch_bounds__(64 * W) void k_node(Tables tb) {
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(64 * kFinWaves) void k_finalize(Tables tb) {
   __shared__ double sh[kFinWaves][2];
-  InstState* st = tb.inst + blockIdx.x;
-  const long long t = st->t;
-  if (st->done || ((t & 1) == 1) != (tb.colour == 0)) return;
-  const int nxt = (int)((((t - 1) >> 1) + 1) % kSlots);
-  const int i0 = st->node0[tb.colour], cnt = st->nnodes[tb.colour];
-  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  double esum = 0.0, emax = 0.0;
-  for (int i = wv; i < cnt; i += kFinWaves) {
-    const NodeItem nd = tb.nodes[i0 + i];
-    const int deg = nd.deg, stride = deg + kRecExtra, tiles = nd.tiles;
-    const double* __restrict__ tp = nd.tpart;
-    for (int k = 0; k < deg; ++k) {
-      double e = 0.0;
-      for (int tt = lane; tt < tiles; tt += 64) e += tp[(size_t)tt * stride + k];
-      e = wave_sum(e);
-      esum += e;
-      emax = fmax(emax, e);
-    }
-    if (!nd.fixed) {
-      const int t0 = min(lane, tiles - 1);
-      const double c = tile_lse(tp, tiles, stride, deg, tp[(size_t)t0 * stride + deg], tp[(size_t)t0 * stride + deg + 1]);
-      if (lane == 0) nd.c[nxt] = c;
-    }
-  }
-  if (lane == 0) {
-    sh[wv][0] = esum;
-    sh[wv][1] = emax;
-  }
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    double E = 0.0, Em = 0.0;
-    for (int w = 0; w < kFinWaves; ++w) {
-      E += sh[w][0];
-      Em = fmax(Em, sh[w][1]);
-    }
-    decide(tb, st, t, E, Em);
-  }
+  fin_instance<kFinWaves>(tb, tb.nodes, tb.colour, tb.inst + blockIdx.x, false, sh);
 }
 
 // ---------------------------------------------------------------------------
@@ -1132,7 +1168,7 @@ hipError_t launch_msg(const Tables& tb, int n_items, int dim, int rows_per_lane,
 
 template <int DIM, int W, int R, int H, bool F64, bool EXPL>
 static hipError_t launch_node_t(const Tables& tb, int n_tiles, hipStream_t s) {
-  hipLaunchKernelGGL((k_node<DIM, W, R, H, F64, EXPL>), dim3(n_tiles), dim3(64 * W), 0, s, tb);
+  hipLaunchKernelGGL((k_node<DIM, W, R, H, F64, EXPL>), dim3(n_tiles + tb.n_fin), dim3(64 * W), 0, s, tb);
   return hipGetLastError();
 }
 

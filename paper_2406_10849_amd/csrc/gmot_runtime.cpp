@@ -106,7 +106,7 @@ constexpr int kMsgBurst = 4;
 // of kStepEvents * k events (see Plan::launch_tstep), so one chain can be read
 // back while the next replay runs.
 struct GraphEntry {
-  bool fp64 = false, timed = false, per_node = false;
+  bool fp64 = false, timed = false, per_node = false, fused = false;
   int start = 0, k = 0;
   hipGraphExec_t exec[2] = {nullptr, nullptr};
   std::vector<hipEvent_t> ev[2];
@@ -170,12 +170,22 @@ struct Plan {
 
   // The node stage of class c: one launch per support-dimension group, or
   // with per_node one launch per node (the same tiles, issued node by node).
-  hipError_t launch_node_stage(int c, bool fp64, hipStream_t s, bool per_node) const {
+  // With fused, the first launch also carries the finalise step of the other
+  // class's half-sweep (the previous launch's), one block per instance.
+  hipError_t launch_node_stage(int c, bool fp64, hipStream_t s, bool per_node, bool fused = false) const {
     hipError_t e;
+    bool fin_pending = fused;
     for (int dk = 0; dk < 4; ++dk) {
       if (tiles[c][dk].empty()) continue;
       if (!per_node) {
-        e = launch_node(tables(c, dk), (int)tiles[c][dk].size(), dk, W, NR, NH, fp64, s);
+        Tables tb = tables(c, dk);
+        if (fin_pending) {
+          tb.n_fin = (int)inst.size();
+          tb.fin_colour = 1 - c;
+          tb.fin_nodes = d_nodes[1 - c];
+          fin_pending = false;
+        }
+        e = launch_node(tb, (int)tiles[c][dk].size(), dk, W, NR, NH, fp64, s);
         if (e != hipSuccess) return e;
         continue;
       }
@@ -195,9 +205,12 @@ struct Plan {
   // of the node stage reads the same state and rewrites the same slots (only
   // its shifts differ), so the burst's mean is the node stage's duration
   // without the event overhead.
+  // Fused (no events, layer schedule): the node stage alone, its first launch
+  // finalising the previous half-sweep.
   hipError_t launch_tstep(int c, bool fp64, hipStream_t s, const hipEvent_t* ev = nullptr,
-                          bool per_node = false) const {
+                          bool per_node = false, bool fused = false) const {
     hipError_t e;
+    if (fused) return launch_node_stage(c, fp64, s, false, true);
     if (ev) {
       if ((e = hipEventRecord(ev[0], s)) != hipSuccess) return e;
       for (int r = 0; r < kMsgBurst; ++r)
@@ -489,13 +502,13 @@ static NodeShape choose_shape(gmot_ctx* ctx, const std::vector<gmot_problem*>& p
   return sh;
 }
 
-static int capture_one(Plan* pl, bool fp64, bool per_node, int start, int k, const std::vector<hipEvent_t>* ev,
-                       hipGraphExec_t* out) {
+static int capture_one(Plan* pl, bool fp64, bool per_node, bool fused, int start, int k,
+                       const std::vector<hipEvent_t>* ev, hipGraphExec_t* out) {
   hipStream_t s = pl->ctx->stream;
   HIPCHK(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
   hipError_t le = hipSuccess;
   for (int i = 0; i < k && le == hipSuccess; ++i)
-    le = pl->launch_tstep((start + i) & 1, fp64, s, ev ? ev->data() + kStepEvents * i : nullptr, per_node);
+    le = pl->launch_tstep((start + i) & 1, fp64, s, ev ? ev->data() + kStepEvents * i : nullptr, per_node, fused);
   hipGraph_t graph = nullptr;
   hipError_t ce = hipStreamEndCapture(s, &graph);
   if (le != hipSuccess) {
@@ -511,9 +524,11 @@ static int capture_one(Plan* pl, bool fp64, bool per_node, int start, int k, con
   return GMOT_OK;
 }
 
-static int get_graph(Plan* pl, bool fp64, bool per_node, int start, int k, bool timed, GraphEntry** out) {
+static int get_graph(Plan* pl, bool fp64, bool per_node, bool fused, int start, int k, bool timed,
+                     GraphEntry** out) {
   for (auto& g : pl->graphs)
-    if (g.fp64 == fp64 && g.per_node == per_node && g.start == start && g.k == k && g.timed == timed) {
+    if (g.fp64 == fp64 && g.per_node == per_node && g.fused == fused && g.start == start && g.k == k &&
+        g.timed == timed) {
       *out = &g;
       return GMOT_OK;
     }
@@ -523,6 +538,7 @@ static int get_graph(Plan* pl, bool fp64, bool per_node, int start, int k, bool 
   g.k = k;
   g.timed = timed;
   g.per_node = per_node;
+  g.fused = fused;
   if (timed) {
     // HIP events recorded by graph nodes cannot be timed, so the timed variant
     // launches directly on the stream with two alternating event chains.
@@ -531,7 +547,7 @@ static int get_graph(Plan* pl, bool fp64, bool per_node, int start, int k, bool 
       for (auto& e : g.ev[c]) HIPCHK(hipEventCreate(&e));
     }
   } else {
-    int rc = capture_one(pl, fp64, per_node, start, k, nullptr, &g.exec[0]);
+    int rc = capture_one(pl, fp64, per_node, fused, start, k, nullptr, &g.exec[0]);
     if (rc) return rc;
   }
   pl->graphs.push_back(std::move(g));
@@ -549,10 +565,12 @@ static int run_plan(Plan* pl, const gmot_opts* o, gmot_result* outs, const std::
   hipStream_t s = pl->ctx->stream;
   const size_t n = pl->probs.size();
   int parity = -1;
+  bool mixed = false;
   int already = 0;
   for (size_t i = 0; i < n; ++i) {
     gmot_problem* p = pl->probs[i];
     InstState& st = pl->inst[i];
+    st.vdone[0] = st.vdone[1] = 1;
     if (active && !(*active)[i]) {
       st.t = p->t;
       st.done = kMaxSteps;
@@ -588,6 +606,23 @@ static int run_plan(Plan* pl, const gmot_opts* o, gmot_result* outs, const std::
     const int par = (int)(p->t & 1);
     // instances at the other parity sit out one launch and then run in step
     if (parity < 0) parity = par;
+    if (par != parity) mixed = true;
+  }
+  // The finalise step rides in the next half-sweep's node launch unless the
+  // half-sweeps are timed, issued node by node, or instances start at both
+  // parities.  The fused node blocks of half-sweep t + 1 then run before t is
+  // decided; they write only slots that no state the decision keeps uses.
+  const bool fused = o->timing == 0 && o->schedule != GMOT_SCHED_PER_NODE && !mixed;
+  for (size_t i = 0; i < n; ++i) {
+    InstState& st = pl->inst[i];
+    if (st.done != kRunning) continue;
+    const int c0 = (st.t & 1) ? 0 : 1;  // odd half-sweeps update class 0
+    st.vt[c0] = st.t;
+    st.vdone[c0] = 0;
+    // the other class's first half-sweep: known in advance when fused, else
+    // published by the finalise step of this one
+    st.vt[1 - c0] = fused ? st.t + 1 : 0;
+    st.vdone[1 - c0] = 0;
   }
   HIPCHK(hipMemcpyAsync(pl->d_inst, pl->inst.data(), sizeof(InstState) * n, hipMemcpyHostToDevice, s));
   HIPCHK(hipMemcpyAsync(pl->d_ndone, &already, sizeof(int), hipMemcpyHostToDevice, s));
@@ -603,15 +638,16 @@ static int run_plan(Plan* pl, const gmot_opts* o, gmot_result* outs, const std::
     const bool no_graph = std::getenv("GMOT_NO_GRAPH") != nullptr && !timed;
     GraphEntry* g = nullptr;
     if (!no_graph) {
-      int rc = get_graph(pl, fp64, per_node, start, k, timed, &g);
+      int rc = get_graph(pl, fp64, per_node, fused, start, k, timed, &g);
       if (rc) return rc;
     }
     HIPCHK(launch_stamp(pl->d_inst, (int)n, s));
     std::vector<int64_t> t_start(n);
     for (size_t i = 0; i < n; ++i) t_start[i] = pl->inst[i].t;
     // every replay advances each running instance by k half-sweeps (one fewer
-    // for an instance that starts at the other parity), so this bound is exact
-    const int64_t max_launches = ceil_div(o->max_steps + 1, k) + 1;
+    // for an instance that starts at the other parity), so this bound is exact;
+    // fused, the last half-sweep is decided one launch later
+    const int64_t max_launches = ceil_div(o->max_steps + 1, k) + 2;
     hipEvent_t ev[2];
     HIPCHK(hipEventCreateWithFlags(&ev[0], hipEventDisableTiming));
     HIPCHK(hipEventCreateWithFlags(&ev[1], hipEventDisableTiming));
@@ -626,7 +662,8 @@ static int run_plan(Plan* pl, const gmot_opts* o, gmot_result* outs, const std::
           e = pl->launch_tstep((start + i) & 1, fp64, s, g->ev[slot].data() + kStepEvents * i, per_node);
       } else if (no_graph) {
         e = hipSuccess;
-        for (int i = 0; i < k && e == hipSuccess; ++i) e = pl->launch_tstep((start + i) & 1, fp64, s, nullptr, per_node);
+        for (int i = 0; i < k && e == hipSuccess; ++i)
+          e = pl->launch_tstep((start + i) & 1, fp64, s, nullptr, per_node, fused);
       } else {
         e = hipGraphLaunch(g->exec[0], s);
       }
