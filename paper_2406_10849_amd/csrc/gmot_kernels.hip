@@ -303,9 +303,15 @@ constexpr int kNodeDegLDS = 16;  // merged messages of the first 16 edges stay i
 // after a node launch (fused = false) for the next two launches; carried by the
 // next node launch (fused = true), only for the launch after it, since that
 // launch's own node blocks are reading the other view.
+// The stopping sum is accumulated in kFinParts partial sums (node i into part
+// i mod kFinParts) added in part order, so it does not depend on NW.
+constexpr int kFinParts = 16;
+
 template <int NW>
 __device__ void fin_instance(const Tables& tb, const NodeItem* __restrict__ nodes, int colour, InstState* st,
                              bool fused, double (*sh)[2]) {
+  static_assert(kFinParts % NW == 0, "each wave takes whole parts");
+  constexpr int Q = kFinParts / NW;  // parts per wave: wv, wv + NW, ...
   const int other = 1 - colour;
   if (st->done) {
     if (threadIdx.x == 0) {
@@ -319,16 +325,21 @@ __device__ void fin_instance(const Tables& tb, const NodeItem* __restrict__ node
   const int nxt = (int)((((t - 1) >> 1) + 1) % kSlots);
   const int i0 = st->node0[colour], cnt = st->nnodes[colour];
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  double esum = 0.0, emax = 0.0;
+  double esum[Q], emax = 0.0;
+#pragma unroll
+  for (int q = 0; q < Q; ++q) esum[q] = 0.0;
   for (int i = wv; i < cnt; i += NW) {
     const NodeItem nd = nodes[i0 + i];
+    const int q = (i / NW) % Q;  // node i is in part i mod kFinParts = wv + q * NW
     const int deg = nd.deg, stride = deg + kRecExtra, tiles = nd.tiles;
     const double* __restrict__ tp = nd.tpart;
     for (int k = 0; k < deg; ++k) {
       double e = 0.0;
       for (int tt = lane; tt < tiles; tt += 64) e += tp[(size_t)tt * stride + k];
       e = wave_sum(e);
-      esum += e;
+#pragma unroll
+      for (int qq = 0; qq < Q; ++qq)
+        if (qq == q) esum[qq] += e;
       emax = fmax(emax, e);
     }
     if (!nd.fixed) {
@@ -338,13 +349,16 @@ __device__ void fin_instance(const Tables& tb, const NodeItem* __restrict__ node
     }
   }
   if (lane == 0) {
-    sh[wv][0] = esum;
-    sh[wv][1] = emax;
+#pragma unroll
+    for (int q = 0; q < Q; ++q) {
+      sh[wv + q * NW][0] = esum[q];
+      sh[wv + q * NW][1] = emax;
+    }
   }
   __syncthreads();
   if (threadIdx.x == 0) {
     double E = 0.0, Em = 0.0;
-    for (int w = 0; w < NW; ++w) {
+    for (int w = 0; w < kFinParts; ++w) {
       E += sh[w][0];
       Em = fmax(Em, sh[w][1]);
     }
@@ -389,7 +403,7 @@ __global__ __launch_bounds__(64 * W) void k_node(Tables tb) {
 
   if ((int)blockIdx.x < tb.n_fin) {
     // the finalise step of the previous launch's half-sweep, one block per instance
-    __shared__ double sh_fin[W][2];
+    __shared__ double sh_fin[kFinParts][2];
     fin_instance<W>(tb, tb.fin_nodes, tb.fin_colour, tb.inst + blockIdx.x, true, sh_fin);
     return;
   }
@@ -978,7 +992,7 @@ __global__ __launch_bounds__(64 * W) void k_node(Tables tb) {
 // fixed order and thread 0 takes the stop decision.
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(64 * kFinWaves) void k_finalize(Tables tb) {
-  __shared__ double sh[kFinWaves][2];
+  __shared__ double sh[kFinParts][2];
   fin_instance<kFinWaves>(tb, tb.nodes, tb.colour, tb.inst + blockIdx.x, false, sh);
 }
 

@@ -427,3 +427,20 @@ def test_one_pass_far_from_stored_shifts(ctx, offset):
         assert abs(g.evaluate()["dual"] - eo["dual"]) <= 1e-6 * eo["scale"]
         for e in range(p.n_edges):
             assert np.max(np.abs(g.coupling(e) - o2.coupling(e))) <= 1e-6
+
+
+def test_fused_finalise_stops_where_separate_one_does(ctx):
+    """The finalise step carried by the next half-sweep's launch (layer
+    schedule) and the separate finalise kernel (per-node schedule, the same
+    arithmetic) stop at the same half-sweep with the same potentials and
+    stopping sum: the speculative half-sweep after the decision leaves the kept
+    state untouched.  Also for a fixed step budget."""
+    p = make_chain(n_nodes=10, n=150, eps=5e-3)
+    for kw in ({"tol": 1e-6, "max_steps": 100000}, {"tol": 0.0, "max_steps": 37}):
+        g1, g2 = gpu_problem(ctx, p), gpu_problem(ctx, p)
+        r1 = g1.solve(**kw)
+        r2 = g2.solve(schedule="per_node", **kw)
+        assert r1["status"] == r2["status"]
+        assert r1["steps"] == r2["steps"] and r1["t"] == r2["t"]
+        assert r1["err_sum"] == r2["err_sum"]
+        assert np.array_equal(g1.potentials(), g2.potentials())
