@@ -32,8 +32,19 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 METRIC = "edge-iterations/s and time-to-1e-6 marginal error; plain vs batched+warm-start"
-# VALU issue capacity of MI355X: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz.
-VALU_SLOTS_PER_S = 256 * 64 * 2.4e9
+# MI355X vector issue: 256 CUs x 4 SIMDs at 2.4 GHz; per SIMD and clock 16 FP64
+# lanes (78.6 TFLOP/s FP64 FMA), 32 FP32 lanes (157.3 TFLOP/s) and a quarter of
+# that for transcendentals, i.e. SIMD cycles per 64-lane instruction:
+SIMD_CLOCKS_PER_S = 256 * 4 * 2.4e9
+CYC_FP64, CYC_FP32, CYC_TRANS = 4.0, 2.0, 8.0
+
+
+def pair_peak_gpairs(dim: int) -> float:
+    """ALU peak of the FP32-core message sums (Gpair/s): per pair the least work
+    the precision contract allows, dim FP64 FMAs forming the exponent (shift
+    folded in), one FP64-to-FP32 conversion, one exp2, one FP32 add."""
+    cycles_per_64_pairs = dim * CYC_FP64 + CYC_FP64 + CYC_TRANS + CYC_FP32
+    return SIMD_CLOCKS_PER_S * 64 / cycles_per_64_pairs / 1e9
 # MI355X HBM3E peak, GB/s
 HBM_PEAK_GBS = 8000.0
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_node_chain32_traffic.txt")
@@ -62,21 +73,22 @@ def kernel_sha() -> str:
 
 def measured_traffic(shape):
     """HBM bytes per node-kernel launch from the committed rocprofv3 PMC
-    summary, valid only for the kernel source and node shape (waves per
-    block, rows per lane, lane groups) it was taken on."""
+    summary, valid only for the kernel source it was taken on and for the node
+    shape (waves per block, rows per lane, lane groups) the bench tuned."""
     if not os.path.exists(TRAFFIC_FILE):
         return None
-    vals = {}
+    sha, want = None, "shape %d,%d,%d:" % shape
     for line in open(TRAFFIC_FILE):
-        if ":" in line:
-            k, v = line.split(":", 1)
-            vals[k.strip()] = v.strip()
-    if vals.get("kernel_sha256_16") != kernel_sha() or vals.get("shape") != "%d,%d,%d" % shape:
-        return None
-    try:
-        return float(vals["fetch_bytes_per_launch"]) + float(vals["write_bytes_per_launch"])
-    except (KeyError, ValueError):
-        return None
+        if line.startswith("kernel_sha256_16:"):
+            sha = line.split(":", 1)[1].strip()
+        elif line.startswith(want) and sha == kernel_sha():
+            f = line[len(want):].split()
+            try:
+                kv = dict(zip(f[0::2], (float(v) for v in f[1::2])))
+                return kv["fetch_bytes_per_launch"] + kv["write_bytes_per_launch"]
+            except (KeyError, ValueError):
+                return None
+    return None
 
 
 def cpu_baseline(prob, seconds: float) -> dict:
@@ -302,7 +314,7 @@ def main() -> int:
     log(f"stats: {st}")
 
     D = prob.dim
-    peak = VALU_SLOTS_PER_S / (D + 2) / 1e9
+    peak = pair_peak_gpairs(D)
     avg_ms = st["msg_ms"] / max(st["msg_launches"], 1)
     pairs_per_launch = st["msg_pairs"] / max(st["msg_launches"], 1)
     achieved = pairs_per_launch / (avg_ms / 1e3) / 1e9 if avg_ms > 0 else 0.0

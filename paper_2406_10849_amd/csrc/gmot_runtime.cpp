@@ -1047,6 +1047,8 @@ static int time_plan(Plan* pl, double* ms) {
   return GMOT_OK;
 }
 
+constexpr double kAutotuneMargin = 0.97;
+
 static int autotune(gmot_ctx* ctx, const std::vector<gmot_problem*>& probs, Plan** plan_io, int32_t* W_out,
                     int32_t* R_out, int32_t* H_out, double* ms_out) {
   static const NodeShape kCand[] = {{2, 1, 1},  {4, 1, 1}, {8, 1, 1}, {16, 1, 1}, {2, 2, 1}, {4, 2, 1},
@@ -1078,7 +1080,9 @@ static int autotune(gmot_ctx* ctx, const std::vector<gmot_problem*>& probs, Plan
       delete best;
       return rc;
     }
-    if (ms < best_ms) {
+    // a later candidate must be 3% faster to replace an earlier one, so
+    // near-equal shapes do not flip from run to run
+    if (ms < best_ms * kAutotuneMargin) {
       delete best;
       best = pl;
       best_ms = ms;
