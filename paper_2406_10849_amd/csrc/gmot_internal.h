@@ -64,6 +64,8 @@ struct MsgDesc {
                              // each wave's column range at the last computation (next shift)
   double* mfull;             // merged message m_{k->j}, [n_dst], natural log
   const float* cost;         // explicit cost stored src-major: cost[y * n_dst + x] = C_(j,k)(x, y)
+  const float* cost_tile;    // the same, tile-major for the node kernel: C_(j,k)(x, y) at
+                             // ((x / 64) * n_src + y) * 64 + x % 64, rows padded to 64
   const double* src_tpart;   // tile records of the source node k (its c_k comes from them)
   int32_t n_dst, n_src, ns, inst;
   int32_t dim, cost_kind, src_tiles, src_deg;  // source node's tile count and degree

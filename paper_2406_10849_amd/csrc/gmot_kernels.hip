@@ -491,7 +491,7 @@ __global__ __launch_bounds__(64 * W) void k_node(Tables tb) {
     const GDbl* __restrict__ lam = (const GDbl*)md.lam_src[src_slot];
     const GDbl* __restrict__ lg = (const GDbl*)md.lg_src;
     const GDbl* __restrict__ ys = (const GDbl*)md.supp_src;
-    const GFlt* __restrict__ cost = (const GFlt*)md.cost;
+    const GFlt* __restrict__ cost = (const GFlt*)md.cost_tile;
     GDblW* __restrict__ wmax = (GDblW*)md.wmax;
 
     // A chunk's column data is fetched into registers (lane = column of its
@@ -555,15 +555,31 @@ __global__ __launch_bounds__(64 * W) void k_node(Tables tb) {
       stage_fetched();
     };
     const double* __restrict__ sth = stage + half * CHH * STR;  // this lane group's columns
-    float cv[EXPL ? R : 1][EXPL ? CH : 1];
-    auto load_cost = [&](int c0, int cn) {
+    // explicit costs (tile-major: a wave's chunk is one contiguous 8 KB run):
+    // cv holds the chunk being summed, cq the next one's, loaded a chunk ahead
+    // (columns clamped into the matrix, past the range they meet a = -inf;
+    // rows past n read the zero padding and are never used)
+    float cv[EXPL ? R : 1][EXPL ? CH : 1], cq[EXPL ? R : 1][EXPL ? CH : 1];
+    auto fetch_cost = [&](int c0) {
       if (EXPL) {
 #pragma unroll
         for (int r = 0; r < R; ++r)
 #pragma unroll
           for (int c = 0; c < CH; ++c)
-            cv[r][c] = (vx[r] && c < cn) ? cost[(size_t)(c0 + c) * n + x[r]] : 0.0f;
+            cq[r][c] = cost[((size_t)(x[r] >> 6) * n_src + min(c0 + c, n_src - 1)) * 64 + (x[r] & 63)];
       }
+    };
+    auto take_cost = [&]() {
+      if (EXPL) {
+#pragma unroll
+        for (int r = 0; r < R; ++r)
+#pragma unroll
+          for (int c = 0; c < CH; ++c) cv[r][c] = cq[r][c];
+      }
+    };
+    auto load_cost = [&](int c0, int) {
+      fetch_cost(c0);
+      take_cost();
     };
     auto wcol = [&](int r, int c, double a) -> double {
       double w = a;
@@ -688,13 +704,14 @@ __global__ __launch_bounds__(64 * W) void k_node(Tables tb) {
 #pragma unroll
       for (int r = 0; r < R; ++r) dl[r] = rowmode ? (pmok[r] ? pmv[r] : 0.0) - sb[r] : 0.0;
 
+      fetch_cost(c_lo);
       for (int j0 = 0; j0 < span; j0 += CHH) {
         const int c0 = c_lo + j0;
-        const int cn = min(CHH, c_hi - c0);
-        load_cost(c0, cn);
+        take_cost();
         stage_fetched();
         advance();
         fetch_into(c0 + 2 * CHH, min(CHH, c_hi - c0 - 2 * CHH), g_raw);  // past the range: masked
+        fetch_cost(c0 + CHH);
         // one pass: sums of 2^(d) with d the staged exponent minus dl, FP32
         // maxima of d alongside
         float Mf[R];

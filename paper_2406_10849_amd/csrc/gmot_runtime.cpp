@@ -80,6 +80,8 @@ struct gmot_problem {
   double* d_qbar = nullptr;
   double* d_c = nullptr;  // [kSlots N]: node normaliser c_j, slot s at kSlots j + s (0 for constrained nodes)
   float* d_cost = nullptr;
+  float* d_cost_tile = nullptr;           // per directed edge, tile-major (node kernel)
+  std::vector<int64_t> tcost_off;         // [2E + 1] offsets into d_cost_tile
   int64_t t = 1;
   uint64_t version = 0;   // bumped whenever the held state changes
   Plan* plan = nullptr;
@@ -302,6 +304,7 @@ static int build_plan(gmot_ctx* ctx, const std::vector<gmot_problem*>& probs, No
             // stored src-major: dst = b uses C_e (rows a = src), dst = a uses C_e^T
             const bool dst_is_b = (de_dst & 1) == 1;
             md.cost = dst_is_b ? p->d_cost + p->cost_off[e] : p->d_cost + p->total_cost + p->cost_off[e];
+            md.cost_tile = p->d_cost_tile + p->tcost_off[de_dst];
           }
           md.n_dst = p->sizes[j];
           md.n_src = p->sizes[k];
@@ -890,6 +893,15 @@ static int validate_and_copy(const gmot_tree_desc* d, gmot_problem* p, int first
     p->cost_off[e + 1] = p->cost_off[e] + (int64_t)p->sizes[a] * p->sizes[b];
   }
   p->total_cost = p->cost_kind == GMOT_COST_EXPLICIT ? p->cost_off[E] : 0;
+  // tile-major copies per directed edge de = (j, k): ceil(n_j / 64) * 64 rows x n_k
+  p->tcost_off.assign(2 * E + 1, 0);
+  for (int de = 0; de < 2 * E; ++de) {
+    const int e = de >> 1;
+    const int j = (de & 1) ? p->edges[2 * e + 1] : p->edges[2 * e];
+    const int k = (de & 1) ? p->edges[2 * e] : p->edges[2 * e + 1];
+    const int64_t rows = p->cost_kind == GMOT_COST_EXPLICIT ? ceil_div(p->sizes[j], 64) * 64 : 0;
+    p->tcost_off[de + 1] = p->tcost_off[de] + rows * p->sizes[k];
+  }
   // marginals
   int64_t nfixed = 0;
   for (int j = 0; j < N; ++j)
@@ -979,6 +991,21 @@ static int upload(const gmot_tree_desc* d, gmot_problem* p) {
         for (int y = 0; y < nb; ++y) tr[(size_t)y * na + x] = src[(size_t)x * nb + y];
       HIPCHK(hipMemcpy(p->d_cost + p->total_cost + p->cost_off[e], tr.data(), sizeof(float) * tr.size(),
                        hipMemcpyHostToDevice));
+    }
+    if (hipMalloc(&p->d_cost_tile, sizeof(float) * p->tcost_off[2 * p->E]) != hipSuccess)
+      return fail(GMOT_ENOMEM, "tile-major cost allocation failed");
+    for (int de = 0; de < 2 * p->E; ++de) {
+      const int e = de >> 1;
+      const int a = p->edges[2 * e], b = p->edges[2 * e + 1];
+      const int na = p->sizes[a], nb = p->sizes[b];
+      const bool dst_b = de & 1;
+      const int nd = dst_b ? nb : na, ns = dst_b ? na : nb;
+      tr.assign((size_t)(p->tcost_off[de + 1] - p->tcost_off[de]), 0.0f);
+      const float* src = d->cost + p->cost_off[e];  // C_e row-major: (a, b) at a * nb + b
+      for (int x = 0; x < nd; ++x)
+        for (int y = 0; y < ns; ++y)
+          tr[((size_t)(x >> 6) * ns + y) * 64 + (x & 63)] = dst_b ? src[(size_t)y * nb + x] : src[(size_t)x * nb + y];
+      HIPCHK(hipMemcpy(p->d_cost_tile + p->tcost_off[de], tr.data(), sizeof(float) * tr.size(), hipMemcpyHostToDevice));
     }
   }
   HIPCHK(hipStreamSynchronize(s));
@@ -1378,6 +1405,7 @@ int gmot_problem_create(gmot_ctx* ctx, const gmot_tree_desc* desc, int32_t first
   rc = upload(desc, p.get());
   if (rc) {
     if (p->arena) (void)hipFree(p->arena);
+    if (p->d_cost_tile) (void)hipFree(p->d_cost_tile);
     return rc;
   }
   *out = p.release();
@@ -1390,6 +1418,7 @@ void gmot_problem_destroy(gmot_problem* p) {
   delete p->plan;
   delete p->round;
   if (p->arena) (void)hipFree(p->arena);
+  if (p->d_cost_tile) (void)hipFree(p->d_cost_tile);
   delete p;
 }
 
