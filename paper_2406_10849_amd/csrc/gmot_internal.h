@@ -99,11 +99,13 @@ struct NodeItem {
   double* tpart;             // tile records
 };
 
-// One block of the node kernel: rows [row0, row0 + 64 R) of node item
-// `node` of instance `inst` (carried here so the instance state and the node
-// item load in parallel).
+// One block of the node kernel: rows [row0, row0 + 64 R / H) of node item
+// `node` of instance `inst`.  The node's first message, degree, size and
+// kind are repeated here so the instance state, the node item and the message
+// descriptors all load one step after the tile item.
 struct TileItem {
-  int32_t node, row0, inst, pad;
+  int32_t node, row0, inst, msg0;
+  int32_t deg, n, fixed, pad;
 };
 
 // Per-instance loop state, written only by the last node block of a half-sweep.

@@ -28,15 +28,38 @@ namespace gmot {
 namespace {
 
 
+// Wave reductions without the LDS crossbar: within each row of 16 lanes, DPP
+// moves pair lane i with i ^ 1, i ^ 2 (quad permutes), 7 - i within each half
+// row and 15 - i within the row, so every lane ends with its row's total (the
+// same bits in all 16 lanes: each step adds two equal-order partials); the four
+// row totals are then read with v_readlane and combined in a fixed order.
+template <int CTRL>
+__device__ inline double dpp_move(double v) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_update_dpp((int)(b & 0xffffffff), (int)(b & 0xffffffff), CTRL, 0xf, 0xf, false);
+  const int hi = __builtin_amdgcn_update_dpp((int)(b >> 32), (int)(b >> 32), CTRL, 0xf, 0xf, false);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+__device__ inline double lane_read(double v, int l) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffff), l);
+  const int hi = __builtin_amdgcn_readlane((int)(b >> 32), l);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+constexpr int kDppXor1 = 0xB1, kDppXor2 = 0x4E, kDppHalfMirror = 0x141, kDppMirror = 0x140;
 __device__ inline double wave_sum(double v) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-  return v;
+  v += dpp_move<kDppXor1>(v);
+  v += dpp_move<kDppXor2>(v);
+  v += dpp_move<kDppHalfMirror>(v);
+  v += dpp_move<kDppMirror>(v);
+  return ((lane_read(v, 0) + lane_read(v, 16)) + lane_read(v, 32)) + lane_read(v, 48);
 }
 __device__ inline double wave_max(double v) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
-  return v;
+  v = fmax(v, dpp_move<kDppXor1>(v));
+  v = fmax(v, dpp_move<kDppXor2>(v));
+  v = fmax(v, dpp_move<kDppHalfMirror>(v));
+  v = fmax(v, dpp_move<kDppMirror>(v));
+  return fmax(fmax(lane_read(v, 0), lane_read(v, 16)), fmax(lane_read(v, 32), lane_read(v, 48)));
 }
 
 // A free node's normaliser c_j = LSE over its tile records of the (max,
@@ -417,10 +440,10 @@ __global__ __launch_bounds__(64 * W) void k_node(Tables tb) {
   const int src_slot = (int)((t >> 1) % kSlots);
   const bool one = !F64 && t >= st->onepass_from;
   const bool rec_ok = t - 1 >= st->t_first;
-  const MsgDesc* __restrict__ mds = tb.msgs + nd.msg0;
-  const int n = nd.n, deg = nd.deg;
+  const MsgDesc* __restrict__ mds = tb.msgs + ti.msg0;
+  const int n = ti.n, deg = ti.deg;
   const bool lds = deg <= kNodeDegLDS;
-  const bool fixed = nd.fixed != 0;
+  const bool fixed = ti.fixed != 0;
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   // H lane groups of LPR lanes: lane (group h, index i) holds rows i, i + LPR, ...
   // of the tile and sums column range h of its wave's share of each edge
@@ -453,7 +476,7 @@ __global__ __launch_bounds__(64 * W) void k_node(Tables tb) {
     const int k = threadIdx.x / TR, xr = ti.row0 + (int)threadIdx.x - k * TR;
     if (xr < n) {
       l_item = mds[k].lam_dst[cur][xr];
-      if (nd.fixed) mu_item = nd.mu[xr];
+      if (fixed) mu_item = nd.mu[xr];
     }
   }
 

@@ -367,7 +367,9 @@ static int build_plan(gmot_ctx* ctx, const std::vector<gmot_problem*>& probs, No
                        [](const NodeTiles& u, const NodeTiles& v) { return u.work > v.work; });
       for (const NodeTiles& q : ntl[c][dk]) {
         pl->node_tiles[c][dk].push_back({(int)pl->tiles[c][dk].size(), q.n_tiles});
-        for (int r = 0; r < q.n_tiles; ++r) pl->tiles[c][dk].push_back({q.node_item, r * TRows, q.inst, 0});
+        const NodeItem& qn = pl->nodes[c][q.node_item];
+        for (int r = 0; r < q.n_tiles; ++r)
+          pl->tiles[c][dk].push_back({q.node_item, r * TRows, q.inst, qn.msg0, qn.deg, qn.n, qn.fixed, 0});
       }
     }
   int64_t wmax_total = 0;
