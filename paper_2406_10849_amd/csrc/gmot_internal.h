@@ -90,7 +90,7 @@ constexpr int kRecExtra = 2;    // tile record entries after the per-edge terms
 // tile's LSE max and scaled sum of abar) start at tpart + tile * (deg + kRecExtra).
 struct NodeItem {
   int32_t inst, node, n, deg;
-  int32_t fixed, msg0, err_idx, tiles;
+  int32_t fixed, msg0, err_idx, tiles;  // tiles: tile records, one per 64 rows
   const double* lg;          // log gamma_j, [n]
   const double* mu;          // mu_j for constrained nodes, else NULL
   double* abar;              // scratch [n]: mean_k m_{k->j}

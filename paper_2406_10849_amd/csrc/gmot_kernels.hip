@@ -420,7 +420,8 @@ __global__ __launch_bounds__(64 * W) void k_node(Tables tb) {
   __shared__ double s_col[W][CH * STR];
   __shared__ double2 s_part[NP][TR];  // (edge, range) partials; then per-(edge, row) terms
   __shared__ double s_m[kNodeDegLDS][TR];
-  __shared__ double s_q[kNodeDegLDS][TR];
+  __shared__ double s_l[kNodeDegLDS][TR];  // held L_(j,k)(x) of the update phase
+  __shared__ double s_mu[TR];
   __shared__ double s_x2[TR];
   __shared__ double s_csrc[kNodeDegLDS];  // c_k of each edge's source node
 
@@ -868,11 +869,23 @@ __global__ __launch_bounds__(64 * W) void k_node(Tables tb) {
   };
   if (lds) {
     for (int k = k_first; k < deg; k += k_step) edge_sums(k, std::true_type{});
+    // the held potentials and mu of every (edge, row) into LDS for the row
+    // owners below (the first item's were loaded at entry)
+    for (int it = threadIdx.x; it < deg * TR; it += NT) {
+      const int k = it / TR, lr = it - k * TR, xr = ti.row0 + lr;
+      double l = l_item, mu = mu_item;
+      if (it != (int)threadIdx.x && xr < n) {
+        l = mds[k].lam_dst[cur][xr];
+        if (fixed && k == 0) mu = nd.mu[xr];
+      }
+      s_l[k][lr] = l;
+      if (k == 0) s_mu[lr] = mu;
+    }
   } else {
     for (int k = k_first; k < deg; k += k_step) edge_sums(k, std::false_type{});
   }
   __syncthreads();
-  double* __restrict__ rec = nd.tpart + (size_t)(ti.row0 / TR) * (deg + kRecExtra);
+  constexpr int TQ = TR / 64;  // 64-row blocks of a tile, one record each
   const double c_old = nd.c ? nd.c[cur] : 0.0;
 
   if (lds) {
@@ -898,69 +911,48 @@ __global__ __launch_bounds__(64 * W) void k_node(Tables tb) {
       s_m[k][lr] = (Mx > -INFINITY && St > 0.0) ? kLn2 * (Mx + log2(St)) - s_x2[lr] / eps - s_csrc[k] : -INFINITY;
     }
     __syncthreads();
-    // per (edge, row): q (free) or the term and update (constrained)
-    for (int it = threadIdx.x; it < deg * TR; it += NT) {
-      const int k = it / TR, lr = it - k * TR;
-      const int xr = ti.row0 + lr;
-      double term = 0.0;
-      if (xr < n) {
+    // Row owners: wave q takes rows q * 64 + lane of the tile and, for each
+    // row, every edge in order (terms of the state before the update, the
+    // update), then sums its 64 rows into the row block's record: per edge the
+    // terms, then (max, scaled sum) of abar.  No block barrier after the merge.
+    if (wv >= TQ || ti.row0 + wv * 64 >= n) return;
+    const int lr = wv * 64 + lane, xr = ti.row0 + lr;
+    const bool vr = xr < n;
+    double* __restrict__ rec = nd.tpart + (size_t)(ti.row0 / 64 + wv) * (deg + kRecExtra);
+    if (fixed) {
+      const double mu = s_mu[lr];
+      for (int k = 0; k < deg; ++k) {
         const double m = s_m[k][lr];
-        const bool first = it == (int)threadIdx.x;
-        const double l = first ? l_item : mds[k].lam_dst[cur][xr];
-        if (fixed) {
-          const double mu = first ? mu_item : nd.mu[xr];
-          if (mu > 0.0) term = mu * fabs(expm1(l + m));
-          mds[k].lam_dst[nxt][xr] = -m;
-        } else {
-          s_q[k][lr] = exp(l - c_old + m);
-        }
-      }
-      if (fixed) s_part[k][lr].x = term;
-    }
-    __syncthreads();
-    if (!fixed) {
-      // free node: abar and qbar per row, then the terms and the update
-      for (int it = threadIdx.x; it < deg * TR; it += NT) {
-        const int k = it / TR, lr = it - k * TR;
-        const int xr = ti.row0 + lr;
         double term = 0.0;
-        if (xr < n) {
-          double as = 0.0, qs = 0.0;
-          for (int kk = 0; kk < deg; ++kk) {
-            as += s_m[kk][lr];
-            qs += s_q[kk][lr];
-          }
-          term = fabs(s_q[k][lr] - qs / deg);
-          mds[k].lam_dst[nxt][xr] = as / deg - s_m[k][lr];
+        if (vr) {
+          if (mu > 0.0) term = mu * fabs(expm1(s_l[k][lr] + m));
+          mds[k].lam_dst[nxt][xr] = -m;
         }
-        s_part[k][lr].x = term;
+        term = wave_sum(term);
+        if (lane == 0) rec[k] = term;
       }
-      __syncthreads();
-    }
-    // tile record: per-edge term sums (edge k on wave k mod W), then abar's LSE
-    constexpr int TQ = TR / 64;  // tile rows per lane of one wave
-    for (int k = wv; k < deg; k += W) {
-      double part = 0.0;
-#pragma unroll
-      for (int q = 0; q < TQ; ++q) part += s_part[k][q * 64 + lane].x;
-      part = wave_sum(part);
-      if (lane == 0) rec[k] = part;
-    }
-    if (!fixed && wv == W - 1) {
-      double av[TQ], am = -INFINITY;
-#pragma unroll
-      for (int q = 0; q < TQ; ++q) {
-        const int lr = q * 64 + lane;
-        double as = 0.0;
-        for (int kk = 0; kk < deg; ++kk) as += s_m[kk][lr];
-        av[q] = ti.row0 + lr < n ? as / deg : -INFINITY;
-        am = fmax(am, av[q]);
+    } else {
+      double as = 0.0, qs = 0.0;
+      for (int k = 0; k < deg; ++k) {
+        const double m = s_m[k][lr];
+        const double q = vr ? exp(s_l[k][lr] - c_old + m) : 0.0;
+        s_part[k][lr].y = q;  // this lane's own scratch from here on
+        as += m;
+        qs += q;
       }
-      const double Mw = wave_max(am);
-      double sv = 0.0;
-#pragma unroll
-      for (int q = 0; q < TQ; ++q) sv += (av[q] > -INFINITY) ? exp(av[q] - Mw) : 0.0;
-      const double Sw = wave_sum(sv);
+      const double ab = as / deg, qb = qs / deg;
+      for (int k = 0; k < deg; ++k) {
+        double term = 0.0;
+        if (vr) {
+          term = fabs(s_part[k][lr].y - qb);
+          mds[k].lam_dst[nxt][xr] = ab - s_m[k][lr];
+        }
+        term = wave_sum(term);
+        if (lane == 0) rec[k] = term;
+      }
+      const double av = vr ? ab : -INFINITY;
+      const double Mw = wave_max(av);
+      const double Sw = wave_sum(av > -INFINITY ? exp(av - Mw) : 0.0);
       if (lane == 0) {
         rec[deg] = Mw;
         rec[deg + 1] = Sw;
@@ -989,37 +981,45 @@ __global__ __launch_bounds__(64 * W) void k_node(Tables tb) {
     a[r] = vx[r] ? asum / deg : -INFINITY;
     qb[r] = qsum / deg;
   }
-  for (int k = 0; k < deg; ++k) {
-    double part = 0.0;
+  // row x of the tile belongs to the 64-row record (x - row0) / 64: lane-row
+  // r of a lane covers rows r * LPR + lrow, record (r * LPR) / 64
+  for (int q = 0; q < TQ; ++q) {
+    if (ti.row0 + q * 64 >= n) break;
+    double* __restrict__ rec = nd.tpart + (size_t)(ti.row0 / 64 + q) * (deg + kRecExtra);
+    for (int k = 0; k < deg; ++k) {
+      double part = 0.0;
 #pragma unroll
-    for (int r = 0; r < R; ++r) {
-      if (!vx[r]) continue;
-      const double m = mds[k].mfull[x[r]];
-      const double l = mds[k].lam_dst[cur][x[r]];
-      double* __restrict__ Ln = mds[k].lam_dst[nxt];
-      if (fixed) {
-        if (mux[r] > 0.0) part += mux[r] * fabs(expm1(l + m));
-        Ln[x[r]] = -m;
-      } else {
-        part += fabs(exp(l - c_old + m) - qb[r]);
-        Ln[x[r]] = a[r] - m;
+      for (int r = 0; r < R; ++r) {
+        if (!vx[r] || (r * LPR) / 64 != q) continue;
+        const double m = mds[k].mfull[x[r]];
+        const double l = mds[k].lam_dst[cur][x[r]];
+        double* __restrict__ Ln = mds[k].lam_dst[nxt];
+        if (fixed) {
+          if (mux[r] > 0.0) part += mux[r] * fabs(expm1(l + m));
+          Ln[x[r]] = -m;
+        } else {
+          part += fabs(exp(l - c_old + m) - qb[r]);
+          Ln[x[r]] = a[r] - m;
+        }
       }
+      part = wave_sum(part);
+      if (lane == 0) rec[k] = part;
     }
-    part = wave_sum(part);
-    if (lane == 0) rec[k] = part;
-  }
-  if (!fixed) {
-    double am = -INFINITY;
+    if (!fixed) {
+      double am = -INFINITY;
 #pragma unroll
-    for (int r = 0; r < R; ++r) am = fmax(am, a[r]);
-    const double Mw = wave_max(am);
-    double sv = 0.0;
+      for (int r = 0; r < R; ++r)
+        if ((r * LPR) / 64 == q) am = fmax(am, a[r]);
+      const double Mw = wave_max(am);
+      double sv = 0.0;
 #pragma unroll
-    for (int r = 0; r < R; ++r) sv += (a[r] > -INFINITY) ? exp(a[r] - Mw) : 0.0;
-    const double Sw = wave_sum(sv);
-    if (lane == 0) {
-      rec[deg] = Mw;
-      rec[deg + 1] = Sw;
+      for (int r = 0; r < R; ++r)
+        if ((r * LPR) / 64 == q) sv += (a[r] > -INFINITY) ? exp(a[r] - Mw) : 0.0;
+      const double Sw = wave_sum(sv);
+      if (lane == 0) {
+        rec[deg] = Mw;
+        rec[deg + 1] = Sw;
+      }
     }
   }
 }

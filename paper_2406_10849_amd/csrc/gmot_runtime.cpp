@@ -275,12 +275,12 @@ static int build_plan(gmot_ctx* ctx, const std::vector<gmot_problem*>& probs, No
         nd.abar = p->d_abar + p->node_off[j];
         nd.qbar = p->d_qbar + p->node_off[j];
         nd.c = p->fixed[j] ? nullptr : p->d_c + kSlots * j;
-        nd.tiles = (int)ceil_div(p->sizes[j], TRows);
+        nd.tiles = (int)ceil_div(p->sizes[j], 64);  // tile records: one per 64 rows
         {
           double src_cols = 0.0;
           for (int k : p->nbrs[j]) src_cols += p->sizes[k];
           const int dk = p->cost_kind == GMOT_COST_EXPLICIT ? 0 : p->dim;
-          ntl[c][dk].push_back({(int)pl->nodes[c].size(), nd.tiles, (int)i, src_cols});
+          ntl[c][dk].push_back({(int)pl->nodes[c].size(), (int)ceil_div(p->sizes[j], TRows), (int)i, src_cols});
         }
         item_of[{(int)i, j}] = {c, (int)pl->nodes[c].size()};
         pl->nodes[c].push_back(nd);
