@@ -330,7 +330,17 @@ def _shape_cases():
                   instance=60)
     star = make_tree([(0, k) for k in range(1, 21)], [150] + [37 + 11 * k for k in range(20)],
                      [0] + [1] * 20, dim=1, eps=0.05, instance=62)
-    return [t, star]
+    # explicit FP32 costs (one row per lane, so every pinned shape runs with its
+    # wave count only), ragged sizes for the tile-major copies
+    ex = make_tree([(0, 1), (1, 2), (1, 3)], [70, 129, 33, 200], [1, 0, 1, 1], dim=1, eps=0.05, instance=63)
+    rng = np.random.default_rng(63)
+    ex.cost = []
+    for a, b in ex.edges:
+        X, Y = ex.node_support(int(a)), ex.node_support(int(b))
+        C = np.sum((X[:, None, :] - Y[None, :, :]) ** 2, axis=2) * rng.uniform(0.5, 1.5, size=(X.shape[0], Y.shape[0]))
+        ex.cost.append(C.astype(np.float32))
+    ex.cost_kind = COST_EXPLICIT
+    return [t, star, ex]
 
 
 @pytest.mark.parametrize("shape", SHAPES)
