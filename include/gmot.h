@@ -304,7 +304,7 @@ int  gmot_mlp_warm_start(gmot_mlp* m, gmot_problem* const* probs, int32_t count,
 /* Time the candidate node-kernel block shapes (2, 4, 8 or 16 waves per tile, the
  * waves splitting each edge's source columns; 1 or 2 rows per lane; 1 or 2 lane
  * groups per wave, the groups of a wave splitting its columns again; tiles of
- * 64 * rows_per_lane / lane_groups rows) by the device time of a
+ * 64 * rows_per_lane / lane_groups = 32, 64 or 128 rows) by the device time of a
  * few real FP32-core half-sweeps (node stage and finalise kernel) run from a
  * snapshot of the held state, which is restored afterwards, and keep the
  * fastest plan; best_ms is that half-sweep time.

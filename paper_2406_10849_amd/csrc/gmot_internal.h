@@ -90,7 +90,7 @@ constexpr int kRecExtra = 2;    // tile record entries after the per-edge terms
 // tile's LSE max and scaled sum of abar) start at tpart + tile * (deg + kRecExtra).
 struct NodeItem {
   int32_t inst, node, n, deg;
-  int32_t fixed, msg0, err_idx, tiles;  // tiles: tile records, one per 64 rows
+  int32_t fixed, msg0, err_idx, tiles;  // tiles: tile records, one per min(tile rows, 64) rows
   const double* lg;          // log gamma_j, [n]
   const double* mu;          // mu_j for constrained nodes, else NULL
   double* abar;              // scratch [n]: mean_k m_{k->j}
@@ -230,7 +230,7 @@ hipError_t launch_star_apply(const StarDesc* stars, int count, int L, int n, con
 #include <map>
 // Host-side context shared by the runtime and the MLP host code.
 // Node-kernel block shape: W waves per block, R rows per lane, H lane groups per
-// wave (tiles of 64 * R / H rows).
+// wave (tiles of 64 * R / H rows: 32, 64 or 128).
 struct NodeShape {
   int W, R, H;
 };

@@ -311,6 +311,10 @@ __global__ __launch_bounds__(kBlock) void k_msg(Tables tb, int src_slot) {
 typedef const __attribute__((address_space(1))) double GDbl;
 typedef __attribute__((address_space(1))) double GDblW;
 typedef const __attribute__((address_space(1))) float GFlt;
+// Message descriptors are written only by the host, between launches: read
+// through the constant address space, a wave-uniform descriptor field is one
+// scalar load instead of a vector load per lane.
+typedef const __attribute__((address_space(4))) MsgDesc CMsg;
 constexpr int kFinWaves = 16;    // waves per finalise block (one node each)
 constexpr double kShiftHi = 96.0;
 constexpr double kShiftLo = -96.0;
@@ -404,8 +408,10 @@ __device__ inline void wave_sync() {
 }
 
 template <int DIM, int W, int R, int H, bool F64, bool EXPL>
-__global__ __launch_bounds__(64 * W) void k_node(Tables tb) {
-  static_assert(R % H == 0 && (H == 1 || !EXPL), "lane groups need as many rows per lane");
+// The 8-wave, 32-row-tile shape asks for four waves per SIMD (at most 128
+// VGPRs), so that two of its blocks share a CU.
+__global__ __launch_bounds__(64 * W, (W == 8 && R == 1 && H == 2 && !EXPL) ? 4 : 1) void k_node(Tables tb) {
+  static_assert(H == 1 || !EXPL, "explicit costs take one lane group");
   constexpr int LPR = 64 / H;                        // lanes per lane group
   constexpr int CH = EXPL ? 32 : 64;                 // columns per wave chunk
   constexpr int CHH = CH / H;                        // columns per lane-group chunk
@@ -441,11 +447,13 @@ __global__ __launch_bounds__(64 * W) void k_node(Tables tb) {
   const int src_slot = (int)((t >> 1) % kSlots);
   const bool one = !F64 && t >= st->onepass_from;
   const bool rec_ok = t - 1 >= st->t_first;
-  const MsgDesc* __restrict__ mds = tb.msgs + ti.msg0;
+  const CMsg* __restrict__ mds = (const CMsg*)(tb.msgs + ti.msg0);
   const int n = ti.n, deg = ti.deg;
   const bool lds = deg <= kNodeDegLDS;
   const bool fixed = ti.fixed != 0;
-  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  // the wave index is the same on every lane; said so, the edge it picks and
+  // that edge's descriptor reads are wave-uniform
+  const int lane = threadIdx.x & 63, wv = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
   // H lane groups of LPR lanes: lane (group h, index i) holds rows i, i + LPR, ...
   // of the tile and sums column range h of its wave's share of each edge
   const int lrow = lane % LPR, half = lane / LPR;
@@ -497,7 +505,7 @@ __global__ __launch_bounds__(64 * W) void k_node(Tables tb) {
   // makes every later wait for a load wait for all of them).
   auto edge_sums = [&](const int k, auto lds_t) {
     constexpr bool LDS_T = decltype(lds_t)::value;
-    const MsgDesc& md = mds[k];
+    const CMsg& md = mds[k];
     const int n_src = md.n_src;
     const int per = (n_src + gr - 1) / gr;
     const int rid = sub * H + half;
@@ -507,11 +515,19 @@ __global__ __launch_bounds__(64 * W) void k_node(Tables tb) {
     const int span = H == 1 ? c_hi - c_lo : per;
     // The source's normaliser c_k only shifts the message (m = m' - c_k with m'
     // summed over L + log gamma): it is formed from the source node's tile
-    // records after the column loop; those loads go out first.
+    // records (or read from its stored slot) after the column loop.  Every
+    // field and value it needs is read here, before the loop: the loop's wave
+    // fences would otherwise make the compiler read the descriptor again after
+    // it, a chain of dependent loads with nothing to overlap them.
     const GDbl* __restrict__ srec = (const GDbl*)md.src_tpart;
-    const int s_stride = md.src_deg + kRecExtra, s_tile = min(lane, md.src_tiles - 1);
-    const double rec_m0 = srec[(size_t)s_tile * s_stride + md.src_deg];
-    const double rec_s0 = srec[(size_t)s_tile * s_stride + md.src_deg + 1];
+    const int src_deg = md.src_deg, src_tiles = md.src_tiles;
+    const bool src_free = md.src_free != 0;
+    const int s_stride = src_deg + kRecExtra, s_tile = min(lane, src_tiles - 1);
+    const double rec_m0 = srec[(size_t)s_tile * s_stride + src_deg];
+    const double rec_s0 = srec[(size_t)s_tile * s_stride + src_deg + 1];
+    // a constrained source has no slots (c = 0); the load then reads any valid
+    // address and its value is not used
+    const double c_held = *(const GDbl*)(md.c_src ? md.c_src + src_slot : md.lam_src[src_slot]);
     const GDbl* __restrict__ lam = (const GDbl*)md.lam_src[src_slot];
     const GDbl* __restrict__ lg = (const GDbl*)md.lg_src;
     const GDbl* __restrict__ ys = (const GDbl*)md.supp_src;
@@ -837,9 +853,8 @@ __global__ __launch_bounds__(64 * W) void k_node(Tables tb) {
     // from the records when the source's last update (half-sweep t - 1) ran in
     // this run, else its stored normaliser
     double ck = 0.0;
-    if (sub == 0 && md.src_free)
-      ck = rec_ok ? tile_lse((const double*)md.src_tpart, md.src_tiles, s_stride, md.src_deg, rec_m0, rec_s0)
-                  : md.c_src[src_slot];
+    if (sub == 0 && src_free)
+      ck = rec_ok ? tile_lse((const double*)srec, src_tiles, s_stride, src_deg, rec_m0, rec_s0) : c_held;
     if (LDS_T && sub == 0 && lane == 0) s_csrc[k] = ck;
 #pragma unroll
     for (int r = 0; r < R; ++r) {
@@ -885,7 +900,8 @@ __global__ __launch_bounds__(64 * W) void k_node(Tables tb) {
     for (int k = k_first; k < deg; k += k_step) edge_sums(k, std::false_type{});
   }
   __syncthreads();
-  constexpr int TQ = TR / 64;  // 64-row blocks of a tile, one record each
+  constexpr int RR = TR < 64 ? TR : 64;  // rows per tile record
+  constexpr int TQ = TR / RR;            // records per tile
   const double c_old = nd.c ? nd.c[cur] : 0.0;
 
   if (lds) {
@@ -911,14 +927,14 @@ __global__ __launch_bounds__(64 * W) void k_node(Tables tb) {
       s_m[k][lr] = (Mx > -INFINITY && St > 0.0) ? kLn2 * (Mx + log2(St)) - s_x2[lr] / eps - s_csrc[k] : -INFINITY;
     }
     __syncthreads();
-    // Row owners: wave q takes rows q * 64 + lane of the tile and, for each
+    // Row owners: wave q takes rows q * RR + lane of the tile and, for each
     // row, every edge in order (terms of the state before the update, the
     // update), then sums its 64 rows into the row block's record: per edge the
     // terms, then (max, scaled sum) of abar.  No block barrier after the merge.
-    if (wv >= TQ || ti.row0 + wv * 64 >= n) return;
-    const int lr = wv * 64 + lane, xr = ti.row0 + lr;
-    const bool vr = xr < n;
-    double* __restrict__ rec = nd.tpart + (size_t)(ti.row0 / 64 + wv) * (deg + kRecExtra);
+    if (wv >= TQ || ti.row0 + wv * RR >= n) return;
+    const int lr = wv * RR + (lane < RR ? lane : 0), xr = ti.row0 + lr;
+    const bool vr = lane < RR && xr < n;  // lanes past RR (RR = 32) only join the sums
+    double* __restrict__ rec = nd.tpart + (size_t)(ti.row0 / RR + wv) * (deg + kRecExtra);
     if (fixed) {
       const double mu = s_mu[lr];
       for (int k = 0; k < deg; ++k) {
@@ -936,7 +952,7 @@ __global__ __launch_bounds__(64 * W) void k_node(Tables tb) {
       for (int k = 0; k < deg; ++k) {
         const double m = s_m[k][lr];
         const double q = vr ? exp(s_l[k][lr] - c_old + m) : 0.0;
-        s_part[k][lr].y = q;  // this lane's own scratch from here on
+        if (lane < RR) s_part[k][lr].y = q;  // this lane's own scratch from here on
         as += m;
         qs += q;
       }
@@ -982,15 +998,15 @@ __global__ __launch_bounds__(64 * W) void k_node(Tables tb) {
     qb[r] = qsum / deg;
   }
   // row x of the tile belongs to the 64-row record (x - row0) / 64: lane-row
-  // r of a lane covers rows r * LPR + lrow, record (r * LPR) / 64
+  // r of a lane covers rows r * LPR + lrow, record (r * LPR) / RR
   for (int q = 0; q < TQ; ++q) {
-    if (ti.row0 + q * 64 >= n) break;
-    double* __restrict__ rec = nd.tpart + (size_t)(ti.row0 / 64 + q) * (deg + kRecExtra);
+    if (ti.row0 + q * RR >= n) break;
+    double* __restrict__ rec = nd.tpart + (size_t)(ti.row0 / RR + q) * (deg + kRecExtra);
     for (int k = 0; k < deg; ++k) {
       double part = 0.0;
 #pragma unroll
       for (int r = 0; r < R; ++r) {
-        if (!vx[r] || (r * LPR) / 64 != q) continue;
+        if (!vx[r] || (r * LPR) / RR != q) continue;
         const double m = mds[k].mfull[x[r]];
         const double l = mds[k].lam_dst[cur][x[r]];
         double* __restrict__ Ln = mds[k].lam_dst[nxt];
@@ -1009,12 +1025,12 @@ __global__ __launch_bounds__(64 * W) void k_node(Tables tb) {
       double am = -INFINITY;
 #pragma unroll
       for (int r = 0; r < R; ++r)
-        if ((r * LPR) / 64 == q) am = fmax(am, a[r]);
+        if ((r * LPR) / RR == q) am = fmax(am, a[r]);
       const double Mw = wave_max(am);
       double sv = 0.0;
 #pragma unroll
       for (int r = 0; r < R; ++r)
-        if ((r * LPR) / 64 == q) sv += (a[r] > -INFINITY) ? exp(a[r] - Mw) : 0.0;
+        if ((r * LPR) / RR == q) sv += (a[r] > -INFINITY) ? exp(a[r] - Mw) : 0.0;
       const double Sw = wave_sum(sv);
       if (lane == 0) {
         rec[deg] = Mw;
@@ -1258,6 +1274,7 @@ hipError_t launch_node(const Tables& tb, int n_tiles, int dim, int waves, int ro
   if (dim == 0) return hipErrorInvalidValue;
   if (rows_per_lane == 2 && lane_groups == 1) return launch_node_r<2, 1>(tb, n_tiles, dim, waves, fp64, s);
   if (rows_per_lane == 2 && lane_groups == 2) return launch_node_r<2, 2>(tb, n_tiles, dim, waves, fp64, s);
+  if (rows_per_lane == 1 && lane_groups == 2) return launch_node_r<1, 2>(tb, n_tiles, dim, waves, fp64, s);
   return hipErrorInvalidValue;
 }
 

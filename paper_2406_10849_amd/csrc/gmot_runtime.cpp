@@ -275,7 +275,7 @@ static int build_plan(gmot_ctx* ctx, const std::vector<gmot_problem*>& probs, No
         nd.abar = p->d_abar + p->node_off[j];
         nd.qbar = p->d_qbar + p->node_off[j];
         nd.c = p->fixed[j] ? nullptr : p->d_c + kSlots * j;
-        nd.tiles = (int)ceil_div(p->sizes[j], 64);  // tile records: one per 64 rows
+        nd.tiles = (int)ceil_div(p->sizes[j], std::min(TRows, 64));  // tile records: one per 64 rows (32 for 32-row tiles)
         {
           double src_cols = 0.0;
           for (int k : p->nbrs[j]) src_cols += p->sizes[k];
@@ -488,13 +488,12 @@ static uint64_t shape_key(const std::vector<gmot_problem*>& probs) {
 constexpr NodeShape kDefaultShape{4, 2, 1};
 
 static bool valid_shape(const NodeShape& s) {
-  return (s.W == 2 || s.W == 4 || s.W == 8 || s.W == 16) && (s.R == 1 || s.R == 2) && (s.H == 1 || s.H == 2) &&
-         s.R % s.H == 0;
+  return (s.W == 2 || s.W == 4 || s.W == 8 || s.W == 16) && (s.R == 1 || s.R == 2) && (s.H == 1 || s.H == 2);
 }
 
 // Node-kernel block shape: a tuned choice cached in the context for these
 // shapes, else the default; GMOT_NODE_SHAPE="W,R" or "W,R,H" (W in 2, 4, 8,
-// 16; R in 1, 2; H in 1, 2 with H <= R) overrides both.
+// 16; R in 1, 2; H in 1, 2) overrides both.
 static NodeShape choose_shape(gmot_ctx* ctx, const std::vector<gmot_problem*>& probs) {
   NodeShape sh = kDefaultShape;
   auto it = ctx->tuned.find(shape_key(probs));
@@ -1080,8 +1079,8 @@ constexpr double kAutotuneMargin = 0.97;
 
 static int autotune(gmot_ctx* ctx, const std::vector<gmot_problem*>& probs, Plan** plan_io, int32_t* W_out,
                     int32_t* R_out, int32_t* H_out, double* ms_out) {
-  static const NodeShape kCand[] = {{2, 1, 1},  {4, 1, 1}, {8, 1, 1}, {16, 1, 1}, {2, 2, 1}, {4, 2, 1},
-                                    {8, 2, 1},  {16, 2, 1}, {4, 2, 2}, {8, 2, 2}, {16, 2, 2}};
+  static const NodeShape kCand[] = {{2, 1, 1}, {4, 1, 1}, {8, 1, 1},  {16, 1, 1}, {2, 2, 1}, {4, 2, 1}, {8, 2, 1},
+                                    {16, 2, 1}, {4, 2, 2}, {8, 2, 2}, {16, 2, 2}, {4, 1, 2}, {8, 1, 2}, {16, 1, 2}};
   bool expl = false;
   for (const gmot_problem* p : probs) expl = expl || p->cost_kind == GMOT_COST_EXPLICIT;
   std::vector<NodeShape> cands;

@@ -318,7 +318,8 @@ def test_one_pass_matches_two_pass(ctx):
             assert np.max(np.abs(g1.coupling(e) - g2.coupling(e))) <= 1e-6
 
 
-SHAPES = ["2,1", "4,1", "8,1", "16,1", "2,2", "4,2", "8,2", "16,2", "2,2,2", "4,2,2", "8,2,2", "16,2,2"]
+SHAPES = ["2,1", "4,1", "8,1", "16,1", "2,2", "4,2", "8,2", "16,2", "2,2,2", "4,2,2", "8,2,2", "16,2,2",
+          "2,1,2", "4,1,2", "8,1,2", "16,1,2"]
 
 
 def _shape_cases():
