@@ -60,8 +60,9 @@ struct MsgDesc {
   double* lam_dst[kSlots];   // stored L_(j,k) slots, [n_dst]
   double2* partial;          // [n_dst * ns]: evaluation pass, per row its ns column splits, each
                              // (split max M, sum of 2^(w - M))
-  double* wmax;              // [kMaxRanges * n_dst]: node kernel, wave-major, per row the max of
-                             // each wave's column range at the last computation (next shift)
+  double* wmax;              // [kMaxRanges * n_dst]: node kernel, wave-major, per row the max (to
+                             // within one binade) of each wave's column range at the last
+                             // computation (next shift)
   double* mfull;             // merged message m_{k->j}, [n_dst], natural log
   const float* cost;         // explicit cost stored src-major: cost[y * n_dst + x] = C_(j,k)(x, y)
   const float* cost_tile;    // the same, tile-major for the node kernel: C_(j,k)(x, y) at

@@ -298,12 +298,14 @@ __global__ __launch_bounds__(kBlock) void k_msg(Tables tb, int src_slot) {
 // Sums (FP32 core): pairs of v_exp_f32 terms of the FP64-reduced argument,
 // added in FP32 and accumulated in FP64.  From the third half-sweep of a call
 // on, one pass shifted by the previous max of the same row and column range
-// (kept in wmax) with the new max tracked alongside; a chunk whose max exceeds
-// the shift by more than kShiftHi moves the shift and is summed again, and a
-// row whose max ends more than kShiftLo below its shift sends the wave back
-// through its range in two passes.  Both decisions are wave-uniform.  The
-// first two half-sweeps of a call take two passes (chunk max, then sum); the
-// FP64 variant (F64) always does, with FP64 exponentials.
+// (kept in wmax: the log2 of the largest FP32 pair sum, so the max term to
+// within one binade above it), tracked alongside as the max of the pair sums;
+// a chunk whose sum exceeds 2^kShiftHi (so a term may have overflowed) moves
+// the shift to its exact max and is summed again, and a row whose sum ends
+// below 2^kShiftLo (terms may have underflowed) sends the wave back through
+// its range in two passes.  Both decisions are wave-uniform.
+// The first two half-sweeps of a call take two passes (chunk max, then sum);
+// the FP64 variant (F64) always does, with FP64 exponentials.
 // ---------------------------------------------------------------------------
 // Global address space views of device arrays reached through descriptors:
 // loads through them are counted in order with the other vector loads, so a
@@ -318,6 +320,8 @@ typedef const __attribute__((address_space(4))) MsgDesc CMsg;
 constexpr int kFinWaves = 16;    // waves per finalise block (one node each)
 constexpr double kShiftHi = 96.0;
 constexpr double kShiftLo = -96.0;
+constexpr double kSumHi = 0x1p96;   // 2^kShiftHi
+constexpr double kSumLo = 0x1p-96;  // 2^kShiftLo
 constexpr int kNodeDegLDS = 16;  // merged messages of the first 16 edges stay in LDS
 
 // The finalise step of one instance (one block of NW waves, one wave per node
@@ -672,11 +676,12 @@ __global__ __launch_bounds__(64 * W, (W == 8 && R == 1 && H == 2 && !EXPL) ? 4 :
     if (one) {
       // Row x is shifted by s(x) = sb(x) + dl(x).  With FOLD, sb(x) = al + be cx(x)
       // is the chord, over the lane group's rows of least and greatest cx, of the
-      // previous row maxima (convex in cx), folded into the staged columns; a
-      // wave whose every row's previous max lies within [-64, 32] of the chord
-      // sums with dl = 0 and one FMA per pair ("folded"), otherwise (and after a
-      // re-shift) dl(x) carries the rest of the previous max ("row mode").
-      // Without FOLD, sb = 0 and s(x) is the previous max as is.
+      // previous row shifts (maxima of exponents affine in cx, so convex in
+      // cx), folded into the staged columns; a wave whose every row's previous
+      // shift lies within [-64, 32] of the chord sums with dl = 0 and one FMA
+      // per pair ("folded"), otherwise (and after a re-shift) dl(x) carries the
+      // rest of the previous shift ("row mode").  Without FOLD, sb = 0 and s(x)
+      // is the previous shift as is.
       double sb[R], dl[R];
       bool pmok[R];
       double pmv[R];
@@ -744,6 +749,9 @@ __global__ __launch_bounds__(64 * W, (W == 8 && R == 1 && H == 2 && !EXPL) ? 4 :
 #pragma unroll
       for (int r = 0; r < R; ++r) dl[r] = rowmode ? (pmok[r] ? pmv[r] : 0.0) - sb[r] : 0.0;
 
+      float Mp[R];  // max pair sum relative to the shift, over the range
+#pragma unroll
+      for (int r = 0; r < R; ++r) Mp[r] = 0.0f;
       fetch_cost(c_lo);
       for (int j0 = 0; j0 < span; j0 += CHH) {
         const int c0 = c_lo + j0;
@@ -752,15 +760,11 @@ __global__ __launch_bounds__(64 * W, (W == 8 && R == 1 && H == 2 && !EXPL) ? 4 :
         advance();
         fetch_into(c0 + 2 * CHH, min(CHH, c_hi - c0 - 2 * CHH), g_raw);  // past the range: masked
         fetch_cost(c0 + CHH);
-        // one pass: sums of 2^(d) with d the staged exponent minus dl, FP32
-        // maxima of d alongside
-        float Mf[R];
+        // one pass: sums of 2^(d) with d the staged exponent minus dl, and
+        // the max of the FP32 pair sums (within a factor 2 of the max term)
         double Sc[R];
 #pragma unroll
-        for (int r = 0; r < R; ++r) {
-          Mf[r] = -INFINITY;
-          Sc[r] = 0.0;
-        }
+        for (int r = 0; r < R; ++r) Sc[r] = 0.0;
         auto pass = [&](auto row_t) {
           constexpr bool ROW = decltype(row_t)::value;
 #pragma unroll 4
@@ -773,21 +777,19 @@ __global__ __launch_bounds__(64 * W, (W == 8 && R == 1 && H == 2 && !EXPL) ? 4 :
                 d0 -= dl[r];
                 d1 -= dl[r];
               }
-              const float f0 = (float)d0, f1 = (float)d1;
-              Mf[r] = fmaxf(Mf[r], fmaxf(f0, f1));
-              const float p = exp2_hw(f0) + exp2_hw(f1);
+              const float p = exp2_hw((float)d0) + exp2_hw((float)d1);
+              Mp[r] = fmaxf(Mp[r], p);
               Sc[r] += (double)p;
             }
           }
         };
         if (rowmode) pass(std::true_type{});
         else pass(std::false_type{});
-        double Mc[R];  // chunk maxima of the exponent, absolute
-#pragma unroll
-        for (int r = 0; r < R; ++r) Mc[r] = (sb[r] + dl[r]) + (double)Mf[r];
+        // The terms are positive, so a chunk sum within 2^kShiftHi bounds every
+        // term (an FP32 overflow gives inf and fails the test too)
         int hi = 0;
 #pragma unroll
-        for (int r = 0; r < R; ++r) hi |= (vx[r] && !(Mf[r] <= (float)kShiftHi)) ? 1 : 0;
+        for (int r = 0; r < R; ++r) hi |= (vx[r] && !(Sc[r] <= kSumHi)) ? 1 : 0;
         if (__any(hi)) {
           // exact FP64 maxima; rows far above their shift move it and the
           // chunk is summed again in row mode
@@ -795,30 +797,42 @@ __global__ __launch_bounds__(64 * W, (W == 8 && R == 1 && H == 2 && !EXPL) ? 4 :
           chunk_max(dl, Md);
 #pragma unroll
           for (int r = 0; r < R; ++r) {
-            Mc[r] = (sb[r] + dl[r]) + Md[r];
             if (Md[r] > kShiftHi) {
+              // this chunk's max term is now 2^0, above every earlier one
               S[r] *= exp2(-Md[r]);
               dl[r] += Md[r];
+              Mp[r] = 1.0f;
             }
           }
           rowmode = true;
           chunk_sum(dl, Sc);
         }
 #pragma unroll
-        for (int r = 0; r < R; ++r) {
-          M[r] = fmax(M[r], Mc[r]);
-          S[r] += Sc[r];
-        }
+        for (int r = 0; r < R; ++r) S[r] += Sc[r];
         wave_sync();
       }
+      // A row of a non-empty range whose sum ends below 2^kShiftLo may have
+      // lost terms to FP32 underflow (or has no finite term): two passes.
+      // Otherwise the range reports M = shift + log2 of its largest pair sum
+      // (the max term to within one binade, the next shift) and S relative
+      // to M; M + log2 S is the shift plus log2 of the sum, whatever the
+      // rounding of the FP32 log.
       int lo = 0;
 #pragma unroll
-      for (int r = 0; r < R; ++r) lo |= (vx[r] && M[r] > -INFINITY && M[r] - (sb[r] + dl[r]) < kShiftLo) ? 1 : 0;
+      for (int r = 0; r < R; ++r) lo |= (vx[r] && c_hi > c_lo && !(S[r] >= kSumLo)) ? 1 : 0;
       if (__any(lo)) {
-        two = true;  // a row's terms fell out of FP32 range: two passes
+        two = true;
       } else {
 #pragma unroll
-        for (int r = 0; r < R; ++r) S[r] = (M[r] > -INFINITY) ? S[r] * exp2((sb[r] + dl[r]) - M[r]) : 0.0;
+        for (int r = 0; r < R; ++r) {
+          if (S[r] > 0.0) {
+            const double lm = (double)__builtin_amdgcn_logf(Mp[r]);
+            M[r] = (sb[r] + dl[r]) + lm;
+            S[r] *= exp2(-lm);
+          } else {
+            M[r] = -INFINITY;
+          }
+        }
       }
     }
     if (two) {
@@ -859,7 +873,7 @@ __global__ __launch_bounds__(64 * W, (W == 8 && R == 1 && H == 2 && !EXPL) ? 4 :
 #pragma unroll
     for (int r = 0; r < R; ++r) {
       if (LDS_T) {
-        // the range maxima go to wmax in the merge below
+        // the ranges' next shifts go to wmax in the merge below
         s_part[k * gr + rid][r * LPR + lrow] = make_double2(M[r], S[r]);
       } else {
         if (vx[r]) wmax[(size_t)rid * n + x[r]] = M[r];
@@ -906,7 +920,8 @@ __global__ __launch_bounds__(64 * W, (W == 8 && R == 1 && H == 2 && !EXPL) ? 4 :
 
   if (lds) {
     // merge the gr ranges of every (edge, row) into m (natural log); each
-    // range's max is the row's next one-pass shift
+    // range's M (its max, or within one binade above it) is the row's next
+    // one-pass shift
     for (int it = threadIdx.x; it < deg * TR; it += NT) {
       const int k = it / TR, lr = it - k * TR;
       const int xr = ti.row0 + lr;
