@@ -444,23 +444,61 @@ __global__ __launch_bounds__(64 * W, (W == 8 && R == 1 && H == 2 && !EXPL) ? 4 :
   const TileItem ti = tb.tiles[blockIdx.x - tb.n_fin];
   const InstState* st = tb.inst + ti.inst;
   const NodeItem nd = tb.nodes[ti.node];
-  const long long t = st->vt[tb.colour];
-  if (st->vdone[tb.colour] || t < st->t_first || ((t & 1) == 1) != (tb.colour == 0)) return;
-  // slots: this class's held state before t, its update, the other class's held state
-  const int cur = (int)(((t - 1) >> 1) % kSlots), nxt = (cur + 1) % kSlots;
-  const int src_slot = (int)((t >> 1) % kSlots);
-  const bool one = !F64 && t >= st->onepass_from;
-  const bool rec_ok = t - 1 >= st->t_first;
   const CMsg* __restrict__ mds = (const CMsg*)(tb.msgs + ti.msg0);
   const int n = ti.n, deg = ti.deg;
-  const bool lds = deg <= kNodeDegLDS;
-  const bool fixed = ti.fixed != 0;
   // the wave index is the same on every lane; said so, the edge it picks and
   // that edge's descriptor reads are wave-uniform
   const int lane = threadIdx.x & 63, wv = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
   // H lane groups of LPR lanes: lane (group h, index i) holds rows i, i + LPR, ...
   // of the tile and sums column range h of its wave's share of each edge
   const int lrow = lane % LPR, half = lane / LPR;
+  // Edges run on different waves: with deg >= W each wave takes whole edges
+  // (k = wv, wv + W, ...); otherwise g = W / deg waves share an edge.  Each
+  // wave's share is split over its H lane groups: gr = g * H column ranges per
+  // edge, range rid = sub * H + half.
+  const int g = deg >= W ? 1 : W / deg;
+  const int gr = g * H;
+  const int k_first = deg >= W ? wv : (wv < deg * g ? wv / g : deg);
+  const int k_step = deg >= W ? W : deg;
+  const int sub = deg >= W ? 0 : wv % g;
+  // The first chunk of the wave's first edge and that edge's stored shifts,
+  // loaded before the instance state arrives: none of it depends on the
+  // half-sweep except the slot of the source potentials, so every slot is read
+  // (a wave without an edge reads the last edge's and ignores them)
+  const int kp = min(k_first, deg - 1);
+  const int p_nsrc = mds[kp].n_src, p_rid = sub * H + half;
+  const int p_col = min(min(p_rid * ((p_nsrc + gr - 1) / gr), p_nsrc) + lrow, p_nsrc - 1);
+  double pf_l[kSlots], pf_y[DIM > 0 ? DIM : 1], pf_pm[R];
+#pragma unroll
+  for (int q = 0; q < kSlots; ++q) pf_l[q] = ((const GDbl*)mds[kp].lam_src[q])[p_col];
+  const double pf_g = ((const GDbl*)mds[kp].lg_src)[p_col];
+#pragma unroll
+  for (int d = 0; d < DIM; ++d) pf_y[d] = EXPL ? 0.0 : ((const GDbl*)mds[kp].supp_src)[(size_t)p_col * DIM + d];
+#pragma unroll
+  for (int r = 0; r < R; ++r)
+    pf_pm[r] = ((const GDbl*)mds[kp].wmax)[(size_t)p_rid * n + min(ti.row0 + r * LPR + lrow, n - 1)];
+  // this thread's rows' supports (clamped: unconditional loads)
+  double pf_x[R][DIM > 0 ? DIM : 1];
+#pragma unroll
+  for (int r = 0; r < R; ++r)
+#pragma unroll
+    for (int d = 0; d < DIM; ++d)
+      pf_x[r][d] = EXPL ? 0.0 : ((const GDbl*)mds[0].supp_dst)[(size_t)min(ti.row0 + r * LPR + lrow, n - 1) * DIM + d];
+  // the instance's view of the loop state (scalar loads, issued with the above)
+  const long long t = st->vt[tb.colour];
+  const bool inst_done = st->vdone[tb.colour] != 0;
+  const long long t_first = st->t_first, onepass_from = st->onepass_from;
+  // keeps every load above here: without it the column loads sink below the
+  // state check (their values are used only after it)
+  asm volatile("" ::: "memory");
+  if (inst_done || t < t_first || ((t & 1) == 1) != (tb.colour == 0)) return;
+  // slots: this class's held state before t, its update, the other class's held state
+  const int cur = (int)(((t - 1) >> 1) % kSlots), nxt = (cur + 1) % kSlots;
+  const int src_slot = (int)((t >> 1) % kSlots);
+  const bool one = !F64 && t >= onepass_from;
+  const bool rec_ok = t - 1 >= t_first;
+  const bool lds = deg <= kNodeDegLDS;
+  const bool fixed = ti.fixed != 0;
   int x[R];
   bool vx[R];
   const double eps = mds[0].eps;
@@ -475,40 +513,33 @@ __global__ __launch_bounds__(64 * W, (W == 8 && R == 1 && H == 2 && !EXPL) ? 4 :
     x2[r] = 0.0;
 #pragma unroll
     for (int d = 0; d < DIM; ++d) {
-      const double v = (vx[r] && !EXPL) ? mds[0].supp_dst[(size_t)x[r] * DIM + d] : 0.0;
+      const double v = (vx[r] && !EXPL) ? pf_x[r][d] : 0.0;
       cx[r][d] = cxs * v;
       x2[r] = fma(v, v, x2[r]);
     }
-    if (wv == 0 && half == 0) s_x2[r * LPR + lrow] = x2[r];
   }
   double* __restrict__ stage = s_col[wv];
   // the held potential (and mu) of this thread's first (edge, row) item of the
   // update phase, loaded now so that phase does not wait for memory
-  double l_item = 0.0, mu_item = 0.0;
-  if (deg <= kNodeDegLDS && (int)threadIdx.x < deg * TR) {
-    const int k = threadIdx.x / TR, xr = ti.row0 + (int)threadIdx.x - k * TR;
-    if (xr < n) {
-      l_item = mds[k].lam_dst[cur][xr];
-      if (fixed) mu_item = nd.mu[xr];
-    }
+  // (unconditional loads at clamped indexes, so the waits before the column
+  // loop can count them; the values of threads without an item are unused)
+  double l_item, mu_item;
+  {
+    const int k = min((int)threadIdx.x / TR, deg - 1);
+    const int xr = min(ti.row0 + (int)threadIdx.x - k * TR, n - 1);
+    l_item = ((const GDbl*)mds[k].lam_dst[cur])[xr];
+    const double mv = ((const GDbl*)(fixed ? nd.mu : mds[k].lam_dst[cur]))[xr];
+    mu_item = fixed ? mv : 0.0;
   }
-
-  // Edges run on different waves: with deg >= W each wave takes whole edges
-  // (k = wv, wv + W, ...); otherwise g = W / deg waves share an edge.  Each
-  // wave's share is split over its H lane groups: gr = g * H column ranges per
-  // edge, range rid = sub * H + half.
-  const int g = deg >= W ? 1 : W / deg;
-  const int gr = g * H;
-  const int k_first = deg >= W ? wv : (wv < deg * g ? wv / g : deg);
-  const int k_step = deg >= W ? W : deg;
-  const int sub = deg >= W ? 0 : wv % g;
 
   // One edge's sums.  LDS_T: the partials stay in LDS (deg <= kNodeDegLDS);
   // otherwise the message goes to global memory at once.  The two cases are
   // separate loops so the common one holds no global store (a store in flight
   // makes every later wait for a load wait for all of them).
-  auto edge_sums = [&](const int k, auto lds_t) {
+  // PRE: the wave's first edge, whose first chunk and shifts were loaded at entry.
+  auto edge_sums = [&](const int k, auto lds_t, auto pre_t) {
     constexpr bool LDS_T = decltype(lds_t)::value;
+    constexpr bool PRE = decltype(pre_t)::value;
     const CMsg& md = mds[k];
     const int n_src = md.n_src;
     const int per = (n_src + gr - 1) / gr;
@@ -691,10 +722,19 @@ __global__ __launch_bounds__(64 * W, (W == 8 && R == 1 && H == 2 && !EXPL) ? 4 :
       // needs the shift).
 #pragma unroll
       for (int r = 0; r < R; ++r) {
-        pmv[r] = wmax[(size_t)rid * n + min(x[r], n - 1)];
+        pmv[r] = PRE ? pf_pm[r] : (double)wmax[(size_t)rid * n + min(x[r], n - 1)];
         sb[r] = 0.0;
       }
-      fetch_chunk(c_lo, min(CHH, c_hi - c_lo));
+      if constexpr (PRE) {
+        // the column fetch_chunk(c_lo, ...) would load, in the current slot
+        f_raw.v = lrow < min(CHH, c_hi - c_lo);
+        f_raw.l = src_slot == 0 ? pf_l[0] : (src_slot == 1 ? pf_l[1] : pf_l[2]);
+        f_raw.g = pf_g;
+#pragma unroll
+        for (int d = 0; d < DIM; ++d) f_raw.y[d] = pf_y[d];
+      } else {
+        fetch_chunk(c_lo, min(CHH, c_hi - c_lo));
+      }
       fetch_into(c_lo + CHH, min(CHH, c_hi - c_lo - CHH), g_raw);
 #pragma unroll
       for (int r = 0; r < R; ++r) {
@@ -897,7 +937,14 @@ __global__ __launch_bounds__(64 * W, (W == 8 && R == 1 && H == 2 && !EXPL) ? 4 :
     }
   };
   if (lds) {
-    for (int k = k_first; k < deg; k += k_step) edge_sums(k, std::true_type{});
+    if (k_first < deg) edge_sums(k_first, std::true_type{}, std::true_type{});
+    for (int k = k_first + k_step; k < deg; k += k_step) edge_sums(k, std::true_type{}, std::false_type{});
+    // |x|^2 of the tile's rows for the merge (written here, not at entry, so
+    // that no wait for the entry loads comes before the column loop)
+    if (wv == 0 && half == 0) {
+#pragma unroll
+      for (int r = 0; r < R; ++r) s_x2[r * LPR + lrow] = x2[r];
+    }
     // the held potentials and mu of every (edge, row) into LDS for the row
     // owners below (the first item's were loaded at entry)
     for (int it = threadIdx.x; it < deg * TR; it += NT) {
@@ -911,7 +958,8 @@ __global__ __launch_bounds__(64 * W, (W == 8 && R == 1 && H == 2 && !EXPL) ? 4 :
       if (k == 0) s_mu[lr] = mu;
     }
   } else {
-    for (int k = k_first; k < deg; k += k_step) edge_sums(k, std::false_type{});
+    if (k_first < deg) edge_sums(k_first, std::false_type{}, std::true_type{});
+    for (int k = k_first + k_step; k < deg; k += k_step) edge_sums(k, std::false_type{}, std::false_type{});
   }
   __syncthreads();
   constexpr int RR = TR < 64 ? TR : 64;  // rows per tile record
