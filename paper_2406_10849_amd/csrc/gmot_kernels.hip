@@ -531,6 +531,9 @@ __global__ __launch_bounds__(64 * W, (W == 8 && R == 1 && H == 2 && !EXPL) ? 4 :
     const double mv = ((const GDbl*)(fixed ? nd.mu : mds[k].lam_dst[cur]))[xr];
     mu_item = fixed ? mv : 0.0;
   }
+  // this node's held normaliser (free nodes; a constrained node has no slots
+  // and reads any valid address), needed by the update phase
+  const double c_held_j = *(const GDbl*)(nd.c ? nd.c + cur : mds[0].lam_dst[0]);
 
   // One edge's sums.  LDS_T: the partials stay in LDS (deg <= kNodeDegLDS);
   // otherwise the message goes to global memory at once.  The two cases are
@@ -964,22 +967,14 @@ __global__ __launch_bounds__(64 * W, (W == 8 && R == 1 && H == 2 && !EXPL) ? 4 :
   __syncthreads();
   constexpr int RR = TR < 64 ? TR : 64;  // rows per tile record
   constexpr int TQ = TR / RR;            // records per tile
-  const double c_old = nd.c ? nd.c[cur] : 0.0;
+  const double c_old = nd.c ? c_held_j : 0.0;
 
   if (lds) {
-    // merge the gr ranges of every (edge, row) into m (natural log); each
-    // range's M (its max, or within one binade above it) is the row's next
-    // one-pass shift
+    // merge the gr ranges of every (edge, row) into m (natural log)
     for (int it = threadIdx.x; it < deg * TR; it += NT) {
       const int k = it / TR, lr = it - k * TR;
-      const int xr = ti.row0 + lr;
-      double* __restrict__ wm = mds[k].wmax;
       double Mx = -INFINITY;
-      for (int u = 0; u < gr; ++u) {
-        const double mu = s_part[k * gr + u][lr].x;
-        if (xr < n) wm[(size_t)u * n + xr] = mu;
-        Mx = fmax(Mx, mu);
-      }
+      for (int u = 0; u < gr; ++u) Mx = fmax(Mx, s_part[k * gr + u][lr].x);
       double St = 0.0;
       if (Mx > -INFINITY) {
         for (int u = 0; u < gr; ++u) {
@@ -990,14 +985,37 @@ __global__ __launch_bounds__(64 * W, (W == 8 && R == 1 && H == 2 && !EXPL) ? 4 :
       s_m[k][lr] = (Mx > -INFINITY && St > 0.0) ? kLn2 * (Mx + log2(St)) - s_x2[lr] / eps - s_csrc[k] : -INFINITY;
     }
     __syncthreads();
+    // Each range's M (its max, or within one binade above it) is the row's
+    // next one-pass shift; it stays in s_part (.x) until stored here, after
+    // the merge: a store in flight would make the row owners' next wait for
+    // a load wait for the store's completion too.  Waves that own no rows
+    // store them while the owners work; with no such wave (two waves over
+    // 128-row tiles), every thread does so at its end.
+    constexpr bool SPARE = W > TQ;
+    auto store_shifts = [&](int t0, int stride) {
+      for (int it = t0; it < deg * gr * TR; it += stride) {
+        const int ku = it / TR, lr = it - ku * TR, k = ku / gr, u = ku - k * gr;
+        const int xr = ti.row0 + lr;
+        if (xr < n) ((GDblW*)mds[k].wmax)[(size_t)u * n + xr] = s_part[ku][lr].x;
+      }
+    };
     // Row owners: wave q takes rows q * RR + lane of the tile and, for each
     // row, every edge in order (terms of the state before the update, the
     // update), then sums its 64 rows into the row block's record: per edge the
     // terms, then (max, scaled sum) of abar.  No block barrier after the merge.
-    if (wv >= TQ || ti.row0 + wv * RR >= n) return;
+    if (wv >= TQ) {
+      store_shifts((wv - TQ) * 64 + lane, (W - TQ) * 64);
+      return;
+    }
+    if (ti.row0 + wv * RR >= n) {
+      if (!SPARE) store_shifts(threadIdx.x, NT);
+      return;
+    }
     const int lr = wv * RR + (lane < RR ? lane : 0), xr = ti.row0 + lr;
     const bool vr = lane < RR && xr < n;  // lanes past RR (RR = 32) only join the sums
-    double* __restrict__ rec = nd.tpart + (size_t)(ti.row0 / RR + wv) * (deg + kRecExtra);
+    // global-space stores: a flat store also counts as an LDS access, so the
+    // next edge's LDS reads would wait for it to complete
+    GDblW* __restrict__ rec = (GDblW*)(nd.tpart + (size_t)(ti.row0 / RR + wv) * (deg + kRecExtra));
     if (fixed) {
       const double mu = s_mu[lr];
       for (int k = 0; k < deg; ++k) {
@@ -1005,7 +1023,7 @@ __global__ __launch_bounds__(64 * W, (W == 8 && R == 1 && H == 2 && !EXPL) ? 4 :
         double term = 0.0;
         if (vr) {
           if (mu > 0.0) term = mu * fabs(expm1(s_l[k][lr] + m));
-          mds[k].lam_dst[nxt][xr] = -m;
+          ((GDblW*)mds[k].lam_dst[nxt])[xr] = -m;
         }
         term = wave_sum(term);
         if (lane == 0) rec[k] = term;
@@ -1024,7 +1042,7 @@ __global__ __launch_bounds__(64 * W, (W == 8 && R == 1 && H == 2 && !EXPL) ? 4 :
         double term = 0.0;
         if (vr) {
           term = fabs(s_part[k][lr].y - qb);
-          mds[k].lam_dst[nxt][xr] = ab - s_m[k][lr];
+          ((GDblW*)mds[k].lam_dst[nxt])[xr] = ab - s_m[k][lr];
         }
         term = wave_sum(term);
         if (lane == 0) rec[k] = term;
@@ -1037,6 +1055,7 @@ __global__ __launch_bounds__(64 * W, (W == 8 && R == 1 && H == 2 && !EXPL) ? 4 :
         rec[deg + 1] = Sw;
       }
     }
+    if (!SPARE) store_shifts(threadIdx.x, NT);
     return;
   }
 
