@@ -916,7 +916,7 @@ __global__ __launch_bounds__(64 * W, (W == 8 && R == 1 && H == 2 && !EXPL) ? 4 :
 #pragma unroll
     for (int r = 0; r < R; ++r) {
       if (LDS_T) {
-        // the ranges' next shifts go to wmax in the merge below
+        // the ranges' next shifts go to wmax after the merge below
         s_part[k * gr + rid][r * LPR + lrow] = make_double2(M[r], S[r]);
       } else {
         if (vx[r]) wmax[(size_t)rid * n + x[r]] = M[r];
