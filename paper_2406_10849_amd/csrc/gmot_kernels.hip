@@ -970,26 +970,34 @@ __global__ __launch_bounds__(64 * W, (W == 8 && R == 1 && H == 2 && !EXPL) ? 4 :
   const double c_old = nd.c ? c_held_j : 0.0;
 
   if (lds) {
-    // merge the gr ranges of every (edge, row) into m (natural log): four
-    // lanes per (edge, row), lane q taking ranges q, q + 4, ..., their max and
-    // rescaled sums combined over the quad with DPP (a quad is always active
-    // as a whole: the loop bound and NT are multiples of four)
-    for (int it = threadIdx.x; it < deg * TR * 4; it += NT) {
-      const int item = it >> 2, q = it & 3;
+    // merge the gr ranges of every (edge, row) into m (natural log).  With
+    // four ranges or more (QL = 4), four lanes per (edge, row), lane q taking
+    // ranges q, q + 4, ..., their max and rescaled sums combined over the quad
+    // with DPP (a quad is always active as a whole: the loop bound and NT are
+    // multiples of four); with fewer (whole edges per wave), one lane each.
+    const int QL = gr >= 4 ? 4 : 1;
+    for (int it = threadIdx.x; it < deg * TR * QL; it += NT) {
+      const int item = QL == 4 ? it >> 2 : it, q = QL == 4 ? it & 3 : 0;
       const int k = item / TR, lr = item - k * TR;
       double Mq = -INFINITY;
-      for (int u = q; u < gr; u += 4) Mq = fmax(Mq, s_part[k * gr + u][lr].x);
-      double Mx = fmax(Mq, dpp_move<kDppXor1>(Mq));
-      Mx = fmax(Mx, dpp_move<kDppXor2>(Mx));
+      for (int u = q; u < gr; u += QL) Mq = fmax(Mq, s_part[k * gr + u][lr].x);
+      double Mx = Mq;
+      if (QL == 4) {
+        Mx = fmax(Mx, dpp_move<kDppXor1>(Mx));
+        Mx = fmax(Mx, dpp_move<kDppXor2>(Mx));
+      }
       double Sq = 0.0;
       if (Mx > -INFINITY) {
-        for (int u = q; u < gr; u += 4) {
+        for (int u = q; u < gr; u += QL) {
           const double2 e = s_part[k * gr + u][lr];
           if (e.y > 0.0) Sq += (e.x == Mx) ? e.y : e.y * exp2(e.x - Mx);
         }
       }
-      double St = Sq + dpp_move<kDppXor1>(Sq);
-      St += dpp_move<kDppXor2>(St);
+      double St = Sq;
+      if (QL == 4) {
+        St += dpp_move<kDppXor1>(St);
+        St += dpp_move<kDppXor2>(St);
+      }
       if (q == 0)
         s_m[k][lr] = (Mx > -INFINITY && St > 0.0) ? kLn2 * (Mx + log2(St)) - s_x2[lr] / eps - s_csrc[k] : -INFINITY;
     }
