@@ -256,7 +256,7 @@ def main() -> int:
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported (the solver runs on a "
-              f"single device; see the sharding notes in DESIGN.md)", file=sys.stderr)
+              f"single device; sharding over several GPUs is not built)", file=sys.stderr)
         return 2
 
     from workloads import make_config

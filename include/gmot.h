@@ -250,8 +250,8 @@ int  gmot_batch_solve(gmot_batch* b, const gmot_opts* opts, gmot_result* outs);
 
 /* ---- learned warm start ------------------------------------------------------------
  * Not part of the paper's method: a small network predicts starting potentials
- * for star instances; the bipartite iteration then runs as usual and remains
- * the judge of convergence (a cold start is the fallback).  For the callers
+ * for star instances; the bipartite iteration then runs as usual and still
+ * decides convergence (a cold start is the fallback).  For the callers
  * that want fewer half-sweeps on families of similar barycenter problems. */
 typedef struct gmot_mlp gmot_mlp;
 

@@ -12,7 +12,7 @@ in float64.  With ``quantize=False`` the network is the plain FP64 function,
 whose gradient is pinned by central finite differences in the tests.
 
 The warm-start network itself is not in the paper; it initialises the
-potentials of the scaling iteration (Section 3), which stays the judge of
+potentials of the scaling iteration (Section 3), which still decides
 convergence.
 """
 from __future__ import annotations

@@ -2,7 +2,7 @@
 // these kernels (BF16 MFMA GEMMs with FP32 accumulation, FP32 master weights
 // and Adam), plus the data movement between star instances and the network.
 // The network is not part of the paper's method; it only initialises the
-// potentials of the bipartite iteration, which stays the judge of convergence.
+// potentials of the bipartite iteration, which still decides convergence.
 #include "gmot.h"
 #include "gmot_internal.h"
 
