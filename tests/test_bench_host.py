@@ -1,0 +1,66 @@
+"""Host logic of bench.py that needs no GPU: the HBM-traffic lookup that keys
+measured counter values to the kernel source they were taken on and to the
+node shape the bench tuned, and the refusal of several GPUs."""
+import os
+import subprocess
+import sys
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+sys.path.insert(0, ROOT)
+import bench  # noqa: E402
+
+
+def _write(path, sha, lines):
+    with open(path, "w") as f:
+        f.write(f"kernel_sha256_16: {sha}\n")
+        for ln in lines:
+            f.write(ln + "\n")
+
+
+def test_traffic_reported_for_matching_source_and_shape(tmp_path, monkeypatch):
+    p = tmp_path / "traffic.txt"
+    _write(p, bench.kernel_sha(), [
+        "shape 8,1,1: fetch_bytes_per_launch 1000.0 write_bytes_per_launch 250.5 dispatches 3",
+        "shape 16,1,1: fetch_bytes_per_launch 7.0 write_bytes_per_launch 1.0 dispatches 3",
+    ])
+    monkeypatch.setattr(bench, "TRAFFIC_FILE", str(p))
+    assert bench.measured_traffic((8, 1, 1)) == pytest.approx(1250.5)
+    assert bench.measured_traffic((16, 1, 1)) == pytest.approx(8.0)
+    # a shape that was not measured has no traffic
+    assert bench.measured_traffic((4, 2, 1)) is None
+
+
+def test_traffic_withheld_once_the_kernel_source_changed(tmp_path, monkeypatch):
+    p = tmp_path / "traffic.txt"
+    stale = "0" * 16 if bench.kernel_sha() != "0" * 16 else "1" * 16
+    _write(p, stale, ["shape 8,1,1: fetch_bytes_per_launch 1000.0 write_bytes_per_launch 250.5 dispatches 3"])
+    monkeypatch.setattr(bench, "TRAFFIC_FILE", str(p))
+    assert bench.measured_traffic((8, 1, 1)) is None
+
+
+def test_traffic_absent_or_malformed(tmp_path, monkeypatch):
+    monkeypatch.setattr(bench, "TRAFFIC_FILE", str(tmp_path / "missing.txt"))
+    assert bench.measured_traffic((8, 1, 1)) is None
+    p = tmp_path / "bad.txt"
+    _write(p, bench.kernel_sha(), ["shape 8,1,1: fetch_bytes_per_launch x write_bytes_per_launch 1 dispatches 3"])
+    monkeypatch.setattr(bench, "TRAFFIC_FILE", str(p))
+    assert bench.measured_traffic((8, 1, 1)) is None
+
+
+def test_committed_traffic_file_lists_the_tuned_shapes():
+    # every line the bench may report carries both byte counts
+    text = open(bench.TRAFFIC_FILE).read().splitlines()
+    assert text[0].startswith("kernel_sha256_16: ")
+    shapes = [ln for ln in text if ln.startswith("shape ")]
+    assert any(ln.startswith("shape 8,1,1:") for ln in shapes)
+    for ln in shapes:
+        assert "fetch_bytes_per_launch" in ln and "write_bytes_per_launch" in ln
+
+
+def test_several_gpus_refused_with_a_message():
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"],
+                       capture_output=True, text=True, timeout=120)
+    assert r.returncode == 2
+    assert "one GPU" in r.stderr
