@@ -461,16 +461,16 @@ __global__ __launch_bounds__(64 * W, (W == 8 && R == 1 && H == 2 && !EXPL) ? 4 :
   const int k_first = deg >= W ? wv : (wv < deg * g ? wv / g : deg);
   const int k_step = deg >= W ? W : deg;
   const int sub = deg >= W ? 0 : wv % g;
-  // The first chunk of the wave's first edge and that edge's stored shifts,
-  // loaded before the instance state arrives: none of it depends on the
-  // half-sweep except the slot of the source potentials, so every slot is read
-  // (a wave without an edge reads the last edge's and ignores them)
+  // The first chunk of the wave's first edge (log gamma and supports) and
+  // that edge's stored shifts, loaded before the instance state arrives: none
+  // of it depends on the half-sweep (the source potentials do, through their
+  // slot, and are read after the state check; reading all three slots here
+  // was slower).  A wave without an edge reads the last edge's and ignores
+  // them.
   const int kp = min(k_first, deg - 1);
   const int p_nsrc = mds[kp].n_src, p_rid = sub * H + half;
   const int p_col = min(min(p_rid * ((p_nsrc + gr - 1) / gr), p_nsrc) + lrow, p_nsrc - 1);
-  double pf_l[kSlots], pf_y[DIM > 0 ? DIM : 1], pf_pm[R];
-#pragma unroll
-  for (int q = 0; q < kSlots; ++q) pf_l[q] = ((const GDbl*)mds[kp].lam_src[q])[p_col];
+  double pf_y[DIM > 0 ? DIM : 1], pf_pm[R];
   const double pf_g = ((const GDbl*)mds[kp].lg_src)[p_col];
 #pragma unroll
   for (int d = 0; d < DIM; ++d) pf_y[d] = EXPL ? 0.0 : ((const GDbl*)mds[kp].supp_src)[(size_t)p_col * DIM + d];
@@ -731,7 +731,7 @@ __global__ __launch_bounds__(64 * W, (W == 8 && R == 1 && H == 2 && !EXPL) ? 4 :
       if constexpr (PRE) {
         // the column fetch_chunk(c_lo, ...) would load, in the current slot
         f_raw.v = lrow < min(CHH, c_hi - c_lo);
-        f_raw.l = src_slot == 0 ? pf_l[0] : (src_slot == 1 ? pf_l[1] : pf_l[2]);
+        f_raw.l = lam[p_col];
         f_raw.g = pf_g;
 #pragma unroll
         for (int d = 0; d < DIM; ++d) f_raw.y[d] = pf_y[d];
