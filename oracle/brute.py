@@ -14,6 +14,12 @@ answer by a different published route, so agreement pins the oracle:
   constraint eliminated.
 * ``lp_coupled`` / ``lp_full_tensor`` — the unregularised problems
   (eq. ot_graph_pairwise and eq. omt_multi_discrete) solved by HiGHS.
+* ``plans_from_scalings`` / ``stopping_sum_from_plans`` — the plans of
+  eq. bi-marginal_B_sol formed as explicit matrices from the scalings
+  ``u = exp(Lam)`` (no log-sum-exp, no message), and the stopping sum of
+  Algorithm tree_local_reg read off their row and column sums.
+* ``sinkhorn_violation_history`` — the marginal violation of textbook Sinkhorn
+  iterates, the stopping sum's value on a single edge with both ends given.
 """
 from __future__ import annotations
 
@@ -349,3 +355,76 @@ def lp_full_tensor(prob: TreeProblem) -> float:
     if res.status != 0:
         raise RuntimeError(res.message)
     return float(res.fun)
+
+
+# ----------------------------------------------------------------------------
+def plans_from_scalings(prob: TreeProblem, lam_flat: np.ndarray) -> List[np.ndarray]:
+    """B_e = diag(u_(a,b) * gamma_a) K_e diag(u_(b,a) * gamma_b) with u = exp(Lam)
+    and K_e = exp(-C_e / eps) (eq. bi-marginal_B_sol), as dense matrices.
+    ``lam_flat`` is in edge order: Lam_(a,b) (n_a values) then Lam_(b,a)."""
+    plans = []
+    o = 0
+    for e in range(prob.n_edges):
+        a, b = int(prob.edges[e][0]), int(prob.edges[e][1])
+        na, nb = int(prob.sizes[a]), int(prob.sizes[b])
+        ua = np.exp(np.asarray(lam_flat[o:o + na], dtype=np.float64)); o += na
+        ub = np.exp(np.asarray(lam_flat[o:o + nb], dtype=np.float64)); o += nb
+        ga = prob.node_marginal(a) if prob.is_fixed[a] else np.ones(na)
+        gb = prob.node_marginal(b) if prob.is_fixed[b] else np.ones(nb)
+        K = np.exp(-_edge_cost(prob, e) / prob.eps)
+        plans.append((ua * ga)[:, None] * K * (ub * gb)[None, :])
+    return plans
+
+
+def plan_marginals(prob: TreeProblem, plans: List[np.ndarray]) -> List[dict]:
+    """For every node j, {k: B_(j,k) 1} (row sums seen from j's side)."""
+    out = [dict() for _ in range(prob.n_nodes)]
+    for e in range(prob.n_edges):
+        a, b = int(prob.edges[e][0]), int(prob.edges[e][1])
+        out[a][b] = plans[e].sum(axis=1)
+        out[b][a] = plans[e].sum(axis=0)
+    return out
+
+
+def stopping_sum_from_plans(prob: TreeProblem, plans: List[np.ndarray], nodes=None) -> Tuple[float, float]:
+    """Stopping sum of Algorithm tree_local_reg over ``nodes`` (default: all):
+    a constrained node adds ||B_(j,k) 1 - mu_j||_1 for each incident edge, a
+    free node adds sum_k ||B_(j,k) 1 - q_bar_j||_1 with q_bar_j the arithmetic
+    mean of its plan marginals (Lemma f_upper_bound_tree).  Returns the sum
+    and its largest single term."""
+    marg = plan_marginals(prob, plans)
+    nodes = range(prob.n_nodes) if nodes is None else nodes
+    terms = []
+    for j in nodes:
+        qs = [marg[j][k] for k in sorted(marg[j])]
+        if prob.is_fixed[j]:
+            mu = prob.node_marginal(j)
+            terms += [float(np.abs(q - mu).sum()) for q in qs]
+        else:
+            qbar = sum(qs) / len(qs)
+            terms += [float(np.abs(q - qbar).sum()) for q in qs]
+    return float(sum(terms)), float(max(terms) if terms else 0.0)
+
+
+def sinkhorn_violation_history(mu: np.ndarray, nu: np.ndarray, C: np.ndarray, eps: float,
+                               steps: int) -> List[float]:
+    """Textbook Sinkhorn on K = exp(-C/eps) started from the column scaling
+    b = nu: after each half-step (rows first) the L1 violation of the marginal
+    that the half-step did not fit, i.e. ||B^T 1 - nu||_1 after a row scaling
+    and ||B 1 - mu||_1 after a column scaling."""
+    K = np.exp(-C / eps)
+    a = np.ones_like(mu)
+    b = nu.copy()
+    out = []
+    for s in range(steps):
+        if s % 2 == 0:
+            with np.errstate(divide="ignore", invalid="ignore"):
+                a = np.where(mu > 0, mu / (K @ b), 0.0)
+            B = a[:, None] * K * b[None, :]
+            out.append(float(np.abs(B.sum(axis=0) - nu).sum()))
+        else:
+            with np.errstate(divide="ignore", invalid="ignore"):
+                b = np.where(nu > 0, nu / (K.T @ a), 0.0)
+            B = a[:, None] * K * b[None, :]
+            out.append(float(np.abs(B.sum(axis=1) - mu).sum()))
+    return out

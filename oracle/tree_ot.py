@@ -42,9 +42,10 @@ Readings where the paper is silent (each is listed in the design notes):
   update and its own term in the stopping sum.
 * The fixed-node rule is used in its general form with ``gamma_k`` inside the
   message (Algorithm form), which also covers edges whose both ends are fixed.
-* Zero marginal entries: ``log 0 = -inf``; the fixed update then takes the
-  limit value ``Lam = -m`` of Theorem "tree_dual_var" instead of
-  ``-inf - (-inf)``.
+* Zero marginal entries: ``log 0 = -inf``; at those entries the fixed update
+  takes the limit value ``Lam = -m_{k->j}`` (the closed form of Theorem
+  "tree_dual_var", u = 1 / (K u')) from the message itself, since
+  ``log q = -inf`` there.
 * Stopping: check-then-update; the test is applied from the second
   half-sweep on (the first state has not been scaled anywhere yet) and the
   state returned is the one whose error passed the test.
@@ -237,18 +238,25 @@ class TreeOracle:
         return e1 + e2, max(m1, m2)
 
     # --------------------------------------------------------------- update
-    def update_node_algorithm(self, j: int, logqs: Dict[int, np.ndarray]) -> Dict[Tuple[int, int], np.ndarray]:
-        """New Lam_(j,k) for all k in N(j) by eq. bipartite_tree_updates1/2."""
+    def update_node_algorithm(self, j: int, logqs: Dict[int, np.ndarray],
+                              msgs: Optional[Dict[int, np.ndarray]] = None) -> Dict[Tuple[int, int], np.ndarray]:
+        """New Lam_(j,k) for all k in N(j) by eq. bipartite_tree_updates1/2.
+
+        ``msgs`` (the messages m_{k->j} behind ``logqs``) is needed only where
+        a constrained node's marginal has zero entries: there log q = -inf
+        carries no information and the update takes its limit value
+        Lam = -m_{k->j} (Lam + log mu - log q = -m wherever mu > 0)."""
         new = {}
         if self.prob.is_fixed[j]:
             # u <- u * mu ./ q   (per incident edge)
+            lg = self.log_gamma[j]
+            zero = ~np.isfinite(lg)
             for k in self.nbrs[j]:
-                lg = self.log_gamma[j]
                 with np.errstate(invalid="ignore"):
                     upd = self.Lam[(j, k)] + lg - logqs[k]
-                # zero-mass entries: the limit value of the closed form
-                m = logqs[k] - self.Lam[(j, k)] - lg
-                upd = np.where(np.isfinite(lg), upd, -m)
+                if np.any(zero):
+                    m = self.message(k, j) if msgs is None else msgs[k]
+                    upd = np.where(zero, -m, upd)
                 new[(j, k)] = upd
         else:
             # q_j^{t+1} = geometric mean of q_(j,k); u <- u * (q_j / |q_j|_1) ./ q_(j,k)
@@ -295,7 +303,7 @@ class TreeOracle:
             return e_sum, e_max, True
         updates = {}
         for j in S:
-            upd = self.update_node_algorithm(j, logqs[j])
+            upd = self.update_node_algorithm(j, logqs[j], msgs[j])
             if check_equivalence:
                 alt = self.update_node_theorem(j, msgs[j])
                 for key in upd:

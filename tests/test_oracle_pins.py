@@ -46,6 +46,24 @@ def test_unit_mass_after_every_half_sweep():
     assert P.mass_lemma(TreeOracle) < 1e-12
 
 
+def test_stopping_sum_matches_dense_plans():
+    # both classes and the class about to be updated, cold state and six half-sweeps
+    assert P.stopping_sum_explicit_plans(TreeOracle) < 1e-12
+
+
+def test_stopping_sum_node_identities():
+    # degree-2 free node: sum_k |q_k - q_bar| = |q_1 - q_2| (arithmetic mean); constrained: |q - mu|
+    assert P.stopping_sum_identities(TreeOracle) < 1e-12
+
+
+def test_stopping_sum_is_textbook_sinkhorn_violation():
+    assert P.stopping_sum_sinkhorn(TreeOracle) < 1e-12
+
+
+def test_zero_mass_marginals():
+    assert P.zero_mass(TreeOracle) < 1e-11
+
+
 def test_logsumexp_special_cases():
     w = np.array([[0.0, -np.inf], [-np.inf, -np.inf], [1000.0, 1000.0]])
     out = logsumexp(w, axis=1)
