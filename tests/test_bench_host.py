@@ -64,3 +64,32 @@ def test_several_gpus_refused_with_a_message():
                        capture_output=True, text=True, timeout=120)
     assert r.returncode == 2
     assert "one GPU" in r.stderr
+
+
+def _gpurun_excluded(rel):
+    """Whether a path (relative to the repo root) matches a .gpurunignore
+    pattern (tar semantics: './x' anchors at the top, other patterns match any
+    path component)."""
+    import fnmatch
+    pats = [ln.strip() for ln in open(os.path.join(ROOT, ".gpurunignore")) if ln.strip() and not ln.startswith("#")]
+    parts = rel.split("/")
+    prefixes = ["./" + "/".join(parts[:i + 1]) for i in range(len(parts))]
+    for pat in pats:
+        if pat.startswith("./"):
+            if any(fnmatch.fnmatch(pr, pat) for pr in prefixes):
+                return True
+        elif any(fnmatch.fnmatch(c, pat) for c in parts):
+            return True
+    return False
+
+
+def test_files_the_gpu_runs_read_are_shipped():
+    """The bench reads its HBM-traffic summaries from profiles/, the GPU tests
+    read the stored references under tests/golden/; none may be left out of
+    the tree copied to the GPU machine."""
+    paths = [os.path.relpath(bench.TRAFFIC_FILE, ROOT)]
+    for d in ("profiles", os.path.join("tests", "golden")):
+        paths += [os.path.join(d, f) for f in os.listdir(os.path.join(ROOT, d))]
+    for rel in paths:
+        assert not _gpurun_excluded(rel), rel
+    assert _gpurun_excluded("_work/probe.py")

@@ -68,6 +68,33 @@ def test_gradient_matches_reference(ctx):
             o += size
 
 
+def test_gradient_matches_reference_at_warm_start_shape(ctx):
+    """The warm-start network's own shape, 8192 -> 512 -> 512 -> 512 -> 8192, at
+    training batch 256: loss and every layer's weight and bias gradient within
+    1e-3 (relative to the layer's largest entry) of the reference on the same
+    BF16-rounded GEMM inputs; the device accumulates over K = 8192 in FP32."""
+    from paper_2406_10849_amd import MLP
+    widths = [8192, 512, 512, 512, 8192]
+    net = MLP(ctx, widths, seed=7)
+    rng = np.random.default_rng(7)
+    p = net.get_params().astype(np.float64)
+    p[:] += rng.normal(0, 0.01, size=p.shape)
+    net.set_params(p.astype(np.float32))
+    p = net.get_params().astype(np.float64)
+    x = rng.normal(size=(256, widths[0])).astype(np.float32)
+    t = rng.normal(size=(256, widths[-1])).astype(np.float32)
+    g = torch.empty(net.n_params, dtype=torch.float32, device="cuda")
+    loss = net.loss_grad(dev(x), dev(t), g)
+    lr_, gr = ref.loss_and_grad(p, widths, x.astype(np.float64), t.astype(np.float64), quantize=True)
+    assert abs(loss - lr_) <= 1e-4 * lr_
+    gg = g.cpu().numpy().astype(np.float64)
+    o = 0
+    for l in range(1, len(widths)):
+        for size in (widths[l] * widths[l - 1], widths[l]):
+            assert rel(gg[o:o + size], gr[o:o + size]) <= 1e-3, (l, size)
+            o += size
+
+
 def test_adam_step(ctx):
     from paper_2406_10849_amd import MLP
     net = MLP(ctx, [16, 8, 24], seed=5)

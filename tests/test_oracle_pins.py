@@ -70,3 +70,21 @@ def test_logsumexp_special_cases():
     assert out[0] == 0.0
     assert out[1] == -np.inf
     assert abs(out[2] - (1000.0 + np.log(2.0))) < 1e-12
+
+
+def test_c_message_oracle_passes_every_pin():
+    """The oracle with its message sums in C (oracle/lse.c) is held to the same
+    pins as the numpy one."""
+    from oracle.fast import FastTreeOracle
+    res = P.all_pins(FastTreeOracle)
+    assert all(res.values()), res
+
+
+def test_c_message_oracle_thread_count_does_not_change_results():
+    from oracle.fast import FastTreeOracle
+    from workloads import make_random_tree
+    p = make_random_tree(n_nodes=14, n_lo=30, n_hi=200, eps=5e-3, dim=2, cfg_id=3, instance=12)
+    a, b = FastTreeOracle(p, threads=1), FastTreeOracle(p, threads=4)
+    a.run_fixed(6)
+    b.run_fixed(6)
+    assert np.array_equal(a.potentials(), b.potentials())
