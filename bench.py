@@ -1,23 +1,30 @@
 #!/usr/bin/env python3
 """Benchmark of the bipartite iterative-scaling hot path on one MI355X.
 
-Workload: the HMM-like chain (32 nodes, n = 1024 points per node on a 1D grid,
-squared-Euclidean cost, eps = 1e-3, every 4th node observed with a 3-component
-Gaussian mixture), solved from cold start until the stopping sum of the
-Bipartite Iterative Scaling algorithm is <= 1e-6, followed by the FP64
-evaluation pass (dual, primal, transport, both-side stopping sum).  One step
-= one such solve + evaluation; inputs are resident in device memory before
-the timed region.
+Headline workload (batched-stars-512): 512 independent barycenter stars, each
+with a free center and 4-16 constrained leaves (Gaussian-mixture marginals),
+n in [128, 2048] points per node on a shared 1D or 2D grid, squared-Euclidean
+cost, eps = 1e-2.  One step = every instance solved from the cold start in the
+same launches (one captured graph per k half-sweeps, per-instance stop) until
+its FP64-judged stopping sum is <= 1e-6, then the FP64 evaluation pass of every
+instance (dual, primal, transport, both-side stopping sum).  Inputs are
+resident in device memory before the timed region.
 
-Metric: edge-iterations/s (an edge-iteration is one edge's message in one
-half-sweep; a half-sweep carries |E| = 31 of them), with the device time to
-reach 1e-6 reported beside it.
+Metric: edge-iterations/s over the whole batch (an edge-iteration is one edge's
+message in one half-sweep), with the device time until the last instance
+reaches 1e-6 beside it, and the same instances solved one by one with their
+own launches ("plain").  Extras: the 32-node chain (n = 1024, eps = 1e-3), the
+256-node random tree (layer-parallel vs per-node launches, explicit-cost
+streaming), the learned warm start.
 
-Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline] [--no-extras]
+       python bench.py --summarize-stats <rocprofv3 kernel_stats.csv>
+       python bench.py --summarize-pmc <rocprofv3 counter_collection.csv>
 """
 from __future__ import annotations
 
 import argparse
+import csv
 import hashlib
 import json
 import os
@@ -45,9 +52,21 @@ def pair_peak_gpairs(dim: int) -> float:
     folded in), one FP64-to-FP32 conversion, one exp2, one FP32 add."""
     cycles_per_64_pairs = dim * CYC_FP64 + CYC_FP64 + CYC_TRANS + CYC_FP32
     return SIMD_CLOCKS_PER_S * 64 / cycles_per_64_pairs / 1e9
+
+
+def weighted_pair_peak(pairs_by_dim: dict) -> float:
+    """Peak (Gpair/s) of a launch mixing support dimensions: the total pairs
+    over the time each dimension's pairs take at its own peak."""
+    tot = sum(pairs_by_dim.values())
+    t = sum(v / pair_peak_gpairs(d) for d, v in pairs_by_dim.items() if v > 0)
+    return tot / t if t > 0 else 0.0
+
+
 # MI355X HBM3E peak, GB/s
 HBM_PEAK_GBS = 8000.0
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "k_node_chain32_traffic.txt")
+PROFILES = os.path.join(ROOT, "profiles")
+TRAFFIC_FILE = os.path.join(PROFILES, "k_node_batched512_traffic.txt")
+CHAIN_TRAFFIC_FILE = os.path.join(PROFILES, "k_node_chain32_traffic.txt")
 KERNEL_SRC = os.path.join(ROOT, "paper_2406_10849_amd", "csrc", "gmot_kernels.hip")
 
 
@@ -71,14 +90,16 @@ def kernel_sha() -> str:
     return hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest()[:16]
 
 
-def measured_traffic(shape):
-    """HBM bytes per node-kernel launch from the committed rocprofv3 PMC
-    summary, valid only for the kernel source it was taken on and for the node
-    shape (waves per block, rows per lane, lane groups) the bench tuned."""
-    if not os.path.exists(TRAFFIC_FILE):
+def measured_traffic(shape, path=None):
+    """HBM bytes per node-kernel launch (per node stage for a batch mixing
+    support dimensions) from a committed rocprofv3 PMC summary, valid only for
+    the kernel source it was taken on and for the node shape (waves per block,
+    rows per lane, lane groups) the bench tuned."""
+    path = TRAFFIC_FILE if path is None else path
+    if not os.path.exists(path):
         return None
-    sha, want = None, "shape %d,%d,%d:" % shape
-    for line in open(TRAFFIC_FILE):
+    sha, want = None, "shape %d,%d,%d:" % tuple(shape)
+    for line in open(path):
         if line.startswith("kernel_sha256_16:"):
             sha = line.split(":", 1)[1].strip()
         elif line.startswith(want) and sha == kernel_sha():
@@ -91,58 +112,248 @@ def measured_traffic(shape):
     return None
 
 
-def cpu_baseline(prob, seconds: float) -> dict:
-    """The FP64 oracle as it stands, on the host, for a bounded number of
-    half-sweeps of the same workload."""
-    from oracle import TreeOracle
-    o = TreeOracle(prob)
-    o.tstep()  # first half-sweep also fills the oracle's cost cache
-    steps = 0
-    t0 = time.perf_counter()
-    while True:
-        o.tstep()
-        steps += 1
-        el = time.perf_counter() - t0
+# ---------------------------------------------------------------------------
+# rocprofv3 output reductions (used to write the summaries under profiles/)
+# ---------------------------------------------------------------------------
+def summarize_stats(path: str, top: int = 40) -> str:
+    """Markdown table of a rocprofv3 --stats kernel summary (CSV)."""
+    rows = list(csv.DictReader(open(path)))
+    out = ["| kernel | calls | total ns | average ns | % | min ns | max ns |", "|---|---|---|---|---|---|---|"]
+    for r in rows[:top]:
+        out.append("| `%s` | %s | %s | %.0f | %.2f | %s | %s |" % (
+            r["Name"], r["Calls"], r["TotalDurationNs"], float(r["AverageNs"]), float(r["Percentage"]),
+            r["MinNs"], r["MaxNs"]))
+    return "\n".join(out)
+
+
+def summarize_pmc(path: str) -> str:
+    """Per kernel name: dispatches, the mean counter value per dispatch and the
+    largest single dispatch (rocprofv3 --pmc counter_collection CSV, one
+    counter per run; with --calib-copy the largest copyBuffer dispatch is the
+    1 GiB calibration copy)."""
+    acc = {}
+    for r in csv.DictReader(open(path)):
+        key = (r["Kernel_Name"], r["Counter_Name"])
+        a = acc.setdefault(key, [0.0, set(), 0.0])
+        v = float(r["Counter_Value"])
+        a[0] += v
+        a[1].add(r.get("Dispatch_Id", len(a[1])))
+        a[2] = max(a[2], v)
+    out = ["| kernel | counter | dispatches | mean per dispatch | max dispatch |", "|---|---|---|---|---|"]
+    for (k, c), (tot, ids, mx) in sorted(acc.items(), key=lambda kv: -kv[1][0]):
+        out.append("| `%s` | %s | %d | %.1f | %.1f |" % (k, c, len(ids), tot / max(len(ids), 1), mx))
+    return "\n".join(out)
+
+
+# ---------------------------------------------------------------------------
+# CPU baseline: the FP64 oracle as it stands (message sums in plain C)
+# ---------------------------------------------------------------------------
+def cpu_baseline(probs, seconds: float, tol: float) -> dict:
+    """Sampled instances of the same batch (seeded choice), each solved by the
+    oracle from the cold start to the same stopping sum on every host thread,
+    until about ``seconds`` of work; then one instance for a fixed number of
+    half-sweeps on one thread."""
+    from oracle.fast import FastTreeOracle, max_threads
+    rng = np.random.default_rng(7)
+    order = [int(i) for i in rng.permutation(len(probs))]
+    threads = max_threads()
+    edges, el, sample = 0, 0.0, []
+    for i in order:
+        o = FastTreeOracle(probs[i], threads=0)
+        t0 = time.perf_counter()
+        r = o.solve(tol=tol, max_steps=100000)
+        dt = time.perf_counter() - t0
+        edges += probs[i].n_edges * r["t"]
+        el += dt
+        sample.append({"instance": i, "edges": probs[i].n_edges, "n": int(probs[i].sizes[0]), "dim": probs[i].dim,
+                       "half_sweeps": r["t"], "status": r["status"], "time_to_tol_s": dt})
         if el >= seconds:
             break
-    rate = prob.n_edges * steps / el
-    return {"value": rate, "unit": "edge-iterations/s", "cores": 1, "kind": "oracle",
-            "sample": f"{steps} half-sweeps (after one warm-up half-sweep) of the same 32-node chain, "
-                      f"FP64 numpy, single thread, {el:.1f} s"}
+    p1 = probs[order[0]]
+    o = FastTreeOracle(p1, threads=1)
+    o.tstep()
+    steps = 0
+    t0 = time.perf_counter()
+    while steps < 2 or time.perf_counter() - t0 < min(seconds / 2, 10.0):
+        o.tstep()
+        steps += 1
+    d1 = time.perf_counter() - t0
+    return {"value": edges / el, "unit": "edge-iterations/s", "cores": threads, "kind": "oracle",
+            "sample": f"{len(sample)} of the 512 stars (seeded choice), each solved from the cold start to a "
+                      f"stopping sum <= {tol:g} by the FP64 oracle (message sums in C over {threads} threads), "
+                      f"{el:.1f} s in total",
+            "instances": sample,
+            "one_core": {"value": p1.n_edges * steps / d1, "unit": "edge-iterations/s", "cores": 1,
+                         "sample": f"{steps} half-sweeps of instance {order[0]} on one thread, {d1:.1f} s"}}
 
 
-def bench_batched(ctx, tol: float, count: int) -> dict:
-    """Uneven barycenter stars (4-16 leaves, n in [128, 2048], 1D/2D grids,
-    eps = 1e-2): all instances advanced by the same launches of one captured
-    graph, against each instance solved on its own (its own plan, graph and
-    launches), both to the same stopping sum."""
+def cpu_baseline_chain(prob, seconds: float) -> dict:
+    """The chain's half-sweeps on the host: every thread, then one thread."""
+    from oracle.fast import FastTreeOracle, max_threads
+    out = {}
+    for th in (0, 1):
+        o = FastTreeOracle(prob, threads=th)
+        o.tstep()
+        steps = 0
+        t0 = time.perf_counter()
+        while steps < 2 or time.perf_counter() - t0 < seconds:
+            o.tstep()
+            steps += 1
+        dt = time.perf_counter() - t0
+        out["all_cores" if th == 0 else "one_core"] = {
+            "edge_iterations_per_s": prob.n_edges * steps / dt, "cores": max_threads() if th == 0 else 1,
+            "half_sweeps": steps, "s": dt}
+    return out
+
+
+# ---------------------------------------------------------------------------
+# headline: the 512 stars in one batch
+# ---------------------------------------------------------------------------
+def bench_headline(ctx, args, sync) -> tuple:
     from workloads import make_batched_stars
-    from paper_2406_10849_amd import Batch, Problem
-    probs = make_batched_stars(count=count)
+    from paper_2406_10849_amd import Batch, Problem, last_tiles
+    probs = make_batched_stars(count=args.batched_count)
     gps = [Problem(ctx, p) for p in probs]
     b = Batch(ctx, gps)
+    log("512 stars built; tuning tiles")
     tuned = b.autotune()
-    b.solve(tol=tol, max_steps=200000)              # warm-up (graph capture)
+    log(f"autotune: {tuned}; tiles: {last_tiles()}")
+
+    def step(timing=False):
+        rs = b.solve(tol=args.tol, max_steps=200000, check_every=args.check_every, timing=timing)
+        evs = [g.evaluate() for g in gps]
+        return rs, evs
+
+    for _ in range(max(args.warmup, 0)):
+        step()
+    sync()
+    runs = []
     t0 = time.perf_counter()
-    rb = b.solve(tol=tol, max_steps=200000)
-    t_batch = time.perf_counter() - t0
-    assert all(r["status"] == "converged" for r in rb), "batched solve did not converge"
-    for g in gps:                                   # per-instance plans and graphs built outside the timing
-        g.solve(tol=tol, max_steps=200000)
-    t0 = time.perf_counter()
-    rs = [g.solve(tol=tol, max_steps=200000) for g in gps]
-    t_single = time.perf_counter() - t0
-    assert all(r["status"] == "converged" for r in rs), "per-instance solve did not converge"
-    pairs = sum(p.pairs_per_tstep() * r["t"] for p, r in zip(probs, rb))
-    edges = sum(p.n_edges * r["t"] for p, r in zip(probs, rb))
-    out = {"instances": count, "edges": sum(p.n_edges for p in probs),
-           "pairs_per_half_sweep": sum(p.pairs_per_tstep() for p in probs),
-           "batched_s": t_batch, "per_instance_s": t_single, "speedup": t_single / t_batch,
-           "batched_edge_iterations_per_s": edges / t_batch, "batched_pairs_per_s": pairs / t_batch,
-           "max_half_sweeps": max(r["t"] for r in rb), "tiles": tuned}
+    for _ in range(args.steps):
+        runs.append(step())
+    sync()
+    elapsed = time.perf_counter() - t0
+    for k, (rs, evs) in enumerate(runs):
+        for i, (r, ev) in enumerate(zip(rs, evs)):
+            if r["status"] != "converged" or ev["err_sum"] > args.tol:
+                raise RuntimeError(f"step {k} instance {i}: not converged: {r} {ev}")
+    edges = [p.n_edges for p in probs]
+    edge_iters = sum(sum(e * r["t"] for e, r in zip(edges, rs)) for rs, _ in runs)
+    ttt = statistics.median(max(r["seconds"] for r in rs) for rs, _ in runs)
+    # the same step with HIP events around every node stage (kernel durations)
+    b.stats(reset=True)
+    rs_t, _ = step(timing=True)
+    st = b.stats()
+    pairs_by_dim = {}
+    for p, r in zip(probs, rs_t):
+        pairs_by_dim[p.dim] = pairs_by_dim.get(p.dim, 0.0) + float(p.pairs_per_tstep()) * r["t"]
+    peak = weighted_pair_peak(pairs_by_dim)
+    avg_ms = st["msg_ms"] / max(st["msg_launches"], 1)
+    pairs_per_stage = st["msg_pairs"] / max(st["msg_launches"], 1)
+    achieved = pairs_per_stage / (avg_ms / 1e3) / 1e9 if avg_ms > 0 else 0.0
+    shape = (tuned["waves_per_block"], tuned["rows_per_lane"], tuned["lane_groups"])
+    traffic = measured_traffic(shape)
+    rs0 = runs[-1][0]
+    hs = [r["t"] for r in rs0]
+    out = {
+        "value": edge_iters / elapsed,
+        "ms_per_step": 1e3 * elapsed / args.steps,
+        "config": {"workload": "batched-stars-512", "instances": len(probs), "edges": int(sum(edges)),
+                   "leaves": "4-16 per star", "n": "128-2048 per instance", "dims": "1 or 2 per instance",
+                   "eps": probs[0].eps, "tol": args.tol, "cost": "squared-euclidean, on the fly",
+                   "marginals": "2-component Gaussian mixtures", "schedule": "bipartite, all instances per launch",
+                   "check_every": args.check_every,
+                   "pairs_per_half_sweep": int(sum(p.pairs_per_tstep() for p in probs))},
+        "time_to_1e-6_s": ttt,
+        "half_sweeps_to_1e-6": {"min": int(min(hs)), "median": float(statistics.median(hs)), "max": int(max(hs))},
+        "tiles": dict(tuned, **last_tiles()),
+        "pairs_per_s": sum(sum(float(p.pairs_per_tstep()) * r["t"] for p, r in zip(probs, rs)) for rs, _ in runs)
+                       / elapsed,
+        "roofline": {"bound": "alu", "achieved": achieved, "peak": peak, "unit": "Gpair/s",
+                     "frac": achieved / peak if peak > 0 else 0.0, "traffic": traffic,
+                     "kernel": "k_node (node stage: one launch per support dimension)",
+                     "avg_stage_ms": avg_ms, "pairs_per_stage": pairs_per_stage,
+                     "stages_timed": st["msg_launches"],
+                     "pairs_by_dim": {str(d): v for d, v in sorted(pairs_by_dim.items())},
+                     "peak_by_dim": {str(d): pair_peak_gpairs(d) for d in sorted(pairs_by_dim)},
+                     "half_sweep_avg_ms": st["sweep_ms"] / max(st["msg_launches"], 1)},
+        "final": {"err_sum_fp64_max": max(ev["err_sum"] for ev in runs[-1][1]),
+                  "dual_sum": float(sum(ev["dual"] for ev in runs[-1][1]))},
+    }
+    if not args.no_extras:
+        # plain: each instance on its own (its own plan, graph and launches)
+        for g in gps:                                   # plans and graphs built outside the timing
+            g.solve(tol=args.tol, max_steps=200000, check_every=args.check_every)
+        sync()
+        t0 = time.perf_counter()
+        rp = [g.solve(tol=args.tol, max_steps=200000, check_every=args.check_every) for g in gps]
+        sync()
+        t_plain = time.perf_counter() - t0
+        assert all(r["status"] == "converged" for r in rp), "per-instance solve did not converge"
+        t_batched = elapsed / args.steps
+        out["plain"] = {"s": t_plain, "edge_iterations_per_s": sum(e * r["t"] for e, r in zip(edges, rp)) / t_plain,
+                        "batched_step_s": t_batched, "speedup_batched_vs_plain": t_plain / t_batched}
     b.close()
     for g in gps:
         g.close()
+    return out, probs
+
+
+# ---------------------------------------------------------------------------
+# extras
+# ---------------------------------------------------------------------------
+def bench_chain(ctx, args, sync) -> dict:
+    """The 32-node chain (n = 1024 on a 1D grid, eps = 1e-3, every 4th node
+    observed): solves to the FP64-judged stopping sum, the node launch's
+    roofline, and the rounding pass of the converged state."""
+    from workloads import make_config
+    from paper_2406_10849_amd import Problem, last_tiles
+    prob = make_config(2)
+    g = Problem(ctx, prob)
+    tuned = g.autotune()
+    for _ in range(2):
+        g.solve(tol=args.tol, max_steps=200000, check_every=args.check_every)
+    steps = 5
+    sync()
+    t0 = time.perf_counter()
+    rs = []
+    for _ in range(steps):
+        rs.append(g.solve(tol=args.tol, max_steps=200000, check_every=args.check_every))
+        ev = g.evaluate()
+    sync()
+    el = time.perf_counter() - t0
+    assert all(r["status"] == "converged" for r in rs) and ev["err_sum"] <= args.tol
+    g.stats(reset=True)
+    g.solve(tol=args.tol, max_steps=200000, check_every=args.check_every, timing=True)
+    st = g.stats()
+    avg_ms = st["msg_ms"] / max(st["msg_launches"], 1)
+    ppl = st["msg_pairs"] / max(st["msg_launches"], 1)
+    ach = ppl / (avg_ms / 1e3) / 1e9 if avg_ms > 0 else 0.0
+    peak = pair_peak_gpairs(1)
+    shape = (tuned["waves_per_block"], tuned["rows_per_lane"], tuned["lane_groups"])
+    out = {"workload": "chain-hmm-32node-n1024", "edges": prob.n_edges,
+           "edge_iterations_per_s": prob.n_edges * sum(r["t"] for r in rs) / el,
+           "time_to_1e-6_s": statistics.median(r["seconds"] for r in rs),
+           "half_sweeps_to_1e-6": int(statistics.median(r["t"] for r in rs)), "tiles": dict(tuned, **last_tiles()),
+           "dual": ev["dual"], "err_sum_fp64": ev["err_sum"],
+           "roofline": {"bound": "alu", "achieved": ach, "peak": peak, "unit": "Gpair/s", "frac": ach / peak,
+                        "traffic": measured_traffic(shape, CHAIN_TRAFFIC_FILE), "kernel": "k_node",
+                        "avg_launch_ms": avg_ms, "pairs_per_launch": ppl, "launches_timed": st["msg_launches"]}}
+    rt = []
+    for _ in range(5):
+        sync()
+        t0 = time.perf_counter()
+        rr = g.round()
+        sync()
+        rt.append(time.perf_counter() - t0)
+    round_ms = 1e3 * statistics.median(rt)
+    pairs = prob.pairs_per_tstep()
+    out["rounding"] = {"wall_ms": round_ms, "pair_evaluations": 4 * pairs, "pairs_per_s": 4 * pairs / (round_ms / 1e3),
+                       "transport_rounded": rr["transport"], "transport_unrounded": ev["transport"],
+                       "err_side": rr["err_side"], "lemma_round_bound": 2 * rr["c_inf"] * rr["err_side"]}
+    if not args.no_cpu_baseline:
+        out["cpu_oracle"] = cpu_baseline_chain(prob, 5.0)
+    g.close()
     return out
 
 
@@ -243,132 +454,51 @@ def main() -> int:
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--tol", type=float, default=1e-6)
     ap.add_argument("--check-every", type=int, default=16)
-    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--cpu-seconds", type=float, default=20.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--calib-copy", action="store_true",
                     help="also run one 1 GiB device copy (PMC calibration for HBM byte counters)")
-    ap.add_argument("--no-extras", action="store_true", help="skip the batched and warm-start comparisons")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="skip the plain comparison, the chain, the tree and the warm start")
     ap.add_argument("--batched-count", type=int, default=512)
     ap.add_argument("--tree-half-sweeps", type=int, default=40)
     ap.add_argument("--warm-train", type=int, default=20000)
     ap.add_argument("--warm-test", type=int, default=1024)
     ap.add_argument("--warm-epochs", type=int, default=30)
+    ap.add_argument("--summarize-stats", metavar="CSV", help="print a rocprofv3 kernel_stats CSV as markdown")
+    ap.add_argument("--summarize-pmc", metavar="CSV", help="print per-dispatch means of a rocprofv3 counter CSV")
     args = ap.parse_args()
+    if args.summarize_stats:
+        print(summarize_stats(args.summarize_stats))
+        return 0
+    if args.summarize_pmc:
+        print(summarize_pmc(args.summarize_pmc))
+        return 0
     if args.gpus != 1:
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported (the solver runs on a "
               f"single device; sharding over several GPUs is not built)", file=sys.stderr)
         return 2
 
-    from workloads import make_config
-    from paper_2406_10849_amd import Context, Problem, last_tiles
-
-    log(f"host: {host_info()}")
-    prob = make_config(2)
-    n_edges = prob.n_edges
-    pairs_per_half_sweep = prob.pairs_per_tstep()
-    ctx = Context(0)
-    g = Problem(ctx, prob)
-    log("workload built; tuning tiles")
-    tuned = g.autotune()
-    log(f"autotune: {tuned}; tiles: {last_tiles()}")
-    for _ in range(max(args.warmup, 0)):
-        g.solve(tol=args.tol, max_steps=200000, check_every=args.check_every)
-        g.evaluate()
-        g.solve(tol=args.tol, max_steps=200000, check_every=args.check_every, timing=True)
-    g.stats(reset=True)
-
+    from paper_2406_10849_amd import Context
     try:
         import torch
         sync = torch.cuda.synchronize if torch.cuda.is_available() else (lambda: None)
     except Exception:
         sync = lambda: None  # noqa: E731
 
-    def timed_region(timing: bool):
-        sync()
-        runs = []
-        t0 = time.perf_counter()
-        for _ in range(args.steps):
-            r = g.solve(tol=args.tol, max_steps=200000, check_every=args.check_every, timing=timing)
-            ev = g.evaluate()
-            runs.append((r, ev))
-        sync()
-        return runs, time.perf_counter() - t0
-
-    # region 1: the product configuration (graph replay) -> value
-    runs, elapsed = timed_region(False)
-    # region 2: the same steps with HIP events around every stage -> kernel durations
-    g.stats(reset=True)
-    runs_t, elapsed_t = timed_region(True)
-    st = g.stats()
-    for i, (r, ev) in enumerate(runs + runs_t):
-        if r["status"] != "converged" or ev["err_sum"] > args.tol:
-            log(f"step {i}: not converged: {r} {ev}")
-            return 1
-    half_sweeps = [r["t"] for r, _ in runs]      # half-sweeps computed, including the one that passed the test
-    edge_iters = n_edges * sum(half_sweeps)
-    value = edge_iters / elapsed
-    ttt = statistics.median(r["seconds"] for r, _ in runs)
-    last_r, last_ev = runs[-1]
-    log(f"solve: {last_r}")
-    log(f"eval: {last_ev}")
-    log(f"stats: {st}")
-
-    D = prob.dim
-    peak = pair_peak_gpairs(D)
-    avg_ms = st["msg_ms"] / max(st["msg_launches"], 1)
-    pairs_per_launch = st["msg_pairs"] / max(st["msg_launches"], 1)
-    achieved = pairs_per_launch / (avg_ms / 1e3) / 1e9 if avg_ms > 0 else 0.0
-    traffic = measured_traffic((tuned["waves_per_block"], tuned["rows_per_lane"], tuned["lane_groups"]))
-    out = {
-        "metric": METRIC,
-        "value": value,
-        "unit": "edge-iterations/s",
-        "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
-        "ms_per_step": 1e3 * elapsed / args.steps,
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": "f64+f32exp",
-        "data": "synthetic",
-        "config": {"workload": "chain-hmm-32node-n1024", "nodes": prob.n_nodes, "edges": n_edges,
-                   "n": int(prob.sizes[0]), "dim": D, "eps": prob.eps, "tol": args.tol,
-                   "cost": "squared-euclidean, on the fly", "observed": "every 4th node, 3-comp GM",
-                   "schedule": "bipartite (layer-parallel)", "check_every": args.check_every},
-        "time_to_1e-6_s": ttt,
-        "half_sweeps_to_1e-6": int(statistics.median(half_sweeps)),
-        "value_event_timed_region": n_edges * sum(r["t"] for r, _ in runs_t) / elapsed_t,
-        "tiles": dict(tuned, **last_tiles()),
-        "pairs_per_s": pairs_per_half_sweep * sum(half_sweeps) / elapsed,
-        "final": {"err_sum_fp64": last_ev["err_sum"], "err_max_fp64": last_ev["err_max"],
-                  "dual": last_ev["dual"], "primal": last_ev["primal"], "transport": last_ev["transport"]},
-        "roofline": {"bound": "alu", "achieved": achieved, "peak": peak, "unit": "Gpair/s",
-                     "frac": achieved / peak, "traffic": traffic,
-                     "kernel": "k_node", "avg_launch_ms": avg_ms, "pairs_per_launch": pairs_per_launch,
-                     "launches_timed": st["msg_launches"],
-                     "half_sweep_avg_ms": st["sweep_ms"] / max(st["msg_launches"], 1)},
-    }
-    # rounding of the converged state onto the constraint set (Algorithm round):
-    # four FP64 row passes over recomputed plan entries (row sums of both
-    # orientations, column scaling, final pass), outside the timed region
-    rt = []
-    for _ in range(5):
-        sync()
-        t0 = time.perf_counter()
-        rr = g.round()
-        sync()
-        rt.append(time.perf_counter() - t0)
-    round_ms = 1e3 * statistics.median(rt)
-    out["rounding"] = {"wall_ms": round_ms, "pair_evaluations": 4 * pairs_per_half_sweep,
-                       "pairs_per_s": 4 * pairs_per_half_sweep / (round_ms / 1e3),
-                       "transport_rounded": rr["transport"], "transport_unrounded": last_ev["transport"],
-                       "err_side": rr["err_side"], "lemma_round_bound": 2 * rr["c_inf"] * rr["err_side"]}
-    log(f"rounding: {out['rounding']}")
+    log(f"host: {host_info()}")
+    ctx = Context(0)
+    head, probs = bench_headline(ctx, args, sync)
+    out = {"metric": METRIC, "value": head.pop("value"), "unit": "edge-iterations/s", "n_gpus": 1,
+           "steps": args.steps, "warmup": args.warmup, "ms_per_step": head.pop("ms_per_step"),
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64+f32exp",
+           "data": "synthetic"}
+    out.update(head)
+    log(f"headline: value {out['value']:.4g} edge-iterations/s, roofline {out['roofline']}")
     if not args.no_extras:
-        log("batched stars: one graph for all instances vs per-instance launches")
-        out["batched"] = bench_batched(ctx, args.tol, args.batched_count)
-        log(f"batched: {out['batched']}")
+        log("chain: time to 1e-6, node launch roofline, rounding")
+        out["chain"] = bench_chain(ctx, args, sync)
+        log(f"chain: {out['chain']}")
         log("random tree: layer-parallel vs plain schedule, explicit-cost streaming")
         out["tree"] = bench_tree(ctx, args.tol, args.tree_half_sweeps)
         log(f"tree: {out['tree']}")
@@ -377,7 +507,8 @@ def main() -> int:
         log(f"warm start: {out['warm_start']}")
     if not args.no_cpu_baseline:
         log("timing the FP64 oracle on the host")
-        out["cpu_baseline"] = cpu_baseline(prob, args.cpu_seconds)
+        out["cpu_baseline"] = cpu_baseline(probs, args.cpu_seconds, args.tol)
+        log(f"cpu baseline: {out['cpu_baseline']}")
     if args.calib_copy:
         import torch
         x = torch.empty(1 << 28, dtype=torch.float32, device="cuda")

@@ -23,14 +23,27 @@
 #include <omp.h>
 #endif
 
+/* Threads for one call: `threads` if positive, else every thread the OpenMP
+ * runtime offers (OMP_NUM_THREADS or the processor count).  Passed as a
+ * num_threads clause, so no call changes the default of later calls. */
+static int team_size(int threads) {
+#ifdef _OPENMP
+  return threads > 0 ? threads : omp_get_max_threads();
+#else
+  (void)threads;
+  return 1;
+#endif
+}
+
 /* Squared-Euclidean cost C(x, y) = sum_d (xs[x*dim+d] - ys[y*dim+d])^2.
  * xs: [n_dst * dim], ys: [n_src * dim], w: [n_src], out: [n_dst].
- * threads <= 0: the OpenMP default. */
+ * threads <= 0: every available thread. */
 void oracle_message_sqeuclid(const double* xs, const double* ys, const double* w, int64_t n_dst, int64_t n_src,
                              int dim, double eps, double* out, int threads) {
+  const int nt = team_size(threads);
+  (void)nt;
 #ifdef _OPENMP
-  if (threads > 0) omp_set_num_threads(threads);
-#pragma omp parallel for schedule(dynamic, 16)
+#pragma omp parallel for schedule(dynamic, 16) num_threads(nt)
 #endif
   for (int64_t x = 0; x < n_dst; ++x) {
     const double* px = xs + x * dim;
@@ -66,9 +79,10 @@ void oracle_message_sqeuclid(const double* xs, const double* ys, const double* w
  * rows are the matrix rows), 1: C(x, y) = cost[y * n_dst + x]. */
 void oracle_message_explicit(const float* cost, int transposed, const double* w, int64_t n_dst, int64_t n_src,
                              double eps, double* out, int threads) {
+  const int nt = team_size(threads);
+  (void)nt;
 #ifdef _OPENMP
-  if (threads > 0) omp_set_num_threads(threads);
-#pragma omp parallel for schedule(dynamic, 16)
+#pragma omp parallel for schedule(dynamic, 16) num_threads(nt)
 #endif
   for (int64_t x = 0; x < n_dst; ++x) {
     double mx = -INFINITY;

@@ -49,14 +49,42 @@ def test_traffic_absent_or_malformed(tmp_path, monkeypatch):
     assert bench.measured_traffic((8, 1, 1)) is None
 
 
-def test_committed_traffic_file_lists_the_tuned_shapes():
+def test_committed_traffic_files_are_well_formed():
     # every line the bench may report carries both byte counts
-    text = open(bench.TRAFFIC_FILE).read().splitlines()
-    assert text[0].startswith("kernel_sha256_16: ")
-    shapes = [ln for ln in text if ln.startswith("shape ")]
-    assert any(ln.startswith("shape 8,1,1:") for ln in shapes)
-    for ln in shapes:
-        assert "fetch_bytes_per_launch" in ln and "write_bytes_per_launch" in ln
+    import glob
+    files = glob.glob(os.path.join(bench.PROFILES, "k_node_*_traffic.txt"))
+    assert files
+    for path in files:
+        text = open(path).read().splitlines()
+        assert text[0].startswith("kernel_sha256_16: ")
+        shapes = [ln for ln in text if ln.startswith("shape ")]
+        assert shapes
+        for ln in shapes:
+            assert "fetch_bytes_per_launch" in ln and "write_bytes_per_launch" in ln
+
+
+def test_weighted_peak_between_the_dimension_peaks():
+    p1, p2 = bench.pair_peak_gpairs(1), bench.pair_peak_gpairs(2)
+    assert p1 > p2
+    w = bench.weighted_pair_peak({1: 3.0e9, 2: 1.0e9})
+    assert p2 < w < p1
+    # time at peak adds up: 4e9 pairs at w take as long as each part at its own peak
+    assert abs(4.0e9 / w - (3.0e9 / p1 + 1.0e9 / p2)) < 1e-12 * (4.0e9 / w)
+    assert bench.weighted_pair_peak({1: 5.0}) == pytest.approx(p1)
+
+
+def test_rocprof_summaries(tmp_path):
+    st = tmp_path / "k_stats.csv"
+    st.write_text("Name,Calls,TotalDurationNs,AverageNs,Percentage,MinNs,MaxNs,StdDev\n"
+                  "k_a,4,400,100.0,80.0,90,110,1\nk_b,1,100,100.0,20.0,100,100,0\n")
+    md = bench.summarize_stats(str(st))
+    assert "| `k_a` | 4 | 400 | 100 | 80.00 | 90 | 110 |" in md
+    pm = tmp_path / "pmc.csv"
+    pm.write_text("Dispatch_Id,Kernel_Name,Counter_Name,Counter_Value\n"
+                  "1,k_a,FETCH_SIZE,10\n2,k_a,FETCH_SIZE,30\n3,copy,FETCH_SIZE,5\n")
+    md = bench.summarize_pmc(str(pm))
+    assert "| `k_a` | FETCH_SIZE | 2 | 20.0 | 30.0 |" in md
+    assert "| `copy` | FETCH_SIZE | 1 | 5.0 | 5.0 |" in md
 
 
 def test_several_gpus_refused_with_a_message():

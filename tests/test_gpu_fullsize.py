@@ -45,16 +45,34 @@ def test_random_tree_256_nodes_2d_converges(ctx):
 
 
 def test_batched_512_stars_sampled(ctx):
-    """512 uneven stars in one batch; 8 sampled instances re-measured."""
+    """512 uneven stars in one batch, the benchmark's launch configuration;
+    8 sampled instances re-measured by the oracle, and the 12 instances of
+    tests/golden/batched_stars_sample_converged.json (oracle only, stopping
+    sum <= 1e-10, make_batched_golden.py) compared with their converged dual:
+    both duals lie within 2 C_inf E of the optimum (Lemma f_upper_bound_tree),
+    so they agree to 1e-6 of the scale and to 2 C_inf (E_gpu + E_ref)."""
+    import json
+    import os
     from paper_2406_10849_amd import Batch, Problem
     probs = make_batched_stars(count=512)
     gps = [Problem(ctx, p) for p in probs]
     b = Batch(ctx, gps)
-    rs = b.solve(tol=1e-6, max_steps=200000)
+    b.autotune()
+    rs = b.solve(tol=1e-6, max_steps=200000, check_every=16)
     assert all(r["status"] == "converged" for r in rs)
     rng = np.random.default_rng(0)
     for i in rng.choice(len(probs), size=8, replace=False):
         check_state(gps[i], probs[i], 1e-6)
+    ref = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "batched_stars_sample_converged.json")))
+    assert len(ref["instances"]) == 12
+    for rec in ref["instances"]:
+        i = rec["index"]
+        assert probs[i].name == rec["name"]
+        ev = gps[i].evaluate()
+        assert ev["err_sum"] <= 1e-6
+        assert abs(ev["dual"] - rec["dual"]) <= 1e-6 * rec["scale"], (i, ev["dual"], rec["dual"])
+        assert abs(ev["dual"] - rec["dual"]) <= 2 * rec["c_inf"] * (ev["err_sum"] + rec["err_sum"]), i
+        assert abs(ev["primal"] - rec["primal"]) <= 3 * rec["c_inf"] * (ev["err_sum"] + rec["err_sum"]), i
 
 
 def test_chain_dual_matches_converged_reference():
