@@ -270,6 +270,19 @@ int  gmot_mlp_set_params(gmot_mlp* m, const float* in);
 /* Device buffers, row-major FP32: x [batch x widths[0]], y [batch x widths[n]];
  * batch must be a positive multiple of 8.  Stream-ordered on the context. */
 int  gmot_mlp_forward_dev(gmot_mlp* m, const float* x_dev, int32_t batch, float* y_dev);
+/* The same forward pass with no allocation, for callers that cannot allocate
+ * device memory (code under HIP graph capture, tight serving loops, harnesses
+ * that forbid hipMalloc).  The activations live in a static device workspace
+ * of 8 MiB per device (held until the process ends) instead of the network's
+ * own buffers: 2 * batch * widths[0] bytes for the BF16 input, then
+ * 6 * batch * widths[l] bytes per hidden layer, each part aligned to 256
+ * bytes; a batch that does not fit returns GMOT_EINVAL (the message gives the
+ * largest batch that fits).  Nothing in it needs clearing: every part is
+ * written before it is read.  Results equal gmot_mlp_forward_dev's.  All calls
+ * on one device share the workspace: calls ordered on one stream are safe,
+ * calls that overlap on one device (other streams, other contexts, other
+ * threads) race.  Stream-ordered on the context stream, no synchronisation. */
+int  gmot_mlp_forward_static(gmot_mlp* m, const float* x_dev, int32_t batch, float* y_dev);
 /* Mean-squared-error loss sum (y - t)^2 / (batch * widths[n]) (host, after a
  * sync; may be NULL) and its FP32 parameter gradient (device, parameter layout;
  * may be NULL) for targets t_dev [batch x widths[n]]. */

@@ -314,6 +314,11 @@ class MLP:
     def forward(self, x, y) -> None:
         _check(self._lib.gmot_mlp_forward_dev(self._h, _dptr(x), int(x.shape[0]), _dptr(y)), "gmot_mlp_forward_dev")
 
+    def forward_static(self, x, y) -> None:
+        """gmot_mlp_forward_static: the forward pass with no allocation (static workspace)."""
+        _check(self._lib.gmot_mlp_forward_static(self._h, _dptr(x), int(x.shape[0]), _dptr(y)),
+               "gmot_mlp_forward_static")
+
     def loss_grad(self, x, t, grad=None) -> float:
         loss = C.c_double()
         g = _dptr(grad) if grad is not None else None

@@ -126,6 +126,7 @@ SIGNATURES = {
     "gmot_mlp_get_params": (C.c_int, [VP, C.POINTER(C.c_float)]),
     "gmot_mlp_set_params": (C.c_int, [VP, C.POINTER(C.c_float)]),
     "gmot_mlp_forward_dev": (C.c_int, [VP, VP, C.c_int32, VP]),
+    "gmot_mlp_forward_static": (C.c_int, [VP, VP, C.c_int32, VP]),
     "gmot_mlp_loss_grad_dev": (C.c_int, [VP, VP, VP, C.c_int32, DP, VP]),
     "gmot_mlp_adam_step": (C.c_int, [VP, C.c_float, C.c_float, C.c_float, C.c_float]),
     "gmot_mlp_train_step_dev": (C.c_int, [VP, VP, VP, C.c_int32, C.c_float, DP]),

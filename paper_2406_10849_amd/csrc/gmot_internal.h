@@ -245,6 +245,9 @@ struct gmot_ctx {
   void* scratch = nullptr;                         // small tables of the warm-start calls
   size_t scratch_size = 0;
 };
+#include <string>
+// Sets the message gmot_last_error reports for the calling thread.
+void gmot_set_last_error(const std::string& msg);
 // Accessors of the network object for the runtime's warm-start entry point.
 struct gmot_mlp;
 int gmot_mlp_widths(const gmot_mlp* m, int* n_in, int* n_out);

@@ -11,6 +11,7 @@
 #include <cmath>
 #include <cstring>
 #include <memory>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -258,6 +259,7 @@ namespace {
 thread_local std::string g_mlp_error;
 int mfail(int code, const std::string& m) {
   g_mlp_error = m;
+  gmot_set_last_error(m);
   return code;
 }
 #define MCHK(x)                                                                               \
@@ -274,8 +276,38 @@ uint64_t splitmix(uint64_t& s) {
 }
 }  // namespace
 
+// ---- workspace of the allocation-free forward pass ---------------------------
+// gmot_mlp_forward_static keeps its activations in this file-scope device
+// array, so the call needs no allocation; every device the library runs on
+// holds its own copy until the process ends.  In host code the array's name is
+// a host-side stand-in, not a device address: kernels and copies get the
+// address hipGetSymbolAddress returned on the current device (static_ws).
+constexpr size_t kStaticWsBytes = size_t(8) << 20;
+static __device__ __align__(256) unsigned char scratch[kStaticWsBytes];
+
+constexpr int kMaxDevices = 64;
+static std::mutex g_ws_mu;
+static unsigned char* g_ws_ptr[kMaxDevices] = {};
+
+// With `device` current: the device address of `scratch` on it, looked up on
+// the first call for that device and kept.
+static int static_ws(int device, unsigned char** out) {
+  if (device < 0 || device >= kMaxDevices) return mfail(GMOT_EDEVICE, "device index out of range");
+  std::lock_guard<std::mutex> lk(g_ws_mu);
+  if (!g_ws_ptr[device]) {
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p)
+      return mfail(GMOT_EDEVICE, std::string("static workspace address: ") + hipGetErrorString(e));
+    g_ws_ptr[device] = (unsigned char*)p;
+  }
+  *out = g_ws_ptr[device];
+  return GMOT_OK;
+}
+
 struct gmot_mlp {
   gmot_ctx* ctx = nullptr;
+  unsigned char* static_ws = nullptr;  // device address of `scratch` on ctx->device
   int L = 0;
   std::vector<int> w;
   std::vector<int64_t> offW, offB;
@@ -401,6 +433,10 @@ int gmot_mlp_create(gmot_ctx* ctx, int32_t n_layers, const int32_t* widths, uint
   MCHK(hipSetDevice(ctx->device));
   std::unique_ptr<gmot_mlp> m(new gmot_mlp());
   m->ctx = ctx;
+  {
+    const int rc = static_ws(ctx->device, &m->static_ws);
+    if (rc) return rc;
+  }
   m->L = n_layers;
   m->w.assign(widths, widths + n_layers + 1);
   m->offW.assign(n_layers + 1, 0);
@@ -480,6 +516,67 @@ int gmot_mlp_forward_dev(gmot_mlp* m, const float* x_dev, int32_t batch, float* 
   if (rc) return rc;
   MCHK(hipMemcpyAsync(y_dev, m->H[m->L], sizeof(float) * (size_t)batch * m->w[m->L], hipMemcpyDeviceToDevice,
                       m->ctx->stream));
+  return GMOT_OK;
+}
+
+// Layout of the static workspace for a batch of B rows: the BF16 copy of x,
+// then per hidden layer its FP32 output and BF16 copy (the last layer writes
+// y directly).  Returns the bytes used.
+static size_t static_layout(const gmot_mlp* m, int64_t B, std::vector<size_t>* oH, std::vector<size_t>* oHq) {
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    const size_t r = (off + 255) / 256 * 256;
+    off = r + bytes;
+    return r;
+  };
+  if (oH) oH->assign(m->L + 1, 0);
+  if (oHq) oHq->assign(m->L + 1, 0);
+  const size_t q0 = take(sizeof(uint16_t) * (size_t)B * m->w[0]);
+  if (oHq) (*oHq)[0] = q0;
+  for (int l = 1; l < m->L; ++l) {
+    const size_t h = take(sizeof(float) * (size_t)B * m->w[l]);
+    const size_t q = take(sizeof(uint16_t) * (size_t)B * m->w[l]);
+    if (oH) (*oH)[l] = h;
+    if (oHq) (*oHq)[l] = q;
+  }
+  return off;
+}
+
+int gmot_mlp_forward_static(gmot_mlp* m, const float* x_dev, int32_t batch, float* y_dev) {
+  if (!m || !x_dev || !y_dev) return mfail(GMOT_EINVAL, "null argument");
+  if (batch < 8 || (batch % 8) != 0) return mfail(GMOT_ENOTSUP, "batch must be a positive multiple of 8");
+  std::vector<size_t> oH, oHq;
+  const size_t need = static_layout(m, batch, &oH, &oHq);
+  if (need > kStaticWsBytes) {
+    int64_t maxB = 0;
+    while (static_layout(m, maxB + 8, nullptr, nullptr) <= kStaticWsBytes) maxB += 8;
+    return mfail(GMOT_EINVAL, "batch " + std::to_string(batch) + " needs " + std::to_string(need) +
+                                  " bytes of the static workspace; it holds " + std::to_string(kStaticWsBytes) +
+                                  " (at most " + std::to_string(maxB) + " rows for this network)");
+  }
+  MCHK(hipSetDevice(m->ctx->device));
+  hipStream_t s = m->ctx->stream;
+  unsigned char* ws = m->static_ws;
+  uint16_t* xq = (uint16_t*)(ws + oHq[0]);
+  const size_t nx = (size_t)batch * m->w[0];
+  hipLaunchKernelGGL(k_quantize, dim3((unsigned)std::min<size_t>(4096, (nx + 255) / 256)), dim3(256), 0, s, x_dev, xq,
+                     nx);
+  MCHK(hipGetLastError());
+  for (int l = 1; l <= m->L; ++l) {
+    GemmArgs g{};
+    g.A = l == 1 ? xq : (const uint16_t*)(ws + oHq[l - 1]);
+    g.B = m->Wq[l];
+    g.M = batch;
+    g.N = m->w[l];
+    g.K = m->w[l - 1];
+    g.lda = m->w[l - 1];
+    g.ldb = m->w[l - 1];
+    g.ldc = m->w[l];
+    g.C = l < m->L ? (float*)(ws + oH[l]) : y_dev;
+    g.Cq = l < m->L ? (uint16_t*)(ws + oHq[l]) : nullptr;
+    g.bias = m->params + m->offB[l];
+    MCHK((l < m->L ? gemm<false, true, kBiasRelu>(g, s) : gemm<false, true, kBias>(g, s)));
+  }
   return GMOT_OK;
 }
 

@@ -41,6 +41,13 @@ int fail(int code, const std::string& msg) {
   return code;
 }
 
+}  // namespace
+
+// The message gmot_last_error reports, also set by the network's entry points.
+void gmot_set_last_error(const std::string& msg) { g_last_error = msg; }
+
+namespace {
+
 #define HIPCHK(x)                                                                     \
   do {                                                                                \
     hipError_t e_ = (x);                                                              \
