@@ -7,8 +7,8 @@ n in [128, 2048] points per node on a shared 1D or 2D grid, squared-Euclidean
 cost, eps = 1e-2.  One step = every instance solved from the cold start in the
 same launches (one captured graph per k half-sweeps, per-instance stop) until
 its FP64-judged stopping sum is <= 1e-6, then the FP64 evaluation pass of every
-instance (dual, primal, transport, both-side stopping sum).  Inputs are
-resident in device memory before the timed region.
+instance in shared launches (dual, primal, transport, both-side stopping
+sum).  Inputs are resident in device memory before the timed region.
 
 Metric: edge-iterations/s over the whole batch (an edge-iteration is one edge's
 message in one half-sweep), with the device time until the last instance
@@ -221,7 +221,7 @@ def bench_headline(ctx, args, sync) -> tuple:
 
     def step(timing=False):
         rs = b.solve(tol=args.tol, max_steps=200000, check_every=args.check_every, timing=timing)
-        evs = [g.evaluate() for g in gps]
+        evs = b.evaluate()
         return rs, evs
 
     for _ in range(max(args.warmup, 0)):
@@ -447,6 +447,27 @@ def bench_warm(ctx, tol: float, n_train: int, n_test: int, epochs: int) -> dict:
                 speedup_batched_warm_vs_plain=t_plain / res["warm_wall_s"])
 
 
+def bench_junction(ctx, tol: float) -> dict:
+    """Wasserstein least squares (the paper's second experiment, alpha = 10) on
+    its modified junction tree: J = 12 observed distributions on n = 32 grid
+    points, separators {0, J+1} (1024 joint states) and {j}, eps = 0.05,
+    solved to the FP64-judged stopping sum."""
+    from workloads import make_wls
+    from paper_2406_10849_amd import JunctionTree
+    jp = make_wls(J=12, n=32, eps=0.05, instance=0)
+    g = JunctionTree(ctx, jp)
+    g.solve(tol=tol, max_steps=200000)
+    t0 = time.perf_counter()
+    r = g.solve(tol=tol, max_steps=200000)
+    dt = time.perf_counter() - t0
+    ev = g.evaluate()
+    pairs = sum(jp.sep_size(a) * jp.sep_size(b) for a, b in jp.cliques)
+    return {"workload": "wls-J12-n32 (modified junction tree)", "cliques": jp.n_cliques, "status": r["status"],
+            "half_sweeps": r["t"], "s": dt, "time_to_tol_device_s": r["seconds"],
+            "clique_iterations_per_s": jp.n_cliques * r["t"] / dt, "pairs_per_half_sweep": pairs,
+            "err_sum_fp64": ev["err_sum"], "dual": ev["dual"], "transport": ev["transport"]}
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -460,6 +481,10 @@ def main() -> int:
                     help="also run one 1 GiB device copy (PMC calibration for HBM byte counters)")
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the plain comparison, the chain, the tree and the warm start")
+    ap.add_argument("--extras", default="chain,tree,warm",
+                    help="comma-separated extras to run (chain, tree, warm, junction)")
+    ap.add_argument("--no-headline", action="store_true",
+                    help="skip the headline batch (profiling runs of one extra); prints no bench line")
     ap.add_argument("--batched-count", type=int, default=512)
     ap.add_argument("--tree-half-sweeps", type=int, default=40)
     ap.add_argument("--warm-train", type=int, default=20000)
@@ -488,24 +513,36 @@ def main() -> int:
 
     log(f"host: {host_info()}")
     ctx = Context(0)
-    head, probs = bench_headline(ctx, args, sync)
-    out = {"metric": METRIC, "value": head.pop("value"), "unit": "edge-iterations/s", "n_gpus": 1,
-           "steps": args.steps, "warmup": args.warmup, "ms_per_step": head.pop("ms_per_step"),
-           "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64+f32exp",
-           "data": "synthetic"}
-    out.update(head)
-    log(f"headline: value {out['value']:.4g} edge-iterations/s, roofline {out['roofline']}")
-    if not args.no_extras:
+    extras = [] if args.no_extras else [e.strip() for e in args.extras.split(",") if e.strip()]
+    if args.no_headline:
+        out, probs = {}, None
+    else:
+        head, probs = bench_headline(ctx, args, sync)
+        out = {"metric": METRIC, "value": head.pop("value"), "unit": "edge-iterations/s", "n_gpus": 1,
+               "steps": args.steps, "warmup": args.warmup, "ms_per_step": head.pop("ms_per_step"),
+               "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64+f32exp",
+               "data": "synthetic"}
+        out.update(head)
+        log(f"headline: value {out['value']:.4g} edge-iterations/s, roofline {out['roofline']}")
+    if "chain" in extras:
         log("chain: time to 1e-6, node launch roofline, rounding")
         out["chain"] = bench_chain(ctx, args, sync)
         log(f"chain: {out['chain']}")
+    if "tree" in extras:
         log("random tree: layer-parallel vs plain schedule, explicit-cost streaming")
         out["tree"] = bench_tree(ctx, args.tol, args.tree_half_sweeps)
         log(f"tree: {out['tree']}")
+    if "warm" in extras:
         log("learned warm start")
         out["warm_start"] = bench_warm(ctx, args.tol, args.warm_train, args.warm_test, args.warm_epochs)
         log(f"warm start: {out['warm_start']}")
-    if not args.no_cpu_baseline:
+    if "junction" in extras:
+        log("Wasserstein least squares on its modified junction tree")
+        out["junction"] = bench_junction(ctx, args.tol)
+        log(f"junction: {out['junction']}")
+    if args.no_headline:
+        return 0
+    if not args.no_cpu_baseline and probs is not None:
         log("timing the FP64 oracle on the host")
         out["cpu_baseline"] = cpu_baseline(probs, args.cpu_seconds, args.tol)
         log(f"cpu baseline: {out['cpu_baseline']}")

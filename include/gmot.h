@@ -247,6 +247,13 @@ int  gmot_batch_create(gmot_ctx* ctx, gmot_problem* const* probs, int32_t count,
 void gmot_batch_destroy(gmot_batch* b);
 /* outs: [count] results, one per instance. */
 int  gmot_batch_solve(gmot_batch* b, const gmot_opts* opts, gmot_result* outs);
+/* gmot_evaluate for every instance of the batch, in shared launches: the FP64
+ * messages into both classes, the node terms and the pair pass of all
+ * instances run as one set of launches, each instance read from its own held
+ * state.  outs: [count]; the values equal per-instance gmot_evaluate calls up
+ * to the order in which column splits of a message are added (the split count
+ * depends on how many messages share the launch). */
+int  gmot_batch_evaluate(gmot_batch* b, gmot_eval* outs);
 
 /* ---- learned warm start ------------------------------------------------------------
  * Not part of the paper's method: a small network predicts starting potentials

@@ -258,6 +258,12 @@ class Batch:
         _check(self._lib.gmot_batch_solve(self._h, C.byref(o), rs), "gmot_batch_solve")
         return [Problem._res(r) for r in rs]
 
+    def evaluate(self) -> List[dict]:
+        """gmot_batch_evaluate: every instance's FP64 objective values in shared launches."""
+        evs = (_lib.Eval * len(self.problems))()
+        _check(self._lib.gmot_batch_evaluate(self._h, evs), "gmot_batch_evaluate")
+        return [{name: float(getattr(ev, name)) for name, _ in _lib.Eval._fields_} for ev in evs]
+
     def stats(self, reset: bool = False) -> dict:
         return Problem._stats(self._lib.gmot_batch_stats, self._h, reset)
 

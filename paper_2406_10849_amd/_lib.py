@@ -117,6 +117,7 @@ SIGNATURES = {
     "gmot_batch_create": (C.c_int, [VP, C.POINTER(VP), C.c_int32, C.POINTER(VP)]),
     "gmot_batch_destroy": (None, [VP]),
     "gmot_batch_solve": (C.c_int, [VP, C.POINTER(Opts), C.POINTER(Result)]),
+    "gmot_batch_evaluate": (C.c_int, [VP, C.POINTER(Eval)]),
     "gmot_strerror": (C.c_char_p, [C.c_int]),
     "gmot_last_error": (C.c_char_p, []),
     "gmot_last_tiles": (C.c_int, [I32P, I32P, I32P, I32P]),

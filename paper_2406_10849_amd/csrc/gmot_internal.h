@@ -68,10 +68,19 @@ struct MsgDesc {
   const float* cost_tile;    // the same, tile-major for the node kernel: C_(j,k)(x, y) at
                              // ((x / 64) * n_src + y) * 64 + x % 64, rows padded to 64
   const double* src_tpart;   // tile records of the source node k (its c_k comes from them)
+  double* sepT;              // separable messages (grid supports): first-pass sums T(u, q),
+                             // [rows_src x cols_dst] (log2), else NULL
   int32_t n_dst, n_src, ns, inst;
   int32_t dim, cost_kind, src_tiles, src_deg;  // source node's tile count and degree
   int32_t src_free, pad0, pad1, pad2;          // 1: free source node (c_k from the records), 0: c_k = 0
+  int32_t rows_src, cols_src, rows_dst, cols_dst;  // grid shapes of both supports (separable messages)
   double eps;
+};
+
+// One wave-row block of the separable first pass: source grid rows
+// [u0, u0 + 4) of message msg (one wave per row).
+struct SepItem {
+  int32_t msg, u0, inst, pad;
 };
 
 // One block of the message kernel: rows [row0, row0 + rows per block) of a
@@ -148,6 +157,11 @@ struct Tables {
   // previous launch wrote (fin_nodes: that class's node items); 0: none
   int n_fin, fin_colour;
   const NodeItem* fin_nodes;
+  const SepItem* sep_items;  // separable first pass of one class
+  int rec_rows;              // rows per tile record (32 or 64)
+  // evaluation pass: per instance the slot holding each class's committed
+  // potentials, [2 * inst + class] (read when a kernel is given slot -1)
+  const int* inst_slot;
 };
 
 // Pair pass of the evaluation (transport, entropy, mass of each plan).
@@ -187,6 +201,7 @@ struct RoundNode {
 
 // ---- launch wrappers (defined in gmot_kernels.hip) ----
 // FP64 evaluation messages from potential slot src_slot of the source class
+// (-1: each instance's committed slot, from tb.inst_slot)
 hipError_t launch_msg(const Tables& tb, int n_items, int dim, int rows_per_lane, int src_slot, hipStream_t s);
 // node kernel over n_tiles tiles of one class and support-dimension group (dim 0: explicit
 // cost); tiles of 64 * rows_per_lane / lane_groups rows, each wave's lanes in lane_groups
@@ -194,6 +209,10 @@ hipError_t launch_msg(const Tables& tb, int n_items, int dim, int rows_per_lane,
 hipError_t launch_node(const Tables& tb, int n_tiles, int dim, int waves, int rows_per_lane, int lane_groups,
                        bool fp64, hipStream_t s);
 hipError_t launch_finalize(const Tables& tb, int n_inst, hipStream_t s);
+// separable messages on Cartesian grid supports (D = 2): the first pass over
+// n_items source-row blocks, then the node stage over n_tiles 64-row tiles
+hipError_t launch_sep_rows(const Tables& tb, int n_items, bool fp64, hipStream_t s);
+hipError_t launch_node_sep(const Tables& tb, int n_tiles, bool fp64, hipStream_t s);
 hipError_t launch_node_eval(const Tables& tb, int n_nodes, int slot, hipStream_t s);
 // dst[i] = src[i] - (c ? *c : 0) over segments (potential read-back on the device)
 struct SegCopy { const double* src; double* dst; const double* c; int64_t len; };

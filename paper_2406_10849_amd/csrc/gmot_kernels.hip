@@ -186,6 +186,7 @@ __global__ __launch_bounds__(kBlock) void k_msg(Tables tb, int src_slot) {
 
   const K1Item it = tb.items[blockIdx.x];
   const MsgDesc* __restrict__ md = tb.msgs + it.msg;
+  if (src_slot < 0) src_slot = tb.inst_slot[2 * it.inst + (1 - tb.colour)];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int n_dst = md->n_dst;
   const double eps = md->eps;
@@ -1140,6 +1141,237 @@ __global__ __launch_bounds__(64 * W, (W == 8 && R == 1 && H == 2 && !EXPL) ? 4 :
 }
 
 // ---------------------------------------------------------------------------
+// Separable messages on Cartesian grids (squared-Euclidean cost, D = 2).
+// When every support of an instance is a row-major grid -- point p of node j
+// at (R_j[p / B_j], C_j[p % B_j]), the last row possibly partial -- the cost
+// splits, |x - y|^2 = (R_j[p] - R_k[u])^2 + (C_j[q] - C_k[v])^2, and so does
+// the log-sum-exp of the message (eq. q), in two one-dimensional passes:
+//   T(u, q) = log2 sum_v 2^(a(u, v) - kap (C_j[q] - C_k[v])^2)     (k_sep_rows)
+//   m(p, q) = ln2 log2 sum_u 2^(T(u, q) - kap (R_j[p] - R_k[u])^2) - c_k
+//                                                                   (k_node_sep)
+// with a = log2e (L_(k,j) + log gamma_k) over the source's points (absent
+// points of a partial last row give -inf), kap = log2e / eps, and c_k the
+// source's normaliser: n_k B_j + n_j A_k terms per message instead of n_j n_k.
+// Each sum takes two passes over its terms (max, then the shifted sum): FP32
+// exponentials of the FP64-reduced argument accumulated in FP64, or FP64
+// throughout (F64).  k_node_sep then does the node's stopping-sum terms,
+// update and tile records exactly as k_node does.
+// ---------------------------------------------------------------------------
+constexpr int kSepWaves = 4;
+
+template <bool F64>
+__device__ inline double exp2_term(double d) {
+  if (F64) return exp2(d);
+  return (double)exp2_hw((float)d);
+}
+
+// One wave per source grid row u of one message: T(u, q) for every column q of
+// the destination grid (lanes over q), the source row's terms staged in the
+// wave's LDS buffer 64 columns at a time.
+// As the first launch of a node stage it also carries the finalise step of
+// the previous half-sweep in its first n_fin blocks, as k_node does.
+template <bool F64>
+__global__ __launch_bounds__(64 * kSepWaves) void k_sep_rows(Tables tb) {
+  __shared__ double s_a[kSepWaves][64];
+  __shared__ double s_y[kSepWaves][64];
+  if ((int)blockIdx.x < tb.n_fin) {
+    __shared__ double sh_fin[kFinParts][2];
+    fin_instance<kSepWaves>(tb, tb.fin_nodes, tb.fin_colour, tb.inst + blockIdx.x, true, sh_fin);
+    return;
+  }
+  const SepItem it = tb.sep_items[blockIdx.x - tb.n_fin];
+  const CMsg& md = *(const CMsg*)(tb.msgs + it.msg);
+  const InstState* st = tb.inst + it.inst;
+  const long long t = st->vt[tb.colour];
+  if (st->vdone[tb.colour] != 0 || t < st->t_first || ((t & 1) == 1) != (tb.colour == 0)) return;
+  const int lane = threadIdx.x & 63, wv = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+  const int u = it.u0 + wv;
+  const int Ak = md.rows_src, Bk = md.cols_src, Bj = md.cols_dst, nk = md.n_src;
+  if (u >= Ak) return;
+  const int src_slot = (int)((t >> 1) % kSlots);
+  const GDbl* __restrict__ lam = (const GDbl*)md.lam_src[src_slot];
+  const GDbl* __restrict__ lg = (const GDbl*)md.lg_src;
+  const GDbl* __restrict__ ys = (const GDbl*)md.supp_src;
+  const GDbl* __restrict__ xs = (const GDbl*)md.supp_dst;
+  GDblW* __restrict__ T = (GDblW*)md.sepT + (size_t)u * Bj;
+  const double kap = kLog2e / md.eps;
+  double* __restrict__ sa = s_a[wv];
+  double* __restrict__ sy = s_y[wv];
+  // columns v0 .. v0 + 63 of source row u into the wave's buffer (loads at
+  // clamped indexes; absent points get a = -inf)
+  auto stage = [&](int v0) -> int {
+    const int v = v0 + lane, y = u * Bk + v;
+    const bool ok = v < Bk && y < nk;
+    const int yc = ok ? y : 0;
+    const double av = lam[yc] + lg[yc];
+    const double yv = ys[(size_t)yc * 2 + 1];
+    sa[lane] = ok ? kLog2e * av : -INFINITY;
+    sy[lane] = ok ? yv : 0.0;
+    wave_sync();
+    return min(64, Bk - v0);
+  };
+  for (int q0 = 0; q0 < Bj; q0 += 64) {
+    const int q = q0 + lane;
+    const double xq = xs[(size_t)min(q, Bj - 1) * 2 + 1];
+    double M = -INFINITY;
+    for (int v0 = 0; v0 < Bk; v0 += 64) {
+      const int cn = stage(v0);
+      for (int c = 0; c < cn; ++c) {
+        const double d = xq - sy[c];
+        M = fmax(M, fma(-kap * d, d, sa[c]));
+      }
+      wave_sync();
+    }
+    double S = 0.0;
+    if (__any(M > -INFINITY)) {
+      for (int v0 = 0; v0 < Bk; v0 += 64) {
+        const int cn = stage(v0);
+        for (int c = 0; c < cn; ++c) {
+          const double d = xq - sy[c];
+          S += exp2_term<F64>(fma(-kap * d, d, sa[c]) - M);
+        }
+        wave_sync();
+      }
+    }
+    if (q < Bj) T[q] = (M > -INFINITY && S > 0.0) ? M + log2(S) : -INFINITY;
+  }
+}
+
+// Node stage of a separable instance: one block of 4 waves per 64-row tile of
+// a node of the class being updated.  Waves take the incident edges in turn
+// (lane = row): the second pass of each message, reading T from the first,
+// then the source normaliser as in k_node; after one barrier the row owners
+// (one wave per tile record) take their rows through every edge for the
+// stopping-sum terms of the state before the update, the update and the
+// record, as k_node does.
+template <bool F64>
+__global__ __launch_bounds__(64 * kSepWaves) void k_node_sep(Tables tb) {
+  __shared__ double s_r[kSepWaves][64];
+  __shared__ double s_m[kNodeDegLDS][64];
+  const TileItem ti = tb.tiles[blockIdx.x];
+  const InstState* st = tb.inst + ti.inst;
+  const long long t = st->vt[tb.colour];
+  const long long t_first = st->t_first;
+  if (st->vdone[tb.colour] != 0 || t < t_first || ((t & 1) == 1) != (tb.colour == 0)) return;
+  const NodeItem nd = tb.nodes[ti.node];
+  const CMsg* __restrict__ mds = (const CMsg*)(tb.msgs + ti.msg0);
+  const int n = ti.n, deg = ti.deg;
+  const int cur = (int)(((t - 1) >> 1) % kSlots), nxt = (cur + 1) % kSlots;
+  const int src_slot = (int)((t >> 1) % kSlots);
+  const bool rec_ok = t - 1 >= t_first;
+  const int lane = threadIdx.x & 63, wv = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+  const int x = ti.row0 + lane;
+  const bool vx = x < n;
+  const int xc = min(x, n - 1);
+  const int Bj = mds[0].cols_dst;
+  const int p = xc / Bj, q = xc - p * Bj;
+  const double Rj = ((const GDbl*)mds[0].supp_dst)[(size_t)p * Bj * 2];
+  const double kap = kLog2e / mds[0].eps;
+  double* __restrict__ sr = s_r[wv];
+  for (int k = wv; k < deg; k += kSepWaves) {
+    const CMsg& md = mds[k];
+    const int Ak = md.rows_src, Bk = md.cols_src;
+    const GDbl* __restrict__ T = (const GDbl*)md.sepT;
+    const GDbl* __restrict__ ys = (const GDbl*)md.supp_src;
+    // the source's normaliser: from its tile records when its last update
+    // (half-sweep t - 1) ran in this run, else its stored value
+    double ck = 0.0;
+    if (md.src_free) {
+      if (rec_ok) {
+        const GDbl* __restrict__ srec = (const GDbl*)md.src_tpart;
+        const int src_deg = md.src_deg, src_tiles = md.src_tiles;
+        const int s_stride = src_deg + kRecExtra, s_tile = min(lane, src_tiles - 1);
+        ck = tile_lse((const double*)srec, src_tiles, s_stride, src_deg, srec[(size_t)s_tile * s_stride + src_deg],
+                      srec[(size_t)s_tile * s_stride + src_deg + 1]);
+      } else {
+        ck = *(const GDbl*)(md.c_src + src_slot);
+      }
+    }
+    auto stage = [&](int u0) -> int {
+      const int u = min(u0 + lane, Ak - 1);
+      sr[lane] = ys[(size_t)u * Bk * 2];
+      wave_sync();
+      return min(64, Ak - u0);
+    };
+    double M = -INFINITY;
+    for (int u0 = 0; u0 < Ak; u0 += 64) {
+      const int cn = stage(u0);
+      for (int c = 0; c < cn; ++c) {
+        const double d = Rj - sr[c];
+        M = fmax(M, fma(-kap * d, d, T[(size_t)(u0 + c) * Bj + q]));
+      }
+      wave_sync();
+    }
+    double S = 0.0;
+    if (__any(M > -INFINITY)) {
+      for (int u0 = 0; u0 < Ak; u0 += 64) {
+        const int cn = stage(u0);
+        for (int c = 0; c < cn; ++c) {
+          const double d = Rj - sr[c];
+          S += exp2_term<F64>(fma(-kap * d, d, T[(size_t)(u0 + c) * Bj + q]) - M);
+        }
+        wave_sync();
+      }
+    }
+    const double m = (M > -INFINITY && S > 0.0) ? kLn2 * (M + log2(S)) - ck : -INFINITY;
+    if (k < kNodeDegLDS) s_m[k][lane] = m;
+    else if (vx) ((GDblW*)md.mfull)[x] = m;
+  }
+  __syncthreads();
+  // row owners: wave w takes rows w * RR + lane (lane < RR) and writes record
+  // row0 / RR + w
+  const int RR = tb.rec_rows, TQ = 64 / RR;
+  if (wv >= TQ || ti.row0 + wv * RR >= n) return;
+  const int lr = wv * RR + (lane < RR ? lane : 0), xr = ti.row0 + lr;
+  const bool vr = lane < RR && xr < n;
+  const int xs = vr ? xr : ti.row0;
+  GDblW* __restrict__ rec = (GDblW*)(nd.tpart + (size_t)(ti.row0 / RR + wv) * (deg + kRecExtra));
+  auto msg = [&](int k) -> double {
+    return k < kNodeDegLDS ? s_m[k][lr] : ((const GDbl*)mds[k].mfull)[xs];
+  };
+  if (ti.fixed) {
+    const double mu = vr ? ((const GDbl*)nd.mu)[xr] : 0.0;
+    for (int k = 0; k < deg; ++k) {
+      const double m = msg(k);
+      double term = 0.0;
+      if (vr) {
+        const double l = ((const GDbl*)mds[k].lam_dst[cur])[xr];
+        if (mu > 0.0) term = mu * fabs(expm1(l + m));
+        ((GDblW*)mds[k].lam_dst[nxt])[xr] = -m;
+      }
+      term = wave_sum(term);
+      if (lane == 0) rec[k] = term;
+    }
+  } else {
+    const double c_old = *(const GDbl*)(nd.c + cur);
+    double as = 0.0, qs = 0.0;
+    for (int k = 0; k < deg; ++k) {
+      const double m = msg(k);
+      as += m;
+      if (vr) qs += exp(((const GDbl*)mds[k].lam_dst[cur])[xr] - c_old + m);
+    }
+    const double ab = as / deg, qb = qs / deg;
+    for (int k = 0; k < deg; ++k) {
+      const double m = msg(k);
+      double term = 0.0;
+      if (vr) {
+        term = fabs(exp(((const GDbl*)mds[k].lam_dst[cur])[xr] - c_old + m) - qb);
+        ((GDblW*)mds[k].lam_dst[nxt])[xr] = ab - m;
+      }
+      term = wave_sum(term);
+      if (lane == 0) rec[k] = term;
+    }
+    const double av = vr ? ab : -INFINITY;
+    const double Mw = wave_max(av);
+    const double Sw = wave_sum(av > -INFINITY ? exp(av - Mw) : 0.0);
+    if (lane == 0) {
+      rec[deg] = Mw;
+      rec[deg + 1] = Sw;
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
 // Finalise kernel: one block of kFinWaves waves per instance, one wave per
 // node of the class (nodes w, w + kFinWaves, ...): per-edge terms summed over
 // the node's tile records (lanes over tiles), and for free nodes
@@ -1159,6 +1391,7 @@ __global__ __launch_bounds__(64 * kFinWaves) void k_finalize(Tables tb) {
 __global__ __launch_bounds__(kBlock) void k_node_eval(Tables tb, int slot) {
   __shared__ double sh[4];
   const NodeItem nd = tb.nodes[blockIdx.x];
+  if (slot < 0) slot = tb.inst_slot[2 * nd.inst + tb.colour];
   const int n = nd.n, deg = nd.deg;
   const MsgDesc* __restrict__ mds = tb.msgs + nd.msg0;
   const int dim = mds[0].dim;
@@ -1330,7 +1563,7 @@ static hipError_t launch_msg_r(const Tables& tb, int n_items, int dim, int src_s
 
 hipError_t launch_msg(const Tables& tb, int n_items, int dim, int rows_per_lane, int src_slot, hipStream_t s) {
   if (n_items <= 0) return hipSuccess;
-  if (src_slot < 0 || src_slot >= kSlots) return hipErrorInvalidValue;
+  if (src_slot < -1 || src_slot >= kSlots) return hipErrorInvalidValue;
   return rows_per_lane == 2 ? launch_msg_r<2>(tb, n_items, dim, src_slot, s)
                             : launch_msg_r<1>(tb, n_items, dim, src_slot, s);
 }
@@ -1380,6 +1613,22 @@ hipError_t launch_node(const Tables& tb, int n_tiles, int dim, int waves, int ro
 hipError_t launch_finalize(const Tables& tb, int n_inst, hipStream_t s) {
   if (n_inst <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_finalize, dim3(n_inst), dim3(64 * kFinWaves), 0, s, tb);
+  return hipGetLastError();
+}
+
+hipError_t launch_sep_rows(const Tables& tb, int n_items, bool fp64, hipStream_t s) {
+  if (n_items <= 0) return hipSuccess;
+  const dim3 grid(n_items + tb.n_fin);
+  if (fp64) hipLaunchKernelGGL(k_sep_rows<true>, grid, dim3(64 * kSepWaves), 0, s, tb);
+  else hipLaunchKernelGGL(k_sep_rows<false>, grid, dim3(64 * kSepWaves), 0, s, tb);
+  return hipGetLastError();
+}
+
+hipError_t launch_node_sep(const Tables& tb, int n_tiles, bool fp64, hipStream_t s) {
+  if (n_tiles <= 0) return hipSuccess;
+  if (tb.rec_rows != 32 && tb.rec_rows != 64) return hipErrorInvalidValue;
+  if (fp64) hipLaunchKernelGGL(k_node_sep<true>, dim3(n_tiles), dim3(64 * kSepWaves), 0, s, tb);
+  else hipLaunchKernelGGL(k_node_sep<false>, dim3(n_tiles), dim3(64 * kSepWaves), 0, s, tb);
   return hipGetLastError();
 }
 

@@ -89,6 +89,11 @@ struct gmot_problem {
   float* d_cost = nullptr;
   float* d_cost_tile = nullptr;           // per directed edge, tile-major (node kernel)
   std::vector<int64_t> tcost_off;         // [2E + 1] offsets into d_cost_tile
+  // separable messages: every support is a row-major grid (D = 2, on-the-fly
+  // squared-Euclidean cost); grid_cols[j] = points per grid row of node j
+  bool sep = false;
+  std::vector<int> grid_cols;
+  int grid_rows(int j) const { return (int)((sizes[j] + grid_cols[j] - 1) / grid_cols[j]); }
   int64_t t = 1;
   uint64_t version = 0;   // bumped whenever the held state changes
   Plan* plan = nullptr;
@@ -104,6 +109,11 @@ struct gmot_problem {
   // slot holding the committed value of class c's potentials
   int slot_of_class(int c) const { return c == 0 ? (int)((t / 2) % kSlots) : (int)(((t - 1) / 2) % kSlots); }
 };
+
+// Tile group of separable instances (after the explicit-cost and D = 1..3 groups).
+constexpr int kSepGroup = 4;
+// Rows per node-stage tile of separable instances.
+constexpr int kSepTileRows = 64;
 
 // Timing mode: events per half-sweep, and back-to-back repeats of the message
 // stage between the first two (so their mean excludes the event overhead).
@@ -145,9 +155,18 @@ struct Plan {
   double2* d_partial = nullptr;
   double* d_wmax = nullptr;
   double* d_tpart = nullptr;
-  std::vector<TileItem> tiles[2][4];                 // [class][0 = explicit, 1..3 = dim]
-  std::vector<std::pair<int, int>> node_tiles[2][4];  // per node: (first tile, tile count)
-  TileItem* d_tiles[2][4] = {};
+  // node-kernel tiles per [class][0 = explicit, 1..3 = dim, kSepGroup = separable grids]
+  std::vector<TileItem> tiles[2][5];
+  std::vector<std::pair<int, int>> node_tiles[2][5];  // per node: (first tile, tile count)
+  TileItem* d_tiles[2][5] = {};
+  // separable instances: first-pass items per class, and per node of the
+  // separable group (in node_tiles[c][kSepGroup] order) its (first item, count)
+  std::vector<SepItem> sep_items[2];
+  std::vector<std::pair<int, int>> node_sep[2];
+  SepItem* d_sep_items[2] = {};
+  double* d_sepT = nullptr;
+  int* d_inst_slot = nullptr;  // evaluation pass: committed slot of each class, per instance
+  int rec_rows = 64;         // rows per tile record
   int* h_ndone = nullptr;  // pinned, two mailboxes
   std::vector<GraphEntry> graphs;
   TileStats stats;
@@ -167,13 +186,16 @@ struct Plan {
   Tables tables(int c, int dk) const {
     Tables tb{};
     tb.msgs = d_msgs;
-    tb.items = dk >= 0 ? d_items[c][dk] : nullptr;
+    tb.items = dk >= 0 && dk < 4 ? d_items[c][dk] : nullptr;
     tb.nodes = d_nodes[c];
     tb.inst = d_inst;
     tb.node_eval = d_node_eval;
     tb.ndone = d_ndone;
     tb.tiles = dk >= 0 ? d_tiles[c][dk] : nullptr;
     tb.colour = c;
+    tb.sep_items = d_sep_items[c];
+    tb.rec_rows = rec_rows;
+    tb.inst_slot = d_inst_slot;
     return tb;
   }
 
@@ -203,6 +225,28 @@ struct Plan {
         tb.tiles += r.first;
         e = launch_node(tb, r.second, dk, W, NR, NH, fp64, s);
         if (e != hipSuccess) return e;
+      }
+    }
+    // separable instances: first pass, then the node stage that reads it
+    if (!sep_items[c].empty()) {
+      if (!per_node) {
+        Tables tb = tables(c, kSepGroup);
+        if (fin_pending) {
+          tb.n_fin = (int)inst.size();
+          tb.fin_colour = 1 - c;
+          tb.fin_nodes = d_nodes[1 - c];
+        }
+        if ((e = launch_sep_rows(tb, (int)sep_items[c].size(), fp64, s)) != hipSuccess) return e;
+        tb.n_fin = 0;
+        if ((e = launch_node_sep(tb, (int)tiles[c][kSepGroup].size(), fp64, s)) != hipSuccess) return e;
+      } else {
+        for (size_t i = 0; i < node_sep[c].size(); ++i) {
+          Tables tb = tables(c, kSepGroup);
+          tb.sep_items += node_sep[c][i].first;
+          if ((e = launch_sep_rows(tb, node_sep[c][i].second, fp64, s)) != hipSuccess) return e;
+          tb.tiles += node_tiles[c][kSepGroup][i].first;
+          if ((e = launch_node_sep(tb, node_tiles[c][kSepGroup][i].second, fp64, s)) != hipSuccess) return e;
+        }
       }
     }
     return hipSuccess;
@@ -253,8 +297,9 @@ static int build_plan(gmot_ctx* ctx, const std::vector<gmot_problem*>& probs, No
   const int R = pl->R, target_blocks = pl->target_blocks;
   const int TM = 256 * R;
   // node tiles per (class, dimension group), with each node's work (pairs) for ordering
-  struct NodeTiles { int node_item, n_tiles, inst; double work; };
-  std::vector<NodeTiles> ntl[2][4];
+  struct NodeTiles { int node_item, n_tiles, inst; double work; int sep_first, sep_count; };
+  std::vector<NodeTiles> ntl[2][5];
+  std::vector<SepItem> sep_tmp[2];  // separable first-pass items, node by node in build order
 
   // messages and node items (class-major within each instance)
   std::vector<int> msg_class;
@@ -283,11 +328,23 @@ static int build_plan(gmot_ctx* ctx, const std::vector<gmot_problem*>& probs, No
         nd.qbar = p->d_qbar + p->node_off[j];
         nd.c = p->fixed[j] ? nullptr : p->d_c + kSlots * j;
         nd.tiles = (int)ceil_div(p->sizes[j], std::min(TRows, 64));  // tile records: one per 64 rows (32 for 32-row tiles)
-        {
+        if (p->sep) {
+          // first-pass items of the node's messages (4 source grid rows each), in message order
+          const int first = (int)sep_tmp[c].size();
+          double work = 0.0;
+          for (size_t q = 0; q < p->nbrs[j].size(); ++q) {
+            const int k = p->nbrs[j][q];
+            const int m = (int)pl->msgs.size() + (int)q;
+            for (int u0 = 0; u0 < p->grid_rows(k); u0 += 4) sep_tmp[c].push_back({m, u0, (int)i, 0});
+            work += (double)p->grid_rows(k) + (double)p->sizes[k] * p->grid_cols[j] / std::max(1, p->sizes[j]);
+          }
+          ntl[c][kSepGroup].push_back({(int)pl->nodes[c].size(), (int)ceil_div(p->sizes[j], kSepTileRows), (int)i,
+                                       work, first, (int)sep_tmp[c].size() - first});
+        } else {
           double src_cols = 0.0;
           for (int k : p->nbrs[j]) src_cols += p->sizes[k];
           const int dk = p->cost_kind == GMOT_COST_EXPLICIT ? 0 : p->dim;
-          ntl[c][dk].push_back({(int)pl->nodes[c].size(), (int)ceil_div(p->sizes[j], TRows), (int)i, src_cols});
+          ntl[c][dk].push_back({(int)pl->nodes[c].size(), (int)ceil_div(p->sizes[j], TRows), (int)i, src_cols, 0, 0});
         }
         item_of[{(int)i, j}] = {c, (int)pl->nodes[c].size()};
         pl->nodes[c].push_back(nd);
@@ -316,6 +373,12 @@ static int build_plan(gmot_ctx* ctx, const std::vector<gmot_problem*>& probs, No
           md.n_dst = p->sizes[j];
           md.n_src = p->sizes[k];
           md.src_free = p->fixed[k] ? 0 : 1;
+          if (p->sep) {
+            md.rows_src = p->grid_rows(k);
+            md.cols_src = p->grid_cols[k];
+            md.rows_dst = p->grid_rows(j);
+            md.cols_dst = p->grid_cols[j];
+          }
           msg_src[pl->msgs.size()] = {(int)i, k};
           md.inst = (int)i;
           md.dim = p->dim;
@@ -331,8 +394,15 @@ static int build_plan(gmot_ctx* ctx, const std::vector<gmot_problem*>& probs, No
   }
   pl->total_nodes = err_counter;
   for (int c = 0; c < 2; ++c) pl->inst_pairs[c].assign(probs.size(), 0.0);
-  for (size_t m = 0; m < pl->msgs.size(); ++m)
-    pl->inst_pairs[msg_class[m]][pl->msgs[m].inst] += (double)pl->msgs[m].n_dst * pl->msgs[m].n_src;
+  // (x, y) term evaluations of the node stage: n_j n_k per message, or
+  // A_k B_j B_k + n_j A_k for a separable one (its two passes)
+  for (size_t m = 0; m < pl->msgs.size(); ++m) {
+    const MsgDesc& md = pl->msgs[m];
+    const double ev = probs[md.inst]->sep
+                          ? (double)md.rows_src * md.cols_dst * md.cols_src + (double)md.n_dst * md.rows_src
+                          : (double)md.n_dst * md.n_src;
+    pl->inst_pairs[msg_class[m]][md.inst] += ev;
+  }
 
   // column splits: enough blocks per class to fill the device
   int64_t row_tiles[2] = {0, 0};
@@ -369,15 +439,30 @@ static int build_plan(gmot_ctx* ctx, const std::vector<gmot_problem*>& probs, No
   // node-kernel tiles: the heaviest nodes (most source columns per row) first,
   // so their long blocks start early; each node's tiles stay consecutive
   for (int c = 0; c < 2; ++c)
-    for (int dk = 0; dk < 4; ++dk) {
+    for (int dk = 0; dk < 5; ++dk) {
       std::stable_sort(ntl[c][dk].begin(), ntl[c][dk].end(),
                        [](const NodeTiles& u, const NodeTiles& v) { return u.work > v.work; });
+      const int rows = dk == kSepGroup ? kSepTileRows : TRows;
       for (const NodeTiles& q : ntl[c][dk]) {
         pl->node_tiles[c][dk].push_back({(int)pl->tiles[c][dk].size(), q.n_tiles});
         const NodeItem& qn = pl->nodes[c][q.node_item];
         for (int r = 0; r < q.n_tiles; ++r)
-          pl->tiles[c][dk].push_back({q.node_item, r * TRows, q.inst, qn.msg0, qn.deg, qn.n, qn.fixed, 0});
+          pl->tiles[c][dk].push_back({q.node_item, r * rows, q.inst, qn.msg0, qn.deg, qn.n, qn.fixed, 0});
+        if (dk == kSepGroup) {
+          pl->node_sep[c].push_back({(int)pl->sep_items[c].size(), q.sep_count});
+          pl->sep_items[c].insert(pl->sep_items[c].end(), sep_tmp[c].begin() + q.sep_first,
+                                  sep_tmp[c].begin() + q.sep_first + q.sep_count);
+        }
       }
+    }
+  pl->rec_rows = std::min(TRows, 64);
+  // first-pass sums of separable messages
+  int64_t sepT_total = 0;
+  std::vector<int64_t> sepT_off(pl->msgs.size(), -1);
+  for (size_t m = 0; m < pl->msgs.size(); ++m)
+    if (probs[pl->msgs[m].inst]->sep) {
+      sepT_off[m] = sepT_total;
+      sepT_total += (int64_t)pl->msgs[m].rows_src * pl->msgs[m].cols_dst;
     }
   int64_t wmax_total = 0;
   std::vector<int64_t> wmax_off(pl->msgs.size());
@@ -397,7 +482,7 @@ static int build_plan(gmot_ctx* ctx, const std::vector<gmot_problem*>& probs, No
   pl->stats.max_splits = shape.W;
   for (int c = 0; c < 2; ++c) {
     pl->stats.blocks[c] = 0;
-    for (int dk = 0; dk < 4; ++dk) pl->stats.blocks[c] += (int)pl->tiles[c][dk].size();
+    for (int dk = 0; dk < 5; ++dk) pl->stats.blocks[c] += (int)pl->tiles[c][dk].size();
   }
 
   // one device allocation for every table
@@ -418,10 +503,14 @@ static int build_plan(gmot_ctx* ctx, const std::vector<gmot_problem*>& probs, No
   const size_t o_ndone = take(sizeof(int) * 4);
   const size_t o_part = take(sizeof(double2) * std::max<int64_t>(1, partial_total));
   const size_t o_wmax = take(sizeof(double) * std::max<int64_t>(1, wmax_total));
-  size_t o_tiles[2][4];
+  size_t o_tiles[2][5];
   for (int c = 0; c < 2; ++c)
-    for (int dk = 0; dk < 4; ++dk) o_tiles[c][dk] = take(sizeof(TileItem) * pl->tiles[c][dk].size());
+    for (int dk = 0; dk < 5; ++dk) o_tiles[c][dk] = take(sizeof(TileItem) * pl->tiles[c][dk].size());
   const size_t o_tpart = take(sizeof(double) * std::max<int64_t>(1, tpart_total));
+  size_t o_sep[2];
+  for (int c = 0; c < 2; ++c) o_sep[c] = take(sizeof(SepItem) * pl->sep_items[c].size());
+  const size_t o_sepT = take(sizeof(double) * std::max<int64_t>(1, sepT_total));
+  const size_t o_islot = take(sizeof(int) * 2 * probs.size());
   const size_t total = off;
   if (hipMalloc(&pl->arena, total) != hipSuccess) return fail(GMOT_ENOMEM, "plan arena allocation failed");
   char* base = (char*)pl->arena;
@@ -435,13 +524,17 @@ static int build_plan(gmot_ctx* ctx, const std::vector<gmot_problem*>& probs, No
   pl->d_partial = (double2*)(base + o_part);
   pl->d_wmax = (double*)(base + o_wmax);
   for (int c = 0; c < 2; ++c)
-    for (int dk = 0; dk < 4; ++dk) pl->d_tiles[c][dk] = (TileItem*)(base + o_tiles[c][dk]);
+    for (int dk = 0; dk < 5; ++dk) pl->d_tiles[c][dk] = (TileItem*)(base + o_tiles[c][dk]);
   pl->d_tpart = (double*)(base + o_tpart);
+  for (int c = 0; c < 2; ++c) pl->d_sep_items[c] = (SepItem*)(base + o_sep[c]);
+  pl->d_sepT = (double*)(base + o_sepT);
+  pl->d_inst_slot = (int*)(base + o_islot);
   for (int c = 0; c < 2; ++c)
     for (size_t i = 0; i < pl->nodes[c].size(); ++i) pl->nodes[c][i].tpart = pl->d_tpart + tpart_off[c][i];
   for (size_t m = 0; m < pl->msgs.size(); ++m) {
     pl->msgs[m].partial = pl->d_partial + partial_off[m];
     pl->msgs[m].wmax = pl->d_wmax + wmax_off[m];
+    pl->msgs[m].sepT = sepT_off[m] >= 0 ? pl->d_sepT + sepT_off[m] : nullptr;
     // the source node's records (constrained sources too: read, then ignored)
     const auto src = item_of.at(msg_src.at(m));
     const NodeItem& sn = pl->nodes[src.first][src.second];
@@ -460,10 +553,13 @@ static int build_plan(gmot_ctx* ctx, const std::vector<gmot_problem*>& probs, No
     if (!pl->nodes[c].empty())
       HIPCHK(hipMemcpyAsync(pl->d_nodes[c], pl->nodes[c].data(), sizeof(NodeItem) * pl->nodes[c].size(),
                             hipMemcpyHostToDevice, s));
-    for (int dk = 0; dk < 4; ++dk)
+    for (int dk = 0; dk < 5; ++dk)
       if (!pl->tiles[c][dk].empty())
         HIPCHK(hipMemcpyAsync(pl->d_tiles[c][dk], pl->tiles[c][dk].data(),
                               sizeof(TileItem) * pl->tiles[c][dk].size(), hipMemcpyHostToDevice, s));
+    if (!pl->sep_items[c].empty())
+      HIPCHK(hipMemcpyAsync(pl->d_sep_items[c], pl->sep_items[c].data(), sizeof(SepItem) * pl->sep_items[c].size(),
+                            hipMemcpyHostToDevice, s));
   }
   // one-pass shifts start at 0; the first two half-sweeps of every call take two passes anyway
   HIPCHK(hipMemsetAsync(pl->d_wmax, 0, sizeof(double) * std::max<int64_t>(1, wmax_total), s));
@@ -981,6 +1077,26 @@ static int upload(const gmot_tree_desc* d, gmot_problem* p) {
     o += p->sizes[j];
   }
   if (d->cost_kind == GMOT_COST_SQEUCLID) std::memcpy(sup.data(), d->support, sizeof(double) * P * p->dim);
+  // Separable messages need every support to be a row-major grid: point i of
+  // node j equals (first coordinate of point (i / B) B, second coordinate of
+  // point i % B) for B = the length of the run of points sharing the first
+  // point's first coordinate (the last grid row may be partial).  Exact
+  // comparisons: any other layout takes the general message kernel.
+  p->grid_cols.assign(p->N, 0);
+  p->sep = false;
+  if (p->dim == 2 && d->cost_kind == GMOT_COST_SQEUCLID && p->E > 0 && !std::getenv("GMOT_NO_SEP")) {
+    bool all = true;
+    for (int j = 0; j < p->N && all; ++j) {
+      const double* X = sup.data() + p->node_off[j] * 2;
+      const int n = p->sizes[j];
+      int B = 1;
+      while (B < n && X[2 * B] == X[0]) ++B;
+      for (int i = 0; i < n && all; ++i)
+        all = X[2 * i] == X[2 * (i / B) * B] && X[2 * i + 1] == X[2 * (i % B) + 1];
+      p->grid_cols[j] = B;
+    }
+    p->sep = all;
+  }
   HIPCHK(hipMemcpy(p->d_support, sup.data(), sizeof(double) * P * p->dim, hipMemcpyHostToDevice));
   HIPCHK(hipMemcpy(p->d_lg, lg.data(), sizeof(double) * P, hipMemcpyHostToDevice));
   HIPCHK(hipMemcpy(p->d_mu, mu.data(), sizeof(double) * P, hipMemcpyHostToDevice));
@@ -1162,17 +1278,23 @@ static int restart_problem(gmot_problem* p) {
 // ---------------------------------------------------------------------------
 // evaluation pass (FP64)
 // ---------------------------------------------------------------------------
-static int eval_messages(gmot_problem* p, int only_class) {
-  Plan* pl = p->plan;
-  hipStream_t s = p->ctx->stream;
+// FP64 messages into, and node terms of, class only_class (-1: both) for every
+// instance of the plan, each read from its committed slots.
+static int eval_messages(Plan* pl, int only_class) {
+  hipStream_t s = pl->ctx->stream;
+  std::vector<int> slots(2 * pl->probs.size());
+  for (size_t i = 0; i < pl->probs.size(); ++i)
+    for (int c = 0; c < 2; ++c) slots[2 * i + c] = pl->probs[i]->slot_of_class(c);
+  HIPCHK(hipMemcpyAsync(pl->d_inst_slot, slots.data(), sizeof(int) * slots.size(), hipMemcpyHostToDevice, s));
   for (int c = 0; c < 2; ++c) {
     if (only_class >= 0 && c != only_class) continue;
-    const int src_slot = p->slot_of_class(1 - c);
     for (int dk = 0; dk < 4; ++dk)
       if (!pl->items[c][dk].empty())
-        HIPCHK(launch_msg(pl->tables(c, dk), (int)pl->items[c][dk].size(), dk, pl->R, src_slot, s));
-    HIPCHK(launch_node_eval(pl->tables(c, -1), (int)pl->nodes[c].size(), p->slot_of_class(c), s));
+        HIPCHK(launch_msg(pl->tables(c, dk), (int)pl->items[c][dk].size(), dk, pl->R, -1, s));
+    HIPCHK(launch_node_eval(pl->tables(c, -1), (int)pl->nodes[c].size(), -1, s));
   }
+  // the slot table is host memory read by a copy still in flight
+  HIPCHK(hipStreamSynchronize(s));
   return GMOT_OK;
 }
 
@@ -1195,6 +1317,109 @@ static EdgeDesc edge_desc(const gmot_problem* p, int e) {
   ed.cost_kind = p->cost_kind;
   ed.eps = p->eps;
   return ed;
+}
+
+// FP64 objective values of the held state of every instance of a plan, in
+// shared launches (outs[i] for plan instance i): the messages into both
+// classes and the node terms (k_msg, k_node_eval), then the pair pass over
+// every edge of every instance (k_pairs); the per-instance sums are taken on
+// the host in the same order for any plan (only the column splits of the
+// messages, and so their merge order, depend on the plan).
+static int evaluate_plan(Plan* pl, gmot_eval* outs) {
+  const size_t n = pl->probs.size();
+  for (size_t i = 0; i < n; ++i) std::memset(&outs[i], 0, sizeof(gmot_eval));
+  hipStream_t s = pl->ctx->stream;
+  int rc = eval_messages(pl, -1);
+  if (rc) return rc;
+  // pair pass
+  std::vector<EdgeDesc> eds;
+  std::vector<PairItem> items;
+  std::vector<int> edge_inst;
+  std::vector<int> edge0(n + 1, 0);
+  for (size_t i = 0; i < n; ++i) {
+    const gmot_problem* p = pl->probs[i];
+    edge0[i] = (int)eds.size();
+    for (int e = 0; e < p->E; ++e) {
+      const int ge = (int)eds.size();
+      eds.push_back(edge_desc(p, e));
+      edge_inst.push_back((int)i);
+      const int na = eds.back().n_a, nb = eds.back().n_b;
+      const int cw = 2048;
+      for (int r0 = 0; r0 < na; r0 += kBlock)
+        for (int c0 = 0; c0 < nb; c0 += cw) items.push_back({ge, r0, c0, std::min(cw, nb - c0)});
+    }
+  }
+  edge0[n] = (int)eds.size();
+  if (eds.empty()) return GMOT_OK;
+  void* buf = nullptr;
+  const size_t b_ed = align_up(sizeof(EdgeDesc) * eds.size(), 256);
+  const size_t b_it = align_up(sizeof(PairItem) * items.size(), 256);
+  const size_t b_out = sizeof(double4) * items.size();
+  if (hipMalloc(&buf, b_ed + b_it + b_out) != hipSuccess) return fail(GMOT_ENOMEM, "evaluation buffers");
+  char* base = (char*)buf;
+  std::vector<double4> parts(items.size());
+  std::vector<double4> ne(pl->total_nodes);
+  hipError_t e1 = hipMemcpyAsync(base, eds.data(), sizeof(EdgeDesc) * eds.size(), hipMemcpyHostToDevice, s);
+  if (e1 == hipSuccess)
+    e1 = hipMemcpyAsync(base + b_ed, items.data(), sizeof(PairItem) * items.size(), hipMemcpyHostToDevice, s);
+  if (e1 == hipSuccess)
+    e1 = launch_pairs((EdgeDesc*)base, (PairItem*)(base + b_ed), (int)items.size(), (double4*)(base + b_ed + b_it), s);
+  if (e1 == hipSuccess)
+    e1 = hipMemcpyAsync(parts.data(), base + b_ed + b_it, b_out, hipMemcpyDeviceToHost, s);
+  if (e1 == hipSuccess)
+    e1 = hipMemcpyAsync(ne.data(), pl->d_node_eval, sizeof(double4) * pl->total_nodes, hipMemcpyDeviceToHost, s);
+  if (e1 == hipSuccess) e1 = hipStreamSynchronize(s);
+  (void)hipFree(buf);
+  if (e1 != hipSuccess) return fail(GMOT_EDEVICE, std::string("evaluation: ") + hipGetErrorString(e1));
+  std::vector<double> T(eds.size(), 0.0), H(eds.size(), 0.0), M(eds.size(), 0.0);
+  for (size_t k = 0; k < items.size(); ++k) {
+    const int e = items[k].edge;
+    T[e] += parts[k].x;
+    H[e] += parts[k].y;
+    M[e] += parts[k].z;
+  }
+  for (size_t i = 0; i < n; ++i) {
+    const gmot_problem* p = pl->probs[i];
+    gmot_eval* out = &outs[i];
+    if (p->E == 0) continue;
+    double Tsum = 0, Hsum = 0, Msum = 0, mmin = INFINITY, mmax = -INFINITY;
+    for (int e = edge0[i]; e < edge0[i + 1]; ++e) {
+      Tsum += T[e];
+      Hsum += H[e];
+      Msum += M[e];
+      mmin = std::min(mmin, M[e]);
+      mmax = std::max(mmax, M[e]);
+    }
+    double err = 0, errm = 0, lin = 0, rho = 0, spread = 0, scale = p->eps * p->E;
+    for (int c = 0; c < 2; ++c) {
+      const int i0 = pl->inst[i].node0[c], cnt = pl->inst[i].nnodes[c];
+      for (int q = i0; q < i0 + cnt; ++q) {
+        const NodeItem& nd = pl->nodes[c][q];
+        const double4 v = ne[nd.err_idx];
+        err += v.x;
+        errm = std::max(errm, v.y);
+        if (nd.fixed) {
+          lin += v.z;
+          scale += p->eps * std::fabs(v.z);
+        } else {
+          rho += v.z;
+          scale += p->eps * std::fabs(v.z);
+          spread = std::max(spread, v.w);
+        }
+      }
+    }
+    out->dual = p->eps * (lin + rho - Msum);
+    out->transport = Tsum;
+    out->primal = Tsum + p->eps * Hsum;
+    out->gap = out->primal - out->dual;
+    out->err_sum = err;
+    out->err_max = errm;
+    out->mass_min = mmin;
+    out->mass_max = mmax;
+    out->rho_spread = spread;
+    out->scale = scale;
+  }
+  return GMOT_OK;
 }
 
 // ---------------------------------------------------------------------------
@@ -1451,81 +1676,7 @@ int gmot_evaluate(gmot_problem* p, gmot_eval* out) {
   HIPCHK(hipSetDevice(p->ctx->device));
   int rc = ensure_plan(p);
   if (rc) return rc;
-  Plan* pl = p->plan;
-  hipStream_t s = p->ctx->stream;
-  rc = eval_messages(p, -1);
-  if (rc) return rc;
-  // pair pass
-  std::vector<EdgeDesc> eds;
-  std::vector<PairItem> items;
-  for (int e = 0; e < p->E; ++e) {
-    eds.push_back(edge_desc(p, e));
-    const int na = eds.back().n_a, nb = eds.back().n_b;
-    const int cw = 2048;
-    for (int r0 = 0; r0 < na; r0 += kBlock)
-      for (int c0 = 0; c0 < nb; c0 += cw) items.push_back({e, r0, c0, std::min(cw, nb - c0)});
-  }
-  void* buf = nullptr;
-  const size_t b_ed = align_up(sizeof(EdgeDesc) * eds.size(), 256);
-  const size_t b_it = align_up(sizeof(PairItem) * items.size(), 256);
-  const size_t b_out = sizeof(double4) * items.size();
-  if (hipMalloc(&buf, b_ed + b_it + b_out) != hipSuccess) return fail(GMOT_ENOMEM, "evaluation buffers");
-  char* base = (char*)buf;
-  std::vector<double4> parts(items.size());
-  std::vector<double4> ne(pl->total_nodes);
-  hipError_t e1 = hipMemcpyAsync(base, eds.data(), sizeof(EdgeDesc) * eds.size(), hipMemcpyHostToDevice, s);
-  if (e1 == hipSuccess)
-    e1 = hipMemcpyAsync(base + b_ed, items.data(), sizeof(PairItem) * items.size(), hipMemcpyHostToDevice, s);
-  if (e1 == hipSuccess)
-    e1 = launch_pairs((EdgeDesc*)base, (PairItem*)(base + b_ed), (int)items.size(), (double4*)(base + b_ed + b_it), s);
-  if (e1 == hipSuccess)
-    e1 = hipMemcpyAsync(parts.data(), base + b_ed + b_it, b_out, hipMemcpyDeviceToHost, s);
-  if (e1 == hipSuccess)
-    e1 = hipMemcpyAsync(ne.data(), pl->d_node_eval, sizeof(double4) * pl->total_nodes, hipMemcpyDeviceToHost, s);
-  if (e1 == hipSuccess) e1 = hipStreamSynchronize(s);
-  (void)hipFree(buf);
-  if (e1 != hipSuccess) return fail(GMOT_EDEVICE, std::string("evaluation: ") + hipGetErrorString(e1));
-  std::vector<double> T(p->E, 0.0), H(p->E, 0.0), M(p->E, 0.0);
-  for (size_t i = 0; i < items.size(); ++i) {
-    const int e = items[i].edge;
-    T[e] += parts[i].x;
-    H[e] += parts[i].y;
-    M[e] += parts[i].z;
-  }
-  double Tsum = 0, Hsum = 0, Msum = 0, mmin = INFINITY, mmax = -INFINITY;
-  for (int e = 0; e < p->E; ++e) {
-    Tsum += T[e];
-    Hsum += H[e];
-    Msum += M[e];
-    mmin = std::min(mmin, M[e]);
-    mmax = std::max(mmax, M[e]);
-  }
-  double err = 0, errm = 0, lin = 0, rho = 0, spread = 0, scale = p->eps * p->E;
-  for (int c = 0; c < 2; ++c)
-    for (const NodeItem& nd : pl->nodes[c]) {
-      const double4 v = ne[nd.err_idx];
-      err += v.x;
-      errm = std::max(errm, v.y);
-      if (nd.fixed) {
-        lin += v.z;
-        scale += p->eps * std::fabs(v.z);
-      } else {
-        rho += v.z;
-        scale += p->eps * std::fabs(v.z);
-        spread = std::max(spread, v.w);
-      }
-    }
-  out->dual = p->eps * (lin + rho - Msum);
-  out->transport = Tsum;
-  out->primal = Tsum + p->eps * Hsum;
-  out->gap = out->primal - out->dual;
-  out->err_sum = err;
-  out->err_max = errm;
-  out->mass_min = mmin;
-  out->mass_max = mmax;
-  out->rho_spread = spread;
-  out->scale = scale;
-  return GMOT_OK;
+  return evaluate_plan(p->plan, out);
 }
 
 int gmot_round(gmot_problem* p, gmot_round_result* out, double* edge_transport) {
@@ -1663,7 +1814,7 @@ int gmot_get_node_marginal(gmot_problem* p, int32_t node, double* out) {
   HIPCHK(hipSetDevice(p->ctx->device));
   int rc = ensure_plan(p);
   if (rc) return rc;
-  rc = eval_messages(p, p->colour[node]);
+  rc = eval_messages(p->plan, p->colour[node]);
   if (rc) return rc;
   HIPCHK(hipStreamSynchronize(p->ctx->stream));
   HIPCHK(hipMemcpy(out, p->d_qbar + p->node_off[node], sizeof(double) * p->sizes[node], hipMemcpyDeviceToHost));
@@ -1710,6 +1861,12 @@ int gmot_batch_solve(gmot_batch* b, const gmot_opts* o, gmot_result* outs) {
       if (rc) return rc;
     }
   return solve_plan(b->plan, o, outs);
+}
+
+int gmot_batch_evaluate(gmot_batch* b, gmot_eval* outs) {
+  if (!b || !outs) return fail(GMOT_EINVAL, "null batch or output");
+  HIPCHK(hipSetDevice(b->ctx->device));
+  return evaluate_plan(b->plan, outs);
 }
 
 int gmot_problem_autotune(gmot_problem* p, int32_t* waves_per_block, int32_t* rows_per_lane, int32_t* lane_groups,
