@@ -211,6 +211,52 @@ int  gmot_get_coupling(gmot_problem* p, int32_t edge, double* out);
 /* q_bar_j: arithmetic mean over neighbours k of B_(j,k) 1 (n_j values). */
 int  gmot_get_node_marginal(gmot_problem* p, int32_t node, double* out);
 
+/* ---- general graphs: modified junction trees -------------------------------------
+ * Coupled MOT on a modified junction tree (Section 4: Definition jt_general,
+ * eq. ot_graph_local_reg): separators alternate with cost cliques, every cost
+ * clique has exactly two neighbouring separators, and the separator--clique
+ * graph is a tree (n_cliques = n_seps - 1, connected).  Supported class: each
+ * clique's variables are the variables of its two separators (every variable
+ * belongs to exactly one separator, so the two sets are disjoint), and a
+ * constraint fixes the joint marginal of all of a separator's variables.  The
+ * Wasserstein least-squares problem of Section 2 on its modified junction tree
+ * is of this class.  Every intersection of a separator with a neighbouring
+ * clique is then the separator itself, and the separator update of
+ * Proposition general_algo becomes the node update of Algorithm
+ * tree_local_reg on the tree whose nodes are the separators: node s has one
+ * state per joint state of its variables (C order over them), edge c carries
+ * the clique's cost tensor read as a (states of a) x (states of b) matrix.
+ * The library builds that problem (explicit FP32 costs) and returns it as an
+ * ordinary gmot_problem: gmot_solve, gmot_evaluate, the batch calls and the
+ * potential, coupling and node-marginal read-backs apply, in clique order for
+ * potentials (log u of separator a, then of b, per clique), with couplings =
+ * clique plans B_c as (states of a) x (states of b) matrices and node
+ * marginals = separator marginals.  The caller owns every array. */
+typedef struct {
+  int32_t        n_vars;       /* variables, >= 1                                             */
+  const int32_t* var_sizes;    /* [n_vars]: support size of each variable, >= 1                */
+  int32_t        n_seps;       /* separators, >= 1                                            */
+  const int32_t* sep_nvars;    /* [n_seps]: variables of each separator, >= 1                  */
+  const int32_t* sep_vars;     /* concatenated variable indices of the separators, in tensor-axis
+                                  order; every variable appears exactly once                  */
+  const uint8_t* sep_fixed;    /* [n_seps]: 1 if the separator's joint marginal is given        */
+  const double*  sep_marginal; /* joint marginals of the fixed separators, concatenated in
+                                  separator order, each in C order over its variables; entries
+                                  >= 0, each sums to 1 within 1e-9                             */
+  int32_t        n_cliques;    /* cost cliques, = n_seps - 1                                  */
+  const int32_t* cliques;      /* [2 * n_cliques]: the two neighbouring separators (a, b)      */
+  const float*   clique_cost;  /* concatenated cost tensors C_c over (variables of a, variables
+                                  of b), C order, in clique order                              */
+  double         eps;          /* regularisation, > 0                                         */
+} gmot_junction_desc;
+
+/* Validate `desc` (GMOT_EINVAL: a variable in no or several separators, a bad
+ * size, a clique count or pair that does not form a tree, more than 2^31 - 1
+ * joint states in a separator; GMOT_EMARGINAL as for trees) and create the
+ * problem.  first_color as in gmot_problem_create (separator 0's class by
+ * default). */
+int  gmot_junction_create(gmot_ctx* ctx, const gmot_junction_desc* desc, int32_t first_color, gmot_problem** out);
+
 /* ---- rounding (Algorithm round) -------------------------------------------------- */
 /* After a half-sweep the class S that was not updated last (the one the next
  * half-sweep would update) misses its marginals.  gmot_round rounds every plan

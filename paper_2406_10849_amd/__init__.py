@@ -227,6 +227,55 @@ class Problem:
         return out
 
 
+class JunctionTree(Problem):
+    """A coupled MOT problem on a modified junction tree (gmot_junction_create),
+    from any object with the fields of ``workloads.JunctionProblem``.  It is a
+    Problem over separators: potentials in clique order, couplings are clique
+    plans as (states of a) x (states of b) matrices, node marginals are
+    separator marginals (flattened in C order)."""
+
+    def __init__(self, ctx: Context, jp, first_color: int = -1):
+        self._lib = ctx._lib
+        self.ctx = ctx
+        keep = []
+        d = _lib.JunctionDesc()
+        vs = _as(jp.var_sizes, np.int32)
+        keep.append(vs)
+        d.n_vars = int(vs.shape[0])
+        d.var_sizes = vs.ctypes.data_as(_lib.I32P)
+        seps = [tuple(int(v) for v in sv) for sv in jp.separators]
+        nv = _as([len(sv) for sv in seps], np.int32)
+        sv = _as([v for t in seps for v in t], np.int32)
+        keep += [nv, sv]
+        d.n_seps = len(seps)
+        d.sep_nvars = nv.ctypes.data_as(_lib.I32P)
+        d.sep_vars = sv.ctypes.data_as(_lib.I32P)
+        fx = _as([1 if f else 0 for f in jp.sep_fixed], np.uint8)
+        keep.append(fx)
+        d.sep_fixed = fx.ctypes.data_as(C.POINTER(C.c_uint8))
+        mg = [np.asarray(jp.sep_marginal[s], dtype=np.float64).reshape(-1) for s in range(len(seps)) if jp.sep_fixed[s]]
+        mg = _as(np.concatenate(mg) if mg else np.zeros(1), np.float64)
+        keep.append(mg)
+        d.sep_marginal = mg.ctypes.data_as(_lib.DP)
+        cl = _as(jp.cliques, np.int32).reshape(-1)
+        keep.append(cl)
+        d.n_cliques = len(jp.cliques)
+        d.cliques = cl.ctypes.data_as(_lib.I32P)
+        cost = [np.asarray(c, dtype=np.float32).reshape(-1) for c in jp.clique_cost]
+        cst = _as(np.concatenate(cost) if cost else np.zeros(1), np.float32)
+        keep.append(cst)
+        d.clique_cost = cst.ctypes.data_as(C.POINTER(C.c_float))
+        d.eps = float(jp.eps)
+        h = C.c_void_p()
+        _check(self._lib.gmot_junction_create(ctx._h, C.byref(d), int(first_color), C.byref(h)),
+               "gmot_junction_create")
+        self._h = h
+        self.n_nodes = len(seps)
+        self.edges = _as(jp.cliques, np.int32).reshape(-1, 2)
+        self.sizes = _as([int(np.prod([jp.var_sizes[v] for v in t])) for t in seps], np.int32)
+        self.n_pot = int(self._lib.gmot_potentials_size(h))
+
+
 class Batch:
     """Many problems advanced by the same launches."""
 
@@ -374,5 +423,5 @@ def last_tiles() -> dict:
             "blocks_c1": v[3].value}
 
 
-__all__ = ["Context", "Problem", "Batch", "MLP", "GmotError", "last_tiles", "star_features", "star_targets",
+__all__ = ["Context", "Problem", "JunctionTree", "Batch", "MLP", "GmotError", "last_tiles", "star_features", "star_targets",
            "star_apply", "STATUS_NAMES"]

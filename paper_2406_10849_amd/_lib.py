@@ -42,6 +42,22 @@ class TreeDesc(C.Structure):
     ]
 
 
+class JunctionDesc(C.Structure):
+    _fields_ = [
+        ("n_vars", C.c_int32),
+        ("var_sizes", C.POINTER(C.c_int32)),
+        ("n_seps", C.c_int32),
+        ("sep_nvars", C.POINTER(C.c_int32)),
+        ("sep_vars", C.POINTER(C.c_int32)),
+        ("sep_fixed", C.POINTER(C.c_uint8)),
+        ("sep_marginal", C.POINTER(C.c_double)),
+        ("n_cliques", C.c_int32),
+        ("cliques", C.POINTER(C.c_int32)),
+        ("clique_cost", C.POINTER(C.c_float)),
+        ("eps", C.c_double),
+    ]
+
+
 class Opts(C.Structure):
     _fields_ = [
         ("tol", C.c_double),
@@ -102,6 +118,7 @@ SIGNATURES = {
     "gmot_ctx_create": (C.c_int, [C.POINTER(VP), C.c_int, VP]),
     "gmot_ctx_destroy": (None, [VP]),
     "gmot_problem_create": (C.c_int, [VP, C.POINTER(TreeDesc), C.c_int32, C.POINTER(VP)]),
+    "gmot_junction_create": (C.c_int, [VP, C.POINTER(JunctionDesc), C.c_int32, C.POINTER(VP)]),
     "gmot_problem_destroy": (None, [VP]),
     "gmot_solve": (C.c_int, [VP, C.POINTER(Opts), C.POINTER(Result)]),
     "gmot_evaluate": (C.c_int, [VP, C.POINTER(Eval)]),

@@ -1645,6 +1645,50 @@ int gmot_problem_create(gmot_ctx* ctx, const gmot_tree_desc* desc, int32_t first
   return GMOT_OK;
 }
 
+int gmot_junction_create(gmot_ctx* ctx, const gmot_junction_desc* d, int32_t first_color, gmot_problem** out) {
+  if (!ctx || !d || !out) return fail(GMOT_EINVAL, "null argument");
+  if (d->n_vars < 1 || d->n_seps < 1 || !d->var_sizes || !d->sep_nvars || !d->sep_vars || !d->sep_fixed)
+    return fail(GMOT_EINVAL, "a junction tree needs variables and separators");
+  if (d->n_cliques != d->n_seps - 1) return fail(GMOT_EINVAL, "a junction tree has one clique fewer than separators");
+  if (d->n_cliques > 0 && (!d->cliques || !d->clique_cost)) return fail(GMOT_EINVAL, "null clique arrays");
+  for (int v = 0; v < d->n_vars; ++v)
+    if (d->var_sizes[v] < 1) return fail(GMOT_EINVAL, "a variable needs at least one support point");
+  // every variable in exactly one separator; joint state counts per separator
+  std::vector<int> owner(d->n_vars, -1);
+  std::vector<int32_t> sizes(d->n_seps, 1);
+  int64_t o = 0;
+  for (int s = 0; s < d->n_seps; ++s) {
+    if (d->sep_nvars[s] < 1) return fail(GMOT_EINVAL, "a separator needs at least one variable");
+    int64_t states = 1;
+    for (int i = 0; i < d->sep_nvars[s]; ++i) {
+      const int v = d->sep_vars[o + i];
+      if (v < 0 || v >= d->n_vars) return fail(GMOT_EINVAL, "separator variable index out of range");
+      if (owner[v] >= 0) return fail(GMOT_EINVAL, "a variable may belong to one separator only");
+      owner[v] = s;
+      states *= d->var_sizes[v];
+      if (states > INT32_MAX) return fail(GMOT_EINVAL, "too many joint states in a separator");
+    }
+    o += d->sep_nvars[s];
+    sizes[s] = (int32_t)states;
+  }
+  for (int v = 0; v < d->n_vars; ++v)
+    if (owner[v] < 0) return fail(GMOT_EINVAL, "every variable must belong to a separator");
+  // the tree over separators: edges are the cliques, costs their tensors read as matrices
+  gmot_tree_desc td{};
+  td.n_nodes = d->n_seps;
+  td.n_edges = d->n_cliques;
+  td.edges = d->cliques;
+  td.sizes = sizes.data();
+  td.dim = 1;
+  td.support = nullptr;
+  td.is_fixed = d->sep_fixed;
+  td.marginal = d->sep_marginal;
+  td.cost_kind = GMOT_COST_EXPLICIT;
+  td.cost = d->clique_cost;
+  td.eps = d->eps;
+  return gmot_problem_create(ctx, &td, first_color, out);
+}
+
 void gmot_problem_destroy(gmot_problem* p) {
   if (!p) return;
   (void)hipStreamSynchronize(p->ctx->stream);
