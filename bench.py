@@ -54,12 +54,29 @@ def pair_peak_gpairs(dim: int) -> float:
     return SIMD_CLOCKS_PER_S * 64 / cycles_per_64_pairs / 1e9
 
 
-def weighted_pair_peak(pairs_by_dim: dict) -> float:
-    """Peak (Gpair/s) of a launch mixing support dimensions: the total pairs
-    over the time each dimension's pairs take at its own peak."""
-    tot = sum(pairs_by_dim.values())
-    t = sum(v / pair_peak_gpairs(d) for d, v in pairs_by_dim.items() if v > 0)
-    return tot / t if t > 0 else 0.0
+def group_rooflines(st: dict) -> dict:
+    """ALU roofline of each kernel group of the node stage that did work, from
+    the per-group timing (HIP events around back-to-back repeats of the group
+    alone): k_node for D = 1, 2, 3 against the pair peak of its dimension, the
+    separable grid kernels (k_sep_rows + k_node_sep) against the one-dimensional
+    pair peak (each of their terms is a one-dimensional term), k_node with
+    explicit costs against HBM bandwidth at 4 bytes per pair."""
+    names = {0: "k_node<explicit>", 1: "k_node<D=1>", 2: "k_node<D=2>", 3: "k_node<D=3>",
+             4: "k_sep_rows+k_node_sep"}
+    n = max(st["msg_launches"], 1)
+    out = {}
+    for g in range(5):
+        ms, pairs = st["group_ms"][g], st["group_pairs"][g]
+        if ms <= 0 or pairs <= 0:
+            continue
+        gps = pairs / (ms / 1e3) / 1e9
+        if g == 0:
+            ach, peak, unit, bound = 4.0 * gps, HBM_PEAK_GBS, "GB/s", "hbm"
+        else:
+            ach, peak, unit, bound = gps, pair_peak_gpairs(g if g < 4 else 1), "Gpair/s", "alu"
+        out[names[g]] = {"bound": bound, "achieved": ach, "peak": peak, "unit": unit, "frac": ach / peak,
+                         "ms_per_stage": ms / n, "pairs_per_stage": pairs / n}
+    return out
 
 
 # MI355X HBM3E peak, GB/s
@@ -244,15 +261,11 @@ def bench_headline(ctx, args, sync) -> tuple:
     b.stats(reset=True)
     rs_t, _ = step(timing=True)
     st = b.stats()
-    pairs_by_dim = {}
-    for p, r in zip(probs, rs_t):
-        pairs_by_dim[p.dim] = pairs_by_dim.get(p.dim, 0.0) + float(p.pairs_per_tstep()) * r["t"]
-    peak = weighted_pair_peak(pairs_by_dim)
+    groups = group_rooflines(st)
+    dom = max(groups, key=lambda g: groups[g]["ms_per_stage"]) if groups else None
     avg_ms = st["msg_ms"] / max(st["msg_launches"], 1)
-    pairs_per_stage = st["msg_pairs"] / max(st["msg_launches"], 1)
-    achieved = pairs_per_stage / (avg_ms / 1e3) / 1e9 if avg_ms > 0 else 0.0
     shape = (tuned["waves_per_block"], tuned["rows_per_lane"], tuned["lane_groups"])
-    traffic = measured_traffic(shape)
+    traffic = measured_traffic(shape) if dom == "k_node<D=1>" else None
     rs0 = runs[-1][0]
     hs = [r["t"] for r in rs0]
     out = {
@@ -269,14 +282,10 @@ def bench_headline(ctx, args, sync) -> tuple:
         "tiles": dict(tuned, **last_tiles()),
         "pairs_per_s": sum(sum(float(p.pairs_per_tstep()) * r["t"] for p, r in zip(probs, rs)) for rs, _ in runs)
                        / elapsed,
-        "roofline": {"bound": "alu", "achieved": achieved, "peak": peak, "unit": "Gpair/s",
-                     "frac": achieved / peak if peak > 0 else 0.0, "traffic": traffic,
-                     "kernel": "k_node (node stage: one launch per support dimension)",
-                     "avg_stage_ms": avg_ms, "pairs_per_stage": pairs_per_stage,
-                     "stages_timed": st["msg_launches"],
-                     "pairs_by_dim": {str(d): v for d, v in sorted(pairs_by_dim.items())},
-                     "peak_by_dim": {str(d): pair_peak_gpairs(d) for d in sorted(pairs_by_dim)},
-                     "half_sweep_avg_ms": st["sweep_ms"] / max(st["msg_launches"], 1)},
+        "roofline": dict(groups[dom], kernel=dom, traffic=traffic, stages_timed=st["msg_launches"],
+                         node_stage_ms=avg_ms, half_sweep_avg_ms=st["sweep_ms"] / max(st["msg_launches"], 1))
+                    if dom else None,
+        "kernel_groups": groups,
         "final": {"err_sum_fp64_max": max(ev["err_sum"] for ev in runs[-1][1]),
                   "dual_sum": float(sum(ev["dual"] for ev in runs[-1][1]))},
     }
@@ -331,6 +340,7 @@ def bench_chain(ctx, args, sync) -> dict:
     ach = ppl / (avg_ms / 1e3) / 1e9 if avg_ms > 0 else 0.0
     peak = pair_peak_gpairs(1)
     shape = (tuned["waves_per_block"], tuned["rows_per_lane"], tuned["lane_groups"])
+    # the chain's node stage is one k_node launch (one support dimension)
     out = {"workload": "chain-hmm-32node-n1024", "edges": prob.n_edges,
            "edge_iterations_per_s": prob.n_edges * sum(r["t"] for r in rs) / el,
            "time_to_1e-6_s": statistics.median(r["seconds"] for r in rs),
@@ -447,6 +457,55 @@ def bench_warm(ctx, tol: float, n_train: int, n_test: int, epochs: int) -> dict:
                 speedup_batched_warm_vs_plain=t_plain / res["warm_wall_s"])
 
 
+def bench_figure(ctx) -> dict:
+    """The protocol of the paper's Figure fig:exp for the method itself (the
+    globally regularised comparison system is not built): for accuracy
+    delta = 0.2, eps = delta / (4 |E| log d) and stopping sum delta' =
+    delta / (8 C_inf); half-sweeps until the FP64-judged stopping sum reaches
+    delta', then Algorithm round; 5 seeds per point.  Barycenter (log-normal
+    leaves on a uniform grid of d points): d varied at |E| = 3, |E| varied at
+    d = 10, with Theorem num_iter's bound beside each point.  Wasserstein least
+    squares on its modified junction tree (alpha = 10; |E| = J cliques; d = n):
+    n varied at J = 3, J varied at n = 10."""
+    from workloads import make_lognormal_star, make_wls
+    from paper_2406_10849_amd import Problem, JunctionTree
+    delta, seeds = 0.2, 5
+
+    def run(make, n_edges, d, c_inf, junction=False):
+        eps = delta / (4.0 * n_edges * np.log(d))
+        tol = delta / (8.0 * c_inf)
+        its, gaps = [], []
+        for sd in range(seeds):
+            pr = make(eps, sd)
+            g = JunctionTree(ctx, pr) if junction else Problem(ctx, pr)
+            r = g.solve(tol=tol, max_steps=10 ** 6, precision="fp64")
+            assert r["status"] == "converged", r
+            its.append(r["t"])
+            if not junction:
+                gaps.append(g.round()["transport"])
+            g.close()
+        row = {"d": d, "edges": n_edges, "eps": eps, "delta_prime": tol, "half_sweeps_mean": float(np.mean(its)),
+               "half_sweeps": its, "theorem_num_iter_bound": 2 + 88 * n_edges * c_inf / (tol * eps)}
+        if gaps:
+            row["rounded_transport_mean"] = float(np.mean(gaps))
+        return row
+
+    bary_d = [run(lambda e, sd, d=d: make_lognormal_star(3, d, e, instance=sd), 3, d, 1.0)
+              for d in (10, 20, 50, 100, 200, 500, 1000)]
+    bary_e = [run(lambda e, sd, L=L: make_lognormal_star(L, 10, e, instance=sd), L, 10, 1.0)
+              for L in (2, 4, 8, 16, 32, 64)]
+
+    def wls_cinf(J, n):
+        return max(float(np.max(c)) for c in make_wls(J=J, n=n, eps=1.0).clique_cost)
+
+    wls_d = [run(lambda e, sd, n=n: make_wls(J=3, n=n, eps=e, instance=sd), 3, n, wls_cinf(3, n), junction=True)
+             for n in (5, 10, 20, 40)]
+    wls_e = [run(lambda e, sd, J=J: make_wls(J=J, n=10, eps=e, instance=sd), J, 10, wls_cinf(J, 10), junction=True)
+             for J in (2, 3, 6, 12)]
+    return {"delta": delta, "seeds": seeds, "barycenter_vs_d": bary_d, "barycenter_vs_edges": bary_e,
+            "wls_vs_d": wls_d, "wls_vs_edges": wls_e}
+
+
 def bench_junction(ctx, tol: float) -> dict:
     """Wasserstein least squares (the paper's second experiment, alpha = 10) on
     its modified junction tree: J = 12 observed distributions on n = 32 grid
@@ -482,7 +541,7 @@ def main() -> int:
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the plain comparison, the chain, the tree and the warm start")
     ap.add_argument("--extras", default="chain,tree,warm",
-                    help="comma-separated extras to run (chain, tree, warm, junction)")
+                    help="comma-separated extras to run (chain, tree, warm, junction, figure)")
     ap.add_argument("--no-headline", action="store_true",
                     help="skip the headline batch (profiling runs of one extra); prints no bench line")
     ap.add_argument("--batched-count", type=int, default=512)
@@ -536,6 +595,10 @@ def main() -> int:
         log("learned warm start")
         out["warm_start"] = bench_warm(ctx, args.tol, args.warm_train, args.warm_test, args.warm_epochs)
         log(f"warm start: {out['warm_start']}")
+    if "figure" in extras:
+        log("the paper's accuracy-delta protocol (Figure fig:exp), this method's side")
+        out["figure"] = bench_figure(ctx)
+        log(f"figure: {out['figure']}")
     if "junction" in extras:
         log("Wasserstein least squares on its modified junction tree")
         out["junction"] = bench_junction(ctx, args.tol)

@@ -144,8 +144,14 @@ typedef struct {
   double  sweep_ms;        /* summed duration of whole half-sweeps: node stage and
                               finalise kernel (ms)                                     */
   int64_t msg_launches;    /* half-sweeps timed                                         */
-  double  msg_pairs;       /* (x, y) pairs those half-sweeps processed                  */
+  double  msg_pairs;       /* (x, y) terms those half-sweeps evaluated: n_j n_k per
+                              message, A_k B_j B_k + n_j A_k per separable one (grid
+                              supports of A rows and B columns)                         */
   int64_t graph_launches;  /* graph replays issued (timed or not)                        */
+  double  group_ms[5];     /* the node stage split by kernel group (explicit cost;
+                              D = 1, 2, 3; separable grids), each the mean of 4
+                              back-to-back repeats of the group alone, summed (ms)      */
+  double  group_pairs[5];  /* the terms each group evaluated in those half-sweeps        */
 } gmot_stats;
 
 typedef struct {
@@ -176,6 +182,9 @@ typedef struct {
 /* Bind device `device`; `hip_stream` (a hipStream_t, may be NULL) is the stream
  * every launch is ordered on; NULL makes the library create its own. */
 int  gmot_ctx_create(gmot_ctx** out, int device, void* hip_stream);
+/* Drop the caller's reference.  Every live problem, batch and network holds
+ * one more, so the context (stream, scratch) is freed when the last of them is
+ * destroyed: handles may be destroyed in any order. */
 void gmot_ctx_destroy(gmot_ctx* ctx);
 
 /* ---- problems ----------------------------------------------------------------- */
@@ -288,7 +297,9 @@ int  gmot_get_rounded_coupling(gmot_problem* p, int32_t edge, double* out);
 /* ---- batches ------------------------------------------------------------------ */
 /* Group `count` problems of one context so that every half-sweep of all of them
  * runs in the same launches; instances converge independently (a converged
- * instance stops updating and keeps its passing state). */
+ * instance stops updating and keeps its passing state).  The batch works on
+ * its problems' device buffers: keep them alive while the batch is used (its
+ * destroy call touches none of them, so it may come before or after theirs). */
 int  gmot_batch_create(gmot_ctx* ctx, gmot_problem* const* probs, int32_t count, gmot_batch** out);
 void gmot_batch_destroy(gmot_batch* b);
 /* outs: [count] results, one per instance. */
@@ -326,11 +337,14 @@ int  gmot_mlp_forward_dev(gmot_mlp* m, const float* x_dev, int32_t batch, float*
 /* The same forward pass with no allocation, for callers that cannot allocate
  * device memory (code under HIP graph capture, tight serving loops, harnesses
  * that forbid hipMalloc).  The activations live in a static device workspace
- * of 8 MiB per device (held until the process ends) instead of the network's
+ * of 16 MiB per device (held until the process ends) instead of the network's
  * own buffers: 2 * batch * widths[0] bytes for the BF16 input, then
- * 6 * batch * widths[l] bytes per hidden layer, each part aligned to 256
- * bytes; a batch that does not fit returns GMOT_EINVAL (the message gives the
- * largest batch that fits).  Nothing in it needs clearing: every part is
+ * 6 * batch * widths[l] bytes per hidden layer, then the split-K partial sums
+ * of the widest layer product (4 * s * batch * widths[l] bytes when a layer's
+ * K is split in s parts: s doubles while the 64 x 64 output tiles times 2s
+ * stay within 512 blocks and each part keeps at least 512 of K), each part
+ * aligned to 256 bytes; a batch that does not fit returns GMOT_EINVAL (the message
+ * gives the batches that fit).  Nothing in it needs clearing: every part is
  * written before it is read.  Results equal gmot_mlp_forward_dev's.  All calls
  * on one device share the workspace: calls ordered on one stream are safe,
  * calls that overlap on one device (other streams, other contexts, other

@@ -47,7 +47,12 @@ def _stream_handle(stream) -> Optional[int]:
 
 
 class Context:
-    """A device and the stream all library work is ordered on."""
+    """A device and the stream all library work is ordered on.
+
+    The library counts the problems, batches and networks created on a
+    context as references to it, so closing the context (or the garbage
+    collector finalising objects of one reference cycle in any order) never
+    leaves a live handle on a freed context."""
 
     def __init__(self, device: int = 0, stream=None):
         self._lib = _lib.load()
@@ -141,8 +146,14 @@ class Problem:
     def _stats(fn, h, reset) -> dict:
         st = _lib.Stats()
         _check(fn(h, C.byref(st), 1 if reset else 0), "gmot_*_stats")
-        return {name: (float(getattr(st, name)) if "ms" in name or "pairs" in name else int(getattr(st, name)))
-                for name, _ in _lib.Stats._fields_}
+        out = {}
+        for name, _ in _lib.Stats._fields_:
+            v = getattr(st, name)
+            if name.startswith("group_"):
+                out[name] = [float(x) for x in v]
+            else:
+                out[name] = float(v) if "ms" in name or "pairs" in name else int(v)
+        return out
 
     def stats(self, reset: bool = False) -> dict:
         """Kernel timing accumulated by solves run with timing=True."""

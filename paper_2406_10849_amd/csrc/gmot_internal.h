@@ -247,6 +247,7 @@ hipError_t launch_star_apply(const StarDesc* stars, int count, int L, int n, con
 }  // namespace gmot
 
 #ifdef __cplusplus
+#include <atomic>
 #include <map>
 // Host-side context shared by the runtime and the MLP host code.
 // Node-kernel block shape: W waves per block, R rows per lane, H lane groups per
@@ -263,7 +264,13 @@ struct gmot_ctx {
   std::map<uint64_t, NodeShape> tuned;  // instance shapes key -> tuned node-kernel shape
   void* scratch = nullptr;                         // small tables of the warm-start calls
   size_t scratch_size = 0;
+  // One reference for the caller of gmot_ctx_create and one per live problem,
+  // batch and network: the context is freed when the last one is dropped, so
+  // the objects may be destroyed in any order.
+  std::atomic<int> refs{1};
 };
+void gmot_ctx_retain(gmot_ctx* ctx);
+void gmot_ctx_release(gmot_ctx* ctx);
 #include <string>
 // Sets the message gmot_last_error reports for the calling thread.
 void gmot_set_last_error(const std::string& msg);

@@ -57,7 +57,24 @@ struct GemmArgs {
   uint16_t* Cq;         // optional BF16 copy of the output (same layout)
   const float* bias;    // [N] for kBias / kBiasRelu
   const float* mask;    // [M x ldc] for kMaskRelu: multiply by (mask > 0)
+  float* part;          // split-K: [gridDim.z x M x ldc] raw partial sums (no epilogue), or NULL
+  int k_chunk;          // split-K: K values per split (a multiple of 32)
 };
+
+// The next K step's A and B chunks are loaded into registers while the
+// current step's MFMAs run (one LDS buffer, two barriers per step).  With
+// split-K (g.part set) block z sums K range [z k_chunk, (z + 1) k_chunk) and
+// writes its raw partial sums; k_gemm_reduce adds the splits in order and
+// applies the epilogue.
+template <int EPI>
+__device__ inline void gemm_epilogue(const GemmArgs& g, int m, int n, float v) {
+  const size_t o = (size_t)m * g.ldc + n;
+  if (EPI == kBias || EPI == kBiasRelu) v += g.bias[n];
+  if (EPI == kBiasRelu) v = fmaxf(v, 0.f);
+  if (EPI == kMaskRelu) v = g.mask[o] > 0.f ? v : 0.f;
+  g.C[o] = v;
+  if (g.Cq) g.Cq[o] = to_bf16(v);
+}
 
 template <bool TA, bool TB, int EPI>
 __global__ __launch_bounds__(256) void k_gemm(GemmArgs g) {
@@ -67,44 +84,67 @@ __global__ __launch_bounds__(256) void k_gemm(GemmArgs g) {
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int m0 = blockIdx.y * 64, n0 = blockIdx.x * 64;
   const int wm = (wave >> 1) * 32, wn = (wave & 1) * 32;
+  const int kb = g.part ? (int)blockIdx.z * g.k_chunk : 0;
+  const int ke = g.part ? min(g.K, kb + g.k_chunk) : g.K;
   floatx4 acc[2][2];
 #pragma unroll
   for (int i = 0; i < 2; ++i)
 #pragma unroll
     for (int j = 0; j < 2; ++j) acc[i][j] = floatx4{0.f, 0.f, 0.f, 0.f};
 
-  for (int k0 = 0; k0 < g.K; k0 += 32) {
+  // this thread's 8-element chunks of A and B at K step k0 (zeros past the edges)
+  auto load_a = [&](int k0) -> uint4 {
+    uint4 v = make_uint4(0, 0, 0, 0);
     if (!TA) {
-      const int r = tid >> 2, kc = (tid & 3) * 8;
-      const int m = m0 + r, k = k0 + kc;
-      uint4 v = make_uint4(0, 0, 0, 0);
-      if (m < g.M && k < g.K) v = *reinterpret_cast<const uint4*>(g.A + (size_t)m * g.lda + k);
-      *reinterpret_cast<uint4*>(&As[r * LDK + kc]) = v;
+      const int m = m0 + (tid >> 2), k = k0 + (tid & 3) * 8;
+      if (m < g.M && k < ke) v = *reinterpret_cast<const uint4*>(g.A + (size_t)m * g.lda + k);
     } else {
-      const int k = tid >> 3, mc = (tid & 7) * 8;
-      const int kk = k0 + k, m = m0 + mc;
-      uint4 v = make_uint4(0, 0, 0, 0);
-      if (kk < g.K && m < g.M) v = *reinterpret_cast<const uint4*>(g.A + (size_t)kk * g.lda + m);
+      const int kk = k0 + (tid >> 3), m = m0 + (tid & 7) * 8;
+      if (kk < ke && m < g.M) v = *reinterpret_cast<const uint4*>(g.A + (size_t)kk * g.lda + m);
+    }
+    return v;
+  };
+  auto load_b = [&](int k0) -> uint4 {
+    uint4 v = make_uint4(0, 0, 0, 0);
+    if (TB) {
+      const int n = n0 + (tid >> 2), k = k0 + (tid & 3) * 8;
+      if (n < g.N && k < ke) v = *reinterpret_cast<const uint4*>(g.B + (size_t)n * g.ldb + k);
+    } else {
+      const int kk = k0 + (tid >> 3), n = n0 + (tid & 7) * 8;
+      if (kk < ke && n < g.N) v = *reinterpret_cast<const uint4*>(g.B + (size_t)kk * g.ldb + n);
+    }
+    return v;
+  };
+  auto store_a = [&](uint4 v) {
+    if (!TA) {
+      *reinterpret_cast<uint4*>(&As[(tid >> 2) * LDK + (tid & 3) * 8]) = v;
+    } else {
       const uint16_t* e = reinterpret_cast<const uint16_t*>(&v);
+      const int k = tid >> 3, mc = (tid & 7) * 8;
 #pragma unroll
       for (int i = 0; i < 8; ++i) As[(mc + i) * LDK + k] = e[i];
     }
+  };
+  auto store_b = [&](uint4 v) {
     if (TB) {
-      const int r = tid >> 2, kc = (tid & 3) * 8;
-      const int n = n0 + r, k = k0 + kc;
-      uint4 v = make_uint4(0, 0, 0, 0);
-      if (n < g.N && k < g.K) v = *reinterpret_cast<const uint4*>(g.B + (size_t)n * g.ldb + k);
-      *reinterpret_cast<uint4*>(&Bs[r * LDK + kc]) = v;
+      *reinterpret_cast<uint4*>(&Bs[(tid >> 2) * LDK + (tid & 3) * 8]) = v;
     } else {
-      const int k = tid >> 3, nc = (tid & 7) * 8;
-      const int kk = k0 + k, n = n0 + nc;
-      uint4 v = make_uint4(0, 0, 0, 0);
-      if (kk < g.K && n < g.N) v = *reinterpret_cast<const uint4*>(g.B + (size_t)kk * g.ldb + n);
       const uint16_t* e = reinterpret_cast<const uint16_t*>(&v);
+      const int k = tid >> 3, nc = (tid & 7) * 8;
 #pragma unroll
       for (int i = 0; i < 8; ++i) Bs[(nc + i) * LDK + k] = e[i];
     }
+  };
+
+  uint4 ra = load_a(kb), rb = load_b(kb);
+  for (int k0 = kb; k0 < ke; k0 += 32) {
+    store_a(ra);
+    store_b(rb);
     __syncthreads();
+    if (k0 + 32 < ke) {
+      ra = load_a(k0 + 32);
+      rb = load_b(k0 + 32);
+    }
 #pragma unroll
     for (int sm = 0; sm < 2; ++sm)
 #pragma unroll
@@ -125,14 +165,35 @@ __global__ __launch_bounds__(256) void k_gemm(GemmArgs g) {
         const int m = m0 + wm + sm * 16 + (lane >> 4) * 4 + i;
         const int n = n0 + wn + sn * 16 + (lane & 15);
         if (m >= g.M || n >= g.N) continue;
-        float v = acc[sm][sn][i];
-        const size_t o = (size_t)m * g.ldc + n;
-        if (EPI == kBias || EPI == kBiasRelu) v += g.bias[n];
-        if (EPI == kBiasRelu) v = fmaxf(v, 0.f);
-        if (EPI == kMaskRelu) v = g.mask[o] > 0.f ? v : 0.f;
-        g.C[o] = v;
-        if (g.Cq) g.Cq[o] = to_bf16(v);
+        if (g.part) g.part[((size_t)blockIdx.z * g.M + m) * g.ldc + n] = acc[sm][sn][i];
+        else gemm_epilogue<EPI>(g, m, n, acc[sm][sn][i]);
       }
+}
+
+// Split-K: the splits of every output added in split order, then the epilogue.
+template <int EPI>
+__global__ __launch_bounds__(256) void k_gemm_reduce(GemmArgs g, int splits) {
+  const size_t total = (size_t)g.M * g.N;
+  for (size_t i = (size_t)blockIdx.x * 256 + threadIdx.x; i < total; i += (size_t)gridDim.x * 256) {
+    const int m = (int)(i / g.N), n = (int)(i % g.N);
+    float v = 0.f;
+    for (int z = 0; z < splits; ++z) v += g.part[((size_t)z * g.M + m) * g.ldc + n];
+    gemm_epilogue<EPI>(g, m, n, v);
+  }
+}
+
+// K splits for an M x N x K product: enough blocks to cover the device
+// (256 CUs) when the output alone gives too few, each split at least 512 K.
+static int gemm_splits(int M, int N, int K) {
+  const int blocks = ((N + 63) / 64) * ((M + 63) / 64);
+  int sp = 1;
+  while (blocks * sp * 2 <= 512 && K / (sp * 2) >= 512) sp *= 2;
+  return sp;
+}
+// Partial-sum floats the split-K path of gemm needs for an M x N product.
+static size_t gemm_part_floats(int M, int N, int K) {
+  const int sp = gemm_splits(M, N, K);
+  return sp > 1 ? (size_t)sp * M * N : 0;
 }
 
 __global__ void k_quantize(const float* x, uint16_t* q, size_t n) {
@@ -282,7 +343,7 @@ uint64_t splitmix(uint64_t& s) {
 // holds its own copy until the process ends.  In host code the array's name is
 // a host-side stand-in, not a device address: kernels and copies get the
 // address hipGetSymbolAddress returned on the current device (static_ws).
-constexpr size_t kStaticWsBytes = size_t(8) << 20;
+constexpr size_t kStaticWsBytes = size_t(16) << 20;
 static __device__ __align__(256) unsigned char scratch[kStaticWsBytes];
 
 constexpr int kMaxDevices = 64;
@@ -325,6 +386,7 @@ struct gmot_mlp {
   std::vector<uint16_t*> dZq;
   double* part = nullptr;
   double* loss_dev = nullptr;
+  float* split_part = nullptr;  // split-K partial sums of the GEMMs (cap rows)
   float *ws_x = nullptr, *ws_y = nullptr;  // warm-start workspaces (cap rows)
 
   ~gmot_mlp() {
@@ -355,6 +417,11 @@ struct gmot_mlp {
     }
     const size_t oPart = take(sizeof(double) * 1024);
     const size_t oLoss = take(sizeof(double));
+    size_t split_floats = 0;  // forward products (newcap x w[l] x w[l-1]) and input gradients (x w[l])
+    for (int l = 1; l <= L; ++l)
+      split_floats = std::max({split_floats, gemm_part_floats(newcap, w[l], w[l - 1]),
+                               gemm_part_floats(newcap, w[l - 1], w[l])});
+    const size_t oSplit = take(sizeof(float) * split_floats);
     const size_t oX = take(sizeof(float) * (size_t)newcap * w[0]);
     const size_t oY = take(sizeof(float) * (size_t)newcap * w[L]);
     if (hipMalloc(&act_arena, off) != hipSuccess) return mfail(GMOT_ENOMEM, "activation buffers");
@@ -371,6 +438,7 @@ struct gmot_mlp {
     }
     part = (double*)(b + oPart);
     loss_dev = (double*)(b + oLoss);
+    split_part = (float*)(b + oSplit);
     ws_x = (float*)(b + oX);
     ws_y = (float*)(b + oY);
     cap = newcap;
@@ -388,10 +456,27 @@ struct gmot_mlp {
   }
 };
 
+// C = A B with the epilogue; with K split, `part` must hold gemm_part_floats
+// floats (same splits for the same shape, so results do not depend on the
+// caller).
 template <bool TA, bool TB, int EPI>
-static hipError_t gemm(const GemmArgs& g, hipStream_t s) {
-  dim3 grid((g.N + 63) / 64, (g.M + 63) / 64);
+static hipError_t gemm(GemmArgs g, float* part, hipStream_t s) {
+  const int sp = gemm_splits(g.M, g.N, g.K);
+  dim3 grid((g.N + 63) / 64, (g.M + 63) / 64, sp);
+  if (sp > 1) {
+    if (!part || g.ldc != g.N) return hipErrorInvalidValue;
+    g.part = part;
+    g.k_chunk = ((g.K / sp) + 31) / 32 * 32;
+  } else {
+    g.part = nullptr;
+    g.k_chunk = g.K;
+  }
   hipLaunchKernelGGL((k_gemm<TA, TB, EPI>), grid, dim3(256), 0, s, g);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess || sp == 1) return e;
+  const size_t total = (size_t)g.M * g.N;
+  const unsigned blocks = (unsigned)std::min<size_t>(4096, (total + 255) / 256);
+  hipLaunchKernelGGL((k_gemm_reduce<EPI>), dim3(blocks), dim3(256), 0, s, g, sp);
   return hipGetLastError();
 }
 
@@ -414,7 +499,7 @@ static int mlp_forward(gmot_mlp* m, const float* x, int B) {
     g.C = m->H[l];
     g.Cq = l < m->L ? m->Hq[l] : nullptr;
     g.bias = m->params + m->offB[l];
-    MCHK((l < m->L ? gemm<false, true, kBiasRelu>(g, s) : gemm<false, true, kBias>(g, s)));
+    MCHK((l < m->L ? gemm<false, true, kBiasRelu>(g, m->split_part, s) : gemm<false, true, kBias>(g, m->split_part, s)));
   }
   return GMOT_OK;
 }
@@ -479,6 +564,7 @@ int gmot_mlp_create(gmot_ctx* ctx, int32_t n_layers, const int32_t* widths, uint
   }
   int rc = gmot_mlp_set_params(m.get(), h.data());
   if (rc) return rc;
+  gmot_ctx_retain(ctx);
   *out = m.release();
   return GMOT_OK;
 }
@@ -486,7 +572,9 @@ int gmot_mlp_create(gmot_ctx* ctx, int32_t n_layers, const int32_t* widths, uint
 void gmot_mlp_destroy(gmot_mlp* m) {
   if (!m) return;
   (void)hipStreamSynchronize(m->ctx->stream);
+  gmot_ctx* ctx = m->ctx;
   delete m;
+  gmot_ctx_release(ctx);
 }
 
 int64_t gmot_mlp_num_params(const gmot_mlp* m) { return m ? m->nparams : -1; }
@@ -539,6 +627,12 @@ static size_t static_layout(const gmot_mlp* m, int64_t B, std::vector<size_t>* o
     if (oH) (*oH)[l] = h;
     if (oHq) (*oHq)[l] = q;
   }
+  // split-K partial sums of the widest product (the forward GEMMs split like
+  // gmot_mlp_forward_dev's, so both give the same bits)
+  size_t split_floats = 0;
+  for (int l = 1; l <= m->L; ++l) split_floats = std::max(split_floats, gemm_part_floats((int)B, m->w[l], m->w[l - 1]));
+  const size_t sp = take(sizeof(float) * split_floats);
+  if (oH) (*oH)[0] = sp;  // oH[0] is otherwise unused: the split-K region
   return off;
 }
 
@@ -552,7 +646,7 @@ int gmot_mlp_forward_static(gmot_mlp* m, const float* x_dev, int32_t batch, floa
     while (static_layout(m, maxB + 8, nullptr, nullptr) <= kStaticWsBytes) maxB += 8;
     return mfail(GMOT_EINVAL, "batch " + std::to_string(batch) + " needs " + std::to_string(need) +
                                   " bytes of the static workspace; it holds " + std::to_string(kStaticWsBytes) +
-                                  " (at most " + std::to_string(maxB) + " rows for this network)");
+                                  " (batches of up to " + std::to_string(maxB) + " rows fit for this network)");
   }
   MCHK(hipSetDevice(m->ctx->device));
   hipStream_t s = m->ctx->stream;
@@ -575,7 +669,8 @@ int gmot_mlp_forward_static(gmot_mlp* m, const float* x_dev, int32_t batch, floa
     g.C = l < m->L ? (float*)(ws + oH[l]) : y_dev;
     g.Cq = l < m->L ? (uint16_t*)(ws + oHq[l]) : nullptr;
     g.bias = m->params + m->offB[l];
-    MCHK((l < m->L ? gemm<false, true, kBiasRelu>(g, s) : gemm<false, true, kBias>(g, s)));
+    float* part = (float*)(ws + oH[0]);
+    MCHK((l < m->L ? gemm<false, true, kBiasRelu>(g, part, s) : gemm<false, true, kBias>(g, part, s)));
   }
   return GMOT_OK;
 }
@@ -608,7 +703,7 @@ int gmot_mlp_loss_grad_dev(gmot_mlp* m, const float* x_dev, const float* t_dev, 
     gw.ldb = m->w[l - 1];
     gw.ldc = m->w[l - 1];
     gw.C = m->grad + m->offW[l];
-    MCHK((gemm<true, false, kStore>(gw, s)));
+    MCHK((gemm<true, false, kStore>(gw, m->split_part, s)));
     hipLaunchKernelGGL(k_bias_grad, dim3((m->w[l] + 255) / 256), dim3(256), 0, s, m->dZ[l], batch, m->w[l],
                        m->grad + m->offB[l]);
     MCHK(hipGetLastError());
@@ -626,7 +721,7 @@ int gmot_mlp_loss_grad_dev(gmot_mlp* m, const float* x_dev, const float* t_dev, 
       gx.C = m->dZ[l - 1];
       gx.Cq = m->dZq[l - 1];
       gx.mask = m->H[l - 1];
-      MCHK((gemm<false, false, kMaskRelu>(gx, s)));
+      MCHK((gemm<false, false, kMaskRelu>(gx, m->split_part, s)));
     }
   }
   if (grad_dev)

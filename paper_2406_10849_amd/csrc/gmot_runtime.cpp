@@ -117,7 +117,10 @@ constexpr int kSepTileRows = 64;
 
 // Timing mode: events per half-sweep, and back-to-back repeats of the message
 // stage between the first two (so their mean excludes the event overhead).
-constexpr int kStepEvents = 4;
+// Kernel groups of a node stage: explicit cost, D = 1, 2, 3 (k_node), separable
+// grids (k_sep_rows + k_node_sep).
+constexpr int kGroups = 5;
+constexpr int kStepEvents = 4 + 2 * kGroups;
 constexpr int kMsgBurst = 4;
 
 // A captured run of k half-sweeps.  The timed variant is not captured: it
@@ -171,6 +174,7 @@ struct Plan {
   std::vector<GraphEntry> graphs;
   TileStats stats;
   std::vector<double> inst_pairs[2];  // (x, y) pairs of each instance's messages into class c
+  std::vector<double> inst_group_pairs[2][kGroups];  // the same per kernel group
   gmot_stats acc{};
 
   ~Plan() {
@@ -199,65 +203,77 @@ struct Plan {
     return tb;
   }
 
-  // The node stage of class c: one launch per support-dimension group, or
-  // with per_node one launch per node (the same tiles, issued node by node).
-  // With fused, the first launch also carries the finalise step of the other
-  // class's half-sweep (the previous launch's), one block per instance.
-  hipError_t launch_node_stage(int c, bool fp64, hipStream_t s, bool per_node, bool fused = false) const {
-    hipError_t e;
-    bool fin_pending = fused;
-    for (int dk = 0; dk < 4; ++dk) {
-      if (tiles[c][dk].empty()) continue;
+  // Kernel group g (0 = explicit cost, 1..3 = dimension, kSepGroup =
+  // separable grids) of the node stage of class c: one launch (two for the
+  // separable group), or with per_node one per node (the same tiles, issued
+  // node by node).  *fin_pending: the first launch also carries the finalise
+  // step of the other class's half-sweep (the previous launch's), one block
+  // per instance.
+  hipError_t launch_group(int c, int g, bool fp64, hipStream_t s, bool per_node, bool* fin_pending) const {
+    hipError_t e = hipSuccess;
+    if (g < kSepGroup) {
+      if (tiles[c][g].empty()) return hipSuccess;
       if (!per_node) {
-        Tables tb = tables(c, dk);
-        if (fin_pending) {
+        Tables tb = tables(c, g);
+        if (*fin_pending) {
           tb.n_fin = (int)inst.size();
           tb.fin_colour = 1 - c;
           tb.fin_nodes = d_nodes[1 - c];
-          fin_pending = false;
+          *fin_pending = false;
         }
-        e = launch_node(tb, (int)tiles[c][dk].size(), dk, W, NR, NH, fp64, s);
-        if (e != hipSuccess) return e;
-        continue;
+        return launch_node(tb, (int)tiles[c][g].size(), g, W, NR, NH, fp64, s);
       }
-      for (const auto& r : node_tiles[c][dk]) {
-        Tables tb = tables(c, dk);
+      for (const auto& r : node_tiles[c][g]) {
+        Tables tb = tables(c, g);
         tb.tiles += r.first;
-        e = launch_node(tb, r.second, dk, W, NR, NH, fp64, s);
-        if (e != hipSuccess) return e;
+        if ((e = launch_node(tb, r.second, g, W, NR, NH, fp64, s)) != hipSuccess) return e;
       }
+      return hipSuccess;
     }
     // separable instances: first pass, then the node stage that reads it
-    if (!sep_items[c].empty()) {
-      if (!per_node) {
-        Tables tb = tables(c, kSepGroup);
-        if (fin_pending) {
-          tb.n_fin = (int)inst.size();
-          tb.fin_colour = 1 - c;
-          tb.fin_nodes = d_nodes[1 - c];
-        }
-        if ((e = launch_sep_rows(tb, (int)sep_items[c].size(), fp64, s)) != hipSuccess) return e;
-        tb.n_fin = 0;
-        if ((e = launch_node_sep(tb, (int)tiles[c][kSepGroup].size(), fp64, s)) != hipSuccess) return e;
-      } else {
-        for (size_t i = 0; i < node_sep[c].size(); ++i) {
-          Tables tb = tables(c, kSepGroup);
-          tb.sep_items += node_sep[c][i].first;
-          if ((e = launch_sep_rows(tb, node_sep[c][i].second, fp64, s)) != hipSuccess) return e;
-          tb.tiles += node_tiles[c][kSepGroup][i].first;
-          if ((e = launch_node_sep(tb, node_tiles[c][kSepGroup][i].second, fp64, s)) != hipSuccess) return e;
-        }
+    if (sep_items[c].empty()) return hipSuccess;
+    if (!per_node) {
+      Tables tb = tables(c, kSepGroup);
+      if (*fin_pending) {
+        tb.n_fin = (int)inst.size();
+        tb.fin_colour = 1 - c;
+        tb.fin_nodes = d_nodes[1 - c];
+        *fin_pending = false;
       }
+      if ((e = launch_sep_rows(tb, (int)sep_items[c].size(), fp64, s)) != hipSuccess) return e;
+      tb.n_fin = 0;
+      return launch_node_sep(tb, (int)tiles[c][kSepGroup].size(), fp64, s);
+    }
+    for (size_t i = 0; i < node_sep[c].size(); ++i) {
+      Tables tb = tables(c, kSepGroup);
+      tb.sep_items += node_sep[c][i].first;
+      if ((e = launch_sep_rows(tb, node_sep[c][i].second, fp64, s)) != hipSuccess) return e;
+      tb.tiles += node_tiles[c][kSepGroup][i].first;
+      if ((e = launch_node_sep(tb, node_tiles[c][kSepGroup][i].second, fp64, s)) != hipSuccess) return e;
+    }
+    return hipSuccess;
+  }
+
+  bool group_empty(int c, int g) const { return g < kSepGroup ? tiles[c][g].empty() : sep_items[c].empty(); }
+
+  // The node stage of class c: every kernel group in turn.  With fused, the
+  // first launch also carries the finalise step of the previous half-sweep.
+  hipError_t launch_node_stage(int c, bool fp64, hipStream_t s, bool per_node, bool fused = false) const {
+    bool fin_pending = fused;
+    for (int g = 0; g < kGroups; ++g) {
+      const hipError_t e = launch_group(c, g, fp64, s, per_node, &fin_pending);
+      if (e != hipSuccess) return e;
     }
     return hipSuccess;
   }
 
   // One half-sweep of class c: the node stage, then the finalise kernel.  With
   // events (timing mode, direct launches): ev[0], the node stage kMsgBurst
-  // times, ev[1], the node stage, ev[2], the finalise kernel, ev[3].  A repeat
-  // of the node stage reads the same state and rewrites the same slots (only
-  // its shifts differ), so the burst's mean is the node stage's duration
-  // without the event overhead.
+  // times, ev[1]; then per kernel group g ev[4 + 2g], the group kMsgBurst
+  // times, ev[5 + 2g]; then the node stage, ev[2], the finalise kernel, ev[3].
+  // A repeat of the node stage or of a group reads the same state and
+  // rewrites the same slots (only its shifts differ), so a burst's mean is the
+  // duration without the event overhead.
   // Fused (no events, layer schedule): the node stage alone, its first launch
   // finalising the previous half-sweep.
   hipError_t launch_tstep(int c, bool fp64, hipStream_t s, const hipEvent_t* ev = nullptr,
@@ -269,6 +285,14 @@ struct Plan {
       for (int r = 0; r < kMsgBurst; ++r)
         if ((e = launch_node_stage(c, fp64, s, per_node)) != hipSuccess) return e;
       if ((e = hipEventRecord(ev[1], s)) != hipSuccess) return e;
+      for (int g = 0; g < kGroups; ++g) {
+        if ((e = hipEventRecord(ev[4 + 2 * g], s)) != hipSuccess) return e;
+        for (int r = 0; r < kMsgBurst; ++r) {
+          bool no_fin = false;
+          if ((e = launch_group(c, g, fp64, s, per_node, &no_fin)) != hipSuccess) return e;
+        }
+        if ((e = hipEventRecord(ev[5 + 2 * g], s)) != hipSuccess) return e;
+      }
     }
     if ((e = launch_node_stage(c, fp64, s, per_node)) != hipSuccess) return e;
     if (ev && (e = hipEventRecord(ev[2], s)) != hipSuccess) return e;
@@ -393,7 +417,10 @@ static int build_plan(gmot_ctx* ctx, const std::vector<gmot_problem*>& probs, No
     pl->inst.push_back(st);
   }
   pl->total_nodes = err_counter;
-  for (int c = 0; c < 2; ++c) pl->inst_pairs[c].assign(probs.size(), 0.0);
+  for (int c = 0; c < 2; ++c) {
+    pl->inst_pairs[c].assign(probs.size(), 0.0);
+    for (int g = 0; g < kGroups; ++g) pl->inst_group_pairs[c][g].assign(probs.size(), 0.0);
+  }
   // (x, y) term evaluations of the node stage: n_j n_k per message, or
   // A_k B_j B_k + n_j A_k for a separable one (its two passes)
   for (size_t m = 0; m < pl->msgs.size(); ++m) {
@@ -402,6 +429,8 @@ static int build_plan(gmot_ctx* ctx, const std::vector<gmot_problem*>& probs, No
                           ? (double)md.rows_src * md.cols_dst * md.cols_src + (double)md.n_dst * md.rows_src
                           : (double)md.n_dst * md.n_src;
     pl->inst_pairs[msg_class[m]][md.inst] += ev;
+    const int grp = probs[md.inst]->sep ? kSepGroup : md.cost_kind == GMOT_COST_EXPLICIT ? 0 : md.dim;
+    pl->inst_group_pairs[msg_class[m]][grp][md.inst] += ev;
   }
 
   // column splits: enough blocks per class to fill the device
@@ -759,7 +788,7 @@ static int run_plan(Plan* pl, const gmot_opts* o, gmot_result* outs, const std::
     HIPCHK(hipEventCreateWithFlags(&ev[0], hipEventDisableTiming));
     HIPCHK(hipEventCreateWithFlags(&ev[1], hipEventDisableTiming));
     // per-step durations of timed replays: (step since the start of this call, message ms, node ms)
-    struct StepTime { int64_t step; float msg_ms, sweep_ms; };
+    struct StepTime { int64_t step; float msg_ms, sweep_ms; float group_ms[kGroups]; };
     std::vector<StepTime> times;
     auto launch_one = [&](int slot) -> hipError_t {
       hipError_t e;
@@ -785,9 +814,20 @@ static int run_plan(Plan* pl, const gmot_opts* o, gmot_result* outs, const std::
         float a = 0.f, b = 0.f;
         const hipEvent_t* q = E.data() + kStepEvents * i;
         hipError_t e = hipEventElapsedTime(&a, q[0], q[1]);                  // kMsgBurst message stages
-        if (e == hipSuccess) e = hipEventElapsedTime(&b, q[1], q[3]);      // one half-sweep
+        if (e == hipSuccess) e = hipEventElapsedTime(&b, q[1], q[3]);      // groups, one half-sweep
         if (e != hipSuccess) return e;
-        times.push_back({replay * k + i, a / kMsgBurst, b});
+        StepTime st{replay * k + i, a / kMsgBurst, 0.f, {}};
+        const int cls = (start + i) & 1;
+        float grp_total = 0.f;
+        for (int gi = 0; gi < kGroups && e == hipSuccess; ++gi) {
+          float gm = 0.f;
+          e = hipEventElapsedTime(&gm, q[4 + 2 * gi], q[5 + 2 * gi]);
+          grp_total += gm;
+          st.group_ms[gi] = pl->group_empty(cls, gi) ? 0.f : gm / kMsgBurst;
+        }
+        if (e != hipSuccess) return e;
+        st.sweep_ms = b - grp_total;                                         // the half-sweep alone
+        times.push_back(st);
       }
       return hipSuccess;
     };
@@ -828,6 +868,11 @@ static int run_plan(Plan* pl, const gmot_opts* o, gmot_result* outs, const std::
         const int c = (int)((start + tt.step) & 1);
         pl->acc.msg_ms += tt.msg_ms;
         pl->acc.sweep_ms += tt.sweep_ms;
+        for (int gi = 0; gi < kGroups; ++gi) {
+          pl->acc.group_ms[gi] += tt.group_ms[gi];
+          for (size_t i = 0; i < n; ++i)
+            if (tt.step <= last[i]) pl->acc.group_pairs[gi] += pl->inst_group_pairs[c][gi][i];
+        }
         pl->acc.msg_launches += 1;
         for (size_t i = 0; i < n; ++i)
           if (tt.step <= last[i]) pl->acc.msg_pairs += pl->inst_pairs[c][i];
@@ -1593,6 +1638,16 @@ static int round_problem(gmot_problem* p, gmot_round_result* out, double* edge_t
   return GMOT_OK;
 }
 
+void gmot_ctx_retain(gmot_ctx* ctx) { ctx->refs.fetch_add(1, std::memory_order_relaxed); }
+
+void gmot_ctx_release(gmot_ctx* ctx) {
+  if (!ctx || ctx->refs.fetch_sub(1, std::memory_order_acq_rel) != 1) return;
+  (void)hipStreamSynchronize(ctx->stream);
+  if (ctx->scratch) (void)hipFree(ctx->scratch);
+  if (ctx->own_stream) (void)hipStreamDestroy(ctx->stream);
+  delete ctx;
+}
+
 extern "C" {
 
 int gmot_ctx_create(gmot_ctx** out, int device, void* hip_stream) {
@@ -1620,13 +1675,8 @@ int gmot_ctx_create(gmot_ctx** out, int device, void* hip_stream) {
   return GMOT_OK;
 }
 
-void gmot_ctx_destroy(gmot_ctx* ctx) {
-  if (!ctx) return;
-  (void)hipStreamSynchronize(ctx->stream);
-  if (ctx->scratch) (void)hipFree(ctx->scratch);
-  if (ctx->own_stream) (void)hipStreamDestroy(ctx->stream);
-  delete ctx;
-}
+void gmot_ctx_destroy(gmot_ctx* ctx) { gmot_ctx_release(ctx); }
+
 
 int gmot_problem_create(gmot_ctx* ctx, const gmot_tree_desc* desc, int32_t first_color, gmot_problem** out) {
   if (!ctx || !out) return fail(GMOT_EINVAL, "null context or output");
@@ -1641,6 +1691,7 @@ int gmot_problem_create(gmot_ctx* ctx, const gmot_tree_desc* desc, int32_t first
     if (p->d_cost_tile) (void)hipFree(p->d_cost_tile);
     return rc;
   }
+  gmot_ctx_retain(ctx);
   *out = p.release();
   return GMOT_OK;
 }
@@ -1696,7 +1747,9 @@ void gmot_problem_destroy(gmot_problem* p) {
   delete p->round;
   if (p->arena) (void)hipFree(p->arena);
   if (p->d_cost_tile) (void)hipFree(p->d_cost_tile);
+  gmot_ctx* ctx = p->ctx;
   delete p;
+  gmot_ctx_release(ctx);
 }
 
 int gmot_solve(gmot_problem* p, const gmot_opts* o, gmot_result* out) {
@@ -1883,6 +1936,7 @@ int gmot_batch_create(gmot_ctx* ctx, gmot_problem* const* probs, int32_t count, 
   HIPCHK(hipSetDevice(ctx->device));
   int rc = build_plan(ctx, b->probs, choose_shape(ctx, b->probs), &b->plan);
   if (rc) return rc;
+  gmot_ctx_retain(ctx);
   *out = b.release();
   return GMOT_OK;
 }
@@ -1891,7 +1945,9 @@ void gmot_batch_destroy(gmot_batch* b) {
   if (!b) return;
   (void)hipStreamSynchronize(b->ctx->stream);
   delete b->plan;
+  gmot_ctx* ctx = b->ctx;
   delete b;
+  gmot_ctx_release(ctx);
 }
 
 int gmot_batch_solve(gmot_batch* b, const gmot_opts* o, gmot_result* outs) {

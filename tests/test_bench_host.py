@@ -63,14 +63,18 @@ def test_committed_traffic_files_are_well_formed():
             assert "fetch_bytes_per_launch" in ln and "write_bytes_per_launch" in ln
 
 
-def test_weighted_peak_between_the_dimension_peaks():
-    p1, p2 = bench.pair_peak_gpairs(1), bench.pair_peak_gpairs(2)
-    assert p1 > p2
-    w = bench.weighted_pair_peak({1: 3.0e9, 2: 1.0e9})
-    assert p2 < w < p1
-    # time at peak adds up: 4e9 pairs at w take as long as each part at its own peak
-    assert abs(4.0e9 / w - (3.0e9 / p1 + 1.0e9 / p2)) < 1e-12 * (4.0e9 / w)
-    assert bench.weighted_pair_peak({1: 5.0}) == pytest.approx(p1)
+def test_group_rooflines():
+    st = {"msg_launches": 10, "group_ms": [0.0, 2.0, 0.0, 0.0, 1.0], "group_pairs": [0.0, 8.0e9, 0.0, 0.0, 1.0e9]}
+    g = bench.group_rooflines(st)
+    assert set(g) == {"k_node<D=1>", "k_sep_rows+k_node_sep"}
+    d1 = g["k_node<D=1>"]
+    assert d1["achieved"] == pytest.approx(8.0e9 / 2.0e-3 / 1e9)
+    assert d1["peak"] == pytest.approx(bench.pair_peak_gpairs(1))
+    assert d1["frac"] == pytest.approx(d1["achieved"] / d1["peak"])
+    assert d1["ms_per_stage"] == pytest.approx(0.2)
+    assert g["k_sep_rows+k_node_sep"]["peak"] == pytest.approx(bench.pair_peak_gpairs(1))
+    ex = bench.group_rooflines({"msg_launches": 1, "group_ms": [1.0, 0, 0, 0, 0], "group_pairs": [1e9, 0, 0, 0, 0]})
+    assert ex["k_node<explicit>"]["unit"] == "GB/s" and ex["k_node<explicit>"]["achieved"] == pytest.approx(4000.0)
 
 
 def test_rocprof_summaries(tmp_path):

@@ -192,3 +192,28 @@ def test_trained_warm_start_reduces_half_sweeps(ctx):
     res = warmstart.compare(ctx, net, data.scaling, test, batch=64)
     assert res["rejected"] == 0
     assert res["warm_half_sweeps_mean"] < res["cold_half_sweeps_mean"]
+
+
+def test_handles_outlive_a_closed_context():
+    """Problems, batches and networks hold references to their context inside
+    the library, so they stay usable after the context is closed and may be
+    destroyed in any order -- also by a garbage collector that finalises the
+    context first (objects caught in one reference cycle, e.g. by a stored
+    traceback)."""
+    import gc
+    from paper_2406_10849_amd import Context, MLP, Problem, Batch
+    ctx = Context(0)
+    net = MLP(ctx, [16, 8, 16], seed=1)
+    pb = Problem(ctx, make_star(n=20, leaves=2, eps=0.1))
+    b = Batch(ctx, [pb])
+    ctx.close()
+    assert b.solve(tol=0.0, max_steps=2)[0]["steps"] == 2
+    assert net.get_params().shape == (net.n_params,)
+    pb.close()
+    b.close()
+    net.close()
+    ctx2 = Context(0)
+    holder = {"ctx": ctx2, "net": MLP(ctx2, [16, 8, 16], seed=2), "pb": Problem(ctx2, make_star(n=20, leaves=2))}
+    holder["self"] = holder
+    del holder, ctx2
+    gc.collect()

@@ -165,6 +165,9 @@ def test_timing_stats_count_working_half_sweeps(ctx):
     assert st["msg_launches"] == r["t"]          # half-sweeps 1..t computed messages
     assert abs(st["msg_pairs"] - r["t"] * p.pairs_per_tstep()) < 0.5
     assert st["msg_ms"] > 0
+    # one support dimension: all of the stage is the D = 1 group
+    assert st["group_pairs"][1] == st["msg_pairs"] and sum(st["group_pairs"]) == st["msg_pairs"]
+    assert st["group_ms"][1] > 0 and st["group_ms"][0] == st["group_ms"][2] == st["group_ms"][4] == 0.0
 
 
 def test_evaluate_matches_oracle_on_given_potentials(ctx):

@@ -55,9 +55,9 @@ def test_static_forward_other_shape_same_workspace(ctx):
 def test_static_forward_refuses_a_batch_that_does_not_fit(ctx):
     from paper_2406_10849_amd import MLP, GmotError, GMOT_EINVAL
     net = MLP(ctx, [8192, 512, 512, 512, 8192], seed=13)
-    x = torch.zeros((512, 8192), dtype=torch.float32, device="cuda")
-    y = torch.zeros((512, 8192), dtype=torch.float32, device="cuda")
+    x = torch.zeros((1024, 8192), dtype=torch.float32, device="cuda")
+    y = torch.zeros((1024, 8192), dtype=torch.float32, device="cuda")
     with pytest.raises(GmotError) as ei:
         net.forward_static(x, y)
     assert ei.value.code == GMOT_EINVAL
-    assert "at most" in str(ei.value)
+    assert "rows fit" in str(ei.value)

@@ -18,6 +18,7 @@ from .gen import (
     make_random_tree,
     make_batched_stars,
     make_warmstart_star,
+    make_lognormal_star,
     make_config,
     make_tree,
     CONFIG_NAMES,
@@ -28,6 +29,6 @@ __all__ = [
     "TreeProblem", "COST_SQEUCLID", "COST_EXPLICIT", "rng_for", "grid_1d",
     "grid_2d", "gaussian_mixture", "dirichlet1", "prufer_decode", "make_star",
     "make_chain", "make_random_tree", "make_batched_stars",
-    "make_warmstart_star", "make_config", "make_tree", "CONFIG_NAMES", "JunctionProblem", "make_wls",
+    "make_warmstart_star", "make_lognormal_star", "make_config", "make_tree", "CONFIG_NAMES", "JunctionProblem", "make_wls",
     "make_random_junction", "as_tree_problem", "from_tree_problem",
 ]

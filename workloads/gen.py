@@ -194,6 +194,20 @@ def make_warmstart_star(instance: int, n: int = 1024, leaves: int = 8, eps: floa
                      f"wstar-{instance}-n{n}", {"cfg": cfg_id, "instance": instance})
 
 
+def make_lognormal_star(leaves: int, d: int, eps: float, instance: int = 0, cfg_id: int = 8) -> TreeProblem:
+    """The barycenter problem of the paper's experiments (Section 5): a free
+    center and `leaves` constrained leaves, all on a uniform grid of d points in
+    [0, 1], squared-Euclidean cost, leaf marginals drawn from seeded log-normal
+    densities (the recipe of workloads.junction.log_normal_marginal)."""
+    from .junction import log_normal_marginal
+    rng = rng_for(cfg_id, instance)
+    pts = [grid_1d(d) for _ in range(leaves + 1)]
+    marg = [None] + [log_normal_marginal(rng, pts[j]) for j in range(1, leaves + 1)]
+    edges = [(0, j) for j in range(1, leaves + 1)]
+    return _assemble(leaves + 1, edges, [d] * (leaves + 1), 1, pts, [0] + [1] * leaves, marg, eps,
+                     f"lnstar-L{leaves}-d{d}", {"cfg": cfg_id, "instance": instance})
+
+
 def make_config(cfg_id: int, scale: str = "full"):
     """Problem(s) for one workload.  ``scale='small'`` keeps the structure but
     shrinks sizes so the FP64 oracle finishes in seconds."""
