@@ -58,11 +58,11 @@ def group_rooflines(st: dict) -> dict:
     """ALU roofline of each kernel group of the node stage that did work, from
     the per-group timing (HIP events around back-to-back repeats of the group
     alone): k_node for D = 1, 2, 3 against the pair peak of its dimension, the
-    separable grid kernels (k_sep_rows + k_node_sep) against the one-dimensional
+    separable grid kernels (k_sep_pass + k_node_sep) against the one-dimensional
     pair peak (each of their terms is a one-dimensional term), k_node with
     explicit costs against HBM bandwidth at 4 bytes per pair."""
     names = {0: "k_node<explicit>", 1: "k_node<D=1>", 2: "k_node<D=2>", 3: "k_node<D=3>",
-             4: "k_sep_rows+k_node_sep"}
+             4: "k_sep_pass+k_node_sep"}
     n = max(st["msg_launches"], 1)
     out = {}
     for g in range(5):

@@ -68,8 +68,9 @@ struct MsgDesc {
   const float* cost_tile;    // the same, tile-major for the node kernel: C_(j,k)(x, y) at
                              // ((x / 64) * n_src + y) * 64 + x % 64, rows padded to 64
   const double* src_tpart;   // tile records of the source node k (its c_k comes from them)
-  double* sepT;              // separable messages (grid supports): first-pass sums T(u, q),
-                             // [rows_src x cols_dst] (log2), else NULL
+  double* sepT;              // separable messages (grid supports): first-pass sums, transposed,
+                             // Tt(q, u) = T(u, q) - kap R_k[u]^2 at q * rows_src + u (log2), else NULL
+  double* sepM;              // separable messages: first-pass shifts (log2 max term), [rows_src x cols_dst]
   int32_t n_dst, n_src, ns, inst;
   int32_t dim, cost_kind, src_tiles, src_deg;  // source node's tile count and degree
   int32_t src_free, pad0, pad1, pad2;          // 1: free source node (c_k from the records), 0: c_k = 0
@@ -77,11 +78,18 @@ struct MsgDesc {
   double eps;
 };
 
-// One wave-row block of the separable first pass: source grid rows
-// [u0, u0 + 4) of message msg (one wave per row).
+// One block of a separable pass: lines [line0, line0 + nlines) of message msg
+// (source grid rows in the first pass, destination grid columns in the second).
 struct SepItem {
-  int32_t msg, u0, inst, pad;
+  int32_t msg, line0, inst, nlines;
 };
+constexpr int kSepWaves = 4;        // waves per block of a separable pass
+constexpr int kSepMaxSide = 2048;   // grid rows and columns of a separable support at most
+constexpr int kSepMaxOut = 2048;    // outputs per separable-pass block (8 per thread)
+constexpr int kSepStage = 4608;     // staged values per separable-pass block (36 KB) at most
+// Staged row stride and length of a separable pass with `inner` terms per output.
+__host__ __device__ inline int sep_row_stride(int inner) { return (inner + 1) | 1; }
+__host__ __device__ inline int sep_inner_even(int inner) { return (inner + 1) & ~1; }
 
 // One block of the message kernel: rows [row0, row0 + rows per block) of a
 // message, columns [col0, col0 + ncols), writing column split `split`.
@@ -158,6 +166,7 @@ struct Tables {
   int n_fin, fin_colour;
   const NodeItem* fin_nodes;
   const SepItem* sep_items;  // separable first pass of one class
+  const SepItem* sep_items2; // separable second pass of one class
   int rec_rows;              // rows per tile record (32 or 64)
   // evaluation pass: per instance the slot holding each class's committed
   // potentials, [2 * inst + class] (read when a kernel is given slot -1)
@@ -209,10 +218,13 @@ hipError_t launch_msg(const Tables& tb, int n_items, int dim, int rows_per_lane,
 hipError_t launch_node(const Tables& tb, int n_tiles, int dim, int waves, int rows_per_lane, int lane_groups,
                        bool fp64, hipStream_t s);
 hipError_t launch_finalize(const Tables& tb, int n_inst, hipStream_t s);
-// separable messages on Cartesian grid supports (D = 2): the first pass over
-// n_items source-row blocks, then the node stage over n_tiles 64-row tiles
-hipError_t launch_sep_rows(const Tables& tb, int n_items, bool fp64, hipStream_t s);
-hipError_t launch_node_sep(const Tables& tb, int n_tiles, bool fp64, hipStream_t s);
+// separable messages on Cartesian grid supports (D = 2): pass 0 over the
+// n_items blocks of tb.sep_items (carrying tb.n_fin finalise blocks), pass 1
+// over those of tb.sep_items2 (lds_bytes of dynamic LDS per block: the largest
+// item's staged values and coordinates), then the node stage over n_tiles
+// 64-row tiles
+hipError_t launch_sep_pass(const Tables& tb, int pass, int n_items, size_t lds_bytes, bool fp64, hipStream_t s);
+hipError_t launch_node_sep(const Tables& tb, int n_tiles, hipStream_t s);
 hipError_t launch_node_eval(const Tables& tb, int n_nodes, int slot, hipStream_t s);
 // dst[i] = src[i] - (c ? *c : 0) over segments (potential read-back on the device)
 struct SegCopy { const double* src; double* dst; const double* c; int64_t len; };

@@ -414,8 +414,12 @@ __device__ inline void wave_sync() {
 
 template <int DIM, int W, int R, int H, bool F64, bool EXPL>
 // The 8-wave, 32-row-tile shape asks for four waves per SIMD (at most 128
-// VGPRs), so that two of its blocks share a CU.
-__global__ __launch_bounds__(64 * W, (W == 8 && R == 1 && H == 2 && !EXPL) ? 4 : 1) void k_node(Tables tb) {
+// VGPRs), so that two of its blocks share a CU; so does the one-row-per-lane
+// FP32-core shape of one-dimensional supports (otherwise one VGPR over 128,
+// and three waves per SIMD).
+__global__ __launch_bounds__(64 * W, ((W == 8 && R == 1 && H == 2 && !EXPL) ||
+                                      (DIM == 1 && R == 1 && H == 1 && !EXPL && !F64)) ? 4 : 1)
+void k_node(Tables tb) {
   static_assert(H == 1 || !EXPL, "explicit costs take one lane group");
   constexpr int LPR = 64 / H;                        // lanes per lane group
   constexpr int CH = EXPL ? 32 : 64;                 // columns per wave chunk
@@ -1146,189 +1150,208 @@ __global__ __launch_bounds__(64 * W, (W == 8 && R == 1 && H == 2 && !EXPL) ? 4 :
 // at (R_j[p / B_j], C_j[p % B_j]), the last row possibly partial -- the cost
 // splits, |x - y|^2 = (R_j[p] - R_k[u])^2 + (C_j[q] - C_k[v])^2, and so does
 // the log-sum-exp of the message (eq. q), in two one-dimensional passes:
-//   T(u, q) = log2 sum_v 2^(a(u, v) - kap (C_j[q] - C_k[v])^2)     (k_sep_rows)
-//   m(p, q) = ln2 log2 sum_u 2^(T(u, q) - kap (R_j[p] - R_k[u])^2) - c_k
-//                                                                   (k_node_sep)
+//   T(u, q) = log2 sum_v 2^(a(u, v) - kap (C_j[q] - C_k[v])^2)           (pass 0)
+//   m(p, q) = ln2 log2 sum_u 2^(T(u, q) - kap (R_j[p] - R_k[u])^2) - c_k   (pass 1)
 // with a = log2e (L_(k,j) + log gamma_k) over the source's points (absent
 // points of a partial last row give -inf), kap = log2e / eps, and c_k the
 // source's normaliser: n_k B_j + n_j A_k terms per message instead of n_j n_k.
-// Each sum takes two passes over its terms (max, then the shifted sum): FP32
-// exponentials of the FP64-reduced argument accumulated in FP64, or FP64
-// throughout (F64).  k_node_sep then does the node's stopping-sum terms,
-// update and tile records exactly as k_node does.
+//
+// Both passes run one kernel over "lines" of a one-dimensional LSE
+// convolution: out(o) = log2 sum_i 2^(s(i) - kap (z_o - y_i)^2).  With the
+// square expanded, the y_i^2 part goes into the staged values s(i) and the
+// z_o^2 part leaves the sum, so a term costs one FP64 FMA, s(i) + 2 kap z_o y_i,
+// before its exponential:
+//   pass 0: line u (source row), outputs q, inner v; s = a(u, v) - kap C_k[v]^2,
+//           y = C_k[v], z = C_j[q]; stores Tt(q, u) = T(u, q) - kap R_k[u]^2;
+//   pass 1: line q (destination column), outputs p, inner u; s = Tt(q, u),
+//           y = R_k[u], z = R_j[p]; stores m(p B_j + q) in mfull.
+// A block stages the values of its lines (every inner index, rows of odd
+// stride so lanes on different lines hit different banks) and the inner
+// coordinates in LDS, after loading each of its outputs' coordinate and
+// shift into registers (up to kSepOut outputs per thread), so a block waits
+// for memory once.
+//
+// Sums (FP32 core) follow the node kernel's contract: pairs of v_exp_f32
+// terms of the FP64-reduced argument, added in FP32 and accumulated in FP64.
+// From the third half-sweep of a call on, one pass shifted by the output's
+// previous shift (the log2 of its largest pair sum, kept per output); an
+// output whose sum leaves [2^kShiftLo, 2^kShiftHi] (terms may have overflowed
+// or underflowed; a non-finite shift lands here too) is taken again in two
+// passes (exact FP64 max, then the shifted sum).  The first two half-sweeps of
+// a call take two passes; the FP64 variant (F64) always does, with FP64
+// exponentials.
 // ---------------------------------------------------------------------------
-constexpr int kSepWaves = 4;
+constexpr int kSepOut = 8;  // outputs per thread of a separable-pass block
 
-template <bool F64>
-__device__ inline double exp2_term(double d) {
-  if (F64) return exp2(d);
-  return (double)exp2_hw((float)d);
-}
-
-// One wave per source grid row u of one message: T(u, q) for every column q of
-// the destination grid (lanes over q), the source row's terms staged in the
-// wave's LDS buffer 64 columns at a time.
-// As the first launch of a node stage it also carries the finalise step of
-// the previous half-sweep in its first n_fin blocks, as k_node does.
-template <bool F64>
-__global__ __launch_bounds__(64 * kSepWaves) void k_sep_rows(Tables tb) {
-  __shared__ double s_a[kSepWaves][64];
-  __shared__ double s_y[kSepWaves][64];
-  if ((int)blockIdx.x < tb.n_fin) {
-    __shared__ double sh_fin[kFinParts][2];
-    fin_instance<kSepWaves>(tb, tb.fin_nodes, tb.fin_colour, tb.inst + blockIdx.x, true, sh_fin);
-    return;
+template <bool F64, int PASS>
+__global__ __launch_bounds__(64 * kSepWaves) void k_sep_pass(Tables tb) {
+  extern __shared__ double s_dyn[];
+  int bid = (int)blockIdx.x;
+  if (PASS == 0) {
+    if (bid < tb.n_fin) {
+      // the finalise step of the previous launch's half-sweep, one block per instance
+      __shared__ double sh_fin[kFinParts][2];
+      fin_instance<kSepWaves>(tb, tb.fin_nodes, tb.fin_colour, tb.inst + bid, true, sh_fin);
+      return;
+    }
+    bid -= tb.n_fin;
   }
-  const SepItem it = tb.sep_items[blockIdx.x - tb.n_fin];
+  const SepItem it = (PASS == 0 ? tb.sep_items : tb.sep_items2)[bid];
   const CMsg& md = *(const CMsg*)(tb.msgs + it.msg);
   const InstState* st = tb.inst + it.inst;
   const long long t = st->vt[tb.colour];
-  if (st->vdone[tb.colour] != 0 || t < st->t_first || ((t & 1) == 1) != (tb.colour == 0)) return;
-  const int lane = threadIdx.x & 63, wv = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
-  const int u = it.u0 + wv;
-  const int Ak = md.rows_src, Bk = md.cols_src, Bj = md.cols_dst, nk = md.n_src;
-  if (u >= Ak) return;
+  const long long t_first = st->t_first;
+  if (st->vdone[tb.colour] != 0 || t < t_first || ((t & 1) == 1) != (tb.colour == 0)) return;
+  const bool one = !F64 && t >= st->onepass_from;
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int Ak = md.rows_src, Bk = md.cols_src, Aj = md.rows_dst, Bj = md.cols_dst;
+  const int nk = md.n_src, nj = md.n_dst;
+  const int outs = PASS == 0 ? Bj : Aj;   // outputs per line
+  const int inner = PASS == 0 ? Bk : Ak;  // terms per output
+  const int IS = (inner + 1) | 1;         // staged row stride (odd, > inner when inner is odd)
+  const int IE = (inner + 1) & ~1;        // inner rounded up to even
+  const int NL = it.nlines, NF = NL * outs;
+  const double kap = kLog2e / md.eps;
   const int src_slot = (int)((t >> 1) % kSlots);
   const GDbl* __restrict__ lam = (const GDbl*)md.lam_src[src_slot];
   const GDbl* __restrict__ lg = (const GDbl*)md.lg_src;
   const GDbl* __restrict__ ys = (const GDbl*)md.supp_src;
   const GDbl* __restrict__ xs = (const GDbl*)md.supp_dst;
-  GDblW* __restrict__ T = (GDblW*)md.sepT + (size_t)u * Bj;
-  const double kap = kLog2e / md.eps;
-  double* __restrict__ sa = s_a[wv];
-  double* __restrict__ sy = s_y[wv];
-  // columns v0 .. v0 + 63 of source row u into the wave's buffer (loads at
-  // clamped indexes; absent points get a = -inf)
-  auto stage = [&](int v0) -> int {
-    const int v = v0 + lane, y = u * Bk + v;
-    const bool ok = v < Bk && y < nk;
-    const int yc = ok ? y : 0;
-    const double av = lam[yc] + lg[yc];
-    const double yv = ys[(size_t)yc * 2 + 1];
-    sa[lane] = ok ? kLog2e * av : -INFINITY;
-    sy[lane] = ok ? yv : 0.0;
-    wave_sync();
-    return min(64, Bk - v0);
-  };
-  for (int q0 = 0; q0 < Bj; q0 += 64) {
-    const int q = q0 + lane;
-    const double xq = xs[(size_t)min(q, Bj - 1) * 2 + 1];
-    double M = -INFINITY;
-    for (int v0 = 0; v0 < Bk; v0 += 64) {
-      const int cn = stage(v0);
-      for (int c = 0; c < cn; ++c) {
-        const double d = xq - sy[c];
-        M = fmax(M, fma(-kap * d, d, sa[c]));
-      }
-      wave_sync();
+  GDblW* __restrict__ Tt = (GDblW*)md.sepT;
+  GDblW* __restrict__ shift = PASS == 0 ? (GDblW*)md.sepM : (GDblW*)md.wmax;
+  double* __restrict__ sy = s_dyn;       // [IE] inner coordinates
+  double* __restrict__ sa = s_dyn + IE;  // [NL x IS] staged values
+  // this thread's outputs f = tid + 256 i: coordinate z and previous shift
+  // (clamped loads; f >= NF is never used)
+  double zr[kSepOut], shr[kSepOut];
+#pragma unroll
+  for (int i = 0; i < kSepOut; ++i) {
+    const int f = min(tid + 64 * kSepWaves * i, NF - 1);
+    const int row = f / outs, o = f - row * outs, line = it.line0 + row;
+    zr[i] = PASS == 0 ? xs[(size_t)o * 2 + 1] : xs[(size_t)min(o * Bj, nj - 1) * 2];
+    const size_t si = PASS == 0 ? (size_t)line * Bj + o : (size_t)min(o * Bj + line, nj - 1);
+    shr[i] = one ? shift[si] : 0.0;
+  }
+  // pass 1: the source's normaliser, from its tile records when its last
+  // update (half-sweep t - 1) ran in this run, else its stored value
+  double ck = 0.0;
+  if (PASS == 1 && md.src_free) {
+    if (t - 1 >= t_first) {
+      const GDbl* __restrict__ srec = (const GDbl*)md.src_tpart;
+      const int src_deg = md.src_deg, src_tiles = md.src_tiles;
+      const int s_stride = src_deg + kRecExtra, s_tile = min(lane, src_tiles - 1);
+      ck = tile_lse((const double*)srec, src_tiles, s_stride, src_deg, srec[(size_t)s_tile * s_stride + src_deg],
+                    srec[(size_t)s_tile * s_stride + src_deg + 1]);
+    } else {
+      ck = *(const GDbl*)(md.c_src + src_slot);
     }
-    double S = 0.0;
-    if (__any(M > -INFINITY)) {
-      for (int v0 = 0; v0 < Bk; v0 += 64) {
-        const int cn = stage(v0);
-        for (int c = 0; c < cn; ++c) {
-          const double d = xq - sy[c];
-          S += exp2_term<F64>(fma(-kap * d, d, sa[c]) - M);
+  }
+  // stage: inner coordinates (pads 0), then the lines' values (pads -inf)
+  for (int c = tid; c < IE; c += 64 * kSepWaves) {
+    double y = 0.0;
+    if (c < inner) y = PASS == 0 ? ys[(size_t)c * 2 + 1] : ys[(size_t)c * Bk * 2];
+    sy[c] = y;
+  }
+  for (int idx = tid; idx < NL * inner; idx += 64 * kSepWaves) {
+    const int l = idx / inner, c = idx - l * inner, line = it.line0 + l;
+    double a;
+    if (PASS == 0) {
+      const int y = line * Bk + c;
+      const int yc = y < nk ? y : nk - 1;
+      const double cv = ys[(size_t)c * 2 + 1];
+      const double av = lam[yc] + lg[yc];
+      a = y < nk ? fma(-kap * cv, cv, kLog2e * av) : -INFINITY;
+    } else {
+      a = Tt[(size_t)line * Ak + c];
+    }
+    sa[l * IS + c] = a;
+  }
+  if (inner & 1)
+    for (int l = tid; l < NL; l += 64 * kSepWaves) sa[l * IS + inner] = -INFINITY;
+  __syncthreads();
+
+#pragma unroll
+  for (int i = 0; i < kSepOut; ++i) {
+    const int f = tid + 64 * kSepWaves * i;
+    if (f < NF) {
+      const int row = f / outs, o = f - row * outs, line = it.line0 + row;
+      const int x = o * Bj + line;  // pass 1: the output's point of node j
+      const double z = zr[i], cf = 2.0 * kap * z;
+      const double* __restrict__ ar = sa + row * IS;
+      double base = shr[i], S = 0.0;
+      float Mp = 0.0f;
+      bool two = !one;
+      if (one) {
+#pragma unroll 4
+        for (int c = 0; c < inner; c += 2) {
+          const double d0 = fma(cf, sy[c], ar[c]) - base, d1 = fma(cf, sy[c + 1], ar[c + 1]) - base;
+          const float p = exp2_hw((float)d0) + exp2_hw((float)d1);
+          Mp = fmaxf(Mp, p);
+          S += (double)p;
         }
-        wave_sync();
+        two = !(S >= kSumLo && S <= kSumHi);
+      }
+      if (two) {
+        double M = -INFINITY;
+#pragma unroll 4
+        for (int c = 0; c < inner; ++c) M = fmax(M, fma(cf, sy[c], ar[c]));
+        base = M;
+        S = 0.0;
+        Mp = 0.0f;
+        if (M > -INFINITY) {
+#pragma unroll 4
+          for (int c = 0; c < inner; c += 2) {
+            const double d0 = fma(cf, sy[c], ar[c]) - M, d1 = fma(cf, sy[c + 1], ar[c + 1]) - M;
+            if (F64) {
+              S += exp2(d0) + exp2(d1);
+            } else {
+              const float p = exp2_hw((float)d0) + exp2_hw((float)d1);
+              Mp = fmaxf(Mp, p);
+              S += (double)p;
+            }
+          }
+        }
+      }
+      const double T = (base > -INFINITY && S > 0.0) ? base + log2(S) : -INFINITY;
+      // next shift: the log2 of the largest pair sum (FP32 core), the exact max (F64)
+      const double nsh = F64 ? base : (Mp > 0.0f ? base + log2((double)Mp) : -INFINITY);
+      if (PASS == 0) {
+        const double Ru = ys[(size_t)line * Bk * 2];
+        Tt[(size_t)o * Ak + line] = T - kap * (z * z) - kap * (Ru * Ru);
+        shift[(size_t)line * Bj + o] = nsh;
+      } else if (x < nj) {
+        ((GDblW*)md.mfull)[x] = T > -INFINITY ? kLn2 * (T - kap * (z * z)) - ck : -INFINITY;
+        shift[x] = nsh;
       }
     }
-    if (q < Bj) T[q] = (M > -INFINITY && S > 0.0) ? M + log2(S) : -INFINITY;
   }
 }
 
-// Node stage of a separable instance: one block of 4 waves per 64-row tile of
-// a node of the class being updated.  Waves take the incident edges in turn
-// (lane = row): the second pass of each message, reading T from the first,
-// then the source normaliser as in k_node; after one barrier the row owners
-// (one wave per tile record) take their rows through every edge for the
-// stopping-sum terms of the state before the update, the update and the
+// Node stage of a separable instance, after its messages (the second pass
+// wrote them to mfull): one wave per tile record (tb.rec_rows rows, lane =
+// row; 64 / rec_rows records per 64-row tile, kSepWaves records per block),
+// the stopping-sum terms of the state before the update, the update and the
 // record, as k_node does.
-template <bool F64>
-__global__ __launch_bounds__(64 * kSepWaves) void k_node_sep(Tables tb) {
-  __shared__ double s_r[kSepWaves][64];
-  __shared__ double s_m[kNodeDegLDS][64];
-  const TileItem ti = tb.tiles[blockIdx.x];
+__global__ __launch_bounds__(64 * kSepWaves) void k_node_sep(Tables tb, int n_tiles) {
+  const int RR = tb.rec_rows, TQ = 64 / RR;
+  const int lane = threadIdx.x & 63, wv = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+  const int gw = (int)blockIdx.x * kSepWaves + wv;
+  if (gw >= n_tiles * TQ) return;
+  const TileItem ti = tb.tiles[gw / TQ];
+  const int sub = gw - (gw / TQ) * TQ;
   const InstState* st = tb.inst + ti.inst;
   const long long t = st->vt[tb.colour];
-  const long long t_first = st->t_first;
-  if (st->vdone[tb.colour] != 0 || t < t_first || ((t & 1) == 1) != (tb.colour == 0)) return;
+  if (st->vdone[tb.colour] != 0 || t < st->t_first || ((t & 1) == 1) != (tb.colour == 0)) return;
+  const int n = ti.n, deg = ti.deg;
+  if (ti.row0 + sub * RR >= n) return;
   const NodeItem nd = tb.nodes[ti.node];
   const CMsg* __restrict__ mds = (const CMsg*)(tb.msgs + ti.msg0);
-  const int n = ti.n, deg = ti.deg;
   const int cur = (int)(((t - 1) >> 1) % kSlots), nxt = (cur + 1) % kSlots;
-  const int src_slot = (int)((t >> 1) % kSlots);
-  const bool rec_ok = t - 1 >= t_first;
-  const int lane = threadIdx.x & 63, wv = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
-  const int x = ti.row0 + lane;
-  const bool vx = x < n;
-  const int xc = min(x, n - 1);
-  const int Bj = mds[0].cols_dst;
-  const int p = xc / Bj, q = xc - p * Bj;
-  const double Rj = ((const GDbl*)mds[0].supp_dst)[(size_t)p * Bj * 2];
-  const double kap = kLog2e / mds[0].eps;
-  double* __restrict__ sr = s_r[wv];
-  for (int k = wv; k < deg; k += kSepWaves) {
-    const CMsg& md = mds[k];
-    const int Ak = md.rows_src, Bk = md.cols_src;
-    const GDbl* __restrict__ T = (const GDbl*)md.sepT;
-    const GDbl* __restrict__ ys = (const GDbl*)md.supp_src;
-    // the source's normaliser: from its tile records when its last update
-    // (half-sweep t - 1) ran in this run, else its stored value
-    double ck = 0.0;
-    if (md.src_free) {
-      if (rec_ok) {
-        const GDbl* __restrict__ srec = (const GDbl*)md.src_tpart;
-        const int src_deg = md.src_deg, src_tiles = md.src_tiles;
-        const int s_stride = src_deg + kRecExtra, s_tile = min(lane, src_tiles - 1);
-        ck = tile_lse((const double*)srec, src_tiles, s_stride, src_deg, srec[(size_t)s_tile * s_stride + src_deg],
-                      srec[(size_t)s_tile * s_stride + src_deg + 1]);
-      } else {
-        ck = *(const GDbl*)(md.c_src + src_slot);
-      }
-    }
-    auto stage = [&](int u0) -> int {
-      const int u = min(u0 + lane, Ak - 1);
-      sr[lane] = ys[(size_t)u * Bk * 2];
-      wave_sync();
-      return min(64, Ak - u0);
-    };
-    double M = -INFINITY;
-    for (int u0 = 0; u0 < Ak; u0 += 64) {
-      const int cn = stage(u0);
-      for (int c = 0; c < cn; ++c) {
-        const double d = Rj - sr[c];
-        M = fmax(M, fma(-kap * d, d, T[(size_t)(u0 + c) * Bj + q]));
-      }
-      wave_sync();
-    }
-    double S = 0.0;
-    if (__any(M > -INFINITY)) {
-      for (int u0 = 0; u0 < Ak; u0 += 64) {
-        const int cn = stage(u0);
-        for (int c = 0; c < cn; ++c) {
-          const double d = Rj - sr[c];
-          S += exp2_term<F64>(fma(-kap * d, d, T[(size_t)(u0 + c) * Bj + q]) - M);
-        }
-        wave_sync();
-      }
-    }
-    const double m = (M > -INFINITY && S > 0.0) ? kLn2 * (M + log2(S)) - ck : -INFINITY;
-    if (k < kNodeDegLDS) s_m[k][lane] = m;
-    else if (vx) ((GDblW*)md.mfull)[x] = m;
-  }
-  __syncthreads();
-  // row owners: wave w takes rows w * RR + lane (lane < RR) and writes record
-  // row0 / RR + w
-  const int RR = tb.rec_rows, TQ = 64 / RR;
-  if (wv >= TQ || ti.row0 + wv * RR >= n) return;
-  const int lr = wv * RR + (lane < RR ? lane : 0), xr = ti.row0 + lr;
+  const int xr = ti.row0 + sub * RR + (lane < RR ? lane : 0);
   const bool vr = lane < RR && xr < n;
-  const int xs = vr ? xr : ti.row0;
-  GDblW* __restrict__ rec = (GDblW*)(nd.tpart + (size_t)(ti.row0 / RR + wv) * (deg + kRecExtra));
-  auto msg = [&](int k) -> double {
-    return k < kNodeDegLDS ? s_m[k][lr] : ((const GDbl*)mds[k].mfull)[xs];
-  };
+  const int xs = vr ? xr : ti.row0 + sub * RR;
+  GDblW* __restrict__ rec = (GDblW*)(nd.tpart + (size_t)(ti.row0 / RR + sub) * (deg + kRecExtra));
+  auto msg = [&](int k) -> double { return ((const GDbl*)mds[k].mfull)[xs]; };
   if (ti.fixed) {
     const double mu = vr ? ((const GDbl*)nd.mu)[xr] : 0.0;
     for (int k = 0; k < deg; ++k) {
@@ -1616,19 +1639,27 @@ hipError_t launch_finalize(const Tables& tb, int n_inst, hipStream_t s) {
   return hipGetLastError();
 }
 
-hipError_t launch_sep_rows(const Tables& tb, int n_items, bool fp64, hipStream_t s) {
+hipError_t launch_sep_pass(const Tables& tb, int pass, int n_items, size_t lds_bytes, bool fp64, hipStream_t s) {
   if (n_items <= 0) return hipSuccess;
-  const dim3 grid(n_items + tb.n_fin);
-  if (fp64) hipLaunchKernelGGL(k_sep_rows<true>, grid, dim3(64 * kSepWaves), 0, s, tb);
-  else hipLaunchKernelGGL(k_sep_rows<false>, grid, dim3(64 * kSepWaves), 0, s, tb);
+  if (lds_bytes > 64 * 1024) return hipErrorInvalidValue;
+  if (pass == 0) {
+    const dim3 grid(n_items + tb.n_fin);
+    if (fp64) hipLaunchKernelGGL((k_sep_pass<true, 0>), grid, dim3(64 * kSepWaves), lds_bytes, s, tb);
+    else hipLaunchKernelGGL((k_sep_pass<false, 0>), grid, dim3(64 * kSepWaves), lds_bytes, s, tb);
+  } else {
+    if (tb.n_fin != 0) return hipErrorInvalidValue;
+    if (fp64) hipLaunchKernelGGL((k_sep_pass<true, 1>), dim3(n_items), dim3(64 * kSepWaves), lds_bytes, s, tb);
+    else hipLaunchKernelGGL((k_sep_pass<false, 1>), dim3(n_items), dim3(64 * kSepWaves), lds_bytes, s, tb);
+  }
   return hipGetLastError();
 }
 
-hipError_t launch_node_sep(const Tables& tb, int n_tiles, bool fp64, hipStream_t s) {
+hipError_t launch_node_sep(const Tables& tb, int n_tiles, hipStream_t s) {
   if (n_tiles <= 0) return hipSuccess;
   if (tb.rec_rows != 32 && tb.rec_rows != 64) return hipErrorInvalidValue;
-  if (fp64) hipLaunchKernelGGL(k_node_sep<true>, dim3(n_tiles), dim3(64 * kSepWaves), 0, s, tb);
-  else hipLaunchKernelGGL(k_node_sep<false>, dim3(n_tiles), dim3(64 * kSepWaves), 0, s, tb);
+  const int waves = n_tiles * (64 / tb.rec_rows);
+  hipLaunchKernelGGL(k_node_sep, dim3((waves + kSepWaves - 1) / kSepWaves), dim3(64 * kSepWaves), 0, s, tb,
+                     n_tiles);
   return hipGetLastError();
 }
 

@@ -162,11 +162,13 @@ struct Plan {
   std::vector<TileItem> tiles[2][5];
   std::vector<std::pair<int, int>> node_tiles[2][5];  // per node: (first tile, tile count)
   TileItem* d_tiles[2][5] = {};
-  // separable instances: first-pass items per class, and per node of the
-  // separable group (in node_tiles[c][kSepGroup] order) its (first item, count)
-  std::vector<SepItem> sep_items[2];
-  std::vector<std::pair<int, int>> node_sep[2];
+  // separable instances: items of both passes per class, and per node of the
+  // separable group (in node_tiles[c][kSepGroup] order) its (first, count) in each
+  std::vector<SepItem> sep_items[2], sep_items2[2];
+  std::vector<std::array<int, 4>> node_sep[2];
   SepItem* d_sep_items[2] = {};
+  SepItem* d_sep_items2[2] = {};
+  size_t sep_lds[2][2] = {};  // dynamic LDS bytes per block, [class][pass]
   double* d_sepT = nullptr;
   int* d_inst_slot = nullptr;  // evaluation pass: committed slot of each class, per instance
   int rec_rows = 64;         // rows per tile record
@@ -198,6 +200,7 @@ struct Plan {
     tb.tiles = dk >= 0 ? d_tiles[c][dk] : nullptr;
     tb.colour = c;
     tb.sep_items = d_sep_items[c];
+    tb.sep_items2 = d_sep_items2[c];
     tb.rec_rows = rec_rows;
     tb.inst_slot = d_inst_slot;
     return tb;
@@ -230,7 +233,7 @@ struct Plan {
       }
       return hipSuccess;
     }
-    // separable instances: first pass, then the node stage that reads it
+    // separable instances: the two passes of their messages, then the node stage
     if (sep_items[c].empty()) return hipSuccess;
     if (!per_node) {
       Tables tb = tables(c, kSepGroup);
@@ -240,16 +243,19 @@ struct Plan {
         tb.fin_nodes = d_nodes[1 - c];
         *fin_pending = false;
       }
-      if ((e = launch_sep_rows(tb, (int)sep_items[c].size(), fp64, s)) != hipSuccess) return e;
+      if ((e = launch_sep_pass(tb, 0, (int)sep_items[c].size(), sep_lds[c][0], fp64, s)) != hipSuccess) return e;
       tb.n_fin = 0;
-      return launch_node_sep(tb, (int)tiles[c][kSepGroup].size(), fp64, s);
+      if ((e = launch_sep_pass(tb, 1, (int)sep_items2[c].size(), sep_lds[c][1], fp64, s)) != hipSuccess) return e;
+      return launch_node_sep(tb, (int)tiles[c][kSepGroup].size(), s);
     }
     for (size_t i = 0; i < node_sep[c].size(); ++i) {
       Tables tb = tables(c, kSepGroup);
-      tb.sep_items += node_sep[c][i].first;
-      if ((e = launch_sep_rows(tb, node_sep[c][i].second, fp64, s)) != hipSuccess) return e;
+      tb.sep_items += node_sep[c][i][0];
+      tb.sep_items2 += node_sep[c][i][2];
+      if ((e = launch_sep_pass(tb, 0, node_sep[c][i][1], sep_lds[c][0], fp64, s)) != hipSuccess) return e;
+      if ((e = launch_sep_pass(tb, 1, node_sep[c][i][3], sep_lds[c][1], fp64, s)) != hipSuccess) return e;
       tb.tiles += node_tiles[c][kSepGroup][i].first;
-      if ((e = launch_node_sep(tb, node_tiles[c][kSepGroup][i].second, fp64, s)) != hipSuccess) return e;
+      if ((e = launch_node_sep(tb, node_tiles[c][kSepGroup][i].second, s)) != hipSuccess) return e;
     }
     return hipSuccess;
   }
@@ -321,9 +327,8 @@ static int build_plan(gmot_ctx* ctx, const std::vector<gmot_problem*>& probs, No
   const int R = pl->R, target_blocks = pl->target_blocks;
   const int TM = 256 * R;
   // node tiles per (class, dimension group), with each node's work (pairs) for ordering
-  struct NodeTiles { int node_item, n_tiles, inst; double work; int sep_first, sep_count; };
+  struct NodeTiles { int node_item, n_tiles, inst; double work; };
   std::vector<NodeTiles> ntl[2][5];
-  std::vector<SepItem> sep_tmp[2];  // separable first-pass items, node by node in build order
 
   // messages and node items (class-major within each instance)
   std::vector<int> msg_class;
@@ -353,22 +358,18 @@ static int build_plan(gmot_ctx* ctx, const std::vector<gmot_problem*>& probs, No
         nd.c = p->fixed[j] ? nullptr : p->d_c + kSlots * j;
         nd.tiles = (int)ceil_div(p->sizes[j], std::min(TRows, 64));  // tile records: one per 64 rows (32 for 32-row tiles)
         if (p->sep) {
-          // first-pass items of the node's messages (4 source grid rows each), in message order
-          const int first = (int)sep_tmp[c].size();
+          // terms of the node's messages (both passes)
           double work = 0.0;
-          for (size_t q = 0; q < p->nbrs[j].size(); ++q) {
-            const int k = p->nbrs[j][q];
-            const int m = (int)pl->msgs.size() + (int)q;
-            for (int u0 = 0; u0 < p->grid_rows(k); u0 += 4) sep_tmp[c].push_back({m, u0, (int)i, 0});
-            work += (double)p->grid_rows(k) + (double)p->sizes[k] * p->grid_cols[j] / std::max(1, p->sizes[j]);
-          }
+          for (int k : p->nbrs[j])
+            work += (double)p->grid_rows(k) * p->grid_cols[j] * p->grid_cols[k] +
+                    (double)p->sizes[j] * p->grid_rows(k);
           ntl[c][kSepGroup].push_back({(int)pl->nodes[c].size(), (int)ceil_div(p->sizes[j], kSepTileRows), (int)i,
-                                       work, first, (int)sep_tmp[c].size() - first});
+                                       work});
         } else {
           double src_cols = 0.0;
           for (int k : p->nbrs[j]) src_cols += p->sizes[k];
           const int dk = p->cost_kind == GMOT_COST_EXPLICIT ? 0 : p->dim;
-          ntl[c][dk].push_back({(int)pl->nodes[c].size(), (int)ceil_div(p->sizes[j], TRows), (int)i, src_cols, 0, 0});
+          ntl[c][dk].push_back({(int)pl->nodes[c].size(), (int)ceil_div(p->sizes[j], TRows), (int)i, src_cols});
         }
         item_of[{(int)i, j}] = {c, (int)pl->nodes[c].size()};
         pl->nodes[c].push_back(nd);
@@ -465,6 +466,15 @@ static int build_plan(gmot_ctx* ctx, const std::vector<gmot_problem*>& probs, No
         pl->items[c][dk].push_back(it);
       }
   }
+  // Separable passes: a block takes as many lines of one message as fit
+  // kSepStage staged values and kSepMaxOut outputs (at least one line: grid
+  // sides are at most kSepMaxSide), with dynamic LDS for the largest block.
+  auto sep_geom = [&](const MsgDesc& md, int pass, int* lines, int* per) {
+    const int outs = pass == 0 ? md.cols_dst : md.rows_dst, inner = pass == 0 ? md.cols_src : md.rows_src;
+    *lines = pass == 0 ? md.rows_src : md.cols_dst;
+    *per = std::max(1, std::min({*lines, kSepStage / sep_row_stride(inner), kSepMaxOut / outs}));
+    return (size_t)sizeof(double) * ((size_t)*per * sep_row_stride(inner) + sep_inner_even(inner));
+  };
   // node-kernel tiles: the heaviest nodes (most source columns per row) first,
   // so their long blocks start early; each node's tiles stay consecutive
   for (int c = 0; c < 2; ++c)
@@ -478,14 +488,23 @@ static int build_plan(gmot_ctx* ctx, const std::vector<gmot_problem*>& probs, No
         for (int r = 0; r < q.n_tiles; ++r)
           pl->tiles[c][dk].push_back({q.node_item, r * rows, q.inst, qn.msg0, qn.deg, qn.n, qn.fixed, 0});
         if (dk == kSepGroup) {
-          pl->node_sep[c].push_back({(int)pl->sep_items[c].size(), q.sep_count});
-          pl->sep_items[c].insert(pl->sep_items[c].end(), sep_tmp[c].begin() + q.sep_first,
-                                  sep_tmp[c].begin() + q.sep_first + q.sep_count);
+          std::array<int, 4> r{(int)pl->sep_items[c].size(), 0, (int)pl->sep_items2[c].size(), 0};
+          for (int m = qn.msg0; m < qn.msg0 + qn.deg; ++m)
+            for (int pass = 0; pass < 2; ++pass) {
+              int lines = 0, per = 0;
+              const size_t lds = sep_geom(pl->msgs[m], pass, &lines, &per);
+              pl->sep_lds[c][pass] = std::max(pl->sep_lds[c][pass], lds);
+              auto& items = pass == 0 ? pl->sep_items[c] : pl->sep_items2[c];
+              for (int l0 = 0; l0 < lines; l0 += per) items.push_back({m, l0, q.inst, std::min(per, lines - l0)});
+            }
+          r[1] = (int)pl->sep_items[c].size() - r[0];
+          r[3] = (int)pl->sep_items2[c].size() - r[2];
+          pl->node_sep[c].push_back(r);
         }
       }
     }
   pl->rec_rows = std::min(TRows, 64);
-  // first-pass sums of separable messages
+  // first-pass sums (then their shifts) of separable messages
   int64_t sepT_total = 0;
   std::vector<int64_t> sepT_off(pl->msgs.size(), -1);
   for (size_t m = 0; m < pl->msgs.size(); ++m)
@@ -536,9 +555,10 @@ static int build_plan(gmot_ctx* ctx, const std::vector<gmot_problem*>& probs, No
   for (int c = 0; c < 2; ++c)
     for (int dk = 0; dk < 5; ++dk) o_tiles[c][dk] = take(sizeof(TileItem) * pl->tiles[c][dk].size());
   const size_t o_tpart = take(sizeof(double) * std::max<int64_t>(1, tpart_total));
-  size_t o_sep[2];
+  size_t o_sep[2], o_sep2[2];
   for (int c = 0; c < 2; ++c) o_sep[c] = take(sizeof(SepItem) * pl->sep_items[c].size());
-  const size_t o_sepT = take(sizeof(double) * std::max<int64_t>(1, sepT_total));
+  for (int c = 0; c < 2; ++c) o_sep2[c] = take(sizeof(SepItem) * pl->sep_items2[c].size());
+  const size_t o_sepT = take(sizeof(double) * 2 * std::max<int64_t>(1, sepT_total));
   const size_t o_islot = take(sizeof(int) * 2 * probs.size());
   const size_t total = off;
   if (hipMalloc(&pl->arena, total) != hipSuccess) return fail(GMOT_ENOMEM, "plan arena allocation failed");
@@ -556,6 +576,7 @@ static int build_plan(gmot_ctx* ctx, const std::vector<gmot_problem*>& probs, No
     for (int dk = 0; dk < 5; ++dk) pl->d_tiles[c][dk] = (TileItem*)(base + o_tiles[c][dk]);
   pl->d_tpart = (double*)(base + o_tpart);
   for (int c = 0; c < 2; ++c) pl->d_sep_items[c] = (SepItem*)(base + o_sep[c]);
+  for (int c = 0; c < 2; ++c) pl->d_sep_items2[c] = (SepItem*)(base + o_sep2[c]);
   pl->d_sepT = (double*)(base + o_sepT);
   pl->d_inst_slot = (int*)(base + o_islot);
   for (int c = 0; c < 2; ++c)
@@ -564,6 +585,7 @@ static int build_plan(gmot_ctx* ctx, const std::vector<gmot_problem*>& probs, No
     pl->msgs[m].partial = pl->d_partial + partial_off[m];
     pl->msgs[m].wmax = pl->d_wmax + wmax_off[m];
     pl->msgs[m].sepT = sepT_off[m] >= 0 ? pl->d_sepT + sepT_off[m] : nullptr;
+    pl->msgs[m].sepM = sepT_off[m] >= 0 ? pl->d_sepT + std::max<int64_t>(1, sepT_total) + sepT_off[m] : nullptr;
     // the source node's records (constrained sources too: read, then ignored)
     const auto src = item_of.at(msg_src.at(m));
     const NodeItem& sn = pl->nodes[src.first][src.second];
@@ -589,9 +611,13 @@ static int build_plan(gmot_ctx* ctx, const std::vector<gmot_problem*>& probs, No
     if (!pl->sep_items[c].empty())
       HIPCHK(hipMemcpyAsync(pl->d_sep_items[c], pl->sep_items[c].data(), sizeof(SepItem) * pl->sep_items[c].size(),
                             hipMemcpyHostToDevice, s));
+    if (!pl->sep_items2[c].empty())
+      HIPCHK(hipMemcpyAsync(pl->d_sep_items2[c], pl->sep_items2[c].data(),
+                            sizeof(SepItem) * pl->sep_items2[c].size(), hipMemcpyHostToDevice, s));
   }
   // one-pass shifts start at 0; the first two half-sweeps of every call take two passes anyway
   HIPCHK(hipMemsetAsync(pl->d_wmax, 0, sizeof(double) * std::max<int64_t>(1, wmax_total), s));
+  HIPCHK(hipMemsetAsync(pl->d_sepT, 0, sizeof(double) * 2 * std::max<int64_t>(1, sepT_total), s));
   HIPCHK(hipHostMalloc((void**)&pl->h_ndone, sizeof(int) * 2, hipHostMallocDefault));
   HIPCHK(hipStreamSynchronize(s));
   g_tiles = pl->stats;
@@ -1136,6 +1162,8 @@ static int upload(const gmot_tree_desc* d, gmot_problem* p) {
       const int n = p->sizes[j];
       int B = 1;
       while (B < n && X[2 * B] == X[0]) ++B;
+      // both grid sides within kSepMaxSide, so a pass block holds at least one line
+      all = B <= kSepMaxSide && (n + B - 1) / B <= kSepMaxSide;
       for (int i = 0; i < n && all; ++i)
         all = X[2 * i] == X[2 * (i / B) * B] && X[2 * i + 1] == X[2 * (i % B) + 1];
       p->grid_cols[j] = B;

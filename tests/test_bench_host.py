@@ -66,13 +66,13 @@ def test_committed_traffic_files_are_well_formed():
 def test_group_rooflines():
     st = {"msg_launches": 10, "group_ms": [0.0, 2.0, 0.0, 0.0, 1.0], "group_pairs": [0.0, 8.0e9, 0.0, 0.0, 1.0e9]}
     g = bench.group_rooflines(st)
-    assert set(g) == {"k_node<D=1>", "k_sep_rows+k_node_sep"}
+    assert set(g) == {"k_node<D=1>", "k_sep_pass+k_node_sep"}
     d1 = g["k_node<D=1>"]
     assert d1["achieved"] == pytest.approx(8.0e9 / 2.0e-3 / 1e9)
     assert d1["peak"] == pytest.approx(bench.pair_peak_gpairs(1))
     assert d1["frac"] == pytest.approx(d1["achieved"] / d1["peak"])
     assert d1["ms_per_stage"] == pytest.approx(0.2)
-    assert g["k_sep_rows+k_node_sep"]["peak"] == pytest.approx(bench.pair_peak_gpairs(1))
+    assert g["k_sep_pass+k_node_sep"]["peak"] == pytest.approx(bench.pair_peak_gpairs(1))
     ex = bench.group_rooflines({"msg_launches": 1, "group_ms": [1.0, 0, 0, 0, 0], "group_pairs": [1e9, 0, 0, 0, 0]})
     assert ex["k_node<explicit>"]["unit"] == "GB/s" and ex["k_node<explicit>"]["achieved"] == pytest.approx(4000.0)
 
