@@ -84,6 +84,7 @@ HBM_PEAK_GBS = 8000.0
 PROFILES = os.path.join(ROOT, "profiles")
 TRAFFIC_FILE = os.path.join(PROFILES, "k_node_batched512_traffic.txt")
 CHAIN_TRAFFIC_FILE = os.path.join(PROFILES, "k_node_chain32_traffic.txt")
+EXPLICIT_TRAFFIC_FILE = os.path.join(PROFILES, "k_node_explicit_tree256_traffic.txt")
 KERNEL_SRC = os.path.join(ROOT, "paper_2406_10849_amd", "csrc", "gmot_kernels.hip")
 
 
@@ -160,6 +161,42 @@ def summarize_pmc(path: str) -> str:
     for (k, c), (tot, ids, mx) in sorted(acc.items(), key=lambda kv: -kv[1][0]):
         out.append("| `%s` | %s | %d | %.1f | %.1f |" % (k, c, len(ids), tot / max(len(ids), 1), mx))
     return "\n".join(out)
+
+
+CALIB_BYTES = 1 << 30   # the --calib-copy device copy: 1 GiB read, 1 GiB written
+
+
+def pmc_kernel_bytes(path: str, kernel: str, min_frac: float = 0.0):
+    """From a rocprofv3 --pmc counter CSV of one byte counter (FETCH_SIZE or
+    WRITE_SIZE, KiB per dispatch): (dispatches of the kernel whose name
+    starts with `kernel`, their mean in bytes scaled by the calibration copy,
+    the scale).  The scale makes the largest copyBuffer dispatch (the 1 GiB
+    copy of --calib-copy) read 1 GiB."""
+    vals, calib = [], 0.0
+    for r in csv.DictReader(open(path)):
+        v = float(r["Counter_Value"])
+        if r["Kernel_Name"].startswith(kernel):
+            vals.append(v)
+        elif "copyBuffer" in r["Kernel_Name"]:
+            calib = max(calib, v)
+    # min_frac > 0 drops launches below that fraction of the largest: ones
+    # that did no stage work (every instance had stopped, so the blocks read
+    # the loop state and return)
+    vals = [v for v in vals if v >= min_frac * max(vals, default=0.0)]
+    if not vals or calib <= 0:
+        return None
+    scale = (CALIB_BYTES / 1024.0) / calib
+    return len(vals), statistics.fmean(vals) * 1024.0 * scale, scale
+
+
+def make_traffic(fetch_csv: str, write_csv: str, kernel: str, shape: str, min_frac: str = "0") -> str:
+    """One `shape W,R,H:` line of a traffic file from the two counter runs."""
+    f = pmc_kernel_bytes(fetch_csv, kernel, float(min_frac))
+    w = pmc_kernel_bytes(write_csv, kernel, float(min_frac))
+    if f is None or w is None:
+        raise SystemExit(f"no dispatches of {kernel} (or no calibration copy) in the counter files")
+    return ("shape %s: fetch_bytes_per_launch %.1f write_bytes_per_launch %.1f dispatches %d\n"
+            "calibration %s: FETCH_SIZE scale %.4f, WRITE_SIZE scale %.4f" % (shape, f[1], w[1], f[0], shape, f[2], w[2]))
 
 
 # ---------------------------------------------------------------------------
@@ -367,30 +404,36 @@ def bench_chain(ctx, args, sync) -> dict:
     return out
 
 
-def bench_tree(ctx, tol: float, half_sweeps: int) -> dict:
+def bench_tree(ctx, tol: float, half_sweeps: int, parts=("layer", "per_node", "explicit")) -> dict:
     """The 256-node random tree (n in [256, 4096], 2D grids, eps = 5e-3):
     (a) solved to the stopping sum with every message of a class in one
     launch (layer-parallel) and with one launch per message (plain), and
     (b) with explicit FP32 cost matrices (the squared distances, stored), whose
     message kernel streams 4 bytes per pair from HBM: its roofline is HBM
     bandwidth (the cost set, 4.8 GB per orientation, is far larger than the
-    256 MB last-level cache)."""
+    256 MB last-level cache).  `parts` selects among "layer", "per_node" and
+    "explicit" (profiling runs take one)."""
     from workloads import make_config, COST_EXPLICIT
     from paper_2406_10849_amd import Problem
     p = make_config(3)
     out = {"workload": "random-tree-256node-2d", "edges": p.n_edges,
            "pairs_per_half_sweep": p.pairs_per_tstep()}
-    g = Problem(ctx, p)
-    g.autotune()
-    for sched in ("layer", "per_node"):
-        g.solve(tol=tol, max_steps=200000, schedule=sched)     # graph capture outside the timing
-        t0 = time.perf_counter()
-        r = g.solve(tol=tol, max_steps=200000, schedule=sched)
-        dt = time.perf_counter() - t0
-        assert r["status"] == "converged", f"tree ({sched}) did not converge"
-        out[sched] = {"s": dt, "half_sweeps": r["t"], "edge_iterations_per_s": p.n_edges * r["t"] / dt}
-    out["layer_vs_plain_speedup"] = out["per_node"]["s"] / out["layer"]["s"]
-    g.close()
+    scheds = [sc for sc in ("layer", "per_node") if sc in parts]
+    if scheds:
+        g = Problem(ctx, p)
+        g.autotune()
+        for sched in scheds:
+            g.solve(tol=tol, max_steps=200000, schedule=sched)     # graph capture outside the timing
+            t0 = time.perf_counter()
+            r = g.solve(tol=tol, max_steps=200000, schedule=sched)
+            dt = time.perf_counter() - t0
+            assert r["status"] == "converged", f"tree ({sched}) did not converge"
+            out[sched] = {"s": dt, "half_sweeps": r["t"], "edge_iterations_per_s": p.n_edges * r["t"] / dt}
+        if len(scheds) == 2:
+            out["layer_vs_plain_speedup"] = out["per_node"]["s"] / out["layer"]["s"]
+        g.close()
+    if "explicit" not in parts:
+        return out
 
     cost = []
     for a, b in p.edges:
@@ -411,12 +454,13 @@ def bench_tree(ctx, tol: float, half_sweeps: int) -> dict:
     avg_ms = st["msg_ms"] / max(st["msg_launches"], 1)
     pairs = st["msg_pairs"] / max(st["msg_launches"], 1)
     gbs = 4.0 * pairs / (avg_ms / 1e3) / 1e9
+    shape = (tuned["waves_per_block"], tuned["rows_per_lane"], tuned["lane_groups"])
     out["explicit_cost"] = {
         "tiles": tuned, "half_sweeps_timed": st["msg_launches"], "pairs_per_launch": pairs,
         "avg_launch_ms": avg_ms, "half_sweep_avg_ms": st["sweep_ms"] / max(st["msg_launches"], 1),
         "roofline": {"bound": "hbm", "achieved": gbs, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": gbs / HBM_PEAK_GBS, "traffic": None, "kernel": "k_node<explicit cost>",
-                     "bytes_per_pair": 4}}
+                     "frac": gbs / HBM_PEAK_GBS, "traffic": measured_traffic(shape, EXPLICIT_TRAFFIC_FILE),
+                     "kernel": "k_node<explicit cost>", "bytes_per_pair": 4}}
     g.close()
     return out
 
@@ -541,7 +585,8 @@ def main() -> int:
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the plain comparison, the chain, the tree and the warm start")
     ap.add_argument("--extras", default="chain,tree,warm",
-                    help="comma-separated extras to run (chain, tree, warm, junction, figure)")
+                    help="comma-separated extras to run (chain, tree, tree_layer, tree_explicit, warm, junction, "
+                         "figure)")
     ap.add_argument("--no-headline", action="store_true",
                     help="skip the headline batch (profiling runs of one extra); prints no bench line")
     ap.add_argument("--batched-count", type=int, default=512)
@@ -551,12 +596,22 @@ def main() -> int:
     ap.add_argument("--warm-epochs", type=int, default=30)
     ap.add_argument("--summarize-stats", metavar="CSV", help="print a rocprofv3 kernel_stats CSV as markdown")
     ap.add_argument("--summarize-pmc", metavar="CSV", help="print per-dispatch means of a rocprofv3 counter CSV")
+    ap.add_argument("--make-traffic", nargs="+", metavar="ARG",
+                    help="FETCH_CSV WRITE_CSV KERNEL SHAPE [MIN_FRAC]: print the traffic-file lines of one "
+                         "kernel (name prefix) and node shape W,R,H, optionally without launches below "
+                         "MIN_FRAC of the largest (ones that did no work)")
     args = ap.parse_args()
     if args.summarize_stats:
         print(summarize_stats(args.summarize_stats))
         return 0
     if args.summarize_pmc:
         print(summarize_pmc(args.summarize_pmc))
+        return 0
+    if args.make_traffic:
+        if len(args.make_traffic) not in (4, 5):
+            ap.error("--make-traffic takes FETCH_CSV WRITE_CSV KERNEL SHAPE [MIN_FRAC]")
+        print("kernel_sha256_16: %s" % kernel_sha())
+        print(make_traffic(*args.make_traffic))
         return 0
     if args.gpus != 1:
         print(f"bench.py measures one GPU; --gpus {args.gpus} is not supported (the solver runs on a "
@@ -587,9 +642,15 @@ def main() -> int:
         log("chain: time to 1e-6, node launch roofline, rounding")
         out["chain"] = bench_chain(ctx, args, sync)
         log(f"chain: {out['chain']}")
+    tree_parts = set()
     if "tree" in extras:
+        tree_parts |= {"layer", "per_node", "explicit"}
+    for e in ("tree_layer", "tree_explicit"):
+        if e in extras:
+            tree_parts.add(e.split("_", 1)[1])
+    if tree_parts:
         log("random tree: layer-parallel vs plain schedule, explicit-cost streaming")
-        out["tree"] = bench_tree(ctx, args.tol, args.tree_half_sweeps)
+        out["tree"] = bench_tree(ctx, args.tol, args.tree_half_sweeps, tree_parts)
         log(f"tree: {out['tree']}")
     if "warm" in extras:
         log("learned warm start")
@@ -603,12 +664,6 @@ def main() -> int:
         log("Wasserstein least squares on its modified junction tree")
         out["junction"] = bench_junction(ctx, args.tol)
         log(f"junction: {out['junction']}")
-    if args.no_headline:
-        return 0
-    if not args.no_cpu_baseline and probs is not None:
-        log("timing the FP64 oracle on the host")
-        out["cpu_baseline"] = cpu_baseline(probs, args.cpu_seconds, args.tol)
-        log(f"cpu baseline: {out['cpu_baseline']}")
     if args.calib_copy:
         import torch
         x = torch.empty(1 << 28, dtype=torch.float32, device="cuda")
@@ -616,6 +671,13 @@ def main() -> int:
         y.copy_(x)
         torch.cuda.synchronize()
         out["calib_copy_bytes"] = 2 * x.numel() * 4
+        del x, y
+    if args.no_headline:
+        return 0
+    if not args.no_cpu_baseline and probs is not None:
+        log("timing the FP64 oracle on the host")
+        out["cpu_baseline"] = cpu_baseline(probs, args.cpu_seconds, args.tol)
+        log(f"cpu baseline: {out['cpu_baseline']}")
     print(json.dumps(out), flush=True)
     return 0
 

@@ -140,9 +140,9 @@ struct InstState {
   int node0[2], nnodes[2];   // node-error index ranges per class
   unsigned long long clk_start, clk_stop;
   long long onepass_from;    // the FP32-core message kernel runs one pass from this half-sweep on
-  double best_err;           // smallest stopping sum seen in this call
+  double best_err;           // last stopping sum of this call that set a record (3% below the previous one)
   long long best_t;          // the half-sweep that measured it
-  long long stall_window;    // stop as stalled after this many half-sweeps without a new minimum (0: never)
+  long long stall_window;    // stop as stalled after this many half-sweeps without a record (0: never)
   long long t_first;         // first half-sweep of this run: tile records are this run's from t_first on
   // What the node blocks of a colour-c launch read (the fields above are
   // written by the finalise step, which can run in the same launch): the

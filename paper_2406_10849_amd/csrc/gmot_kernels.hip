@@ -128,6 +128,8 @@ __device__ inline double sq_norm(const double* xs, int dim, int x) {
   return x2;
 }
 
+constexpr double kStallGain = 0.97;
+
 // Stop decision of an instance after its half-sweep t, from the stopping sum
 // E of the state before the update and its largest per-edge term Em (one
 // thread of the instance's finalise block).
@@ -141,7 +143,9 @@ __device__ void decide(const Tables& tb, InstState* st, long long t, double E, d
     st->err_sum = E;
     st->err_max = Em;
     st->checked_t = t;
-    if (E < st->best_err) {
+    // progress: a sum at least kStallGain below the last recorded one (a
+    // sum jittering at a noise floor sets no new record by chance)
+    if (E < kStallGain * st->best_err) {
       st->best_err = E;
       st->best_t = t;
     }
@@ -338,6 +342,7 @@ constexpr int kNodeDegLDS = 16;  // merged messages of the first 16 edges stay i
 // The stopping sum is accumulated in kFinParts partial sums (node i into part
 // i mod kFinParts) added in part order, so it does not depend on NW.
 constexpr int kFinParts = 16;
+constexpr int kFinEdges = 2;  // edges whose record entries a finalise wave loads together
 
 template <int NW>
 __device__ void fin_instance(const Tables& tb, const NodeItem* __restrict__ nodes, int colour, InstState* st,
@@ -365,14 +370,29 @@ __device__ void fin_instance(const Tables& tb, const NodeItem* __restrict__ node
     const int q = (i / NW) % Q;  // node i is in part i mod kFinParts = wv + q * NW
     const int deg = nd.deg, stride = deg + kRecExtra, tiles = nd.tiles;
     const double* __restrict__ tp = nd.tpart;
-    for (int k = 0; k < deg; ++k) {
-      double e = 0.0;
-      for (int tt = lane; tt < tiles; tt += 64) e += tp[(size_t)tt * stride + k];
-      e = wave_sum(e);
+    // edges k0 .. k0 + 7 at a time: each lane loads those entries of its
+    // tiles' records before any reduction, so a node waits for memory once
+    // per eight edges; per edge the sum over tiles (lane partials in tile
+    // order, then the wave sum) and the order over edges are as one at a time
+    for (int k0 = 0; k0 < deg; k0 += kFinEdges) {
+      double acc[kFinEdges];
 #pragma unroll
-      for (int qq = 0; qq < Q; ++qq)
-        if (qq == q) esum[qq] += e;
-      emax = fmax(emax, e);
+      for (int kk = 0; kk < kFinEdges; ++kk) acc[kk] = 0.0;
+      for (int tt = lane; tt < tiles; tt += 64) {
+#pragma unroll
+        for (int kk = 0; kk < kFinEdges; ++kk)
+          if (k0 + kk < deg) acc[kk] += tp[(size_t)tt * stride + k0 + kk];
+      }
+#pragma unroll
+      for (int kk = 0; kk < kFinEdges; ++kk) {
+        if (k0 + kk < deg) {
+          const double e = wave_sum(acc[kk]);
+#pragma unroll
+          for (int qq = 0; qq < Q; ++qq)
+            if (qq == q) esum[qq] += e;
+          emax = fmax(emax, e);
+        }
+      }
     }
     if (!nd.fixed) {
       const int t0 = min(lane, tiles - 1);

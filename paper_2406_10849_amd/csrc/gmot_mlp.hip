@@ -225,13 +225,26 @@ __global__ __launch_bounds__(256) void k_sum_parts(const double* part, int n, do
   if (threadIdx.x == 0) *out = s;
 }
 
-// db[n] = sum over the batch of dz[b][n]
-__global__ void k_bias_grad(const float* dz, int B, int N, float* db) {
-  const int n = blockIdx.x * blockDim.x + threadIdx.x;
-  if (n >= N) return;
+// db[n] = sum over the batch of dz[b][n]: a block takes 64 columns with 16 row
+// groups (rows g, g + 16, ...), whose partial sums are added in group order
+// through LDS (the same order on every call).
+constexpr int kBiasGroups = 16;
+__global__ __launch_bounds__(64 * kBiasGroups) void k_bias_grad(const float* dz, int B, int N, float* db) {
+  __shared__ float part[kBiasGroups][64];
+  const int c = threadIdx.x & 63, g = threadIdx.x >> 6;
+  const int n = blockIdx.x * 64 + c;
   float s = 0.f;
-  for (int b = 0; b < B; ++b) s += dz[(size_t)b * N + n];
-  db[n] = s;
+  if (n < N) {
+#pragma unroll 4
+    for (int b = g; b < B; b += kBiasGroups) s += dz[(size_t)b * N + n];
+  }
+  part[g][c] = s;
+  __syncthreads();
+  if (g == 0 && n < N) {
+    float t = 0.f;
+    for (int i = 0; i < kBiasGroups; ++i) t += part[i][c];
+    db[n] = t;
+  }
 }
 
 __global__ void k_adam(float* p, const float* g, float* m, float* v, size_t n, float lr, float b1, float b2,
@@ -704,8 +717,8 @@ int gmot_mlp_loss_grad_dev(gmot_mlp* m, const float* x_dev, const float* t_dev, 
     gw.ldc = m->w[l - 1];
     gw.C = m->grad + m->offW[l];
     MCHK((gemm<true, false, kStore>(gw, m->split_part, s)));
-    hipLaunchKernelGGL(k_bias_grad, dim3((m->w[l] + 255) / 256), dim3(256), 0, s, m->dZ[l], batch, m->w[l],
-                       m->grad + m->offB[l]);
+    hipLaunchKernelGGL(k_bias_grad, dim3((m->w[l] + 63) / 64), dim3(64 * kBiasGroups), 0, s, m->dZ[l], batch,
+                       m->w[l], m->grad + m->offB[l]);
     MCHK(hipGetLastError());
     if (l > 1) {
       // dZ_{l-1} = (dZq_l W_l) * (H_{l-1} > 0): A = dZq [b][o], B(k=o, n=i) = Wq[o][i]

@@ -114,6 +114,8 @@ struct gmot_problem {
 constexpr int kSepGroup = 4;
 // Rows per node-stage tile of separable instances.
 constexpr int kSepTileRows = 64;
+// Blocks per launch a separable pass aims at when its messages are few.
+constexpr int64_t kSepTargetBlocks = 2048;
 
 // Timing mode: events per half-sweep, and back-to-back repeats of the message
 // stage between the first two (so their mean excludes the event overhead).
@@ -469,10 +471,24 @@ static int build_plan(gmot_ctx* ctx, const std::vector<gmot_problem*>& probs, No
   // Separable passes: a block takes as many lines of one message as fit
   // kSepStage staged values and kSepMaxOut outputs (at least one line: grid
   // sides are at most kSepMaxSide), with dynamic LDS for the largest block.
-  auto sep_geom = [&](const MsgDesc& md, int pass, int* lines, int* per) {
+  // Fewer lines per block when a class has few lines in all (large messages):
+  // about kSepTargetBlocks blocks per launch, but at least one output per thread.
+  int64_t sep_total_lines[2][2] = {{0, 0}, {0, 0}};
+  for (int c = 0; c < 2; ++c)
+    for (const NodeTiles& q : ntl[c][kSepGroup]) {
+      const NodeItem& qn = pl->nodes[c][q.node_item];
+      for (int m = qn.msg0; m < qn.msg0 + qn.deg; ++m) {
+        sep_total_lines[c][0] += pl->msgs[m].rows_src;
+        sep_total_lines[c][1] += pl->msgs[m].cols_dst;
+      }
+    }
+  auto sep_geom = [&](const MsgDesc& md, int c, int pass, int* lines, int* per) {
     const int outs = pass == 0 ? md.cols_dst : md.rows_dst, inner = pass == 0 ? md.cols_src : md.rows_src;
     *lines = pass == 0 ? md.rows_src : md.cols_dst;
-    *per = std::max(1, std::min({*lines, kSepStage / sep_row_stride(inner), kSepMaxOut / outs}));
+    const int cap = std::max(1, std::min({*lines, kSepStage / sep_row_stride(inner), kSepMaxOut / outs}));
+    const int64_t want = std::max<int64_t>(ceil_div(sep_total_lines[c][pass], kSepTargetBlocks),
+                                           ceil_div(64 * kSepWaves, outs));
+    *per = (int)std::min<int64_t>(cap, want);
     return (size_t)sizeof(double) * ((size_t)*per * sep_row_stride(inner) + sep_inner_even(inner));
   };
   // node-kernel tiles: the heaviest nodes (most source columns per row) first,
@@ -492,7 +508,7 @@ static int build_plan(gmot_ctx* ctx, const std::vector<gmot_problem*>& probs, No
           for (int m = qn.msg0; m < qn.msg0 + qn.deg; ++m)
             for (int pass = 0; pass < 2; ++pass) {
               int lines = 0, per = 0;
-              const size_t lds = sep_geom(pl->msgs[m], pass, &lines, &per);
+              const size_t lds = sep_geom(pl->msgs[m], c, pass, &lines, &per);
               pl->sep_lds[c][pass] = std::max(pl->sep_lds[c][pass], lds);
               auto& items = pass == 0 ? pl->sep_items[c] : pl->sep_items2[c];
               for (int l0 = 0; l0 < lines; l0 += per) items.push_back({m, l0, q.inst, std::min(per, lines - l0)});
@@ -927,15 +943,16 @@ static int run_plan(Plan* pl, const gmot_opts* o, gmot_result* outs, const std::
 }
 
 // FP32-core solves judge convergence in FP64: the FP32-core loop stops at
-// kVerifyMargin * tol, or when its stopping sum has not reached a new minimum
-// for kStallWindow half-sweeps (the FP32 exponentials leave a noise floor that
-// can lie above a small tol), and FP64 half-sweeps then run from that state
+// kVerifyMargin * tol, or when its stopping sum has not come 3% below its
+// last record for kStallWindow half-sweeps (the FP32 exponentials leave a
+// noise floor that can lie above a small tol), and FP64 half-sweeps then run
+// from that state
 // until the FP64 stopping sum is <= tol, within the remaining step budget.
 // On large trees the FP32-core sum can read below the FP64 sum of the same
 // state (the iteration settles at the fixed point of the rounded map), which
 // the FP64 phase corrects.
 constexpr double kVerifyMargin = 0.8;
-constexpr int64_t kStallWindow = 128;
+constexpr int64_t kStallWindow = 64;
 
 static int solve_plan(Plan* pl, const gmot_opts* o, gmot_result* outs) {
   const size_t n = pl->probs.size();
