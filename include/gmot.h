@@ -107,8 +107,9 @@ typedef struct {
                            gmot_*_stats); 0: graph replay, no events                  */
   int32_t skip_verify;  /* GMOT_PREC_FP32CORE only.  0 (default): the FP32-core loop
                            runs until its own stopping sum is <= 0.8 * tol, or until
-                           that sum has not reached a new minimum for 128 half-sweeps
-                           (FP32 noise floor above tol), then FP64 half-sweeps continue
+                           that sum has not come 3% below its last record for 64
+                           half-sweeps (FP32 noise floor above tol), then FP64
+                           half-sweeps continue
                            within the remaining max_steps until the FP64 stopping sum
                            is <= tol, so convergence is judged in FP64.  1: stop on
                            the FP32-core sum <= tol.                                 */

@@ -49,6 +49,11 @@ Readings where the paper is silent (each is listed in the design notes):
 * Stopping: check-then-update; the test is applied from the second
   half-sweep on (the first state has not been scaled anywhere yet) and the
   state returned is the one whose error passed the test.
+* The node-sequential ("plain") schedule, which the paper does not state: a
+  Gauss-Seidel sweep updates every node once, in breadth-first order from
+  node 0, each with the same per-node rule from the latest potentials of its
+  neighbours; after a sweep no class is exact, so its stop test uses the
+  stopping sum over every node.
 """
 from __future__ import annotations
 
@@ -343,6 +348,56 @@ class TreeOracle:
                 e_last = (e_sum, e_max)
             steps_done += 1
         return {"status": status, "t": self.t, "updates": steps_done, "err_sum": e_last[0], "err_max": e_last[1]}
+
+    # ------------------------------------------------- Gauss-Seidel schedule
+    def gs_order(self) -> List[int]:
+        """The nodes with neighbours in breadth-first order from node 0 (each
+        node's neighbours ascending): the order of one Gauss-Seidel sweep."""
+        seen = [False] * self.prob.n_nodes
+        seen[0] = True
+        order, dq = [], deque([0])
+        while dq:
+            v = dq.popleft()
+            if self.nbrs[v]:
+                order.append(v)
+            for w in self.nbrs[v]:
+                if not seen[w]:
+                    seen[w] = True
+                    dq.append(w)
+        return order
+
+    def gs_update(self, j: int) -> None:
+        """Node j takes the update of eq. bipartite_tree_updates1/2 from the
+        current potentials of its neighbours, and keeps it at once."""
+        msgs = {k: self.message(k, j) for k in self.nbrs[j]}
+        logqs = {k: self.log_q(j, k, msgs[k]) for k in self.nbrs[j]}
+        self.Lam.update(self.update_node_algorithm(j, logqs, msgs))
+
+    def gs_sweep(self) -> None:
+        """One node-sequential sweep: every node in gs_order() updated in turn,
+        each from its neighbours' latest potentials (the same per-node rule as
+        Algorithm tree_local_reg, with the bipartite classes replaced by single
+        nodes)."""
+        for j in self.gs_order():
+            self.gs_update(j)
+
+    def solve_gauss_seidel(self, tol: float = 1e-6, max_sweeps: int = 100000, check_every: int = 1,
+                           history: Optional[list] = None) -> dict:
+        """Sweeps until the stopping sum of the whole state (every node, both
+        classes: no class is exact after a sweep) is <= tol, tested before
+        the first sweep and after every check_every sweeps."""
+        sweeps = 0
+        while True:
+            if sweeps % check_every == 0 or sweeps >= max_sweeps:
+                e_sum, e_max = self.full_error()
+                if history is not None:
+                    history.append(e_sum)
+                if e_sum <= tol:
+                    return {"status": "converged", "sweeps": sweeps, "err_sum": e_sum, "err_max": e_max}
+                if sweeps >= max_sweeps:
+                    return {"status": "not_converged", "sweeps": sweeps, "err_sum": e_sum, "err_max": e_max}
+            self.gs_sweep()
+            sweeps += 1
 
     def run_fixed(self, steps: int, check_equivalence: bool = False) -> List[Tuple[float, float]]:
         """Exactly ``steps`` half-sweeps; returns the per-step (E_S, E_S_max)."""
