@@ -404,15 +404,18 @@ def bench_chain(ctx, args, sync) -> dict:
     return out
 
 
-def bench_tree(ctx, tol: float, half_sweeps: int, parts=("layer", "per_node", "explicit")) -> dict:
+def bench_tree(ctx, tol: float, half_sweeps: int, parts=("layer", "per_node", "gauss_seidel", "explicit")) -> dict:
     """The 256-node random tree (n in [256, 4096], 2D grids, eps = 5e-3):
     (a) solved to the stopping sum with every message of a class in one
-    launch (layer-parallel) and with one launch per message (plain), and
+    launch (layer-parallel), with one launch per node (the same iterates), and
+    by node-sequential Gauss-Seidel sweeps (FP64, |V| dependent launches per
+    sweep; an edge-iteration there is one of the 2|E| messages of a sweep
+    counted per edge, i.e. 2|E| per sweep), and
     (b) with explicit FP32 cost matrices (the squared distances, stored), whose
     message kernel streams 4 bytes per pair from HBM: its roofline is HBM
     bandwidth (the cost set, 4.8 GB per orientation, is far larger than the
     256 MB last-level cache).  `parts` selects among "layer", "per_node" and
-    "explicit" (profiling runs take one)."""
+    "explicit", "gauss_seidel" (profiling runs take one)."""
     from workloads import make_config, COST_EXPLICIT
     from paper_2406_10849_amd import Problem
     p = make_config(3)
@@ -431,6 +434,18 @@ def bench_tree(ctx, tol: float, half_sweeps: int, parts=("layer", "per_node", "e
             out[sched] = {"s": dt, "half_sweeps": r["t"], "edge_iterations_per_s": p.n_edges * r["t"] / dt}
         if len(scheds) == 2:
             out["layer_vs_plain_speedup"] = out["per_node"]["s"] / out["layer"]["s"]
+        g.close()
+    if "gauss_seidel" in parts:
+        g = Problem(ctx, p)
+        g.solve(tol=0.0, max_steps=1, schedule="gauss_seidel", check_every=1)   # plan outside the timing
+        t0 = time.perf_counter()
+        r = g.solve(tol=tol, max_steps=100000, schedule="gauss_seidel", check_every=8)
+        dt = time.perf_counter() - t0
+        assert r["status"] == "converged", "tree (Gauss-Seidel) did not converge"
+        out["gauss_seidel"] = {"s": dt, "sweeps": r["steps"], "precision": "f64", "check_every": 8,
+                               "edge_iterations_per_s": 2 * p.n_edges * r["steps"] / dt}
+        if "layer" in out:
+            out["layer_vs_gauss_seidel_speedup"] = dt / out["layer"]["s"]
         g.close()
     if "explicit" not in parts:
         return out
@@ -585,8 +600,8 @@ def main() -> int:
     ap.add_argument("--no-extras", action="store_true",
                     help="skip the plain comparison, the chain, the tree and the warm start")
     ap.add_argument("--extras", default="chain,tree,warm",
-                    help="comma-separated extras to run (chain, tree, tree_layer, tree_explicit, warm, junction, "
-                         "figure)")
+                    help="comma-separated extras to run (chain, tree, tree_layer, tree_explicit, "
+                         "tree_gauss_seidel, warm, junction, figure)")
     ap.add_argument("--no-headline", action="store_true",
                     help="skip the headline batch (profiling runs of one extra); prints no bench line")
     ap.add_argument("--batched-count", type=int, default=512)
@@ -644,8 +659,8 @@ def main() -> int:
         log(f"chain: {out['chain']}")
     tree_parts = set()
     if "tree" in extras:
-        tree_parts |= {"layer", "per_node", "explicit"}
-    for e in ("tree_layer", "tree_explicit"):
+        tree_parts |= {"layer", "per_node", "gauss_seidel", "explicit"}
+    for e in ("tree_layer", "tree_explicit", "tree_gauss_seidel"):
         if e in extras:
             tree_parts.add(e.split("_", 1)[1])
     if tree_parts:

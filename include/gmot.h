@@ -116,7 +116,15 @@ typedef struct {
   int32_t schedule;     /* GMOT_SCHED_LAYER (default): every message of the class being
                            updated in one launch; GMOT_SCHED_PER_NODE: the same
                            half-sweep with one launch per node, issued node after
-                           node (same iterates)                                      */
+                           node (same iterates); GMOT_SCHED_GAUSS_SEIDEL (gmot_solve
+                           only): node-sequential sweeps -- every node, in
+                           breadth-first order from node 0, takes the per-node
+                           update of Algorithm tree_local_reg from its neighbours'
+                           latest potentials -- always in FP64; the stop test is the
+                           stopping sum over every node, before the first sweep and
+                           after every check_every sweeps (0: 4); result.steps counts
+                           sweeps, max_steps bounds them, t is left unchanged; a
+                           non-finite sum stops with GMOT_NONFINITE without rollback */
   int32_t msg_passes;   /* FP32-core message sums.  GMOT_PASSES_AUTO (0, default): two
                            passes (row max, then sum) for the first two half-sweeps of
                            the call, then one pass shifted by each row's max from the
@@ -132,8 +140,9 @@ typedef struct {
 #define GMOT_PASSES_ONE   1
 #define GMOT_PASSES_TWO   2
 
-#define GMOT_SCHED_LAYER     0
-#define GMOT_SCHED_PER_NODE  1
+#define GMOT_SCHED_LAYER         0
+#define GMOT_SCHED_PER_NODE      1
+#define GMOT_SCHED_GAUSS_SEIDEL  2
 
 /* Kernel timing accumulated by solves with opts.timing = 1 (since the last
  * reset).  Only half-sweeps that did work for at least one instance count. */

@@ -21,7 +21,7 @@ from ._lib import (GMOT_OK, GMOT_EINVAL, GMOT_EMARGINAL, GMOT_ENOMEM, GMOT_EDEVI
 
 STATUS_NAMES = {GMOT_CONVERGED: "converged", GMOT_NOT_CONVERGED: "not_converged", GMOT_NONFINITE: "nonfinite"}
 PRECISIONS = {"fp32core": GMOT_PREC_FP32CORE, "fp64": GMOT_PREC_FP64}
-SCHEDULES = {"layer": 0, "per_node": 1}
+SCHEDULES = {"layer": 0, "per_node": 1, "gauss_seidel": 2}
 PASSES = {"auto": 0, "one": 1, "two": 2}
 
 

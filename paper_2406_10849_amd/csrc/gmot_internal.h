@@ -226,6 +226,9 @@ hipError_t launch_finalize(const Tables& tb, int n_inst, hipStream_t s);
 hipError_t launch_sep_pass(const Tables& tb, int pass, int n_items, size_t lds_bytes, bool fp64, hipStream_t s);
 hipError_t launch_node_sep(const Tables& tb, int n_tiles, hipStream_t s);
 hipError_t launch_node_eval(const Tables& tb, int n_nodes, int slot, hipStream_t s);
+// node-sequential update of node item `node_item` of tb's class from the
+// message partials k_msg wrote, into potential slot `slot` (one block)
+hipError_t launch_gs_update(const Tables& tb, int node_item, int slot, hipStream_t s);
 // dst[i] = src[i] - (c ? *c : 0) over segments (potential read-back on the device)
 struct SegCopy { const double* src; double* dst; const double* c; int64_t len; };
 hipError_t launch_seg_copy(const SegCopy* segs, int n_segs, hipStream_t s);

@@ -1427,6 +1427,48 @@ __global__ __launch_bounds__(64 * kFinWaves) void k_finalize(Tables tb) {
 }
 
 // ---------------------------------------------------------------------------
+// Node-sequential (Gauss-Seidel) update of one node (one block), after k_msg
+// wrote the column-split partials of every message into node j from its
+// neighbours' current potentials: merge them (m_{k->j}) and write the node's
+// new potentials into `slot` in the closed form of Theorem tree_dual_var
+// (Prop. equi): constrained L_(j,k) = -m_{k->j}; free L_(j,k) = abar -
+// m_{k->j}, abar = mean_k m_{k->j}, with the normaliser c_j = LSE_x abar
+// (the potential being L - c_j), in FP64.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(kBlock) void k_gs_update(Tables tb, int node_item, int slot) {
+  __shared__ double sh[4];
+  const NodeItem nd = tb.nodes[node_item];
+  const int n = nd.n, deg = nd.deg;
+  const MsgDesc* __restrict__ mds = tb.msgs + nd.msg0;
+  const int dim = mds[0].dim;
+  const bool sq = mds[0].cost_kind == 0;
+  const double* __restrict__ xs = mds[0].supp_dst;
+  double mx = -INFINITY;
+  for (int x = threadIdx.x; x < n; x += kBlock) {
+    const double x2 = sq ? sq_norm(xs, dim, x) : 0.0;
+    double as = 0.0;
+    for (int k = 0; k < deg; ++k) {
+      const double m = merge_row(mds[k], x, x2);
+      mds[k].mfull[x] = m;
+      as += m;
+    }
+    const double ab = nd.fixed ? 0.0 : as / deg;
+    for (int k = 0; k < deg; ++k) mds[k].lam_dst[slot][x] = (nd.fixed ? 0.0 : ab) - mds[k].mfull[x];
+    if (!nd.fixed) {
+      nd.abar[x] = ab;
+      mx = fmax(mx, ab);
+    }
+  }
+  if (nd.fixed) return;
+  const double M = block_max(mx, sh);
+  double sum = 0.0;
+  if (M > -INFINITY)
+    for (int x = threadIdx.x; x < n; x += kBlock) sum += exp(nd.abar[x] - M);
+  const double S = block_sum(sum, sh);
+  if (threadIdx.x == 0) nd.c[slot] = (M > -INFINITY && S > 0.0) ? M + log(S) : -INFINITY;
+}
+
+// ---------------------------------------------------------------------------
 // Evaluation node pass (one block per node, given slot): merge the splits,
 // stopping-sum terms of the state, qbar (the node marginal q_bar_j), and
 // <Lam, mu> (constrained) or rho_j and its spread in x (free).
@@ -1680,6 +1722,12 @@ hipError_t launch_node_sep(const Tables& tb, int n_tiles, hipStream_t s) {
   const int waves = n_tiles * (64 / tb.rec_rows);
   hipLaunchKernelGGL(k_node_sep, dim3((waves + kSepWaves - 1) / kSepWaves), dim3(64 * kSepWaves), 0, s, tb,
                      n_tiles);
+  return hipGetLastError();
+}
+
+hipError_t launch_gs_update(const Tables& tb, int node_item, int slot, hipStream_t s) {
+  if (node_item < 0 || slot < 0 || slot >= kSlots) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_gs_update, dim3(1), dim3(kBlock), 0, s, tb, node_item, slot);
   return hipGetLastError();
 }
 

@@ -147,6 +147,7 @@ struct Plan {
   std::vector<MsgDesc> msgs;
   std::vector<K1Item> items[2][4];  // [class][0 = explicit, 1..3 = dim]
   std::vector<std::pair<int, int>> msg_items[2][4];  // per message: (first item, item count)
+  std::vector<std::pair<int, int>> msg_item_range;    // per plan message: (first item, count) in its (class, group)
   std::vector<NodeItem> nodes[2];
   std::vector<InstState> inst;
   int total_nodes = 0;
@@ -456,6 +457,7 @@ static int build_plan(gmot_ctx* ctx, const std::vector<gmot_problem*>& probs, No
     partial_total += ns * md.n_dst;
     const int dk = md.cost_kind == GMOT_COST_EXPLICIT ? 0 : md.dim;
     pl->msg_items[c][dk].push_back({(int)pl->items[c][dk].size(), (int)(ceil_div(md.n_dst, TM) * ns)});
+    pl->msg_item_range.push_back(pl->msg_items[c][dk].back());
     for (int64_t rt = 0; rt < ceil_div(md.n_dst, TM); ++rt)
       for (int64_t s = 0; s < ns; ++s) {
         K1Item it{};
@@ -1350,7 +1352,8 @@ static int validate_opts(const gmot_opts* o) {
   if (o->check_every < 0) return fail(GMOT_EINVAL, "check_every must be >= 0");
   if (o->precision != GMOT_PREC_FP32CORE && o->precision != GMOT_PREC_FP64)
     return fail(GMOT_EINVAL, "unknown precision");
-  if (o->schedule != GMOT_SCHED_LAYER && o->schedule != GMOT_SCHED_PER_NODE)
+  if (o->schedule != GMOT_SCHED_LAYER && o->schedule != GMOT_SCHED_PER_NODE &&
+      o->schedule != GMOT_SCHED_GAUSS_SEIDEL)
     return fail(GMOT_EINVAL, "unknown schedule");
   if (o->msg_passes != GMOT_PASSES_AUTO && o->msg_passes != GMOT_PASSES_ONE && o->msg_passes != GMOT_PASSES_TWO)
     return fail(GMOT_EINVAL, "unknown msg_passes");
@@ -1693,6 +1696,110 @@ void gmot_ctx_release(gmot_ctx* ctx) {
   delete ctx;
 }
 
+// Stopping sum over every node (both classes) of the plan's first instance,
+// FP64 from the committed slots (eval_messages), summed as evaluate_plan sums it.
+static int stopping_sum(Plan* pl, double* e_sum, double* e_max) {
+  int rc = eval_messages(pl, -1);
+  if (rc) return rc;
+  std::vector<double4> ne(std::max(1, pl->total_nodes));
+  HIPCHK(hipMemcpy(ne.data(), pl->d_node_eval, sizeof(double4) * pl->total_nodes, hipMemcpyDeviceToHost));
+  double err = 0.0, errm = 0.0;
+  for (int c = 0; c < 2; ++c) {
+    const int i0 = pl->inst[0].node0[c], cnt = pl->inst[0].nnodes[c];
+    for (int q = i0; q < i0 + cnt; ++q) {
+      const double4 v = ne[pl->nodes[c][q].err_idx];
+      err += v.x;
+      errm = std::max(errm, v.y);
+    }
+  }
+  *e_sum = err;
+  *e_max = errm;
+  return GMOT_OK;
+}
+
+// Node-sequential (Gauss-Seidel) sweeps: every node with neighbours, in
+// breadth-first order from node 0, takes the per-node update of Algorithm
+// tree_local_reg from its neighbours' committed potentials -- the FP64
+// message kernel over that node's messages alone (k_msg, its plan items),
+// then k_gs_update -- written in place into its class's committed slot, so
+// the nodes after it in the sweep read it.  The stop test is the FP64
+// stopping sum over every node, before the first sweep and after every
+// check_every sweeps (4 by default); steps counts sweeps, t is unchanged.
+static int solve_gauss_seidel(gmot_problem* p, const gmot_opts* o, gmot_result* out) {
+  Plan* pl = p->plan;
+  std::memset(out, 0, sizeof(*out));
+  out->t = p->t;
+  if (p->E == 0) {
+    out->status = GMOT_CONVERGED;
+    return GMOT_OK;
+  }
+  hipStream_t s = p->ctx->stream;
+  struct Step { int c, item, dk, first, count; };
+  std::vector<Step> steps;
+  std::map<int, int> item_of[2];
+  for (int c = 0; c < 2; ++c)
+    for (size_t i = 0; i < pl->nodes[c].size(); ++i) item_of[c][pl->nodes[c][i].node] = (int)i;
+  std::vector<char> seen(p->N, 0);
+  std::deque<int> dq{0};
+  seen[0] = 1;
+  while (!dq.empty()) {
+    const int v = dq.front();
+    dq.pop_front();
+    if (!p->nbrs[v].empty()) {
+      const int c = p->colour[v], item = item_of[c].at(v);
+      const NodeItem& nd = pl->nodes[c][item];
+      const int dk = p->cost_kind == GMOT_COST_EXPLICIT ? 0 : p->dim;
+      int count = 0;
+      for (int m = nd.msg0; m < nd.msg0 + nd.deg; ++m) count += pl->msg_item_range[m].second;
+      steps.push_back({c, item, dk, pl->msg_item_range[nd.msg0].first, count});
+    }
+    for (int w : p->nbrs[v])
+      if (!seen[w]) {
+        seen[w] = 1;
+        dq.push_back(w);
+      }
+  }
+  const int every = o->check_every > 0 ? o->check_every : 4;
+  // messages into class c read the other class's committed slot; updates go
+  // to class c's committed slot
+  const int src_slot[2] = {p->slot_of_class(1), p->slot_of_class(0)};
+  const int dst_slot[2] = {p->slot_of_class(0), p->slot_of_class(1)};
+  const auto t0 = std::chrono::steady_clock::now();
+  int64_t sweeps = 0;
+  double E = INFINITY, Em = 0.0;
+  int status = GMOT_NOT_CONVERGED;
+  for (;;) {
+    if (sweeps % every == 0 || sweeps >= o->max_steps) {
+      int rc = stopping_sum(pl, &E, &Em);
+      if (rc) return rc;
+      if (!std::isfinite(E)) {
+        status = GMOT_NONFINITE;
+        break;
+      }
+      if (E <= o->tol) {
+        status = GMOT_CONVERGED;
+        break;
+      }
+      if (sweeps >= o->max_steps) break;
+    }
+    for (const Step& g : steps) {
+      Tables tb = pl->tables(g.c, g.dk);
+      tb.items += g.first;
+      HIPCHK(launch_msg(tb, g.count, g.dk, pl->R, src_slot[g.c], s));
+      HIPCHK(launch_gs_update(pl->tables(g.c, -1), g.item, dst_slot[g.c], s));
+    }
+    ++sweeps;
+    ++p->version;
+  }
+  out->status = status;
+  out->steps = sweeps;
+  out->t = p->t;
+  out->err_sum = E;
+  out->err_max = Em;
+  out->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  return GMOT_OK;
+}
+
 extern "C" {
 
 int gmot_ctx_create(gmot_ctx** out, int device, void* hip_stream) {
@@ -1808,6 +1915,7 @@ int gmot_solve(gmot_problem* p, const gmot_opts* o, gmot_result* out) {
   }
   rc = ensure_plan(p);
   if (rc) return rc;
+  if (o->schedule == GMOT_SCHED_GAUSS_SEIDEL) return solve_gauss_seidel(p, o, out);
   return solve_plan(p->plan, o, out);
 }
 
@@ -1999,6 +2107,8 @@ int gmot_batch_solve(gmot_batch* b, const gmot_opts* o, gmot_result* outs) {
   if (!b || !outs) return fail(GMOT_EINVAL, "null batch or results");
   int rc = validate_opts(o);
   if (rc) return rc;
+  if (o->schedule == GMOT_SCHED_GAUSS_SEIDEL)
+    return fail(GMOT_ENOTSUP, "the Gauss-Seidel schedule runs one problem at a time (gmot_solve)");
   HIPCHK(hipSetDevice(b->ctx->device));
   if (o->restart)
     for (gmot_problem* p : b->probs) {
