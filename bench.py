@@ -432,6 +432,14 @@ def bench_tree(ctx, tol: float, half_sweeps: int, parts=("layer", "per_node", "g
             dt = time.perf_counter() - t0
             assert r["status"] == "converged", f"tree ({sched}) did not converge"
             out[sched] = {"s": dt, "half_sweeps": r["t"], "edge_iterations_per_s": p.n_edges * r["t"] / dt}
+        if "layer" in scheds:
+            # per-group rooflines of the node stage from event-timed half-sweeps
+            g.solve(tol=0.0, max_steps=4, timing=True)
+            g.stats(reset=True)
+            g.solve(tol=0.0, max_steps=half_sweeps, timing=True)
+            st = g.stats()
+            out["layer"]["kernel_groups"] = group_rooflines(st)
+            out["layer"]["half_sweep_avg_ms"] = st["sweep_ms"] / max(st["msg_launches"], 1)
         if len(scheds) == 2:
             out["layer_vs_plain_speedup"] = out["per_node"]["s"] / out["layer"]["s"]
         g.close()

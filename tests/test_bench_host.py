@@ -91,6 +91,26 @@ def test_rocprof_summaries(tmp_path):
     assert "| `copy` | FETCH_SIZE | 1 | 5.0 | 5.0 |" in md
 
 
+def test_make_traffic_scales_by_the_calibration_copy(tmp_path):
+    """Per-dispatch means of a kernel, scaled so the 1 GiB calibration copy
+    reads 1 GiB; MIN_FRAC drops launches that did no work."""
+    hdr = "Dispatch_Id,Kernel_Name,Counter_Name,Counter_Value\n"
+    f = tmp_path / "f.csv"
+    f.write_text(hdr + "1,__amd_rocclr_copyBuffer,FETCH_SIZE,524288\n2,k_x<1>,FETCH_SIZE,1000\n"
+                       "3,k_x<1>,FETCH_SIZE,3000\n4,k_x<1>,FETCH_SIZE,2\n5,k_y,FETCH_SIZE,7\n")
+    w = tmp_path / "w.csv"
+    w.write_text(hdr + "1,__amd_rocclr_copyBuffer,WRITE_SIZE,1048576\n2,k_x<1>,WRITE_SIZE,10\n"
+                       "3,k_x<1>,WRITE_SIZE,30\n4,k_x<1>,WRITE_SIZE,2\n")
+    n, mean, scale = bench.pmc_kernel_bytes(str(f), "k_x")
+    assert n == 3 and scale == pytest.approx(2.0) and mean == pytest.approx((1000 + 3000 + 2) / 3 * 1024 * 2)
+    n, mean, _ = bench.pmc_kernel_bytes(str(f), "k_x", 0.01)
+    assert n == 2 and mean == pytest.approx(2000 * 1024 * 2)
+    txt = bench.make_traffic(str(f), str(w), "k_x", "4,1,1", "0.01")
+    line = txt.splitlines()[0]
+    assert line.startswith("shape 4,1,1: fetch_bytes_per_launch 4096000.0 write_bytes_per_launch 14336.0")
+    assert bench.pmc_kernel_bytes(str(f), "k_none") is None
+
+
 def test_several_gpus_refused_with_a_message():
     r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"],
                        capture_output=True, text=True, timeout=120)
