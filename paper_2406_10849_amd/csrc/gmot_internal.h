@@ -120,10 +120,12 @@ struct NodeItem {
 // One block of the node kernel: rows [row0, row0 + 64 R / H) of node item
 // `node` of instance `inst`.  The node's first message, degree, size and
 // kind are repeated here so the instance state, the node item and the message
-// descriptors all load one step after the tile item.
+// descriptors all load one step after the tile item.  msg_only = 1: messages
+// msg0 .. msg0 + deg of the node (a subset of its edges) are summed and
+// written to mfull, and the node's update is left to k_node_sep.
 struct TileItem {
   int32_t node, row0, inst, msg0;
-  int32_t deg, n, fixed, pad;
+  int32_t deg, n, fixed, msg_only;
 };
 
 // Per-instance loop state, written only by the last node block of a half-sweep.

@@ -993,6 +993,8 @@ void k_node(Tables tb) {
   constexpr int RR = TR < 64 ? TR : 64;  // rows per tile record
   constexpr int TQ = TR / RR;            // records per tile
   const double c_old = nd.c ? c_held_j : 0.0;
+  // a message-only item (one edge of a node whose update runs in k_node_sep)
+  const bool msg_only = ti.msg_only != 0;
 
   if (lds) {
     // merge the gr ranges of every (edge, row) into m (natural log).  With
@@ -1041,6 +1043,15 @@ void k_node(Tables tb) {
         if (xr < n) ((GDblW*)mds[k].wmax)[(size_t)u * n + xr] = s_part[ku][lr].x;
       }
     };
+    if (msg_only) {
+      // the messages go to mfull for the update kernel, with the next shifts
+      for (int it = threadIdx.x; it < deg * TR; it += NT) {
+        const int k = it / TR, lr = it - k * TR, xr = ti.row0 + lr;
+        if (xr < n) ((GDblW*)mds[k].mfull)[xr] = s_m[k][lr];
+      }
+      store_shifts(threadIdx.x, NT);
+      return;
+    }
     // Row owners: wave q takes rows q * RR + lane of the tile and, for each
     // row, every edge in order (terms of the state before the update, the
     // update), then sums its 64 rows into the row block's record: per edge the

@@ -114,6 +114,13 @@ struct gmot_problem {
 constexpr int kSepGroup = 4;
 // Rows per node-stage tile of separable instances.
 constexpr int kSepTileRows = 64;
+// In a class whose k_node groups have fewer than kSplitBelowTiles tiles, nodes
+// of degree >= kSplitDeg take their messages as one message-only item per
+// (tile, edge) and their update in k_node_sep, so a few large high-degree
+// nodes still fill the device (in a large batch the extra blocks and launch
+// cost more than they save).  GMOT_SPLIT_DEG=d splits every node of degree >= d.
+constexpr int kSplitDeg = 4;
+constexpr int64_t kSplitBelowTiles = 2048;
 // Blocks per launch a separable pass aims at when its messages are few.
 constexpr int64_t kSepTargetBlocks = 2048;
 
@@ -165,6 +172,14 @@ struct Plan {
   std::vector<TileItem> tiles[2][5];
   std::vector<std::pair<int, int>> node_tiles[2][5];  // per node: (first tile, tile count)
   TileItem* d_tiles[2][5] = {};
+  // Nodes of degree >= split_deg in the k_node groups: their tiles above are
+  // message-only items, one per (tile, edge), and their update runs in
+  // k_node_sep over these 64-row tiles (per node: (first, count), count 0 for
+  // the other nodes, in node_tiles order).
+  int split_deg = 0;
+  std::vector<TileItem> upd_tiles[2][4];
+  std::vector<std::pair<int, int>> node_upd[2][4];
+  TileItem* d_upd_tiles[2][4] = {};
   // separable instances: items of both passes per class, and per node of the
   // separable group (in node_tiles[c][kSepGroup] order) its (first, count) in each
   std::vector<SepItem> sep_items[2], sep_items2[2];
@@ -227,12 +242,21 @@ struct Plan {
           tb.fin_nodes = d_nodes[1 - c];
           *fin_pending = false;
         }
-        return launch_node(tb, (int)tiles[c][g].size(), g, W, NR, NH, fp64, s);
+        if ((e = launch_node(tb, (int)tiles[c][g].size(), g, W, NR, NH, fp64, s)) != hipSuccess) return e;
+        if (upd_tiles[c][g].empty()) return hipSuccess;
+        tb = tables(c, g);
+        tb.tiles = d_upd_tiles[c][g];
+        return launch_node_sep(tb, (int)upd_tiles[c][g].size(), s);
       }
-      for (const auto& r : node_tiles[c][g]) {
+      for (size_t i = 0; i < node_tiles[c][g].size(); ++i) {
         Tables tb = tables(c, g);
-        tb.tiles += r.first;
-        if ((e = launch_node(tb, r.second, g, W, NR, NH, fp64, s)) != hipSuccess) return e;
+        tb.tiles += node_tiles[c][g][i].first;
+        if ((e = launch_node(tb, node_tiles[c][g][i].second, g, W, NR, NH, fp64, s)) != hipSuccess) return e;
+        if (node_upd[c][g][i].second > 0) {
+          tb = tables(c, g);
+          tb.tiles = d_upd_tiles[c][g] + node_upd[c][g][i].first;
+          if ((e = launch_node_sep(tb, node_upd[c][g][i].second, s)) != hipSuccess) return e;
+        }
       }
       return hipSuccess;
     }
@@ -326,6 +350,12 @@ static int build_plan(gmot_ctx* ctx, const std::vector<gmot_problem*>& probs, No
   pl->W = shape.W;
   pl->NR = shape.R;
   pl->NH = shape.H;
+  pl->split_deg = kSplitDeg;
+  bool split_forced = false;
+  if (const char* v = std::getenv("GMOT_SPLIT_DEG")) {
+    pl->split_deg = std::max(1, std::atoi(v));
+    split_forced = true;
+  }
   const int TRows = kNodeRowsLane * shape.R / shape.H;
   const int R = pl->R, target_blocks = pl->target_blocks;
   const int TM = 256 * R;
@@ -495,16 +525,36 @@ static int build_plan(gmot_ctx* ctx, const std::vector<gmot_problem*>& probs, No
   };
   // node-kernel tiles: the heaviest nodes (most source columns per row) first,
   // so their long blocks start early; each node's tiles stay consecutive
+  bool split_class[2];
+  for (int c = 0; c < 2; ++c) {
+    int64_t class_tiles = 0;
+    for (int dk = 0; dk < kSepGroup; ++dk)
+      for (const NodeTiles& q : ntl[c][dk]) class_tiles += q.n_tiles;
+    split_class[c] = split_forced || class_tiles < kSplitBelowTiles;
+  }
   for (int c = 0; c < 2; ++c)
     for (int dk = 0; dk < 5; ++dk) {
       std::stable_sort(ntl[c][dk].begin(), ntl[c][dk].end(),
                        [](const NodeTiles& u, const NodeTiles& v) { return u.work > v.work; });
       const int rows = dk == kSepGroup ? kSepTileRows : TRows;
       for (const NodeTiles& q : ntl[c][dk]) {
-        pl->node_tiles[c][dk].push_back({(int)pl->tiles[c][dk].size(), q.n_tiles});
         const NodeItem& qn = pl->nodes[c][q.node_item];
-        for (int r = 0; r < q.n_tiles; ++r)
-          pl->tiles[c][dk].push_back({q.node_item, r * rows, q.inst, qn.msg0, qn.deg, qn.n, qn.fixed, 0});
+        const bool split = dk < kSepGroup && split_class[c] && qn.deg >= pl->split_deg;
+        pl->node_tiles[c][dk].push_back({(int)pl->tiles[c][dk].size(), q.n_tiles * (split ? qn.deg : 1)});
+        if (split) {
+          // one message-only item per (tile, edge), then the update's 64-row tiles
+          for (int r = 0; r < q.n_tiles; ++r)
+            for (int k = 0; k < qn.deg; ++k)
+              pl->tiles[c][dk].push_back({q.node_item, r * rows, q.inst, qn.msg0 + k, 1, qn.n, qn.fixed, 1});
+          const int nu = (int)ceil_div(qn.n, 64);
+          pl->node_upd[c][dk].push_back({(int)pl->upd_tiles[c][dk].size(), nu});
+          for (int r = 0; r < nu; ++r)
+            pl->upd_tiles[c][dk].push_back({q.node_item, r * 64, q.inst, qn.msg0, qn.deg, qn.n, qn.fixed, 0});
+        } else {
+          for (int r = 0; r < q.n_tiles; ++r)
+            pl->tiles[c][dk].push_back({q.node_item, r * rows, q.inst, qn.msg0, qn.deg, qn.n, qn.fixed, 0});
+          if (dk < kSepGroup) pl->node_upd[c][dk].push_back({(int)pl->upd_tiles[c][dk].size(), 0});
+        }
         if (dk == kSepGroup) {
           std::array<int, 4> r{(int)pl->sep_items[c].size(), 0, (int)pl->sep_items2[c].size(), 0};
           for (int m = qn.msg0; m < qn.msg0 + qn.deg; ++m)
@@ -549,6 +599,7 @@ static int build_plan(gmot_ctx* ctx, const std::vector<gmot_problem*>& probs, No
   for (int c = 0; c < 2; ++c) {
     pl->stats.blocks[c] = 0;
     for (int dk = 0; dk < 5; ++dk) pl->stats.blocks[c] += (int)pl->tiles[c][dk].size();
+    for (int dk = 0; dk < 4; ++dk) pl->stats.blocks[c] += (int)pl->upd_tiles[c][dk].size();
   }
 
   // one device allocation for every table
@@ -572,6 +623,9 @@ static int build_plan(gmot_ctx* ctx, const std::vector<gmot_problem*>& probs, No
   size_t o_tiles[2][5];
   for (int c = 0; c < 2; ++c)
     for (int dk = 0; dk < 5; ++dk) o_tiles[c][dk] = take(sizeof(TileItem) * pl->tiles[c][dk].size());
+  size_t o_upd[2][4];
+  for (int c = 0; c < 2; ++c)
+    for (int dk = 0; dk < 4; ++dk) o_upd[c][dk] = take(sizeof(TileItem) * pl->upd_tiles[c][dk].size());
   const size_t o_tpart = take(sizeof(double) * std::max<int64_t>(1, tpart_total));
   size_t o_sep[2], o_sep2[2];
   for (int c = 0; c < 2; ++c) o_sep[c] = take(sizeof(SepItem) * pl->sep_items[c].size());
@@ -592,6 +646,8 @@ static int build_plan(gmot_ctx* ctx, const std::vector<gmot_problem*>& probs, No
   pl->d_wmax = (double*)(base + o_wmax);
   for (int c = 0; c < 2; ++c)
     for (int dk = 0; dk < 5; ++dk) pl->d_tiles[c][dk] = (TileItem*)(base + o_tiles[c][dk]);
+  for (int c = 0; c < 2; ++c)
+    for (int dk = 0; dk < 4; ++dk) pl->d_upd_tiles[c][dk] = (TileItem*)(base + o_upd[c][dk]);
   pl->d_tpart = (double*)(base + o_tpart);
   for (int c = 0; c < 2; ++c) pl->d_sep_items[c] = (SepItem*)(base + o_sep[c]);
   for (int c = 0; c < 2; ++c) pl->d_sep_items2[c] = (SepItem*)(base + o_sep2[c]);
@@ -626,6 +682,10 @@ static int build_plan(gmot_ctx* ctx, const std::vector<gmot_problem*>& probs, No
       if (!pl->tiles[c][dk].empty())
         HIPCHK(hipMemcpyAsync(pl->d_tiles[c][dk], pl->tiles[c][dk].data(),
                               sizeof(TileItem) * pl->tiles[c][dk].size(), hipMemcpyHostToDevice, s));
+    for (int dk = 0; dk < 4; ++dk)
+      if (!pl->upd_tiles[c][dk].empty())
+        HIPCHK(hipMemcpyAsync(pl->d_upd_tiles[c][dk], pl->upd_tiles[c][dk].data(),
+                              sizeof(TileItem) * pl->upd_tiles[c][dk].size(), hipMemcpyHostToDevice, s));
     if (!pl->sep_items[c].empty())
       HIPCHK(hipMemcpyAsync(pl->d_sep_items[c], pl->sep_items[c].data(), sizeof(SepItem) * pl->sep_items[c].size(),
                             hipMemcpyHostToDevice, s));

@@ -1,0 +1,75 @@
+"""Nodes whose messages run as message-only node-kernel items, one per
+(tile, edge), with the update in k_node_sep (by default nodes of degree >= 4
+in classes of fewer than 2048 node tiles, so every case here; GMOT_SPLIT_DEG
+forces a threshold): FP64 iterates to 1e-9 of the oracle and
+FP32-core ones to 1e-6 (couplings, dual relative to the scale), for several
+block shapes, the per-node schedule, explicit costs and a converged solve
+(needs an MI355X)."""
+import numpy as np
+import pytest
+
+from oracle import TreeOracle
+from workloads import make_tree, make_star, COST_EXPLICIT
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    from paper_2406_10849_amd import Context
+    return Context(0)
+
+
+def _cases():
+    tree = make_tree([(0, 1), (0, 2), (0, 3), (1, 4), (1, 5), (5, 6)], [300, 129, 70, 64, 257, 33, 190],
+                     [0, 0, 1, 1, 1, 0, 1], dim=1, eps=0.02, instance=91)
+    star = make_star(n=200, leaves=10, eps=0.03, instance=92)
+    ex = make_tree([(0, 1), (1, 2), (1, 3)], [70, 129, 33, 200], [1, 0, 1, 1], dim=1, eps=0.05, instance=93)
+    rng = np.random.default_rng(93)
+    ex.cost = []
+    for a, b in ex.edges:
+        X, Y = ex.node_support(int(a)), ex.node_support(int(b))
+        C = np.sum((X[:, None, :] - Y[None, :, :]) ** 2, axis=2) * rng.uniform(0.5, 1.5, size=(X.shape[0], Y.shape[0]))
+        ex.cost.append(C.astype(np.float32))
+    ex.cost_kind = COST_EXPLICIT
+    return {"tree": tree, "star10": star, "explicit": ex}
+
+
+@pytest.mark.parametrize("shape", ["4,1,1", "8,1,2", "2,2,1"])
+@pytest.mark.parametrize("split", ["1", "default"])
+def test_split_nodes_match_oracle(ctx, shape, split, monkeypatch):
+    from paper_2406_10849_amd import Problem
+    monkeypatch.setenv("GMOT_NODE_SHAPE", shape)
+    if split != "default":
+        monkeypatch.setenv("GMOT_SPLIT_DEG", split)
+    for name, p in _cases().items():
+        o = TreeOracle(p)
+        o.run_fixed(12)
+        eo = o.evaluate()
+        for precision, tol in (("fp64", 1e-9), ("fp32core", 1e-6)):
+            for sched in ("layer", "per_node"):
+                g = Problem(ctx, p)
+                r = g.solve(tol=0.0, max_steps=12, precision=precision, schedule=sched)
+                assert r["steps"] == 12, (name, precision, sched)
+                assert abs(g.evaluate()["dual"] - eo["dual"]) <= tol * eo["scale"], (name, precision, sched)
+                for e in range(p.n_edges):
+                    assert np.max(np.abs(g.coupling(e) - o.coupling(e))) <= tol, (name, precision, sched, e)
+
+
+def test_split_nodes_converge_like_the_oracle(ctx, monkeypatch):
+    """Converged FP32-core solve with every node split: the oracle re-measures
+    the stopping sum of the returned potentials and stops at the same
+    half-sweep (within two) in FP64."""
+    from paper_2406_10849_amd import Problem
+    monkeypatch.setenv("GMOT_SPLIT_DEG", "1")
+    p = _cases()["star10"]
+    g = Problem(ctx, p)
+    r = g.solve(tol=1e-7, max_steps=100000)
+    assert r["status"] == "converged"
+    o = TreeOracle(p)
+    lam = o.set_potentials(g.potentials())
+    assert o.full_error(lam)[0] <= 1e-7 + 1e-12
+    ro = TreeOracle(p).solve(tol=1e-7, max_steps=100000)
+    g2 = Problem(ctx, p)
+    r2 = g2.solve(tol=1e-7, max_steps=100000, precision="fp64")
+    assert abs(r2["t"] - ro["t"]) <= 2
