@@ -139,6 +139,7 @@ constexpr int kMsgBurst = 4;
 struct GraphEntry {
   bool fp64 = false, timed = false, per_node = false, fused = false;
   int start = 0, k = 0;
+  uint64_t lists = 0;  // key of the work lists it was captured on (Plan::list_key)
   hipGraphExec_t exec[2] = {nullptr, nullptr};
   std::vector<hipEvent_t> ev[2];
 };
@@ -192,6 +193,55 @@ struct Plan {
   int rec_rows = 64;         // rows per tile record
   int* h_ndone = nullptr;  // pinned, two mailboxes
   std::vector<GraphEntry> graphs;
+  // Work lists of the node stage for a subset of the instances.  The fields
+  // above hold the lists in use (key list_key; 0 = every instance); the sets
+  // here hold the others, each in its own device buffer, so that a graph
+  // captured on a set stays valid while another is in use.  Once most
+  // instances of a batch have stopped, run_plan swaps in the lists of the
+  // running ones, so its launches no longer start blocks that only find their
+  // instance stopped.
+  struct ListSet {
+    uint64_t key = 0;
+    void* buf = nullptr;
+    std::vector<TileItem> tiles[2][5], upd[2][4];
+    std::vector<SepItem> sep[2], sep2[2];
+    TileItem* d_tiles[2][5] = {};
+    TileItem* d_upd[2][4] = {};
+    SepItem* d_sep[2] = {};
+    SepItem* d_sep2[2] = {};
+  };
+  std::vector<ListSet> list_sets;
+  uint64_t list_key = 0;
+
+  void swap_lists(ListSet& L) {
+    for (int c = 0; c < 2; ++c) {
+      for (int g = 0; g < 5; ++g) {
+        std::swap(tiles[c][g], L.tiles[c][g]);
+        std::swap(d_tiles[c][g], L.d_tiles[c][g]);
+      }
+      for (int g = 0; g < 4; ++g) {
+        std::swap(upd_tiles[c][g], L.upd[c][g]);
+        std::swap(d_upd_tiles[c][g], L.d_upd[c][g]);
+      }
+      std::swap(sep_items[c], L.sep[c]);
+      std::swap(sep_items2[c], L.sep2[c]);
+      std::swap(d_sep_items[c], L.d_sep[c]);
+      std::swap(d_sep_items2[c], L.d_sep2[c]);
+    }
+    std::swap(list_key, L.key);
+    std::swap(buf_in_use, L.buf);
+  }
+  void* buf_in_use = nullptr;  // device buffer of the lists in use (nullptr: the plan arena)
+  // Put the lists of `key` in use; false when no set has that key.
+  bool select_lists(uint64_t key) {
+    if (key == list_key) return true;
+    for (auto& L : list_sets)
+      if (L.key == key) {
+        swap_lists(L);
+        return true;
+      }
+    return false;
+  }
   TileStats stats;
   std::vector<double> inst_pairs[2];  // (x, y) pairs of each instance's messages into class c
   std::vector<double> inst_group_pairs[2][kGroups];  // the same per kernel group
@@ -203,6 +253,9 @@ struct Plan {
         if (g.exec[i]) (void)hipGraphExecDestroy(g.exec[i]);
         for (hipEvent_t e : g.ev[i]) (void)hipEventDestroy(e);
       }
+    for (auto& L : list_sets)
+      if (L.buf) (void)hipFree(L.buf);
+    if (buf_in_use) (void)hipFree(buf_in_use);
     if (arena) (void)hipFree(arena);
     if (h_ndone) (void)hipHostFree(h_ndone);
   }
@@ -768,7 +821,7 @@ static int get_graph(Plan* pl, bool fp64, bool per_node, bool fused, int start, 
                      GraphEntry** out) {
   for (auto& g : pl->graphs)
     if (g.fp64 == fp64 && g.per_node == per_node && g.fused == fused && g.start == start && g.k == k &&
-        g.timed == timed) {
+        g.timed == timed && g.lists == pl->list_key) {
       *out = &g;
       return GMOT_OK;
     }
@@ -776,6 +829,7 @@ static int get_graph(Plan* pl, bool fp64, bool per_node, bool fused, int start, 
   g.fp64 = fp64;
   g.start = start;
   g.k = k;
+  g.lists = pl->list_key;
   g.timed = timed;
   g.per_node = per_node;
   g.fused = fused;
@@ -792,6 +846,109 @@ static int get_graph(Plan* pl, bool fp64, bool per_node, bool fused, int start, 
   }
   pl->graphs.push_back(std::move(g));
   *out = &pl->graphs.back();
+  return GMOT_OK;
+}
+
+// Batches of at least kCompactMin instances swap in the work lists of their
+// running instances whenever these number at most 1/kCompactRatio of the
+// instances in the lists in use; at most kMaxListSets compacted sets (and
+// their graphs) are kept.
+constexpr int kCompactMin = 64;
+constexpr int kCompactRatio = 2;
+constexpr size_t kMaxListSets = 8;
+
+// Puts in use the work lists of the instances with running[i] != 0 (taken, in
+// order, from the lists in use, which hold them all), from the stored set with
+// that instance set's key or a new one in a device buffer of its own.
+static int compact_lists(Plan* pl, const std::vector<char>& running, int* count) {
+  uint64_t key = 1469598103934665603ull;  // FNV-1a over the running instance indexes
+  int cnt = 0;
+  for (size_t i = 0; i < running.size(); ++i)
+    if (running[i]) {
+      key = (key ^ (uint64_t)i) * 1099511628211ull;
+      ++cnt;
+    }
+  key |= 1;  // 0 stands for every instance
+  *count = cnt;
+  if (pl->select_lists(key)) return GMOT_OK;
+  if (pl->list_sets.size() >= kMaxListSets) {
+    // drop the stored compacted sets and the graphs captured on them
+    for (auto it = pl->graphs.begin(); it != pl->graphs.end();) {
+      const bool stale = it->lists != 0 && it->lists != pl->list_key;
+      if (stale) {
+        for (int i = 0; i < 2; ++i) {
+          if (it->exec[i]) (void)hipGraphExecDestroy(it->exec[i]);
+          for (hipEvent_t e : it->ev[i]) (void)hipEventDestroy(e);
+        }
+        it = pl->graphs.erase(it);
+      } else {
+        ++it;
+      }
+    }
+    for (auto it = pl->list_sets.begin(); it != pl->list_sets.end();) {
+      if (it->key != 0) {
+        if (it->buf) (void)hipFree(it->buf);
+        it = pl->list_sets.erase(it);
+      } else {
+        ++it;
+      }
+    }
+  }
+  Plan::ListSet L;
+  L.key = key;
+  auto keep = [&](int inst) { return inst >= 0 && inst < (int)running.size() && running[inst]; };
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    const size_t o = align_up(off, 256);
+    off = o + std::max<size_t>(bytes, 1);
+    return o;
+  };
+  size_t o_t[2][5], o_u[2][4], o_s[2], o_s2[2];
+  for (int c = 0; c < 2; ++c) {
+    for (int g = 0; g < 5; ++g) {
+      for (const TileItem& t : pl->tiles[c][g])
+        if (keep(t.inst)) L.tiles[c][g].push_back(t);
+      o_t[c][g] = take(sizeof(TileItem) * L.tiles[c][g].size());
+    }
+    for (int g = 0; g < 4; ++g) {
+      for (const TileItem& t : pl->upd_tiles[c][g])
+        if (keep(t.inst)) L.upd[c][g].push_back(t);
+      o_u[c][g] = take(sizeof(TileItem) * L.upd[c][g].size());
+    }
+    for (const SepItem& it : pl->sep_items[c])
+      if (keep(it.inst)) L.sep[c].push_back(it);
+    for (const SepItem& it : pl->sep_items2[c])
+      if (keep(it.inst)) L.sep2[c].push_back(it);
+    o_s[c] = take(sizeof(SepItem) * L.sep[c].size());
+    o_s2[c] = take(sizeof(SepItem) * L.sep2[c].size());
+  }
+  if (hipMalloc(&L.buf, off) != hipSuccess) return fail(GMOT_ENOMEM, "compacted work lists");
+  char* b = (char*)L.buf;
+  hipStream_t s = pl->ctx->stream;
+  for (int c = 0; c < 2; ++c) {
+    for (int g = 0; g < 5; ++g) {
+      L.d_tiles[c][g] = (TileItem*)(b + o_t[c][g]);
+      if (!L.tiles[c][g].empty())
+        HIPCHK(hipMemcpyAsync(L.d_tiles[c][g], L.tiles[c][g].data(), sizeof(TileItem) * L.tiles[c][g].size(),
+                              hipMemcpyHostToDevice, s));
+    }
+    for (int g = 0; g < 4; ++g) {
+      L.d_upd[c][g] = (TileItem*)(b + o_u[c][g]);
+      if (!L.upd[c][g].empty())
+        HIPCHK(hipMemcpyAsync(L.d_upd[c][g], L.upd[c][g].data(), sizeof(TileItem) * L.upd[c][g].size(),
+                              hipMemcpyHostToDevice, s));
+    }
+    L.d_sep[c] = (SepItem*)(b + o_s[c]);
+    L.d_sep2[c] = (SepItem*)(b + o_s2[c]);
+    if (!L.sep[c].empty())
+      HIPCHK(hipMemcpyAsync(L.d_sep[c], L.sep[c].data(), sizeof(SepItem) * L.sep[c].size(), hipMemcpyHostToDevice, s));
+    if (!L.sep2[c].empty())
+      HIPCHK(hipMemcpyAsync(L.d_sep2[c], L.sep2[c].data(), sizeof(SepItem) * L.sep2[c].size(),
+                            hipMemcpyHostToDevice, s));
+  }
+  HIPCHK(hipStreamSynchronize(s));
+  pl->list_sets.push_back(std::move(L));
+  pl->swap_lists(pl->list_sets.back());
   return GMOT_OK;
 }
 
@@ -876,6 +1033,14 @@ static int run_plan(Plan* pl, const gmot_opts* o, gmot_result* outs, const std::
     const bool timed = o->timing != 0;
     const bool per_node = o->schedule == GMOT_SCHED_PER_NODE;
     const bool no_graph = std::getenv("GMOT_NO_GRAPH") != nullptr && !timed;
+    // every run starts on the lists of all instances
+    if (!pl->select_lists(0)) return fail(GMOT_ESTATE, "the full work lists of the plan are missing");
+    // GMOT_COMPACT_RATIO=r compacts at 1/r instead (r >= 2), 0 never
+    int compact_ratio = kCompactRatio;
+    if (const char* v = std::getenv("GMOT_COMPACT_RATIO")) compact_ratio = std::atoi(v) > 0 ? std::max(2, std::atoi(v)) : 0;
+    const bool can_compact = !timed && !no_graph && !per_node && n >= (size_t)kCompactMin && compact_ratio > 0;
+    int in_lists = (int)n;  // instances in the lists in use
+    int compact_rc = GMOT_OK;
     GraphEntry* g = nullptr;
     if (!no_graph) {
       int rc = get_graph(pl, fp64, per_node, fused, start, k, timed, &g);
@@ -946,11 +1111,29 @@ static int run_plan(Plan* pl, const gmot_opts* o, gmot_result* outs, const std::
       if (le != hipSuccess) break;
       ++waited;
       if (pl->h_ndone[slot] >= (int)n) break;
+      if (can_compact && (int64_t)((int)n - pl->h_ndone[slot]) * compact_ratio <= in_lists) {
+        // drain the replay in flight, then swap in the lists of the running instances
+        le = hipStreamSynchronize(s);
+        if (le != hipSuccess) break;
+        waited = launched;
+        if (pl->h_ndone[(launched - 1) & 1] >= (int)n) break;
+        std::vector<InstState> now(n);
+        le = hipMemcpy(now.data(), pl->d_inst, sizeof(InstState) * n, hipMemcpyDeviceToHost);
+        if (le != hipSuccess) break;
+        std::vector<char> running(n);
+        for (size_t i = 0; i < n; ++i) running[i] = now[i].done == kRunning;
+        compact_rc = compact_lists(pl, running, &in_lists);
+        if (compact_rc == GMOT_OK) compact_rc = get_graph(pl, fp64, per_node, fused, start, k, timed, &g);
+        if (compact_rc != GMOT_OK) break;
+        while (le == hipSuccess && launched < max_launches && launched - waited < 2) le = launch_one((int)(launched++ & 1));
+        continue;
+      }
       if (launched < max_launches) le = launch_one((int)(launched++ & 1));
     }
     hipError_t se = hipStreamSynchronize(s);
     (void)hipEventDestroy(ev[0]);
     (void)hipEventDestroy(ev[1]);
+    if (compact_rc != GMOT_OK) return compact_rc;
     if (le != hipSuccess) return fail(GMOT_EDEVICE, std::string("half-sweep loop: ") + hipGetErrorString(le));
     if (se != hipSuccess) return fail(GMOT_EDEVICE, std::string("half-sweep loop: ") + hipGetErrorString(se));
     pl->acc.graph_launches += launched;

@@ -458,3 +458,30 @@ def test_fused_finalise_stops_where_separate_one_does(ctx):
         assert r1["steps"] == r2["steps"] and r1["t"] == r2["t"]
         assert r1["err_sum"] == r2["err_sum"]
         assert np.array_equal(g1.potentials(), g2.potentials())
+
+
+def test_compacted_batch_matches_uncompacted(ctx, monkeypatch):
+    """A batch of 96 stars of mixed size and dimension, solved to 1e-6: once
+    most instances have stopped the replays run on the work lists of the
+    running ones (GMOT_COMPACT_RATIO=0 keeps the full lists); every instance
+    ends at the same half-sweep with bit-identical potentials either way, and
+    a sample agrees with the oracle's re-measured stopping sum."""
+    from paper_2406_10849_amd import Batch
+    monkeypatch.setenv("GMOT_NODE_SHAPE", "4,1,1")
+    probs = make_batched_stars(count=96, l_lo=2, l_hi=9, n_lo=16, n_hi=400, first_instance=300)
+    out = {}
+    for ratio in ("0", "2"):
+        monkeypatch.setenv("GMOT_COMPACT_RATIO", ratio)
+        gps = [gpu_problem(ctx, p) for p in probs]
+        b = Batch(ctx, gps)
+        rs = b.solve(tol=1e-6, max_steps=20000, check_every=4)
+        assert all(r["status"] == "converged" for r in rs)
+        out[ratio] = (rs, [g.potentials() for g in gps])
+    ts = [r["t"] for r in out["0"][0]]
+    assert max(ts) >= 2 * min(ts)  # the batch does thin out
+    for i in range(len(probs)):
+        assert out["2"][0][i]["t"] == out["0"][0][i]["t"], i
+        assert np.array_equal(out["2"][1][i], out["0"][1][i]), i
+    for i in (0, 37, 95):
+        o = TreeOracle(probs[i])
+        assert o.full_error(o.set_potentials(out["2"][1][i]))[0] <= 1e-6 + 1e-10
