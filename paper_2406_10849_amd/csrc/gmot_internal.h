@@ -281,6 +281,11 @@ struct gmot_ctx {
   std::map<uint64_t, NodeShape> tuned;  // instance shapes key -> tuned node-kernel shape
   void* scratch = nullptr;                         // small tables of the warm-start calls
   size_t scratch_size = 0;
+  // a second stream and two events, used only while capturing graphs: kernel
+  // groups of one node stage that touch different instances are captured as
+  // parallel branches (fork on ev_fork, join on ev_join)
+  hipStream_t aux = nullptr;
+  hipEvent_t ev_fork = nullptr, ev_join = nullptr;
   // One reference for the caller of gmot_ctx_create and one per live problem,
   // batch and network: the context is freed when the last one is dropped, so
   // the objects may be destroyed in any order.

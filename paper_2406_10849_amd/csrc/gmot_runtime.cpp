@@ -353,6 +353,26 @@ struct Plan {
     return hipSuccess;
   }
 
+  // The fused node stage under graph capture: the k_node groups on s and the
+  // separable group on the context's second stream as parallel branches (they
+  // work on different instances), joined before the stage ends; the finalise
+  // blocks ride in the first launch of the k_node groups (of the separable
+  // group when those are empty).  One group alone: launch_node_stage.
+  hipError_t launch_node_stage_forked(int c, bool fp64, hipStream_t s) const {
+    bool d_any = false;
+    for (int g = 0; g < kSepGroup; ++g) d_any = d_any || !group_empty(c, g);
+    if (!d_any || group_empty(c, kSepGroup)) return launch_node_stage(c, fp64, s, false, true);
+    hipError_t e;
+    bool fin_d = true, fin_sep = false;
+    if ((e = hipEventRecord(ctx->ev_fork, s)) != hipSuccess) return e;
+    if ((e = hipStreamWaitEvent(ctx->aux, ctx->ev_fork, 0)) != hipSuccess) return e;
+    if ((e = launch_group(c, kSepGroup, fp64, ctx->aux, false, &fin_sep)) != hipSuccess) return e;
+    for (int g = 0; g < kSepGroup; ++g)
+      if ((e = launch_group(c, g, fp64, s, false, &fin_d)) != hipSuccess) return e;
+    if ((e = hipEventRecord(ctx->ev_join, ctx->aux)) != hipSuccess) return e;
+    return hipStreamWaitEvent(s, ctx->ev_join, 0);
+  }
+
   // One half-sweep of class c: the node stage, then the finalise kernel.  With
   // events (timing mode, direct launches): ev[0], the node stage kMsgBurst
   // times, ev[1]; then per kernel group g ev[4 + 2g], the group kMsgBurst
@@ -363,9 +383,9 @@ struct Plan {
   // Fused (no events, layer schedule): the node stage alone, its first launch
   // finalising the previous half-sweep.
   hipError_t launch_tstep(int c, bool fp64, hipStream_t s, const hipEvent_t* ev = nullptr,
-                          bool per_node = false, bool fused = false) const {
+                          bool per_node = false, bool fused = false, bool forked = false) const {
     hipError_t e;
-    if (fused) return launch_node_stage(c, fp64, s, false, true);
+    if (fused) return forked ? launch_node_stage_forked(c, fp64, s) : launch_node_stage(c, fp64, s, false, true);
     if (ev) {
       if ((e = hipEventRecord(ev[0], s)) != hipSuccess) return e;
       for (int r = 0; r < kMsgBurst; ++r)
@@ -801,7 +821,8 @@ static int capture_one(Plan* pl, bool fp64, bool per_node, bool fused, int start
   HIPCHK(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
   hipError_t le = hipSuccess;
   for (int i = 0; i < k && le == hipSuccess; ++i)
-    le = pl->launch_tstep((start + i) & 1, fp64, s, ev ? ev->data() + kStepEvents * i : nullptr, per_node, fused);
+    le = pl->launch_tstep((start + i) & 1, fp64, s, ev ? ev->data() + kStepEvents * i : nullptr, per_node, fused,
+                          !ev && !per_node);
   hipGraph_t graph = nullptr;
   hipError_t ce = hipStreamEndCapture(s, &graph);
   if (le != hipSuccess) {
@@ -1935,6 +1956,9 @@ void gmot_ctx_release(gmot_ctx* ctx) {
   if (!ctx || ctx->refs.fetch_sub(1, std::memory_order_acq_rel) != 1) return;
   (void)hipStreamSynchronize(ctx->stream);
   if (ctx->scratch) (void)hipFree(ctx->scratch);
+  if (ctx->ev_fork) (void)hipEventDestroy(ctx->ev_fork);
+  if (ctx->ev_join) (void)hipEventDestroy(ctx->ev_join);
+  if (ctx->aux) (void)hipStreamDestroy(ctx->aux);
   if (ctx->own_stream) (void)hipStreamDestroy(ctx->stream);
   delete ctx;
 }
@@ -2066,6 +2090,9 @@ int gmot_ctx_create(gmot_ctx** out, int device, void* hip_stream) {
   int khz = 0;
   if (hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, device) == hipSuccess && khz > 0)
     c->clk_hz = 1000.0 * khz;
+  HIPCHK(hipStreamCreateWithFlags(&c->aux, hipStreamNonBlocking));
+  HIPCHK(hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming));
+  HIPCHK(hipEventCreateWithFlags(&c->ev_join, hipEventDisableTiming));
   *out = c.release();
   return GMOT_OK;
 }
