@@ -485,3 +485,25 @@ def test_compacted_batch_matches_uncompacted(ctx, monkeypatch):
     for i in (0, 37, 95):
         o = TreeOracle(probs[i])
         assert o.full_error(o.set_potentials(out["2"][1][i]))[0] <= 1e-6 + 1e-10
+
+
+def test_context_on_a_caller_stream(ctx):
+    """A context ordered on a caller's stream (a torch stream) captures its
+    graphs on that stream, with the separable group as a parallel branch:
+    a batch mixing 1D and 2D-grid stars ends with bit-identical potentials and
+    half-sweep counts to those of a context with its own stream."""
+    import torch
+    from paper_2406_10849_amd import Context, Batch
+    probs = make_batched_stars(count=8, l_lo=2, l_hi=6, n_lo=40, n_hi=300, first_instance=500)
+    assert {p.dim for p in probs} == {1, 2}
+    outs = []
+    stream = torch.cuda.Stream()
+    for c in (ctx, Context(0, stream=stream)):
+        gps = [gpu_problem(c, p) for p in probs]
+        rs = Batch(c, gps).solve(tol=1e-6, max_steps=20000, check_every=4)
+        assert all(r["status"] == "converged" for r in rs)
+        outs.append(([r["t"] for r in rs], [g.potentials() for g in gps]))
+    stream.synchronize()
+    assert outs[0][0] == outs[1][0]
+    for a, b in zip(outs[0][1], outs[1][1]):
+        assert np.array_equal(a, b)
