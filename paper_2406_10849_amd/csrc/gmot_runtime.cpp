@@ -212,6 +212,10 @@ struct Plan {
   };
   std::vector<ListSet> list_sets;
   uint64_t list_key = 0;
+  // evaluation pair pass: edge descriptors, work items and partial sums (kept
+  // between calls; the descriptors are rewritten each call)
+  void* pair_buf = nullptr;
+  size_t pair_buf_size = 0;
 
   void swap_lists(ListSet& L) {
     for (int c = 0; c < 2; ++c) {
@@ -256,6 +260,7 @@ struct Plan {
     for (auto& L : list_sets)
       if (L.buf) (void)hipFree(L.buf);
     if (buf_in_use) (void)hipFree(buf_in_use);
+    if (pair_buf) (void)hipFree(pair_buf);
     if (arena) (void)hipFree(arena);
     if (h_ndone) (void)hipHostFree(h_ndone);
   }
@@ -1686,12 +1691,9 @@ static int evaluate_plan(Plan* pl, gmot_eval* outs) {
   const size_t n = pl->probs.size();
   for (size_t i = 0; i < n; ++i) std::memset(&outs[i], 0, sizeof(gmot_eval));
   hipStream_t s = pl->ctx->stream;
-  int rc = eval_messages(pl, -1);
-  if (rc) return rc;
-  // pair pass
+  // pair pass work lists
   std::vector<EdgeDesc> eds;
   std::vector<PairItem> items;
-  std::vector<int> edge_inst;
   std::vector<int> edge0(n + 1, 0);
   for (size_t i = 0; i < n; ++i) {
     const gmot_problem* p = pl->probs[i];
@@ -1699,7 +1701,6 @@ static int evaluate_plan(Plan* pl, gmot_eval* outs) {
     for (int e = 0; e < p->E; ++e) {
       const int ge = (int)eds.size();
       eds.push_back(edge_desc(p, e));
-      edge_inst.push_back((int)i);
       const int na = eds.back().n_a, nb = eds.back().n_b;
       const int cw = 2048;
       for (int r0 = 0; r0 < na; r0 += kBlock)
@@ -1708,26 +1709,42 @@ static int evaluate_plan(Plan* pl, gmot_eval* outs) {
   }
   edge0[n] = (int)eds.size();
   if (eds.empty()) return GMOT_OK;
-  void* buf = nullptr;
   const size_t b_ed = align_up(sizeof(EdgeDesc) * eds.size(), 256);
   const size_t b_it = align_up(sizeof(PairItem) * items.size(), 256);
   const size_t b_out = sizeof(double4) * items.size();
-  if (hipMalloc(&buf, b_ed + b_it + b_out) != hipSuccess) return fail(GMOT_ENOMEM, "evaluation buffers");
-  char* base = (char*)buf;
+  if (pl->pair_buf_size < b_ed + b_it + b_out) {
+    if (pl->pair_buf) (void)hipFree(pl->pair_buf);
+    pl->pair_buf = nullptr;
+    pl->pair_buf_size = 0;
+    if (hipMalloc(&pl->pair_buf, b_ed + b_it + b_out) != hipSuccess) return fail(GMOT_ENOMEM, "evaluation buffers");
+    pl->pair_buf_size = b_ed + b_it + b_out;
+  }
+  char* base = (char*)pl->pair_buf;
   std::vector<double4> parts(items.size());
   std::vector<double4> ne(pl->total_nodes);
-  hipError_t e1 = hipMemcpyAsync(base, eds.data(), sizeof(EdgeDesc) * eds.size(), hipMemcpyHostToDevice, s);
+  // The pair pass reads only the committed potentials, so it runs on the
+  // context's second stream (after everything issued so far on the main
+  // one) beside the messages and node terms on the main stream.
+  gmot_ctx* ctx = pl->ctx;
+  hipError_t e1 = hipEventRecord(ctx->ev_fork, s);
+  if (e1 == hipSuccess) e1 = hipStreamWaitEvent(ctx->aux, ctx->ev_fork, 0);
   if (e1 == hipSuccess)
-    e1 = hipMemcpyAsync(base + b_ed, items.data(), sizeof(PairItem) * items.size(), hipMemcpyHostToDevice, s);
+    e1 = hipMemcpyAsync(base, eds.data(), sizeof(EdgeDesc) * eds.size(), hipMemcpyHostToDevice, ctx->aux);
   if (e1 == hipSuccess)
-    e1 = launch_pairs((EdgeDesc*)base, (PairItem*)(base + b_ed), (int)items.size(), (double4*)(base + b_ed + b_it), s);
+    e1 = hipMemcpyAsync(base + b_ed, items.data(), sizeof(PairItem) * items.size(), hipMemcpyHostToDevice, ctx->aux);
   if (e1 == hipSuccess)
-    e1 = hipMemcpyAsync(parts.data(), base + b_ed + b_it, b_out, hipMemcpyDeviceToHost, s);
-  if (e1 == hipSuccess)
-    e1 = hipMemcpyAsync(ne.data(), pl->d_node_eval, sizeof(double4) * pl->total_nodes, hipMemcpyDeviceToHost, s);
-  if (e1 == hipSuccess) e1 = hipStreamSynchronize(s);
-  (void)hipFree(buf);
+    e1 = launch_pairs((EdgeDesc*)base, (PairItem*)(base + b_ed), (int)items.size(), (double4*)(base + b_ed + b_it),
+                      ctx->aux);
+  if (e1 == hipSuccess) e1 = hipMemcpyAsync(parts.data(), base + b_ed + b_it, b_out, hipMemcpyDeviceToHost, ctx->aux);
+  int rc = GMOT_OK;
+  if (e1 == hipSuccess) rc = eval_messages(pl, -1);
+  hipError_t e2 = hipStreamSynchronize(ctx->aux);
   if (e1 != hipSuccess) return fail(GMOT_EDEVICE, std::string("evaluation: ") + hipGetErrorString(e1));
+  if (rc) return rc;
+  if (e2 == hipSuccess)
+    e2 = hipMemcpyAsync(ne.data(), pl->d_node_eval, sizeof(double4) * pl->total_nodes, hipMemcpyDeviceToHost, s);
+  if (e2 == hipSuccess) e2 = hipStreamSynchronize(s);
+  if (e2 != hipSuccess) return fail(GMOT_EDEVICE, std::string("evaluation: ") + hipGetErrorString(e2));
   std::vector<double> T(eds.size(), 0.0), H(eds.size(), 0.0), M(eds.size(), 0.0);
   for (size_t k = 0; k < items.size(); ++k) {
     const int e = items[k].edge;
