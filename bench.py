@@ -54,24 +54,36 @@ def pair_peak_gpairs(dim: int) -> float:
     return SIMD_CLOCKS_PER_S * 64 / cycles_per_64_pairs / 1e9
 
 
+def fma_peak_gpairs() -> float:
+    """ALU peak of the uniform-grid message sums (Gpair/s): one FP64 FMA per
+    pair (Horner's rule in the row's ratio), 78.6 TFLOP/s / 2."""
+    return SIMD_CLOCKS_PER_S * 64 / CYC_FP64 / 1e9
+
+
+GRID_GROUP_NAME = "k_msg_grid+k_node_sep"
+
+
 def group_rooflines(st: dict) -> dict:
     """ALU roofline of each kernel group of the node stage that did work, from
     the per-group timing (HIP events around back-to-back repeats of the group
     alone): k_node for D = 1, 2, 3 against the pair peak of its dimension, the
     separable grid kernels (k_sep_pass + k_node_sep) against the one-dimensional
-    pair peak (each of their terms is a one-dimensional term), k_node with
+    pair peak (each of their terms is a one-dimensional term), the uniform-grid
+    kernels (k_msg_grid + k_node_sep) against one FP64 FMA per pair, k_node with
     explicit costs against HBM bandwidth at 4 bytes per pair."""
     names = {0: "k_node<explicit>", 1: "k_node<D=1>", 2: "k_node<D=2>", 3: "k_node<D=3>",
-             4: "k_sep_pass+k_node_sep"}
+             4: "k_sep_pass+k_node_sep", 5: GRID_GROUP_NAME}
     n = max(st["msg_launches"], 1)
     out = {}
-    for g in range(5):
+    for g in range(len(st["group_ms"])):
         ms, pairs = st["group_ms"][g], st["group_pairs"][g]
         if ms <= 0 or pairs <= 0:
             continue
         gps = pairs / (ms / 1e3) / 1e9
         if g == 0:
             ach, peak, unit, bound = 4.0 * gps, HBM_PEAK_GBS, "GB/s", "hbm"
+        elif g == 5:
+            ach, peak, unit, bound = gps, fma_peak_gpairs(), "Gpair/s", "alu"
         else:
             ach, peak, unit, bound = gps, pair_peak_gpairs(g if g < 4 else 1), "Gpair/s", "alu"
         out[names[g]] = {"bound": bound, "achieved": ach, "peak": peak, "unit": unit, "frac": ach / peak,
@@ -83,7 +95,9 @@ def group_rooflines(st: dict) -> dict:
 HBM_PEAK_GBS = 8000.0
 PROFILES = os.path.join(ROOT, "profiles")
 TRAFFIC_FILE = os.path.join(PROFILES, "k_node_batched512_traffic.txt")
+GRID_TRAFFIC_FILE = os.path.join(PROFILES, "k_msg_grid_batched512_traffic.txt")
 CHAIN_TRAFFIC_FILE = os.path.join(PROFILES, "k_node_chain32_traffic.txt")
+GRID_CHAIN_TRAFFIC_FILE = os.path.join(PROFILES, "k_msg_grid_chain32_traffic.txt")
 EXPLICIT_TRAFFIC_FILE = os.path.join(PROFILES, "k_node_explicit_tree256_traffic.txt")
 KERNEL_SRC = os.path.join(ROOT, "paper_2406_10849_amd", "csrc", "gmot_kernels.hip")
 
@@ -302,7 +316,8 @@ def bench_headline(ctx, args, sync) -> tuple:
     dom = max(groups, key=lambda g: groups[g]["ms_per_stage"]) if groups else None
     avg_ms = st["msg_ms"] / max(st["msg_launches"], 1)
     shape = (tuned["waves_per_block"], tuned["rows_per_lane"], tuned["lane_groups"])
-    traffic = measured_traffic(shape) if dom == "k_node<D=1>" else None
+    traffic = (measured_traffic(shape) if dom == "k_node<D=1>" else
+               measured_traffic(shape, GRID_TRAFFIC_FILE) if dom == GRID_GROUP_NAME else None)
     rs0 = runs[-1][0]
     hs = [r["t"] for r in rs0]
     out = {
@@ -374,18 +389,19 @@ def bench_chain(ctx, args, sync) -> dict:
     st = g.stats()
     avg_ms = st["msg_ms"] / max(st["msg_launches"], 1)
     ppl = st["msg_pairs"] / max(st["msg_launches"], 1)
-    ach = ppl / (avg_ms / 1e3) / 1e9 if avg_ms > 0 else 0.0
-    peak = pair_peak_gpairs(1)
+    groups = group_rooflines(st)
+    dom = max(groups, key=lambda k: groups[k]["ms_per_stage"]) if groups else None
     shape = (tuned["waves_per_block"], tuned["rows_per_lane"], tuned["lane_groups"])
-    # the chain's node stage is one k_node launch (one support dimension)
+    traffic = (measured_traffic(shape, CHAIN_TRAFFIC_FILE) if dom == "k_node<D=1>" else
+               measured_traffic(shape, GRID_CHAIN_TRAFFIC_FILE) if dom == GRID_GROUP_NAME else None)
+    # the chain's node stage is one kernel group (one-dimensional uniform grids)
     out = {"workload": "chain-hmm-32node-n1024", "edges": prob.n_edges,
            "edge_iterations_per_s": prob.n_edges * sum(r["t"] for r in rs) / el,
            "time_to_1e-6_s": statistics.median(r["seconds"] for r in rs),
            "half_sweeps_to_1e-6": int(statistics.median(r["t"] for r in rs)), "tiles": dict(tuned, **last_tiles()),
            "dual": ev["dual"], "err_sum_fp64": ev["err_sum"],
-           "roofline": {"bound": "alu", "achieved": ach, "peak": peak, "unit": "Gpair/s", "frac": ach / peak,
-                        "traffic": measured_traffic(shape, CHAIN_TRAFFIC_FILE), "kernel": "k_node",
-                        "avg_launch_ms": avg_ms, "pairs_per_launch": ppl, "launches_timed": st["msg_launches"]}}
+           "roofline": dict(groups[dom], kernel=dom, traffic=traffic, node_stage_ms=avg_ms, pairs_per_stage=ppl,
+                            stages_timed=st["msg_launches"]) if dom else None}
     rt = []
     for _ in range(5):
         sync()

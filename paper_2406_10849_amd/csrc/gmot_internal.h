@@ -87,6 +87,12 @@ constexpr int kSepWaves = 4;        // waves per block of a separable pass
 constexpr int kSepMaxSide = 2048;   // grid rows and columns of a separable support at most
 constexpr int kSepMaxOut = 2048;    // outputs per separable-pass block (8 per thread)
 constexpr int kSepStage = 4608;     // staged values per separable-pass block (36 KB) at most
+// Messages from uniform one-dimensional grids sum a polynomial in each row's
+// ratio rho; the host admits a message only when every power of rho it takes
+// lies within 2^(+-kGridRange).  With the column values v_j <= 2^512 the sums
+// stay below 2^1003, and a v_j lost below the FP64 range (2^-1074) is a term
+// below 2^(-1074 + 2 kGridRange) = 2^-114 of the row's largest one.
+constexpr double kGridRange = 480.0;
 // Staged row stride and length of a separable pass with `inner` terms per output.
 __host__ __device__ inline int sep_row_stride(int inner) { return (inner + 1) | 1; }
 __host__ __device__ inline int sep_inner_even(int inner) { return (inner + 1) & ~1; }
@@ -227,6 +233,10 @@ hipError_t launch_finalize(const Tables& tb, int n_inst, hipStream_t s);
 // 64-row tiles
 hipError_t launch_sep_pass(const Tables& tb, int pass, int n_items, size_t lds_bytes, bool fp64, hipStream_t s);
 hipError_t launch_node_sep(const Tables& tb, int n_tiles, hipStream_t s);
+// messages on uniform one-dimensional source grids: one wave per tile item of
+// tb.tiles (a message, msg0, for 64 destination rows from row0), writing mfull;
+// the first tb.n_fin blocks carry the finalise step
+hipError_t launch_msg_grid(const Tables& tb, int n_items, hipStream_t s);
 hipError_t launch_node_eval(const Tables& tb, int n_nodes, int slot, hipStream_t s);
 // node-sequential update of node item `node_item` of tb's class from the
 // message partials k_msg wrote, into potential slot `slot` (one block)

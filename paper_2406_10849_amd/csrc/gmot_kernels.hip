@@ -1426,6 +1426,141 @@ __global__ __launch_bounds__(64 * kSepWaves) void k_node_sep(Tables tb, int n_ti
 }
 
 // ---------------------------------------------------------------------------
+// Messages whose source support is a uniform one-dimensional grid,
+// y_j = y_0 + j h (j < n_src), for the squared-Euclidean cost.  One wave takes
+// one message for 64 destination rows x (any support).  With x_c the midpoint
+// of the wave's smallest and largest row and kap = log2e / eps,
+//   w(x, y_j) = C(j) + g(x) j + 2 kap (x - x_c) y_0 - kap x^2,
+//   C(j) = log2e (L_(k,j) + log gamma_k)(y_j) - kap y_j^2 + 2 kap x_c y_j,
+//   g(x) = 2 kap (x - x_c) h,
+// so sum_j 2^w = 2^(theta + 2 kap (x - x_c) y_0 - kap x^2) * sum_j v_j rho^j
+// with v_j = 2^(C(j) - theta), the same for the wave's rows, and rho = 2^g(x)
+// per row: a polynomial in rho, summed by Horner's rule at one FP64 FMA per
+// (row, column) pair.  Columns come 64 at a time from the last tile down
+// (Horner in rho^64 across tiles).  Inside a tile every row of 16 lanes holds
+// the tile's 64 values v (four registers), the lane's powers rho^0..rho^15
+// stay in registers, and v_fmac_f64 with row_newbcast:q hands each lane
+// column q of a 16-column group; the four groups combine in rho^16.
+// theta is the largest C met so far, moved (and the partial sum rescaled) only
+// when a column exceeds it by more than kGridSlack binades, so v <= 2^kGridSlack.
+// The host takes this path only when 2 kap * (half the span of any 64 rows)
+// * |h| * max(n_src - 1, 64) <= kGridRange binades, so every power of rho
+// formed here (up to rho^64) or summed (rho^j, j < n_src) stays within
+// 2^(+-kGridRange): with FP64 no term that matters underflows and no sum
+// overflows.  Every step is FP64 (v and rho from exp2 in FP64), so the
+// messages agree with the FP64 node kernel to rounding.  The update of each
+// node follows in k_node_sep from the merged messages in mfull.
+// ---------------------------------------------------------------------------
+constexpr int kGridWaves = 4;          // waves (items) per block
+constexpr double kGridSlack = 512.0;   // v_j <= 2^kGridSlack
+
+// acc += a[lane q of acc's 16-lane row] * b (double-precision DPP row broadcast)
+#define GMOT_FMAC_ROWBCAST(acc, a, b, Q) \
+  asm("v_fmac_f64_dpp %0, %1, %2 row_newbcast:" #Q " row_mask:0xf bank_mask:0xf" : "+v"(acc) : "v"(a), "v"(b))
+
+__global__ __launch_bounds__(64 * kGridWaves) void k_msg_grid(Tables tb, int n_items) {
+  __shared__ double s_v[kGridWaves][64];
+  if ((int)blockIdx.x < tb.n_fin) {
+    // the finalise step of the previous launch's half-sweep, one block per instance
+    __shared__ double sh_fin[kFinParts][2];
+    fin_instance<kGridWaves>(tb, tb.fin_nodes, tb.fin_colour, tb.inst + blockIdx.x, true, sh_fin);
+    return;
+  }
+  const int lane = threadIdx.x & 63, wv = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+  const int gw = ((int)blockIdx.x - tb.n_fin) * kGridWaves + wv;
+  if (gw >= n_items) return;
+  const TileItem ti = tb.tiles[gw];
+  const InstState* st = tb.inst + ti.inst;
+  const long long t = st->vt[tb.colour];
+  if (st->vdone[tb.colour] != 0 || t < st->t_first || ((t & 1) == 1) != (tb.colour == 0)) return;
+  const CMsg& md = *(const CMsg*)(tb.msgs + ti.msg0);
+  const int n = md.n_dst, ns = md.n_src;
+  const int src_slot = (int)((t >> 1) % kSlots);
+  const GDbl* __restrict__ lam = (const GDbl*)md.lam_src[src_slot];
+  const GDbl* __restrict__ lg = (const GDbl*)md.lg_src;
+  const GDbl* __restrict__ ys = (const GDbl*)md.supp_src;
+  const GDbl* __restrict__ xs = (const GDbl*)md.supp_dst;
+  const double kap = kLog2e / md.eps;
+  // this lane's row (clamped: rows past n compute a value that is not stored)
+  const int x = ti.row0 + lane;
+  const double xv = xs[min(x, n - 1)];
+  const double xc = 0.5 * (wave_max(x < n ? xv : -INFINITY) - wave_max(x < n ? -xv : -INFINITY));
+  const double y0 = ys[0];
+  const double h = ns > 1 ? (ys[ns - 1] - y0) / (double)(ns - 1) : 0.0;
+  const double dx = xv - xc;
+  const double rho = exp2(2.0 * kap * dx * h);
+  double pw[16];
+  pw[0] = 1.0;
+#pragma unroll
+  for (int q = 1; q < 16; ++q) pw[q] = pw[q - 1] * rho;
+  const double r16 = pw[15] * rho;
+  const double r64 = (r16 * r16) * (r16 * r16);
+  const double cxc = 2.0 * kap * xc;
+  // column data of tile J (lane = column 64 J + lane, clamped; past n_src: no term)
+  auto c_of = [&](double l, double g, double y, bool ok) -> double {
+    return ok ? fma(cxc - kap * y, y, kLog2e * (l + g)) : -INFINITY;
+  };
+  const int nt = (ns + 63) / 64;
+  int jn = min((nt - 1) * 64 + lane, ns - 1);
+  double l_n = lam[jn], g_n = lg[jn], y_n = ys[jn];
+  double theta = -INFINITY, P = 0.0;
+  double* __restrict__ sv = s_v[wv];
+  for (int J = nt - 1; J >= 0; --J) {
+    const double C = c_of(l_n, g_n, y_n, J * 64 + lane < ns);
+    if (J > 0) {
+      // the next tile's columns, loaded while this one is summed
+      jn = (J - 1) * 64 + lane;
+      l_n = lam[jn];
+      g_n = lg[jn];
+      y_n = ys[jn];
+    }
+    if (__any(C > theta + kGridSlack)) {
+      const double m = wave_max(C);
+      if (theta > -INFINITY) P *= exp2(theta - m);
+      theta = m;
+    }
+    sv[lane] = C > -INFINITY ? exp2(C - theta) : 0.0;
+    wave_sync();
+    double vc[4];
+#pragma unroll
+    for (int c = 0; c < 4; ++c) vc[c] = sv[16 * c + (lane & 15)];
+    wave_sync();
+    double S[4] = {0.0, 0.0, 0.0, 0.0};
+    // the four groups interleaved: four independent accumulation chains
+#define GMOT_GRID_COL(Q)                                  \
+  GMOT_FMAC_ROWBCAST(S[0], vc[0], pw[Q], Q);              \
+  GMOT_FMAC_ROWBCAST(S[1], vc[1], pw[Q], Q);              \
+  GMOT_FMAC_ROWBCAST(S[2], vc[2], pw[Q], Q);              \
+  GMOT_FMAC_ROWBCAST(S[3], vc[3], pw[Q], Q);
+    GMOT_GRID_COL(0) GMOT_GRID_COL(1) GMOT_GRID_COL(2) GMOT_GRID_COL(3)
+    GMOT_GRID_COL(4) GMOT_GRID_COL(5) GMOT_GRID_COL(6) GMOT_GRID_COL(7)
+    GMOT_GRID_COL(8) GMOT_GRID_COL(9) GMOT_GRID_COL(10) GMOT_GRID_COL(11)
+    GMOT_GRID_COL(12) GMOT_GRID_COL(13) GMOT_GRID_COL(14) GMOT_GRID_COL(15)
+#undef GMOT_GRID_COL
+    P = fma(P, r64, fma(fma(fma(S[3], r16, S[2]), r16, S[1]), r16, S[0]));
+  }
+  // the source's normaliser c_k, from its tile records when its last update
+  // (half-sweep t - 1) ran in this run, else its stored value
+  double ck = 0.0;
+  if (md.src_free) {
+    if (t - 1 >= st->t_first) {
+      const GDbl* __restrict__ srec = (const GDbl*)md.src_tpart;
+      const int src_deg = md.src_deg, src_tiles = md.src_tiles;
+      const int s_stride = src_deg + kRecExtra, s_tile = min(lane, src_tiles - 1);
+      ck = tile_lse((const double*)srec, src_tiles, s_stride, src_deg, srec[(size_t)s_tile * s_stride + src_deg],
+                    srec[(size_t)s_tile * s_stride + src_deg + 1]);
+    } else {
+      ck = *(const GDbl*)(md.c_src + src_slot);
+    }
+  }
+  if (x < n) {
+    const double e = theta + fma(2.0 * kap * dx, y0, -kap * xv * xv);
+    ((GDblW*)md.mfull)[x] = (theta > -INFINITY && P > 0.0) ? kLn2 * (e + log2(P)) - ck : -INFINITY;
+  }
+}
+#undef GMOT_FMAC_ROWBCAST
+
+// ---------------------------------------------------------------------------
 // Finalise kernel: one block of kFinWaves waves per instance, one wave per
 // node of the class (nodes w, w + kFinWaves, ...): per-edge terms summed over
 // the node's tile records (lanes over tiles), and for free nodes
@@ -1733,6 +1868,13 @@ hipError_t launch_node_sep(const Tables& tb, int n_tiles, hipStream_t s) {
   const int waves = n_tiles * (64 / tb.rec_rows);
   hipLaunchKernelGGL(k_node_sep, dim3((waves + kSepWaves - 1) / kSepWaves), dim3(64 * kSepWaves), 0, s, tb,
                      n_tiles);
+  return hipGetLastError();
+}
+
+hipError_t launch_msg_grid(const Tables& tb, int n_items, hipStream_t s) {
+  if (n_items <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_msg_grid, dim3((n_items + kGridWaves - 1) / kGridWaves + tb.n_fin), dim3(64 * kGridWaves), 0,
+                     s, tb, n_items);
   return hipGetLastError();
 }
 

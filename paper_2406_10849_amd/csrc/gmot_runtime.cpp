@@ -18,6 +18,7 @@
 #include <algorithm>
 #include <chrono>
 #include <array>
+#include <cfloat>
 #include <cmath>
 #include <cstdio>
 #include <cstdlib>
@@ -93,6 +94,10 @@ struct gmot_problem {
   // squared-Euclidean cost); grid_cols[j] = points per grid row of node j
   bool sep = false;
   std::vector<int> grid_cols;
+  // messages from uniform one-dimensional grids (k_msg_grid): every support is
+  // y_j = y_0 + j h to within a few ulps, and every message keeps the powers of
+  // its rows' ratios within 2^(+-kGridRange)
+  bool grid = false;
   int grid_rows(int j) const { return (int)((sizes[j] + grid_cols[j] - 1) / grid_cols[j]); }
   int64_t t = 1;
   uint64_t version = 0;   // bumped whenever the held state changes
@@ -112,6 +117,8 @@ struct gmot_problem {
 
 // Tile group of separable instances (after the explicit-cost and D = 1..3 groups).
 constexpr int kSepGroup = 4;
+// Tile group of instances on uniform one-dimensional grids (k_msg_grid + k_node_sep).
+constexpr int kGridGroup = 5;
 // Rows per node-stage tile of separable instances.
 constexpr int kSepTileRows = 64;
 // In a class whose k_node groups have fewer than kSplitBelowTiles tiles, nodes
@@ -127,8 +134,9 @@ constexpr int64_t kSepTargetBlocks = 2048;
 // Timing mode: events per half-sweep, and back-to-back repeats of the message
 // stage between the first two (so their mean excludes the event overhead).
 // Kernel groups of a node stage: explicit cost, D = 1, 2, 3 (k_node), separable
-// grids (k_sep_rows + k_node_sep).
-constexpr int kGroups = 5;
+// grids (k_sep_pass + k_node_sep), uniform one-dimensional grids (k_msg_grid +
+// k_node_sep).
+constexpr int kGroups = 6;
 constexpr int kStepEvents = 4 + 2 * kGroups;
 constexpr int kMsgBurst = 4;
 
@@ -169,18 +177,21 @@ struct Plan {
   double2* d_partial = nullptr;
   double* d_wmax = nullptr;
   double* d_tpart = nullptr;
-  // node-kernel tiles per [class][0 = explicit, 1..3 = dim, kSepGroup = separable grids]
-  std::vector<TileItem> tiles[2][5];
-  std::vector<std::pair<int, int>> node_tiles[2][5];  // per node: (first tile, tile count)
-  TileItem* d_tiles[2][5] = {};
+  // node-kernel tiles per [class][0 = explicit, 1..3 = dim, kSepGroup = separable
+  // grids, kGridGroup = uniform one-dimensional grids (message items, one per
+  // (edge, 64 rows))]
+  std::vector<TileItem> tiles[2][kGroups];
+  std::vector<std::pair<int, int>> node_tiles[2][kGroups];  // per node: (first tile, tile count)
+  TileItem* d_tiles[2][kGroups] = {};
   // Nodes of degree >= split_deg in the k_node groups: their tiles above are
   // message-only items, one per (tile, edge), and their update runs in
   // k_node_sep over these 64-row tiles (per node: (first, count), count 0 for
-  // the other nodes, in node_tiles order).
+  // the other nodes, in node_tiles order).  The grid group's nodes all update
+  // here (index kSepGroup is unused).
   int split_deg = 0;
-  std::vector<TileItem> upd_tiles[2][4];
-  std::vector<std::pair<int, int>> node_upd[2][4];
-  TileItem* d_upd_tiles[2][4] = {};
+  std::vector<TileItem> upd_tiles[2][kGroups];
+  std::vector<std::pair<int, int>> node_upd[2][kGroups];
+  TileItem* d_upd_tiles[2][kGroups] = {};
   // separable instances: items of both passes per class, and per node of the
   // separable group (in node_tiles[c][kSepGroup] order) its (first, count) in each
   std::vector<SepItem> sep_items[2], sep_items2[2];
@@ -203,10 +214,10 @@ struct Plan {
   struct ListSet {
     uint64_t key = 0;
     void* buf = nullptr;
-    std::vector<TileItem> tiles[2][5], upd[2][4];
+    std::vector<TileItem> tiles[2][kGroups], upd[2][kGroups];
     std::vector<SepItem> sep[2], sep2[2];
-    TileItem* d_tiles[2][5] = {};
-    TileItem* d_upd[2][4] = {};
+    TileItem* d_tiles[2][kGroups] = {};
+    TileItem* d_upd[2][kGroups] = {};
     SepItem* d_sep[2] = {};
     SepItem* d_sep2[2] = {};
   };
@@ -219,11 +230,11 @@ struct Plan {
 
   void swap_lists(ListSet& L) {
     for (int c = 0; c < 2; ++c) {
-      for (int g = 0; g < 5; ++g) {
+      for (int g = 0; g < kGroups; ++g) {
         std::swap(tiles[c][g], L.tiles[c][g]);
         std::swap(d_tiles[c][g], L.d_tiles[c][g]);
       }
-      for (int g = 0; g < 4; ++g) {
+      for (int g = 0; g < kGroups; ++g) {
         std::swap(upd_tiles[c][g], L.upd[c][g]);
         std::swap(d_upd_tiles[c][g], L.d_upd[c][g]);
       }
@@ -283,9 +294,10 @@ struct Plan {
   }
 
   // Kernel group g (0 = explicit cost, 1..3 = dimension, kSepGroup =
-  // separable grids) of the node stage of class c: one launch (two for the
-  // separable group), or with per_node one per node (the same tiles, issued
-  // node by node).  *fin_pending: the first launch also carries the finalise
+  // separable grids, kGridGroup = uniform one-dimensional grids) of the node
+  // stage of class c: one launch (three for the separable group, two for the
+  // grid group), or with per_node one per node (the same tiles, issued node
+  // by node).  *fin_pending: the first launch also carries the finalise
   // step of the other class's half-sweep (the previous launch's), one block
   // per instance.
   hipError_t launch_group(int c, int g, bool fp64, hipStream_t s, bool per_node, bool* fin_pending) const {
@@ -318,6 +330,32 @@ struct Plan {
       }
       return hipSuccess;
     }
+    if (g == kGridGroup) {
+      // uniform one-dimensional grids: the messages, then the node stage
+      if (tiles[c][g].empty()) return hipSuccess;
+      if (!per_node) {
+        Tables tb = tables(c, g);
+        if (*fin_pending) {
+          tb.n_fin = (int)inst.size();
+          tb.fin_colour = 1 - c;
+          tb.fin_nodes = d_nodes[1 - c];
+          *fin_pending = false;
+        }
+        if ((e = launch_msg_grid(tb, (int)tiles[c][g].size(), s)) != hipSuccess) return e;
+        tb = tables(c, g);
+        tb.tiles = d_upd_tiles[c][g];
+        return launch_node_sep(tb, (int)upd_tiles[c][g].size(), s);
+      }
+      for (size_t i = 0; i < node_tiles[c][g].size(); ++i) {
+        Tables tb = tables(c, g);
+        tb.tiles += node_tiles[c][g][i].first;
+        if ((e = launch_msg_grid(tb, node_tiles[c][g][i].second, s)) != hipSuccess) return e;
+        tb = tables(c, g);
+        tb.tiles = d_upd_tiles[c][g] + node_upd[c][g][i].first;
+        if ((e = launch_node_sep(tb, node_upd[c][g][i].second, s)) != hipSuccess) return e;
+      }
+      return hipSuccess;
+    }
     // separable instances: the two passes of their messages, then the node stage
     if (sep_items[c].empty()) return hipSuccess;
     if (!per_node) {
@@ -345,7 +383,7 @@ struct Plan {
     return hipSuccess;
   }
 
-  bool group_empty(int c, int g) const { return g < kSepGroup ? tiles[c][g].empty() : sep_items[c].empty(); }
+  bool group_empty(int c, int g) const { return g == kSepGroup ? sep_items[c].empty() : tiles[c][g].empty(); }
 
   // The node stage of class c: every kernel group in turn.  With fused, the
   // first launch also carries the finalise step of the previous half-sweep.
@@ -358,22 +396,22 @@ struct Plan {
     return hipSuccess;
   }
 
-  // The fused node stage under graph capture: the k_node groups on s and the
+  // The fused node stage under graph capture: the other groups on s and the
   // separable group on the context's second stream as parallel branches (they
   // work on different instances), joined before the stage ends; the finalise
-  // blocks ride in the first launch of the k_node groups (of the separable
-  // group when those are empty).  One group alone: launch_node_stage.
+  // blocks ride in the first launch on s (of the separable group when the
+  // others are empty).  One group alone: launch_node_stage.
   hipError_t launch_node_stage_forked(int c, bool fp64, hipStream_t s) const {
     bool d_any = false;
-    for (int g = 0; g < kSepGroup; ++g) d_any = d_any || !group_empty(c, g);
+    for (int g = 0; g < kGroups; ++g) d_any = d_any || (g != kSepGroup && !group_empty(c, g));
     if (!d_any || group_empty(c, kSepGroup)) return launch_node_stage(c, fp64, s, false, true);
     hipError_t e;
     bool fin_d = true, fin_sep = false;
     if ((e = hipEventRecord(ctx->ev_fork, s)) != hipSuccess) return e;
     if ((e = hipStreamWaitEvent(ctx->aux, ctx->ev_fork, 0)) != hipSuccess) return e;
     if ((e = launch_group(c, kSepGroup, fp64, ctx->aux, false, &fin_sep)) != hipSuccess) return e;
-    for (int g = 0; g < kSepGroup; ++g)
-      if ((e = launch_group(c, g, fp64, s, false, &fin_d)) != hipSuccess) return e;
+    for (int g = 0; g < kGroups; ++g)
+      if (g != kSepGroup && (e = launch_group(c, g, fp64, s, false, &fin_d)) != hipSuccess) return e;
     if ((e = hipEventRecord(ctx->ev_join, ctx->aux)) != hipSuccess) return e;
     return hipStreamWaitEvent(s, ctx->ev_join, 0);
   }
@@ -439,7 +477,7 @@ static int build_plan(gmot_ctx* ctx, const std::vector<gmot_problem*>& probs, No
   const int TM = 256 * R;
   // node tiles per (class, dimension group), with each node's work (pairs) for ordering
   struct NodeTiles { int node_item, n_tiles, inst; double work; };
-  std::vector<NodeTiles> ntl[2][5];
+  std::vector<NodeTiles> ntl[2][kGroups];
 
   // messages and node items (class-major within each instance)
   std::vector<int> msg_class;
@@ -476,6 +514,10 @@ static int build_plan(gmot_ctx* ctx, const std::vector<gmot_problem*>& probs, No
                     (double)p->sizes[j] * p->grid_rows(k);
           ntl[c][kSepGroup].push_back({(int)pl->nodes[c].size(), (int)ceil_div(p->sizes[j], kSepTileRows), (int)i,
                                        work});
+        } else if (p->grid) {
+          double src_cols = 0.0;
+          for (int k : p->nbrs[j]) src_cols += p->sizes[k];
+          ntl[c][kGridGroup].push_back({(int)pl->nodes[c].size(), (int)ceil_div(p->sizes[j], 64), (int)i, src_cols});
         } else {
           double src_cols = 0.0;
           for (int k : p->nbrs[j]) src_cols += p->sizes[k];
@@ -541,7 +583,10 @@ static int build_plan(gmot_ctx* ctx, const std::vector<gmot_problem*>& probs, No
                           ? (double)md.rows_src * md.cols_dst * md.cols_src + (double)md.n_dst * md.rows_src
                           : (double)md.n_dst * md.n_src;
     pl->inst_pairs[msg_class[m]][md.inst] += ev;
-    const int grp = probs[md.inst]->sep ? kSepGroup : md.cost_kind == GMOT_COST_EXPLICIT ? 0 : md.dim;
+    const int grp = probs[md.inst]->sep    ? kSepGroup
+                    : probs[md.inst]->grid ? kGridGroup
+                    : md.cost_kind == GMOT_COST_EXPLICIT ? 0
+                                                         : md.dim;
     pl->inst_group_pairs[msg_class[m]][grp][md.inst] += ev;
   }
 
@@ -611,12 +656,24 @@ static int build_plan(gmot_ctx* ctx, const std::vector<gmot_problem*>& probs, No
     split_class[c] = split_forced || class_tiles < kSplitBelowTiles;
   }
   for (int c = 0; c < 2; ++c)
-    for (int dk = 0; dk < 5; ++dk) {
+    for (int dk = 0; dk < kGroups; ++dk) {
       std::stable_sort(ntl[c][dk].begin(), ntl[c][dk].end(),
                        [](const NodeTiles& u, const NodeTiles& v) { return u.work > v.work; });
       const int rows = dk == kSepGroup ? kSepTileRows : TRows;
       for (const NodeTiles& q : ntl[c][dk]) {
         const NodeItem& qn = pl->nodes[c][q.node_item];
+        if (dk == kGridGroup) {
+          // one message item per (edge, 64 rows), the rows of one edge together
+          // (their waves share the source's columns), then the update's 64-row tiles
+          pl->node_tiles[c][dk].push_back({(int)pl->tiles[c][dk].size(), q.n_tiles * qn.deg});
+          for (int k = 0; k < qn.deg; ++k)
+            for (int r = 0; r < q.n_tiles; ++r)
+              pl->tiles[c][dk].push_back({q.node_item, r * 64, q.inst, qn.msg0 + k, 1, qn.n, qn.fixed, 1});
+          pl->node_upd[c][dk].push_back({(int)pl->upd_tiles[c][dk].size(), q.n_tiles});
+          for (int r = 0; r < q.n_tiles; ++r)
+            pl->upd_tiles[c][dk].push_back({q.node_item, r * 64, q.inst, qn.msg0, qn.deg, qn.n, qn.fixed, 0});
+          continue;
+        }
         const bool split = dk < kSepGroup && split_class[c] && qn.deg >= pl->split_deg;
         pl->node_tiles[c][dk].push_back({(int)pl->tiles[c][dk].size(), q.n_tiles * (split ? qn.deg : 1)});
         if (split) {
@@ -676,8 +733,8 @@ static int build_plan(gmot_ctx* ctx, const std::vector<gmot_problem*>& probs, No
   pl->stats.max_splits = shape.W;
   for (int c = 0; c < 2; ++c) {
     pl->stats.blocks[c] = 0;
-    for (int dk = 0; dk < 5; ++dk) pl->stats.blocks[c] += (int)pl->tiles[c][dk].size();
-    for (int dk = 0; dk < 4; ++dk) pl->stats.blocks[c] += (int)pl->upd_tiles[c][dk].size();
+    for (int dk = 0; dk < kGroups; ++dk) pl->stats.blocks[c] += (int)pl->tiles[c][dk].size();
+    for (int dk = 0; dk < kGroups; ++dk) pl->stats.blocks[c] += (int)pl->upd_tiles[c][dk].size();
   }
 
   // one device allocation for every table
@@ -698,12 +755,12 @@ static int build_plan(gmot_ctx* ctx, const std::vector<gmot_problem*>& probs, No
   const size_t o_ndone = take(sizeof(int) * 4);
   const size_t o_part = take(sizeof(double2) * std::max<int64_t>(1, partial_total));
   const size_t o_wmax = take(sizeof(double) * std::max<int64_t>(1, wmax_total));
-  size_t o_tiles[2][5];
+  size_t o_tiles[2][kGroups];
   for (int c = 0; c < 2; ++c)
-    for (int dk = 0; dk < 5; ++dk) o_tiles[c][dk] = take(sizeof(TileItem) * pl->tiles[c][dk].size());
-  size_t o_upd[2][4];
+    for (int dk = 0; dk < kGroups; ++dk) o_tiles[c][dk] = take(sizeof(TileItem) * pl->tiles[c][dk].size());
+  size_t o_upd[2][kGroups];
   for (int c = 0; c < 2; ++c)
-    for (int dk = 0; dk < 4; ++dk) o_upd[c][dk] = take(sizeof(TileItem) * pl->upd_tiles[c][dk].size());
+    for (int dk = 0; dk < kGroups; ++dk) o_upd[c][dk] = take(sizeof(TileItem) * pl->upd_tiles[c][dk].size());
   const size_t o_tpart = take(sizeof(double) * std::max<int64_t>(1, tpart_total));
   size_t o_sep[2], o_sep2[2];
   for (int c = 0; c < 2; ++c) o_sep[c] = take(sizeof(SepItem) * pl->sep_items[c].size());
@@ -723,9 +780,9 @@ static int build_plan(gmot_ctx* ctx, const std::vector<gmot_problem*>& probs, No
   pl->d_partial = (double2*)(base + o_part);
   pl->d_wmax = (double*)(base + o_wmax);
   for (int c = 0; c < 2; ++c)
-    for (int dk = 0; dk < 5; ++dk) pl->d_tiles[c][dk] = (TileItem*)(base + o_tiles[c][dk]);
+    for (int dk = 0; dk < kGroups; ++dk) pl->d_tiles[c][dk] = (TileItem*)(base + o_tiles[c][dk]);
   for (int c = 0; c < 2; ++c)
-    for (int dk = 0; dk < 4; ++dk) pl->d_upd_tiles[c][dk] = (TileItem*)(base + o_upd[c][dk]);
+    for (int dk = 0; dk < kGroups; ++dk) pl->d_upd_tiles[c][dk] = (TileItem*)(base + o_upd[c][dk]);
   pl->d_tpart = (double*)(base + o_tpart);
   for (int c = 0; c < 2; ++c) pl->d_sep_items[c] = (SepItem*)(base + o_sep[c]);
   for (int c = 0; c < 2; ++c) pl->d_sep_items2[c] = (SepItem*)(base + o_sep2[c]);
@@ -756,11 +813,11 @@ static int build_plan(gmot_ctx* ctx, const std::vector<gmot_problem*>& probs, No
     if (!pl->nodes[c].empty())
       HIPCHK(hipMemcpyAsync(pl->d_nodes[c], pl->nodes[c].data(), sizeof(NodeItem) * pl->nodes[c].size(),
                             hipMemcpyHostToDevice, s));
-    for (int dk = 0; dk < 5; ++dk)
+    for (int dk = 0; dk < kGroups; ++dk)
       if (!pl->tiles[c][dk].empty())
         HIPCHK(hipMemcpyAsync(pl->d_tiles[c][dk], pl->tiles[c][dk].data(),
                               sizeof(TileItem) * pl->tiles[c][dk].size(), hipMemcpyHostToDevice, s));
-    for (int dk = 0; dk < 4; ++dk)
+    for (int dk = 0; dk < kGroups; ++dk)
       if (!pl->upd_tiles[c][dk].empty())
         HIPCHK(hipMemcpyAsync(pl->d_upd_tiles[c][dk], pl->upd_tiles[c][dk].data(),
                               sizeof(TileItem) * pl->upd_tiles[c][dk].size(), hipMemcpyHostToDevice, s));
@@ -929,14 +986,14 @@ static int compact_lists(Plan* pl, const std::vector<char>& running, int* count)
     off = o + std::max<size_t>(bytes, 1);
     return o;
   };
-  size_t o_t[2][5], o_u[2][4], o_s[2], o_s2[2];
+  size_t o_t[2][kGroups], o_u[2][kGroups], o_s[2], o_s2[2];
   for (int c = 0; c < 2; ++c) {
-    for (int g = 0; g < 5; ++g) {
+    for (int g = 0; g < kGroups; ++g) {
       for (const TileItem& t : pl->tiles[c][g])
         if (keep(t.inst)) L.tiles[c][g].push_back(t);
       o_t[c][g] = take(sizeof(TileItem) * L.tiles[c][g].size());
     }
-    for (int g = 0; g < 4; ++g) {
+    for (int g = 0; g < kGroups; ++g) {
       for (const TileItem& t : pl->upd_tiles[c][g])
         if (keep(t.inst)) L.upd[c][g].push_back(t);
       o_u[c][g] = take(sizeof(TileItem) * L.upd[c][g].size());
@@ -952,13 +1009,13 @@ static int compact_lists(Plan* pl, const std::vector<char>& running, int* count)
   char* b = (char*)L.buf;
   hipStream_t s = pl->ctx->stream;
   for (int c = 0; c < 2; ++c) {
-    for (int g = 0; g < 5; ++g) {
+    for (int g = 0; g < kGroups; ++g) {
       L.d_tiles[c][g] = (TileItem*)(b + o_t[c][g]);
       if (!L.tiles[c][g].empty())
         HIPCHK(hipMemcpyAsync(L.d_tiles[c][g], L.tiles[c][g].data(), sizeof(TileItem) * L.tiles[c][g].size(),
                               hipMemcpyHostToDevice, s));
     }
-    for (int g = 0; g < 4; ++g) {
+    for (int g = 0; g < kGroups; ++g) {
       L.d_upd[c][g] = (TileItem*)(b + o_u[c][g]);
       if (!L.upd[c][g].empty())
         HIPCHK(hipMemcpyAsync(L.d_upd[c][g], L.upd[c][g].data(), sizeof(TileItem) * L.upd[c][g].size(),
@@ -1457,6 +1514,40 @@ static int upload(const gmot_tree_desc* d, gmot_problem* p) {
       p->grid_cols[j] = B;
     }
     p->sep = all;
+  }
+  // Messages from uniform one-dimensional grids (k_msg_grid): every support
+  // X[i] = X[0] + i h with h = (X[n-1] - X[0]) / (n - 1), to within 8 ulps of
+  // its largest magnitude, and for every message (source k, destination j)
+  // 2 log2e / eps * (half the span of any 64 rows of j) * |h_k| * max(n_k - 1, 64)
+  // <= kGridRange: the kernel forms the powers rho^0 .. rho^64 of a row's
+  // ratio, and its sums take rho^j for j < n_k.
+  p->grid = false;
+  if (p->dim == 1 && d->cost_kind == GMOT_COST_SQEUCLID && p->E > 0 && !std::getenv("GMOT_NO_GRID")) {
+    bool all = true;
+    std::vector<double> hs(p->N, 0.0), half(p->N, 0.0);
+    for (int j = 0; j < p->N && all; ++j) {
+      const double* X = sup.data() + p->node_off[j];
+      const int n = p->sizes[j];
+      const double h = n > 1 ? (X[n - 1] - X[0]) / (double)(n - 1) : 0.0;
+      const double tolx = 8.0 * DBL_EPSILON * std::max(std::fabs(X[0]), std::fabs(X[n - 1]));
+      for (int i = 0; i < n && all; ++i) all = std::isfinite(X[i]) && std::fabs(X[i] - (X[0] + i * h)) <= tolx;
+      hs[j] = h;
+      for (int r0 = 0; r0 < n; r0 += 64) {
+        double lo = X[r0], hi = X[r0];
+        for (int i = r0; i < std::min(n, r0 + 64); ++i) {
+          lo = std::min(lo, X[i]);
+          hi = std::max(hi, X[i]);
+        }
+        half[j] = std::max(half[j], 0.5 * (hi - lo));
+      }
+    }
+    const double two_kap = 2.0 * kLog2e / p->eps;
+    for (int e = 0; e < p->E && all; ++e) {
+      const int a = p->edges[2 * e], b = p->edges[2 * e + 1];
+      all = two_kap * half[b] * std::fabs(hs[a]) * std::max(p->sizes[a] - 1, 64) <= kGridRange &&
+            two_kap * half[a] * std::fabs(hs[b]) * std::max(p->sizes[b] - 1, 64) <= kGridRange;
+    }
+    p->grid = all;
   }
   HIPCHK(hipMemcpy(p->d_support, sup.data(), sizeof(double) * P * p->dim, hipMemcpyHostToDevice));
   HIPCHK(hipMemcpy(p->d_lg, lg.data(), sizeof(double) * P, hipMemcpyHostToDevice));

@@ -1,0 +1,177 @@
+"""Messages from uniform one-dimensional grids (k_msg_grid: the message of
+eq. q as a polynomial in each row's ratio, summed by Horner's rule), through
+the C ABI (needs an MI355X).
+
+Every D = 1 problem whose supports are uniform grids takes this path by
+default; GMOT_NO_GRID=1 (read at problem creation) sends it to the general
+node kernel instead.  The grid path sums in FP64 in both precisions, so after
+the same half-sweeps its potentials match the oracle to 1e-9 of their size,
+couplings to 1e-9 and the dual to 1e-9 of the objective scale, FP32-core mode
+included; converged solves are re-measured by the oracle.  Problems outside
+the path (non-uniform supports, or powers of a row's ratio beyond the admitted
+range) take the general kernel and still match the oracle.
+"""
+import copy
+
+import numpy as np
+import pytest
+
+from oracle import TreeOracle
+from workloads import make_chain, make_star, make_tree, make_batched_stars
+
+pytestmark = pytest.mark.gpu
+
+GRID_GROUP = 5  # kernel group of the grid path in the timing stats
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    from paper_2406_10849_amd import Context
+    return Context(0)
+
+
+def gpu_problem(ctx, p):
+    from paper_2406_10849_amd import Problem
+    return Problem(ctx, p)
+
+
+def grid_pairs(ctx, p):
+    """Terms the grid group evaluated in one timed half-sweep pair."""
+    g = gpu_problem(ctx, p)
+    g.solve(tol=0.0, max_steps=2, timing=True)
+    return g.stats()["group_pairs"][GRID_GROUP]
+
+
+def _reversed(p):
+    """The same problem with every support listed in descending order (h < 0)."""
+    q = copy.deepcopy(p)
+    off = q.offsets()
+    moff = q.marginal_offsets()
+    for j in range(q.n_nodes):
+        q.support[off[j]:off[j + 1]] = q.support[off[j]:off[j + 1]][::-1].copy()
+        if moff[j] >= 0:
+            n = int(q.sizes[j])
+            q.marginal[moff[j]:moff[j] + n] = q.marginal[moff[j]:moff[j] + n][::-1].copy()
+    return q
+
+
+def _cases():
+    # ragged sizes (not multiples of 64), a constrained interior node, a star
+    # centre of degree 12 over supports of different sizes, single-point and
+    # two-point nodes (h = 0 and one interval), a large node (32 column tiles)
+    chain = make_chain(n_nodes=12, n=200, eps=1e-3)
+    star = make_tree([(0, k) for k in range(1, 13)], [150] + [37 + 53 * k for k in range(12)], [0] + [1] * 12,
+                     dim=1, eps=0.05, instance=120, support="grid", marginals="gm")
+    tiny = make_tree([(0, 1), (1, 2), (1, 3), (3, 4)], [1, 70, 2, 129, 65], [1, 0, 1, 0, 1], dim=1, eps=0.5,
+                     instance=121, support="grid", marginals="gm")
+    big = make_star(n=2048, leaves=3, eps=0.01, instance=122)
+    return {"chain": chain, "star12": star, "tiny": tiny, "big": big, "reversed": _reversed(chain)}
+
+
+@pytest.mark.parametrize("name", ["chain", "star12", "tiny", "big", "reversed"])
+def test_grid_iterates_match_oracle_and_general_kernel(ctx, name, monkeypatch):
+    p = _cases()[name]
+    assert grid_pairs(ctx, p) > 0
+    steps = 12
+    o = TreeOracle(p)
+    o.run_fixed(steps)
+    eo = o.evaluate()
+    lo = o.potentials()
+    scale = max(1.0, float(np.max(np.abs(lo))))
+    for precision in ("fp64", "fp32core"):
+        g = gpu_problem(ctx, p)
+        r = g.solve(tol=0.0, max_steps=steps, precision=precision)
+        assert r["steps"] == steps
+        assert np.max(np.abs(g.potentials() - lo)) <= 1e-9 * scale, precision
+        assert abs(g.evaluate()["dual"] - eo["dual"]) <= 1e-9 * eo["scale"], precision
+        for e in range(p.n_edges):
+            assert np.max(np.abs(g.coupling(e) - o.coupling(e))) <= 1e-9, (precision, e)
+    # the general node kernel (FP64) on the same problem
+    monkeypatch.setenv("GMOT_NO_GRID", "1")
+    assert grid_pairs(ctx, p) == 0
+    h = gpu_problem(ctx, p)
+    assert h.solve(tol=0.0, max_steps=steps, precision="fp64")["steps"] == steps
+    assert np.max(np.abs(h.potentials() - g.potentials())) <= 1e-9 * scale
+
+
+def test_grid_per_node_schedule_gives_identical_iterates(ctx):
+    """Per-node launches of the same items give bit-identical iterates."""
+    p = _cases()["star12"]
+    a, b = gpu_problem(ctx, p), gpu_problem(ctx, p)
+    assert a.solve(tol=0.0, max_steps=15)["steps"] == 15
+    assert b.solve(tol=0.0, max_steps=15, schedule="per_node")["steps"] == 15
+    assert np.array_equal(a.potentials(), b.potentials())
+
+
+def test_grid_converged_solves(ctx):
+    """Converged solves (chain at eps = 1e-3, a batch of one-dimensional stars):
+    the oracle re-measures the stopping sum of the returned potentials, and the
+    dual matches the oracle's converged dual."""
+    from paper_2406_10849_amd import Batch
+    p = make_chain(n_nodes=12, n=200, eps=1e-3)
+    ref = TreeOracle(p)
+    ref.solve(tol=1e-11, max_steps=20000)
+    er = ref.evaluate()
+    g = gpu_problem(ctx, p)
+    assert g.solve(tol=1e-6, max_steps=20000)["status"] == "converged"
+    o = TreeOracle(p)
+    lam = o.set_potentials(g.potentials())
+    assert o.full_error(lam)[0] <= 1e-6 + 1e-10
+    assert abs(o.evaluate(lam)["dual"] - er["dual"]) <= 1e-6 * er["scale"]
+    probs = [q for q in make_batched_stars(count=40, l_lo=3, l_hi=8, n_lo=64, n_hi=700, first_instance=500)
+             if q.dim == 1][:12]
+    gps = [gpu_problem(ctx, q) for q in probs]
+    rs = Batch(ctx, gps).solve(tol=1e-6, max_steps=20000)
+    assert all(r["status"] == "converged" for r in rs)
+    for q, gq in zip(probs, gps):
+        oq = TreeOracle(q)
+        assert oq.full_error(oq.set_potentials(gq.potentials()))[0] <= 1e-6 + 1e-10
+
+
+def test_grid_eligibility(ctx):
+    """A support moved off its grid, or powers of a row's ratio beyond the
+    admitted range (a small eps on a coarse grid), take the general kernel;
+    the iterates still match the oracle."""
+    base = make_chain(n_nodes=6, n=150, eps=1e-2)
+    off = copy.deepcopy(base)
+    off.support = off.support.copy()
+    off.support[3] += 1e-9
+    coarse = make_chain(n_nodes=6, n=64, eps=1e-5)
+    assert grid_pairs(ctx, base) > 0
+    for p in (off, coarse):
+        assert grid_pairs(ctx, p) == 0
+        o = TreeOracle(p)
+        o.run_fixed(8)
+        g = gpu_problem(ctx, p)
+        assert g.solve(tol=0.0, max_steps=8, precision="fp64")["steps"] == 8
+        lo = o.potentials()
+        assert np.max(np.abs(g.potentials() - lo)) <= 1e-9 * max(1.0, float(np.max(np.abs(lo))))
+
+
+def test_grid_zero_mass_and_far_potentials(ctx):
+    """Zero entries in a given marginal (log 0 = -inf columns) and potentials
+    moved 300 nats away: the running maximum moves, and the partial sums are
+    rescaled, within one call."""
+    p = make_chain(n_nodes=8, n=200, eps=1e-2)
+    q = copy.deepcopy(p)
+    off, n = int(q.marginal_offsets()[0]), int(q.sizes[0])
+    mu = q.marginal[off:off + n].copy()
+    mu[:80] = 0.0
+    q.marginal = q.marginal.copy()
+    q.marginal[off:off + n] = mu / mu.sum()
+    for prob, shift in ((q, 0.0), (p, 300.0), (p, -300.0)):
+        o = TreeOracle(prob)
+        o.run_fixed(6)
+        lam = o.potentials() + shift
+        g = gpu_problem(ctx, prob)
+        g.solve(tol=0.0, max_steps=2)
+        g.set_potentials(lam)
+        o2 = TreeOracle(prob)
+        o2.Lam = o2.set_potentials(lam)
+        r = g.solve(tol=0.0, max_steps=4, restart=False, verify=False, precision="fp64")
+        assert r["steps"] == 4
+        o2.run_fixed(4)
+        lo = o2.potentials()
+        fin = np.isfinite(lo)
+        assert np.array_equal(fin, np.isfinite(g.potentials()))
+        assert np.max(np.abs(g.potentials()[fin] - lo[fin])) <= 1e-9 * max(1.0, float(np.max(np.abs(lo[fin]))))

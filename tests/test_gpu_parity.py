@@ -56,8 +56,13 @@ def test_config1_star_fp64_1000_half_sweeps(ctx):
     assert abs(eg["err_sum"] - eo["err_sum"]) <= 1e-12 + 1e-6 * eo["err_sum"]
 
 
+@pytest.mark.parametrize("path", ["grid", "general"])
 @pytest.mark.parametrize("precision", ["fp64", "fp32core"])
-def test_small_chain_fixed_steps(ctx, precision):
+def test_small_chain_fixed_steps(ctx, precision, path, monkeypatch):
+    """Both message paths of uniform one-dimensional grids: the grid kernel
+    (default) and the general node kernel (GMOT_NO_GRID=1)."""
+    if path == "general":
+        monkeypatch.setenv("GMOT_NO_GRID", "1")
     p = make_chain(n_nodes=12, n=200, eps=1e-3)
     g = gpu_problem(ctx, p)
     steps = 40
@@ -155,7 +160,10 @@ def test_batch_with_mixed_parities(ctx):
         assert np.max(np.abs(g.potentials() - o.potentials())) <= 1e-9 * max(1.0, np.max(np.abs(o.potentials())))
 
 
-def test_timing_stats_count_working_half_sweeps(ctx):
+@pytest.mark.parametrize("path", ["grid", "general"])
+def test_timing_stats_count_working_half_sweeps(ctx, path, monkeypatch):
+    if path == "general":
+        monkeypatch.setenv("GMOT_NO_GRID", "1")
     p = make_chain(n_nodes=10, n=150, eps=1e-2)
     g = gpu_problem(ctx, p)
     g.stats(reset=True)
@@ -165,9 +173,12 @@ def test_timing_stats_count_working_half_sweeps(ctx):
     assert st["msg_launches"] == r["t"]          # half-sweeps 1..t computed messages
     assert abs(st["msg_pairs"] - r["t"] * p.pairs_per_tstep()) < 0.5
     assert st["msg_ms"] > 0
-    # one support dimension: all of the stage is the D = 1 group
-    assert st["group_pairs"][1] == st["msg_pairs"] and sum(st["group_pairs"]) == st["msg_pairs"]
-    assert st["group_ms"][1] > 0 and st["group_ms"][0] == st["group_ms"][2] == st["group_ms"][4] == 0.0
+    # one kernel group does all of the stage: the uniform-grid group (5) by
+    # default, the D = 1 node-kernel group (1) with GMOT_NO_GRID
+    grp = 5 if path == "grid" else 1
+    assert st["group_pairs"][grp] == st["msg_pairs"] and sum(st["group_pairs"]) == st["msg_pairs"]
+    assert st["group_ms"][grp] > 0
+    assert all(st["group_ms"][k] == 0.0 for k in range(6) if k != grp)
 
 
 def test_evaluate_matches_oracle_on_given_potentials(ctx):
@@ -299,11 +310,13 @@ def test_per_node_schedule_gives_identical_iterates(ctx):
     assert np.array_equal(a.potentials(), b.potentials())
 
 
-def test_one_pass_matches_two_pass(ctx):
+def test_one_pass_matches_two_pass(ctx, monkeypatch):
     """The one-pass message sums (shifted by the previous max of each row and
     column range) and the
     two-pass sums give the same FP32-core iterates within the FP32-core
-    tolerance, and both match the oracle after the same half-sweeps."""
+    tolerance, and both match the oracle after the same half-sweeps (general
+    node kernel: GMOT_NO_GRID=1 keeps the chain off the grid kernel)."""
+    monkeypatch.setenv("GMOT_NO_GRID", "1")
     cases = [make_chain(n_nodes=12, n=200, eps=1e-3),
              make_random_tree(n_nodes=20, n_lo=100, n_hi=600, instance=5)]
     for p in cases:
@@ -418,12 +431,14 @@ def test_scattered_one_dimensional_rows(ctx):
 
 
 @pytest.mark.parametrize("offset", [300.0, -300.0])
-def test_one_pass_far_from_stored_shifts(ctx, offset):
+def test_one_pass_far_from_stored_shifts(ctx, offset, monkeypatch):
     """One-pass sums from the first half-sweep (passes="one") on potentials
     moved 300 nats away from those the stored shifts were computed for: every
     row's max lies far above its shift (moved inside the kernel) or far below
     it (the wave falls back to two passes).  Iterates against the oracle run
-    from the same potentials, sorted and shuffled 1D supports."""
+    from the same potentials, sorted and shuffled 1D supports (general node
+    kernel: GMOT_NO_GRID=1)."""
+    monkeypatch.setenv("GMOT_NO_GRID", "1")
     for p in (make_chain(n_nodes=8, n=200, eps=1e-2), _shuffled(make_chain(n_nodes=8, n=200, eps=1e-2), 6)):
         g = gpu_problem(ctx, p)
         g.solve(tol=0.0, max_steps=6)

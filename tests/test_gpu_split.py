@@ -40,6 +40,7 @@ def _cases():
 def test_split_nodes_match_oracle(ctx, shape, split, monkeypatch):
     from paper_2406_10849_amd import Problem
     monkeypatch.setenv("GMOT_NODE_SHAPE", shape)
+    monkeypatch.setenv("GMOT_NO_GRID", "1")  # the star's uniform grids stay on the node kernel
     if split != "default":
         monkeypatch.setenv("GMOT_SPLIT_DEG", split)
     for name, p in _cases().items():
@@ -62,6 +63,7 @@ def test_split_nodes_converge_like_the_oracle(ctx, monkeypatch):
     half-sweep (within two) in FP64."""
     from paper_2406_10849_amd import Problem
     monkeypatch.setenv("GMOT_SPLIT_DEG", "1")
+    monkeypatch.setenv("GMOT_NO_GRID", "1")
     p = _cases()["star10"]
     g = Problem(ctx, p)
     r = g.solve(tol=1e-7, max_steps=100000)
