@@ -69,10 +69,11 @@ def group_rooflines(st: dict) -> dict:
     alone): k_node for D = 1, 2, 3 against the pair peak of its dimension, the
     separable grid kernels (k_sep_pass + k_node_sep) against the one-dimensional
     pair peak (each of their terms is a one-dimensional term), the uniform-grid
-    kernels (k_msg_grid + k_node_sep) against one FP64 FMA per pair, k_node with
-    explicit costs against HBM bandwidth at 4 bytes per pair."""
+    kernels (k_msg_grid + k_node_sep, k_sep_horner + k_node_sep) against one
+    FP64 FMA per pair or term, k_node with explicit costs against HBM bandwidth
+    at 4 bytes per pair."""
     names = {0: "k_node<explicit>", 1: "k_node<D=1>", 2: "k_node<D=2>", 3: "k_node<D=3>",
-             4: "k_sep_pass+k_node_sep", 5: GRID_GROUP_NAME}
+             4: "k_sep_pass+k_node_sep", 5: GRID_GROUP_NAME, 6: "k_sep_horner+k_node_sep"}
     n = max(st["msg_launches"], 1)
     out = {}
     for g in range(len(st["group_ms"])):
@@ -82,7 +83,7 @@ def group_rooflines(st: dict) -> dict:
         gps = pairs / (ms / 1e3) / 1e9
         if g == 0:
             ach, peak, unit, bound = 4.0 * gps, HBM_PEAK_GBS, "GB/s", "hbm"
-        elif g == 5:
+        elif g in (5, 6):
             ach, peak, unit, bound = gps, fma_peak_gpairs(), "Gpair/s", "alu"
         else:
             ach, peak, unit, bound = gps, pair_peak_gpairs(g if g < 4 else 1), "Gpair/s", "alu"

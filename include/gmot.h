@@ -158,11 +158,11 @@ typedef struct {
                               message, A_k B_j B_k + n_j A_k per separable one (grid
                               supports of A rows and B columns)                         */
   int64_t graph_launches;  /* graph replays issued (timed or not)                        */
-  double  group_ms[6];     /* the node stage split by kernel group (explicit cost;
-                              D = 1, 2, 3; separable grids; uniform 1D grids), each the
-                              mean of 4 back-to-back repeats of the group alone,
-                              summed (ms)                                               */
-  double  group_pairs[6];  /* the terms each group evaluated in those half-sweeps        */
+  double  group_ms[7];     /* the node stage split by kernel group (explicit cost;
+                              D = 1, 2, 3; separable grids; uniform 1D grids; separable
+                              uniform grids), each the mean of 4 back-to-back repeats
+                              of the group alone, summed (ms)                           */
+  double  group_pairs[7];  /* the terms each group evaluated in those half-sweeps        */
 } gmot_stats;
 
 typedef struct {

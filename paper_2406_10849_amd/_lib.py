@@ -79,8 +79,8 @@ class Stats(C.Structure):
         ("msg_launches", C.c_int64),
         ("msg_pairs", C.c_double),
         ("graph_launches", C.c_int64),
-        ("group_ms", C.c_double * 6),
-        ("group_pairs", C.c_double * 6),
+        ("group_ms", C.c_double * 7),
+        ("group_pairs", C.c_double * 7),
     ]
 
 

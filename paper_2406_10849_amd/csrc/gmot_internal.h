@@ -83,6 +83,12 @@ struct MsgDesc {
 struct SepItem {
   int32_t msg, line0, inst, nlines;
 };
+// One 16-lane row of a separable pass on uniform grids (k_sep_horner):
+// outputs [o0, o0 + 16) of line `line` of message msg; a wave takes four
+// consecutive tasks of one message (padding tasks have o0 = outputs per line).
+struct SepTask {
+  int32_t msg, line, o0, inst;
+};
 constexpr int kSepWaves = 4;        // waves per block of a separable pass
 constexpr int kSepMaxSide = 2048;   // grid rows and columns of a separable support at most
 constexpr int kSepMaxOut = 2048;    // outputs per separable-pass block (8 per thread)
@@ -175,6 +181,8 @@ struct Tables {
   const NodeItem* fin_nodes;
   const SepItem* sep_items;  // separable first pass of one class
   const SepItem* sep_items2; // separable second pass of one class
+  const SepTask* sep_tasks;  // separable first pass on uniform grids (k_sep_horner)
+  const SepTask* sep_tasks2; // separable second pass on uniform grids
   int rec_rows;              // rows per tile record (32 or 64)
   // evaluation pass: per instance the slot holding each class's committed
   // potentials, [2 * inst + class] (read when a kernel is given slot -1)
@@ -233,10 +241,15 @@ hipError_t launch_finalize(const Tables& tb, int n_inst, hipStream_t s);
 // 64-row tiles
 hipError_t launch_sep_pass(const Tables& tb, int pass, int n_items, size_t lds_bytes, bool fp64, hipStream_t s);
 hipError_t launch_node_sep(const Tables& tb, int n_tiles, hipStream_t s);
+// separable pass `pass` on uniform grids over the n_tasks tasks of
+// tb.sep_tasks (pass 0, carrying tb.n_fin finalise blocks) or tb.sep_tasks2
+// (pass 1); n_tasks a multiple of four
+hipError_t launch_sep_horner(const Tables& tb, int pass, int n_tasks, hipStream_t s);
 // messages on uniform one-dimensional source grids: one wave per tile item of
-// tb.tiles (a message, msg0, for 64 destination rows from row0), writing mfull;
-// the first tb.n_fin blocks carry the finalise step
-hipError_t launch_msg_grid(const Tables& tb, int n_items, hipStream_t s);
+// tb.tiles (a message, msg0, for 64 * rows_per_lane destination rows from
+// row0; rows_per_lane 1 or 2), writing mfull; the first tb.n_fin blocks carry
+// the finalise step
+hipError_t launch_msg_grid(const Tables& tb, int n_items, int rows_per_lane, hipStream_t s);
 hipError_t launch_node_eval(const Tables& tb, int n_nodes, int slot, hipStream_t s);
 // node-sequential update of node item `node_item` of tb's class from the
 // message partials k_msg wrote, into potential slot `slot` (one block)

@@ -1428,8 +1428,9 @@ __global__ __launch_bounds__(64 * kSepWaves) void k_node_sep(Tables tb, int n_ti
 // ---------------------------------------------------------------------------
 // Messages whose source support is a uniform one-dimensional grid,
 // y_j = y_0 + j h (j < n_src), for the squared-Euclidean cost.  One wave takes
-// one message for 64 destination rows x (any support).  With x_c the midpoint
-// of the wave's smallest and largest row and kap = log2e / eps,
+// one message for 64 R destination rows x (any support; R rows per lane).
+// With x_c the midpoint of the wave's smallest and largest row and
+// kap = log2e / eps,
 //   w(x, y_j) = C(j) + g(x) j + 2 kap (x - x_c) y_0 - kap x^2,
 //   C(j) = log2e (L_(k,j) + log gamma_k)(y_j) - kap y_j^2 + 2 kap x_c y_j,
 //   g(x) = 2 kap (x - x_c) h,
@@ -1443,7 +1444,7 @@ __global__ __launch_bounds__(64 * kSepWaves) void k_node_sep(Tables tb, int n_ti
 // column q of a 16-column group; the four groups combine in rho^16.
 // theta is the largest C met so far, moved (and the partial sum rescaled) only
 // when a column exceeds it by more than kGridSlack binades, so v <= 2^kGridSlack.
-// The host takes this path only when 2 kap * (half the span of any 64 rows)
+// The host takes this path only when 2 kap * (half the span of any 64 R rows)
 // * |h| * max(n_src - 1, 64) <= kGridRange binades, so every power of rho
 // formed here (up to rho^64) or summed (rho^j, j < n_src) stays within
 // 2^(+-kGridRange): with FP64 no term that matters underflows and no sum
@@ -1458,7 +1459,9 @@ constexpr double kGridSlack = 512.0;   // v_j <= 2^kGridSlack
 #define GMOT_FMAC_ROWBCAST(acc, a, b, Q) \
   asm("v_fmac_f64_dpp %0, %1, %2 row_newbcast:" #Q " row_mask:0xf bank_mask:0xf" : "+v"(acc) : "v"(a), "v"(b))
 
-__global__ __launch_bounds__(64 * kGridWaves) void k_msg_grid(Tables tb, int n_items) {
+// two rows per lane asks for four waves per SIMD (at most 128 VGPRs)
+template <int R>
+__global__ __launch_bounds__(64 * kGridWaves, R == 2 ? 4 : 1) void k_msg_grid(Tables tb, int n_items) {
   __shared__ double s_v[kGridWaves][64];
   if ((int)blockIdx.x < tb.n_fin) {
     // the finalise step of the previous launch's half-sweep, one block per instance
@@ -1481,20 +1484,33 @@ __global__ __launch_bounds__(64 * kGridWaves) void k_msg_grid(Tables tb, int n_i
   const GDbl* __restrict__ ys = (const GDbl*)md.supp_src;
   const GDbl* __restrict__ xs = (const GDbl*)md.supp_dst;
   const double kap = kLog2e / md.eps;
-  // this lane's row (clamped: rows past n compute a value that is not stored)
-  const int x = ti.row0 + lane;
-  const double xv = xs[min(x, n - 1)];
-  const double xc = 0.5 * (wave_max(x < n ? xv : -INFINITY) - wave_max(x < n ? -xv : -INFINITY));
+  // this lane's rows row0 + 64 r + lane (clamped: rows past n compute a value
+  // that is not stored); x_c the midpoint of the wave's rows
+  int x[R];
+  double xv[R], hi = -INFINITY, lo = -INFINITY;
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    x[r] = ti.row0 + 64 * r + lane;
+    xv[r] = xs[min(x[r], n - 1)];
+    if (x[r] < n) {
+      hi = fmax(hi, xv[r]);
+      lo = fmax(lo, -xv[r]);
+    }
+  }
+  const double xc = 0.5 * (wave_max(hi) - wave_max(lo));
   const double y0 = ys[0];
   const double h = ns > 1 ? (ys[ns - 1] - y0) / (double)(ns - 1) : 0.0;
-  const double dx = xv - xc;
-  const double rho = exp2(2.0 * kap * dx * h);
-  double pw[16];
-  pw[0] = 1.0;
+  double dx[R], pw[R][16], r16[R], r64[R];
 #pragma unroll
-  for (int q = 1; q < 16; ++q) pw[q] = pw[q - 1] * rho;
-  const double r16 = pw[15] * rho;
-  const double r64 = (r16 * r16) * (r16 * r16);
+  for (int r = 0; r < R; ++r) {
+    dx[r] = xv[r] - xc;
+    const double rho = exp2(2.0 * kap * dx[r] * h);
+    pw[r][0] = 1.0;
+#pragma unroll
+    for (int q = 1; q < 16; ++q) pw[r][q] = pw[r][q - 1] * rho;
+    r16[r] = pw[r][15] * rho;
+    r64[r] = (r16[r] * r16[r]) * (r16[r] * r16[r]);
+  }
   const double cxc = 2.0 * kap * xc;
   // column data of tile J (lane = column 64 J + lane, clamped; past n_src: no term)
   auto c_of = [&](double l, double g, double y, bool ok) -> double {
@@ -1503,7 +1519,9 @@ __global__ __launch_bounds__(64 * kGridWaves) void k_msg_grid(Tables tb, int n_i
   const int nt = (ns + 63) / 64;
   int jn = min((nt - 1) * 64 + lane, ns - 1);
   double l_n = lam[jn], g_n = lg[jn], y_n = ys[jn];
-  double theta = -INFINITY, P = 0.0;
+  double theta = -INFINITY, P[R];
+#pragma unroll
+  for (int r = 0; r < R; ++r) P[r] = 0.0;
   double* __restrict__ sv = s_v[wv];
   for (int J = nt - 1; J >= 0; --J) {
     const double C = c_of(l_n, g_n, y_n, J * 64 + lane < ns);
@@ -1516,7 +1534,11 @@ __global__ __launch_bounds__(64 * kGridWaves) void k_msg_grid(Tables tb, int n_i
     }
     if (__any(C > theta + kGridSlack)) {
       const double m = wave_max(C);
-      if (theta > -INFINITY) P *= exp2(theta - m);
+      if (theta > -INFINITY) {
+        const double f = exp2(theta - m);
+#pragma unroll
+        for (int r = 0; r < R; ++r) P[r] *= f;
+      }
       theta = m;
     }
     sv[lane] = C > -INFINITY ? exp2(C - theta) : 0.0;
@@ -1525,19 +1547,27 @@ __global__ __launch_bounds__(64 * kGridWaves) void k_msg_grid(Tables tb, int n_i
 #pragma unroll
     for (int c = 0; c < 4; ++c) vc[c] = sv[16 * c + (lane & 15)];
     wave_sync();
-    double S[4] = {0.0, 0.0, 0.0, 0.0};
-    // the four groups interleaved: four independent accumulation chains
-#define GMOT_GRID_COL(Q)                                  \
-  GMOT_FMAC_ROWBCAST(S[0], vc[0], pw[Q], Q);              \
-  GMOT_FMAC_ROWBCAST(S[1], vc[1], pw[Q], Q);              \
-  GMOT_FMAC_ROWBCAST(S[2], vc[2], pw[Q], Q);              \
-  GMOT_FMAC_ROWBCAST(S[3], vc[3], pw[Q], Q);
+    double S[R][4];
+#pragma unroll
+    for (int r = 0; r < R; ++r)
+#pragma unroll
+      for (int c = 0; c < 4; ++c) S[r][c] = 0.0;
+    // the four groups (and the rows) interleaved: 4 R independent chains
+#define GMOT_GRID_COL(Q)                                              \
+  _Pragma("unroll") for (int r = 0; r < R; ++r) {                     \
+    GMOT_FMAC_ROWBCAST(S[r][0], vc[0], pw[r][Q], Q);                  \
+    GMOT_FMAC_ROWBCAST(S[r][1], vc[1], pw[r][Q], Q);                  \
+    GMOT_FMAC_ROWBCAST(S[r][2], vc[2], pw[r][Q], Q);                  \
+    GMOT_FMAC_ROWBCAST(S[r][3], vc[3], pw[r][Q], Q);                  \
+  }
     GMOT_GRID_COL(0) GMOT_GRID_COL(1) GMOT_GRID_COL(2) GMOT_GRID_COL(3)
     GMOT_GRID_COL(4) GMOT_GRID_COL(5) GMOT_GRID_COL(6) GMOT_GRID_COL(7)
     GMOT_GRID_COL(8) GMOT_GRID_COL(9) GMOT_GRID_COL(10) GMOT_GRID_COL(11)
     GMOT_GRID_COL(12) GMOT_GRID_COL(13) GMOT_GRID_COL(14) GMOT_GRID_COL(15)
 #undef GMOT_GRID_COL
-    P = fma(P, r64, fma(fma(fma(S[3], r16, S[2]), r16, S[1]), r16, S[0]));
+#pragma unroll
+    for (int r = 0; r < R; ++r)
+      P[r] = fma(P[r], r64[r], fma(fma(fma(S[r][3], r16[r], S[r][2]), r16[r], S[r][1]), r16[r], S[r][0]));
   }
   // the source's normaliser c_k, from its tile records when its last update
   // (half-sweep t - 1) ran in this run, else its stored value
@@ -1553,12 +1583,179 @@ __global__ __launch_bounds__(64 * kGridWaves) void k_msg_grid(Tables tb, int n_i
       ck = *(const GDbl*)(md.c_src + src_slot);
     }
   }
-  if (x < n) {
-    const double e = theta + fma(2.0 * kap * dx, y0, -kap * xv * xv);
-    ((GDblW*)md.mfull)[x] = (theta > -INFINITY && P > 0.0) ? kLn2 * (e + log2(P)) - ck : -INFINITY;
-  }
+#pragma unroll
+  for (int r = 0; r < R; ++r)
+    if (x[r] < n) {
+      const double e = theta + fma(2.0 * kap * dx[r], y0, -kap * xv[r] * xv[r]);
+      ((GDblW*)md.mfull)[x[r]] = (theta > -INFINITY && P[r] > 0.0) ? kLn2 * (e + log2(P[r])) - ck : -INFINITY;
+    }
 }
 #undef GMOT_FMAC_ROWBCAST
+
+// ---------------------------------------------------------------------------
+// Separable passes on uniform grids by Horner's rule (FP64).  Each pass of a
+// separable message (the two one-dimensional LSE convolutions above) is, per
+// line, a one-dimensional message from uniformly spaced inputs y_i = y_0 + i h
+// to the line's outputs z_o:
+//   out(o) = log2 sum_i 2^(s(i) + 2 kap z_o y_i),   s(i) = staged value - kap y_i^2,
+// summed as in k_msg_grid: with z_c the midpoint of a group's outputs,
+//   out(o) = theta + log2 sum_i v_i rho_o^i + 2 kap (z_o - z_c) y_0,
+//   v_i = 2^(C(i) - theta),  C(i) = s(i) + 2 kap z_c y_i,  rho_o = 2^(2 kap (z_o - z_c) h).
+// Each 16-lane row of a wave takes one task: 16 consecutive outputs of one
+// line; its lanes hold the line's values v of four 16-input groups of a
+// 64-input tile (lane q of the row: inputs q, 16 + q, 32 + q, 48 + q), so the
+// row broadcast of v_fmac_f64 hands every output of the row each input of
+// its own line, and theta is a row maximum.  The four tasks of a wave belong
+// to one message (the task list pads each message to whole waves).  The host
+// takes this path only when every grid coordinate list is uniform and, per
+// pass, 2 kap * (half the span of 16 outputs) * |h| * W <= kGridRange, with W
+// the largest power of rho formed: 16 g - 1 for g = ceil(inner / 16) <= 4
+// groups in one tile, max(inner - 1, 64) over several tiles.  Pass 0 stores
+// Tt(q, u) = T(u, q) - kap C_j[q]^2 - kap R_k[u]^2, pass 1 the message in mfull,
+// as k_sep_pass does.
+// ---------------------------------------------------------------------------
+// maximum over the 16 lanes of each row (every lane of the row gets it)
+__device__ inline double row_max(double v) {
+  v = fmax(v, dpp_move<kDppXor1>(v));
+  v = fmax(v, dpp_move<kDppXor2>(v));
+  v = fmax(v, dpp_move<kDppHalfMirror>(v));
+  return fmax(v, dpp_move<kDppMirror>(v));
+}
+
+#define GMOT_FMAC_ROWBCAST_S(acc, a, b, Q) \
+  asm("v_fmac_f64_dpp %0, %1, %2 row_newbcast:" #Q " row_mask:0xf bank_mask:0xf" : "+v"(acc) : "v"(a), "v"(b))
+
+template <int PASS>
+__global__ __launch_bounds__(64 * kSepWaves) void k_sep_horner(Tables tb, int n_tasks) {
+  int bid = (int)blockIdx.x;
+  if (PASS == 0) {
+    if (bid < tb.n_fin) {
+      // the finalise step of the previous launch's half-sweep, one block per instance
+      __shared__ double sh_fin[kFinParts][2];
+      fin_instance<kSepWaves>(tb, tb.fin_nodes, tb.fin_colour, tb.inst + bid, true, sh_fin);
+      return;
+    }
+    bid -= tb.n_fin;
+  }
+  const int lane = threadIdx.x & 63, wv = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
+  const int ql = lane & 15;
+  const int w = bid * kSepWaves + wv;
+  if (w * 4 >= n_tasks) return;
+  const SepTask* __restrict__ tasks = PASS == 0 ? tb.sep_tasks : tb.sep_tasks2;
+  const SepTask tk = tasks[w * 4 + (lane >> 4)];
+  // message and instance: the same for the wave's four tasks
+  const int msg = __builtin_amdgcn_readfirstlane(tk.msg), inst = __builtin_amdgcn_readfirstlane(tk.inst);
+  const InstState* st = tb.inst + inst;
+  const long long t = st->vt[tb.colour];
+  if (st->vdone[tb.colour] != 0 || t < st->t_first || ((t & 1) == 1) != (tb.colour == 0)) return;
+  const CMsg& md = *(const CMsg*)(tb.msgs + msg);
+  const int Ak = md.rows_src, Bk = md.cols_src, Bj = md.cols_dst, Aj = md.rows_dst;
+  const int nk = md.n_src, nj = md.n_dst;
+  const int outs = PASS == 0 ? Bj : Aj;   // outputs per line
+  const int inner = PASS == 0 ? Bk : Ak;  // inputs per output
+  const int src_slot = (int)((t >> 1) % kSlots);
+  const GDbl* __restrict__ lam = (const GDbl*)md.lam_src[src_slot];
+  const GDbl* __restrict__ lg = (const GDbl*)md.lg_src;
+  const GDbl* __restrict__ ys = (const GDbl*)md.supp_src;
+  const GDbl* __restrict__ xs = (const GDbl*)md.supp_dst;
+  const GDbl* __restrict__ Tr = (const GDbl*)md.sepT;
+  const double kap = kLog2e / md.eps;
+  const int line = tk.line, o = tk.o0 + ql;
+  const bool ov = o < outs;
+  const int oc = min(o, outs - 1);
+  // input coordinate i of the pass and the output coordinate of this lane
+  auto yin = [&](int i) -> double { return PASS == 0 ? ys[(size_t)i * 2 + 1] : ys[(size_t)i * Bk * 2]; };
+  const double z = PASS == 0 ? xs[(size_t)oc * 2 + 1] : xs[(size_t)oc * Bj * 2];
+  const double zhi = row_max(ov ? z : -INFINITY), zlo = -row_max(ov ? -z : -INFINITY);
+  const double zc = zhi > -INFINITY ? 0.5 * (zhi + zlo) : 0.0;
+  const double y0 = yin(0);
+  const double h = inner > 1 ? (yin(inner - 1) - y0) / (double)(inner - 1) : 0.0;
+  const double dz = z - zc;
+  const double rho = exp2(2.0 * kap * dz * h);
+  double pw[16];
+  pw[0] = 1.0;
+#pragma unroll
+  for (int q = 1; q < 16; ++q) pw[q] = pw[q - 1] * rho;
+  const double r16 = pw[15] * rho;
+  const double czc = 2.0 * kap * zc;
+  const int nt = (inner + 63) / 64;
+  const int ng = min(4, (inner + 15) / 16);  // 16-input groups per tile
+  // pass 1: the source's normaliser c_k (every lane of the wave, before any divergence)
+  double ck = 0.0;
+  if (PASS == 1 && md.src_free) {
+    if (t - 1 >= st->t_first) {
+      const GDbl* __restrict__ srec = (const GDbl*)md.src_tpart;
+      const int src_deg = md.src_deg, src_tiles = md.src_tiles;
+      const int s_stride = src_deg + kRecExtra, s_tile = min(lane, src_tiles - 1);
+      ck = tile_lse((const double*)srec, src_tiles, s_stride, src_deg, srec[(size_t)s_tile * s_stride + src_deg],
+                    srec[(size_t)s_tile * s_stride + src_deg + 1]);
+    } else {
+      ck = *(const GDbl*)(md.c_src + src_slot);
+    }
+  }
+  double theta = -INFINITY, P = 0.0;
+  for (int J = nt - 1; J >= 0; --J) {
+    double Cv[4];
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+      const int i = J * 64 + 16 * c + ql;
+      const int ic = min(i, inner - 1);
+      double s;
+      if (PASS == 0) {
+        const int idx = min(line * Bk + ic, nk - 1);
+        const double y = yin(ic);
+        s = fma(-kap * y, y, kLog2e * (lam[idx] + lg[idx]));
+        if (!(i < inner && line * Bk + i < nk)) s = -INFINITY;
+        Cv[c] = s > -INFINITY ? fma(czc, y, s) : -INFINITY;
+      } else {
+        s = Tr[(size_t)line * Ak + ic];
+        if (!(i < inner)) s = -INFINITY;
+        Cv[c] = s > -INFINITY ? fma(czc, yin(ic), s) : -INFINITY;
+      }
+    }
+    const double m = row_max(fmax(fmax(Cv[0], Cv[1]), fmax(Cv[2], Cv[3])));
+    if (m > theta + kGridSlack) {
+      if (theta > -INFINITY) P *= exp2(theta - m);
+      theta = m;
+    }
+    double vc[4];
+#pragma unroll
+    for (int c = 0; c < 4; ++c) vc[c] = Cv[c] > -INFINITY ? exp2(Cv[c] - theta) : 0.0;
+    double S[4] = {0.0, 0.0, 0.0, 0.0};
+#define GMOT_SEP_COL(Q)                                   \
+  GMOT_FMAC_ROWBCAST_S(S[0], vc[0], pw[Q], Q);            \
+  GMOT_FMAC_ROWBCAST_S(S[1], vc[1], pw[Q], Q);            \
+  GMOT_FMAC_ROWBCAST_S(S[2], vc[2], pw[Q], Q);            \
+  GMOT_FMAC_ROWBCAST_S(S[3], vc[3], pw[Q], Q);
+    GMOT_SEP_COL(0) GMOT_SEP_COL(1) GMOT_SEP_COL(2) GMOT_SEP_COL(3)
+    GMOT_SEP_COL(4) GMOT_SEP_COL(5) GMOT_SEP_COL(6) GMOT_SEP_COL(7)
+    GMOT_SEP_COL(8) GMOT_SEP_COL(9) GMOT_SEP_COL(10) GMOT_SEP_COL(11)
+    GMOT_SEP_COL(12) GMOT_SEP_COL(13) GMOT_SEP_COL(14) GMOT_SEP_COL(15)
+#undef GMOT_SEP_COL
+    // groups past the inputs hold zeros; only the powers the host bounded are formed
+    double St = S[0];
+    if (ng == 2) St = fma(S[1], r16, S[0]);
+    else if (ng == 3) St = fma(fma(S[2], r16, S[1]), r16, S[0]);
+    else if (ng == 4) St = fma(fma(fma(S[3], r16, S[2]), r16, S[1]), r16, S[0]);
+    if (J == nt - 1) {
+      P = St;
+    } else {
+      const double r64 = (r16 * r16) * (r16 * r16);
+      P = fma(P, r64, St);
+    }
+  }
+  const double T = (theta > -INFINITY && P > 0.0) ? theta + log2(P) + 2.0 * kap * dz * y0 : -INFINITY;
+  if (PASS == 0) {
+    if (ov) {
+      const double Ru = ys[(size_t)line * Bk * 2];
+      ((GDblW*)md.sepT)[(size_t)o * Ak + line] = T - kap * (z * z) - kap * (Ru * Ru);
+    }
+  } else {
+    const int x = o * Bj + line;
+    if (ov && x < nj) ((GDblW*)md.mfull)[x] = T > -INFINITY ? kLn2 * (T - kap * (z * z)) - ck : -INFINITY;
+  }
+}
+#undef GMOT_FMAC_ROWBCAST_S
 
 // ---------------------------------------------------------------------------
 // Finalise kernel: one block of kFinWaves waves per instance, one wave per
@@ -1871,10 +2068,25 @@ hipError_t launch_node_sep(const Tables& tb, int n_tiles, hipStream_t s) {
   return hipGetLastError();
 }
 
-hipError_t launch_msg_grid(const Tables& tb, int n_items, hipStream_t s) {
+hipError_t launch_msg_grid(const Tables& tb, int n_items, int rows_per_lane, hipStream_t s) {
   if (n_items <= 0) return hipSuccess;
-  hipLaunchKernelGGL(k_msg_grid, dim3((n_items + kGridWaves - 1) / kGridWaves + tb.n_fin), dim3(64 * kGridWaves), 0,
-                     s, tb, n_items);
+  const dim3 grid((n_items + kGridWaves - 1) / kGridWaves + tb.n_fin);
+  if (rows_per_lane == 1) hipLaunchKernelGGL(k_msg_grid<1>, grid, dim3(64 * kGridWaves), 0, s, tb, n_items);
+  else if (rows_per_lane == 2) hipLaunchKernelGGL(k_msg_grid<2>, grid, dim3(64 * kGridWaves), 0, s, tb, n_items);
+  else return hipErrorInvalidValue;
+  return hipGetLastError();
+}
+
+hipError_t launch_sep_horner(const Tables& tb, int pass, int n_tasks, hipStream_t s) {
+  if (n_tasks <= 0) return hipSuccess;
+  if (n_tasks % 4 != 0) return hipErrorInvalidValue;  // whole waves of four tasks
+  const int blocks = (n_tasks / 4 + kSepWaves - 1) / kSepWaves;
+  if (pass == 0) {
+    hipLaunchKernelGGL((k_sep_horner<0>), dim3(blocks + tb.n_fin), dim3(64 * kSepWaves), 0, s, tb, n_tasks);
+  } else {
+    if (tb.n_fin != 0) return hipErrorInvalidValue;
+    hipLaunchKernelGGL((k_sep_horner<1>), dim3(blocks), dim3(64 * kSepWaves), 0, s, tb, n_tasks);
+  }
   return hipGetLastError();
 }
 

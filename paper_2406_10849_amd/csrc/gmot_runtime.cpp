@@ -98,6 +98,11 @@ struct gmot_problem {
   // y_j = y_0 + j h to within a few ulps, and every message keeps the powers of
   // its rows' ratios within 2^(+-kGridRange)
   bool grid = false;
+  int grid_rows_lane = 1;  // rows per lane the grid kernel may take (1, or 2 when 128-row spans qualify)
+  // separable messages whose grid coordinate lists are all uniform and whose
+  // passes keep the powers of each output's ratio within 2^(+-kGridRange):
+  // k_sep_horner instead of k_sep_pass
+  bool sep_h = false;
   int grid_rows(int j) const { return (int)((sizes[j] + grid_cols[j] - 1) / grid_cols[j]); }
   int64_t t = 1;
   uint64_t version = 0;   // bumped whenever the held state changes
@@ -119,6 +124,8 @@ struct gmot_problem {
 constexpr int kSepGroup = 4;
 // Tile group of instances on uniform one-dimensional grids (k_msg_grid + k_node_sep).
 constexpr int kGridGroup = 5;
+// Tile group of separable instances on uniform grids (k_sep_horner + k_node_sep).
+constexpr int kSepHGroup = 6;
 // Rows per node-stage tile of separable instances.
 constexpr int kSepTileRows = 64;
 // In a class whose k_node groups have fewer than kSplitBelowTiles tiles, nodes
@@ -135,8 +142,8 @@ constexpr int64_t kSepTargetBlocks = 2048;
 // stage between the first two (so their mean excludes the event overhead).
 // Kernel groups of a node stage: explicit cost, D = 1, 2, 3 (k_node), separable
 // grids (k_sep_pass + k_node_sep), uniform one-dimensional grids (k_msg_grid +
-// k_node_sep).
-constexpr int kGroups = 6;
+// k_node_sep), separable uniform grids (k_sep_horner + k_node_sep).
+constexpr int kGroups = 7;
 constexpr int kStepEvents = 4 + 2 * kGroups;
 constexpr int kMsgBurst = 4;
 
@@ -189,6 +196,7 @@ struct Plan {
   // the other nodes, in node_tiles order).  The grid group's nodes all update
   // here (index kSepGroup is unused).
   int split_deg = 0;
+  int grid_R = 1;  // rows per lane of the grid group's message items (64 grid_R rows each)
   std::vector<TileItem> upd_tiles[2][kGroups];
   std::vector<std::pair<int, int>> node_upd[2][kGroups];
   TileItem* d_upd_tiles[2][kGroups] = {};
@@ -198,6 +206,11 @@ struct Plan {
   std::vector<std::array<int, 4>> node_sep[2];
   SepItem* d_sep_items[2] = {};
   SepItem* d_sep_items2[2] = {};
+  // separable instances on uniform grids: tasks of both passes per class
+  // ([class][pass]), and per node of the separable group its (first, count) in each
+  std::vector<SepTask> sep_tasks[2][2];
+  std::vector<std::array<int, 4>> node_sept[2];
+  SepTask* d_sep_tasks[2][2] = {};
   size_t sep_lds[2][2] = {};  // dynamic LDS bytes per block, [class][pass]
   double* d_sepT = nullptr;
   int* d_inst_slot = nullptr;  // evaluation pass: committed slot of each class, per instance
@@ -216,10 +229,12 @@ struct Plan {
     void* buf = nullptr;
     std::vector<TileItem> tiles[2][kGroups], upd[2][kGroups];
     std::vector<SepItem> sep[2], sep2[2];
+    std::vector<SepTask> sept[2][2];
     TileItem* d_tiles[2][kGroups] = {};
     TileItem* d_upd[2][kGroups] = {};
     SepItem* d_sep[2] = {};
     SepItem* d_sep2[2] = {};
+    SepTask* d_sept[2][2] = {};
   };
   std::vector<ListSet> list_sets;
   uint64_t list_key = 0;
@@ -242,6 +257,10 @@ struct Plan {
       std::swap(sep_items2[c], L.sep2[c]);
       std::swap(d_sep_items[c], L.d_sep[c]);
       std::swap(d_sep_items2[c], L.d_sep2[c]);
+      for (int q = 0; q < 2; ++q) {
+        std::swap(sep_tasks[c][q], L.sept[c][q]);
+        std::swap(d_sep_tasks[c][q], L.d_sept[c][q]);
+      }
     }
     std::swap(list_key, L.key);
     std::swap(buf_in_use, L.buf);
@@ -288,6 +307,8 @@ struct Plan {
     tb.colour = c;
     tb.sep_items = d_sep_items[c];
     tb.sep_items2 = d_sep_items2[c];
+    tb.sep_tasks = d_sep_tasks[c][0];
+    tb.sep_tasks2 = d_sep_tasks[c][1];
     tb.rec_rows = rec_rows;
     tb.inst_slot = d_inst_slot;
     return tb;
@@ -341,7 +362,7 @@ struct Plan {
           tb.fin_nodes = d_nodes[1 - c];
           *fin_pending = false;
         }
-        if ((e = launch_msg_grid(tb, (int)tiles[c][g].size(), s)) != hipSuccess) return e;
+        if ((e = launch_msg_grid(tb, (int)tiles[c][g].size(), grid_R, s)) != hipSuccess) return e;
         tb = tables(c, g);
         tb.tiles = d_upd_tiles[c][g];
         return launch_node_sep(tb, (int)upd_tiles[c][g].size(), s);
@@ -349,10 +370,38 @@ struct Plan {
       for (size_t i = 0; i < node_tiles[c][g].size(); ++i) {
         Tables tb = tables(c, g);
         tb.tiles += node_tiles[c][g][i].first;
-        if ((e = launch_msg_grid(tb, node_tiles[c][g][i].second, s)) != hipSuccess) return e;
+        if ((e = launch_msg_grid(tb, node_tiles[c][g][i].second, grid_R, s)) != hipSuccess) return e;
         tb = tables(c, g);
         tb.tiles = d_upd_tiles[c][g] + node_upd[c][g][i].first;
         if ((e = launch_node_sep(tb, node_upd[c][g][i].second, s)) != hipSuccess) return e;
+      }
+      return hipSuccess;
+    }
+    if (g == kSepHGroup) {
+      // separable instances on uniform grids: both passes by Horner's rule,
+      // then the node stage
+      if (sep_tasks[c][0].empty()) return hipSuccess;
+      if (!per_node) {
+        Tables tb = tables(c, g);
+        if (*fin_pending) {
+          tb.n_fin = (int)inst.size();
+          tb.fin_colour = 1 - c;
+          tb.fin_nodes = d_nodes[1 - c];
+          *fin_pending = false;
+        }
+        if ((e = launch_sep_horner(tb, 0, (int)sep_tasks[c][0].size(), s)) != hipSuccess) return e;
+        tb.n_fin = 0;
+        if ((e = launch_sep_horner(tb, 1, (int)sep_tasks[c][1].size(), s)) != hipSuccess) return e;
+        return launch_node_sep(tb, (int)tiles[c][g].size(), s);
+      }
+      for (size_t i = 0; i < node_sept[c].size(); ++i) {
+        Tables tb = tables(c, g);
+        tb.sep_tasks += node_sept[c][i][0];
+        tb.sep_tasks2 += node_sept[c][i][2];
+        if ((e = launch_sep_horner(tb, 0, node_sept[c][i][1], s)) != hipSuccess) return e;
+        if ((e = launch_sep_horner(tb, 1, node_sept[c][i][3], s)) != hipSuccess) return e;
+        tb.tiles += node_tiles[c][g][i].first;
+        if ((e = launch_node_sep(tb, node_tiles[c][g][i].second, s)) != hipSuccess) return e;
       }
       return hipSuccess;
     }
@@ -383,7 +432,10 @@ struct Plan {
     return hipSuccess;
   }
 
-  bool group_empty(int c, int g) const { return g == kSepGroup ? sep_items[c].empty() : tiles[c][g].empty(); }
+  bool group_empty(int c, int g) const {
+    return g == kSepGroup ? sep_items[c].empty() : g == kSepHGroup ? sep_tasks[c][0].empty() : tiles[c][g].empty();
+  }
+  static bool aux_group(int g) { return g == kSepGroup || g == kSepHGroup; }
 
   // The node stage of class c: every kernel group in turn.  With fused, the
   // first launch also carries the finalise step of the previous half-sweep.
@@ -397,21 +449,22 @@ struct Plan {
   }
 
   // The fused node stage under graph capture: the other groups on s and the
-  // separable group on the context's second stream as parallel branches (they
-  // work on different instances), joined before the stage ends; the finalise
-  // blocks ride in the first launch on s (of the separable group when the
-  // others are empty).  One group alone: launch_node_stage.
+  // separable groups on the context's second stream as parallel branches
+  // (they work on different instances), joined before the stage ends; the
+  // finalise blocks ride in the first launch on s.  Groups on one side only:
+  // launch_node_stage.
   hipError_t launch_node_stage_forked(int c, bool fp64, hipStream_t s) const {
-    bool d_any = false;
-    for (int g = 0; g < kGroups; ++g) d_any = d_any || (g != kSepGroup && !group_empty(c, g));
-    if (!d_any || group_empty(c, kSepGroup)) return launch_node_stage(c, fp64, s, false, true);
+    bool d_any = false, a_any = false;
+    for (int g = 0; g < kGroups; ++g) (aux_group(g) ? a_any : d_any) |= !group_empty(c, g);
+    if (!d_any || !a_any) return launch_node_stage(c, fp64, s, false, true);
     hipError_t e;
     bool fin_d = true, fin_sep = false;
     if ((e = hipEventRecord(ctx->ev_fork, s)) != hipSuccess) return e;
     if ((e = hipStreamWaitEvent(ctx->aux, ctx->ev_fork, 0)) != hipSuccess) return e;
-    if ((e = launch_group(c, kSepGroup, fp64, ctx->aux, false, &fin_sep)) != hipSuccess) return e;
     for (int g = 0; g < kGroups; ++g)
-      if (g != kSepGroup && (e = launch_group(c, g, fp64, s, false, &fin_d)) != hipSuccess) return e;
+      if (aux_group(g) && (e = launch_group(c, g, fp64, ctx->aux, false, &fin_sep)) != hipSuccess) return e;
+    for (int g = 0; g < kGroups; ++g)
+      if (!aux_group(g) && (e = launch_group(c, g, fp64, s, false, &fin_d)) != hipSuccess) return e;
     if ((e = hipEventRecord(ctx->ev_join, ctx->aux)) != hipSuccess) return e;
     return hipStreamWaitEvent(s, ctx->ev_join, 0);
   }
@@ -467,6 +520,13 @@ static int build_plan(gmot_ctx* ctx, const std::vector<gmot_problem*>& probs, No
   pl->NR = shape.R;
   pl->NH = shape.H;
   pl->split_deg = kSplitDeg;
+  // two rows per lane in the grid kernel when every grid instance admits
+  // 128-row spans; GMOT_GRID_ROWS=1 keeps one
+  pl->grid_R = 2;
+  for (const gmot_problem* p : probs)
+    if (p->grid && p->grid_rows_lane < 2) pl->grid_R = 1;
+  if (const char* v = std::getenv("GMOT_GRID_ROWS"))
+    if (std::atoi(v) == 1) pl->grid_R = 1;
   bool split_forced = false;
   if (const char* v = std::getenv("GMOT_SPLIT_DEG")) {
     pl->split_deg = std::max(1, std::atoi(v));
@@ -512,8 +572,8 @@ static int build_plan(gmot_ctx* ctx, const std::vector<gmot_problem*>& probs, No
           for (int k : p->nbrs[j])
             work += (double)p->grid_rows(k) * p->grid_cols[j] * p->grid_cols[k] +
                     (double)p->sizes[j] * p->grid_rows(k);
-          ntl[c][kSepGroup].push_back({(int)pl->nodes[c].size(), (int)ceil_div(p->sizes[j], kSepTileRows), (int)i,
-                                       work});
+          ntl[c][p->sep_h ? kSepHGroup : kSepGroup].push_back(
+              {(int)pl->nodes[c].size(), (int)ceil_div(p->sizes[j], kSepTileRows), (int)i, work});
         } else if (p->grid) {
           double src_cols = 0.0;
           for (int k : p->nbrs[j]) src_cols += p->sizes[k];
@@ -583,7 +643,7 @@ static int build_plan(gmot_ctx* ctx, const std::vector<gmot_problem*>& probs, No
                           ? (double)md.rows_src * md.cols_dst * md.cols_src + (double)md.n_dst * md.rows_src
                           : (double)md.n_dst * md.n_src;
     pl->inst_pairs[msg_class[m]][md.inst] += ev;
-    const int grp = probs[md.inst]->sep    ? kSepGroup
+    const int grp = probs[md.inst]->sep    ? (probs[md.inst]->sep_h ? kSepHGroup : kSepGroup)
                     : probs[md.inst]->grid ? kGridGroup
                     : md.cost_kind == GMOT_COST_EXPLICIT ? 0
                                                          : md.dim;
@@ -659,16 +719,18 @@ static int build_plan(gmot_ctx* ctx, const std::vector<gmot_problem*>& probs, No
     for (int dk = 0; dk < kGroups; ++dk) {
       std::stable_sort(ntl[c][dk].begin(), ntl[c][dk].end(),
                        [](const NodeTiles& u, const NodeTiles& v) { return u.work > v.work; });
-      const int rows = dk == kSepGroup ? kSepTileRows : TRows;
+      const int rows = dk == kSepGroup || dk == kSepHGroup ? kSepTileRows : TRows;
       for (const NodeTiles& q : ntl[c][dk]) {
         const NodeItem& qn = pl->nodes[c][q.node_item];
         if (dk == kGridGroup) {
-          // one message item per (edge, 64 rows), the rows of one edge together
-          // (their waves share the source's columns), then the update's 64-row tiles
-          pl->node_tiles[c][dk].push_back({(int)pl->tiles[c][dk].size(), q.n_tiles * qn.deg});
+          // one message item per (edge, 64 grid_R rows), the rows of one edge
+          // together (their waves share the source's columns), then the
+          // update's 64-row tiles
+          const int mt = (int)ceil_div(qn.n, 64 * pl->grid_R);
+          pl->node_tiles[c][dk].push_back({(int)pl->tiles[c][dk].size(), mt * qn.deg});
           for (int k = 0; k < qn.deg; ++k)
-            for (int r = 0; r < q.n_tiles; ++r)
-              pl->tiles[c][dk].push_back({q.node_item, r * 64, q.inst, qn.msg0 + k, 1, qn.n, qn.fixed, 1});
+            for (int r = 0; r < mt; ++r)
+              pl->tiles[c][dk].push_back({q.node_item, r * 64 * pl->grid_R, q.inst, qn.msg0 + k, 1, qn.n, qn.fixed, 1});
           pl->node_upd[c][dk].push_back({(int)pl->upd_tiles[c][dk].size(), q.n_tiles});
           for (int r = 0; r < q.n_tiles; ++r)
             pl->upd_tiles[c][dk].push_back({q.node_item, r * 64, q.inst, qn.msg0, qn.deg, qn.n, qn.fixed, 0});
@@ -703,6 +765,22 @@ static int build_plan(gmot_ctx* ctx, const std::vector<gmot_problem*>& probs, No
           r[1] = (int)pl->sep_items[c].size() - r[0];
           r[3] = (int)pl->sep_items2[c].size() - r[2];
           pl->node_sep[c].push_back(r);
+        }
+        if (dk == kSepHGroup) {
+          // 16 outputs of one line per task, each message padded to whole waves
+          std::array<int, 4> r{(int)pl->sep_tasks[c][0].size(), 0, (int)pl->sep_tasks[c][1].size(), 0};
+          for (int m = qn.msg0; m < qn.msg0 + qn.deg; ++m)
+            for (int pass = 0; pass < 2; ++pass) {
+              const MsgDesc& md = pl->msgs[m];
+              const int lines = pass == 0 ? md.rows_src : md.cols_dst, outs = pass == 0 ? md.cols_dst : md.rows_dst;
+              auto& tk = pl->sep_tasks[c][pass];
+              for (int l = 0; l < lines; ++l)
+                for (int o0 = 0; o0 < outs; o0 += 16) tk.push_back({m, l, o0, q.inst});
+              while (tk.size() % 4 != 0) tk.push_back({m, 0, outs, q.inst});
+            }
+          r[1] = (int)pl->sep_tasks[c][0].size() - r[0];
+          r[3] = (int)pl->sep_tasks[c][1].size() - r[2];
+          pl->node_sept[c].push_back(r);
         }
       }
     }
@@ -765,6 +843,9 @@ static int build_plan(gmot_ctx* ctx, const std::vector<gmot_problem*>& probs, No
   size_t o_sep[2], o_sep2[2];
   for (int c = 0; c < 2; ++c) o_sep[c] = take(sizeof(SepItem) * pl->sep_items[c].size());
   for (int c = 0; c < 2; ++c) o_sep2[c] = take(sizeof(SepItem) * pl->sep_items2[c].size());
+  size_t o_sept[2][2];
+  for (int c = 0; c < 2; ++c)
+    for (int q = 0; q < 2; ++q) o_sept[c][q] = take(sizeof(SepTask) * pl->sep_tasks[c][q].size());
   const size_t o_sepT = take(sizeof(double) * 2 * std::max<int64_t>(1, sepT_total));
   const size_t o_islot = take(sizeof(int) * 2 * probs.size());
   const size_t total = off;
@@ -786,6 +867,8 @@ static int build_plan(gmot_ctx* ctx, const std::vector<gmot_problem*>& probs, No
   pl->d_tpart = (double*)(base + o_tpart);
   for (int c = 0; c < 2; ++c) pl->d_sep_items[c] = (SepItem*)(base + o_sep[c]);
   for (int c = 0; c < 2; ++c) pl->d_sep_items2[c] = (SepItem*)(base + o_sep2[c]);
+  for (int c = 0; c < 2; ++c)
+    for (int q = 0; q < 2; ++q) pl->d_sep_tasks[c][q] = (SepTask*)(base + o_sept[c][q]);
   pl->d_sepT = (double*)(base + o_sepT);
   pl->d_inst_slot = (int*)(base + o_islot);
   for (int c = 0; c < 2; ++c)
@@ -827,6 +910,10 @@ static int build_plan(gmot_ctx* ctx, const std::vector<gmot_problem*>& probs, No
     if (!pl->sep_items2[c].empty())
       HIPCHK(hipMemcpyAsync(pl->d_sep_items2[c], pl->sep_items2[c].data(),
                             sizeof(SepItem) * pl->sep_items2[c].size(), hipMemcpyHostToDevice, s));
+    for (int q = 0; q < 2; ++q)
+      if (!pl->sep_tasks[c][q].empty())
+        HIPCHK(hipMemcpyAsync(pl->d_sep_tasks[c][q], pl->sep_tasks[c][q].data(),
+                              sizeof(SepTask) * pl->sep_tasks[c][q].size(), hipMemcpyHostToDevice, s));
   }
   // one-pass shifts start at 0; the first two half-sweeps of every call take two passes anyway
   HIPCHK(hipMemsetAsync(pl->d_wmax, 0, sizeof(double) * std::max<int64_t>(1, wmax_total), s));
@@ -986,7 +1073,7 @@ static int compact_lists(Plan* pl, const std::vector<char>& running, int* count)
     off = o + std::max<size_t>(bytes, 1);
     return o;
   };
-  size_t o_t[2][kGroups], o_u[2][kGroups], o_s[2], o_s2[2];
+  size_t o_t[2][kGroups], o_u[2][kGroups], o_s[2], o_s2[2], o_k[2][2];
   for (int c = 0; c < 2; ++c) {
     for (int g = 0; g < kGroups; ++g) {
       for (const TileItem& t : pl->tiles[c][g])
@@ -1004,6 +1091,12 @@ static int compact_lists(Plan* pl, const std::vector<char>& running, int* count)
       if (keep(it.inst)) L.sep2[c].push_back(it);
     o_s[c] = take(sizeof(SepItem) * L.sep[c].size());
     o_s2[c] = take(sizeof(SepItem) * L.sep2[c].size());
+    // whole waves: a wave's four tasks share one instance
+    for (int q = 0; q < 2; ++q) {
+      for (const SepTask& tk : pl->sep_tasks[c][q])
+        if (keep(tk.inst)) L.sept[c][q].push_back(tk);
+      o_k[c][q] = take(sizeof(SepTask) * L.sept[c][q].size());
+    }
   }
   if (hipMalloc(&L.buf, off) != hipSuccess) return fail(GMOT_ENOMEM, "compacted work lists");
   char* b = (char*)L.buf;
@@ -1028,6 +1121,12 @@ static int compact_lists(Plan* pl, const std::vector<char>& running, int* count)
     if (!L.sep2[c].empty())
       HIPCHK(hipMemcpyAsync(L.d_sep2[c], L.sep2[c].data(), sizeof(SepItem) * L.sep2[c].size(),
                             hipMemcpyHostToDevice, s));
+    for (int q = 0; q < 2; ++q) {
+      L.d_sept[c][q] = (SepTask*)(b + o_k[c][q]);
+      if (!L.sept[c][q].empty())
+        HIPCHK(hipMemcpyAsync(L.d_sept[c][q], L.sept[c][q].data(), sizeof(SepTask) * L.sept[c][q].size(),
+                              hipMemcpyHostToDevice, s));
+    }
   }
   HIPCHK(hipStreamSynchronize(s));
   pl->list_sets.push_back(std::move(L));
@@ -1515,6 +1614,56 @@ static int upload(const gmot_tree_desc* d, gmot_problem* p) {
     }
     p->sep = all;
   }
+  // Separable passes by Horner's rule (k_sep_horner): every grid's row and
+  // column coordinate lists uniform (as for the one-dimensional grids), and for
+  // every message (source k, destination j) and pass, 2 log2e / eps * (half
+  // the span of any 16 consecutive outputs) * |h of the inputs| * W <=
+  // kGridRange, W the largest power of an output's ratio the pass forms
+  // (16 g - 1 for inputs in g <= 4 groups of 16, max(inputs - 1, 64) beyond).
+  p->sep_h = false;
+  if (p->sep && !std::getenv("GMOT_NO_GRID")) {
+    bool all = true;
+    std::vector<double> hR(p->N), hC(p->N), halfR(p->N, 0.0), halfC(p->N, 0.0);
+    auto uniform = [](const std::vector<double>& L, double* h) {
+      const size_t n = L.size();
+      *h = n > 1 ? (L[n - 1] - L[0]) / (double)(n - 1) : 0.0;
+      const double tol = 8.0 * DBL_EPSILON * std::max(std::fabs(L[0]), std::fabs(L[n - 1]));
+      for (size_t i = 0; i < n; ++i)
+        if (!std::isfinite(L[i]) || std::fabs(L[i] - (L[0] + (double)i * *h)) > tol) return false;
+      return true;
+    };
+    auto half16 = [](const std::vector<double>& L) {
+      double hs = 0.0;
+      for (size_t o0 = 0; o0 < L.size(); o0 += 16) {
+        double lo = L[o0], hi = L[o0];
+        for (size_t i = o0; i < std::min(L.size(), o0 + 16); ++i) {
+          lo = std::min(lo, L[i]);
+          hi = std::max(hi, L[i]);
+        }
+        hs = std::max(hs, 0.5 * (hi - lo));
+      }
+      return hs;
+    };
+    for (int j = 0; j < p->N && all; ++j) {
+      const double* X = sup.data() + p->node_off[j] * 2;
+      const int B = p->grid_cols[j], A = p->grid_rows(j);
+      std::vector<double> R(A), Cc(B);
+      for (int r = 0; r < A; ++r) R[r] = X[2 * (size_t)r * B];
+      for (int c = 0; c < B; ++c) Cc[c] = X[2 * c + 1];
+      all = uniform(R, &hR[j]) && uniform(Cc, &hC[j]);
+      halfR[j] = half16(R);
+      halfC[j] = half16(Cc);
+    }
+    auto W = [](int inner) { return inner > 64 ? std::max(inner - 1, 64) : 16 * ((inner + 15) / 16) - 1; };
+    const double two_kap = 2.0 * kLog2e / p->eps;
+    for (int e = 0; e < p->E && all; ++e)
+      for (int d = 0; d < 2 && all; ++d) {
+        const int k = p->edges[2 * e + d], j = p->edges[2 * e + 1 - d];  // message k -> j
+        all = two_kap * halfC[j] * std::fabs(hC[k]) * W(p->grid_cols[k]) <= kGridRange &&
+              two_kap * halfR[j] * std::fabs(hR[k]) * W(p->grid_rows(k)) <= kGridRange;
+      }
+    p->sep_h = all;
+  }
   // Messages from uniform one-dimensional grids (k_msg_grid): every support
   // X[i] = X[0] + i h with h = (X[n-1] - X[0]) / (n - 1), to within 8 ulps of
   // its largest magnitude, and for every message (source k, destination j)
@@ -1524,7 +1673,7 @@ static int upload(const gmot_tree_desc* d, gmot_problem* p) {
   p->grid = false;
   if (p->dim == 1 && d->cost_kind == GMOT_COST_SQEUCLID && p->E > 0 && !std::getenv("GMOT_NO_GRID")) {
     bool all = true;
-    std::vector<double> hs(p->N, 0.0), half(p->N, 0.0);
+    std::vector<double> hs(p->N, 0.0), half(p->N, 0.0), half2(p->N, 0.0);
     for (int j = 0; j < p->N && all; ++j) {
       const double* X = sup.data() + p->node_off[j];
       const int n = p->sizes[j];
@@ -1532,22 +1681,28 @@ static int upload(const gmot_tree_desc* d, gmot_problem* p) {
       const double tolx = 8.0 * DBL_EPSILON * std::max(std::fabs(X[0]), std::fabs(X[n - 1]));
       for (int i = 0; i < n && all; ++i) all = std::isfinite(X[i]) && std::fabs(X[i] - (X[0] + i * h)) <= tolx;
       hs[j] = h;
-      for (int r0 = 0; r0 < n; r0 += 64) {
-        double lo = X[r0], hi = X[r0];
-        for (int i = r0; i < std::min(n, r0 + 64); ++i) {
-          lo = std::min(lo, X[i]);
-          hi = std::max(hi, X[i]);
+      for (int rows = 64; rows <= 128; rows += 64)
+        for (int r0 = 0; r0 < n; r0 += rows) {
+          double lo = X[r0], hi = X[r0];
+          for (int i = r0; i < std::min(n, r0 + rows); ++i) {
+            lo = std::min(lo, X[i]);
+            hi = std::max(hi, X[i]);
+          }
+          double& hf = rows == 64 ? half[j] : half2[j];
+          hf = std::max(hf, 0.5 * (hi - lo));
         }
-        half[j] = std::max(half[j], 0.5 * (hi - lo));
-      }
     }
     const double two_kap = 2.0 * kLog2e / p->eps;
+    bool two = true;  // the same with 128-row spans (two rows per lane)
     for (int e = 0; e < p->E && all; ++e) {
       const int a = p->edges[2 * e], b = p->edges[2 * e + 1];
-      all = two_kap * half[b] * std::fabs(hs[a]) * std::max(p->sizes[a] - 1, 64) <= kGridRange &&
-            two_kap * half[a] * std::fabs(hs[b]) * std::max(p->sizes[b] - 1, 64) <= kGridRange;
+      const double ga = two_kap * std::fabs(hs[a]) * std::max(p->sizes[a] - 1, 64);  // message a -> b
+      const double gb = two_kap * std::fabs(hs[b]) * std::max(p->sizes[b] - 1, 64);  // message b -> a
+      all = ga * half[b] <= kGridRange && gb * half[a] <= kGridRange;
+      two = two && ga * half2[b] <= kGridRange && gb * half2[a] <= kGridRange;
     }
     p->grid = all;
+    p->grid_rows_lane = all && two ? 2 : 1;
   }
   HIPCHK(hipMemcpy(p->d_support, sup.data(), sizeof(double) * P * p->dim, hipMemcpyHostToDevice));
   HIPCHK(hipMemcpy(p->d_lg, lg.data(), sizeof(double) * P, hipMemcpyHostToDevice));

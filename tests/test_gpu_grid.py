@@ -22,6 +22,7 @@ from workloads import make_chain, make_star, make_tree, make_batched_stars
 pytestmark = pytest.mark.gpu
 
 GRID_GROUP = 5  # kernel group of the grid path in the timing stats
+SEP_HORNER_GROUP = 6  # separable passes by Horner's rule
 
 
 @pytest.fixture(scope="module")
@@ -35,11 +36,11 @@ def gpu_problem(ctx, p):
     return Problem(ctx, p)
 
 
-def grid_pairs(ctx, p):
-    """Terms the grid group evaluated in one timed half-sweep pair."""
+def grid_pairs(ctx, p, group=GRID_GROUP):
+    """Terms a kernel group evaluated in one timed half-sweep pair."""
     g = gpu_problem(ctx, p)
     g.solve(tol=0.0, max_steps=2, timing=True)
-    return g.stats()["group_pairs"][GRID_GROUP]
+    return g.stats()["group_pairs"][group]
 
 
 def _reversed(p):
@@ -68,8 +69,13 @@ def _cases():
     return {"chain": chain, "star12": star, "tiny": tiny, "big": big, "reversed": _reversed(chain)}
 
 
+@pytest.mark.parametrize("rows", ["auto", "1"])
 @pytest.mark.parametrize("name", ["chain", "star12", "tiny", "big", "reversed"])
-def test_grid_iterates_match_oracle_and_general_kernel(ctx, name, monkeypatch):
+def test_grid_iterates_match_oracle_and_general_kernel(ctx, name, rows, monkeypatch):
+    """rows: two rows per lane where every message admits 128-row spans
+    (star12, tiny, big), one otherwise; GMOT_GRID_ROWS=1 forces one."""
+    if rows == "1":
+        monkeypatch.setenv("GMOT_GRID_ROWS", "1")
     p = _cases()[name]
     assert grid_pairs(ctx, p) > 0
     steps = 12
@@ -175,3 +181,60 @@ def test_grid_zero_mass_and_far_potentials(ctx):
         fin = np.isfinite(lo)
         assert np.array_equal(fin, np.isfinite(g.potentials()))
         assert np.max(np.abs(g.potentials()[fin] - lo[fin])) <= 1e-9 * max(1.0, float(np.max(np.abs(lo[fin]))))
+
+
+def rect_grid_problem(rows, cols, eps, instance):
+    """A three-node chain on one rows x cols Cartesian grid per node (row-major,
+    uniform coordinates in [0, 1]), the middle node free."""
+    p = make_tree([(0, 1), (1, 2)], [rows * cols] * 3, [1, 0, 1], dim=2, eps=eps, instance=instance,
+                  support="grid", marginals="dirichlet")
+    R = np.linspace(0.0, 1.0, rows) if rows > 1 else np.zeros(1)
+    Cc = np.linspace(0.0, 1.0, cols) if cols > 1 else np.zeros(1)
+    pts = np.stack(np.meshgrid(R, Cc, indexing="ij"), axis=-1).reshape(-1, 2)
+    p.support = np.ascontiguousarray(np.concatenate([pts] * 3, axis=0))
+    return p
+
+
+@pytest.mark.parametrize("rows,cols", [(2, 100), (100, 2), (9, 70), (70, 9)])
+def test_separable_horner_several_input_tiles(ctx, rows, cols, monkeypatch):
+    """Grid lines of more than 64 points (several 64-input tiles per pass, Horner
+    across tiles), both orientations: FP64 and FP32-core iterates to 1e-9 of
+    the oracle and of the shifted-sum path (GMOT_NO_GRID=1, FP64)."""
+    p = rect_grid_problem(rows, cols, eps=0.05, instance=130 + rows)
+    assert grid_pairs(ctx, p, SEP_HORNER_GROUP) > 0
+    steps = 10
+    o = TreeOracle(p)
+    o.run_fixed(steps)
+    lo = o.potentials()
+    scale = max(1.0, float(np.max(np.abs(lo))))
+    for precision in ("fp64", "fp32core"):
+        g = gpu_problem(ctx, p)
+        assert g.solve(tol=0.0, max_steps=steps, precision=precision)["steps"] == steps
+        assert np.max(np.abs(g.potentials() - lo)) <= 1e-9 * scale, precision
+    monkeypatch.setenv("GMOT_NO_GRID", "1")
+    h = gpu_problem(ctx, p)
+    assert h.solve(tol=0.0, max_steps=steps, precision="fp64")["steps"] == steps
+    assert np.max(np.abs(h.potentials() - lo)) <= 1e-9 * scale
+
+
+def test_separable_horner_fallback(ctx):
+    """A coarse grid at a small eps (powers of an output's ratio beyond the
+    admitted range) takes the shifted-sum passes: FP64 iterates still match the
+    oracle; a uniform grid at the same size and a larger eps matches in FP32-core
+    mode to 1e-9 (the Horner passes are FP64)."""
+    coarse = rect_grid_problem(6, 7, eps=1e-4, instance=140)
+    assert grid_pairs(ctx, coarse, SEP_HORNER_GROUP) == 0 and grid_pairs(ctx, coarse, 4) > 0
+    o = TreeOracle(coarse)
+    o.run_fixed(6)
+    g = gpu_problem(ctx, coarse)
+    assert g.solve(tol=0.0, max_steps=6, precision="fp64")["steps"] == 6
+    lo = o.potentials()
+    assert np.max(np.abs(g.potentials() - lo)) <= 1e-9 * max(1.0, float(np.max(np.abs(lo))))
+    fine = rect_grid_problem(6, 7, eps=0.05, instance=141)
+    assert grid_pairs(ctx, fine, SEP_HORNER_GROUP) > 0
+    o = TreeOracle(fine)
+    o.run_fixed(6)
+    g = gpu_problem(ctx, fine)
+    assert g.solve(tol=0.0, max_steps=6, precision="fp32core")["steps"] == 6
+    lo = o.potentials()
+    assert np.max(np.abs(g.potentials() - lo)) <= 1e-9 * max(1.0, float(np.max(np.abs(lo))))

@@ -178,7 +178,7 @@ def test_timing_stats_count_working_half_sweeps(ctx, path, monkeypatch):
     grp = 5 if path == "grid" else 1
     assert st["group_pairs"][grp] == st["msg_pairs"] and sum(st["group_pairs"]) == st["msg_pairs"]
     assert st["group_ms"][grp] > 0
-    assert all(st["group_ms"][k] == 0.0 for k in range(6) if k != grp)
+    assert all(st["group_ms"][k] == 0.0 for k in range(7) if k != grp)
 
 
 def test_evaluate_matches_oracle_on_given_potentials(ctx):

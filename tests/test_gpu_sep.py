@@ -42,28 +42,43 @@ def _cases():
     return [t, r, s]
 
 
+@pytest.mark.parametrize("path", ["horner", "pass"])
 @pytest.mark.parametrize("case", [0, 1, 2])
-def test_separable_iterates_match_oracle_and_general_kernel(ctx, case, monkeypatch):
+def test_separable_iterates_match_oracle_and_general_kernel(ctx, case, path, monkeypatch):
+    """Both separable paths: Horner's rule on uniform grids (k_sep_horner, FP64
+    in both precisions, the default) and the shifted exponential sums
+    (k_sep_pass, GMOT_NO_GRID=1)."""
+    if path == "pass":
+        monkeypatch.setenv("GMOT_NO_GRID", "1")
     p = _cases()[case]
+    # which separable kernel group the instance takes (5 x 6 grids at eps = 5e-3
+    # lie outside the Horner passes' range and take k_sep_pass either way)
+    t = gpu_problem(ctx, p)
+    t.solve(tol=0.0, max_steps=2, timing=True)
+    gp = t.stats()["group_pairs"]
+    horner = gp[6] > 0
+    assert (gp[4] > 0) != horner and (path == "horner" or not horner)
     steps = 12
     o = TreeOracle(p)
     hist = o.run_fixed(steps)
     eo = o.evaluate()
-    for precision, tol in (("fp64", 1e-9), ("fp32core", 1e-6)):
+    for precision, tol in (("fp64", 1e-9), ("fp32core", 1e-9 if horner else 1e-6)):
         g = gpu_problem(ctx, p)
         r = g.solve(tol=0.0, max_steps=steps, precision=precision)
         assert r["steps"] == steps
         assert abs(g.evaluate()["dual"] - eo["dual"]) <= tol * eo["scale"]
         for e in range(p.n_edges):
             assert np.max(np.abs(g.coupling(e) - o.coupling(e))) <= tol
-        rel = 1e-8 if precision == "fp64" else 1e-3
+        rel = 1e-8 if tol < 1e-6 else 1e-3
         assert abs(r["err_sum"] - hist[-1][0]) <= rel * hist[-1][0] + 1e-10
         monkeypatch.setenv("GMOT_NO_SEP", "1")
         h = gpu_problem(ctx, p)
         monkeypatch.delenv("GMOT_NO_SEP")
         h.solve(tol=0.0, max_steps=steps, precision=precision)
+        # the general kernel's own precision bounds this comparison
+        tol_h = 1e-9 if precision == "fp64" else 1e-6
         for e in range(p.n_edges):
-            assert np.max(np.abs(g.coupling(e) - h.coupling(e))) <= tol
+            assert np.max(np.abs(g.coupling(e) - h.coupling(e))) <= tol_h
 
 
 @pytest.mark.parametrize("shape", ["8,1,2", "4,1,1", "16,2"])
