@@ -294,6 +294,7 @@ hipError_t launch_star_apply(const StarDesc* stars, int count, int L, int n, con
 // wave (tiles of 64 * R / H rows: 32, 64 or 128).
 struct NodeShape {
   int W, R, H;
+  int G = 1;  // 1: the uniform-grid kernels (k_msg_grid, k_sep_horner) where a problem admits them
 };
 
 struct gmot_ctx {

@@ -522,9 +522,14 @@ static int build_plan(gmot_ctx* ctx, const std::vector<gmot_problem*>& probs, No
   pl->split_deg = kSplitDeg;
   // two rows per lane in the grid kernel when every grid instance admits
   // 128-row spans; GMOT_GRID_ROWS=1 keeps one
+  // the uniform-grid kernels where a problem admits them, unless the shape
+  // turns them off (the autotuner times both)
+  const bool use_grid = shape.G != 0;
+  auto on_grid = [&](const gmot_problem* p) { return use_grid && p->grid; };
+  auto on_sep_h = [&](const gmot_problem* p) { return use_grid && p->sep_h; };
   pl->grid_R = 2;
   for (const gmot_problem* p : probs)
-    if (p->grid && p->grid_rows_lane < 2) pl->grid_R = 1;
+    if (on_grid(p) && p->grid_rows_lane < 2) pl->grid_R = 1;
   if (const char* v = std::getenv("GMOT_GRID_ROWS"))
     if (std::atoi(v) == 1) pl->grid_R = 1;
   bool split_forced = false;
@@ -572,9 +577,9 @@ static int build_plan(gmot_ctx* ctx, const std::vector<gmot_problem*>& probs, No
           for (int k : p->nbrs[j])
             work += (double)p->grid_rows(k) * p->grid_cols[j] * p->grid_cols[k] +
                     (double)p->sizes[j] * p->grid_rows(k);
-          ntl[c][p->sep_h ? kSepHGroup : kSepGroup].push_back(
+          ntl[c][on_sep_h(p) ? kSepHGroup : kSepGroup].push_back(
               {(int)pl->nodes[c].size(), (int)ceil_div(p->sizes[j], kSepTileRows), (int)i, work});
-        } else if (p->grid) {
+        } else if (on_grid(p)) {
           double src_cols = 0.0;
           for (int k : p->nbrs[j]) src_cols += p->sizes[k];
           ntl[c][kGridGroup].push_back({(int)pl->nodes[c].size(), (int)ceil_div(p->sizes[j], 64), (int)i, src_cols});
@@ -643,8 +648,8 @@ static int build_plan(gmot_ctx* ctx, const std::vector<gmot_problem*>& probs, No
                           ? (double)md.rows_src * md.cols_dst * md.cols_src + (double)md.n_dst * md.rows_src
                           : (double)md.n_dst * md.n_src;
     pl->inst_pairs[msg_class[m]][md.inst] += ev;
-    const int grp = probs[md.inst]->sep    ? (probs[md.inst]->sep_h ? kSepHGroup : kSepGroup)
-                    : probs[md.inst]->grid ? kGridGroup
+    const int grp = probs[md.inst]->sep       ? (on_sep_h(probs[md.inst]) ? kSepHGroup : kSepGroup)
+                    : on_grid(probs[md.inst]) ? kGridGroup
                     : md.cost_kind == GMOT_COST_EXPLICIT ? 0
                                                          : md.dim;
     pl->inst_group_pairs[msg_class[m]][grp][md.inst] += ev;
@@ -1811,11 +1816,27 @@ static int autotune(gmot_ctx* ctx, const std::vector<gmot_problem*>& probs, Plan
                     int32_t* R_out, int32_t* H_out, double* ms_out) {
   static const NodeShape kCand[] = {{2, 1, 1}, {4, 1, 1}, {8, 1, 1},  {16, 1, 1}, {2, 2, 1}, {4, 2, 1}, {8, 2, 1},
                                     {16, 2, 1}, {4, 2, 2}, {8, 2, 2}, {16, 2, 2}, {4, 1, 2}, {8, 1, 2}, {16, 1, 2}};
-  bool expl = false;
-  for (const gmot_problem* p : probs) expl = expl || p->cost_kind == GMOT_COST_EXPLICIT;
+  bool expl = false, any_grid = false, all_grid = true;
+  for (const gmot_problem* p : probs) {
+    expl = expl || p->cost_kind == GMOT_COST_EXPLICIT;
+    const bool g = p->grid || p->sep_h;
+    any_grid = any_grid || g;
+    all_grid = all_grid && g;
+  }
   std::vector<NodeShape> cands;
-  for (const auto& c : kCand)
-    if (!expl || (c.R == 1 && c.H == 1)) cands.push_back(c);  // explicit cost: one row per lane
+  // With the uniform-grid kernels on, the node shape matters only for the
+  // problems they do not take; with every problem on them, one shape.  When
+  // some problem admits them, every shape is also timed with them off (a small
+  // plan can fill the device better through the node kernel's column ranges).
+  if (all_grid) {
+    cands.push_back(NodeShape{4, 1, 1, 1});
+  } else {
+    for (const auto& c : kCand)
+      if (!expl || (c.R == 1 && c.H == 1)) cands.push_back(c);  // explicit cost: one row per lane
+  }
+  if (any_grid)
+    for (const auto& c : kCand)
+      if (!expl || (c.R == 1 && c.H == 1)) cands.push_back(NodeShape{c.W, c.R, c.H, 0});
   if (std::getenv("GMOT_NODE_SHAPE")) {  // a pinned shape is the only candidate
     NodeShape pin = choose_shape(ctx, probs);
     if (expl) pin.R = pin.H = 1;
