@@ -83,12 +83,12 @@ struct MsgDesc {
 struct SepItem {
   int32_t msg, line0, inst, nlines;
 };
-// One 16-lane row of a separable pass on uniform grids (k_sep_horner):
-// outputs [o0, o0 + 16) of line `line` of message msg; a wave takes four
-// consecutive tasks of one message (padding tasks have o0 = outputs per line).
+// One wave of a separable pass on uniform grids (k_sep_horner): outputs
+// [o0, o0 + 64) of lines [line, line + kSepLines) of message msg.
 struct SepTask {
   int32_t msg, line, o0, inst;
 };
+constexpr int kSepTaskLines = 8;  // lines per SepTask (the kernel's kSepLines)
 constexpr int kSepWaves = 4;        // waves per block of a separable pass
 constexpr int kSepMaxSide = 2048;   // grid rows and columns of a separable support at most
 constexpr int kSepMaxOut = 2048;    // outputs per separable-pass block (8 per thread)
@@ -243,7 +243,7 @@ hipError_t launch_sep_pass(const Tables& tb, int pass, int n_items, size_t lds_b
 hipError_t launch_node_sep(const Tables& tb, int n_tiles, hipStream_t s);
 // separable pass `pass` on uniform grids over the n_tasks tasks of
 // tb.sep_tasks (pass 0, carrying tb.n_fin finalise blocks) or tb.sep_tasks2
-// (pass 1); n_tasks a multiple of four
+// (pass 1), one wave each
 hipError_t launch_sep_horner(const Tables& tb, int pass, int n_tasks, hipStream_t s);
 // messages on uniform one-dimensional source grids: one wave per tile item of
 // tb.tiles (a message, msg0, for 64 * rows_per_lane destination rows from

@@ -1598,35 +1598,49 @@ __global__ __launch_bounds__(64 * kGridWaves, R == 2 ? 4 : 1) void k_msg_grid(Ta
 // line, a one-dimensional message from uniformly spaced inputs y_i = y_0 + i h
 // to the line's outputs z_o:
 //   out(o) = log2 sum_i 2^(s(i) + 2 kap z_o y_i),   s(i) = staged value - kap y_i^2,
-// summed as in k_msg_grid: with z_c the midpoint of a group's outputs,
+// summed as in k_msg_grid: with z_c the midpoint of the wave's outputs,
 //   out(o) = theta + log2 sum_i v_i rho_o^i + 2 kap (z_o - z_c) y_0,
 //   v_i = 2^(C(i) - theta),  C(i) = s(i) + 2 kap z_c y_i,  rho_o = 2^(2 kap (z_o - z_c) h).
-// Each 16-lane row of a wave takes one task: 16 consecutive outputs of one
-// line; its lanes hold the line's values v of four 16-input groups of a
-// 64-input tile (lane q of the row: inputs q, 16 + q, 32 + q, 48 + q), so the
-// row broadcast of v_fmac_f64 hands every output of the row each input of
-// its own line, and theta is a row maximum.  The four tasks of a wave belong
-// to one message (the task list pads each message to whole waves).  The host
-// takes this path only when every grid coordinate list is uniform and, per
-// pass, 2 kap * (half the span of 16 outputs) * |h| * W <= kGridRange, with W
-// the largest power of rho formed: 16 g - 1 for g = ceil(inner / 16) <= 4
-// groups in one tile, max(inner - 1, 64) over several tiles.  Pass 0 stores
-// Tt(q, u) = T(u, q) - kap C_j[q]^2 - kap R_k[u]^2, pass 1 the message in mfull,
-// as k_sep_pass does.
+// One wave takes one task: 64 outputs (lane = output) of kSepLines lines of
+// one message; the powers of each lane's rho are formed once, and for each
+// line the lanes compute the line's values v (lane = input, 64 per tile),
+// exchange them through LDS so that every 16-lane row holds all of them, and
+// sum with the row broadcast of v_fmac_f64, only over the 16-input groups
+// the inputs fill.  The host takes this path only when every grid coordinate
+// list is uniform and, per pass, 2 kap * (half the span of 64 consecutive
+// outputs) * |h| * W <= kGridRange, with W the largest power of rho formed:
+// 16 g - 1 for g = ceil(inner / 16) <= 4 groups in one tile, max(inner - 1, 64)
+// over several tiles.  Pass 0 stores Tt(q, u) = T(u, q) - kap C_j[q]^2 -
+// kap R_k[u]^2, pass 1 the message in mfull, as k_sep_pass does.
 // ---------------------------------------------------------------------------
-// maximum over the 16 lanes of each row (every lane of the row gets it)
-__device__ inline double row_max(double v) {
-  v = fmax(v, dpp_move<kDppXor1>(v));
-  v = fmax(v, dpp_move<kDppXor2>(v));
-  v = fmax(v, dpp_move<kDppHalfMirror>(v));
-  return fmax(v, dpp_move<kDppMirror>(v));
-}
+constexpr int kSepLines = kSepTaskLines;  // lines per task of a separable Horner pass
 
 #define GMOT_FMAC_ROWBCAST_S(acc, a, b, Q) \
   asm("v_fmac_f64_dpp %0, %1, %2 row_newbcast:" #Q " row_mask:0xf bank_mask:0xf" : "+v"(acc) : "v"(a), "v"(b))
 
+// sum over the NG groups of 16 inputs of one tile: sum_c rho^(16 c) sum_q v[16 c + q] rho^q
+template <int NG>
+__device__ inline double horner_tile(const double* vc, const double* pw, double r16) {
+  double S[4] = {0.0, 0.0, 0.0, 0.0};
+#define GMOT_SEP_COL(Q)                                                  \
+  GMOT_FMAC_ROWBCAST_S(S[0], vc[0], pw[Q], Q);                           \
+  if (NG > 1) GMOT_FMAC_ROWBCAST_S(S[1], vc[1], pw[Q], Q);               \
+  if (NG > 2) GMOT_FMAC_ROWBCAST_S(S[2], vc[2], pw[Q], Q);               \
+  if (NG > 3) GMOT_FMAC_ROWBCAST_S(S[3], vc[3], pw[Q], Q);
+  GMOT_SEP_COL(0) GMOT_SEP_COL(1) GMOT_SEP_COL(2) GMOT_SEP_COL(3)
+  GMOT_SEP_COL(4) GMOT_SEP_COL(5) GMOT_SEP_COL(6) GMOT_SEP_COL(7)
+  GMOT_SEP_COL(8) GMOT_SEP_COL(9) GMOT_SEP_COL(10) GMOT_SEP_COL(11)
+  GMOT_SEP_COL(12) GMOT_SEP_COL(13) GMOT_SEP_COL(14) GMOT_SEP_COL(15)
+#undef GMOT_SEP_COL
+  if (NG == 1) return S[0];
+  if (NG == 2) return fma(S[1], r16, S[0]);
+  if (NG == 3) return fma(fma(S[2], r16, S[1]), r16, S[0]);
+  return fma(fma(fma(S[3], r16, S[2]), r16, S[1]), r16, S[0]);
+}
+
 template <int PASS>
 __global__ __launch_bounds__(64 * kSepWaves) void k_sep_horner(Tables tb, int n_tasks) {
+  __shared__ double s_v[kSepWaves][64];
   int bid = (int)blockIdx.x;
   if (PASS == 0) {
     if (bid < tb.n_fin) {
@@ -1638,21 +1652,18 @@ __global__ __launch_bounds__(64 * kSepWaves) void k_sep_horner(Tables tb, int n_
     bid -= tb.n_fin;
   }
   const int lane = threadIdx.x & 63, wv = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
-  const int ql = lane & 15;
   const int w = bid * kSepWaves + wv;
-  if (w * 4 >= n_tasks) return;
-  const SepTask* __restrict__ tasks = PASS == 0 ? tb.sep_tasks : tb.sep_tasks2;
-  const SepTask tk = tasks[w * 4 + (lane >> 4)];
-  // message and instance: the same for the wave's four tasks
-  const int msg = __builtin_amdgcn_readfirstlane(tk.msg), inst = __builtin_amdgcn_readfirstlane(tk.inst);
-  const InstState* st = tb.inst + inst;
+  if (w >= n_tasks) return;
+  const SepTask tk = (PASS == 0 ? tb.sep_tasks : tb.sep_tasks2)[w];
+  const InstState* st = tb.inst + tk.inst;
   const long long t = st->vt[tb.colour];
   if (st->vdone[tb.colour] != 0 || t < st->t_first || ((t & 1) == 1) != (tb.colour == 0)) return;
-  const CMsg& md = *(const CMsg*)(tb.msgs + msg);
+  const CMsg& md = *(const CMsg*)(tb.msgs + tk.msg);
   const int Ak = md.rows_src, Bk = md.cols_src, Bj = md.cols_dst, Aj = md.rows_dst;
   const int nk = md.n_src, nj = md.n_dst;
-  const int outs = PASS == 0 ? Bj : Aj;   // outputs per line
-  const int inner = PASS == 0 ? Bk : Ak;  // inputs per output
+  const int outs = PASS == 0 ? Bj : Aj;     // outputs per line
+  const int inner = PASS == 0 ? Bk : Ak;    // inputs per output
+  const int lines = PASS == 0 ? Ak : Bj;
   const int src_slot = (int)((t >> 1) % kSlots);
   const GDbl* __restrict__ lam = (const GDbl*)md.lam_src[src_slot];
   const GDbl* __restrict__ lg = (const GDbl*)md.lg_src;
@@ -1660,14 +1671,13 @@ __global__ __launch_bounds__(64 * kSepWaves) void k_sep_horner(Tables tb, int n_
   const GDbl* __restrict__ xs = (const GDbl*)md.supp_dst;
   const GDbl* __restrict__ Tr = (const GDbl*)md.sepT;
   const double kap = kLog2e / md.eps;
-  const int line = tk.line, o = tk.o0 + ql;
+  const int o = tk.o0 + lane;
   const bool ov = o < outs;
   const int oc = min(o, outs - 1);
   // input coordinate i of the pass and the output coordinate of this lane
   auto yin = [&](int i) -> double { return PASS == 0 ? ys[(size_t)i * 2 + 1] : ys[(size_t)i * Bk * 2]; };
   const double z = PASS == 0 ? xs[(size_t)oc * 2 + 1] : xs[(size_t)oc * Bj * 2];
-  const double zhi = row_max(ov ? z : -INFINITY), zlo = -row_max(ov ? -z : -INFINITY);
-  const double zc = zhi > -INFINITY ? 0.5 * (zhi + zlo) : 0.0;
+  const double zc = 0.5 * (wave_max(ov ? z : -INFINITY) - wave_max(ov ? -z : -INFINITY));
   const double y0 = yin(0);
   const double h = inner > 1 ? (yin(inner - 1) - y0) / (double)(inner - 1) : 0.0;
   const double dz = z - zc;
@@ -1679,8 +1689,8 @@ __global__ __launch_bounds__(64 * kSepWaves) void k_sep_horner(Tables tb, int n_
   const double r16 = pw[15] * rho;
   const double czc = 2.0 * kap * zc;
   const int nt = (inner + 63) / 64;
-  const int ng = min(4, (inner + 15) / 16);  // 16-input groups per tile
-  // pass 1: the source's normaliser c_k (every lane of the wave, before any divergence)
+  const int ng = nt > 1 ? 4 : (inner + 15) / 16;  // 16-input groups of a tile
+  // pass 1: the source's normaliser c_k
   double ck = 0.0;
   if (PASS == 1 && md.src_free) {
     if (t - 1 >= st->t_first) {
@@ -1693,66 +1703,60 @@ __global__ __launch_bounds__(64 * kSepWaves) void k_sep_horner(Tables tb, int n_
       ck = *(const GDbl*)(md.c_src + src_slot);
     }
   }
-  double theta = -INFINITY, P = 0.0;
-  for (int J = nt - 1; J >= 0; --J) {
-    double Cv[4];
-#pragma unroll
-    for (int c = 0; c < 4; ++c) {
-      const int i = J * 64 + 16 * c + ql;
+  double* __restrict__ sv = s_v[wv];
+  const int l_end = min(tk.line + kSepLines, lines);
+  for (int line = tk.line; line < l_end; ++line) {
+    double theta = -INFINITY, P = 0.0;
+    for (int J = nt - 1; J >= 0; --J) {
+      const int i = J * 64 + lane;
       const int ic = min(i, inner - 1);
+      const double y = yin(ic);
       double s;
       if (PASS == 0) {
         const int idx = min(line * Bk + ic, nk - 1);
-        const double y = yin(ic);
-        s = fma(-kap * y, y, kLog2e * (lam[idx] + lg[idx]));
-        if (!(i < inner && line * Bk + i < nk)) s = -INFINITY;
-        Cv[c] = s > -INFINITY ? fma(czc, y, s) : -INFINITY;
+        s = (i < inner && line * Bk + i < nk) ? fma(-kap * y, y, kLog2e * (lam[idx] + lg[idx])) : -INFINITY;
       } else {
-        s = Tr[(size_t)line * Ak + ic];
-        if (!(i < inner)) s = -INFINITY;
-        Cv[c] = s > -INFINITY ? fma(czc, yin(ic), s) : -INFINITY;
+        s = i < inner ? Tr[(size_t)line * Ak + ic] : -INFINITY;
+      }
+      const double C = s > -INFINITY ? fma(czc, y, s) : -INFINITY;
+      // a line's first tile starts from the first input's value (any value
+      // within the slack below the maximum serves; v_i <= 2^kGridSlack)
+      if (J == nt - 1) theta = lane_read(C, 0);
+      if (__any(C > theta + kGridSlack)) {
+        const double m = wave_max(C);
+        if (J != nt - 1 && theta > -INFINITY) P *= exp2(theta - m);
+        theta = m;
+      }
+      sv[lane] = C > -INFINITY ? exp2(C - theta) : 0.0;
+      wave_sync();
+      double vc[4];
+#pragma unroll
+      for (int c = 0; c < 4; ++c) vc[c] = sv[16 * c + (lane & 15)];
+      wave_sync();
+      double St;
+      switch (ng) {
+        case 1: St = horner_tile<1>(vc, pw, r16); break;
+        case 2: St = horner_tile<2>(vc, pw, r16); break;
+        case 3: St = horner_tile<3>(vc, pw, r16); break;
+        default: St = horner_tile<4>(vc, pw, r16); break;
+      }
+      if (J == nt - 1) {
+        P = St;
+      } else {
+        const double r64 = (r16 * r16) * (r16 * r16);
+        P = fma(P, r64, St);
       }
     }
-    const double m = row_max(fmax(fmax(Cv[0], Cv[1]), fmax(Cv[2], Cv[3])));
-    if (m > theta + kGridSlack) {
-      if (theta > -INFINITY) P *= exp2(theta - m);
-      theta = m;
-    }
-    double vc[4];
-#pragma unroll
-    for (int c = 0; c < 4; ++c) vc[c] = Cv[c] > -INFINITY ? exp2(Cv[c] - theta) : 0.0;
-    double S[4] = {0.0, 0.0, 0.0, 0.0};
-#define GMOT_SEP_COL(Q)                                   \
-  GMOT_FMAC_ROWBCAST_S(S[0], vc[0], pw[Q], Q);            \
-  GMOT_FMAC_ROWBCAST_S(S[1], vc[1], pw[Q], Q);            \
-  GMOT_FMAC_ROWBCAST_S(S[2], vc[2], pw[Q], Q);            \
-  GMOT_FMAC_ROWBCAST_S(S[3], vc[3], pw[Q], Q);
-    GMOT_SEP_COL(0) GMOT_SEP_COL(1) GMOT_SEP_COL(2) GMOT_SEP_COL(3)
-    GMOT_SEP_COL(4) GMOT_SEP_COL(5) GMOT_SEP_COL(6) GMOT_SEP_COL(7)
-    GMOT_SEP_COL(8) GMOT_SEP_COL(9) GMOT_SEP_COL(10) GMOT_SEP_COL(11)
-    GMOT_SEP_COL(12) GMOT_SEP_COL(13) GMOT_SEP_COL(14) GMOT_SEP_COL(15)
-#undef GMOT_SEP_COL
-    // groups past the inputs hold zeros; only the powers the host bounded are formed
-    double St = S[0];
-    if (ng == 2) St = fma(S[1], r16, S[0]);
-    else if (ng == 3) St = fma(fma(S[2], r16, S[1]), r16, S[0]);
-    else if (ng == 4) St = fma(fma(fma(S[3], r16, S[2]), r16, S[1]), r16, S[0]);
-    if (J == nt - 1) {
-      P = St;
+    const double T = (theta > -INFINITY && P > 0.0) ? theta + log2(P) + 2.0 * kap * dz * y0 : -INFINITY;
+    if (PASS == 0) {
+      if (ov) {
+        const double Ru = ys[(size_t)line * Bk * 2];
+        ((GDblW*)md.sepT)[(size_t)o * Ak + line] = T - kap * (z * z) - kap * (Ru * Ru);
+      }
     } else {
-      const double r64 = (r16 * r16) * (r16 * r16);
-      P = fma(P, r64, St);
+      const int x = o * Bj + line;
+      if (ov && x < nj) ((GDblW*)md.mfull)[x] = T > -INFINITY ? kLn2 * (T - kap * (z * z)) - ck : -INFINITY;
     }
-  }
-  const double T = (theta > -INFINITY && P > 0.0) ? theta + log2(P) + 2.0 * kap * dz * y0 : -INFINITY;
-  if (PASS == 0) {
-    if (ov) {
-      const double Ru = ys[(size_t)line * Bk * 2];
-      ((GDblW*)md.sepT)[(size_t)o * Ak + line] = T - kap * (z * z) - kap * (Ru * Ru);
-    }
-  } else {
-    const int x = o * Bj + line;
-    if (ov && x < nj) ((GDblW*)md.mfull)[x] = T > -INFINITY ? kLn2 * (T - kap * (z * z)) - ck : -INFINITY;
   }
 }
 #undef GMOT_FMAC_ROWBCAST_S
@@ -1892,6 +1896,7 @@ __global__ __launch_bounds__(kBlock) void k_pairs(const EdgeDesc* edges, const P
   __shared__ double sh[4];
   __shared__ double s_b[kChunk];
   __shared__ double s_y[kChunk * 3];
+  __shared__ double s_g[kChunk];
   const PairItem it = items[blockIdx.x];
   const EdgeDesc ed = edges[it.edge];
   const int x = it.row0 + threadIdx.x;
@@ -1899,6 +1904,7 @@ __global__ __launch_bounds__(kBlock) void k_pairs(const EdgeDesc* edges, const P
   const bool sq = ed.cost_kind == 0;
   const double ca = ed.c_a ? *ed.c_a : 0.0;
   const double cb = ed.c_b ? *ed.c_b : 0.0;
+  const double inv_eps = 1.0 / ed.eps;
   double ax = -INFINITY, lax = 0.0, xp[3] = {0.0, 0.0, 0.0};
   if (vx) {
     lax = ed.lam_a[x] - ca;
@@ -1913,6 +1919,7 @@ __global__ __launch_bounds__(kBlock) void k_pairs(const EdgeDesc* edges, const P
     if (threadIdx.x < cn) {
       const int y = it.col0 + c0 + threadIdx.x;
       s_b[threadIdx.x] = ed.lam_b[y] - cb;
+      s_g[threadIdx.x] = ed.lg_b[y];
       if (sq)
         for (int d = 0; d < ed.dim; ++d) s_y[threadIdx.x * 3 + d] = ed.supp_b[(size_t)y * ed.dim + d];
     }
@@ -1930,13 +1937,12 @@ __global__ __launch_bounds__(kBlock) void k_pairs(const EdgeDesc* edges, const P
         } else {
           C = (double)ed.cost[(size_t)x * ed.n_b + y];
         }
-        const double lgb = ed.lg_b[y];
         const double lb = s_b[c];
-        const double logB = ax + lb + lgb - C / ed.eps;
-        const double B = exp(logB);
+        const double ce = C * inv_eps;
+        const double B = exp(ax + lb + s_g[c] - ce);
         if (B > 0.0) {
           sT += C * B;
-          sH += B * (lax + lb - C / ed.eps - 1.0);
+          sH += B * (lax + lb - ce - 1.0);
           sM += B;
         }
       }
@@ -2079,8 +2085,7 @@ hipError_t launch_msg_grid(const Tables& tb, int n_items, int rows_per_lane, hip
 
 hipError_t launch_sep_horner(const Tables& tb, int pass, int n_tasks, hipStream_t s) {
   if (n_tasks <= 0) return hipSuccess;
-  if (n_tasks % 4 != 0) return hipErrorInvalidValue;  // whole waves of four tasks
-  const int blocks = (n_tasks / 4 + kSepWaves - 1) / kSepWaves;
+  const int blocks = (n_tasks + kSepWaves - 1) / kSepWaves;
   if (pass == 0) {
     hipLaunchKernelGGL((k_sep_horner<0>), dim3(blocks + tb.n_fin), dim3(64 * kSepWaves), 0, s, tb, n_tasks);
   } else {

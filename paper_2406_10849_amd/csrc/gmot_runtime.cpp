@@ -772,16 +772,15 @@ static int build_plan(gmot_ctx* ctx, const std::vector<gmot_problem*>& probs, No
           pl->node_sep[c].push_back(r);
         }
         if (dk == kSepHGroup) {
-          // 16 outputs of one line per task, each message padded to whole waves
+          // one wave per (64 outputs, kSepTaskLines lines) of each message and pass
           std::array<int, 4> r{(int)pl->sep_tasks[c][0].size(), 0, (int)pl->sep_tasks[c][1].size(), 0};
           for (int m = qn.msg0; m < qn.msg0 + qn.deg; ++m)
             for (int pass = 0; pass < 2; ++pass) {
               const MsgDesc& md = pl->msgs[m];
               const int lines = pass == 0 ? md.rows_src : md.cols_dst, outs = pass == 0 ? md.cols_dst : md.rows_dst;
               auto& tk = pl->sep_tasks[c][pass];
-              for (int l = 0; l < lines; ++l)
-                for (int o0 = 0; o0 < outs; o0 += 16) tk.push_back({m, l, o0, q.inst});
-              while (tk.size() % 4 != 0) tk.push_back({m, 0, outs, q.inst});
+              for (int o0 = 0; o0 < outs; o0 += 64)
+                for (int l = 0; l < lines; l += kSepTaskLines) tk.push_back({m, l, o0, q.inst});
             }
           r[1] = (int)pl->sep_tasks[c][0].size() - r[0];
           r[3] = (int)pl->sep_tasks[c][1].size() - r[2];
@@ -1096,7 +1095,6 @@ static int compact_lists(Plan* pl, const std::vector<char>& running, int* count)
       if (keep(it.inst)) L.sep2[c].push_back(it);
     o_s[c] = take(sizeof(SepItem) * L.sep[c].size());
     o_s2[c] = take(sizeof(SepItem) * L.sep2[c].size());
-    // whole waves: a wave's four tasks share one instance
     for (int q = 0; q < 2; ++q) {
       for (const SepTask& tk : pl->sep_tasks[c][q])
         if (keep(tk.inst)) L.sept[c][q].push_back(tk);
@@ -1622,9 +1620,10 @@ static int upload(const gmot_tree_desc* d, gmot_problem* p) {
   // Separable passes by Horner's rule (k_sep_horner): every grid's row and
   // column coordinate lists uniform (as for the one-dimensional grids), and for
   // every message (source k, destination j) and pass, 2 log2e / eps * (half
-  // the span of any 16 consecutive outputs) * |h of the inputs| * W <=
+  // the span of the outputs of a wave) * |h of the inputs| * W <=
   // kGridRange, W the largest power of an output's ratio the pass forms
-  // (16 g - 1 for inputs in g <= 4 groups of 16, max(inputs - 1, 64) beyond).
+  // (16 g - 1 for inputs in g <= 4 groups of 16, max(inputs - 1, 64) beyond);
+  // the span is that of any 64 consecutive outputs (one wave's).
   p->sep_h = false;
   if (p->sep && !std::getenv("GMOT_NO_GRID")) {
     bool all = true;
@@ -1637,11 +1636,11 @@ static int upload(const gmot_tree_desc* d, gmot_problem* p) {
         if (!std::isfinite(L[i]) || std::fabs(L[i] - (L[0] + (double)i * *h)) > tol) return false;
       return true;
     };
-    auto half16 = [](const std::vector<double>& L) {
+    auto half64 = [](const std::vector<double>& L) {
       double hs = 0.0;
-      for (size_t o0 = 0; o0 < L.size(); o0 += 16) {
+      for (size_t o0 = 0; o0 < L.size(); o0 += 64) {
         double lo = L[o0], hi = L[o0];
-        for (size_t i = o0; i < std::min(L.size(), o0 + 16); ++i) {
+        for (size_t i = o0; i < std::min(L.size(), o0 + 64); ++i) {
           lo = std::min(lo, L[i]);
           hi = std::max(hi, L[i]);
         }
@@ -1656,8 +1655,8 @@ static int upload(const gmot_tree_desc* d, gmot_problem* p) {
       for (int r = 0; r < A; ++r) R[r] = X[2 * (size_t)r * B];
       for (int c = 0; c < B; ++c) Cc[c] = X[2 * c + 1];
       all = uniform(R, &hR[j]) && uniform(Cc, &hC[j]);
-      halfR[j] = half16(R);
-      halfC[j] = half16(Cc);
+      halfR[j] = half64(R);
+      halfC[j] = half64(Cc);
     }
     auto W = [](int inner) { return inner > 64 ? std::max(inner - 1, 64) : 16 * ((inner + 15) / 16) - 1; };
     const double two_kap = 2.0 * kLog2e / p->eps;
