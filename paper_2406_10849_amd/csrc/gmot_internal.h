@@ -95,10 +95,12 @@ constexpr int kSepMaxOut = 2048;    // outputs per separable-pass block (8 per t
 constexpr int kSepStage = 4608;     // staged values per separable-pass block (36 KB) at most
 // Messages from uniform one-dimensional grids sum a polynomial in each row's
 // ratio rho; the host admits a message only when every power of rho it takes
-// lies within 2^(+-kGridRange).  With the column values v_j <= 2^512 the sums
-// stay below 2^1003, and a v_j lost below the FP64 range (2^-1074) is a term
-// below 2^(-1074 + 2 kGridRange) = 2^-114 of the row's largest one.
-constexpr double kGridRange = 480.0;
+// lies within 2^(+-kGridRange).  With the column values v_j <= 2^kGridSlack
+// (128) the sums stay below 2^(11 + 128 + 850) = 2^989, and a v_j lost below
+// the FP64 range (2^-1074) is a term below 2^(-1074 + kGridRange) = 2^-224 of
+// the row's largest one (at least 2^-G when rho < 1, at least 1 otherwise).
+constexpr double kGridRange = 850.0;
+constexpr double kGridSlack = 128.0;  // the kernels keep v_j = 2^(C(j) - theta) <= 2^kGridSlack
 // Staged row stride and length of a separable pass with `inner` terms per output.
 __host__ __device__ inline int sep_row_stride(int inner) { return (inner + 1) | 1; }
 __host__ __device__ inline int sep_inner_even(int inner) { return (inner + 1) & ~1; }

@@ -1447,13 +1447,12 @@ __global__ __launch_bounds__(64 * kSepWaves) void k_node_sep(Tables tb, int n_ti
 // The host takes this path only when 2 kap * (half the span of any 64 R rows)
 // * |h| * max(n_src - 1, 64) <= kGridRange binades, so every power of rho
 // formed here (up to rho^64) or summed (rho^j, j < n_src) stays within
-// 2^(+-kGridRange): with FP64 no term that matters underflows and no sum
-// overflows.  Every step is FP64 (v and rho from exp2 in FP64), so the
+// 2^(+-kGridRange): with v_j <= 2^kGridSlack in FP64 no term that matters
+// underflows and no sum overflows.  Every step is FP64 (v and rho from exp2 in FP64), so the
 // messages agree with the FP64 node kernel to rounding.  The update of each
 // node follows in k_node_sep from the merged messages in mfull.
 // ---------------------------------------------------------------------------
 constexpr int kGridWaves = 4;          // waves (items) per block
-constexpr double kGridSlack = 512.0;   // v_j <= 2^kGridSlack
 
 // acc += a[lane q of acc's 16-lane row] * b (double-precision DPP row broadcast)
 #define GMOT_FMAC_ROWBCAST(acc, a, b, Q) \

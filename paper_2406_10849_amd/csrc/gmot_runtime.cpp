@@ -1858,6 +1858,9 @@ static int autotune(gmot_ctx* ctx, const std::vector<gmot_problem*>& probs, Plan
       delete best;
       return rc;
     }
+    if (std::getenv("GMOT_AUTOTUNE_LOG"))  // diagnostic: every candidate's time
+      std::fprintf(stderr, "autotune W=%d R=%d H=%d grid=%d: %.4f ms per half-sweep\n", cand.W, cand.R, cand.H,
+                   cand.G, ms);
     // a later candidate must be 3% faster to replace an earlier one, so
     // near-equal shapes do not flip from run to run
     if (ms < best_ms * kAutotuneMargin) {

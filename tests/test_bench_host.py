@@ -77,6 +77,20 @@ def test_group_rooflines():
     assert ex["k_node<explicit>"]["unit"] == "GB/s" and ex["k_node<explicit>"]["achieved"] == pytest.approx(4000.0)
 
 
+def test_uniform_grid_groups_price_one_fma_per_pair():
+    """Groups 5 and 6 (the Horner kernels on uniform grids) take one FP64 FMA
+    per pair: 1024 SIMDs x 2.4 GHz x 64 lanes / 4 cycles = 39.3e12 pairs/s."""
+    assert bench.fma_peak_gpairs() == pytest.approx(1024 * 2.4e9 * 64 / 4 / 1e9)
+    st = {"msg_launches": 4, "group_ms": [0, 0, 0, 0, 0, 0.4, 0.2], "group_pairs": [0, 0, 0, 0, 0, 4.0e9, 2.0e8]}
+    g = bench.group_rooflines(st)
+    assert set(g) == {bench.GRID_GROUP_NAME, "k_sep_horner+k_node_sep"}
+    grid = g[bench.GRID_GROUP_NAME]
+    assert grid["peak"] == pytest.approx(bench.fma_peak_gpairs())
+    assert grid["achieved"] == pytest.approx(4.0e9 / 0.4e-3 / 1e9)
+    assert grid["ms_per_stage"] == pytest.approx(0.1) and grid["pairs_per_stage"] == pytest.approx(1.0e9)
+    assert g["k_sep_horner+k_node_sep"]["peak"] == pytest.approx(bench.fma_peak_gpairs())
+
+
 def test_rocprof_summaries(tmp_path):
     st = tmp_path / "k_stats.csv"
     st.write_text("Name,Calls,TotalDurationNs,AverageNs,Percentage,MinNs,MaxNs,StdDev\n"
@@ -139,7 +153,8 @@ def test_files_the_gpu_runs_read_are_shipped():
     """The bench reads its HBM-traffic summaries from profiles/, the GPU tests
     read the stored references under tests/golden/; none may be left out of
     the tree copied to the GPU machine."""
-    paths = [os.path.relpath(bench.TRAFFIC_FILE, ROOT)]
+    paths = [os.path.relpath(f, ROOT) for f in (bench.TRAFFIC_FILE, bench.GRID_TRAFFIC_FILE,
+                                                  bench.GRID_CHAIN_TRAFFIC_FILE, bench.CHAIN_TRAFFIC_FILE)]
     for d in ("profiles", os.path.join("tests", "golden")):
         paths += [os.path.join(d, f) for f in os.listdir(os.path.join(ROOT, d))]
     for rel in paths:
