@@ -953,18 +953,46 @@ static bool valid_shape(const NodeShape& s) {
   return (s.W == 2 || s.W == 4 || s.W == 8 || s.W == 16) && (s.R == 1 || s.R == 2) && (s.H == 1 || s.H == 2);
 }
 
+// Without a tuned choice, the uniform-grid kernels serve a plan whose node
+// stage gives them at least kGridMinWaves message waves (one per SIMD of the
+// device); a smaller plan fills the device better through the node kernel's
+// column ranges (a single star, the 32-node chain).
+constexpr int64_t kGridMinWaves = 1024;
+
+static int grid_default(const std::vector<gmot_problem*>& probs) {
+  int64_t waves = 0;  // both classes' message waves, halved below
+  for (const gmot_problem* p : probs) {
+    if (!p->grid && !p->sep_h) continue;
+    for (int e = 0; e < p->E; ++e)
+      for (int d = 0; d < 2; ++d) {
+        const int k = p->edges[2 * e + d], j = p->edges[2 * e + 1 - d];  // message k -> j
+        if (p->grid) {
+          waves += ceil_div(p->sizes[j], 64 * p->grid_rows_lane);
+        } else {
+          const int rows_k = p->grid_rows(k), cols_j = p->grid_cols[j];
+          waves += ceil_div(rows_k, kSepTaskLines) * ceil_div(cols_j, 64) +
+                   ceil_div(cols_j, kSepTaskLines) * ceil_div(p->grid_rows(j), 64);
+        }
+      }
+  }
+  return waves / 2 >= kGridMinWaves ? 1 : 0;
+}
+
 // Node-kernel block shape: a tuned choice cached in the context for these
-// shapes, else the default; GMOT_NODE_SHAPE="W,R" or "W,R,H" (W in 2, 4, 8,
-// 16; R in 1, 2; H in 1, 2) overrides both.
+// shapes, else the default (with the uniform-grid kernels as grid_default
+// decides); GMOT_NODE_SHAPE="W,R" or "W,R,H" (W in 2, 4, 8, 16; R in 1, 2; H
+// in 1, 2) overrides the block shape and GMOT_GRID=0 or 1 the grid kernels.
 static NodeShape choose_shape(gmot_ctx* ctx, const std::vector<gmot_problem*>& probs) {
   NodeShape sh = kDefaultShape;
   auto it = ctx->tuned.find(shape_key(probs));
   if (it != ctx->tuned.end()) sh = it->second;
+  else sh.G = grid_default(probs);
   if (const char* v = std::getenv("GMOT_NODE_SHAPE")) {
-    NodeShape e{0, 0, 1};
+    NodeShape e{0, 0, 1, sh.G};
     const int got = std::sscanf(v, "%d,%d,%d", &e.W, &e.R, &e.H);
     if (got >= 2 && valid_shape(e)) sh = e;
   }
+  if (const char* v = std::getenv("GMOT_GRID")) sh.G = std::atoi(v) != 0 ? 1 : 0;
   return sh;
 }
 

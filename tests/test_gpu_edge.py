@@ -47,11 +47,10 @@ def test_more_than_128_tile_records(ctx, shape, path, monkeypatch):
     """A free node of 4200 points has 132 records of 32 rows (8,1,2 and
     2,1,2) or 66 of 64 rows (16,2): every record loop runs more than one round
     per lane.  Fixed-step iterates and in-loop stopping sums against the oracle,
-    FP64 and FP32 core, on the grid kernel and on the general node kernel
-    (GMOT_NO_GRID=1)."""
+    FP64 and FP32 core, on the grid kernel (GMOT_GRID=1) and on the general
+    node kernel (GMOT_GRID=0)."""
     monkeypatch.setenv("GMOT_NODE_SHAPE", shape)
-    if path == "general":
-        monkeypatch.setenv("GMOT_NO_GRID", "1")
+    monkeypatch.setenv("GMOT_GRID", "1" if path == "grid" else "0")
     p = make_tree([(0, 1), (1, 2), (1, 3)], [700, 4200, 900, 4200], [1, 0, 1, 1], dim=1, eps=0.02,
                   instance=70, support="grid", marginals="gm")
     steps = 8

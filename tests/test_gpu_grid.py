@@ -2,9 +2,11 @@
 eq. q as a polynomial in each row's ratio, summed by Horner's rule), through
 the C ABI (needs an MI355X).
 
-Every D = 1 problem whose supports are uniform grids takes this path by
-default; GMOT_NO_GRID=1 (read at problem creation) sends it to the general
-node kernel instead.  The grid path sums in FP64 in both precisions, so after
+A D = 1 problem whose supports are uniform grids takes this path when the
+autotuner finds it faster, or untuned when its node stage has at least 1024
+message waves; GMOT_GRID=1 forces it for a plan (these tests) and
+GMOT_NO_GRID=1 (read at problem creation) keeps the general node kernel.
+The grid path sums in FP64 in both precisions, so after
 the same half-sweeps its potentials match the oracle to 1e-9 of their size,
 couplings to 1e-9 and the dual to 1e-9 of the objective scale, FP32-core mode
 included; converged solves are re-measured by the oracle.  Problems outside
@@ -29,6 +31,13 @@ SEP_HORNER_GROUP = 6  # separable passes by Horner's rule
 def ctx():
     from paper_2406_10849_amd import Context
     return Context(0)
+
+
+@pytest.fixture(autouse=True)
+def grid_on(monkeypatch):
+    """These problems are small: without GMOT_GRID=1 the untuned default keeps
+    the node kernel for plans of fewer than 1024 message waves."""
+    monkeypatch.setenv("GMOT_GRID", "1")
 
 
 def gpu_problem(ctx, p):

@@ -60,9 +60,8 @@ def test_config1_star_fp64_1000_half_sweeps(ctx):
 @pytest.mark.parametrize("precision", ["fp64", "fp32core"])
 def test_small_chain_fixed_steps(ctx, precision, path, monkeypatch):
     """Both message paths of uniform one-dimensional grids: the grid kernel
-    (default) and the general node kernel (GMOT_NO_GRID=1)."""
-    if path == "general":
-        monkeypatch.setenv("GMOT_NO_GRID", "1")
+    (GMOT_GRID=1) and the general node kernel (GMOT_GRID=0)."""
+    monkeypatch.setenv("GMOT_GRID", "1" if path == "grid" else "0")
     p = make_chain(n_nodes=12, n=200, eps=1e-3)
     g = gpu_problem(ctx, p)
     steps = 40
@@ -162,8 +161,7 @@ def test_batch_with_mixed_parities(ctx):
 
 @pytest.mark.parametrize("path", ["grid", "general"])
 def test_timing_stats_count_working_half_sweeps(ctx, path, monkeypatch):
-    if path == "general":
-        monkeypatch.setenv("GMOT_NO_GRID", "1")
+    monkeypatch.setenv("GMOT_GRID", "1" if path == "grid" else "0")
     p = make_chain(n_nodes=10, n=150, eps=1e-2)
     g = gpu_problem(ctx, p)
     g.stats(reset=True)
@@ -173,8 +171,8 @@ def test_timing_stats_count_working_half_sweeps(ctx, path, monkeypatch):
     assert st["msg_launches"] == r["t"]          # half-sweeps 1..t computed messages
     assert abs(st["msg_pairs"] - r["t"] * p.pairs_per_tstep()) < 0.5
     assert st["msg_ms"] > 0
-    # one kernel group does all of the stage: the uniform-grid group (5) by
-    # default, the D = 1 node-kernel group (1) with GMOT_NO_GRID
+    # one kernel group does all of the stage: the uniform-grid group (5) with
+    # GMOT_GRID=1, the D = 1 node-kernel group (1) with GMOT_GRID=0
     grp = 5 if path == "grid" else 1
     assert st["group_pairs"][grp] == st["msg_pairs"] and sum(st["group_pairs"]) == st["msg_pairs"]
     assert st["group_ms"][grp] > 0

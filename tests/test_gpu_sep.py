@@ -46,10 +46,9 @@ def _cases():
 @pytest.mark.parametrize("case", [0, 1, 2])
 def test_separable_iterates_match_oracle_and_general_kernel(ctx, case, path, monkeypatch):
     """Both separable paths: Horner's rule on uniform grids (k_sep_horner, FP64
-    in both precisions, the default) and the shifted exponential sums
-    (k_sep_pass, GMOT_NO_GRID=1)."""
-    if path == "pass":
-        monkeypatch.setenv("GMOT_NO_GRID", "1")
+    in both precisions; GMOT_GRID=1) and the shifted exponential sums
+    (k_sep_pass; GMOT_GRID=0)."""
+    monkeypatch.setenv("GMOT_GRID", "1" if path == "horner" else "0")
     p = _cases()[case]
     # which separable kernel group the instance takes (5 x 6 grids at eps = 5e-3
     # lie outside the Horner passes' range and take k_sep_pass either way)
