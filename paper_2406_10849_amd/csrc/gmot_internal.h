@@ -245,13 +245,14 @@ hipError_t launch_sep_pass(const Tables& tb, int pass, int n_items, size_t lds_b
 hipError_t launch_node_sep(const Tables& tb, int n_tiles, hipStream_t s);
 // separable pass `pass` on uniform grids over the n_tasks tasks of
 // tb.sep_tasks (pass 0, carrying tb.n_fin finalise blocks) or tb.sep_tasks2
-// (pass 1), one wave each
-hipError_t launch_sep_horner(const Tables& tb, int pass, int n_tasks, hipStream_t s);
+// (pass 1), one wave each; eval as for launch_msg_grid
+hipError_t launch_sep_horner(const Tables& tb, int pass, int n_tasks, bool eval, hipStream_t s);
 // messages on uniform one-dimensional source grids: one wave per tile item of
 // tb.tiles (a message, msg0, for 64 * rows_per_lane destination rows from
 // row0; rows_per_lane 1 or 2), writing mfull; the first tb.n_fin blocks carry
-// the finalise step
-hipError_t launch_msg_grid(const Tables& tb, int n_items, int rows_per_lane, hipStream_t s);
+// the finalise step.  eval: the FP64 evaluation pass (committed slots from
+// tb.inst_slot, every item, the message as column split 0 of md.partial)
+hipError_t launch_msg_grid(const Tables& tb, int n_items, int rows_per_lane, bool eval, hipStream_t s);
 hipError_t launch_node_eval(const Tables& tb, int n_nodes, int slot, hipStream_t s);
 // node-sequential update of node item `node_item` of tb's class from the
 // message partials k_msg wrote, into potential slot `slot` (one block)

@@ -1458,11 +1458,15 @@ constexpr int kGridWaves = 4;          // waves (items) per block
 #define GMOT_FMAC_ROWBCAST(acc, a, b, Q) \
   asm("v_fmac_f64_dpp %0, %1, %2 row_newbcast:" #Q " row_mask:0xf bank_mask:0xf" : "+v"(acc) : "v"(a), "v"(b))
 
-// two rows per lane asks for four waves per SIMD (at most 128 VGPRs)
-template <int R>
+// two rows per lane asks for four waves per SIMD (at most 128 VGPRs).
+// EVAL: the FP64 evaluation pass -- every item regardless of its instance's
+// loop state, the source's committed slot from tb.inst_slot and its stored
+// normaliser, and the message written as column split 0 of the evaluation's
+// partials (the other splits empty), as k_msg leaves them.
+template <int R, bool EVAL>
 __global__ __launch_bounds__(64 * kGridWaves, R == 2 ? 4 : 1) void k_msg_grid(Tables tb, int n_items) {
   __shared__ double s_v[kGridWaves][64];
-  if ((int)blockIdx.x < tb.n_fin) {
+  if (!EVAL && (int)blockIdx.x < tb.n_fin) {
     // the finalise step of the previous launch's half-sweep, one block per instance
     __shared__ double sh_fin[kFinParts][2];
     fin_instance<kGridWaves>(tb, tb.fin_nodes, tb.fin_colour, tb.inst + blockIdx.x, true, sh_fin);
@@ -1473,11 +1477,14 @@ __global__ __launch_bounds__(64 * kGridWaves, R == 2 ? 4 : 1) void k_msg_grid(Ta
   if (gw >= n_items) return;
   const TileItem ti = tb.tiles[gw];
   const InstState* st = tb.inst + ti.inst;
-  const long long t = st->vt[tb.colour];
-  if (st->vdone[tb.colour] != 0 || t < st->t_first || ((t & 1) == 1) != (tb.colour == 0)) return;
+  long long t = 0;
+  if (!EVAL) {
+    t = st->vt[tb.colour];
+    if (st->vdone[tb.colour] != 0 || t < st->t_first || ((t & 1) == 1) != (tb.colour == 0)) return;
+  }
   const CMsg& md = *(const CMsg*)(tb.msgs + ti.msg0);
   const int n = md.n_dst, ns = md.n_src;
-  const int src_slot = (int)((t >> 1) % kSlots);
+  const int src_slot = EVAL ? tb.inst_slot[2 * ti.inst + (1 - tb.colour)] : (int)((t >> 1) % kSlots);
   const GDbl* __restrict__ lam = (const GDbl*)md.lam_src[src_slot];
   const GDbl* __restrict__ lg = (const GDbl*)md.lg_src;
   const GDbl* __restrict__ ys = (const GDbl*)md.supp_src;
@@ -1569,10 +1576,11 @@ __global__ __launch_bounds__(64 * kGridWaves, R == 2 ? 4 : 1) void k_msg_grid(Ta
       P[r] = fma(P[r], r64[r], fma(fma(fma(S[r][3], r16[r], S[r][2]), r16[r], S[r][1]), r16[r], S[r][0]));
   }
   // the source's normaliser c_k, from its tile records when its last update
-  // (half-sweep t - 1) ran in this run, else its stored value
+  // (half-sweep t - 1) ran in this run, else (and in the evaluation) its
+  // stored value
   double ck = 0.0;
   if (md.src_free) {
-    if (t - 1 >= st->t_first) {
+    if (!EVAL && t - 1 >= st->t_first) {
       const GDbl* __restrict__ srec = (const GDbl*)md.src_tpart;
       const int src_deg = md.src_deg, src_tiles = md.src_tiles;
       const int s_stride = src_deg + kRecExtra, s_tile = min(lane, src_tiles - 1);
@@ -1586,7 +1594,16 @@ __global__ __launch_bounds__(64 * kGridWaves, R == 2 ? 4 : 1) void k_msg_grid(Ta
   for (int r = 0; r < R; ++r)
     if (x[r] < n) {
       const double e = theta + fma(2.0 * kap * dx[r], y0, -kap * xv[r] * xv[r]);
-      ((GDblW*)md.mfull)[x[r]] = (theta > -INFINITY && P[r] > 0.0) ? kLn2 * (e + log2(P[r])) - ck : -INFINITY;
+      const bool fin = theta > -INFINITY && P[r] > 0.0;
+      if (EVAL) {
+        // log2 of the sum without the -|x|^2 / eps the merge subtracts, c_k included
+        const double l2 = fin ? e + log2(P[r]) + kap * xv[r] * xv[r] - kLog2e * ck : -INFINITY;
+        double2* __restrict__ part = md.partial + (size_t)x[r] * md.ns;
+        part[0] = make_double2(l2, fin ? 1.0 : 0.0);
+        for (int sp = 1; sp < md.ns; ++sp) part[sp] = make_double2(-INFINITY, 0.0);
+      } else {
+        ((GDblW*)md.mfull)[x[r]] = fin ? kLn2 * (e + log2(P[r])) - ck : -INFINITY;
+      }
     }
 }
 #undef GMOT_FMAC_ROWBCAST
@@ -1637,11 +1654,14 @@ __device__ inline double horner_tile(const double* vc, const double* pw, double 
   return fma(fma(fma(S[3], r16, S[2]), r16, S[1]), r16, S[0]);
 }
 
-template <int PASS>
+// EVAL: the FP64 evaluation pass (as for k_msg_grid): every task, the
+// source's committed slot and stored normaliser, the message as split 0 of
+// the evaluation's partials.
+template <int PASS, bool EVAL>
 __global__ __launch_bounds__(64 * kSepWaves) void k_sep_horner(Tables tb, int n_tasks) {
   __shared__ double s_v[kSepWaves][64];
   int bid = (int)blockIdx.x;
-  if (PASS == 0) {
+  if (PASS == 0 && !EVAL) {
     if (bid < tb.n_fin) {
       // the finalise step of the previous launch's half-sweep, one block per instance
       __shared__ double sh_fin[kFinParts][2];
@@ -1655,15 +1675,18 @@ __global__ __launch_bounds__(64 * kSepWaves) void k_sep_horner(Tables tb, int n_
   if (w >= n_tasks) return;
   const SepTask tk = (PASS == 0 ? tb.sep_tasks : tb.sep_tasks2)[w];
   const InstState* st = tb.inst + tk.inst;
-  const long long t = st->vt[tb.colour];
-  if (st->vdone[tb.colour] != 0 || t < st->t_first || ((t & 1) == 1) != (tb.colour == 0)) return;
+  long long t = 0;
+  if (!EVAL) {
+    t = st->vt[tb.colour];
+    if (st->vdone[tb.colour] != 0 || t < st->t_first || ((t & 1) == 1) != (tb.colour == 0)) return;
+  }
   const CMsg& md = *(const CMsg*)(tb.msgs + tk.msg);
   const int Ak = md.rows_src, Bk = md.cols_src, Bj = md.cols_dst, Aj = md.rows_dst;
   const int nk = md.n_src, nj = md.n_dst;
   const int outs = PASS == 0 ? Bj : Aj;     // outputs per line
   const int inner = PASS == 0 ? Bk : Ak;    // inputs per output
   const int lines = PASS == 0 ? Ak : Bj;
-  const int src_slot = (int)((t >> 1) % kSlots);
+  const int src_slot = EVAL ? tb.inst_slot[2 * tk.inst + (1 - tb.colour)] : (int)((t >> 1) % kSlots);
   const GDbl* __restrict__ lam = (const GDbl*)md.lam_src[src_slot];
   const GDbl* __restrict__ lg = (const GDbl*)md.lg_src;
   const GDbl* __restrict__ ys = (const GDbl*)md.supp_src;
@@ -1689,10 +1712,10 @@ __global__ __launch_bounds__(64 * kSepWaves) void k_sep_horner(Tables tb, int n_
   const double czc = 2.0 * kap * zc;
   const int nt = (inner + 63) / 64;
   const int ng = nt > 1 ? 4 : (inner + 15) / 16;  // 16-input groups of a tile
-  // pass 1: the source's normaliser c_k
+  // pass 1: the source's normaliser c_k (its stored value in the evaluation)
   double ck = 0.0;
   if (PASS == 1 && md.src_free) {
-    if (t - 1 >= st->t_first) {
+    if (!EVAL && t - 1 >= st->t_first) {
       const GDbl* __restrict__ srec = (const GDbl*)md.src_tpart;
       const int src_deg = md.src_deg, src_tiles = md.src_tiles;
       const int s_stride = src_deg + kRecExtra, s_tile = min(lane, src_tiles - 1);
@@ -1754,7 +1777,21 @@ __global__ __launch_bounds__(64 * kSepWaves) void k_sep_horner(Tables tb, int n_
       }
     } else {
       const int x = o * Bj + line;
-      if (ov && x < nj) ((GDblW*)md.mfull)[x] = T > -INFINITY ? kLn2 * (T - kap * (z * z)) - ck : -INFINITY;
+      if (ov && x < nj) {
+        if (EVAL) {
+          // log2 of the sum without the -|x|^2 / eps the merge subtracts
+          // (here the -kap C_j[q]^2 of the first pass is |x|^2's second part)
+          const double l2 = T > -INFINITY ? T - kap * (z * z) + kap * (xs[(size_t)x * 2] * xs[(size_t)x * 2] +
+                                                                      xs[(size_t)x * 2 + 1] * xs[(size_t)x * 2 + 1]) -
+                                                kLog2e * ck
+                                          : -INFINITY;
+          double2* __restrict__ part = md.partial + (size_t)x * md.ns;
+          part[0] = make_double2(l2, T > -INFINITY ? 1.0 : 0.0);
+          for (int sp = 1; sp < md.ns; ++sp) part[sp] = make_double2(-INFINITY, 0.0);
+        } else {
+          ((GDblW*)md.mfull)[x] = T > -INFINITY ? kLn2 * (T - kap * (z * z)) - ck : -INFINITY;
+        }
+      }
     }
   }
 }
@@ -2073,23 +2110,33 @@ hipError_t launch_node_sep(const Tables& tb, int n_tiles, hipStream_t s) {
   return hipGetLastError();
 }
 
-hipError_t launch_msg_grid(const Tables& tb, int n_items, int rows_per_lane, hipStream_t s) {
+hipError_t launch_msg_grid(const Tables& tb, int n_items, int rows_per_lane, bool eval, hipStream_t s) {
   if (n_items <= 0) return hipSuccess;
-  const dim3 grid((n_items + kGridWaves - 1) / kGridWaves + tb.n_fin);
-  if (rows_per_lane == 1) hipLaunchKernelGGL(k_msg_grid<1>, grid, dim3(64 * kGridWaves), 0, s, tb, n_items);
-  else if (rows_per_lane == 2) hipLaunchKernelGGL(k_msg_grid<2>, grid, dim3(64 * kGridWaves), 0, s, tb, n_items);
-  else return hipErrorInvalidValue;
+  if (eval && tb.n_fin != 0) return hipErrorInvalidValue;
+  const dim3 grid((n_items + kGridWaves - 1) / kGridWaves + tb.n_fin), block(64 * kGridWaves);
+  if (rows_per_lane == 1) {
+    if (eval) hipLaunchKernelGGL((k_msg_grid<1, true>), grid, block, 0, s, tb, n_items);
+    else hipLaunchKernelGGL((k_msg_grid<1, false>), grid, block, 0, s, tb, n_items);
+  } else if (rows_per_lane == 2) {
+    if (eval) hipLaunchKernelGGL((k_msg_grid<2, true>), grid, block, 0, s, tb, n_items);
+    else hipLaunchKernelGGL((k_msg_grid<2, false>), grid, block, 0, s, tb, n_items);
+  } else {
+    return hipErrorInvalidValue;
+  }
   return hipGetLastError();
 }
 
-hipError_t launch_sep_horner(const Tables& tb, int pass, int n_tasks, hipStream_t s) {
+hipError_t launch_sep_horner(const Tables& tb, int pass, int n_tasks, bool eval, hipStream_t s) {
   if (n_tasks <= 0) return hipSuccess;
   const int blocks = (n_tasks + kSepWaves - 1) / kSepWaves;
+  if ((pass == 1 || eval) && tb.n_fin != 0) return hipErrorInvalidValue;
+  const dim3 block(64 * kSepWaves);
   if (pass == 0) {
-    hipLaunchKernelGGL((k_sep_horner<0>), dim3(blocks + tb.n_fin), dim3(64 * kSepWaves), 0, s, tb, n_tasks);
+    if (eval) hipLaunchKernelGGL((k_sep_horner<0, true>), dim3(blocks), block, 0, s, tb, n_tasks);
+    else hipLaunchKernelGGL((k_sep_horner<0, false>), dim3(blocks + tb.n_fin), block, 0, s, tb, n_tasks);
   } else {
-    if (tb.n_fin != 0) return hipErrorInvalidValue;
-    hipLaunchKernelGGL((k_sep_horner<1>), dim3(blocks), dim3(64 * kSepWaves), 0, s, tb, n_tasks);
+    if (eval) hipLaunchKernelGGL((k_sep_horner<1, true>), dim3(blocks), block, 0, s, tb, n_tasks);
+    else hipLaunchKernelGGL((k_sep_horner<1, false>), dim3(blocks), block, 0, s, tb, n_tasks);
   }
   return hipGetLastError();
 }

@@ -171,6 +171,9 @@ struct Plan {
   std::vector<K1Item> items[2][4];  // [class][0 = explicit, 1..3 = dim]
   std::vector<std::pair<int, int>> msg_items[2][4];  // per message: (first item, item count)
   std::vector<std::pair<int, int>> msg_item_range;    // per plan message: (first item, count) in its (class, group)
+  // items of the messages the node kernel's groups evaluate come first; the
+  // uniform-grid groups' messages (after them) are evaluated by their own kernels
+  int items_general[2][4] = {};
   std::vector<NodeItem> nodes[2];
   std::vector<InstState> inst;
   int total_nodes = 0;
@@ -362,7 +365,7 @@ struct Plan {
           tb.fin_nodes = d_nodes[1 - c];
           *fin_pending = false;
         }
-        if ((e = launch_msg_grid(tb, (int)tiles[c][g].size(), grid_R, s)) != hipSuccess) return e;
+        if ((e = launch_msg_grid(tb, (int)tiles[c][g].size(), grid_R, false, s)) != hipSuccess) return e;
         tb = tables(c, g);
         tb.tiles = d_upd_tiles[c][g];
         return launch_node_sep(tb, (int)upd_tiles[c][g].size(), s);
@@ -370,7 +373,7 @@ struct Plan {
       for (size_t i = 0; i < node_tiles[c][g].size(); ++i) {
         Tables tb = tables(c, g);
         tb.tiles += node_tiles[c][g][i].first;
-        if ((e = launch_msg_grid(tb, node_tiles[c][g][i].second, grid_R, s)) != hipSuccess) return e;
+        if ((e = launch_msg_grid(tb, node_tiles[c][g][i].second, grid_R, false, s)) != hipSuccess) return e;
         tb = tables(c, g);
         tb.tiles = d_upd_tiles[c][g] + node_upd[c][g][i].first;
         if ((e = launch_node_sep(tb, node_upd[c][g][i].second, s)) != hipSuccess) return e;
@@ -389,17 +392,17 @@ struct Plan {
           tb.fin_nodes = d_nodes[1 - c];
           *fin_pending = false;
         }
-        if ((e = launch_sep_horner(tb, 0, (int)sep_tasks[c][0].size(), s)) != hipSuccess) return e;
+        if ((e = launch_sep_horner(tb, 0, (int)sep_tasks[c][0].size(), false, s)) != hipSuccess) return e;
         tb.n_fin = 0;
-        if ((e = launch_sep_horner(tb, 1, (int)sep_tasks[c][1].size(), s)) != hipSuccess) return e;
+        if ((e = launch_sep_horner(tb, 1, (int)sep_tasks[c][1].size(), false, s)) != hipSuccess) return e;
         return launch_node_sep(tb, (int)tiles[c][g].size(), s);
       }
       for (size_t i = 0; i < node_sept[c].size(); ++i) {
         Tables tb = tables(c, g);
         tb.sep_tasks += node_sept[c][i][0];
         tb.sep_tasks2 += node_sept[c][i][2];
-        if ((e = launch_sep_horner(tb, 0, node_sept[c][i][1], s)) != hipSuccess) return e;
-        if ((e = launch_sep_horner(tb, 1, node_sept[c][i][3], s)) != hipSuccess) return e;
+        if ((e = launch_sep_horner(tb, 0, node_sept[c][i][1], false, s)) != hipSuccess) return e;
+        if ((e = launch_sep_horner(tb, 1, node_sept[c][i][3], false, s)) != hipSuccess) return e;
         tb.tiles += node_tiles[c][g][i].first;
         if ((e = launch_node_sep(tb, node_tiles[c][g][i].second, s)) != hipSuccess) return e;
       }
@@ -664,7 +667,19 @@ static int build_plan(gmot_ctx* ctx, const std::vector<gmot_problem*>& probs, No
   int64_t partial_total = 0;
   std::vector<int64_t> partial_off(pl->msgs.size());
   pl->stats = TileStats();
-  for (size_t m = 0; m < pl->msgs.size(); ++m) {
+  pl->msg_item_range.assign(pl->msgs.size(), {0, 0});
+  auto horner = [&](size_t m) { return on_grid(probs[pl->msgs[m].inst]) || on_sep_h(probs[pl->msgs[m].inst]); };
+  std::vector<size_t> order;
+  for (size_t m = 0; m < pl->msgs.size(); ++m)
+    if (!horner(m)) order.push_back(m);
+  const size_t n_general = order.size();
+  for (size_t m = 0; m < pl->msgs.size(); ++m)
+    if (horner(m)) order.push_back(m);
+  for (size_t oi = 0; oi < order.size(); ++oi) {
+    const size_t m = order[oi];
+    if (oi == n_general)
+      for (int c = 0; c < 2; ++c)
+        for (int dk = 0; dk < 4; ++dk) pl->items_general[c][dk] = (int)pl->items[c][dk].size();
     MsgDesc& md = pl->msgs[m];
     const int c = msg_class[m];
     int64_t ns = std::min<int64_t>(want_ns[c], std::max<int64_t>(1, ceil_div(md.n_src, 64)));
@@ -675,7 +690,7 @@ static int build_plan(gmot_ctx* ctx, const std::vector<gmot_problem*>& probs, No
     partial_total += ns * md.n_dst;
     const int dk = md.cost_kind == GMOT_COST_EXPLICIT ? 0 : md.dim;
     pl->msg_items[c][dk].push_back({(int)pl->items[c][dk].size(), (int)(ceil_div(md.n_dst, TM) * ns)});
-    pl->msg_item_range.push_back(pl->msg_items[c][dk].back());
+    pl->msg_item_range[m] = pl->msg_items[c][dk].back();
     for (int64_t rt = 0; rt < ceil_div(md.n_dst, TM); ++rt)
       for (int64_t s = 0; s < ns; ++s) {
         K1Item it{};
@@ -688,6 +703,9 @@ static int build_plan(gmot_ctx* ctx, const std::vector<gmot_problem*>& probs, No
         pl->items[c][dk].push_back(it);
       }
   }
+  if (n_general == order.size())
+    for (int c = 0; c < 2; ++c)
+      for (int dk = 0; dk < 4; ++dk) pl->items_general[c][dk] = (int)pl->items[c][dk].size();
   // Separable passes: a block takes as many lines of one message as fit
   // kSepStage staged values and kSepMaxOut outputs (at least one line: grid
   // sides are at most kSepMaxSide), with dynamic LDS for the largest block.
@@ -1945,11 +1963,20 @@ static int eval_messages(Plan* pl, int only_class) {
   for (size_t i = 0; i < pl->probs.size(); ++i)
     for (int c = 0; c < 2; ++c) slots[2 * i + c] = pl->probs[i]->slot_of_class(c);
   HIPCHK(hipMemcpyAsync(pl->d_inst_slot, slots.data(), sizeof(int) * slots.size(), hipMemcpyHostToDevice, s));
+  // the work lists of every instance (a solve may end on thinned ones)
+  if (!pl->select_lists(0)) return fail(GMOT_EDEVICE, "evaluation: full work lists missing");
   for (int c = 0; c < 2; ++c) {
     if (only_class >= 0 && c != only_class) continue;
     for (int dk = 0; dk < 4; ++dk)
-      if (!pl->items[c][dk].empty())
-        HIPCHK(launch_msg(pl->tables(c, dk), (int)pl->items[c][dk].size(), dk, pl->R, -1, s));
+      if (pl->items_general[c][dk] > 0)
+        HIPCHK(launch_msg(pl->tables(c, dk), pl->items_general[c][dk], dk, pl->R, -1, s));
+    // messages of the uniform-grid groups by their own kernels, in FP64
+    if (!pl->tiles[c][kGridGroup].empty())
+      HIPCHK(launch_msg_grid(pl->tables(c, kGridGroup), (int)pl->tiles[c][kGridGroup].size(), pl->grid_R, true, s));
+    if (!pl->sep_tasks[c][0].empty()) {
+      HIPCHK(launch_sep_horner(pl->tables(c, kSepHGroup), 0, (int)pl->sep_tasks[c][0].size(), true, s));
+      HIPCHK(launch_sep_horner(pl->tables(c, kSepHGroup), 1, (int)pl->sep_tasks[c][1].size(), true, s));
+    }
     HIPCHK(launch_node_eval(pl->tables(c, -1), (int)pl->nodes[c].size(), -1, s));
   }
   // the slot table is host memory read by a copy still in flight

@@ -247,3 +247,38 @@ def test_separable_horner_fallback(ctx):
     assert g.solve(tol=0.0, max_steps=6, precision="fp32core")["steps"] == 6
     lo = o.potentials()
     assert np.max(np.abs(g.potentials() - lo)) <= 1e-9 * max(1.0, float(np.max(np.abs(lo))))
+
+
+def test_evaluation_on_uniform_grids_matches_oracle(ctx):
+    """The FP64 evaluation pass takes the messages of uniform-grid plans from
+    the Horner kernels (one-dimensional and separable): on given potentials,
+    objectives, the stopping sum, node marginals and couplings agree with the
+    oracle as for the general kernel; a batch mixing both kinds (and the
+    general kernel) evaluates every instance the same way."""
+    from paper_2406_10849_amd import Batch
+    one = make_chain(n_nodes=7, n=150, eps=1e-2)
+    two = make_tree([(0, 1), (1, 2), (1, 3)], [120, 300, 70, 200], [1, 0, 1, 1], dim=2, eps=0.05, instance=150,
+                    support="grid", marginals="gm")
+    scattered = make_tree([(0, 1), (0, 2)], [60, 50, 40], [0, 1, 1], dim=1, eps=0.05, instance=151)
+    assert grid_pairs(ctx, one) > 0 and grid_pairs(ctx, two, SEP_HORNER_GROUP) > 0
+    probs = [one, two, scattered]
+    for p in probs:
+        o = TreeOracle(p)
+        o.run_fixed(7)
+        g = gpu_problem(ctx, p)
+        g.set_potentials(o.potentials())
+        eg, eo = g.evaluate(), o.evaluate()
+        for key in ["dual", "primal", "transport"]:
+            assert abs(eg[key] - eo[key]) <= 1e-10 * max(1.0, eo["scale"]), key
+        assert abs(eg["err_sum"] - eo["err_sum"]) <= 1e-10 + 1e-8 * eo["err_sum"]
+        for j in range(p.n_nodes):
+            assert np.max(np.abs(g.node_marginal(j) - o.node_marginal(j))) <= 1e-12
+    gps = [gpu_problem(ctx, p) for p in probs]
+    b = Batch(ctx, gps)
+    b.solve(tol=0.0, max_steps=9)
+    evs = b.evaluate()
+    for p, g, ev in zip(probs, gps, evs):
+        o = TreeOracle(p)
+        eo = o.evaluate(o.set_potentials(g.potentials()))
+        assert abs(ev["dual"] - eo["dual"]) <= 1e-10 * max(1.0, eo["scale"])
+        assert abs(ev["err_sum"] - eo["err_sum"]) <= 1e-10 + 1e-8 * eo["err_sum"]
