@@ -1464,7 +1464,7 @@ constexpr int kGridWaves = 4;          // waves (items) per block
 // normaliser, and the message written as column split 0 of the evaluation's
 // partials (the other splits empty), as k_msg leaves them.
 template <int R, bool EVAL>
-__global__ __launch_bounds__(64 * kGridWaves, R == 2 ? 4 : 1) void k_msg_grid(Tables tb, int n_items) {
+__global__ __launch_bounds__(64 * kGridWaves, R == 2 ? 3 : 1) void k_msg_grid(Tables tb, int n_items) {
   __shared__ double s_v[kGridWaves][64];
   if (!EVAL && (int)blockIdx.x < tb.n_fin) {
     // the finalise step of the previous launch's half-sweep, one block per instance
@@ -1523,20 +1523,26 @@ __global__ __launch_bounds__(64 * kGridWaves, R == 2 ? 4 : 1) void k_msg_grid(Ta
     return ok ? fma(cxc - kap * y, y, kLog2e * (l + g)) : -INFINITY;
   };
   const int nt = (ns + 63) / 64;
+  // columns two tiles ahead: tile J's in (l_n, g_n, y_n), tile J - 1's in
+  // (l_m, g_m, y_m), loaded while tile J + 1 is summed (clamped indexes)
   int jn = min((nt - 1) * 64 + lane, ns - 1);
   double l_n = lam[jn], g_n = lg[jn], y_n = ys[jn];
+  jn = max(nt - 2, 0) * 64 + lane;
+  double l_m = lam[jn], g_m = lg[jn], y_m = ys[jn];
   double theta = -INFINITY, P[R];
 #pragma unroll
   for (int r = 0; r < R; ++r) P[r] = 0.0;
   double* __restrict__ sv = s_v[wv];
   for (int J = nt - 1; J >= 0; --J) {
     const double C = c_of(l_n, g_n, y_n, J * 64 + lane < ns);
-    if (J > 0) {
-      // the next tile's columns, loaded while this one is summed
-      jn = (J - 1) * 64 + lane;
-      l_n = lam[jn];
-      g_n = lg[jn];
-      y_n = ys[jn];
+    l_n = l_m;
+    g_n = g_m;
+    y_n = y_m;
+    if (J > 1) {
+      jn = (J - 2) * 64 + lane;
+      l_m = lam[jn];
+      g_m = lg[jn];
+      y_m = ys[jn];
     }
     if (__any(C > theta + kGridSlack)) {
       const double m = wave_max(C);
@@ -1727,18 +1733,46 @@ __global__ __launch_bounds__(64 * kSepWaves) void k_sep_horner(Tables tb, int n_
   }
   double* __restrict__ sv = s_v[wv];
   const int l_end = min(tk.line + kSepLines, lines);
+  // a line's inputs of its first-summed tile (the last): the coordinate is the
+  // same for every line, the values of the next line are loaded while the
+  // current one is summed (clamped indexes)
+  const int i_top = (nt - 1) * 64 + lane, ic_top = min(i_top, inner - 1);
+  const double y_top = yin(ic_top);
+  double ra, rb;  // raw inputs of (line, top tile): pass 0 L and log gamma, pass 1 Tt
+  auto load_top = [&](int line, double& a, double& b) {
+    if (PASS == 0) {
+      const int idx = min(line * Bk + ic_top, nk - 1);
+      a = lam[idx];
+      b = lg[idx];
+    } else {
+      a = Tr[(size_t)line * Ak + ic_top];
+      b = 0.0;
+    }
+  };
+  load_top(tk.line, ra, rb);
   for (int line = tk.line; line < l_end; ++line) {
     double theta = -INFINITY, P = 0.0;
+    const double ra_c = ra, rb_c = rb;
+    if (line + 1 < l_end) load_top(line + 1, ra, rb);
     for (int J = nt - 1; J >= 0; --J) {
       const int i = J * 64 + lane;
       const int ic = min(i, inner - 1);
-      const double y = yin(ic);
+      const double y = J == nt - 1 ? y_top : yin(ic);
       double s;
       if (PASS == 0) {
-        const int idx = min(line * Bk + ic, nk - 1);
-        s = (i < inner && line * Bk + i < nk) ? fma(-kap * y, y, kLog2e * (lam[idx] + lg[idx])) : -INFINITY;
+        double l, g;
+        if (J == nt - 1) {
+          l = ra_c;
+          g = rb_c;
+        } else {
+          const int idx = min(line * Bk + ic, nk - 1);
+          l = lam[idx];
+          g = lg[idx];
+        }
+        s = (i < inner && line * Bk + i < nk) ? fma(-kap * y, y, kLog2e * (l + g)) : -INFINITY;
       } else {
-        s = i < inner ? Tr[(size_t)line * Ak + ic] : -INFINITY;
+        const double tv = J == nt - 1 ? ra_c : Tr[(size_t)line * Ak + ic];
+        s = i < inner ? tv : -INFINITY;
       }
       const double C = s > -INFINITY ? fma(czc, y, s) : -INFINITY;
       // a line's first tile starts from the first input's value (any value
