@@ -73,7 +73,10 @@ struct MsgDesc {
   double* sepM;              // separable messages: first-pass shifts (log2 max term), [rows_src x cols_dst]
   int32_t n_dst, n_src, ns, inst;
   int32_t dim, cost_kind, src_tiles, src_deg;  // source node's tile count and degree
-  int32_t src_free, pad0, pad1, pad2;          // 1: free source node (c_k from the records), 0: c_k = 0
+  int32_t src_free;          // 1: free source node (c_k from the records), 0: c_k = 0
+  int32_t grid;              // 1: the message is summed by k_msg_grid (whose evaluation mode leaves in
+                             // wmax[x] the mean cost of row x under the plan's row: sum_y B C / sum_y B)
+  int32_t pad1, pad2;
   int32_t rows_src, cols_src, rows_dst, cols_dst;  // grid shapes of both supports (separable messages)
   double eps;
 };
@@ -189,6 +192,10 @@ struct Tables {
   // evaluation pass: per instance the slot holding each class's committed
   // potentials, [2 * inst + class] (read when a kernel is given slot -1)
   const int* inst_slot;
+  // evaluation pass, per plan message into node j: (sum_x q, sum_x q (L - c_j),
+  // sum_x q Cbar, 0) with q the plan's marginal on j and Cbar its row's mean
+  // cost (grid messages only, else 0)
+  double4* msg_eval;
 };
 
 // Pair pass of the evaluation (transport, entropy, mass of each plan).

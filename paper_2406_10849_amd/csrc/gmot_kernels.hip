@@ -1462,7 +1462,10 @@ constexpr int kGridWaves = 4;          // waves (items) per block
 // EVAL: the FP64 evaluation pass -- every item regardless of its instance's
 // loop state, the source's committed slot from tb.inst_slot and its stored
 // normaliser, and the message written as column split 0 of the evaluation's
-// partials (the other splits empty), as k_msg leaves them.
+// partials (the other splits empty), as k_msg leaves them.  It also sums
+// j v_j rho^j and j^2 v_j rho^j, so that the row's mean cost under the plan,
+// sum_j B (x - y_j)^2 / sum_j B = d^2 - 2 d h S1 / S0 + h^2 S2 / S0 with
+// d = x - y_0, goes to wmax[x] (the transport cost without a pair pass).
 template <int R, bool EVAL>
 __global__ __launch_bounds__(64 * kGridWaves, R == 2 ? 3 : 1) void k_msg_grid(Tables tb, int n_items) {
   __shared__ double s_v[kGridWaves][64];
@@ -1529,9 +1532,11 @@ __global__ __launch_bounds__(64 * kGridWaves, R == 2 ? 3 : 1) void k_msg_grid(Ta
   double l_n = lam[jn], g_n = lg[jn], y_n = ys[jn];
   jn = max(nt - 2, 0) * 64 + lane;
   double l_m = lam[jn], g_m = lg[jn], y_m = ys[jn];
-  double theta = -INFINITY, P[R];
+  double theta = -INFINITY, P[R], P1[EVAL ? R : 1], P2[EVAL ? R : 1];
 #pragma unroll
   for (int r = 0; r < R; ++r) P[r] = 0.0;
+#pragma unroll
+  for (int r = 0; r < (EVAL ? R : 1); ++r) P1[r] = P2[r] = 0.0;
   double* __restrict__ sv = s_v[wv];
   for (int J = nt - 1; J >= 0; --J) {
     const double C = c_of(l_n, g_n, y_n, J * 64 + lane < ns);
@@ -1550,6 +1555,12 @@ __global__ __launch_bounds__(64 * kGridWaves, R == 2 ? 3 : 1) void k_msg_grid(Ta
         const double f = exp2(theta - m);
 #pragma unroll
         for (int r = 0; r < R; ++r) P[r] *= f;
+        if (EVAL)
+#pragma unroll
+          for (int r = 0; r < R; ++r) {
+            P1[r] *= f;
+            P2[r] *= f;
+          }
       }
       theta = m;
     }
@@ -1580,6 +1591,36 @@ __global__ __launch_bounds__(64 * kGridWaves, R == 2 ? 3 : 1) void k_msg_grid(Ta
 #pragma unroll
     for (int r = 0; r < R; ++r)
       P[r] = fma(P[r], r64[r], fma(fma(fma(S[r][3], r16[r], S[r][2]), r16[r], S[r][1]), r16[r], S[r][0]));
+    if (EVAL) {
+      // the same sums with the coefficients j v_j and j^2 v_j (j the column)
+      double w1[4], w2[4];
+#pragma unroll
+      for (int c = 0; c < 4; ++c) {
+        const double jj = (double)(J * 64 + 16 * c + (lane & 15));
+        w1[c] = jj * vc[c];
+        w2[c] = jj * w1[c];
+      }
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        double T1[4] = {0.0, 0.0, 0.0, 0.0}, T2[4] = {0.0, 0.0, 0.0, 0.0};
+#define GMOT_GRID_MOM(Q)                                    \
+  GMOT_FMAC_ROWBCAST(T1[0], w1[0], pw[r][Q], Q);            \
+  GMOT_FMAC_ROWBCAST(T1[1], w1[1], pw[r][Q], Q);            \
+  GMOT_FMAC_ROWBCAST(T1[2], w1[2], pw[r][Q], Q);            \
+  GMOT_FMAC_ROWBCAST(T1[3], w1[3], pw[r][Q], Q);            \
+  GMOT_FMAC_ROWBCAST(T2[0], w2[0], pw[r][Q], Q);            \
+  GMOT_FMAC_ROWBCAST(T2[1], w2[1], pw[r][Q], Q);            \
+  GMOT_FMAC_ROWBCAST(T2[2], w2[2], pw[r][Q], Q);            \
+  GMOT_FMAC_ROWBCAST(T2[3], w2[3], pw[r][Q], Q);
+        GMOT_GRID_MOM(0) GMOT_GRID_MOM(1) GMOT_GRID_MOM(2) GMOT_GRID_MOM(3)
+        GMOT_GRID_MOM(4) GMOT_GRID_MOM(5) GMOT_GRID_MOM(6) GMOT_GRID_MOM(7)
+        GMOT_GRID_MOM(8) GMOT_GRID_MOM(9) GMOT_GRID_MOM(10) GMOT_GRID_MOM(11)
+        GMOT_GRID_MOM(12) GMOT_GRID_MOM(13) GMOT_GRID_MOM(14) GMOT_GRID_MOM(15)
+#undef GMOT_GRID_MOM
+        P1[r] = fma(P1[r], r64[r], fma(fma(fma(T1[3], r16[r], T1[2]), r16[r], T1[1]), r16[r], T1[0]));
+        P2[r] = fma(P2[r], r64[r], fma(fma(fma(T2[3], r16[r], T2[2]), r16[r], T2[1]), r16[r], T2[0]));
+      }
+    }
   }
   // the source's normaliser c_k, from its tile records when its last update
   // (half-sweep t - 1) ran in this run, else (and in the evaluation) its
@@ -1607,6 +1648,8 @@ __global__ __launch_bounds__(64 * kGridWaves, R == 2 ? 3 : 1) void k_msg_grid(Ta
         double2* __restrict__ part = md.partial + (size_t)x[r] * md.ns;
         part[0] = make_double2(l2, fin ? 1.0 : 0.0);
         for (int sp = 1; sp < md.ns; ++sp) part[sp] = make_double2(-INFINITY, 0.0);
+        const double d = xv[r] - y0;
+        md.wmax[x[r]] = fin ? fma(d, d, h * fma(-2.0 * d, P1[r] / P[r], h * (P2[r] / P[r]))) : 0.0;
       } else {
         ((GDblW*)md.mfull)[x[r]] = fin ? kLn2 * (e + log2(P[r])) - ck : -INFINITY;
       }
@@ -1917,15 +1960,26 @@ __global__ __launch_bounds__(kBlock) void k_node_eval(Tables tb, int slot) {
   double e_sum = 0.0, e_max = 0.0;
   for (int k = 0; k < deg; ++k) {
     const MsgDesc& md = mds[k];
-    double part = 0.0;
+    double part = 0.0, sq = 0.0, sl = 0.0, sc = 0.0;
     for (int x = threadIdx.x; x < n; x += kBlock) {
-      const double q = exp(md.lam_dst[slot][x] - cj + nd.lg[x] + md.mfull[x]);
+      const double l = md.lam_dst[slot][x] - cj;
+      const double q = exp(l + nd.lg[x] + md.mfull[x]);
       const double ref = nd.fixed ? nd.mu[x] : nd.qbar[x];
       part += fabs(q - ref);
+      // the plan's marginal on this node and its sums for the objective
+      if (q > 0.0) {
+        sq += q;
+        sl += q * l;
+        if (md.grid) sc += q * md.wmax[x];
+      }
     }
     const double tot = block_sum(part, sh);
     e_sum += tot;
     e_max = fmax(e_max, tot);
+    sq = block_sum(sq, sh);
+    sl = block_sum(sl, sh);
+    sc = block_sum(sc, sh);
+    if (threadIdx.x == 0) tb.msg_eval[nd.msg0 + k] = make_double4(sq, sl, sc, 0.0);
   }
   double v0 = 0.0, lo = INFINITY, hi = -INFINITY;
   if (nd.fixed) {

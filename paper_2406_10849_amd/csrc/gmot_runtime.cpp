@@ -217,6 +217,11 @@ struct Plan {
   size_t sep_lds[2][2] = {};  // dynamic LDS bytes per block, [class][pass]
   double* d_sepT = nullptr;
   int* d_inst_slot = nullptr;  // evaluation pass: committed slot of each class, per instance
+  double4* d_msg_eval = nullptr;  // evaluation pass: per-message sums of the plans' marginals
+  // per instance: whether k_msg_grid sums its messages, and the plan message
+  // of each directed edge (its destination node's side)
+  std::vector<uint8_t> inst_on_grid;
+  std::vector<std::vector<int>> de_msg;
   int rec_rows = 64;         // rows per tile record
   int* h_ndone = nullptr;  // pinned, two mailboxes
   std::vector<GraphEntry> graphs;
@@ -314,6 +319,7 @@ struct Plan {
     tb.sep_tasks2 = d_sep_tasks[c][1];
     tb.rec_rows = rec_rows;
     tb.inst_slot = d_inst_slot;
+    tb.msg_eval = d_msg_eval;
     return tb;
   }
 
@@ -552,8 +558,12 @@ static int build_plan(gmot_ctx* ctx, const std::vector<gmot_problem*>& probs, No
   std::map<size_t, std::pair<int, int>> msg_src;            // message -> (instance, source node)
   std::map<std::pair<int, int>, std::pair<int, int>> item_of;  // (instance, node) -> (class, node item)
   int err_counter = 0;
+  pl->inst_on_grid.assign(probs.size(), 0);
+  pl->de_msg.assign(probs.size(), {});
   for (size_t i = 0; i < probs.size(); ++i) {
     gmot_problem* p = probs[i];
+    pl->inst_on_grid[i] = on_grid(p) ? 1 : 0;
+    pl->de_msg[i].assign(2 * (size_t)p->E, -1);
     InstState st{};
     for (int c = 0; c < 2; ++c) {
       st.node0[c] = (int)pl->nodes[c].size();
@@ -630,6 +640,8 @@ static int build_plan(gmot_ctx* ctx, const std::vector<gmot_problem*>& probs, No
           md.dim = p->dim;
           md.cost_kind = p->cost_kind;
           md.eps = p->eps;
+          md.grid = on_grid(p) ? 1 : 0;
+          pl->de_msg[i][de_dst] = (int)pl->msgs.size();
           pl->msgs.push_back(md);
           msg_class.push_back(c);
         }
@@ -870,6 +882,7 @@ static int build_plan(gmot_ctx* ctx, const std::vector<gmot_problem*>& probs, No
     for (int q = 0; q < 2; ++q) o_sept[c][q] = take(sizeof(SepTask) * pl->sep_tasks[c][q].size());
   const size_t o_sepT = take(sizeof(double) * 2 * std::max<int64_t>(1, sepT_total));
   const size_t o_islot = take(sizeof(int) * 2 * probs.size());
+  const size_t o_meval = take(sizeof(double4) * std::max<size_t>(1, pl->msgs.size()));
   const size_t total = off;
   if (hipMalloc(&pl->arena, total) != hipSuccess) return fail(GMOT_ENOMEM, "plan arena allocation failed");
   char* base = (char*)pl->arena;
@@ -893,6 +906,7 @@ static int build_plan(gmot_ctx* ctx, const std::vector<gmot_problem*>& probs, No
     for (int q = 0; q < 2; ++q) pl->d_sep_tasks[c][q] = (SepTask*)(base + o_sept[c][q]);
   pl->d_sepT = (double*)(base + o_sepT);
   pl->d_inst_slot = (int*)(base + o_islot);
+  pl->d_msg_eval = (double4*)(base + o_meval);
   for (int c = 0; c < 2; ++c)
     for (size_t i = 0; i < pl->nodes[c].size(); ++i) pl->nodes[c][i].tpart = pl->d_tpart + tpart_off[c][i];
   for (size_t m = 0; m < pl->msgs.size(); ++m) {
@@ -2025,6 +2039,9 @@ static int evaluate_plan(Plan* pl, gmot_eval* outs) {
     for (int e = 0; e < p->E; ++e) {
       const int ge = (int)eds.size();
       eds.push_back(edge_desc(p, e));
+      // instances on the grid kernel take their plans' sums from the messages
+      // (marginals and mean costs), with no pair pass
+      if (pl->inst_on_grid[i]) continue;
       const int na = eds.back().n_a, nb = eds.back().n_b;
       const int cw = 2048;
       for (int r0 = 0; r0 < na; r0 += kBlock)
@@ -2034,8 +2051,8 @@ static int evaluate_plan(Plan* pl, gmot_eval* outs) {
   edge0[n] = (int)eds.size();
   if (eds.empty()) return GMOT_OK;
   const size_t b_ed = align_up(sizeof(EdgeDesc) * eds.size(), 256);
-  const size_t b_it = align_up(sizeof(PairItem) * items.size(), 256);
-  const size_t b_out = sizeof(double4) * items.size();
+  const size_t b_it = align_up(sizeof(PairItem) * std::max<size_t>(1, items.size()), 256);
+  const size_t b_out = sizeof(double4) * std::max<size_t>(1, items.size());
   if (pl->pair_buf_size < b_ed + b_it + b_out) {
     if (pl->pair_buf) (void)hipFree(pl->pair_buf);
     pl->pair_buf = nullptr;
@@ -2054,19 +2071,24 @@ static int evaluate_plan(Plan* pl, gmot_eval* outs) {
   if (e1 == hipSuccess) e1 = hipStreamWaitEvent(ctx->aux, ctx->ev_fork, 0);
   if (e1 == hipSuccess)
     e1 = hipMemcpyAsync(base, eds.data(), sizeof(EdgeDesc) * eds.size(), hipMemcpyHostToDevice, ctx->aux);
-  if (e1 == hipSuccess)
+  if (e1 == hipSuccess && !items.empty())
     e1 = hipMemcpyAsync(base + b_ed, items.data(), sizeof(PairItem) * items.size(), hipMemcpyHostToDevice, ctx->aux);
   if (e1 == hipSuccess)
     e1 = launch_pairs((EdgeDesc*)base, (PairItem*)(base + b_ed), (int)items.size(), (double4*)(base + b_ed + b_it),
                       ctx->aux);
-  if (e1 == hipSuccess) e1 = hipMemcpyAsync(parts.data(), base + b_ed + b_it, b_out, hipMemcpyDeviceToHost, ctx->aux);
+  if (e1 == hipSuccess && !items.empty())
+    e1 = hipMemcpyAsync(parts.data(), base + b_ed + b_it, sizeof(double4) * items.size(), hipMemcpyDeviceToHost,
+                        ctx->aux);
   int rc = GMOT_OK;
   if (e1 == hipSuccess) rc = eval_messages(pl, -1);
   hipError_t e2 = hipStreamSynchronize(ctx->aux);
   if (e1 != hipSuccess) return fail(GMOT_EDEVICE, std::string("evaluation: ") + hipGetErrorString(e1));
   if (rc) return rc;
+  std::vector<double4> me(pl->msgs.size());
   if (e2 == hipSuccess)
     e2 = hipMemcpyAsync(ne.data(), pl->d_node_eval, sizeof(double4) * pl->total_nodes, hipMemcpyDeviceToHost, s);
+  if (e2 == hipSuccess && !me.empty())
+    e2 = hipMemcpyAsync(me.data(), pl->d_msg_eval, sizeof(double4) * me.size(), hipMemcpyDeviceToHost, s);
   if (e2 == hipSuccess) e2 = hipStreamSynchronize(s);
   if (e2 != hipSuccess) return fail(GMOT_EDEVICE, std::string("evaluation: ") + hipGetErrorString(e2));
   std::vector<double> T(eds.size(), 0.0), H(eds.size(), 0.0), M(eds.size(), 0.0);
@@ -2075,6 +2097,21 @@ static int evaluate_plan(Plan* pl, gmot_eval* outs) {
     T[e] += parts[k].x;
     H[e] += parts[k].y;
     M[e] += parts[k].z;
+  }
+  // grid instances: for edge (a, b), the message into a carries the plan's
+  // row sums r = q_a (mass sum r, sum r (L_(a,b) - c_a), transport sum r Cbar)
+  // and the one into b its column sums; entropy sum B (log B - 1) =
+  // sum r (L_(a,b) - c_a) + sum q_b (L_(b,a) - c_b) - T / eps - M
+  for (size_t i = 0; i < n; ++i) {
+    if (!pl->inst_on_grid[i]) continue;
+    const gmot_problem* p = pl->probs[i];
+    for (int e = 0; e < p->E; ++e) {
+      const double4 ra = me[pl->de_msg[i][2 * e]], rb = me[pl->de_msg[i][2 * e + 1]];
+      const int ge = edge0[i] + e;
+      M[ge] = ra.x;
+      T[ge] = ra.z;
+      H[ge] = ra.y + rb.y - ra.z / p->eps - ra.x;
+    }
   }
   for (size_t i = 0; i < n; ++i) {
     const gmot_problem* p = pl->probs[i];
