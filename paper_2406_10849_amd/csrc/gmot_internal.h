@@ -70,12 +70,15 @@ struct MsgDesc {
   const double* src_tpart;   // tile records of the source node k (its c_k comes from them)
   double* sepT;              // separable messages (grid supports): first-pass sums, transposed,
                              // Tt(q, u) = T(u, q) - kap R_k[u]^2 at q * rows_src + u (log2), else NULL
-  double* sepM;              // separable messages: first-pass shifts (log2 max term), [rows_src x cols_dst]
+  double* sepM;              // separable messages, [rows_src x cols_dst]: first-pass shifts (log2 max
+                             // term) of k_sep_pass; in k_sep_horner's evaluation mode, at Tt's index,
+                             // the first pass's mean of (C_j[q] - C_k[i])^2 under the line's weights
   int32_t n_dst, n_src, ns, inst;
   int32_t dim, cost_kind, src_tiles, src_deg;  // source node's tile count and degree
   int32_t src_free;          // 1: free source node (c_k from the records), 0: c_k = 0
-  int32_t grid;              // 1: the message is summed by k_msg_grid (whose evaluation mode leaves in
-                             // wmax[x] the mean cost of row x under the plan's row: sum_y B C / sum_y B)
+  int32_t grid;              // 1: the message is summed by k_msg_grid or k_sep_horner (whose evaluation
+                             // modes leave in wmax[x] the mean cost of row x under the plan's row:
+                             // sum_y B C / sum_y B)
   int32_t pad1, pad2;
   int32_t rows_src, cols_src, rows_dst, cols_dst;  // grid shapes of both supports (separable messages)
   double eps;

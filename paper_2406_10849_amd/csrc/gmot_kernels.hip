@@ -1705,10 +1705,17 @@ __device__ inline double horner_tile(const double* vc, const double* pw, double 
 
 // EVAL: the FP64 evaluation pass (as for k_msg_grid): every task, the
 // source's committed slot and stored normaliser, the message as split 0 of
-// the evaluation's partials.
+// the evaluation's partials.  It also leaves the mean cost of each plan row:
+// with the cost |x - y|^2 = (R_j - R_k)^2 + (C_j - C_k)^2, pass 0 sums the
+// moments i v_i rho^i and i^2 v_i rho^i of its line and stores the line's mean
+// of (C_j[q] - C_k[i])^2 (d^2 - 2 d h S1 / S0 + h^2 S2 / S0, d = C_j[q] - C_k[0])
+// in sepM at Tt's index; pass 1 weights the inputs by the same moments of
+// (R_j[p] - R_k[u])^2 and by that stored mean, and writes the row's mean
+// cost sum_y B C / sum_y B to wmax[x] (the transport cost without a pair pass).
 template <int PASS, bool EVAL>
 __global__ __launch_bounds__(64 * kSepWaves) void k_sep_horner(Tables tb, int n_tasks) {
   __shared__ double s_v[kSepWaves][64];
+  __shared__ double s_m[EVAL && PASS == 1 ? kSepWaves : 1][64];
   int bid = (int)blockIdx.x;
   if (PASS == 0 && !EVAL) {
     if (bid < tb.n_fin) {
@@ -1794,7 +1801,7 @@ __global__ __launch_bounds__(64 * kSepWaves) void k_sep_horner(Tables tb, int n_
   };
   load_top(tk.line, ra, rb);
   for (int line = tk.line; line < l_end; ++line) {
-    double theta = -INFINITY, P = 0.0;
+    double theta = -INFINITY, P = 0.0, P1 = 0.0, P2 = 0.0, P3 = 0.0;
     const double ra_c = ra, rb_c = rb;
     if (line + 1 < l_end) load_top(line + 1, ra, rb);
     for (int J = nt - 1; J >= 0; --J) {
@@ -1823,34 +1830,98 @@ __global__ __launch_bounds__(64 * kSepWaves) void k_sep_horner(Tables tb, int n_
       if (J == nt - 1) theta = lane_read(C, 0);
       if (__any(C > theta + kGridSlack)) {
         const double m = wave_max(C);
-        if (J != nt - 1 && theta > -INFINITY) P *= exp2(theta - m);
+        if (J != nt - 1 && theta > -INFINITY) {
+          const double f = exp2(theta - m);
+          P *= f;
+          if (EVAL) {
+            P1 *= f;
+            P2 *= f;
+            P3 *= f;
+          }
+        }
         theta = m;
       }
-      sv[lane] = C > -INFINITY ? exp2(C - theta) : 0.0;
+      const double vl = C > -INFINITY ? exp2(C - theta) : 0.0;
+      sv[lane] = vl;
+      // pass 1: the input's stored mean of the first pass's squared distance
+      if (EVAL && PASS == 1) s_m[wv][lane] = vl * ((const GDbl*)md.sepM)[(size_t)line * Ak + ic];
       wave_sync();
-      double vc[4];
+      double vc[4], w1[4], w2[4], w3[4];
 #pragma unroll
-      for (int c = 0; c < 4; ++c) vc[c] = sv[16 * c + (lane & 15)];
+      for (int c = 0; c < 4; ++c) {
+        vc[c] = sv[16 * c + (lane & 15)];
+        if (EVAL) {
+          const double jj = (double)(J * 64 + 16 * c + (lane & 15));
+          w1[c] = jj * vc[c];
+          w2[c] = jj * w1[c];
+          w3[c] = PASS == 1 ? s_m[wv][16 * c + (lane & 15)] : 0.0;
+        }
+      }
       wave_sync();
-      double St;
+      double St, St1 = 0.0, St2 = 0.0, St3 = 0.0;
       switch (ng) {
-        case 1: St = horner_tile<1>(vc, pw, r16); break;
-        case 2: St = horner_tile<2>(vc, pw, r16); break;
-        case 3: St = horner_tile<3>(vc, pw, r16); break;
-        default: St = horner_tile<4>(vc, pw, r16); break;
+        case 1:
+          St = horner_tile<1>(vc, pw, r16);
+          if (EVAL) {
+            St1 = horner_tile<1>(w1, pw, r16);
+            St2 = horner_tile<1>(w2, pw, r16);
+            if (PASS == 1) St3 = horner_tile<1>(w3, pw, r16);
+          }
+          break;
+        case 2:
+          St = horner_tile<2>(vc, pw, r16);
+          if (EVAL) {
+            St1 = horner_tile<2>(w1, pw, r16);
+            St2 = horner_tile<2>(w2, pw, r16);
+            if (PASS == 1) St3 = horner_tile<2>(w3, pw, r16);
+          }
+          break;
+        case 3:
+          St = horner_tile<3>(vc, pw, r16);
+          if (EVAL) {
+            St1 = horner_tile<3>(w1, pw, r16);
+            St2 = horner_tile<3>(w2, pw, r16);
+            if (PASS == 1) St3 = horner_tile<3>(w3, pw, r16);
+          }
+          break;
+        default:
+          St = horner_tile<4>(vc, pw, r16);
+          if (EVAL) {
+            St1 = horner_tile<4>(w1, pw, r16);
+            St2 = horner_tile<4>(w2, pw, r16);
+            if (PASS == 1) St3 = horner_tile<4>(w3, pw, r16);
+          }
+          break;
       }
       if (J == nt - 1) {
         P = St;
+        P1 = St1;
+        P2 = St2;
+        P3 = St3;
       } else {
         const double r64 = (r16 * r16) * (r16 * r16);
         P = fma(P, r64, St);
+        if (EVAL) {
+          P1 = fma(P1, r64, St1);
+          P2 = fma(P2, r64, St2);
+          P3 = fma(P3, r64, St3);
+        }
       }
+    }
+    // EVAL: the line's mean of the pass's squared distance (z - y_i)^2 under
+    // the weights v_i rho^i, plus (pass 1) the inputs' stored first-pass means
+    double mc = 0.0;
+    if (EVAL && theta > -INFINITY && P > 0.0) {
+      const double d = z - y0;
+      mc = fma(d, d, h * fma(-2.0 * d, P1 / P, h * (P2 / P)));
+      if (PASS == 1) mc += P3 / P;
     }
     const double T = (theta > -INFINITY && P > 0.0) ? theta + log2(P) + 2.0 * kap * dz * y0 : -INFINITY;
     if (PASS == 0) {
       if (ov) {
         const double Ru = ys[(size_t)line * Bk * 2];
         ((GDblW*)md.sepT)[(size_t)o * Ak + line] = T - kap * (z * z) - kap * (Ru * Ru);
+        if (EVAL) md.sepM[(size_t)o * Ak + line] = mc;
       }
     } else {
       const int x = o * Bj + line;
@@ -1865,6 +1936,7 @@ __global__ __launch_bounds__(64 * kSepWaves) void k_sep_horner(Tables tb, int n_
           double2* __restrict__ part = md.partial + (size_t)x * md.ns;
           part[0] = make_double2(l2, T > -INFINITY ? 1.0 : 0.0);
           for (int sp = 1; sp < md.ns; ++sp) part[sp] = make_double2(-INFINITY, 0.0);
+          md.wmax[x] = mc;
         } else {
           ((GDblW*)md.mfull)[x] = T > -INFINITY ? kLn2 * (T - kap * (z * z)) - ck : -INFINITY;
         }

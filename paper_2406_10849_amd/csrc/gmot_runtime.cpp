@@ -218,9 +218,10 @@ struct Plan {
   double* d_sepT = nullptr;
   int* d_inst_slot = nullptr;  // evaluation pass: committed slot of each class, per instance
   double4* d_msg_eval = nullptr;  // evaluation pass: per-message sums of the plans' marginals
-  // per instance: whether k_msg_grid sums its messages, and the plan message
-  // of each directed edge (its destination node's side)
-  std::vector<uint8_t> inst_on_grid;
+  // per instance: whether the uniform-grid kernels (k_msg_grid, k_sep_horner)
+  // sum its messages, and the plan message of each directed edge (its
+  // destination node's side)
+  std::vector<uint8_t> inst_horner;
   std::vector<std::vector<int>> de_msg;
   int rec_rows = 64;         // rows per tile record
   int* h_ndone = nullptr;  // pinned, two mailboxes
@@ -558,11 +559,11 @@ static int build_plan(gmot_ctx* ctx, const std::vector<gmot_problem*>& probs, No
   std::map<size_t, std::pair<int, int>> msg_src;            // message -> (instance, source node)
   std::map<std::pair<int, int>, std::pair<int, int>> item_of;  // (instance, node) -> (class, node item)
   int err_counter = 0;
-  pl->inst_on_grid.assign(probs.size(), 0);
+  pl->inst_horner.assign(probs.size(), 0);
   pl->de_msg.assign(probs.size(), {});
   for (size_t i = 0; i < probs.size(); ++i) {
     gmot_problem* p = probs[i];
-    pl->inst_on_grid[i] = on_grid(p) ? 1 : 0;
+    pl->inst_horner[i] = on_grid(p) || on_sep_h(p) ? 1 : 0;
     pl->de_msg[i].assign(2 * (size_t)p->E, -1);
     InstState st{};
     for (int c = 0; c < 2; ++c) {
@@ -640,7 +641,7 @@ static int build_plan(gmot_ctx* ctx, const std::vector<gmot_problem*>& probs, No
           md.dim = p->dim;
           md.cost_kind = p->cost_kind;
           md.eps = p->eps;
-          md.grid = on_grid(p) ? 1 : 0;
+          md.grid = on_grid(p) || on_sep_h(p) ? 1 : 0;
           pl->de_msg[i][de_dst] = (int)pl->msgs.size();
           pl->msgs.push_back(md);
           msg_class.push_back(c);
@@ -2022,9 +2023,11 @@ static EdgeDesc edge_desc(const gmot_problem* p, int e) {
 // FP64 objective values of the held state of every instance of a plan, in
 // shared launches (outs[i] for plan instance i): the messages into both
 // classes and the node terms (k_msg, k_node_eval), then the pair pass over
-// every edge of every instance (k_pairs); the per-instance sums are taken on
-// the host in the same order for any plan (only the column splits of the
-// messages, and so their merge order, depend on the plan).
+// every edge of every instance (k_pairs) except those of instances on the
+// uniform-grid kernels, whose messages carry their plans' mean costs; the
+// per-instance sums are taken on the host in the same order for any plan
+// (only the column splits of the messages, and so their merge order, depend
+// on the plan).
 static int evaluate_plan(Plan* pl, gmot_eval* outs) {
   const size_t n = pl->probs.size();
   for (size_t i = 0; i < n; ++i) std::memset(&outs[i], 0, sizeof(gmot_eval));
@@ -2039,9 +2042,9 @@ static int evaluate_plan(Plan* pl, gmot_eval* outs) {
     for (int e = 0; e < p->E; ++e) {
       const int ge = (int)eds.size();
       eds.push_back(edge_desc(p, e));
-      // instances on the grid kernel take their plans' sums from the messages
-      // (marginals and mean costs), with no pair pass
-      if (pl->inst_on_grid[i]) continue;
+      // instances on the uniform-grid kernels take their plans' sums from the
+      // messages (marginals and mean costs), with no pair pass
+      if (pl->inst_horner[i]) continue;
       const int na = eds.back().n_a, nb = eds.back().n_b;
       const int cw = 2048;
       for (int r0 = 0; r0 < na; r0 += kBlock)
@@ -2098,12 +2101,12 @@ static int evaluate_plan(Plan* pl, gmot_eval* outs) {
     H[e] += parts[k].y;
     M[e] += parts[k].z;
   }
-  // grid instances: for edge (a, b), the message into a carries the plan's
+  // uniform-grid instances: for edge (a, b), the message into a carries the plan's
   // row sums r = q_a (mass sum r, sum r (L_(a,b) - c_a), transport sum r Cbar)
   // and the one into b its column sums; entropy sum B (log B - 1) =
   // sum r (L_(a,b) - c_a) + sum q_b (L_(b,a) - c_b) - T / eps - M
   for (size_t i = 0; i < n; ++i) {
-    if (!pl->inst_on_grid[i]) continue;
+    if (!pl->inst_horner[i]) continue;
     const gmot_problem* p = pl->probs[i];
     for (int e = 0; e < p->E; ++e) {
       const double4 ra = me[pl->de_msg[i][2 * e]], rb = me[pl->de_msg[i][2 * e + 1]];

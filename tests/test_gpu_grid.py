@@ -208,7 +208,9 @@ def rect_grid_problem(rows, cols, eps, instance):
 def test_separable_horner_several_input_tiles(ctx, rows, cols, monkeypatch):
     """Grid lines of more than 64 points (several 64-input tiles per pass, Horner
     across tiles), both orientations: FP64 and FP32-core iterates to 1e-9 of
-    the oracle and of the shifted-sum path (GMOT_NO_GRID=1, FP64)."""
+    the oracle and of the shifted-sum path (GMOT_NO_GRID=1, FP64); on the
+    oracle's potentials the evaluation (whose transport cost comes from the
+    passes' moments, with no pair pass) matches the oracle's objectives."""
     p = rect_grid_problem(rows, cols, eps=0.05, instance=130 + rows)
     assert grid_pairs(ctx, p, SEP_HORNER_GROUP) > 0
     steps = 10
@@ -220,6 +222,10 @@ def test_separable_horner_several_input_tiles(ctx, rows, cols, monkeypatch):
         g = gpu_problem(ctx, p)
         assert g.solve(tol=0.0, max_steps=steps, precision=precision)["steps"] == steps
         assert np.max(np.abs(g.potentials() - lo)) <= 1e-9 * scale, precision
+    g.set_potentials(lo)
+    eg, eo = g.evaluate(), o.evaluate()
+    for key in ["dual", "primal", "transport"]:
+        assert abs(eg[key] - eo[key]) <= 1e-10 * max(1.0, eo["scale"]), key
     monkeypatch.setenv("GMOT_NO_GRID", "1")
     h = gpu_problem(ctx, p)
     assert h.solve(tol=0.0, max_steps=steps, precision="fp64")["steps"] == steps
