@@ -271,6 +271,9 @@ hipError_t launch_gs_update(const Tables& tb, int node_item, int slot, hipStream
 struct SegCopy { const double* src; double* dst; const double* c; int64_t len; };
 hipError_t launch_seg_copy(const SegCopy* segs, int n_segs, hipStream_t s);
 hipError_t launch_stamp(InstState* inst, int count, hipStream_t s);
+// dst[0 .. len) = 0 for every segment (a batch's cold restart in one launch)
+struct ZeroSeg { double* dst; int64_t len; };
+hipError_t launch_zero_segs(const ZeroSeg* segs, int n_segs, hipStream_t s);
 hipError_t launch_pairs(const EdgeDesc* edges, const PairItem* items, int n_items, double4* out, hipStream_t s);
 hipError_t launch_coupling(const EdgeDesc* edge, double* out, size_t total, hipStream_t s);
 

@@ -2084,6 +2084,12 @@ __global__ void k_stamp(InstState* inst, int count) {
   if (i < count) inst[i].clk_start = wall_clock64();
 }
 
+// one block per segment: zero its doubles (vector stores)
+__global__ __launch_bounds__(kBlock) void k_zero_segs(const ZeroSeg* segs) {
+  const ZeroSeg sg = segs[blockIdx.x];
+  for (int64_t i = threadIdx.x; i < sg.len; i += kBlock) sg.dst[i] = 0.0;
+}
+
 // ---------------------------------------------------------------------------
 // FP64 pair pass: for each plan, sum_xy C B, sum_xy B (log B - log M - 1)
 // and sum_xy B over a (256 rows x ncols) tile.
@@ -2322,6 +2328,12 @@ __global__ __launch_bounds__(kBlock) void k_seg_copy(const SegCopy* segs) {
 hipError_t launch_seg_copy(const SegCopy* segs, int n_segs, hipStream_t s) {
   if (n_segs <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_seg_copy, dim3(n_segs), dim3(kBlock), 0, s, segs);
+  return hipGetLastError();
+}
+
+hipError_t launch_zero_segs(const ZeroSeg* segs, int n_segs, hipStream_t s) {
+  if (n_segs <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_zero_segs, dim3(n_segs), dim3(kBlock), 0, s, segs);
   return hipGetLastError();
 }
 

@@ -2726,6 +2726,10 @@ struct gmot_batch {
   gmot_ctx* ctx = nullptr;
   std::vector<gmot_problem*> probs;
   Plan* plan = nullptr;
+  // the cold restart's segments (every instance's first potential slot and
+  // normalisers), uploaded on the first restart
+  ZeroSeg* d_zero = nullptr;
+  int n_zero = 0;
 };
 
 int gmot_batch_create(gmot_ctx* ctx, gmot_problem* const* probs, int32_t count, gmot_batch** out) {
@@ -2749,6 +2753,7 @@ void gmot_batch_destroy(gmot_batch* b) {
   if (!b) return;
   (void)hipStreamSynchronize(b->ctx->stream);
   delete b->plan;
+  if (b->d_zero) (void)hipFree(b->d_zero);
   gmot_ctx* ctx = b->ctx;
   delete b;
   gmot_ctx_release(ctx);
@@ -2761,11 +2766,27 @@ int gmot_batch_solve(gmot_batch* b, const gmot_opts* o, gmot_result* outs) {
   if (o->schedule == GMOT_SCHED_GAUSS_SEIDEL)
     return fail(GMOT_ENOTSUP, "the Gauss-Seidel schedule runs one problem at a time (gmot_solve)");
   HIPCHK(hipSetDevice(b->ctx->device));
-  if (o->restart)
-    for (gmot_problem* p : b->probs) {
-      rc = restart_problem(p);
-      if (rc) return rc;
+  if (o->restart) {
+    // what restart_problem clears, for every instance in one launch
+    if (!b->d_zero) {
+      std::vector<ZeroSeg> segs;
+      for (gmot_problem* p : b->probs) {
+        if (p->total_de > 0) segs.push_back({p->d_lam[0], (int64_t)p->total_de});
+        segs.push_back({p->d_c, (int64_t)kSlots * p->N});
+      }
+      if (hipMalloc(&b->d_zero, sizeof(ZeroSeg) * segs.size()) != hipSuccess) {
+        b->d_zero = nullptr;
+        return fail(GMOT_ENOMEM, "restart segments");
+      }
+      HIPCHK(hipMemcpy(b->d_zero, segs.data(), sizeof(ZeroSeg) * segs.size(), hipMemcpyHostToDevice));
+      b->n_zero = (int)segs.size();
     }
+    HIPCHK(launch_zero_segs(b->d_zero, b->n_zero, b->ctx->stream));
+    for (gmot_problem* p : b->probs) {
+      p->t = 1;
+      ++p->version;
+    }
+  }
   return solve_plan(b->plan, o, outs);
 }
 
