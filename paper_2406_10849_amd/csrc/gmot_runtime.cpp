@@ -2813,11 +2813,12 @@ int gmot_batch_autotune(gmot_batch* b, int32_t* waves_per_block, int32_t* rows_p
 
 // ---- star warm-start data movement ------------------------------------------
 static int star_descs(gmot_problem* const* probs, int32_t count, int* L_out, int* n_out, StarDesc** d_out,
-                      int** d_rejected) {
+                      int** d_rejected, ZeroSeg** d_zero = nullptr) {
   if (!probs || count < 1) return fail(GMOT_EINVAL, "no problems");
   gmot_ctx* ctx = probs[0]->ctx;
   int L = -1, n = -1;
   std::vector<StarDesc> h(count);
+  std::vector<ZeroSeg> zs(count);  // every instance's normalisers (cleared by the warm start)
   for (int i = 0; i < count; ++i) {
     const gmot_problem* p = probs[i];
     if (!p || p->ctx != ctx) return fail(GMOT_ESTATE, "problems must share one context");
@@ -2834,8 +2835,11 @@ static int star_descs(gmot_problem* const* probs, int32_t count, int* L_out, int
     h[i].lg_leaf = p->d_lg + p->node_off[1];
     h[i].lam0 = p->d_lam[0] + p->de_off[0];
     h[i].lam_cur = p->d_lam[p->slot_of_class(p->colour[1])] + p->de_off[0];
+    zs[i] = {p->d_c, (int64_t)kSlots * p->N};
   }
-  const size_t need = align_up(sizeof(StarDesc) * count, 256) + 256;
+  // scratch: the star table, the rejection counter, the segment table
+  const size_t o_zero = align_up(sizeof(StarDesc) * count, 256) + 256;
+  const size_t need = o_zero + sizeof(ZeroSeg) * count;
   if (ctx->scratch_size < need) {
     HIPCHK(hipStreamSynchronize(ctx->stream));
     if (ctx->scratch) (void)hipFree(ctx->scratch);
@@ -2848,6 +2852,10 @@ static int star_descs(gmot_problem* const* probs, int32_t count, int* L_out, int
   // earlier launches may still read the scratch tables: wait, then copy synchronously
   HIPCHK(hipStreamSynchronize(ctx->stream));
   HIPCHK(hipMemcpy(d, h.data(), sizeof(StarDesc) * count, hipMemcpyHostToDevice));
+  if (d_zero) {
+    *d_zero = (ZeroSeg*)((char*)ctx->scratch + o_zero);
+    HIPCHK(hipMemcpy(*d_zero, zs.data(), sizeof(ZeroSeg) * count, hipMemcpyHostToDevice));
+  }
   *L_out = L;
   *n_out = n;
   *d_out = d;
@@ -2881,11 +2889,12 @@ int gmot_star_apply_dev(gmot_problem* const* probs, int32_t count, const float* 
   int L, n;
   StarDesc* d;
   int* d_rej = nullptr;
-  int rc = star_descs(probs, count, &L, &n, &d, &d_rej);
+  ZeroSeg* d_zero = nullptr;
+  int rc = star_descs(probs, count, &L, &n, &d, &d_rej, &d_zero);
   if (rc) return rc;
   hipStream_t s = probs[0]->ctx->stream;
   HIPCHK(hipMemsetAsync(d_rej, 0, sizeof(int), s));
-  for (int i = 0; i < count; ++i) HIPCHK(hipMemsetAsync(probs[i]->d_c, 0, sizeof(double) * kSlots * probs[i]->N, s));
+  HIPCHK(launch_zero_segs(d_zero, count, s));
   HIPCHK(launch_star_apply(d, count, L, n, y_dev, out_scale, d_rej, s));
   int rej = 0;
   HIPCHK(hipMemcpyAsync(&rej, d_rej, sizeof(int), hipMemcpyDeviceToHost, s));
