@@ -1363,8 +1363,6 @@ __global__ __launch_bounds__(64 * kSepWaves) void k_sep_pass(Tables tb) {
 // row; 64 / rec_rows records per 64-row tile, kSepWaves records per block),
 // the stopping-sum terms of the state before the update, the update and the
 // record, as k_node does.
-constexpr int kNodeSepCache = 16;  // free nodes of at most this degree keep their edges in registers
-
 __global__ __launch_bounds__(64 * kSepWaves) void k_node_sep(Tables tb, int n_tiles) {
   const int RR = tb.rec_rows, TQ = 64 / RR;
   const int lane = threadIdx.x & 63, wv = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));
@@ -1401,41 +1399,6 @@ __global__ __launch_bounds__(64 * kSepWaves) void k_node_sep(Tables tb, int n_ti
   } else {
     const double c_old = *(const GDbl*)(nd.c + cur);
     double as = 0.0, qs = 0.0;
-    if (deg <= kNodeSepCache) {
-      // each edge's message and plan marginal kept in registers between the
-      // two loops (the same sums in the same order as below)
-      double mk[kNodeSepCache], qk[kNodeSepCache];
-#pragma unroll
-      for (int k = 0; k < kNodeSepCache; ++k) {
-        if (k < deg) {
-          mk[k] = msg(k);
-          as += mk[k];
-          qk[k] = vr ? exp(((const GDbl*)mds[k].lam_dst[cur])[xr] - c_old + mk[k]) : 0.0;
-          if (vr) qs += qk[k];
-        }
-      }
-      const double ab = as / deg, qb = qs / deg;
-#pragma unroll
-      for (int k = 0; k < kNodeSepCache; ++k) {
-        if (k < deg) {
-          double term = 0.0;
-          if (vr) {
-            term = fabs(qk[k] - qb);
-            ((GDblW*)mds[k].lam_dst[nxt])[xr] = ab - mk[k];
-          }
-          term = wave_sum(term);
-          if (lane == 0) rec[k] = term;
-        }
-      }
-      const double av = vr ? ab : -INFINITY;
-      const double Mw = wave_max(av);
-      const double Sw = wave_sum(av > -INFINITY ? exp(av - Mw) : 0.0);
-      if (lane == 0) {
-        rec[deg] = Mw;
-        rec[deg + 1] = Sw;
-      }
-      return;
-    }
     for (int k = 0; k < deg; ++k) {
       const double m = msg(k);
       as += m;
